@@ -1,0 +1,274 @@
+"""ctypes wrapper of the FP64 CPU oracle (liboracle.so).
+
+Test infrastructure only: the tests, the smoke check and the benchmark's CPU
+baseline leg use it; the product path never does.  It takes numpy arrays and
+the event / site / bound descriptors from the seeded input module.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from typing import Optional, Sequence
+
+import numpy as np
+
+from paper_2601_02336_amd import synth
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "oracle.cpp")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with g++ (OpenMP, -O2, FP64, no fast-math)."""
+    if force or not os.path.exists(_LIB_PATH):
+        cmd = ["g++", "-O2", "-fopenmp", "-std=c++17", "-Wall", "-shared", "-fPIC", _SRC, "-o", _LIB_PATH]
+        subprocess.run(cmd, check=True)
+    return _LIB_PATH
+
+
+class OrcEvent(C.Structure):
+    _fields_ = [("f_low", C.c_double), ("df", C.c_double), ("n_bins", C.c_int32), ("n_det", C.c_int32),
+                ("gmst", C.c_double), ("t_sun", C.c_double), ("mpc_m", C.c_double), ("c_light", C.c_double),
+                ("pn_order", C.c_int32), ("reserved", C.c_int32)]
+
+
+class OrcDetector(C.Structure):
+    _fields_ = [("lat", C.c_double), ("lon", C.c_double), ("az_x", C.c_double), ("az_y", C.c_double),
+                ("radius", C.c_double)]
+
+
+class OrcBound(C.Structure):
+    _fields_ = [("lo", C.c_double), ("hi", C.c_double), ("bnd", C.c_int32), ("prior", C.c_int32)]
+
+
+class OrcTarget(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("dim", C.c_int32), ("bounds", C.POINTER(OrcBound)),
+                ("params", C.POINTER(C.c_double)), ("ev", C.POINTER(OrcEvent)),
+                ("dets", C.POINTER(OrcDetector)), ("data_reim", C.POINTER(C.c_double)),
+                ("psd", C.POINTER(C.c_double)), ("param_index", C.POINTER(C.c_int32)),
+                ("fixed11", C.POINTER(C.c_double))]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=True)
+        _lib = C.CDLL(_LIB_PATH)
+    return _lib
+
+
+def _dp(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _ip(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+class Target:
+    """Keeps the ctypes target and every array it points to alive."""
+
+    def __init__(self, kind: int, dim: int, bounds, params=None, event=None,
+                 param_index: Optional[Sequence[int]] = None, fixed11=None):
+        self.keep = []
+        self.b = (OrcBound * dim)(*[OrcBound(b.lo, b.hi, b.bnd, b.prior) for b in bounds])
+        self.t = OrcTarget()
+        self.t.kind = kind
+        self.t.dim = dim
+        self.t.bounds = C.cast(self.b, C.POINTER(OrcBound))
+        if params is not None:
+            p = _f64(params)
+            self.keep.append(p)
+            self.t.params = _dp(p)
+        if event is not None:
+            self.ev, self.dets = event_structs(event)
+            data = _f64(event.data_reim())
+            psd = _f64(event.psd)
+            self.keep += [data, psd]
+            self.t.ev = C.pointer(self.ev)
+            self.t.dets = C.cast(self.dets, C.POINTER(OrcDetector))
+            self.t.data_reim = _dp(data)
+            self.t.psd = _dp(psd)
+            idx = np.arange(dim, dtype=np.int32) if param_index is None else np.asarray(param_index, np.int32)
+            fx = _f64(event.theta_inj if fixed11 is None else fixed11)
+            self.keep += [idx, fx]
+            self.t.param_index = _ip(idx)
+            self.t.fixed11 = _dp(fx)
+
+    @property
+    def ptr(self):
+        return C.byref(self.t)
+
+
+def event_structs(ev):
+    e = OrcEvent(ev.f_low, ev.df, ev.n, ev.n_det, ev.gmst, ev.t_sun, ev.mpc_m, ev.c_light, ev.pn_order, 0)
+    dets = (OrcDetector * ev.n_det)(*[OrcDetector(*s.as_tuple()) for s in ev.sites])
+    return e, dets
+
+
+# ----------------------------------------------------------------- wrappers
+def philox4x32_10(ctr, key) -> np.ndarray:
+    c = np.asarray(ctr, np.uint32)
+    k = np.asarray(key, np.uint32)
+    o = np.zeros(4, np.uint32)
+    lib().orc_philox4x32_10(c.ctypes.data_as(C.c_void_p), k.ctypes.data_as(C.c_void_p), o.ctypes.data_as(C.c_void_p))
+    return o
+
+
+def uniforms2(seed: int, index: int, particle: int, iteration: int, purpose: int) -> np.ndarray:
+    u = np.zeros(2)
+    lib().orc_uniforms2(C.c_uint64(seed), C.c_uint32(index), C.c_uint32(particle), C.c_uint64(iteration),
+                        C.c_uint32(purpose), _dp(u))
+    return u
+
+
+def antenna(site, ra: float, dec: float, psi: float, gmst: float = 0.0, c_light: float = 299792458.0):
+    d = OrcDetector(*site.as_tuple())
+    o = np.zeros(3)
+    lib().orc_antenna(C.byref(d), C.c_double(ra), C.c_double(dec), C.c_double(psi), C.c_double(gmst),
+                      C.c_double(c_light), _dp(o))
+    return o
+
+
+def detector_geometry(site):
+    d = OrcDetector(*site.as_tuple())
+    pos = np.zeros(3)
+    resp = np.zeros(9)
+    lib().orc_detector_geometry(C.byref(d), _dp(pos), _dp(resp))
+    return pos, resp.reshape(3, 3)
+
+
+def phase(theta11, f, t_sun: float, pn_order: int = 7) -> np.ndarray:
+    th = _f64(theta11)
+    ff = _f64(f)
+    out = np.zeros_like(ff)
+    lib().orc_phase(_dp(th), C.c_double(t_sun), C.c_int(pn_order), C.c_int(ff.size), _dp(ff), _dp(out))
+    return out
+
+
+def waveform(ev, theta11) -> np.ndarray:
+    e, dets = event_structs(ev)
+    th = _f64(theta11)
+    h = np.zeros((ev.n_det, ev.n, 2))
+    lib().orc_waveform(C.byref(e), C.cast(dets, C.POINTER(OrcDetector)), _dp(th), _dp(h))
+    return h[..., 0] + 1j * h[..., 1]
+
+
+def gw_target(ev, param_index: Optional[Sequence[int]] = None, bounds=None, fixed11=None) -> Target:
+    idx = list(range(11)) if param_index is None else list(param_index)
+    full = synth.gw_prior_for(ev) if bounds is None else bounds
+    b = [full[i] for i in idx] if len(full) == 11 and len(idx) != 11 else full
+    return Target(synth.TARGET_GW, len(idx), b, event=ev, param_index=idx, fixed11=fixed11)
+
+
+def loglike_grad(target: Target, x: np.ndarray, want_grad: bool = True):
+    x = _f64(x)
+    P = x.shape[0]
+    logl = np.zeros(P)
+    grad = np.zeros_like(x) if want_grad else None
+    lib().orc_loglike_grad(target.ptr, C.c_int(P), _dp(x), _dp(logl), _dp(grad))
+    return (logl, grad) if want_grad else logl
+
+
+def loglike_zero_data(ev, theta11) -> float:
+    """logL at theta for an event whose data are zero (= -<h|h>/2)."""
+    ev0 = ev.with_data(np.zeros_like(ev.data))
+    t = gw_target(ev0, bounds=synth.gw_bounds(1.0, 1e5), fixed11=theta11)
+    return float(loglike_grad(t, np.asarray(theta11, float)[None, :], want_grad=False)[0])
+
+
+def logprior(target: Target, x: np.ndarray, want_grad: bool = True):
+    x = _f64(x)
+    lp = np.zeros(x.shape[0])
+    g = np.zeros_like(x) if want_grad else None
+    lib().orc_logprior(target.ptr, C.c_int(x.shape[0]), _dp(x), _dp(lp), _dp(g))
+    return (lp, g) if want_grad else lp
+
+
+def apply_boundaries(target: Target, x: np.ndarray, r: np.ndarray):
+    x = _f64(x).copy()
+    r = _f64(r).copy()
+    lib().orc_apply_boundaries(target.ptr, C.c_int(x.shape[0]), _dp(x), _dp(r))
+    return x, r
+
+
+def leapfrog(target: Target, x, r, chol, eps: float, n_steps: int, beta: float = 1.0):
+    x = _f64(x).copy()
+    r = _f64(r).copy()
+    L = _f64(chol)
+    e = np.zeros(2)
+    lib().orc_leapfrog(target.ptr, C.c_double(beta), _dp(L), C.c_double(eps), C.c_int(n_steps), _dp(x), _dp(r), _dp(e))
+    return x, r, e
+
+
+def nuts_step(target: Target, x, chol, step: float, max_depth: int, beta: float, seed: int, iteration: int,
+              max_depth_per_particle=None, uturn: bool = True, max_dh: float = 1000.0):
+    x = _f64(x).copy()
+    P, D = x.shape
+    logl = np.zeros(P)
+    grad = np.zeros((P, D))
+    depth = np.zeros(P, np.int32)
+    nlf = np.zeros(P, np.int32)
+    div = np.zeros(P, np.uint8)
+    acc = np.zeros(P)
+    mdp = None if max_depth_per_particle is None else np.ascontiguousarray(max_depth_per_particle, np.int32)
+    lib().orc_nuts_step(target.ptr, C.c_int(P), _dp(x), _dp(logl), _dp(grad), _dp(_f64(chol)), C.c_double(step),
+                        C.c_int(max_depth), _ip(mdp), C.c_int(1 if uturn else 0), C.c_double(max_dh),
+                        C.c_double(beta), C.c_uint64(seed), C.c_uint64(iteration), _ip(depth), _ip(nlf),
+                        div.ctypes.data_as(C.c_void_p), _dp(acc))
+    return dict(x=x, logl=logl, grad=grad, depth=depth, n_leapfrog=nlf, divergent=div, accept_stat=acc)
+
+
+def smc_reweight(logl, beta_prev: float, alpha: float):
+    ll = _f64(logl)
+    w = np.zeros_like(ll)
+    b = C.c_double()
+    dz = C.c_double()
+    rc = lib().orc_smc_reweight(C.c_int(ll.size), _dp(ll), C.c_double(beta_prev), C.c_double(alpha),
+                                C.byref(b), C.byref(dz), _dp(w))
+    return rc, b.value, dz.value, w
+
+
+def resample(weights, seed: int, iteration: int) -> np.ndarray:
+    w = _f64(weights)
+    a = np.zeros(w.size, np.int32)
+    lib().orc_resample(C.c_int(w.size), _dp(w), C.c_uint64(seed), C.c_uint64(iteration), _ip(a))
+    return a
+
+
+def mass_matrix(x, shrink: float):
+    x = _f64(x)
+    P, D = x.shape
+    inv = np.zeros((D, D))
+    L = np.zeros((D, D))
+    rc = lib().orc_mass_matrix(C.c_int(P), C.c_int(D), _dp(x), C.c_double(shrink), _dp(inv), _dp(L))
+    return rc, inv, L
+
+
+def smc_run(target: Target, x0, alpha: float, step: float, max_depth: int, shrink: float, seed: int,
+            max_iter: int = 200):
+    x = _f64(x0).copy()
+    P, D = x.shape
+    logz = C.c_double()
+    nit = C.c_int()
+    betas = np.zeros(max_iter)
+    dz = np.zeros(max_iter)
+    rc = lib().orc_smc_run(target.ptr, C.c_int(P), _dp(x), C.c_double(alpha), C.c_double(step), C.c_int(max_depth),
+                           C.c_double(shrink), C.c_uint64(seed), C.c_int(max_iter), C.byref(logz), C.byref(nit),
+                           _dp(betas), _dp(dz))
+    n = nit.value
+    return dict(rc=rc, logz=logz.value, n_iter=n, betas=betas[:n], dlogz=dz[:n], x=x)
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
