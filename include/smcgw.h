@@ -1,0 +1,195 @@
+/*
+ * smcgw.h - C ABI of the MI355X (gfx950) batched gravitational-wave
+ * likelihood, adjoint gradient, NUTS and SMC library.
+ *
+ * Method: "The Sequential Monte Carlo goes NUTS: Boosting Gravitational-Wave
+ * Inference" (arXiv:2601.02336).  Every entry point below names the passage
+ * that defines what it computes.
+ *
+ * Conventions
+ *   - Every function returns an int status: 0 = OK, > 0 = warning, < 0 = error
+ *     (see SMCGW_* codes; smcgw_status_string() gives a message).  On an error
+ *     no output has been written unless stated.
+ *   - Batch arrays (theta, logl, grad, ancestors, per-particle outputs) are
+ *     DEVICE pointers owned by the caller (e.g. torch tensors' data_ptr()).
+ *     Set-up arrays (event data, PSD, detectors, bounds, target parameters)
+ *     are HOST pointers; the library copies them.  The library never frees
+ *     or allocates caller memory; the context owns its device tables and
+ *     scratch, which grow on demand.
+ *   - Work is enqueued asynchronously on the context's HIP stream.  Only
+ *     functions documented as synchronising wait for the GPU.
+ *   - Layouts: theta is row-major [P][D] float64 over the D sampled
+ *     coordinates; the 11 source parameters are, in order,
+ *     (chirp mass [Msun], q = m2/m1, chi1, chi2, d_L [Mpc], inclination,
+ *     polarisation, right ascension, declination, t_c [s], phi_c).
+ *     Event data are [n_det][N] interleaved complex float64, the PSD is
+ *     [n_det][N] one-sided float64, f_j = f_low + j df, j = 0..N-1.
+ *   - Reductions use a fixed order and no floating-point atomics, so results
+ *     are bitwise reproducible for a given launch configuration.
+ *   - One context per host thread; calls on one context must not overlap.
+ */
+#ifndef SMCGW_H
+#define SMCGW_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ status */
+#define SMCGW_OK 0
+#define SMCGW_WARN_FALLBACK 1       /* a fallback was used (e.g. diagonal mass matrix) */
+#define SMCGW_ERR_INVALID (-1)      /* invalid argument / null pointer */
+#define SMCGW_ERR_SHAPE (-2)        /* size out of the supported range */
+#define SMCGW_ERR_HIP (-3)          /* a HIP runtime call failed */
+#define SMCGW_ERR_OOM (-4)          /* device allocation failed */
+#define SMCGW_ERR_NOT_INIT (-5)     /* no event / prior / target set */
+#define SMCGW_ERR_STALL (-6)        /* tempering ladder cannot advance */
+
+/* ------------------------------------------------------------ enums */
+enum { SMCGW_PLAIN_FP64 = 0, SMCGW_MIXED = 1 };
+enum { SMCGW_TARGET_GW = 0, SMCGW_TARGET_GAUSS = 1, SMCGW_TARGET_GAUSS_X_GAUSS = 2, SMCGW_TARGET_BIMODAL = 3 };
+enum { SMCGW_BND_NONE = 0, SMCGW_BND_REFLECT = 1, SMCGW_BND_PERIODIC = 2 };
+enum { SMCGW_PRIOR_FLAT = 0, SMCGW_PRIOR_UNIFORM = 1, SMCGW_PRIOR_LOGUNIFORM = 2, SMCGW_PRIOR_GAUSSIAN = 3 };
+
+#define SMCGW_MAX_DET 4
+#define SMCGW_MAX_DIM 16
+#define SMCGW_MAX_DEPTH 12
+#define SMCGW_MAX_EVENTS 64
+
+typedef struct smcgw_ctx smcgw_ctx;
+
+/* One event: frequency grid, detector count, sidereal angle and the physical
+ * constants (seconds per solar mass G Msun / c^3, metres per Mpc, c). */
+typedef struct {
+    double f_low, df;
+    int32_t n_bins, n_det;
+    double gmst;
+    double t_sun, mpc_m, c_light;
+    int32_t pn_order;                /* 0..7: highest half-PN order kept in the phase */
+    int32_t reserved;
+} smcgw_event_desc;
+
+/* An L-shaped interferometer on a sphere: latitude, longitude, azimuths of
+ * the two arms measured from local East towards North (radians), radius [m]. */
+typedef struct {
+    double lat, lon, az_x, az_y, radius;
+} smcgw_detector;
+
+/* Prior and boundary of one sampled coordinate (Sec. 5, "Boundary
+ * conditions"): uniform / log-uniform on [lo, hi], Gaussian (lo = mean,
+ * hi = sigma) or flat; reflective, periodic or no boundary. */
+typedef struct {
+    double lo, hi;
+    int32_t bnd;
+    int32_t prior;
+} smcgw_bounds;
+
+/* NUTS transition settings (Sec. 4). */
+typedef struct {
+    double step;           /* leapfrog step size epsilon */
+    double beta;           /* temperature of the target L^beta pi (Sec. 3, Eq. 3) */
+    double max_delta_h;    /* divergence threshold on H - H0 */
+    int32_t max_depth;     /* maximum number of trajectory doublings (<= SMCGW_MAX_DEPTH) */
+    int32_t uturn;         /* 1: stop at a U-turn; 0: always build to the depth limit */
+    uint64_t seed;         /* Philox4x32-10 key */
+    uint64_t iteration;    /* SMC iteration (part of the Philox counter) */
+} smcgw_nuts_params;
+
+/* Message for a status code (static storage). */
+const char *smcgw_status_string(int status);
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  *ctx receives the handle. */
+int smcgw_create(smcgw_ctx **ctx, int device, void *hip_stream);
+
+/* Destroy a context and free everything it owns (synchronises). */
+int smcgw_destroy(smcgw_ctx *ctx);
+
+/* Change the stream later calls enqueue on. */
+int smcgw_set_stream(smcgw_ctx *ctx, void *hip_stream);
+
+/* Add an event: the data d(f) and PSD S_n(f) of Sec. 2, Eq. 2.  Builds the
+ * frequency-major bin tables on the device: whitened data
+ * 4 df conj(d)/S f^{-7/6}, the phase basis of every bin, <d|d> and
+ * sum_j 4 df f^{-7/3}/S per detector.  data_reim [n_det][N][2], psd
+ * [n_det][N] and dets [n_det] are host arrays; synchronises.  *event_id
+ * receives the index used by smcgw_loglike_grad's event_of_particle. */
+int smcgw_add_event(smcgw_ctx *ctx, const smcgw_event_desc *ev, const double *data_reim, const double *psd,
+                    const smcgw_detector *dets, int *event_id);
+
+/* Which of the 11 source parameters are sampled: param_index[dim] gives the
+ * source-parameter index of each sampled coordinate; fixed11[11] (host)
+ * supplies the others.  Default: dim = 11, identity. */
+int smcgw_set_param_map(smcgw_ctx *ctx, int dim, const int32_t *param_index, const double *fixed11);
+
+/* Prior and boundaries of the dim sampled coordinates (host array). */
+int smcgw_set_prior(smcgw_ctx *ctx, int dim, const smcgw_bounds *bounds);
+
+/* Likelihood used by smcgw_nuts_step / smcgw_smc_reweight_resample:
+ * SMCGW_TARGET_GW (the event likelihood of Sec. 2), or an analytic test
+ * likelihood over dim coordinates: GAUSS logL = -|x|^2/2; GAUSS_X_GAUSS
+ * normalised N(y; x, diag s^2) with params = y[dim], s[dim]; BIMODAL the
+ * unweighted sum of two normalised isotropic Gaussians of App. A
+ * (params = mu1[dim], mu2[dim], sigma).  params is a host array. */
+int smcgw_set_target(smcgw_ctx *ctx, int kind, int dim, const double *params, int n_params);
+
+/* Batched log-likelihood logL = -1/2 <d-h|d-h> (Sec. 2, Eq. 2) and its
+ * gradient with respect to the dim sampled coordinates (hand-written
+ * adjoint; the paper differentiates automatically, Sec. 5 "JAX
+ * implementation").  theta [P][dim], logl [P], grad [P][dim] (NULL: forward
+ * only) are device arrays; event_of_particle [P] (device, NULL = event 0)
+ * picks each particle's event, so events of different lengths share one
+ * launch.  precision: SMCGW_PLAIN_FP64 (FP64 throughout) or SMCGW_MIXED
+ * (FP64 phase and argument reduction, FP32 trigonometry and per-bin
+ * products, FP32 partial sums flushed into FP64 accumulators). */
+int smcgw_loglike_grad(smcgw_ctx *ctx, int P, const int32_t *event_of_particle, const double *theta, double *logl,
+                       double *grad, int precision);
+
+/* Projected detector strain h_d(f_j; theta) of event event_id for one point
+ * of the 11 source parameters (theta11, host), written to the device array
+ * h_reim [n_det][N][2].  Used to build injections. */
+int smcgw_waveform(smcgw_ctx *ctx, int event_id, const double *theta11, double *h_reim);
+
+/* Mass matrix from the particle population (Sec. 5, "Exploitation of local
+ * geometry", read as the population covariance): inv_mass = cov(theta) with
+ * the diagonal scaled by (1 + shrink), chol its lower Cholesky factor
+ * (M^{-1} = chol chol^T).  theta [P][D], inv_mass [D][D], chol [D][D] are
+ * device arrays.  Synchronises; returns SMCGW_WARN_FALLBACK when the
+ * covariance was not positive definite and a diagonal was used. */
+int smcgw_mass_matrix(smcgw_ctx *ctx, int P, int D, const double *theta, double shrink, double *inv_mass,
+                      double *chol);
+
+/* One No-U-Turn transition per particle (Sec. 4: momentum r ~ N(0, M),
+ * Hamiltonian H = -log p_t + r^T M^{-1} r / 2, leapfrog Eqs. 11-13,
+ * reflective / periodic boundaries of Sec. 5; multinomial trajectory
+ * sampling with the generalised U-turn criterion).  theta [P][D], logl [P]
+ * and grad [P][D] (device) hold the current point, its likelihood and the
+ * likelihood gradient on entry and the selected point on exit.  chol [D][D]
+ * (device) is the Cholesky factor of M^{-1}.  max_depth_per_particle [P]
+ * (device, NULL = params->max_depth) caps each tree.  Per-particle
+ * diagnostics (device, each may be NULL): doublings done, leapfrog steps,
+ * divergence flag, mean acceptance statistic. */
+int smcgw_nuts_step(smcgw_ctx *ctx, int P, int D, double *theta, double *logl, double *grad, const double *chol,
+                    const smcgw_nuts_params *params, const int32_t *max_depth_per_particle, int precision,
+                    int32_t *depth, int32_t *n_leapfrog, uint8_t *divergent, double *accept_stat);
+
+/* Reweighting, adaptive temperature and multinomial resampling of one SMC
+ * iteration (Sec. 3, Eqs. 4-6): beta_next solves ESS(beta) = alpha P by
+ * bisection on [beta_prev, 1] (beta_next = 1 when ESS(1) >= alpha P); the
+ * evidence increment log(Z_t/Z_{t-1}) = log mean_i L_i^(beta_next-beta_prev)
+ * (Sec. 3.1, Eq. 7) is accumulated in FP64.  Ancestors are drawn with
+ * Philox uniforms keyed by (seed, iteration) and theta [P][D], logl [P],
+ * grad [P][D] (device) are gathered in place; ancestors [P] (device) receives
+ * the indices.  Synchronises: *beta_next_host and *dlogz_host are host
+ * scalars.  Returns SMCGW_ERR_STALL when beta cannot advance. */
+int smcgw_smc_reweight_resample(smcgw_ctx *ctx, int P, int D, double beta_prev, double alpha, uint64_t seed,
+                                uint64_t iteration, double *theta, double *logl, double *grad, int32_t *ancestors,
+                                double *beta_next_host, double *dlogz_host);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SMCGW_H */

@@ -1,0 +1,252 @@
+// Host side of the C ABI declared in smcgw.h: context, event set-up and the
+// likelihood entry points.  Sampler entry points live in sampler.hip.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+#include "context.h"
+
+using namespace smcgw;
+
+extern "C" const char* smcgw_status_string(int status) {
+    switch (status) {
+    case SMCGW_OK: return "ok";
+    case SMCGW_WARN_FALLBACK: return "warning: fallback used (diagonal mass matrix)";
+    case SMCGW_ERR_INVALID: return "invalid argument";
+    case SMCGW_ERR_SHAPE: return "size out of the supported range";
+    case SMCGW_ERR_HIP: return "HIP runtime error";
+    case SMCGW_ERR_OOM: return "device allocation failed";
+    case SMCGW_ERR_NOT_INIT: return "context not initialised (event, prior or target missing)";
+    case SMCGW_ERR_STALL: return "tempering ladder cannot advance";
+    default: return "unknown status";
+    }
+}
+
+namespace smcgw {
+
+int ctx_reserve(smcgw_ctx* c, int P) {
+    if (P <= c->cap) return SMCGW_OK;
+    const int cap = std::max(P, std::max(2 * c->cap, 256));
+    hipFree(c->d_cb);
+    hipFree(c->d_mom);
+    c->d_cb = nullptr;
+    c->d_mom = nullptr;
+    c->cap = 0;
+    if (hipMalloc(&c->d_cb, (size_t)cap * CB_SIZE * sizeof(double)) != hipSuccess) return SMCGW_ERR_OOM;
+    if (hipMalloc(&c->d_mom, (size_t)cap * MOM_SIZE * sizeof(double)) != hipSuccess) return SMCGW_ERR_OOM;
+    c->cap = cap;
+    return SMCGW_OK;
+}
+
+// logL / gradient of P particles on the context's stream (no synchronisation).
+int ctx_loglike(smcgw_ctx* c, int P, const int32_t* ev_of_p, const double* theta, double* logl, double* grad,
+                int precision) {
+    if (c->events.empty()) return SMCGW_ERR_NOT_INIT;
+    int rc = ctx_reserve(c, P);
+    if (rc) return rc;
+    if (launch_prep(c->d_events, ev_of_p, c->pmap, P, theta, c->d_cb, c->stream) != hipSuccess) return SMCGW_ERR_HIP;
+    if (launch_bins(c->d_events, ev_of_p, P, c->n_det, precision, c->d_cb, c->d_mom, c->stream) != hipSuccess)
+        return SMCGW_ERR_HIP;
+    if (launch_finish(c->d_events, ev_of_p, c->pmap, P, c->d_cb, c->d_mom, logl, grad, c->stream) != hipSuccess)
+        return SMCGW_ERR_HIP;
+    return SMCGW_OK;
+}
+
+}  // namespace smcgw
+
+extern "C" int smcgw_create(smcgw_ctx** out, int device, void* hip_stream) {
+    if (!out) return SMCGW_ERR_INVALID;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return SMCGW_ERR_INVALID;
+    if (hipSetDevice(device) != hipSuccess) return SMCGW_ERR_HIP;
+    smcgw_ctx* c = new smcgw_ctx();
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    c->pmap.dim = NPAR;
+    for (int k = 0; k < NPAR; ++k) { c->pmap.idx[k] = k; c->pmap.fixed[k] = 0.0; }
+    if (hipMalloc(&c->d_events, SMCGW_MAX_EVENTS * sizeof(DevEvent)) != hipSuccess ||
+        hipMalloc(&c->d_small, 4096) != hipSuccess) {
+        hipFree(c->d_events);
+        delete c;
+        return SMCGW_ERR_OOM;
+    }
+    *out = c;
+    return SMCGW_OK;
+}
+
+extern "C" int smcgw_destroy(smcgw_ctx* c) {
+    if (!c) return SMCGW_ERR_INVALID;
+    hipSetDevice(c->device);
+    hipStreamSynchronize(c->stream);
+    for (void* p : c->event_bufs) hipFree(p);
+    hipFree(c->d_events);
+    hipFree(c->d_small);
+    hipFree(c->d_cb);
+    hipFree(c->d_mom);
+    c->sampler_free();
+    delete c;
+    return SMCGW_OK;
+}
+
+extern "C" int smcgw_set_stream(smcgw_ctx* c, void* hip_stream) {
+    if (!c) return SMCGW_ERR_INVALID;
+    c->stream = (hipStream_t)hip_stream;
+    return SMCGW_OK;
+}
+
+// Detector position and response tensor D = (x x^T - y y^T)/2 from the site.
+static void site_geometry(const smcgw_detector& s, double pos[3], double resp[3][3]) {
+    const double cl = std::cos(s.lat), sl = std::sin(s.lat), co = std::cos(s.lon), so = std::sin(s.lon);
+    pos[0] = s.radius * cl * co;
+    pos[1] = s.radius * cl * so;
+    pos[2] = s.radius * sl;
+    const double e[3] = {-so, co, 0.0}, nn[3] = {-sl * co, -sl * so, cl};
+    double x[3], y[3];
+    for (int i = 0; i < 3; ++i) {
+        x[i] = std::cos(s.az_x) * e[i] + std::sin(s.az_x) * nn[i];
+        y[i] = std::cos(s.az_y) * e[i] + std::sin(s.az_y) * nn[i];
+    }
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) resp[i][j] = 0.5 * (x[i] * x[j] - y[i] * y[j]);
+}
+
+extern "C" int smcgw_add_event(smcgw_ctx* c, const smcgw_event_desc* ev, const double* data_reim, const double* psd,
+                               const smcgw_detector* dets, int* event_id) {
+    if (!c || !ev || !data_reim || !psd || !dets) return SMCGW_ERR_INVALID;
+    if (ev->n_bins <= 0 || ev->n_det <= 0 || ev->n_det > MAXDET || !(ev->df > 0.0) || !(ev->f_low > 0.0) ||
+        ev->pn_order < 0 || ev->pn_order > 7)
+        return SMCGW_ERR_SHAPE;
+    if ((int)c->events.size() >= SMCGW_MAX_EVENTS) return SMCGW_ERR_SHAPE;
+    if (!c->events.empty() && ev->n_det != c->n_det) return SMCGW_ERR_SHAPE;
+    const int n = ev->n_bins, nd = ev->n_det;
+    const int npad = ((n + TABLE_PAD - 1) / TABLE_PAD) * TABLE_PAD;
+    // Power-of-two scale of the whitened data, so the FP32 table sits near unit magnitude.
+    double umax = 0.0;
+    for (int d = 0; d < nd; ++d)
+        for (int j = 0; j < n; ++j) {
+            const double f = ev->f_low + ev->df * j;
+            const double* x = data_reim + 2 * ((size_t)d * n + j);
+            const double v = 4.0 * ev->df * std::hypot(x[0], x[1]) / psd[(size_t)d * n + j] * std::pow(f, -7.0 / 6.0);
+            if (std::isfinite(v)) umax = std::max(umax, v);
+        }
+    const double us = umax > 0.0 ? std::ldexp(1.0, (int)std::lround(std::log2(umax))) : 1.0;
+
+    hipSetDevice(c->device);
+    double *d_data = nullptr, *d_psd = nullptr, *basis = nullptr, *freq = nullptr, *sums = nullptr;
+    float2* u32 = nullptr;
+    double2* u64 = nullptr;
+    int rc = SMCGW_OK;
+    auto fail = [&](int code) {
+        hipFree(d_data); hipFree(d_psd); hipFree(basis); hipFree(freq); hipFree(u32); hipFree(u64); hipFree(sums);
+        return code;
+    };
+    if (hipMalloc(&d_data, sizeof(double) * 2 * nd * (size_t)n) != hipSuccess ||
+        hipMalloc(&d_psd, sizeof(double) * nd * (size_t)n) != hipSuccess ||
+        hipMalloc(&basis, sizeof(double) * NBASIS * (size_t)npad) != hipSuccess ||
+        hipMalloc(&freq, sizeof(double) * (size_t)npad) != hipSuccess ||
+        hipMalloc(&u32, sizeof(float2) * nd * (size_t)npad) != hipSuccess ||
+        hipMalloc(&u64, sizeof(double2) * nd * (size_t)npad) != hipSuccess ||
+        hipMalloc(&sums, sizeof(double) * 2 * MAXDET) != hipSuccess)
+        return fail(SMCGW_ERR_OOM);
+    if (hipMemcpyAsync(d_data, data_reim, sizeof(double) * 2 * nd * (size_t)n, hipMemcpyHostToDevice, c->stream) ||
+        hipMemcpyAsync(d_psd, psd, sizeof(double) * nd * (size_t)n, hipMemcpyHostToDevice, c->stream))
+        return fail(SMCGW_ERR_HIP);
+    if (launch_build_tables(d_data, d_psd, nd, n, npad, ev->f_low, ev->df, us, basis, freq, u32, u64, sums, c->stream))
+        return fail(SMCGW_ERR_HIP);
+    double hs[2 * MAXDET];
+    if (hipMemcpyAsync(hs, sums, sizeof(double) * 2 * nd, hipMemcpyDeviceToHost, c->stream) ||
+        hipStreamSynchronize(c->stream))
+        return fail(SMCGW_ERR_HIP);
+    hipFree(d_data);
+    hipFree(d_psd);
+    hipFree(sums);
+    d_data = d_psd = sums = nullptr;
+
+    DevEvent de;
+    std::memset(&de, 0, sizeof(de));
+    de.n_bins = n;
+    de.n_pad = npad;
+    de.n_det = nd;
+    de.pn_order = ev->pn_order;
+    de.f_low = ev->f_low;
+    de.df = ev->df;
+    de.basis = basis;
+    de.freq = freq;
+    de.u32 = u32;
+    de.u64 = u64;
+    de.dd = 0.0;
+    for (int d = 0; d < nd; ++d) {
+        de.hnorm[d] = hs[2 * d] / (us * us);
+        de.dd += hs[2 * d + 1];
+        site_geometry(dets[d], de.pos[d], de.resp[d]);
+    }
+    de.u_scale = us;
+    de.t_sun = ev->t_sun;
+    de.mpc_m = ev->mpc_m;
+    de.c_light = ev->c_light;
+    de.gmst = ev->gmst;
+    const int id = (int)c->events.size();
+    if (hipMemcpyAsync(c->d_events + id, &de, sizeof(de), hipMemcpyHostToDevice, c->stream) ||
+        hipStreamSynchronize(c->stream))
+        return fail(SMCGW_ERR_HIP);
+    c->events.push_back(de);
+    c->event_bufs.push_back(basis);
+    c->event_bufs.push_back(freq);
+    c->event_bufs.push_back(u32);
+    c->event_bufs.push_back(u64);
+    c->n_det = nd;
+    if (event_id) *event_id = id;
+    (void)rc;
+    return SMCGW_OK;
+}
+
+extern "C" int smcgw_set_param_map(smcgw_ctx* c, int dim, const int32_t* param_index, const double* fixed11) {
+    if (!c || dim <= 0 || dim > NPAR || !param_index) return SMCGW_ERR_INVALID;
+    ParamMap pm;
+    pm.dim = dim;
+    for (int k = 0; k < NPAR; ++k) pm.fixed[k] = fixed11 ? fixed11[k] : 0.0;
+    for (int k = 0; k < MAXDIM; ++k) pm.idx[k] = 0;
+    for (int k = 0; k < dim; ++k) {
+        if (param_index[k] < 0 || param_index[k] >= NPAR) return SMCGW_ERR_INVALID;
+        pm.idx[k] = param_index[k];
+    }
+    c->pmap = pm;
+    return SMCGW_OK;
+}
+
+extern "C" int smcgw_loglike_grad(smcgw_ctx* c, int P, const int32_t* event_of_particle, const double* theta,
+                                  double* logl, double* grad, int precision) {
+    if (!c || P < 0 || (P > 0 && (!theta || !logl))) return SMCGW_ERR_INVALID;
+    if (precision != SMCGW_PLAIN_FP64 && precision != SMCGW_MIXED) return SMCGW_ERR_INVALID;
+    if (P == 0) return SMCGW_OK;
+    hipSetDevice(c->device);
+    return ctx_loglike(c, P, event_of_particle, theta, logl, grad, precision);
+}
+
+extern "C" int smcgw_waveform(smcgw_ctx* c, int event_id, const double* theta11, double* h_reim) {
+    if (!c || !theta11 || !h_reim) return SMCGW_ERR_INVALID;
+    if (event_id < 0 || event_id >= (int)c->events.size()) return SMCGW_ERR_INVALID;
+    hipSetDevice(c->device);
+    int rc = ctx_reserve(c, 1);
+    if (rc) return rc;
+    // d_small: [0, 88) theta11, [128, 132) event index
+    char* small = (char*)c->d_small;
+    int32_t eid = event_id;
+    if (hipMemcpyAsync(small, theta11, NPAR * sizeof(double), hipMemcpyHostToDevice, c->stream) ||
+        hipMemcpyAsync(small + 128, &eid, sizeof(eid), hipMemcpyHostToDevice, c->stream))
+        return SMCGW_ERR_HIP;
+    ParamMap id;
+    id.dim = NPAR;
+    for (int k = 0; k < NPAR; ++k) { id.idx[k] = k; id.fixed[k] = 0.0; }
+    if (launch_prep(c->d_events, (const int32_t*)(small + 128), id, 1, (const double*)small, c->d_cb, c->stream))
+        return SMCGW_ERR_HIP;
+    const DevEvent& e = c->events[event_id];
+    if (launch_waveform(c->d_events, event_id, c->d_cb, h_reim, e.n_bins, e.n_det, c->stream)) return SMCGW_ERR_HIP;
+    // the small staging buffer is reused by the next call: wait for this one
+    if (hipStreamSynchronize(c->stream)) return SMCGW_ERR_HIP;
+    return SMCGW_OK;
+}

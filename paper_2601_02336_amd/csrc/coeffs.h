@@ -1,0 +1,212 @@
+// Per-particle prologue of the likelihood: source parameters -> phase-basis
+// coefficients, per-detector delay and complex projection, and the Jacobians
+// the adjoint needs.  FP64, one particle per lane.
+//
+// Waveform (not given in the paper, which uses IMRPhenomD): TaylorF2 with
+// Newtonian amplitude and 3.5PN stationary-phase phase,
+//   Psi(f) = 2 pi f t_c - phi_c - pi/4 + 3/(128 eta v^5) sum_k (phi_k + phi_k^l ln v) v^k,
+//   v = (pi M f)^{1/3};
+// coefficients: Buonanno et al., PRD 80, 084043 (2009), Eq. (3.18) (non-spinning)
+// and the aligned-spin terms collected in Khan et al., PRD 93, 044007 (2016), App. B.
+// With ln v = (ln(pi M) + ln f)/3 every term is a fixed function of f times a
+// per-particle coefficient, so the per-bin phase is a short FP64 dot product
+// with the tables' basis rows and needs no per-bin transcendental.
+#pragma once
+
+#include "common.h"
+
+namespace smcgw {
+
+// ---------------------------------------------------------------- dual numbers
+template <int N>
+struct Dv {
+    double v;
+    double d[N];
+};
+template <int N> __device__ __forceinline__ Dv<N> dconst(double x) { Dv<N> r; r.v = x;
+#pragma unroll
+    for (int i = 0; i < N; ++i) r.d[i] = 0.0; return r; }
+template <int N> __device__ __forceinline__ Dv<N> dvar(double x, int k) { Dv<N> r = dconst<N>(x); r.d[k] = 1.0; return r; }
+template <int N> __device__ __forceinline__ Dv<N> operator+(const Dv<N>& a, const Dv<N>& b) { Dv<N> r; r.v = a.v + b.v;
+#pragma unroll
+    for (int i = 0; i < N; ++i) r.d[i] = a.d[i] + b.d[i]; return r; }
+template <int N> __device__ __forceinline__ Dv<N> operator-(const Dv<N>& a, const Dv<N>& b) { Dv<N> r; r.v = a.v - b.v;
+#pragma unroll
+    for (int i = 0; i < N; ++i) r.d[i] = a.d[i] - b.d[i]; return r; }
+template <int N> __device__ __forceinline__ Dv<N> operator*(const Dv<N>& a, const Dv<N>& b) { Dv<N> r; r.v = a.v * b.v;
+#pragma unroll
+    for (int i = 0; i < N; ++i) r.d[i] = fma(a.d[i], b.v, a.v * b.d[i]); return r; }
+template <int N> __device__ __forceinline__ Dv<N> operator*(double a, const Dv<N>& b) { Dv<N> r; r.v = a * b.v;
+#pragma unroll
+    for (int i = 0; i < N; ++i) r.d[i] = a * b.d[i]; return r; }
+template <int N> __device__ __forceinline__ Dv<N> operator+(double a, const Dv<N>& b) { Dv<N> r = b; r.v += a; return r; }
+template <int N> __device__ __forceinline__ Dv<N> operator-(double a, const Dv<N>& b) { Dv<N> r; r.v = a - b.v;
+#pragma unroll
+    for (int i = 0; i < N; ++i) r.d[i] = -b.d[i]; return r; }
+template <int N> __device__ __forceinline__ Dv<N> recip(const Dv<N>& a) { Dv<N> r; r.v = 1.0 / a.v; const double s = -r.v * r.v;
+#pragma unroll
+    for (int i = 0; i < N; ++i) r.d[i] = s * a.d[i]; return r; }
+template <int N> __device__ __forceinline__ Dv<N> operator/(const Dv<N>& a, const Dv<N>& b) { return a * recip(b); }
+template <int N> __device__ __forceinline__ Dv<N> scale_chain(const Dv<N>& a, double f, double fp) { Dv<N> r; r.v = f;
+#pragma unroll
+    for (int i = 0; i < N; ++i) r.d[i] = fp * a.d[i]; return r; }
+template <int N> __device__ __forceinline__ Dv<N> dlog(const Dv<N>& a) { return scale_chain(a, log(a.v), 1.0 / a.v); }
+template <int N> __device__ __forceinline__ Dv<N> dexp(const Dv<N>& a) { const double e = exp(a.v); return scale_chain(a, e, e); }
+
+// ---------------------------------------------------------------- TaylorF2
+// Phase coefficients in the (eta, delta = (m1-m2)/M, chi_s, chi_a) form.
+typedef Dv<4> D4;
+__device__ __forceinline__ void tf2_phi(const D4& eta, const D4& delta, const D4& chis, const D4& chia, int pn,
+                                        D4 phi[8], D4& phi5l, D4& phi6l) {
+    const double pi = PI;
+    const D4 eta2 = eta * eta;
+    const D4 eta3 = eta2 * eta;
+    const D4 dchia = delta * chia;
+    phi[0] = dconst<4>(1.0);
+    phi[1] = dconst<4>(0.0);
+    phi[2] = 3715.0 / 756.0 + (55.0 / 9.0) * eta;
+    phi[3] = (-16.0 * pi) + (113.0 / 3.0) * dchia + ((113.0 / 3.0) - (76.0 / 3.0) * eta) * chis;
+    phi[4] = (15293365.0 / 508032.0) + (27145.0 / 504.0) * eta + (3085.0 / 72.0) * eta2
+           + ((-405.0 / 8.0) + 200.0 * eta) * (chia * chia) - (405.0 / 4.0) * (dchia * chis)
+           + ((-405.0 / 8.0) + 2.5 * eta) * (chis * chis);
+    const D4 x5 = (38645.0 * pi / 756.0) - (65.0 * pi / 9.0) * eta
+               + ((-732985.0 / 2268.0) - (140.0 / 9.0) * eta) * dchia
+               + ((-732985.0 / 2268.0) + (24260.0 / 81.0) * eta + (340.0 / 9.0) * eta2) * chis;
+    phi[5] = x5;
+    phi5l = 3.0 * x5;
+    // 3PN: the constant part carries -6848/21 ln 4 from -6848/63 ln(64 v^3).
+    phi[6] = (11583231236531.0 / 4694215680.0 - (6848.0 / 21.0) * 0.57721566490153286061 - (640.0 / 3.0) * pi * pi
+              - (6848.0 / 21.0) * 1.38629436111989061883)
+           + ((-15737765635.0 / 3048192.0) + (2255.0 / 12.0) * pi * pi) * eta + (76055.0 / 1728.0) * eta2
+           - (127825.0 / 1296.0) * eta3 + ((2270.0 / 3.0) * pi) * dchia
+           + ((2270.0 / 3.0) * pi - (520.0 * pi) * eta) * chis;
+    phi6l = dconst<4>(-6848.0 / 21.0);
+    phi[7] = (77096675.0 * pi / 254016.0) + (378515.0 * pi / 1512.0) * eta - (74045.0 * pi / 756.0) * eta2
+           + ((-25150083775.0 / 3048192.0) + (26804935.0 / 6048.0) * eta - (1985.0 / 48.0) * eta2) * dchia
+           + ((-25150083775.0 / 3048192.0) + (10566655595.0 / 762048.0) * eta - (1042165.0 / 3024.0) * eta2
+              + (5345.0 / 36.0) * eta3) * chis;
+    for (int k = 0; k < 8; ++k)
+        if (k > pn) phi[k] = dconst<4>(0.0);
+    if (pn < 5) phi5l = dconst<4>(0.0);
+    if (pn < 6) phi6l = dconst<4>(0.0);
+}
+
+// Intrinsic part: coefficients c_b (cycles) and their derivatives with
+// respect to (Mc, q, chi1, chi2); phi_c and the -1/8 cycle offset included.
+__device__ __forceinline__ void prep_intrinsic(const DevEvent& ev, const double th[NPAR], double* cb) {
+    const D4 mc = dvar<4>(th[P_MC], 0);
+    const D4 q = dvar<4>(th[P_Q], 1);
+    const D4 c1 = dvar<4>(th[P_CHI1], 2);
+    const D4 c2 = dvar<4>(th[P_CHI2], 3);
+    const D4 opq = 1.0 + q;
+    const D4 iopq = recip(opq);
+    const D4 eta = q * (iopq * iopq);
+    const D4 delta = (1.0 - q) * iopq;
+    const D4 chis = 0.5 * (c1 + c2);
+    const D4 chia = 0.5 * (c1 - c2);
+    const D4 lneta = dlog(eta);
+    const D4 lnmc = dlog(mc);
+    // ln(pi M), M = Mc eta^{-3/5} t_sun
+    const D4 lnpm = lnmc + (-0.6) * lneta + dconst<4>(log(PI * ev.t_sun));
+    const D4 pm13 = dexp((1.0 / 3.0) * lnpm);
+    const D4 pmm13 = recip(pm13);
+    const D4 pm23 = pm13 * pm13;
+    const D4 pmm23 = pmm13 * pmm13;
+    const D4 pmm1 = pmm23 * pmm13;
+    const D4 pmm53 = pmm1 * pmm23;
+    D4 phi[8], phi5l, phi6l;
+    tf2_phi(eta, delta, chis, chia, ev.pn_order, phi, phi5l, phi6l);
+    const D4 pref = (3.0 / (256.0 * PI)) * recip(eta);   // 3/(128 eta) / (2 pi): cycles
+    D4 c[NCOEF];
+    const D4 third5l = (1.0 / 3.0) * phi5l;
+    const D4 third6l = (1.0 / 3.0) * phi6l;
+    c[0] = pref * (phi[5] + third5l * lnpm);
+    c[1 + B_M53] = pref * (phi[0] * pmm53);
+    c[1 + B_M1] = pref * (phi[2] * pmm1);
+    c[1 + B_M23] = pref * (phi[3] * pmm23);
+    c[1 + B_M13] = pref * (phi[4] * pmm13);
+    c[1 + B_LN] = pref * third5l;
+    c[1 + B_P13] = pref * (pm13 * (phi[6] + third6l * lnpm));
+    c[1 + B_P13LN] = pref * (pm13 * third6l);
+    c[1 + B_P23] = pref * (phi[7] * pm23);
+    for (int b = 0; b < NCOEF; ++b) {
+        cb[CB_C + b] = c[b].v;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) cb[CB_DC + 4 * b + k] = c[b].d[k];
+    }
+    cb[CB_C] += -th[P_PHIC] / TWO_PI - 0.125;
+}
+
+// Extrinsic part: delays, complex projections C_A u_scale P_d and Jacobians.
+// F+ = A cos 2psi + B sin 2psi, Fx = B cos 2psi - A sin 2psi with
+// A = p.Dp - q.Dq, B = 2 p.Dq for the polarisation frame (p, q) at psi = 0.
+__device__ __forceinline__ void prep_extrinsic(const DevEvent& ev, const double th[NPAR], double* cb) {
+    typedef Dv<2> D2;
+    const D2 phi = dvar<2>(th[P_RA] - ev.gmst, 0);
+    const D2 dec = dvar<2>(th[P_DEC], 1);
+    double sp, cp, sd, cd;
+    sincos(phi.v, &sp, &cp);
+    sincos(dec.v, &sd, &cd);
+    const D2 sphi = scale_chain(phi, sp, cp), cphi = scale_chain(phi, cp, -sp);
+    const D2 sdec = scale_chain(dec, sd, cd), cdec = scale_chain(dec, cd, -sd);
+    const D2 pv[3] = {sphi, dconst<2>(0.0) - cphi, dconst<2>(0.0)};
+    const D2 qv[3] = {dconst<2>(0.0) - cphi * sdec, dconst<2>(0.0) - sphi * sdec, cdec};
+    const D2 nv[3] = {cdec * cphi, cdec * sphi, sdec};
+    double s2, c2;
+    sincos(2.0 * th[P_PSI], &s2, &c2);
+    double si, ci;
+    sincos(th[P_IOTA], &si, &ci);
+    const double pp = 0.5 * (1.0 + ci * ci);
+    const double camp = 0.45643546458763842789 /* sqrt(5/24) */ * 0.46619407703541166 /* pi^-2/3 */
+                      * pow(th[P_MC] * ev.t_sun, 5.0 / 6.0) * ev.c_light / (th[P_DL] * ev.mpc_m);
+    const double S = camp * ev.u_scale;
+    cb[CB_DLNCA_MC] = (5.0 / 6.0) / th[P_MC];
+    cb[CB_DLNCA_DL] = -1.0 / th[P_DL];
+    for (int d = 0; d < MAXDET; ++d) {
+        if (d >= ev.n_det) {
+            cb[CB_TAU + d] = 0.0; cb[CB_PR + d] = 0.0; cb[CB_PI + d] = 0.0;
+            for (int k = 0; k < 2; ++k) cb[CB_DTAU + 2 * d + k] = 0.0;
+            for (int k = 0; k < 4; ++k) { cb[CB_DPR + 4 * d + k] = 0.0; cb[CB_DPI + 4 * d + k] = 0.0; }
+            continue;
+        }
+        D2 Dp[3], Dq[3];
+        for (int i = 0; i < 3; ++i) {
+            Dp[i] = dconst<2>(0.0);
+            Dq[i] = dconst<2>(0.0);
+            for (int j = 0; j < 3; ++j) {
+                Dp[i] = Dp[i] + ev.resp[d][i][j] * pv[j];
+                Dq[i] = Dq[i] + ev.resp[d][i][j] * qv[j];
+            }
+        }
+        D2 A = dconst<2>(0.0), B = dconst<2>(0.0), nr = dconst<2>(0.0);
+        for (int i = 0; i < 3; ++i) {
+            A = A + (pv[i] * Dp[i] - qv[i] * Dq[i]);
+            B = B + 2.0 * (pv[i] * Dq[i]);
+            nr = nr + ev.pos[d][i] * nv[i];
+        }
+        const D2 fp = c2 * A + s2 * B;
+        const D2 fx = c2 * B - s2 * A;
+        const D2 dt = (-1.0 / ev.c_light) * nr;
+        cb[CB_TAU + d] = th[P_TC] + dt.v;
+        cb[CB_DTAU + 2 * d + 0] = dt.d[0];
+        cb[CB_DTAU + 2 * d + 1] = dt.d[1];
+        // P = F+ (1 + cos^2 i)/2 - i Fx cos i
+        cb[CB_PR + d] = S * pp * fp.v;
+        cb[CB_PI + d] = -S * ci * fx.v;
+        cb[CB_DPR + 4 * d + 0] = -S * ci * si * fp.v;            // iota
+        cb[CB_DPI + 4 * d + 0] = S * si * fx.v;
+        cb[CB_DPR + 4 * d + 1] = S * pp * 2.0 * fx.v;            // psi: dF+/dpsi = 2 Fx
+        cb[CB_DPI + 4 * d + 1] = S * ci * 2.0 * fp.v;            //      dFx/dpsi = -2 F+
+        cb[CB_DPR + 4 * d + 2] = S * pp * fp.d[0];               // ra
+        cb[CB_DPI + 4 * d + 2] = -S * ci * fx.d[0];
+        cb[CB_DPR + 4 * d + 3] = S * pp * fp.d[1];               // dec
+        cb[CB_DPI + 4 * d + 3] = -S * ci * fx.d[1];
+    }
+}
+
+__device__ __forceinline__ void expand_params(const ParamMap& pm, const double* x, double th[NPAR]) {
+    for (int k = 0; k < NPAR; ++k) th[k] = pm.fixed[k];
+    for (int k = 0; k < pm.dim; ++k) th[pm.idx[k]] = x[k];
+}
+
+}  // namespace smcgw

@@ -1,0 +1,93 @@
+// Internal declarations shared by the library's HIP translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "smcgw.h"
+
+namespace smcgw {
+
+constexpr int NPAR = 11;            // source parameters
+constexpr int MAXDET = SMCGW_MAX_DET;
+constexpr int MAXDIM = SMCGW_MAX_DIM;
+constexpr int NBASIS = 8;           // per-bin phase basis rows kept in the tables
+constexpr int NCOEF = NBASIS + 1;   // + the constant term
+constexpr int TABLE_PAD = 512;      // tables are zero-padded to a multiple of this many bins
+constexpr double PI = 3.14159265358979323846;
+constexpr double TWO_PI = 6.28318530717958647692;
+
+// Source-parameter indices.
+enum { P_MC = 0, P_Q, P_CHI1, P_CHI2, P_DL, P_IOTA, P_PSI, P_RA, P_DEC, P_TC, P_PHIC };
+
+// Phase basis rows of the tables: the TaylorF2 phase in cycles is
+//   Phi(f) = c_0 + sum_b c_b B_b(f) + f (t_c + dt_det)
+// with B = {f^-5/3, f^-1, f^-2/3, f^-1/3, ln f, f^1/3, f^1/3 ln f, f^2/3}.
+enum { B_M53 = 0, B_M1, B_M23, B_M13, B_LN, B_P13, B_P13LN, B_P23 };
+
+// Device view of one event's bin tables (frequency-major, padded to n_pad).
+struct DevEvent {
+    int n_bins, n_pad, n_det, pn_order;
+    double f_low, df;
+    const double* basis;     // [NBASIS][n_pad]
+    const double* freq;      // [n_pad]
+    const float2* u32;       // [n_det][n_pad]  4 df conj(d) f^-7/6 / (S u_scale), FP32
+    const double2* u64;      // [n_det][n_pad]  same in FP64
+    double hnorm[MAXDET];    // sum_j 4 df f^-7/3 / S / u_scale^2
+    double dd;               // sum_d <d|d>_d
+    double u_scale;          // power of two keeping the FP32 table near unit magnitude
+    double t_sun, mpc_m, c_light, gmst;
+    double pos[MAXDET][3];   // detector positions [m]
+    double resp[MAXDET][3][3];
+};
+
+// Sampled-coordinate map into the 11 source parameters.
+struct ParamMap {
+    int dim;
+    int idx[MAXDIM];
+    double fixed[NPAR];
+};
+
+// Per-particle coefficient block written by the prologue kernel (FP64).
+// The first CB_BINS entries are all the bin loop reads.
+enum {
+    CB_C = 0,                            // NCOEF phase coefficients (cycles): const, then basis rows
+    CB_TAU = CB_C + NCOEF,               // MAXDET: t_c + delay of each detector
+    CB_PR = CB_TAU + MAXDET,             // MAXDET: Re of C_A u_scale P_d
+    CB_PI = CB_PR + MAXDET,              // MAXDET: Im of C_A u_scale P_d
+    CB_BINS = CB_PI + MAXDET,
+    CB_DC = CB_BINS,                     // [NCOEF][4]: d c_b / d(Mc, q, chi1, chi2)
+    CB_DTAU = CB_DC + 4 * NCOEF,         // [MAXDET][2]: d tau_d / d(ra, dec)
+    CB_DPR = CB_DTAU + 2 * MAXDET,       // [MAXDET][4]: d Re P'_d / d(iota, psi, ra, dec)
+    CB_DPI = CB_DPR + 4 * MAXDET,        // [MAXDET][4]: d Im P'_d / d(iota, psi, ra, dec)
+    CB_DLNCA_MC = CB_DPI + 4 * MAXDET,   // d ln C_A / d Mc
+    CB_DLNCA_DL = CB_DLNCA_MC + 1,       // d ln C_A / d d_L
+    CB_SIZE = 104
+};
+static_assert(CB_DLNCA_DL < CB_SIZE, "coefficient block overflow");
+
+// Per-particle bin moments written by the bin loop (FP64).
+enum {
+    MOM_ZR = 0,                 // MAXDET: Re Z_d = Re sum_j u_dj e^{-2 pi i Phi_dj}
+    MOM_ZI = MOM_ZR + MAXDET,   // MAXDET: Im Z_d
+    MOM_G = MOM_ZI + MAXDET,    // NCOEF: sum_j psibar_j B_b(f_j) (b = const first)
+    MOM_T = MOM_G + NCOEF,      // MAXDET: sum_j q_dj f_j
+    MOM_SIZE = 24
+};
+static_assert(MOM_T + MAXDET <= MOM_SIZE, "moment block overflow");
+
+// ------------------------------------------------------------- host launchers
+// (each .hip file exposes host functions; kernels stay in their own unit)
+hipError_t launch_build_tables(const double* d_data, const double* d_psd, int n_det, int n_bins, int n_pad,
+                               double f_low, double df, double u_scale, double* basis, double* freq, float2* u32,
+                               double2* u64, double* sums, hipStream_t s);
+hipError_t launch_prep(const DevEvent* d_events, const int32_t* ev_of_p, const ParamMap& pm, int P,
+                       const double* theta, double* cb, hipStream_t s);
+hipError_t launch_bins(const DevEvent* d_events, const int32_t* ev_of_p, int P, int n_det, int precision,
+                       const double* cb, double* mom, hipStream_t s);
+hipError_t launch_finish(const DevEvent* d_events, const int32_t* ev_of_p, const ParamMap& pm, int P,
+                         const double* cb, const double* mom, double* logl, double* grad, hipStream_t s);
+hipError_t launch_waveform(const DevEvent* d_events, int event_id, const double* cb, double* h_reim, int n_bins,
+                           int n_det, hipStream_t s);
+
+}  // namespace smcgw

@@ -1,0 +1,62 @@
+// The opaque context behind smcgw_ctx (host side only).
+#pragma once
+
+#include <vector>
+
+#include "common.h"
+
+// Prior / boundary of the sampled coordinates, passed to kernels by value.
+namespace smcgw {
+struct PriorDesc {
+    int dim;
+    double lo[MAXDIM], hi[MAXDIM];
+    int bnd[MAXDIM], kind[MAXDIM];
+};
+
+// Likelihood selector for the sampler kernels, passed by value.
+struct TargetDesc {
+    int kind;                 // SMCGW_TARGET_*
+    int dim;
+    const double* params;     // device copy of the analytic target's parameters
+};
+}  // namespace smcgw
+
+struct smcgw_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int n_det = 0;
+    std::vector<smcgw::DevEvent> events;
+    std::vector<void*> event_bufs;
+    smcgw::DevEvent* d_events = nullptr;
+    void* d_small = nullptr;               // 4 KiB staging buffer
+    smcgw::ParamMap pmap;
+    // likelihood scratch, sized for `cap` particles
+    double* d_cb = nullptr;
+    double* d_mom = nullptr;
+    int cap = 0;
+    // sampler state
+    bool prior_set = false;
+    smcgw::PriorDesc prior{};
+    smcgw::TargetDesc target{SMCGW_TARGET_GW, 0, nullptr};
+    double* d_target_params = nullptr;
+    // sampler scratch
+    void* d_sampler = nullptr;
+    size_t sampler_bytes = 0;
+    double* h_pinned = nullptr;            // small pinned host buffer for scalar read-backs
+
+    void sampler_free() {
+        hipFree(d_target_params);
+        hipFree(d_sampler);
+        if (h_pinned) hipHostFree(h_pinned);
+        d_target_params = nullptr;
+        d_sampler = nullptr;
+        h_pinned = nullptr;
+        sampler_bytes = 0;
+    }
+};
+
+namespace smcgw {
+int ctx_reserve(smcgw_ctx* c, int P);
+int ctx_loglike(smcgw_ctx* c, int P, const int32_t* ev_of_p, const double* theta, double* logl, double* grad,
+                int precision);
+}  // namespace smcgw

@@ -1,0 +1,88 @@
+// Event bin tables (built once per event, frequency-major).
+//
+// For the inner product of arXiv:2601.02336 Sec. 2 (Eq. 2) discretised on
+// f_j = f_low + j df, every particle reuses the same per-bin quantities:
+//   u_dj = 4 df conj(d_dj) f_j^-7/6 / S_dj            (whitened data x amplitude shape)
+//   B_b(f_j)                                        (phase basis rows)
+//   H_d  = sum_j 4 df f_j^-7/3 / S_dj,  <d|d>_d = sum_j 4 df |d_dj|^2 / S_dj.
+// The tables are zero-padded to a multiple of TABLE_PAD bins; padded bins have
+// u = 0 and finite basis values, so they add nothing to any sum.
+#include "common.h"
+
+namespace smcgw {
+
+__global__ __launch_bounds__(256) void build_tables_kernel(const double* __restrict__ data, const double* __restrict__ psd,
+                                                           int n_det, int n, int npad, double f_low, double df,
+                                                           double inv_us, double* __restrict__ basis,
+                                                           double* __restrict__ freq, float2* __restrict__ u32,
+                                                           double2* __restrict__ u64) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= npad) return;
+    const double f = f_low + df * (double)j;
+    const double lf = log(f);
+    const double f13 = cbrt(f);
+    basis[(size_t)B_M53 * npad + j] = pow(f, -5.0 / 3.0);
+    basis[(size_t)B_M1 * npad + j] = 1.0 / f;
+    basis[(size_t)B_M23 * npad + j] = pow(f, -2.0 / 3.0);
+    basis[(size_t)B_M13 * npad + j] = 1.0 / f13;
+    basis[(size_t)B_LN * npad + j] = lf;
+    basis[(size_t)B_P13 * npad + j] = f13;
+    basis[(size_t)B_P13LN * npad + j] = f13 * lf;
+    basis[(size_t)B_P23 * npad + j] = pow(f, 2.0 / 3.0);
+    freq[j] = f;
+    const double a = pow(f, -7.0 / 6.0);
+    for (int d = 0; d < n_det; ++d) {
+        double ur = 0.0, ui = 0.0;
+        if (j < n) {
+            const double w = 4.0 * df / psd[(size_t)d * n + j];
+            const double* dd = data + 2 * ((size_t)d * n + j);
+            ur = w * a * dd[0] * inv_us;
+            ui = -w * a * dd[1] * inv_us;
+        }
+        u64[(size_t)d * npad + j] = make_double2(ur, ui);
+        u32[(size_t)d * npad + j] = make_float2((float)ur, (float)ui);
+    }
+}
+
+// One workgroup per detector: sums[2d] = H_d, sums[2d+1] = <d|d>_d (fixed-order tree).
+__global__ __launch_bounds__(256) void table_sums_kernel(const double* __restrict__ data, const double* __restrict__ psd,
+                                                         int n, double f_low, double df, double* __restrict__ sums) {
+    __shared__ double sh[2][256];
+    const int d = blockIdx.x;
+    double h = 0.0, dd = 0.0;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        const double f = f_low + df * (double)j;
+        const double w = 4.0 * df / psd[(size_t)d * n + j];
+        const double a = pow(f, -7.0 / 6.0);
+        const double* x = data + 2 * ((size_t)d * n + j);
+        h += w * a * a;
+        dd += w * (x[0] * x[0] + x[1] * x[1]);
+    }
+    sh[0][threadIdx.x] = h;
+    sh[1][threadIdx.x] = dd;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + s];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        sums[2 * d] = sh[0][0];
+        sums[2 * d + 1] = sh[1][0];
+    }
+}
+
+hipError_t launch_build_tables(const double* d_data, const double* d_psd, int n_det, int n_bins, int n_pad,
+                               double f_low, double df, double u_scale, double* basis, double* freq, float2* u32,
+                               double2* u64, double* sums, hipStream_t s) {
+    hipLaunchKernelGGL(build_tables_kernel, dim3((n_pad + 255) / 256), dim3(256), 0, s, d_data, d_psd, n_det, n_bins,
+                       n_pad, f_low, df, 1.0 / u_scale, basis, freq, u32, u64);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(table_sums_kernel, dim3(n_det), dim3(256), 0, s, d_data, d_psd, n_bins, f_low, df, sums);
+    return hipGetLastError();
+}
+
+}  // namespace smcgw

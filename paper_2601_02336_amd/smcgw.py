@@ -1,0 +1,247 @@
+"""Python binding of libsmcgw.so (argument marshalling only).
+
+Every computation runs in the HIP library; PyTorch supplies device memory
+(tensors' data pointers) and the current HIP stream.  The functions mirror
+the C ABI in include/smcgw.h.  Importing this module on a machine without
+the built library raises immediately: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import synth
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "lib", "libsmcgw.so")
+
+OK, WARN_FALLBACK = 0, 1
+ERR_INVALID, ERR_SHAPE, ERR_HIP, ERR_OOM, ERR_NOT_INIT, ERR_STALL = -1, -2, -3, -4, -5, -6
+PLAIN_FP64, MIXED = 0, 1
+
+
+class SmcgwError(RuntimeError):
+    def __init__(self, fn: str, code: int):
+        super().__init__(f"{fn} failed: {code} ({status_string(code)})")
+        self.code = code
+
+
+class EventDesc(C.Structure):
+    _fields_ = [("f_low", C.c_double), ("df", C.c_double), ("n_bins", C.c_int32), ("n_det", C.c_int32),
+                ("gmst", C.c_double), ("t_sun", C.c_double), ("mpc_m", C.c_double), ("c_light", C.c_double),
+                ("pn_order", C.c_int32), ("reserved", C.c_int32)]
+
+
+class Detector(C.Structure):
+    _fields_ = [("lat", C.c_double), ("lon", C.c_double), ("az_x", C.c_double), ("az_y", C.c_double),
+                ("radius", C.c_double)]
+
+
+class Bounds(C.Structure):
+    _fields_ = [("lo", C.c_double), ("hi", C.c_double), ("bnd", C.c_int32), ("prior", C.c_int32)]
+
+
+class NutsParams(C.Structure):
+    _fields_ = [("step", C.c_double), ("beta", C.c_double), ("max_delta_h", C.c_double),
+                ("max_depth", C.c_int32), ("uturn", C.c_int32), ("seed", C.c_uint64), ("iteration", C.c_uint64)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libsmcgw.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError(f"{_LIB_PATH} is missing: run `python -m paper_2601_02336_amd.build` "
+                               "(or __graft_entry__.build()) first; there is no fallback path")
+        L = C.CDLL(_LIB_PATH)
+        vp, i, d, u64 = C.c_void_p, C.c_int, C.c_double, C.c_uint64
+        L.smcgw_status_string.restype = C.c_char_p
+        L.smcgw_status_string.argtypes = [i]
+        L.smcgw_create.argtypes = [C.POINTER(vp), i, vp]
+        L.smcgw_destroy.argtypes = [vp]
+        L.smcgw_set_stream.argtypes = [vp, vp]
+        L.smcgw_add_event.argtypes = [vp, C.POINTER(EventDesc), vp, vp, C.POINTER(Detector), C.POINTER(i)]
+        L.smcgw_set_param_map.argtypes = [vp, i, vp, vp]
+        L.smcgw_set_prior.argtypes = [vp, i, C.POINTER(Bounds)]
+        L.smcgw_set_target.argtypes = [vp, i, i, vp, i]
+        L.smcgw_loglike_grad.argtypes = [vp, i, vp, vp, vp, vp, i]
+        L.smcgw_waveform.argtypes = [vp, i, vp, vp]
+        L.smcgw_mass_matrix.argtypes = [vp, i, i, vp, d, vp, vp]
+        L.smcgw_nuts_step.argtypes = [vp, i, i, vp, vp, vp, vp, C.POINTER(NutsParams), vp, i, vp, vp, vp, vp]
+        L.smcgw_smc_reweight_resample.argtypes = [vp, i, i, d, d, u64, u64, vp, vp, vp, vp,
+                                                  C.POINTER(d), C.POINTER(d)]
+        _lib = L
+    return _lib
+
+
+def status_string(code: int) -> str:
+    return lib().smcgw_status_string(code).decode()
+
+
+def _check(fn: str, rc: int, allow=(OK,)) -> int:
+    if rc not in allow:
+        raise SmcgwError(fn, rc)
+    return rc
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _dev(t: torch.Tensor, dtype, name: str) -> torch.Tensor:
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {dtype} tensor")
+    return t
+
+
+class Context:
+    """One library context on one device, enqueueing on torch's current stream."""
+
+    def __init__(self, device: int = 0):
+        self.device = device
+        self._h = C.c_void_p()
+        with torch.cuda.device(device):
+            s = torch.cuda.current_stream(device).cuda_stream
+        _check("smcgw_create", lib().smcgw_create(C.byref(self._h), device, C.c_void_p(s)))
+        self.events = []
+
+    def close(self):
+        if self._h:
+            lib().smcgw_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _stream(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        lib().smcgw_set_stream(self._h, C.c_void_p(s))
+
+    # ------------------------------------------------------------ set-up
+    def add_event(self, ev: "synth.Event") -> int:
+        desc = EventDesc(ev.f_low, ev.df, ev.n, ev.n_det, ev.gmst, ev.t_sun, ev.mpc_m, ev.c_light, ev.pn_order, 0)
+        dets = (Detector * ev.n_det)(*[Detector(*s.as_tuple()) for s in ev.sites])
+        data = np.ascontiguousarray(ev.data_reim(), dtype=np.float64)
+        psd = np.ascontiguousarray(ev.psd, dtype=np.float64)
+        eid = C.c_int()
+        self._stream()
+        _check("smcgw_add_event", lib().smcgw_add_event(self._h, C.byref(desc), data.ctypes.data_as(C.c_void_p),
+                                                        psd.ctypes.data_as(C.c_void_p), dets, C.byref(eid)))
+        self.events.append(ev)
+        return eid.value
+
+    def set_param_map(self, param_index: Sequence[int], fixed11: Optional[Sequence[float]] = None):
+        idx = np.ascontiguousarray(param_index, dtype=np.int32)
+        fx = None if fixed11 is None else np.ascontiguousarray(fixed11, dtype=np.float64)
+        _check("smcgw_set_param_map", lib().smcgw_set_param_map(
+            self._h, len(idx), idx.ctypes.data_as(C.c_void_p), None if fx is None else fx.ctypes.data_as(C.c_void_p)))
+
+    def set_prior(self, bounds):
+        arr = (Bounds * len(bounds))(*[Bounds(b.lo, b.hi, b.bnd, b.prior) for b in bounds])
+        _check("smcgw_set_prior", lib().smcgw_set_prior(self._h, len(bounds), arr))
+
+    def set_target(self, kind: int, dim: int, params: Optional[Sequence[float]] = None):
+        p = None if params is None else np.ascontiguousarray(params, dtype=np.float64)
+        self._stream()
+        _check("smcgw_set_target", lib().smcgw_set_target(
+            self._h, kind, dim, None if p is None else p.ctypes.data_as(C.c_void_p), 0 if p is None else p.size))
+
+    # ------------------------------------------------------------ hot path
+    def loglike_grad(self, theta: torch.Tensor, logl: Optional[torch.Tensor] = None,
+                     grad: Optional[torch.Tensor] = None, want_grad: bool = True,
+                     event_of_particle: Optional[torch.Tensor] = None, precision: int = MIXED):
+        theta = _dev(theta, torch.float64, "theta")
+        P = theta.shape[0]
+        if logl is None:
+            logl = torch.empty(P, dtype=torch.float64, device=theta.device)
+        if want_grad and grad is None:
+            grad = torch.empty_like(theta)
+        if event_of_particle is not None:
+            _dev(event_of_particle, torch.int32, "event_of_particle")
+        self._stream()
+        _check("smcgw_loglike_grad", lib().smcgw_loglike_grad(
+            self._h, P, _ptr(event_of_particle), _ptr(theta), _ptr(logl), _ptr(grad) if want_grad else None,
+            precision))
+        return (logl, grad) if want_grad else logl
+
+    def waveform(self, event_id: int, theta11) -> torch.Tensor:
+        ev = self.events[event_id]
+        th = np.ascontiguousarray(theta11, dtype=np.float64)
+        h = torch.empty((ev.n_det, ev.n, 2), dtype=torch.float64, device=f"cuda:{self.device}")
+        self._stream()
+        _check("smcgw_waveform", lib().smcgw_waveform(self._h, event_id, th.ctypes.data_as(C.c_void_p), _ptr(h)))
+        return h
+
+    def mass_matrix(self, theta: torch.Tensor, shrink: float = 0.0):
+        theta = _dev(theta, torch.float64, "theta")
+        P, D = theta.shape
+        inv = torch.empty((D, D), dtype=torch.float64, device=theta.device)
+        L = torch.empty_like(inv)
+        self._stream()
+        rc = _check("smcgw_mass_matrix", lib().smcgw_mass_matrix(self._h, P, D, _ptr(theta), shrink, _ptr(inv),
+                                                                 _ptr(L)), allow=(OK, WARN_FALLBACK))
+        return inv, L, rc
+
+    def nuts_step(self, theta: torch.Tensor, logl: torch.Tensor, grad: torch.Tensor, chol: torch.Tensor,
+                  step: float, beta: float, seed: int, iteration: int, max_depth: int = 10, uturn: bool = True,
+                  max_delta_h: float = 1000.0, max_depth_per_particle: Optional[torch.Tensor] = None,
+                  precision: int = MIXED, diagnostics: bool = True):
+        theta = _dev(theta, torch.float64, "theta")
+        P, D = theta.shape
+        prm = NutsParams(step, beta, max_delta_h, max_depth, 1 if uturn else 0, seed, iteration)
+        dev = theta.device
+        out = {}
+        if diagnostics:
+            out = dict(depth=torch.zeros(P, dtype=torch.int32, device=dev),
+                       n_leapfrog=torch.zeros(P, dtype=torch.int32, device=dev),
+                       divergent=torch.zeros(P, dtype=torch.uint8, device=dev),
+                       accept_stat=torch.zeros(P, dtype=torch.float64, device=dev))
+        if max_depth_per_particle is not None:
+            _dev(max_depth_per_particle, torch.int32, "max_depth_per_particle")
+        self._stream()
+        _check("smcgw_nuts_step", lib().smcgw_nuts_step(
+            self._h, P, D, _ptr(theta), _ptr(logl), _ptr(grad), _ptr(chol), C.byref(prm),
+            _ptr(max_depth_per_particle), precision, _ptr(out.get("depth")), _ptr(out.get("n_leapfrog")),
+            _ptr(out.get("divergent")), _ptr(out.get("accept_stat"))))
+        return out
+
+    def smc_reweight_resample(self, theta: torch.Tensor, logl: torch.Tensor, grad: Optional[torch.Tensor],
+                              beta_prev: float, alpha: float, seed: int, iteration: int,
+                              ancestors: Optional[torch.Tensor] = None):
+        theta = _dev(theta, torch.float64, "theta")
+        P, D = theta.shape
+        if ancestors is None:
+            ancestors = torch.empty(P, dtype=torch.int32, device=theta.device)
+        b = C.c_double()
+        dz = C.c_double()
+        self._stream()
+        rc = lib().smcgw_smc_reweight_resample(self._h, P, D, beta_prev, alpha, seed, iteration, _ptr(theta),
+                                               _ptr(logl), _ptr(grad), _ptr(ancestors), C.byref(b), C.byref(dz))
+        _check("smcgw_smc_reweight_resample", rc)
+        return b.value, dz.value, ancestors
+
+
+class LogLikelihood(torch.autograd.Function):
+    """logL(theta) with the hand-written adjoint as its backward pass."""
+
+    @staticmethod
+    def forward(ctx_, theta: torch.Tensor, context: Context, precision: int = MIXED):
+        logl, grad = context.loglike_grad(theta.detach().contiguous(), precision=precision)
+        ctx_.save_for_backward(grad)
+        return logl
+
+    @staticmethod
+    def backward(ctx_, grad_out):
+        (grad,) = ctx_.saved_tensors
+        return grad_out[:, None] * grad, None, None

@@ -1,0 +1,180 @@
+"""Parity of the HIP likelihood / adjoint gradient with the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2601_02336_amd import synth
+from oracle import oracle as O
+
+from helpers import CONFIG0_INDEX, TOL, event, grad_err, logl_rel_err, widths
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def smc():
+    from paper_2601_02336_amd import smcgw
+    return smcgw
+
+
+def _ctx(smc, ev, idx=None):
+    c = smc.Context(0)
+    c.add_event(ev)
+    if idx is not None:
+        c.set_param_map(idx, ev.theta_inj)
+    return c
+
+
+def _compare(smc, ev, idx, P, seed, precisions=("plain", "mixed")):
+    full = synth.gw_prior_for(ev)
+    b = [full[i] for i in idx]
+    x = synth.prior_draw(np.random.default_rng(seed), P, b)
+    tgt = O.gw_target(ev, param_index=idx)
+    ll_ref, g_ref = O.loglike_grad(tgt, x)
+    c = _ctx(smc, ev, idx)
+    xt = torch.tensor(x, device="cuda")
+    w = widths(b)
+    for name in precisions:
+        prec = smc.PLAIN_FP64 if name == "plain" else smc.MIXED
+        ll, g = c.loglike_grad(xt, precision=prec)
+        torch.cuda.synchronize()
+        ll, g = ll.cpu().numpy(), g.cpu().numpy()
+        e_ll, e_g = logl_rel_err(ll, ll_ref), grad_err(g, g_ref, w)
+        print(f"{name}: P={P} N={ev.n} ndet={ev.n_det} logL rel err {e_ll:.3e} grad err {e_g:.3e}", flush=True)
+        assert e_ll <= TOL[name]["logl"], (name, e_ll)
+        assert e_g <= TOL[name]["grad"], (name, e_g)
+    c.close()
+
+
+def test_parity_one_detector_four_params(smc):
+    """1 detector, 1969 bins, (Mc, q, t_c, phi_c); P = 37 leaves a partial workgroup."""
+    _compare(smc, event(synth.SPEC_SMALL), CONFIG0_INDEX, 37, 1)
+
+
+def test_parity_three_detectors_eleven_params(smc):
+    """3 detectors, 8033 bins (ragged tail of the 512-bin padding), 11 params."""
+    _compare(smc, event(synth.SPEC_8S), list(range(11)), 45, 2)
+
+
+def test_parity_full_size_sampled(smc):
+    """4096 particles in one launch; the oracle checks a spread sample of them."""
+    ev = event(synth.SPEC_8S)
+    b = synth.gw_prior_for(ev)
+    x = synth.prior_draw(np.random.default_rng(7), 4096, b)
+    c = _ctx(smc, ev)
+    xt = torch.tensor(x, device="cuda")
+    pick = np.array([0, 1, 63, 64, 255, 1000, 2047, 2048, 3001, 4094, 4095])
+    ll_ref, g_ref = O.loglike_grad(O.gw_target(ev), x[pick])
+    for name, prec in (("plain", smc.PLAIN_FP64), ("mixed", smc.MIXED)):
+        ll, g = c.loglike_grad(xt, precision=prec)
+        ll, g = ll.cpu().numpy(), g.cpu().numpy()
+        assert np.all(np.isfinite(ll)) and np.all(np.isfinite(g))
+        e_ll, e_g = logl_rel_err(ll[pick], ll_ref), grad_err(g[pick], g_ref, widths(b))
+        print(f"{name} full: logL {e_ll:.3e} grad {e_g:.3e}", flush=True)
+        assert e_ll <= TOL[name]["logl"] and e_g <= TOL[name]["grad"]
+    c.close()
+
+
+def test_parity_long_segment_sampled(smc):
+    """128 s segment, 20-2048 Hz (259585 bins), SNR 30: sampled particles."""
+    ev = event(synth.SPEC_128S)
+    b = synth.gw_prior_for(ev)
+    x = synth.prior_draw(np.random.default_rng(8), 256, b)
+    c = _ctx(smc, ev)
+    xt = torch.tensor(x, device="cuda")
+    pick = np.array([0, 131, 255])
+    ll_ref, g_ref = O.loglike_grad(O.gw_target(ev), x[pick])
+    for name, prec in (("plain", smc.PLAIN_FP64), ("mixed", smc.MIXED)):
+        ll, g = c.loglike_grad(xt, precision=prec)
+        ll, g = ll.cpu().numpy(), g.cpu().numpy()
+        e_ll, e_g = logl_rel_err(ll[pick], ll_ref), grad_err(g[pick], g_ref, widths(b))
+        print(f"{name} 128s: logL {e_ll:.3e} grad {e_g:.3e}", flush=True)
+        assert e_ll <= TOL[name]["logl"] and e_g <= TOL[name]["grad"]
+    c.close()
+
+
+def test_ragged_events_one_launch(smc):
+    """Two events of different lengths (4 s and 8 s) batched through event_of_particle."""
+    specs = synth.ragged_specs()
+    evs = [event(specs[0]), event(specs[2])]
+    c = smc.Context(0)
+    for e in evs:
+        c.add_event(e)
+    rng = np.random.default_rng(9)
+    P = 24
+    eop = (np.arange(P) % 2).astype(np.int32)
+    x = np.concatenate([synth.prior_draw(rng, 1, synth.gw_prior_for(evs[k])) for k in eop])
+    xt = torch.tensor(x, device="cuda")
+    ll, g = c.loglike_grad(xt, event_of_particle=torch.tensor(eop, device="cuda"), precision=smc.MIXED)
+    ll, g = ll.cpu().numpy(), g.cpu().numpy()
+    for k in range(2):
+        sel = eop == k
+        ll_ref, g_ref = O.loglike_grad(O.gw_target(evs[k]), x[sel])
+        assert logl_rel_err(ll[sel], ll_ref) <= TOL["mixed"]["logl"]
+        assert grad_err(g[sel], g_ref, widths(synth.gw_prior_for(evs[k]))) <= TOL["mixed"]["grad"]
+    c.close()
+
+
+def test_waveform_parity(smc):
+    ev = event(synth.SPEC_8S)
+    c = _ctx(smc, ev)
+    th = synth.prior_draw(np.random.default_rng(4), 1, synth.gw_prior_for(ev))[0]
+    h = c.waveform(0, th).cpu().numpy()
+    h = h[..., 0] + 1j * h[..., 1]
+    ref = O.waveform(ev, th)
+    assert np.max(np.abs(h - ref)) / np.max(np.abs(ref)) < 1e-11
+    c.close()
+
+
+def test_zero_noise_maximum(smc):
+    ev0 = event(synth.SPEC_8S)
+    ev = ev0.with_data(O.waveform(ev0, ev0.theta_inj))
+    c = _ctx(smc, ev)
+    ll, g = c.loglike_grad(torch.tensor(ev.theta_inj[None, :], device="cuda"), precision=smc.PLAIN_FP64)
+    dd = float(np.sum(4 * ev.df * np.abs(ev.data) ** 2 / ev.psd))
+    assert abs(ll.item()) < 1e-9 * dd
+    w = widths(synth.gw_prior_for(ev))
+    # relative to the gradient scale at a nearby point
+    th2 = ev.theta_inj.copy()
+    th2[9] += 1e-4
+    _, g2 = c.loglike_grad(torch.tensor(th2[None, :], device="cuda"), precision=smc.PLAIN_FP64)
+    assert np.max(np.abs(g.cpu().numpy()) * w) < 1e-7 * np.max(np.abs(g2.cpu().numpy()) * w)
+    c.close()
+
+
+def test_deterministic_and_empty(smc):
+    ev = event(synth.SPEC_SMALL)
+    c = _ctx(smc, ev, CONFIG0_INDEX)
+    x = torch.tensor(synth.prior_draw(np.random.default_rng(3), 130, [synth.gw_prior_for(ev)[i] for i in CONFIG0_INDEX]),
+                     device="cuda")
+    a = c.loglike_grad(x, precision=smc.MIXED)
+    b = c.loglike_grad(x, precision=smc.MIXED)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    ll = c.loglike_grad(x[:0], precision=smc.MIXED)
+    assert ll[0].numel() == 0
+    one = c.loglike_grad(x[:1].contiguous(), precision=smc.MIXED)
+    assert torch.equal(one[0], a[0][:1])
+    c.close()
+
+
+def test_autograd_function(smc):
+    ev = event(synth.SPEC_SMALL)
+    c = _ctx(smc, ev, CONFIG0_INDEX)
+    x = torch.tensor(synth.prior_draw(np.random.default_rng(5), 8, [synth.gw_prior_for(ev)[i] for i in CONFIG0_INDEX]),
+                     device="cuda", requires_grad=True)
+    ll = smc.LogLikelihood.apply(x, c, smc.PLAIN_FP64)
+    (2.0 * ll.sum()).backward()
+    _, g = c.loglike_grad(x.detach(), precision=smc.PLAIN_FP64)
+    assert torch.allclose(x.grad, 2.0 * g, rtol=0, atol=0)
+    c.close()
+
+
+def test_invalid_calls_raise(smc):
+    c = smc.Context(0)
+    x = torch.zeros((4, 11), dtype=torch.float64, device="cuda")
+    with pytest.raises(smc.SmcgwError):
+        c.loglike_grad(x)           # no event added
+    c.add_event(event(synth.SPEC_SMALL))
+    with pytest.raises(smc.SmcgwError):
+        c.loglike_grad(x, precision=7)
+    c.close()
