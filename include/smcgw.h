@@ -188,6 +188,17 @@ int smcgw_smc_reweight_resample(smcgw_ctx *ctx, int P, int D, double beta_prev, 
                                 uint64_t iteration, double *theta, double *logl, double *grad, int32_t *ancestors,
                                 double *beta_next_host, double *dlogz_host);
 
+/* ------------------------------------------------------------ timing
+ * Kernel timing for measurement: HIP events are recorded on the context's
+ * stream around every launch of the kernel classes whose bit is set in
+ * class_mask (bit c = class c; 0 turns timing off).
+ * smcgw_timing_read synchronises, returns the summed duration [ms] and the
+ * launch count of one class since the last read, and resets that class. */
+enum { SMCGW_KERNEL_BINS = 0, SMCGW_KERNEL_PREP = 1, SMCGW_KERNEL_FINISH = 2, SMCGW_KERNEL_NUTS = 3,
+       SMCGW_KERNEL_SMC = 4, SMCGW_KERNEL_CLASSES = 5 };
+int smcgw_timing_enable(smcgw_ctx *ctx, int class_mask);
+int smcgw_timing_read(smcgw_ctx *ctx, int kernel_class, double *total_ms, int64_t *launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -27,6 +27,30 @@ extern "C" const char* smcgw_status_string(int status) {
 
 namespace smcgw {
 
+static hipEvent_t pool_event(smcgw_ctx* c) {
+    if (!c->ev_pool.empty()) {
+        hipEvent_t e = c->ev_pool.back();
+        c->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+TimedLaunch::TimedLaunch(smcgw_ctx* ctx, int kernel_class) : c(ctx), cls(kernel_class) {
+    if (!on()) return;
+    a = pool_event(c);
+    b = pool_event(c);
+    if (a) hipEventRecord(a, c->stream);
+}
+
+TimedLaunch::~TimedLaunch() {
+    if (!on() || !a || !b) return;
+    hipEventRecord(b, c->stream);
+    c->ev_pending[cls].push_back({a, b});
+}
+
 int ctx_reserve(smcgw_ctx* c, int P) {
     if (P <= c->cap) return SMCGW_OK;
     const int cap = std::max(P, std::max(2 * c->cap, 256));
@@ -47,11 +71,21 @@ int ctx_loglike(smcgw_ctx* c, int P, const int32_t* ev_of_p, const double* theta
     if (c->events.empty()) return SMCGW_ERR_NOT_INIT;
     int rc = ctx_reserve(c, P);
     if (rc) return rc;
-    if (launch_prep(c->d_events, ev_of_p, c->pmap, P, theta, c->d_cb, c->stream) != hipSuccess) return SMCGW_ERR_HIP;
-    if (launch_bins(c->d_events, ev_of_p, P, c->n_det, precision, c->d_cb, c->d_mom, c->stream) != hipSuccess)
-        return SMCGW_ERR_HIP;
-    if (launch_finish(c->d_events, ev_of_p, c->pmap, P, c->d_cb, c->d_mom, logl, grad, c->stream) != hipSuccess)
-        return SMCGW_ERR_HIP;
+    {
+        TimedLaunch t(c, SMCGW_KERNEL_PREP);
+        if (launch_prep(c->d_events, ev_of_p, c->pmap, P, theta, c->d_cb, c->stream) != hipSuccess)
+            return SMCGW_ERR_HIP;
+    }
+    {
+        TimedLaunch t(c, SMCGW_KERNEL_BINS);
+        if (launch_bins(c->d_events, ev_of_p, P, c->n_det, precision, c->d_cb, c->d_mom, c->stream) != hipSuccess)
+            return SMCGW_ERR_HIP;
+    }
+    {
+        TimedLaunch t(c, SMCGW_KERNEL_FINISH);
+        if (launch_finish(c->d_events, ev_of_p, c->pmap, P, c->d_cb, c->d_mom, logl, grad, c->stream) != hipSuccess)
+            return SMCGW_ERR_HIP;
+    }
     return SMCGW_OK;
 }
 
@@ -88,7 +122,38 @@ extern "C" int smcgw_destroy(smcgw_ctx* c) {
     hipFree(c->d_cb);
     hipFree(c->d_mom);
     c->sampler_free();
+    for (auto& v : c->ev_pending)
+        for (auto& pr : v) { hipEventDestroy(pr.first); hipEventDestroy(pr.second); }
+    for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
     delete c;
+    return SMCGW_OK;
+}
+
+extern "C" int smcgw_timing_enable(smcgw_ctx* c, int class_mask) {
+    if (!c || class_mask < 0 || class_mask >= (1 << SMCGW_KERNEL_CLASSES)) return SMCGW_ERR_INVALID;
+    c->timing_mask = (unsigned)class_mask;
+    return SMCGW_OK;
+}
+
+extern "C" int smcgw_timing_read(smcgw_ctx* c, int kernel_class, double* total_ms, int64_t* launches) {
+    if (!c || kernel_class < 0 || kernel_class >= SMCGW_KERNEL_CLASSES || !total_ms || !launches)
+        return SMCGW_ERR_INVALID;
+    hipSetDevice(c->device);
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return SMCGW_ERR_HIP;
+    double tot = 0.0;
+    int64_t n = 0;
+    for (auto& pr : c->ev_pending[kernel_class]) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) {
+            tot += ms;
+            ++n;
+        }
+        c->ev_pool.push_back(pr.first);
+        c->ev_pool.push_back(pr.second);
+    }
+    c->ev_pending[kernel_class].clear();
+    *total_ms = tot;
+    *launches = n;
     return SMCGW_OK;
 }
 

@@ -43,6 +43,10 @@ struct smcgw_ctx {
     void* d_sampler = nullptr;
     size_t sampler_bytes = 0;
     double* h_pinned = nullptr;            // small pinned host buffer for scalar read-backs
+    // kernel timing (events recorded around launches when enabled)
+    unsigned timing_mask = 0;              // bit c: time kernel class c
+    std::vector<hipEvent_t> ev_pool;       // free events
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending[SMCGW_KERNEL_CLASSES];
 
     void sampler_free() {
         hipFree(d_target_params);
@@ -56,6 +60,15 @@ struct smcgw_ctx {
 };
 
 namespace smcgw {
+// Brackets a launch with timing events when the context's timing is on.
+struct TimedLaunch {
+    smcgw_ctx* c;
+    int cls;
+    hipEvent_t a = nullptr, b = nullptr;
+    TimedLaunch(smcgw_ctx* ctx, int kernel_class);
+    bool on() const { return (c->timing_mask >> cls) & 1u; }
+    ~TimedLaunch();
+};
 int ctx_reserve(smcgw_ctx* c, int P);
 int ctx_loglike(smcgw_ctx* c, int P, const int32_t* ev_of_p, const double* theta, double* logl, double* grad,
                 int precision);

@@ -21,6 +21,7 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "lib", "lib
 OK, WARN_FALLBACK = 0, 1
 ERR_INVALID, ERR_SHAPE, ERR_HIP, ERR_OOM, ERR_NOT_INIT, ERR_STALL = -1, -2, -3, -4, -5, -6
 PLAIN_FP64, MIXED = 0, 1
+KERNEL_BINS, KERNEL_PREP, KERNEL_FINISH, KERNEL_NUTS, KERNEL_SMC = 0, 1, 2, 3, 4
 
 
 class SmcgwError(RuntimeError):
@@ -74,6 +75,8 @@ def lib():
         L.smcgw_waveform.argtypes = [vp, i, vp, vp]
         L.smcgw_mass_matrix.argtypes = [vp, i, i, vp, d, vp, vp]
         L.smcgw_nuts_step.argtypes = [vp, i, i, vp, vp, vp, vp, C.POINTER(NutsParams), vp, i, vp, vp, vp, vp]
+        L.smcgw_timing_enable.argtypes = [vp, i]
+        L.smcgw_timing_read.argtypes = [vp, i, C.POINTER(d), C.POINTER(C.c_int64)]
         L.smcgw_smc_reweight_resample.argtypes = [vp, i, i, d, d, u64, u64, vp, vp, vp, vp,
                                                   C.POINTER(d), C.POINTER(d)]
         _lib = L
@@ -127,6 +130,21 @@ class Context:
     def _stream(self):
         s = torch.cuda.current_stream(self.device).cuda_stream
         lib().smcgw_set_stream(self._h, C.c_void_p(s))
+
+    # ------------------------------------------------------------ timing
+    def timing(self, *kernel_classes: int):
+        """Record events around launches of the given kernel classes (none: off)."""
+        mask = 0
+        for k in kernel_classes:
+            mask |= 1 << k
+        _check("smcgw_timing_enable", lib().smcgw_timing_enable(self._h, mask))
+
+    def timing_read(self, kernel_class: int):
+        """(summed milliseconds, launches) of one kernel class since the last read."""
+        ms = C.c_double()
+        n = C.c_int64()
+        _check("smcgw_timing_read", lib().smcgw_timing_read(self._h, kernel_class, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
 
     # ------------------------------------------------------------ set-up
     def add_event(self, ev: "synth.Event") -> int:
