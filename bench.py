@@ -1,12 +1,17 @@
 """Throughput benchmark: logL + gradient evaluations per second on one MI355X.
 
 Workload: one synthetic three-detector event, 8 s at 20-1024 Hz (df = 1/8 Hz,
-8033 bins), 11 source parameters, 4096 particles drawn from the prior, seeded
-injection at network SNR 20 in Gaussian noise.  A step is one batched
-logL + adjoint-gradient evaluation of all particles (prologue, bin loop,
-epilogue).  Prints one JSON line.
+8033 bins), 11 source parameters, seeded injection at network SNR 20 in
+Gaussian noise, particles drawn from the prior.
 
-    python bench.py [--steps K] [--warmup W] [--precision mixed|plain]
+Default (--mode smc): a step is one SMC-NUTS iteration of 2048 particles
+(reweight, adaptive temperature, resampling, population mass matrix and one
+NUTS transition per particle with the likelihood and adjoint gradient at every
+leapfrog step); the value is leapfrog evaluations per second.  --mode loglike:
+a step is one batched logL + gradient evaluation of 4096 particles.  Prints
+one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--mode smc|loglike] [--precision mixed|plain]
 """
 from __future__ import annotations
 
@@ -83,19 +88,76 @@ def cpu_baseline(ev, synth, x_all, budget_s=12.0):
                       f"(forward-mode dual numbers, FP64), {elapsed:.1f} s on {threads} threads"}
 
 
+def smc_setup(smcgw, synth, ev, P, seed=7):
+    import torch
+    ctx = smcgw.Context(0)
+    ctx.add_event(ev)
+    bounds = synth.gw_prior_for(ev)
+    ctx.set_prior(bounds)
+    ctx.set_target(synth.TARGET_GW, 11)
+    x_np = synth.prior_draw(np.random.default_rng(seed), P, bounds)
+    return ctx, x_np, torch.tensor(x_np, device="cuda")
+
+
+def run_smc_steps(smcgw, ctx, theta, precision, args, n_warm, n_steps, time_kernels):
+    """SMC iterations from prior draws; returns (evals, seconds, nuts kernel ms, launches, per-step stats)."""
+    import torch
+    logl, grad = ctx.target_loglike_grad(theta, precision=precision)
+    beta, it = 0.0, 0
+    stats = []
+
+    def one_step():
+        nonlocal beta, it
+        b, dz, _ = ctx.smc_reweight_resample(theta, logl, grad, beta, args.alpha, args.seed, it)
+        _, L, _ = ctx.mass_matrix(theta, 0.0)
+        out = ctx.nuts_step(theta, logl, grad, L, step=args.step, beta=b, seed=args.seed, iteration=it,
+                            max_depth=args.max_depth, precision=precision)
+        beta = b
+        it += 1
+        return out
+
+    nlf = torch.zeros((), dtype=torch.int64, device="cuda")
+    for _ in range(n_warm):
+        out = one_step()
+        nlf += out["n_leapfrog"].sum()   # warm up the same device work as the timed steps
+    nlf.zero_()
+    torch.cuda.synchronize()
+    ctx.timing_read(smcgw.KERNEL_NUTS)
+    if time_kernels:
+        ctx.timing(smcgw.KERNEL_NUTS)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(n_steps):
+        out = one_step()
+        nlf += out["n_leapfrog"].sum()
+        stats.append((beta, out["depth"]))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.timing()
+    k_ms, k_n = ctx.timing_read(smcgw.KERNEL_NUTS)
+    depth_hist = [np.bincount(d.cpu().numpy(), minlength=args.max_depth + 1).tolist() for _, d in stats]
+    return int(nlf.item()), dt, k_ms, k_n, [b for b, _ in stats], depth_hist
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=40)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--particles", type=int, default=4096)
+    ap.add_argument("--steps", type=int, default=8)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--mode", choices=["smc", "loglike"], default="smc",
+                    help="smc: one SMC-NUTS iteration per step; loglike: one batched logL+grad per step")
+    ap.add_argument("--particles", type=int, default=None)
     ap.add_argument("--precision", choices=["mixed", "plain"], default="mixed")
+    ap.add_argument("--alpha", type=float, default=0.95)
+    ap.add_argument("--step", type=float, default=0.5)
+    ap.add_argument("--max-depth", type=int, default=10)
+    ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="skip the plain/forward-only side measurements")
+    ap.add_argument("--no-extra", action="store_true", help="skip the side measurements")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for {args.gpus}); the multi-GPU split is a design note, "
-              "not part of this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); splitting particles across GPUs is "
+              "described in the design notes and not part of this build", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -103,58 +165,95 @@ def main():
 
     log("building event")
     ev = build_event(smcgw, synth)
-    ctx = smcgw.Context(0)
-    ctx.add_event(ev)
-    bounds = synth.gw_prior_for(ev)
-    x_np = synth.prior_draw(np.random.default_rng(7), args.particles, bounds)
-    x = torch.tensor(x_np, device="cuda")
-    P = args.particles
-    logl = torch.empty(P, dtype=torch.float64, device="cuda")
-    grad = torch.empty_like(x)
     prec = smcgw.MIXED if args.precision == "mixed" else smcgw.PLAIN_FP64
-
-    def step(precision=prec, want_grad=True):
-        ctx.loglike_grad(x, logl, grad, want_grad=want_grad, precision=precision)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    ctx.timing_read(smcgw.KERNEL_BINS)
-    ctx.timing(smcgw.KERNEL_BINS)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ctx.timing()
-    bins_ms, bins_n = ctx.timing_read(smcgw.KERNEL_BINS)
-    value = P * args.steps / dt
-    log(f"{args.precision}: {value:.4g} evals/s, {1e3 * dt / args.steps:.3f} ms/step, bins kernel "
-        f"{bins_ms / max(bins_n, 1):.3f} ms x {bins_n}")
-
-    avg_bins_s = bins_ms / max(bins_n, 1) / 1e3
-    ops = OPS_PER_PARTICLE_BIN[args.precision] * ev.n * P
-    achieved = ops / avg_bins_s / 1e12
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TLANEOPS, 3),
-                "unit": "Tlane-op/s", "frac": round(achieved / VALU_PEAK_TLANEOPS, 4), "traffic": None,
-                "kernel": f"bins_{'mixed' if prec == smcgw.MIXED else 'fp64'}_kernel<3>",
-                "kernel_ms": round(avg_bins_s * 1e3, 4),
-                "ops_per_particle_bin": OPS_PER_PARTICLE_BIN[args.precision]}
-
+    ops = OPS_PER_PARTICLE_BIN[args.precision]
     extra = {}
+
+    if args.mode == "smc":
+        P = args.particles or 2048
+        ctx, x_np, x = smc_setup(smcgw, synth, ev, P)
+        evals, dt, k_ms, k_n, betas, hist = run_smc_steps(smcgw, ctx, x, prec, args, args.warmup, args.steps, True)
+        value = evals / dt
+        kernel_s = k_ms / 1e3
+        achieved = ops * ev.n * evals / kernel_s / 1e12
+        log(f"smc {args.precision}: {evals} evals in {dt:.3f} s -> {value:.4g} evals/s; nuts kernel "
+            f"{k_ms / max(k_n, 1):.2f} ms x {k_n}; betas {betas}")
+        roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TLANEOPS, 3),
+                    "unit": "Tlane-op/s", "frac": round(achieved / VALU_PEAK_TLANEOPS, 4), "traffic": None,
+                    "kernel": f"nuts_kernel<3,{'MIXED' if prec == smcgw.MIXED else 'PLAIN_FP64'},GW,4>",
+                    "kernel_ms": round(k_ms / max(k_n, 1), 3), "ops_per_particle_bin": ops,
+                    "evals_in_kernel": evals}
+        extra["betas"] = [round(b, 8) for b in betas]
+        extra["depth_histograms"] = hist
+        ms_step = 1e3 * dt / args.steps
+        workload = (f"SMC-NUTS iteration (reweight + adaptive beta + resample, population mass matrix, one NUTS "
+                    f"transition per particle): 3-detector 8 s event, 20-1024 Hz, df=1/8 Hz (8033 bins), 11 params, "
+                    f"{P} particles from the prior, alpha={args.alpha}, eps={args.step}, depth<={args.max_depth}, "
+                    f"iterations {args.warmup + 1}-{args.warmup + args.steps} of the run")
+        if not args.no_extra:
+            # the plain-FP64 sampler on the same iterations, and the batched-likelihood kernel rates
+            ctx2, _, x2 = smc_setup(smcgw, synth, ev, P)
+            e2, d2, _, _, _, _ = run_smc_steps(smcgw, ctx2, x2, smcgw.PLAIN_FP64 if prec == smcgw.MIXED else smcgw.MIXED,
+                                               args, args.warmup, max(2, args.steps // 2), False)
+            extra["other_precision_in_sampler_evals_per_s"] = round(e2 / d2, 1)
+            ctx2.close()
+    else:
+        P = args.particles or 4096
+        ctx = smcgw.Context(0)
+        ctx.add_event(ev)
+        x_np = synth.prior_draw(np.random.default_rng(7), P, synth.gw_prior_for(ev))
+        x = torch.tensor(x_np, device="cuda")
+        logl = torch.empty(P, dtype=torch.float64, device="cuda")
+        grad = torch.empty_like(x)
+
+        def step(precision=prec, want_grad=True):
+            ctx.loglike_grad(x, logl, grad, want_grad=want_grad, precision=precision)
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        ctx.timing_read(smcgw.KERNEL_BINS)
+        ctx.timing(smcgw.KERNEL_BINS)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ctx.timing()
+        bins_ms, bins_n = ctx.timing_read(smcgw.KERNEL_BINS)
+        value = P * args.steps / dt
+        avg_bins_s = bins_ms / max(bins_n, 1) / 1e3
+        achieved = ops * ev.n * P / avg_bins_s / 1e12
+        log(f"loglike {args.precision}: {value:.4g} evals/s, bins kernel {bins_ms / max(bins_n, 1):.3f} ms x {bins_n}")
+        roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TLANEOPS, 3),
+                    "unit": "Tlane-op/s", "frac": round(achieved / VALU_PEAK_TLANEOPS, 4), "traffic": None,
+                    "kernel": f"bins_{'mixed' if prec == smcgw.MIXED else 'fp64'}_kernel<3>",
+                    "kernel_ms": round(avg_bins_s * 1e3, 4), "ops_per_particle_bin": ops}
+        ms_step = 1e3 * dt / args.steps
+        workload = (f"batched logL + adjoint gradient: 3-detector 8 s event, 20-1024 Hz, df=1/8 Hz (8033 bins), "
+                    f"11 params, {P} prior-draw particles")
+
     if not args.no_extra:
-        for name, p_, g_ in (("plain_fp64_grad", smcgw.PLAIN_FP64, True), ("mixed_forward_only", smcgw.MIXED, False),
-                             ("mixed_grad", smcgw.MIXED, True)):
+        # batched-likelihood rates at 4096 particles (kernel-level context for the sampler number)
+        Pl = 4096
+        ctxl = smcgw.Context(0)
+        ctxl.add_event(ev)
+        xl = torch.tensor(synth.prior_draw(np.random.default_rng(8), Pl, synth.gw_prior_for(ev)), device="cuda")
+        ll_ = torch.empty(Pl, dtype=torch.float64, device="cuda")
+        g_ = torch.empty_like(xl)
+        for name, p_, wg in (("loglike_plain_fp64_grad", smcgw.PLAIN_FP64, True),
+                             ("loglike_mixed_forward_only", smcgw.MIXED, False),
+                             ("loglike_mixed_grad", smcgw.MIXED, True)):
             for _ in range(2):
-                step(p_, g_)
+                ctxl.loglike_grad(xl, ll_, g_, want_grad=wg, precision=p_)
             torch.cuda.synchronize()
-            n_rep = 10
             t1 = time.perf_counter()
-            for _ in range(n_rep):
-                step(p_, g_)
+            for _ in range(10):
+                ctxl.loglike_grad(xl, ll_, g_, want_grad=wg, precision=p_)
             torch.cuda.synchronize()
-            extra[name + "_evals_per_s"] = round(P * n_rep / (time.perf_counter() - t1), 1)
+            extra[name + "_evals_per_s"] = round(Pl * 10 / (time.perf_counter() - t1), 1)
+        ctxl.close()
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -162,14 +261,12 @@ def main():
         cpu = cpu_baseline(ev, synth, x_np)
 
     out = {"metric": METRIC, "value": round(value, 1), "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": round(1e3 * dt / args.steps, 4), "higher_is_better": True,
+           "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None,
            "dtype": "f64+f32" if prec == smcgw.MIXED else "f64",
            "data": "synthetic",
-           "config": {"workload": "3-detector 8 s event, 20-1024 Hz, df=1/8 Hz (8033 bins), 11 params, "
-                                  f"{P} prior-draw particles, batched logL + adjoint gradient",
-                      "particles": P, "bins": ev.n, "detectors": ev.n_det, "params": 11,
-                      "precision": args.precision},
+           "config": {"workload": workload, "particles": P, "bins": ev.n, "detectors": ev.n_det, "params": 11,
+                      "precision": args.precision, "mode": args.mode},
            "roofline": roofline, "cpu_baseline": cpu, "extra": extra}
     print(json.dumps(out), flush=True)
     ctx.close()

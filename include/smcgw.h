@@ -119,6 +119,13 @@ int smcgw_set_stream(smcgw_ctx *ctx, void *hip_stream);
 int smcgw_add_event(smcgw_ctx *ctx, const smcgw_event_desc *ev, const double *data_reim, const double *psd,
                     const smcgw_detector *dets, int *event_id);
 
+/* Event of every particle for the sampler entry points: event_of_particle
+ * [P] is a caller-owned DEVICE array that must stay valid while the
+ * sampler runs (NULL: every particle uses event 0; indices outside the
+ * added events are clamped).  All events of one context share the
+ * detector count. */
+int smcgw_set_event_map(smcgw_ctx *ctx, const int32_t *event_of_particle);
+
 /* Which of the 11 source parameters are sampled: param_index[dim] gives the
  * source-parameter index of each sampled coordinate; fixed11[11] (host)
  * supplies the others.  Default: dim = 11, identity. */
@@ -141,11 +148,18 @@ int smcgw_set_target(smcgw_ctx *ctx, int kind, int dim, const double *params, in
  * implementation").  theta [P][dim], logl [P], grad [P][dim] (NULL: forward
  * only) are device arrays; event_of_particle [P] (device, NULL = event 0)
  * picks each particle's event, so events of different lengths share one
- * launch.  precision: SMCGW_PLAIN_FP64 (FP64 throughout) or SMCGW_MIXED
+ * launch (indices outside [0, events) are clamped).  precision: SMCGW_PLAIN_FP64 (FP64 throughout) or SMCGW_MIXED
  * (FP64 phase and argument reduction, FP32 trigonometry and per-bin
  * products, FP32 partial sums flushed into FP64 accumulators). */
 int smcgw_loglike_grad(smcgw_ctx *ctx, int P, const int32_t *event_of_particle, const double *theta, double *logl,
                        double *grad, int precision);
+
+/* logL and its gradient of the context's current target (smcgw_set_target):
+ * the event likelihood (as smcgw_loglike_grad with event_of_particle taken
+ * from smcgw_set_event_map) or an analytic test likelihood.  theta [P][dim],
+ * logl [P], grad [P][dim] are device arrays. */
+int smcgw_target_loglike_grad(smcgw_ctx *ctx, int P, const double *theta, double *logl, double *grad,
+                              int precision);
 
 /* Projected detector strain h_d(f_j; theta) of event event_id for one point
  * of the 11 source parameters (theta11, host), written to the device array
@@ -183,10 +197,18 @@ int smcgw_nuts_step(smcgw_ctx *ctx, int P, int D, double *theta, double *logl, d
  * Philox uniforms keyed by (seed, iteration) and theta [P][D], logl [P],
  * grad [P][D] (device) are gathered in place; ancestors [P] (device) receives
  * the indices.  Synchronises: *beta_next_host and *dlogz_host are host
- * scalars.  Returns SMCGW_ERR_STALL when beta cannot advance. */
+ * scalars.  beta_prev = 1 is allowed (beta_next = 1, a resample-only
+ * reweighting).  Returns SMCGW_ERR_STALL when beta cannot advance. */
 int smcgw_smc_reweight_resample(smcgw_ctx *ctx, int P, int D, double beta_prev, double alpha, uint64_t seed,
                                 uint64_t iteration, double *theta, double *logl, double *grad, int32_t *ancestors,
                                 double *beta_next_host, double *dlogz_host);
+
+/* ------------------------------------------------------------ options
+ * Launch-shape options of a context (chosen by the autotuner or by hand).
+ *   SMCGW_OPT_NUTS_WAVES: wavefronts that share one particle's bin loop in the
+ *     persistent NUTS kernel (2, 4 or 8; 0 = the library default of 4). */
+enum { SMCGW_OPT_NUTS_WAVES = 0 };
+int smcgw_set_option(smcgw_ctx *ctx, int option, int64_t value);
 
 /* ------------------------------------------------------------ timing
  * Kernel timing for measurement: HIP events are recorded on the context's

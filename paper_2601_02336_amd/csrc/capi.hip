@@ -73,17 +73,19 @@ int ctx_loglike(smcgw_ctx* c, int P, const int32_t* ev_of_p, const double* theta
     if (rc) return rc;
     {
         TimedLaunch t(c, SMCGW_KERNEL_PREP);
-        if (launch_prep(c->d_events, ev_of_p, c->pmap, P, theta, c->d_cb, c->stream) != hipSuccess)
+        if (launch_prep(c->d_events, (int)c->events.size(), ev_of_p, c->pmap, P, theta, c->d_cb, c->stream) != hipSuccess)
             return SMCGW_ERR_HIP;
     }
     {
         TimedLaunch t(c, SMCGW_KERNEL_BINS);
-        if (launch_bins(c->d_events, ev_of_p, P, c->n_det, precision, c->d_cb, c->d_mom, c->stream) != hipSuccess)
+        if (launch_bins(c->d_events, (int)c->events.size(), ev_of_p, P, c->n_det, precision, c->d_cb, c->d_mom,
+                        c->stream) != hipSuccess)
             return SMCGW_ERR_HIP;
     }
     {
         TimedLaunch t(c, SMCGW_KERNEL_FINISH);
-        if (launch_finish(c->d_events, ev_of_p, c->pmap, P, c->d_cb, c->d_mom, logl, grad, c->stream) != hipSuccess)
+        if (launch_finish(c->d_events, (int)c->events.size(), ev_of_p, c->pmap, P, c->d_cb, c->d_mom, logl, grad,
+                          c->stream) != hipSuccess)
             return SMCGW_ERR_HIP;
     }
     return SMCGW_OK;
@@ -127,6 +129,18 @@ extern "C" int smcgw_destroy(smcgw_ctx* c) {
     for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
     delete c;
     return SMCGW_OK;
+}
+
+extern "C" int smcgw_set_option(smcgw_ctx* c, int option, int64_t value) {
+    if (!c) return SMCGW_ERR_INVALID;
+    switch (option) {
+    case SMCGW_OPT_NUTS_WAVES:
+        if (value != 0 && value != 2 && value != 4 && value != 8) return SMCGW_ERR_INVALID;
+        c->nuts_waves = (int)value;
+        return SMCGW_OK;
+    default:
+        return SMCGW_ERR_INVALID;
+    }
 }
 
 extern "C" int smcgw_timing_enable(smcgw_ctx* c, int class_mask) {
@@ -201,18 +215,17 @@ extern "C" int smcgw_add_event(smcgw_ctx* c, const smcgw_event_desc* ev, const d
     const double us = umax > 0.0 ? std::ldexp(1.0, (int)std::lround(std::log2(umax))) : 1.0;
 
     hipSetDevice(c->device);
-    double *d_data = nullptr, *d_psd = nullptr, *basis = nullptr, *freq = nullptr, *sums = nullptr;
+    double *d_data = nullptr, *d_psd = nullptr, *fwl = nullptr, *sums = nullptr;
     float2* u32 = nullptr;
     double2* u64 = nullptr;
     int rc = SMCGW_OK;
     auto fail = [&](int code) {
-        hipFree(d_data); hipFree(d_psd); hipFree(basis); hipFree(freq); hipFree(u32); hipFree(u64); hipFree(sums);
+        hipFree(d_data); hipFree(d_psd); hipFree(fwl); hipFree(u32); hipFree(u64); hipFree(sums);
         return code;
     };
     if (hipMalloc(&d_data, sizeof(double) * 2 * nd * (size_t)n) != hipSuccess ||
         hipMalloc(&d_psd, sizeof(double) * nd * (size_t)n) != hipSuccess ||
-        hipMalloc(&basis, sizeof(double) * NBASIS * (size_t)npad) != hipSuccess ||
-        hipMalloc(&freq, sizeof(double) * (size_t)npad) != hipSuccess ||
+        hipMalloc(&fwl, sizeof(double) * NROWS * (size_t)npad) != hipSuccess ||
         hipMalloc(&u32, sizeof(float2) * nd * (size_t)npad) != hipSuccess ||
         hipMalloc(&u64, sizeof(double2) * nd * (size_t)npad) != hipSuccess ||
         hipMalloc(&sums, sizeof(double) * 2 * MAXDET) != hipSuccess)
@@ -220,7 +233,7 @@ extern "C" int smcgw_add_event(smcgw_ctx* c, const smcgw_event_desc* ev, const d
     if (hipMemcpyAsync(d_data, data_reim, sizeof(double) * 2 * nd * (size_t)n, hipMemcpyHostToDevice, c->stream) ||
         hipMemcpyAsync(d_psd, psd, sizeof(double) * nd * (size_t)n, hipMemcpyHostToDevice, c->stream))
         return fail(SMCGW_ERR_HIP);
-    if (launch_build_tables(d_data, d_psd, nd, n, npad, ev->f_low, ev->df, us, basis, freq, u32, u64, sums, c->stream))
+    if (launch_build_tables(d_data, d_psd, nd, n, npad, ev->f_low, ev->df, us, fwl, u32, u64, sums, c->stream))
         return fail(SMCGW_ERR_HIP);
     double hs[2 * MAXDET];
     if (hipMemcpyAsync(hs, sums, sizeof(double) * 2 * nd, hipMemcpyDeviceToHost, c->stream) ||
@@ -239,8 +252,7 @@ extern "C" int smcgw_add_event(smcgw_ctx* c, const smcgw_event_desc* ev, const d
     de.pn_order = ev->pn_order;
     de.f_low = ev->f_low;
     de.df = ev->df;
-    de.basis = basis;
-    de.freq = freq;
+    de.fwl = fwl;
     de.u32 = u32;
     de.u64 = u64;
     de.dd = 0.0;
@@ -259,13 +271,18 @@ extern "C" int smcgw_add_event(smcgw_ctx* c, const smcgw_event_desc* ev, const d
         hipStreamSynchronize(c->stream))
         return fail(SMCGW_ERR_HIP);
     c->events.push_back(de);
-    c->event_bufs.push_back(basis);
-    c->event_bufs.push_back(freq);
+    c->event_bufs.push_back(fwl);
     c->event_bufs.push_back(u32);
     c->event_bufs.push_back(u64);
     c->n_det = nd;
     if (event_id) *event_id = id;
     (void)rc;
+    return SMCGW_OK;
+}
+
+extern "C" int smcgw_set_event_map(smcgw_ctx* c, const int32_t* event_of_particle) {
+    if (!c) return SMCGW_ERR_INVALID;
+    c->ev_of_p = event_of_particle;
     return SMCGW_OK;
 }
 
@@ -307,7 +324,8 @@ extern "C" int smcgw_waveform(smcgw_ctx* c, int event_id, const double* theta11,
     ParamMap id;
     id.dim = NPAR;
     for (int k = 0; k < NPAR; ++k) { id.idx[k] = k; id.fixed[k] = 0.0; }
-    if (launch_prep(c->d_events, (const int32_t*)(small + 128), id, 1, (const double*)small, c->d_cb, c->stream))
+    if (launch_prep(c->d_events, (int)c->events.size(), (const int32_t*)(small + 128), id, 1, (const double*)small,
+                    c->d_cb, c->stream))
         return SMCGW_ERR_HIP;
     const DevEvent& e = c->events[event_id];
     if (launch_waveform(c->d_events, event_id, c->d_cb, h_reim, e.n_bins, e.n_det, c->stream)) return SMCGW_ERR_HIP;

@@ -20,17 +20,33 @@ constexpr double TWO_PI = 6.28318530717958647692;
 // Source-parameter indices.
 enum { P_MC = 0, P_Q, P_CHI1, P_CHI2, P_DL, P_IOTA, P_PSI, P_RA, P_DEC, P_TC, P_PHIC };
 
-// Phase basis rows of the tables: the TaylorF2 phase in cycles is
+// Phase basis: the TaylorF2 phase in cycles is
 //   Phi(f) = c_0 + sum_b c_b B_b(f) + f (t_c + dt_det)
-// with B = {f^-5/3, f^-1, f^-2/3, f^-1/3, ln f, f^1/3, f^1/3 ln f, f^2/3}.
+// with B = {f^-5/3, f^-1, f^-2/3, f^-1/3, ln f, f^1/3, f^1/3 ln f, f^2/3}.  The
+// tables keep three FP64 rows per bin, f, w = f^-1/3 and ln f; every basis
+// value is a product of them (basis_rows).
 enum { B_M53 = 0, B_M1, B_M23, B_M13, B_LN, B_P13, B_P13LN, B_P23 };
+enum { ROW_F = 0, ROW_W = 1, ROW_LN = 2, NROWS = 3 };
+
+__device__ __forceinline__ void basis_rows(double f, double w, double lnf, double B[8]) {
+    const double w2 = w * w;
+    const double w3 = w2 * w;
+    const double u = f * w2;   // f^1/3
+    B[B_M53] = w3 * w2;
+    B[B_M1] = w3;
+    B[B_M23] = w2;
+    B[B_M13] = w;
+    B[B_LN] = lnf;
+    B[B_P13] = u;
+    B[B_P13LN] = u * lnf;
+    B[B_P23] = u * u;
+}
 
 // Device view of one event's bin tables (frequency-major, padded to n_pad).
 struct DevEvent {
     int n_bins, n_pad, n_det, pn_order;
     double f_low, df;
-    const double* basis;     // [NBASIS][n_pad]
-    const double* freq;      // [n_pad]
+    const double* fwl;       // [NROWS][n_pad]: f, f^-1/3, ln f
     const float2* u32;       // [n_det][n_pad]  4 df conj(d) f^-7/6 / (S u_scale), FP32
     const double2* u64;      // [n_det][n_pad]  same in FP64
     double hnorm[MAXDET];    // sum_j 4 df f^-7/3 / S / u_scale^2
@@ -76,16 +92,23 @@ enum {
 };
 static_assert(MOM_T + MAXDET <= MOM_SIZE, "moment block overflow");
 
+// Event index of particle p (out-of-range indices are clamped to a valid event).
+__device__ __forceinline__ int event_index(const int32_t* ev_of_p, int p, int n_events) {
+    if (!ev_of_p) return 0;
+    const int e = ev_of_p[p];
+    return e < 0 ? 0 : (e >= n_events ? n_events - 1 : e);
+}
+
 // ------------------------------------------------------------- host launchers
 // (each .hip file exposes host functions; kernels stay in their own unit)
 hipError_t launch_build_tables(const double* d_data, const double* d_psd, int n_det, int n_bins, int n_pad,
-                               double f_low, double df, double u_scale, double* basis, double* freq, float2* u32,
-                               double2* u64, double* sums, hipStream_t s);
-hipError_t launch_prep(const DevEvent* d_events, const int32_t* ev_of_p, const ParamMap& pm, int P,
+                               double f_low, double df, double u_scale, double* fwl, float2* u32, double2* u64,
+                               double* sums, hipStream_t s);
+hipError_t launch_prep(const DevEvent* d_events, int n_events, const int32_t* ev_of_p, const ParamMap& pm, int P,
                        const double* theta, double* cb, hipStream_t s);
-hipError_t launch_bins(const DevEvent* d_events, const int32_t* ev_of_p, int P, int n_det, int precision,
+hipError_t launch_bins(const DevEvent* d_events, int n_events, const int32_t* ev_of_p, int P, int n_det, int precision,
                        const double* cb, double* mom, hipStream_t s);
-hipError_t launch_finish(const DevEvent* d_events, const int32_t* ev_of_p, const ParamMap& pm, int P,
+hipError_t launch_finish(const DevEvent* d_events, int n_events, const int32_t* ev_of_p, const ParamMap& pm, int P,
                          const double* cb, const double* mom, double* logl, double* grad, hipStream_t s);
 hipError_t launch_waveform(const DevEvent* d_events, int event_id, const double* cb, double* h_reim, int n_bins,
                            int n_det, hipStream_t s);

@@ -1,6 +1,7 @@
 // The opaque context behind smcgw_ctx (host side only).
 #pragma once
 
+#include <unordered_map>
 #include <vector>
 
 #include "common.h"
@@ -40,6 +41,10 @@ struct smcgw_ctx {
     smcgw::TargetDesc target{SMCGW_TARGET_GW, 0, nullptr};
     double* d_target_params = nullptr;
     // sampler scratch
+    void* d_queue = nullptr;               // work-queue counter of the persistent kernels
+    int nuts_waves = 0;                    // wavefronts per NUTS slot (0: default)
+    std::unordered_map<const void*, int> resident;   // resident workgroups per device, per kernel
+    const int32_t* ev_of_p = nullptr;      // caller-owned event index per particle (NULL: event 0)
     void* d_sampler = nullptr;
     size_t sampler_bytes = 0;
     double* h_pinned = nullptr;            // small pinned host buffer for scalar read-backs
@@ -51,6 +56,8 @@ struct smcgw_ctx {
     void sampler_free() {
         hipFree(d_target_params);
         hipFree(d_sampler);
+        hipFree(d_queue);
+        d_queue = nullptr;
         if (h_pinned) hipHostFree(h_pinned);
         d_target_params = nullptr;
         d_sampler = nullptr;

@@ -1,12 +1,613 @@
-// NUTS transition kernels (placeholder until the persistent kernel lands).
+// Persistent No-U-Turn kernel (arXiv:2601.02336, Sec. 4 and Sec. 5).
+//
+// One NUTS transition per particle: momentum r ~ N(0, M) with M^{-1} = L L^T,
+// Hamiltonian H = -log p_t(x) + r^T M^{-1} r / 2 with p_t ~ L^beta pi (Sec. 3,
+// Eq. 3), leapfrog steps (Eqs. 11-13) mapped back into the prior box by the
+// reflective / periodic boundaries of Sec. 5, trajectory doubling in a random
+// direction until the generalised U-turn criterion fires or the depth limit
+// is reached (Hoffman & Gelman 2014; multinomial variant of Betancourt 2017,
+// App. A): uniform progressive sampling inside each new subtree, biased
+// progressive sampling when it is merged, divergence when H - H0 exceeds a
+// threshold.
+//
+// Execution: each workgroup owns one particle slot at a time and pulls the
+// next particle index from an atomic queue when its transition ends, so trees
+// of uneven depth keep every slot busy until the queue drains.  Wavefront 0
+// runs the tree logic with one coordinate per lane (lanes 0..D-1); for the
+// gravitational-wave target every leaf's likelihood is evaluated by all
+// wavefronts of the workgroup: prologue on two lanes, the bin loop split into
+// interleaved blocks across the wavefronts, FP64 epilogue on wavefront 0.
+// Random numbers come from Philox4x32-10 with counter (index, particle,
+// iteration, purpose), so every decision can be replayed.
+#include <algorithm>
+
+#include "binloop.h"
+#include "coeffs.h"
 #include "common.h"
 #include "context.h"
+#include "philox.h"
+
+namespace smcgw {
+
+struct NutsArgs {
+    int P, D;
+    double* theta;
+    double* logl;
+    double* grad;
+    const double* chol;
+    double step, beta, max_dh;
+    int max_depth, uturn;
+    uint64_t seed, iteration;
+    const int32_t* md_per_p;
+    int32_t* depth_out;
+    int32_t* nlf_out;
+    uint8_t* div_out;
+    double* acc_out;
+    const DevEvent* events;
+    int n_events;
+    const int32_t* ev_of_p;
+    int* queue;
+};
+
+constexpr int MAX_WAVES = 8;
+constexpr int MAXD1 = SMCGW_MAX_DEPTH + 1;
+
+struct NutsShared {
+    double L[MAXDIM * MAXDIM];
+    double Minv[MAXDIM * MAXDIM];
+    double cb[CB_SIZE];
+    double mom[MAX_WAVES][MOM_SIZE];
+    double th[NPAR];
+    double left[4][MAXDIM], right[4][MAXDIM];   // x, r, g (grad log p_t), gl (grad logL)
+    double prop[2][MAXDIM], sprop[2][MAXDIM];    // x, gl
+    double ck_rho[MAXD1][MAXDIM], ck_r[MAXD1][MAXDIM];
+    double end_ll[2], end_lp[2];                 // logL, log p_t of left / right
+    double plo[MAXDIM], phi[MAXDIM];             // prior / boundary description
+    int pbnd[MAXDIM], pkind[MAXDIM];
+    int pidx[MAXDIM];                            // sampled coordinate -> source parameter
+    double pfixed[NPAR];
+    int p;
+    int cmd;
+};
+
+enum { ST_START = 0, ST_SUBTREE = 1, ST_DONE = 2 };
+enum { CMD_EVAL = 0, CMD_DONE = 1 };
+
+__device__ __forceinline__ double log_add_exp(double a, double b) {
+    if (a == -INFINITY) return b;
+    if (b == -INFINITY) return a;
+    const double m = fmax(a, b);
+    return m + log(exp(a - m) + exp(b - m));
+}
+
+// (M^{-1} v) for this lane's coordinate; all 64 lanes of the wavefront call it.
+__device__ __forceinline__ double minv_apply(const NutsShared& S, int D, int lane, double v) {
+    double acc = 0.0;
+    const int row = lane < D ? lane : 0;
+    for (int m = 0; m < D; ++m) acc = fma(S.Minv[row * MAXDIM + m], __shfl(v, m, 64), acc);
+    return lane < D ? acc : 0.0;
+}
+
+// r^T M^{-1} r / 2 = |L^T r|^2 / 2.
+__device__ __forceinline__ double kinetic(const NutsShared& S, int D, int lane, double r) {
+    double t = 0.0;
+    const int col = lane < D ? lane : 0;
+    for (int i = 0; i < D; ++i) {
+        const double ri = __shfl(r, i, 64);
+        if (i >= col) t = fma(S.L[i * MAXDIM + col], ri, t);
+    }
+    return 0.5 * wave_sum(lane < D ? t * t : 0.0);
+}
+
+// Generalised no-U-turn criterion: rho.M^{-1}r_a > 0 and rho.M^{-1}r_b > 0.
+__device__ __forceinline__ bool no_uturn(const NutsShared& S, int D, int lane, double rho, double ra, double rb) {
+    const double va = minv_apply(S, D, lane, ra);
+    const double vb = minv_apply(S, D, lane, rb);
+    const double sa = wave_sum(lane < D ? rho * va : 0.0);
+    const double sb = wave_sum(lane < D ? rho * vb : 0.0);
+    return sa > 0.0 && sb > 0.0;
+}
+
+// Normalised log prior of this lane's coordinate and its derivative.
+__device__ __forceinline__ double log_prior_lane(const NutsShared& S, int k, double x, double& g) {
+    g = 0.0;
+    const double lo = S.plo[k], hi = S.phi[k];
+    switch (S.pkind[k]) {
+    case SMCGW_PRIOR_UNIFORM:
+        return (x < lo || x > hi) ? -INFINITY : -log(hi - lo);
+    case SMCGW_PRIOR_LOGUNIFORM:
+        if (x < lo || x > hi) return -INFINITY;
+        g = -1.0 / x;
+        return -log(x) - log(log(hi / lo));
+    case SMCGW_PRIOR_GAUSSIAN: {
+        const double r = (x - lo) / hi;
+        g = -r / hi;
+        return -0.5 * r * r - 0.5 * log(2.0 * PI * hi * hi);
+    }
+    default:
+        return 0.0;
+    }
+}
+
+// Reflect (flipping this momentum component) or wrap into the box.
+__device__ __forceinline__ void boundary_lane(const NutsShared& S, int k, double& x, double& r) {
+    const double lo = S.plo[k], hi = S.phi[k];
+    if (S.pbnd[k] == SMCGW_BND_REFLECT) {
+        for (int it = 0; it < 64 && (x < lo || x > hi); ++it) {
+            x = (x > hi) ? 2.0 * hi - x : 2.0 * lo - x;
+            r = -r;
+        }
+    } else if (S.pbnd[k] == SMCGW_BND_PERIODIC) {
+        const double w = hi - lo;
+        for (int it = 0; it < 64 && (x < lo || x >= hi); ++it) x = (x >= hi) ? x - w : x + w;
+    }
+}
+
+// Analytic likelihoods (one coordinate per lane of wavefront 0).
+template <int TK>
+__device__ __forceinline__ double analytic_loglike(const TargetDesc& t, int D, int lane, double x, double& gl) {
+    const bool dl = lane < D;
+    if (TK == SMCGW_TARGET_GAUSS) {
+        gl = dl ? -x : 0.0;
+        return -0.5 * wave_sum(dl ? x * x : 0.0);
+    } else if (TK == SMCGW_TARGET_GAUSS_X_GAUSS) {
+        const double y = dl ? t.params[lane] : 0.0, s = dl ? t.params[D + lane] : 1.0;
+        const double r = (y - x) / s;
+        gl = dl ? r / s : 0.0;
+        return wave_sum(dl ? -0.5 * r * r - 0.5 * log(2.0 * PI * s * s) : 0.0);
+    } else {
+        const double m1 = dl ? t.params[lane] : 0.0, m2 = dl ? t.params[D + lane] : 0.0, sg = t.params[2 * D];
+        const double s1 = wave_sum(dl ? (x - m1) * (x - m1) : 0.0);
+        const double s2 = wave_sum(dl ? (x - m2) * (x - m2) : 0.0);
+        const double c = -0.5 * D * log(2.0 * PI * sg * sg);
+        const double l1 = c - 0.5 * s1 / (sg * sg), l2 = c - 0.5 * s2 / (sg * sg);
+        const double mx = fmax(l1, l2);
+        const double w1 = exp(l1 - mx), w2 = exp(l2 - mx);
+        gl = dl ? (w1 * (m1 - x) + w2 * (m2 - x)) / (sg * sg) / (w1 + w2) : 0.0;
+        return mx + log(w1 + w2);
+    }
+}
+
+// Tree state of the slot's current transition (LDS; wavefront 0 only).
+struct NutsState {
+    double x[MAXDIM], r[MAXDIM], g[MAXDIM], gl[MAXDIM];   // the edge being extended
+    double rho[MAXDIM], srho[MAXDIM];                    // momentum sums of the tree / subtree
+    double gl_new[MAXDIM];                               // likelihood gradient of the last leaf
+    double h0, logw, sub_logw, uacc, acc_sum, eps, ll, lp, prop_ll, sprop_ll, ll_new;
+    int state, j, n, nleaves, depth, nlf, div, dir, md;
+    uint32_t leafc;
+};
+
+// Start a transition of particle p (wavefront 0): momentum, H0, tree of one point.
+__device__ __forceinline__ void start_transition(NutsShared& S, NutsState& T, const NutsArgs& a, int p, int lane) {
+    const int D = a.D;
+    const bool dl = lane < D;
+    const int kk = dl ? lane : 0;
+    const double x = dl ? a.theta[(size_t)p * D + lane] : 0.0;
+    const double gl = dl ? a.grad[(size_t)p * D + lane] : 0.0;
+    const double ll = a.logl[p];
+    double gp;
+    const double lpr = wave_sum(dl ? log_prior_lane(S, kk, x, gp) : 0.0);
+    if (!dl) gp = 0.0;
+    const double lp = a.beta * ll + lpr;
+    const double g = a.beta * gl + gp;
+    // r = L^{-T} z with z ~ N(0, I) from Box-Muller on Philox uniform pairs.
+    double u0, u1;
+    rng_uniform2(a.seed, (uint32_t)(lane >> 1), (uint32_t)p, a.iteration, RNG_MOMENTUM, u0, u1);
+    const double rad = sqrt(-2.0 * log(1.0 - u0));
+    const double z = (lane & 1) ? rad * sin(2.0 * PI * u1) : rad * cos(2.0 * PI * u1);
+    double accz = dl ? z : 0.0, r = 0.0;
+    for (int i = D - 1; i >= 0; --i) {
+        const double ri = __shfl(accz, i, 64) / S.L[i * MAXDIM + i];
+        if (lane == i) r = ri;
+        if (lane < i) accz = fma(-S.L[i * MAXDIM + lane], ri, accz);
+    }
+    if (!dl) r = 0.0;
+    const double h0 = -lp + kinetic(S, D, lane, r);
+    if (dl) {
+        S.left[0][lane] = x; S.left[1][lane] = r; S.left[2][lane] = g; S.left[3][lane] = gl;
+        S.right[0][lane] = x; S.right[1][lane] = r; S.right[2][lane] = g; S.right[3][lane] = gl;
+        S.prop[0][lane] = x; S.prop[1][lane] = gl;
+        T.rho[lane] = r;
+    }
+    if (lane == 0) {
+        S.end_ll[0] = S.end_ll[1] = ll;
+        S.end_lp[0] = S.end_lp[1] = lp;
+        T.prop_ll = ll;
+        T.h0 = h0;
+        T.logw = 0.0;
+        T.acc_sum = 0.0;
+        T.state = ST_START;
+        T.j = 0;
+        T.depth = 0;
+        T.nlf = 0;
+        T.div = 0;
+        T.leafc = 0;
+        T.md = a.md_per_p ? min(a.md_per_p[p], SMCGW_MAX_DEPTH) : a.max_depth;
+    }
+}
+
+// Advance to the next leaf (wavefront 0): start a doubling if needed, then the
+// first momentum half-step, the position step and the boundary maps.  Returns
+// CMD_EVAL with the new position in T.x (and the source parameters in S.th),
+// or CMD_DONE when the transition is complete.
+template <int TK>
+__device__ __forceinline__ int pre_leaf(NutsShared& S, NutsState& T, const NutsArgs& a, int p, int lane) {
+    const int D = a.D;
+    const bool dl = lane < D;
+    int state = T.state;
+    if (state == ST_START) {
+        const int j = T.j;
+        if (j < T.md) {
+            double ud0, ud1;
+            rng_uniform2(a.seed, (uint32_t)j, (uint32_t)p, a.iteration, RNG_DOUBLING, ud0, ud1);
+            const int dir = (ud0 < 0.5) ? -1 : 1;
+            const int side = dir > 0 ? 1 : 0;
+            if (dl) {
+                const double (*E)[MAXDIM] = side ? S.right : S.left;
+                T.x[lane] = E[0][lane]; T.r[lane] = E[1][lane]; T.g[lane] = E[2][lane]; T.gl[lane] = E[3][lane];
+                S.sprop[0][lane] = E[0][lane];
+                S.sprop[1][lane] = E[3][lane];
+                T.srho[lane] = 0.0;
+            }
+            const double ell = S.end_ll[side], elp = S.end_lp[side];
+            __builtin_amdgcn_wave_barrier();
+            if (lane == 0) {
+                T.dir = dir;
+                T.uacc = ud1;
+                T.ll = ell;
+                T.lp = elp;
+                T.sprop_ll = ell;
+                T.sub_logw = -INFINITY;
+                T.n = 0;
+                T.nleaves = 1 << j;
+                T.state = ST_SUBTREE;
+            }
+            state = ST_SUBTREE;
+        } else {
+            if (lane == 0) T.state = ST_DONE;
+            state = ST_DONE;
+        }
+    }
+    if (state != ST_SUBTREE) return CMD_DONE;
+    __builtin_amdgcn_wave_barrier();
+    const double eps = T.dir * a.step;
+    double r = dl ? fma(0.5 * eps, T.g[lane], T.r[lane]) : 0.0;
+    const double v = minv_apply(S, D, lane, r);
+    double x = dl ? fma(eps, v, T.x[lane]) : 0.0;
+    if (dl) boundary_lane(S, lane, x, r);
+    if (dl) { T.x[lane] = x; T.r[lane] = r; }
+    if (lane == 0) T.eps = eps;
+    if (TK == SMCGW_TARGET_GW) {
+        if (lane < NPAR) S.th[lane] = S.pfixed[lane];
+        __builtin_amdgcn_wave_barrier();
+        if (dl) S.th[S.pidx[lane]] = x;
+    }
+    return CMD_EVAL;
+}
+
+// Second half of the leaf (wavefront 0): momentum half-step with the new
+// gradient, energy, divergence, progressive sampling, U-turn checks of the
+// nodes this leaf completes, and the merge when the subtree is complete.
+__device__ __forceinline__ void post_leaf(NutsShared& S, NutsState& T, const NutsArgs& a, int p, int lane) {
+    const int D = a.D;
+    const bool dl = lane < D;
+    const int kk = dl ? lane : 0;
+    const double ll = T.ll_new;
+    const double gl = dl ? T.gl_new[lane] : 0.0;
+    const double x = dl ? T.x[lane] : 0.0;
+    double gp;
+    const double lpr = wave_sum(dl ? log_prior_lane(S, kk, x, gp) : 0.0);
+    if (!dl) gp = 0.0;
+    const double lp = a.beta * ll + lpr;
+    const double g = a.beta * gl + gp;
+    const double eps = T.eps;
+    const double r = dl ? fma(0.5 * eps, g, T.r[lane]) : 0.0;
+    const int j = T.j, n = T.n;
+    const double h0 = T.h0;
+    const double dh = -lp + kinetic(S, D, lane, r) - h0;
+    const bool finite = (dh == dh) && dh != INFINITY && dh != -INFINITY;
+    double acc_sum = T.acc_sum + (finite ? fmin(1.0, exp(-dh)) : 0.0);
+    double srho = dl ? T.srho[lane] : 0.0;
+    double sub_logw = T.sub_logw;
+    double sprop_ll = T.sprop_ll;
+    uint32_t leafc = T.leafc;
+    bool ok = true;
+    int div = T.div;
+    if (!finite || dh > a.max_dh) {
+        div = 1;
+        ok = false;
+    } else {
+        for (int l = 1; l <= j; ++l)
+            if ((n & ((1 << l) - 1)) == 0 && dl) { S.ck_rho[l][lane] = srho; S.ck_r[l][lane] = r; }
+        srho += r;
+        const double lw = -dh;
+        const double nlw = log_add_exp(sub_logw, lw);
+        double ul0, ul1;
+        rng_uniform2(a.seed, leafc, (uint32_t)p, a.iteration, RNG_LEAF, ul0, ul1);
+        ++leafc;
+        if (ul0 < exp(lw - nlw)) {
+            if (dl) { S.sprop[0][lane] = x; S.sprop[1][lane] = gl; }
+            sprop_ll = ll;
+        }
+        sub_logw = nlw;
+        if (a.uturn) {
+            __builtin_amdgcn_wave_barrier();
+            for (int l = 1; l <= j && ok; ++l)
+                if (((n + 1) & ((1 << l) - 1)) == 0) {
+                    const double nr = srho - (dl ? S.ck_rho[l][lane] : 0.0);
+                    const double r0 = dl ? S.ck_r[l][lane] : 0.0;
+                    if (!no_uturn(S, D, lane, nr, r0, r)) ok = false;
+                }
+        }
+    }
+    int state = ST_SUBTREE, depth = T.depth, jn = j, nn = n;
+    double logw = T.logw, prop_ll = T.prop_ll;
+    if (!ok) {
+        state = ST_DONE;
+    } else if (n + 1 == T.nleaves) {
+        depth = j + 1;
+        __builtin_amdgcn_wave_barrier();
+        if (T.uacc < exp(sub_logw - logw)) {
+            if (dl) { S.prop[0][lane] = S.sprop[0][lane]; S.prop[1][lane] = S.sprop[1][lane]; }
+            prop_ll = sprop_ll;
+        }
+        logw = log_add_exp(logw, sub_logw);
+        const double rho = (dl ? T.rho[lane] : 0.0) + srho;
+        const int side = T.dir > 0 ? 1 : 0;
+        if (dl) {
+            double (*E)[MAXDIM] = side ? S.right : S.left;
+            E[0][lane] = x; E[1][lane] = r; E[2][lane] = g; E[3][lane] = gl;
+            T.rho[lane] = rho;
+        }
+        if (lane == 0) { S.end_ll[side] = ll; S.end_lp[side] = lp; }
+        __builtin_amdgcn_wave_barrier();
+        bool stop = false;
+        if (a.uturn) {
+            const double rl = dl ? S.left[1][lane] : 0.0, rr = dl ? S.right[1][lane] : 0.0;
+            stop = !no_uturn(S, D, lane, rho, rl, rr);
+        }
+        if (stop) {
+            state = ST_DONE;
+        } else {
+            jn = j + 1;
+            state = ST_START;
+        }
+    } else {
+        nn = n + 1;
+    }
+    if (dl) { T.r[lane] = r; T.g[lane] = g; T.gl[lane] = gl; T.srho[lane] = srho; }
+    __builtin_amdgcn_wave_barrier();
+    if (lane == 0) {
+        T.ll = ll; T.lp = lp; T.acc_sum = acc_sum; T.sub_logw = sub_logw; T.sprop_ll = sprop_ll; T.leafc = leafc;
+        T.div = div; T.state = state; T.depth = depth; T.j = jn; T.n = nn; T.logw = logw; T.prop_ll = prop_ll;
+        T.nlf = T.nlf + 1;
+    }
+}
+
+__device__ __forceinline__ void write_outputs(NutsShared& S, NutsState& T, const NutsArgs& a, int p, int lane) {
+    const int D = a.D;
+    __builtin_amdgcn_wave_barrier();
+    if (lane < D) {
+        a.theta[(size_t)p * D + lane] = S.prop[0][lane];
+        a.grad[(size_t)p * D + lane] = S.prop[1][lane];
+    }
+    if (lane == 0) {
+        a.logl[p] = T.prop_ll;
+        if (a.depth_out) a.depth_out[p] = T.depth;
+        if (a.nlf_out) a.nlf_out[p] = T.nlf;
+        if (a.div_out) a.div_out[p] = (uint8_t)T.div;
+        if (a.acc_out) a.acc_out[p] = T.nlf > 0 ? T.acc_sum / T.nlf : 0.0;
+    }
+}
+
+template <int NDET, int PREC, int TK, int WAVES>
+__global__ __launch_bounds__(WAVES * 64, (WAVES == 1 ? 2 : 4)) void nuts_kernel(NutsArgs a, PriorDesc pri, ParamMap pm,
+                                                                             TargetDesc tgt) {
+    __shared__ NutsShared S;
+    __shared__ NutsState T;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int D = a.D;
+
+    for (int i = tid; i < MAXDIM * MAXDIM; i += blockDim.x) {
+        const int r = i / MAXDIM, c = i % MAXDIM;
+        S.L[i] = (r < D && c < D) ? a.chol[r * D + c] : 0.0;
+    }
+    if (tid == 0) {
+        for (int k = 0; k < MAXDIM; ++k) {
+            S.plo[k] = pri.lo[k]; S.phi[k] = pri.hi[k]; S.pbnd[k] = pri.bnd[k]; S.pkind[k] = pri.kind[k];
+            S.pidx[k] = pm.idx[k];
+        }
+        for (int k = 0; k < NPAR; ++k) S.pfixed[k] = pm.fixed[k];
+    }
+    __syncthreads();
+    for (int i = tid; i < MAXDIM * MAXDIM; i += blockDim.x) {
+        const int r = i / MAXDIM, c = i % MAXDIM;
+        double s = 0.0;
+        for (int m = 0; m < D; ++m) s = fma(S.L[r * MAXDIM + m], S.L[c * MAXDIM + m], s);
+        S.Minv[i] = s;
+    }
+    __syncthreads();
+
+    for (;;) {
+        if (tid == 0) S.p = __hip_atomic_fetch_add(a.queue, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const int p = __builtin_amdgcn_readfirstlane(S.p);
+        if (p >= a.P) break;
+        const DevEvent* ev = nullptr;
+        if (TK == SMCGW_TARGET_GW)
+            ev = a.events + __builtin_amdgcn_readfirstlane(event_index(a.ev_of_p, p, a.n_events));
+        if (wave == 0) start_transition(S, T, a, p, lane);
+
+        for (;;) {
+            if (wave == 0) {
+                const int cmd = pre_leaf<TK>(S, T, a, p, lane);
+                if (lane == 0) S.cmd = cmd;
+            }
+            __syncthreads();
+            if (__builtin_amdgcn_readfirstlane(S.cmd) == CMD_DONE) break;
+
+            if (TK == SMCGW_TARGET_GW) {
+                if (wave == 0 && lane == 0) prep_intrinsic(*ev, S.th, S.cb);
+                if (wave == (WAVES > 1 ? 1 : 0) && lane == 0) prep_extrinsic(*ev, S.th, S.cb);
+                __syncthreads();
+                {
+                    const BinCoef k = load_coef(S.cb);
+                    double m[MOM_SIZE];
+                    if (PREC == SMCGW_MIXED)
+                        bins_mixed_wave<NDET>(ev, k, wave, WAVES, m);
+                    else
+                        bins_fp64_wave<NDET>(ev, k, wave, WAVES, m);
+                    if (lane == 0)
+                        for (int i = 0; i < MOM_SIZE; ++i) S.mom[wave][i] = m[i];
+                }
+                __syncthreads();
+                if (wave == 0) {
+                    double mt[MOM_SIZE];
+                    for (int i = 0; i < MOM_SIZE; ++i) {
+                        double s = S.mom[0][i];
+                        for (int w = 1; w < WAVES; ++w) s += S.mom[w][i];
+                        mt[i] = s;
+                    }
+                    double g11[NPAR];
+                    const double ll = finish_particle(*ev, S.cb, mt, g11);
+                    const int src = lane < D ? S.pidx[lane] : 0;
+                    double v = 0.0;
+#pragma unroll
+                    for (int q = 0; q < NPAR; ++q) v = (src == q) ? g11[q] : v;
+                    if (lane < D) T.gl_new[lane] = v;
+                    if (lane == 0) T.ll_new = ll;
+                }
+            } else if (wave == 0) {
+                double gl;
+                const double ll = analytic_loglike<TK>(tgt, D, lane, lane < D ? T.x[lane] : 0.0, gl);
+                if (lane < D) T.gl_new[lane] = gl;
+                if (lane == 0) T.ll_new = ll;
+            }
+            if (wave == 0) {
+                __builtin_amdgcn_wave_barrier();
+                post_leaf(S, T, a, p, lane);
+            }
+        }
+        if (wave == 0) write_outputs(S, T, a, p, lane);
+        __syncthreads();
+    }
+}
+
+__global__ void zero_int_kernel(int* q) { *q = 0; }
+
+}  // namespace smcgw
+
+using namespace smcgw;
+
+namespace {
+
+template <class K>
+int launch_persistent(smcgw_ctx* c, K kernel, int block, const NutsArgs& a, const PriorDesc& pri, const ParamMap& pm,
+                      const TargetDesc& t) {
+    auto it = c->resident.find((const void*)kernel);
+    if (it == c->resident.end()) {
+        int dev_cus = 0, per_cu = 0;
+        if (hipDeviceGetAttribute(&dev_cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess)
+            return SMCGW_ERR_HIP;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess || per_cu < 1)
+            per_cu = 1;
+        it = c->resident.emplace((const void*)kernel, dev_cus * per_cu).first;
+    }
+    const int grid = std::max(1, std::min(a.P, it->second));
+    hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, c->stream, a.queue);
+    {
+        TimedLaunch tl(c, SMCGW_KERNEL_NUTS);
+        hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), 0, c->stream, a, pri, pm, t);
+    }
+    return hipGetLastError() == hipSuccess ? SMCGW_OK : SMCGW_ERR_HIP;
+}
+
+template <int NDET, int W>
+int launch_gw_w(smcgw_ctx* c, int precision, const NutsArgs& a, const PriorDesc& pri, const ParamMap& pm,
+                const TargetDesc& t) {
+    if (precision == SMCGW_MIXED)
+        return launch_persistent(c, nuts_kernel<NDET, SMCGW_MIXED, SMCGW_TARGET_GW, W>, W * 64, a, pri, pm, t);
+    return launch_persistent(c, nuts_kernel<NDET, SMCGW_PLAIN_FP64, SMCGW_TARGET_GW, W>, W * 64, a, pri, pm, t);
+}
+
+template <int NDET>
+int launch_gw(smcgw_ctx* c, int precision, const NutsArgs& a, const PriorDesc& pri, const ParamMap& pm,
+              const TargetDesc& t) {
+    switch (c->nuts_waves) {
+    case 2: return launch_gw_w<NDET, 2>(c, precision, a, pri, pm, t);
+    case 8: return launch_gw_w<NDET, 8>(c, precision, a, pri, pm, t);
+    default: return launch_gw_w<NDET, 4>(c, precision, a, pri, pm, t);
+    }
+}
+
+}  // namespace
 
 extern "C" int smcgw_nuts_step(smcgw_ctx* c, int P, int D, double* theta, double* logl, double* grad,
-                               const double* chol, const smcgw_nuts_params* params,
+                               const double* chol, const smcgw_nuts_params* prm,
                                const int32_t* max_depth_per_particle, int precision, int32_t* depth,
                                int32_t* n_leapfrog, uint8_t* divergent, double* accept_stat) {
-    (void)c; (void)P; (void)D; (void)theta; (void)logl; (void)grad; (void)chol; (void)params;
-    (void)max_depth_per_particle; (void)precision; (void)depth; (void)n_leapfrog; (void)divergent; (void)accept_stat;
-    return SMCGW_ERR_NOT_INIT;
+    if (!c || !prm || P < 0 || D <= 0 || D > MAXDIM || (P > 0 && (!theta || !logl || !grad || !chol)))
+        return SMCGW_ERR_INVALID;
+    if (precision != SMCGW_PLAIN_FP64 && precision != SMCGW_MIXED) return SMCGW_ERR_INVALID;
+    if (prm->max_depth < 0 || prm->max_depth > SMCGW_MAX_DEPTH || !(prm->step > 0.0) || !(prm->beta >= 0.0) ||
+        !(prm->max_delta_h > 0.0))
+        return SMCGW_ERR_INVALID;
+    if (!c->prior_set || c->prior.dim != D) return SMCGW_ERR_NOT_INIT;
+    const int kind = c->target.kind;
+    if (kind == SMCGW_TARGET_GW) {
+        if (c->events.empty() || c->pmap.dim != D) return SMCGW_ERR_NOT_INIT;
+    } else if (c->target.dim != D) {
+        return SMCGW_ERR_NOT_INIT;
+    }
+    if (P == 0) return SMCGW_OK;
+    hipSetDevice(c->device);
+    if (!c->d_queue && hipMalloc(&c->d_queue, 256) != hipSuccess) return SMCGW_ERR_OOM;
+    NutsArgs a;
+    a.P = P;
+    a.D = D;
+    a.theta = theta;
+    a.logl = logl;
+    a.grad = grad;
+    a.chol = chol;
+    a.step = prm->step;
+    a.beta = prm->beta;
+    a.max_dh = prm->max_delta_h;
+    a.max_depth = prm->max_depth;
+    a.uturn = prm->uturn ? 1 : 0;
+    a.seed = prm->seed;
+    a.iteration = prm->iteration;
+    a.md_per_p = max_depth_per_particle;
+    a.depth_out = depth;
+    a.nlf_out = n_leapfrog;
+    a.div_out = divergent;
+    a.acc_out = accept_stat;
+    a.events = c->d_events;
+    a.n_events = (int)c->events.size();
+    a.ev_of_p = c->ev_of_p;
+    a.queue = (int*)c->d_queue;
+    const TargetDesc t = c->target;
+    switch (kind) {
+    case SMCGW_TARGET_GW:
+        switch (c->n_det) {
+        case 1: return launch_gw<1>(c, precision, a, c->prior, c->pmap, t);
+        case 2: return launch_gw<2>(c, precision, a, c->prior, c->pmap, t);
+        case 3: return launch_gw<3>(c, precision, a, c->prior, c->pmap, t);
+        case 4: return launch_gw<4>(c, precision, a, c->prior, c->pmap, t);
+        default: return SMCGW_ERR_SHAPE;
+        }
+    case SMCGW_TARGET_GAUSS:
+        return launch_persistent(c, nuts_kernel<1, SMCGW_PLAIN_FP64, SMCGW_TARGET_GAUSS, 1>, 64, a, c->prior,
+                                 c->pmap, t);
+    case SMCGW_TARGET_GAUSS_X_GAUSS:
+        return launch_persistent(c, nuts_kernel<1, SMCGW_PLAIN_FP64, SMCGW_TARGET_GAUSS_X_GAUSS, 1>, 64, a, c->prior,
+                                 c->pmap, t);
+    case SMCGW_TARGET_BIMODAL:
+        return launch_persistent(c, nuts_kernel<1, SMCGW_PLAIN_FP64, SMCGW_TARGET_BIMODAL, 1>, 64, a, c->prior,
+                                 c->pmap, t);
+    default:
+        return SMCGW_ERR_INVALID;
+    }
 }

@@ -216,6 +216,41 @@ __global__ __launch_bounds__(256) void mass_matrix_kernel(const double* __restri
     status[0] = bad;
 }
 
+// Analytic test likelihoods, one particle per lane (same definitions as the
+// persistent NUTS kernel's).
+__global__ __launch_bounds__(256) void analytic_loglike_kernel(int kind, int P, int D, const double* __restrict__ prm,
+                                                               const double* __restrict__ x, double* __restrict__ logl,
+                                                               double* __restrict__ grad) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P) return;
+    const double* xi = x + (size_t)i * D;
+    double* gi = grad ? grad + (size_t)i * D : nullptr;
+    double ll = 0.0;
+    if (kind == SMCGW_TARGET_GAUSS) {
+        for (int k = 0; k < D; ++k) { ll += -0.5 * xi[k] * xi[k]; if (gi) gi[k] = -xi[k]; }
+    } else if (kind == SMCGW_TARGET_GAUSS_X_GAUSS) {
+        for (int k = 0; k < D; ++k) {
+            const double r = (prm[k] - xi[k]) / prm[D + k];
+            ll += -0.5 * r * r - 0.5 * log(2.0 * PI * prm[D + k] * prm[D + k]);
+            if (gi) gi[k] = r / prm[D + k];
+        }
+    } else {
+        const double sg = prm[2 * D];
+        double s1 = 0.0, s2 = 0.0;
+        for (int k = 0; k < D; ++k) {
+            s1 += (xi[k] - prm[k]) * (xi[k] - prm[k]);
+            s2 += (xi[k] - prm[D + k]) * (xi[k] - prm[D + k]);
+        }
+        const double c = -0.5 * D * log(2.0 * PI * sg * sg);
+        const double l1 = c - 0.5 * s1 / (sg * sg), l2 = c - 0.5 * s2 / (sg * sg);
+        const double mx = fmax(l1, l2), w1 = exp(l1 - mx), w2 = exp(l2 - mx);
+        ll = mx + log(w1 + w2);
+        if (gi)
+            for (int k = 0; k < D; ++k) gi[k] = (w1 * (prm[k] - xi[k]) + w2 * (prm[D + k] - xi[k])) / (sg * sg) / (w1 + w2);
+    }
+    logl[i] = ll;
+}
+
 // Scratch of the sampler entry points (device), grown on demand.
 void* sampler_scratch(smcgw_ctx* c, size_t bytes) {
     if (bytes <= c->sampler_bytes) return c->d_sampler;
@@ -303,7 +338,7 @@ extern "C" int smcgw_smc_reweight_resample(smcgw_ctx* c, int P, int D, double be
                                            int32_t* ancestors, double* beta_next_host, double* dlogz_host) {
     if (!c || P < 1 || D <= 0 || D > MAXDIM || !theta || !logl || !ancestors || !beta_next_host || !dlogz_host)
         return SMCGW_ERR_INVALID;
-    if (!(alpha > 0.0 && alpha <= 1.0) || !(beta_prev >= 0.0 && beta_prev < 1.0)) return SMCGW_ERR_INVALID;
+    if (!(alpha > 0.0 && alpha <= 1.0) || !(beta_prev >= 0.0 && beta_prev <= 1.0)) return SMCGW_ERR_INVALID;
     hipSetDevice(c->device);
     const size_t off_cum = 64 * sizeof(double);
     const size_t off_x = off_cum + (size_t)P * sizeof(double);
@@ -329,6 +364,19 @@ extern "C" int smcgw_smc_reweight_resample(smcgw_ctx* c, int P, int D, double be
         return SMCGW_ERR_HIP;
     *beta_next_host = hp[0];
     *dlogz_host = hp[1];
-    if (!(hp[0] > beta_prev)) return SMCGW_ERR_STALL;
+    if (!(hp[0] > beta_prev) && beta_prev < 1.0) return SMCGW_ERR_STALL;
     return SMCGW_OK;
+}
+
+extern "C" int smcgw_target_loglike_grad(smcgw_ctx* c, int P, const double* theta, double* logl, double* grad,
+                                         int precision) {
+    if (!c || P < 0 || (P > 0 && (!theta || !logl))) return SMCGW_ERR_INVALID;
+    if (precision != SMCGW_PLAIN_FP64 && precision != SMCGW_MIXED) return SMCGW_ERR_INVALID;
+    if (P == 0) return SMCGW_OK;
+    hipSetDevice(c->device);
+    if (c->target.kind == SMCGW_TARGET_GW) return ctx_loglike(c, P, c->ev_of_p, theta, logl, grad, precision);
+    if (c->target.dim <= 0) return SMCGW_ERR_NOT_INIT;
+    hipLaunchKernelGGL(analytic_loglike_kernel, dim3((P + 255) / 256), dim3(256), 0, c->stream, c->target.kind, P,
+                       c->target.dim, c->target.params, theta, logl, grad);
+    return hipGetLastError() == hipSuccess ? SMCGW_OK : SMCGW_ERR_HIP;
 }

@@ -3,7 +3,7 @@
 // For the inner product of arXiv:2601.02336 Sec. 2 (Eq. 2) discretised on
 // f_j = f_low + j df, every particle reuses the same per-bin quantities:
 //   u_dj = 4 df conj(d_dj) f_j^-7/6 / S_dj            (whitened data x amplitude shape)
-//   B_b(f_j)                                        (phase basis rows)
+//   f_j, f_j^-1/3, ln f_j                           (phase basis generators)
 //   H_d  = sum_j 4 df f_j^-7/3 / S_dj,  <d|d>_d = sum_j 4 df |d_dj|^2 / S_dj.
 // The tables are zero-padded to a multiple of TABLE_PAD bins; padded bins have
 // u = 0 and finite basis values, so they add nothing to any sum.
@@ -13,23 +13,14 @@ namespace smcgw {
 
 __global__ __launch_bounds__(256) void build_tables_kernel(const double* __restrict__ data, const double* __restrict__ psd,
                                                            int n_det, int n, int npad, double f_low, double df,
-                                                           double inv_us, double* __restrict__ basis,
-                                                           double* __restrict__ freq, float2* __restrict__ u32,
-                                                           double2* __restrict__ u64) {
+                                                           double inv_us, double* __restrict__ fwl,
+                                                           float2* __restrict__ u32, double2* __restrict__ u64) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= npad) return;
     const double f = f_low + df * (double)j;
-    const double lf = log(f);
-    const double f13 = cbrt(f);
-    basis[(size_t)B_M53 * npad + j] = pow(f, -5.0 / 3.0);
-    basis[(size_t)B_M1 * npad + j] = 1.0 / f;
-    basis[(size_t)B_M23 * npad + j] = pow(f, -2.0 / 3.0);
-    basis[(size_t)B_M13 * npad + j] = 1.0 / f13;
-    basis[(size_t)B_LN * npad + j] = lf;
-    basis[(size_t)B_P13 * npad + j] = f13;
-    basis[(size_t)B_P13LN * npad + j] = f13 * lf;
-    basis[(size_t)B_P23 * npad + j] = pow(f, 2.0 / 3.0);
-    freq[j] = f;
+    fwl[(size_t)ROW_F * npad + j] = f;
+    fwl[(size_t)ROW_W * npad + j] = 1.0 / cbrt(f);
+    fwl[(size_t)ROW_LN * npad + j] = log(f);
     const double a = pow(f, -7.0 / 6.0);
     for (int d = 0; d < n_det; ++d) {
         double ur = 0.0, ui = 0.0;
@@ -75,10 +66,10 @@ __global__ __launch_bounds__(256) void table_sums_kernel(const double* __restric
 }
 
 hipError_t launch_build_tables(const double* d_data, const double* d_psd, int n_det, int n_bins, int n_pad,
-                               double f_low, double df, double u_scale, double* basis, double* freq, float2* u32,
-                               double2* u64, double* sums, hipStream_t s) {
+                               double f_low, double df, double u_scale, double* fwl, float2* u32, double2* u64,
+                               double* sums, hipStream_t s) {
     hipLaunchKernelGGL(build_tables_kernel, dim3((n_pad + 255) / 256), dim3(256), 0, s, d_data, d_psd, n_det, n_bins,
-                       n_pad, f_low, df, 1.0 / u_scale, basis, freq, u32, u64);
+                       n_pad, f_low, df, 1.0 / u_scale, fwl, u32, u64);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(table_sums_kernel, dim3(n_det), dim3(256), 0, s, d_data, d_psd, n_bins, f_low, df, sums);

@@ -22,6 +22,7 @@ OK, WARN_FALLBACK = 0, 1
 ERR_INVALID, ERR_SHAPE, ERR_HIP, ERR_OOM, ERR_NOT_INIT, ERR_STALL = -1, -2, -3, -4, -5, -6
 PLAIN_FP64, MIXED = 0, 1
 KERNEL_BINS, KERNEL_PREP, KERNEL_FINISH, KERNEL_NUTS, KERNEL_SMC = 0, 1, 2, 3, 4
+OPT_NUTS_WAVES = 0
 
 
 class SmcgwError(RuntimeError):
@@ -69,13 +70,16 @@ def lib():
         L.smcgw_set_stream.argtypes = [vp, vp]
         L.smcgw_add_event.argtypes = [vp, C.POINTER(EventDesc), vp, vp, C.POINTER(Detector), C.POINTER(i)]
         L.smcgw_set_param_map.argtypes = [vp, i, vp, vp]
+        L.smcgw_set_event_map.argtypes = [vp, vp]
         L.smcgw_set_prior.argtypes = [vp, i, C.POINTER(Bounds)]
         L.smcgw_set_target.argtypes = [vp, i, i, vp, i]
         L.smcgw_loglike_grad.argtypes = [vp, i, vp, vp, vp, vp, i]
         L.smcgw_waveform.argtypes = [vp, i, vp, vp]
+        L.smcgw_target_loglike_grad.argtypes = [vp, i, vp, vp, vp, i]
         L.smcgw_mass_matrix.argtypes = [vp, i, i, vp, d, vp, vp]
         L.smcgw_nuts_step.argtypes = [vp, i, i, vp, vp, vp, vp, C.POINTER(NutsParams), vp, i, vp, vp, vp, vp]
         L.smcgw_timing_enable.argtypes = [vp, i]
+        L.smcgw_set_option.argtypes = [vp, i, C.c_int64]
         L.smcgw_timing_read.argtypes = [vp, i, C.POINTER(d), C.POINTER(C.c_int64)]
         L.smcgw_smc_reweight_resample.argtypes = [vp, i, i, d, d, u64, u64, vp, vp, vp, vp,
                                                   C.POINTER(d), C.POINTER(d)]
@@ -131,6 +135,9 @@ class Context:
         s = torch.cuda.current_stream(self.device).cuda_stream
         lib().smcgw_set_stream(self._h, C.c_void_p(s))
 
+    def set_option(self, option: int, value: int):
+        _check("smcgw_set_option", lib().smcgw_set_option(self._h, option, value))
+
     # ------------------------------------------------------------ timing
     def timing(self, *kernel_classes: int):
         """Record events around launches of the given kernel classes (none: off)."""
@@ -158,6 +165,13 @@ class Context:
                                                         psd.ctypes.data_as(C.c_void_p), dets, C.byref(eid)))
         self.events.append(ev)
         return eid.value
+
+    def set_event_map(self, event_of_particle: Optional[torch.Tensor]):
+        """Device int32 [P] event index per particle for the sampler calls (kept alive here)."""
+        if event_of_particle is not None:
+            _dev(event_of_particle, torch.int32, "event_of_particle")
+        self._event_map = event_of_particle
+        _check("smcgw_set_event_map", lib().smcgw_set_event_map(self._h, _ptr(event_of_particle)))
 
     def set_param_map(self, param_index: Sequence[int], fixed11: Optional[Sequence[float]] = None):
         idx = np.ascontiguousarray(param_index, dtype=np.int32)
@@ -192,6 +206,20 @@ class Context:
             self._h, P, _ptr(event_of_particle), _ptr(theta), _ptr(logl), _ptr(grad) if want_grad else None,
             precision))
         return (logl, grad) if want_grad else logl
+
+    def target_loglike_grad(self, theta: torch.Tensor, logl: Optional[torch.Tensor] = None,
+                            grad: Optional[torch.Tensor] = None, precision: int = MIXED):
+        """logL and gradient of the context's current target (GW or analytic)."""
+        theta = _dev(theta, torch.float64, "theta")
+        P = theta.shape[0]
+        if logl is None:
+            logl = torch.empty(P, dtype=torch.float64, device=theta.device)
+        if grad is None:
+            grad = torch.empty_like(theta)
+        self._stream()
+        _check("smcgw_target_loglike_grad", lib().smcgw_target_loglike_grad(
+            self._h, P, _ptr(theta), _ptr(logl), _ptr(grad), precision))
+        return logl, grad
 
     def waveform(self, event_id: int, theta11) -> torch.Tensor:
         ev = self.events[event_id]
