@@ -263,6 +263,7 @@ extern "C" int smcgw_add_event(smcgw_ctx* c, const smcgw_event_desc* ev, const d
     }
     de.u_scale = us;
     de.t_sun = ev->t_sun;
+    de.ln_pi_tsun = std::log(M_PI * ev->t_sun);
     de.mpc_m = ev->mpc_m;
     de.c_light = ev->c_light;
     de.gmst = ev->gmst;

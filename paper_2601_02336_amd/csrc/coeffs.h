@@ -55,21 +55,22 @@ template <int N> __device__ __forceinline__ Dv<N> dexp(const Dv<N>& a) { const d
 
 // ---------------------------------------------------------------- TaylorF2
 // Phase coefficients in the (eta, delta = (m1-m2)/M, chi_s, chi_a) form.
-typedef Dv<4> D4;
-__device__ __forceinline__ void tf2_phi(const D4& eta, const D4& delta, const D4& chis, const D4& chia, int pn,
-                                        D4 phi[8], D4& phi5l, D4& phi6l) {
+template <int N>
+__device__ __forceinline__ void tf2_phi(const Dv<N>& eta, const Dv<N>& delta, const Dv<N>& chis, const Dv<N>& chia,
+                                        int pn, Dv<N> phi[8], Dv<N>& phi5l, Dv<N>& phi6l) {
+    typedef Dv<N> DN;
     const double pi = PI;
-    const D4 eta2 = eta * eta;
-    const D4 eta3 = eta2 * eta;
-    const D4 dchia = delta * chia;
-    phi[0] = dconst<4>(1.0);
-    phi[1] = dconst<4>(0.0);
+    const DN eta2 = eta * eta;
+    const DN eta3 = eta2 * eta;
+    const DN dchia = delta * chia;
+    phi[0] = dconst<N>(1.0);
+    phi[1] = dconst<N>(0.0);
     phi[2] = 3715.0 / 756.0 + (55.0 / 9.0) * eta;
     phi[3] = (-16.0 * pi) + (113.0 / 3.0) * dchia + ((113.0 / 3.0) - (76.0 / 3.0) * eta) * chis;
     phi[4] = (15293365.0 / 508032.0) + (27145.0 / 504.0) * eta + (3085.0 / 72.0) * eta2
            + ((-405.0 / 8.0) + 200.0 * eta) * (chia * chia) - (405.0 / 4.0) * (dchia * chis)
            + ((-405.0 / 8.0) + 2.5 * eta) * (chis * chis);
-    const D4 x5 = (38645.0 * pi / 756.0) - (65.0 * pi / 9.0) * eta
+    const DN x5 = (38645.0 * pi / 756.0) - (65.0 * pi / 9.0) * eta
                + ((-732985.0 / 2268.0) - (140.0 / 9.0) * eta) * dchia
                + ((-732985.0 / 2268.0) + (24260.0 / 81.0) * eta + (340.0 / 9.0) * eta2) * chis;
     phi[5] = x5;
@@ -80,46 +81,60 @@ __device__ __forceinline__ void tf2_phi(const D4& eta, const D4& delta, const D4
            + ((-15737765635.0 / 3048192.0) + (2255.0 / 12.0) * pi * pi) * eta + (76055.0 / 1728.0) * eta2
            - (127825.0 / 1296.0) * eta3 + ((2270.0 / 3.0) * pi) * dchia
            + ((2270.0 / 3.0) * pi - (520.0 * pi) * eta) * chis;
-    phi6l = dconst<4>(-6848.0 / 21.0);
+    phi6l = dconst<N>(-6848.0 / 21.0);
     phi[7] = (77096675.0 * pi / 254016.0) + (378515.0 * pi / 1512.0) * eta - (74045.0 * pi / 756.0) * eta2
            + ((-25150083775.0 / 3048192.0) + (26804935.0 / 6048.0) * eta - (1985.0 / 48.0) * eta2) * dchia
            + ((-25150083775.0 / 3048192.0) + (10566655595.0 / 762048.0) * eta - (1042165.0 / 3024.0) * eta2
               + (5345.0 / 36.0) * eta3) * chis;
     for (int k = 0; k < 8; ++k)
-        if (k > pn) phi[k] = dconst<4>(0.0);
-    if (pn < 5) phi5l = dconst<4>(0.0);
-    if (pn < 6) phi6l = dconst<4>(0.0);
+        if (k > pn) phi[k] = dconst<N>(0.0);
+    if (pn < 5) phi5l = dconst<N>(0.0);
+    if (pn < 6) phi6l = dconst<N>(0.0);
 }
 
-// Intrinsic part: coefficients c_b (cycles) and their derivatives with
-// respect to (Mc, q, chi1, chi2); phi_c and the -1/8 cycle offset included.
-__device__ __forceinline__ void prep_intrinsic(const DevEvent& ev, const double th[NPAR], double* cb) {
-    const D4 mc = dvar<4>(th[P_MC], 0);
-    const D4 q = dvar<4>(th[P_Q], 1);
-    const D4 c1 = dvar<4>(th[P_CHI1], 2);
-    const D4 c2 = dvar<4>(th[P_CHI2], 3);
-    const D4 opq = 1.0 + q;
-    const D4 iopq = recip(opq);
-    const D4 eta = q * (iopq * iopq);
-    const D4 delta = (1.0 - q) * iopq;
-    const D4 chis = 0.5 * (c1 + c2);
-    const D4 chia = 0.5 * (c1 - c2);
-    const D4 lneta = dlog(eta);
-    const D4 lnmc = dlog(mc);
+// Seeds parameter p of (Mc, q, chi1, chi2) as tangent p - k0 when it falls in [k0, k0 + N).
+template <int N>
+__device__ __forceinline__ Dv<N> seed(double x, int p, int k0) {
+    Dv<N> r = dconst<N>(x);
+    const int t = p - k0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) r.d[i] = (i == t) ? 1.0 : 0.0;
+    return r;
+}
+
+// Intrinsic part: coefficients c_b (cycles) and their derivatives with respect
+// to the N intrinsic parameters k0 .. k0+N-1 of (Mc, q, chi1, chi2); phi_c and
+// the -1/8 cycle offset included.  Values are written when write_values.
+template <int N>
+__device__ __forceinline__ void prep_intrinsic_n(const DevEvent& ev, const double th[NPAR], double* cb, int k0,
+                                                 bool write_values) {
+    typedef Dv<N> DN;
+    const DN mc = seed<N>(th[P_MC], 0, k0);
+    const DN q = seed<N>(th[P_Q], 1, k0);
+    const DN c1 = seed<N>(th[P_CHI1], 2, k0);
+    const DN c2 = seed<N>(th[P_CHI2], 3, k0);
+    const DN opq = 1.0 + q;
+    const DN iopq = recip(opq);
+    const DN eta = q * (iopq * iopq);
+    const DN delta = (1.0 - q) * iopq;
+    const DN chis = 0.5 * (c1 + c2);
+    const DN chia = 0.5 * (c1 - c2);
+    const DN lneta = dlog(eta);
+    const DN lnmc = dlog(mc);
     // ln(pi M), M = Mc eta^{-3/5} t_sun
-    const D4 lnpm = lnmc + (-0.6) * lneta + dconst<4>(log(PI * ev.t_sun));
-    const D4 pm13 = dexp((1.0 / 3.0) * lnpm);
-    const D4 pmm13 = recip(pm13);
-    const D4 pm23 = pm13 * pm13;
-    const D4 pmm23 = pmm13 * pmm13;
-    const D4 pmm1 = pmm23 * pmm13;
-    const D4 pmm53 = pmm1 * pmm23;
-    D4 phi[8], phi5l, phi6l;
-    tf2_phi(eta, delta, chis, chia, ev.pn_order, phi, phi5l, phi6l);
-    const D4 pref = (3.0 / (256.0 * PI)) * recip(eta);   // 3/(128 eta) / (2 pi): cycles
-    D4 c[NCOEF];
-    const D4 third5l = (1.0 / 3.0) * phi5l;
-    const D4 third6l = (1.0 / 3.0) * phi6l;
+    const DN lnpm = lnmc + (-0.6) * lneta + dconst<N>(ev.ln_pi_tsun);
+    const DN pm13 = dexp((1.0 / 3.0) * lnpm);
+    const DN pmm13 = recip(pm13);
+    const DN pm23 = pm13 * pm13;
+    const DN pmm23 = pmm13 * pmm13;
+    const DN pmm1 = pmm23 * pmm13;
+    const DN pmm53 = pmm1 * pmm23;
+    DN phi[8], phi5l, phi6l;
+    tf2_phi<N>(eta, delta, chis, chia, ev.pn_order, phi, phi5l, phi6l);
+    const DN pref = (3.0 / (256.0 * PI)) * recip(eta);   // 3/(128 eta) / (2 pi): cycles
+    DN c[NCOEF];
+    const DN third5l = (1.0 / 3.0) * phi5l;
+    const DN third6l = (1.0 / 3.0) * phi6l;
     c[0] = pref * (phi[5] + third5l * lnpm);
     c[1 + B_M53] = pref * (phi[0] * pmm53);
     c[1 + B_M1] = pref * (phi[2] * pmm1);
@@ -130,17 +145,27 @@ __device__ __forceinline__ void prep_intrinsic(const DevEvent& ev, const double 
     c[1 + B_P13LN] = pref * (pm13 * third6l);
     c[1 + B_P23] = pref * (phi[7] * pm23);
     for (int b = 0; b < NCOEF; ++b) {
-        cb[CB_C + b] = c[b].v;
+        if (write_values) cb[CB_C + b] = (b == 0) ? c[0].v - th[P_PHIC] / TWO_PI - 0.125 : c[b].v;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) cb[CB_DC + 4 * b + k] = c[b].d[k];
+        for (int k = 0; k < N; ++k) cb[CB_DC + 4 * b + k0 + k] = c[b].d[k];
     }
-    cb[CB_C] += -th[P_PHIC] / TWO_PI - 0.125;
 }
 
-// Extrinsic part: delays, complex projections C_A u_scale P_d and Jacobians.
+__device__ __forceinline__ void prep_intrinsic(const DevEvent& ev, const double th[NPAR], double* cb) {
+    prep_intrinsic_n<4>(ev, th, cb, 0, true);
+}
+
+// Extrinsic part of detector d: delay, complex projection C_A u_scale P_d and
+// their Jacobians (zeros for d >= n_det).
 // F+ = A cos 2psi + B sin 2psi, Fx = B cos 2psi - A sin 2psi with
 // A = p.Dp - q.Dq, B = 2 p.Dq for the polarisation frame (p, q) at psi = 0.
-__device__ __forceinline__ void prep_extrinsic(const DevEvent& ev, const double th[NPAR], double* cb) {
+__device__ __forceinline__ void prep_extrinsic_det(const DevEvent& ev, const double th[NPAR], double* cb, int d) {
+    if (d >= ev.n_det) {
+        cb[CB_TAU + d] = 0.0; cb[CB_PR + d] = 0.0; cb[CB_PI + d] = 0.0;
+        for (int k = 0; k < 2; ++k) cb[CB_DTAU + 2 * d + k] = 0.0;
+        for (int k = 0; k < 4; ++k) { cb[CB_DPR + 4 * d + k] = 0.0; cb[CB_DPI + 4 * d + k] = 0.0; }
+        return;
+    }
     typedef Dv<2> D2;
     const D2 phi = dvar<2>(th[P_RA] - ev.gmst, 0);
     const D2 dec = dvar<2>(th[P_DEC], 1);
@@ -158,50 +183,51 @@ __device__ __forceinline__ void prep_extrinsic(const DevEvent& ev, const double 
     sincos(th[P_IOTA], &si, &ci);
     const double pp = 0.5 * (1.0 + ci * ci);
     const double camp = 0.45643546458763842789 /* sqrt(5/24) */ * 0.46619407703541166 /* pi^-2/3 */
-                      * pow(th[P_MC] * ev.t_sun, 5.0 / 6.0) * ev.c_light / (th[P_DL] * ev.mpc_m);
+                      * exp((5.0 / 6.0) * log(th[P_MC] * ev.t_sun)) * ev.c_light / (th[P_DL] * ev.mpc_m);
     const double S = camp * ev.u_scale;
+    D2 Dp[3], Dq[3];
+    for (int i = 0; i < 3; ++i) {
+        Dp[i] = dconst<2>(0.0);
+        Dq[i] = dconst<2>(0.0);
+        for (int j = 0; j < 3; ++j) {
+            Dp[i] = Dp[i] + ev.resp[d][i][j] * pv[j];
+            Dq[i] = Dq[i] + ev.resp[d][i][j] * qv[j];
+        }
+    }
+    D2 A = dconst<2>(0.0), B = dconst<2>(0.0), nr = dconst<2>(0.0);
+    for (int i = 0; i < 3; ++i) {
+        A = A + (pv[i] * Dp[i] - qv[i] * Dq[i]);
+        B = B + 2.0 * (pv[i] * Dq[i]);
+        nr = nr + ev.pos[d][i] * nv[i];
+    }
+    const D2 fp = c2 * A + s2 * B;
+    const D2 fx = c2 * B - s2 * A;
+    const D2 dt = (-1.0 / ev.c_light) * nr;
+    cb[CB_TAU + d] = th[P_TC] + dt.v;
+    cb[CB_DTAU + 2 * d + 0] = dt.d[0];
+    cb[CB_DTAU + 2 * d + 1] = dt.d[1];
+    // P = F+ (1 + cos^2 i)/2 - i Fx cos i
+    cb[CB_PR + d] = S * pp * fp.v;
+    cb[CB_PI + d] = -S * ci * fx.v;
+    cb[CB_DPR + 4 * d + 0] = -S * ci * si * fp.v;            // iota
+    cb[CB_DPI + 4 * d + 0] = S * si * fx.v;
+    cb[CB_DPR + 4 * d + 1] = S * pp * 2.0 * fx.v;            // psi: dF+/dpsi = 2 Fx
+    cb[CB_DPI + 4 * d + 1] = S * ci * 2.0 * fp.v;            //      dFx/dpsi = -2 F+
+    cb[CB_DPR + 4 * d + 2] = S * pp * fp.d[0];               // ra
+    cb[CB_DPI + 4 * d + 2] = -S * ci * fx.d[0];
+    cb[CB_DPR + 4 * d + 3] = S * pp * fp.d[1];               // dec
+    cb[CB_DPI + 4 * d + 3] = -S * ci * fx.d[1];
+}
+
+// Entries shared by all detectors: derivatives of ln C_A.
+__device__ __forceinline__ void prep_extrinsic_common(const double th[NPAR], double* cb) {
     cb[CB_DLNCA_MC] = (5.0 / 6.0) / th[P_MC];
     cb[CB_DLNCA_DL] = -1.0 / th[P_DL];
-    for (int d = 0; d < MAXDET; ++d) {
-        if (d >= ev.n_det) {
-            cb[CB_TAU + d] = 0.0; cb[CB_PR + d] = 0.0; cb[CB_PI + d] = 0.0;
-            for (int k = 0; k < 2; ++k) cb[CB_DTAU + 2 * d + k] = 0.0;
-            for (int k = 0; k < 4; ++k) { cb[CB_DPR + 4 * d + k] = 0.0; cb[CB_DPI + 4 * d + k] = 0.0; }
-            continue;
-        }
-        D2 Dp[3], Dq[3];
-        for (int i = 0; i < 3; ++i) {
-            Dp[i] = dconst<2>(0.0);
-            Dq[i] = dconst<2>(0.0);
-            for (int j = 0; j < 3; ++j) {
-                Dp[i] = Dp[i] + ev.resp[d][i][j] * pv[j];
-                Dq[i] = Dq[i] + ev.resp[d][i][j] * qv[j];
-            }
-        }
-        D2 A = dconst<2>(0.0), B = dconst<2>(0.0), nr = dconst<2>(0.0);
-        for (int i = 0; i < 3; ++i) {
-            A = A + (pv[i] * Dp[i] - qv[i] * Dq[i]);
-            B = B + 2.0 * (pv[i] * Dq[i]);
-            nr = nr + ev.pos[d][i] * nv[i];
-        }
-        const D2 fp = c2 * A + s2 * B;
-        const D2 fx = c2 * B - s2 * A;
-        const D2 dt = (-1.0 / ev.c_light) * nr;
-        cb[CB_TAU + d] = th[P_TC] + dt.v;
-        cb[CB_DTAU + 2 * d + 0] = dt.d[0];
-        cb[CB_DTAU + 2 * d + 1] = dt.d[1];
-        // P = F+ (1 + cos^2 i)/2 - i Fx cos i
-        cb[CB_PR + d] = S * pp * fp.v;
-        cb[CB_PI + d] = -S * ci * fx.v;
-        cb[CB_DPR + 4 * d + 0] = -S * ci * si * fp.v;            // iota
-        cb[CB_DPI + 4 * d + 0] = S * si * fx.v;
-        cb[CB_DPR + 4 * d + 1] = S * pp * 2.0 * fx.v;            // psi: dF+/dpsi = 2 Fx
-        cb[CB_DPI + 4 * d + 1] = S * ci * 2.0 * fp.v;            //      dFx/dpsi = -2 F+
-        cb[CB_DPR + 4 * d + 2] = S * pp * fp.d[0];               // ra
-        cb[CB_DPI + 4 * d + 2] = -S * ci * fx.d[0];
-        cb[CB_DPR + 4 * d + 3] = S * pp * fp.d[1];               // dec
-        cb[CB_DPI + 4 * d + 3] = -S * ci * fx.d[1];
-    }
+}
+
+__device__ __forceinline__ void prep_extrinsic(const DevEvent& ev, const double th[NPAR], double* cb) {
+    prep_extrinsic_common(th, cb);
+    for (int d = 0; d < MAXDET; ++d) prep_extrinsic_det(ev, th, cb, d);
 }
 
 __device__ __forceinline__ void expand_params(const ParamMap& pm, const double* x, double th[NPAR]) {

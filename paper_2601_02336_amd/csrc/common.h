@@ -53,6 +53,7 @@ struct DevEvent {
     double dd;               // sum_d <d|d>_d
     double u_scale;          // power of two keeping the FP32 table near unit magnitude
     double t_sun, mpc_m, c_light, gmst;
+    double ln_pi_tsun;       // ln(pi G Msun / c^3)
     double pos[MAXDET][3];   // detector positions [m]
     double resp[MAXDET][3][3];
 };

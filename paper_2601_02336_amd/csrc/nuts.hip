@@ -54,15 +54,18 @@ constexpr int MAXD1 = SMCGW_MAX_DEPTH + 1;
 
 struct NutsShared {
     double L[MAXDIM * MAXDIM];
+    double LT[MAXDIM * MAXDIM];                  // transpose of L
     double Minv[MAXDIM * MAXDIM];
+    double vec[MAXDIM], red[2][MAXDIM];          // cross-lane exchange of wavefront 0
     double cb[CB_SIZE];
     double mom[MAX_WAVES][MOM_SIZE];
     double th[NPAR];
-    double left[4][MAXDIM], right[4][MAXDIM];   // x, r, g (grad log p_t), gl (grad logL)
+    double left[5][MAXDIM], right[5][MAXDIM];   // x, r, g (grad log p_t), gl (grad logL), v = M^{-1} r
     double prop[2][MAXDIM], sprop[2][MAXDIM];    // x, gl
-    double ck_rho[MAXD1][MAXDIM], ck_r[MAXD1][MAXDIM];
+    double ck_rho[MAXD1][MAXDIM], ck_v[MAXD1][MAXDIM];   // U-turn checkpoints: prefix sum, first velocity
     double end_ll[2], end_lp[2];                 // logL, log p_t of left / right
     double plo[MAXDIM], phi[MAXDIM];             // prior / boundary description
+    double pnorm[MAXDIM];                        // log normalising constant of each coordinate's prior
     int pbnd[MAXDIM], pkind[MAXDIM];
     int pidx[MAXDIM];                            // sampled coordinate -> source parameter
     double pfixed[NPAR];
@@ -80,32 +83,49 @@ __device__ __forceinline__ double log_add_exp(double a, double b) {
     return m + log(exp(a - m) + exp(b - m));
 }
 
-// (M^{-1} v) for this lane's coordinate; all 64 lanes of the wavefront call it.
-__device__ __forceinline__ double minv_apply(const NutsShared& S, int D, int lane, double v) {
-    double acc = 0.0;
-    const int row = lane < D ? lane : 0;
-    for (int m = 0; m < D; ++m) acc = fma(S.Minv[row * MAXDIM + m], __shfl(v, m, 64), acc);
-    return lane < D ? acc : 0.0;
+// Cross-lane operations of wavefront 0 over the coordinate lanes 0..D-1, done
+// through LDS: each lane writes its value, then every lane reads all MAXDIM
+// entries (zero beyond D) and combines them in the same fixed order, so all
+// lanes obtain bitwise identical results.  LDS accesses of one wavefront
+// complete in issue order, so no barrier is needed between the write and the
+// reads.
+
+// Sum over the coordinate lanes of v.
+__device__ __forceinline__ double dim_sum(NutsShared& S, int D, int lane, double v) {
+    if (lane < MAXDIM) S.red[0][lane] = (lane < D) ? v : 0.0;
+    __builtin_amdgcn_wave_barrier();
+    double s = 0.0;
+#pragma unroll
+    for (int m = 0; m < MAXDIM; ++m) s += S.red[0][m];
+    __builtin_amdgcn_wave_barrier();
+    return s;
 }
 
-// r^T M^{-1} r / 2 = |L^T r|^2 / 2.
-__device__ __forceinline__ double kinetic(const NutsShared& S, int D, int lane, double r) {
-    double t = 0.0;
-    const int col = lane < D ? lane : 0;
-    for (int i = 0; i < D; ++i) {
-        const double ri = __shfl(r, i, 64);
-        if (i >= col) t = fma(S.L[i * MAXDIM + col], ri, t);
+// Two sums at once.
+__device__ __forceinline__ void dim_sum2(NutsShared& S, int D, int lane, double a, double b, double& sa, double& sb) {
+    if (lane < MAXDIM) {
+        S.red[0][lane] = (lane < D) ? a : 0.0;
+        S.red[1][lane] = (lane < D) ? b : 0.0;
     }
-    return 0.5 * wave_sum(lane < D ? t * t : 0.0);
+    __builtin_amdgcn_wave_barrier();
+    double x = 0.0, y = 0.0;
+#pragma unroll
+    for (int m = 0; m < MAXDIM; ++m) { x += S.red[0][m]; y += S.red[1][m]; }
+    __builtin_amdgcn_wave_barrier();
+    sa = x;
+    sb = y;
 }
 
-// Generalised no-U-turn criterion: rho.M^{-1}r_a > 0 and rho.M^{-1}r_b > 0.
-__device__ __forceinline__ bool no_uturn(const NutsShared& S, int D, int lane, double rho, double ra, double rb) {
-    const double va = minv_apply(S, D, lane, ra);
-    const double vb = minv_apply(S, D, lane, rb);
-    const double sa = wave_sum(lane < D ? rho * va : 0.0);
-    const double sb = wave_sum(lane < D ? rho * vb : 0.0);
-    return sa > 0.0 && sb > 0.0;
+// (M^{-1} v) for this lane's coordinate.
+__device__ __forceinline__ double minv_apply(NutsShared& S, int D, int lane, double v) {
+    if (lane < MAXDIM) S.vec[lane] = (lane < D) ? v : 0.0;
+    __builtin_amdgcn_wave_barrier();
+    const int row = lane < D ? lane : 0;
+    double acc = 0.0;
+#pragma unroll
+    for (int m = 0; m < MAXDIM; ++m) acc = fma(S.Minv[row * MAXDIM + m], S.vec[m], acc);
+    __builtin_amdgcn_wave_barrier();
+    return lane < D ? acc : 0.0;
 }
 
 // Normalised log prior of this lane's coordinate and its derivative.
@@ -114,15 +134,15 @@ __device__ __forceinline__ double log_prior_lane(const NutsShared& S, int k, dou
     const double lo = S.plo[k], hi = S.phi[k];
     switch (S.pkind[k]) {
     case SMCGW_PRIOR_UNIFORM:
-        return (x < lo || x > hi) ? -INFINITY : -log(hi - lo);
+        return (x < lo || x > hi) ? -INFINITY : S.pnorm[k];
     case SMCGW_PRIOR_LOGUNIFORM:
         if (x < lo || x > hi) return -INFINITY;
         g = -1.0 / x;
-        return -log(x) - log(log(hi / lo));
+        return -log(x) + S.pnorm[k];
     case SMCGW_PRIOR_GAUSSIAN: {
         const double r = (x - lo) / hi;
         g = -r / hi;
-        return -0.5 * r * r - 0.5 * log(2.0 * PI * hi * hi);
+        return -0.5 * r * r + S.pnorm[k];
     }
     default:
         return 0.0;
@@ -145,20 +165,21 @@ __device__ __forceinline__ void boundary_lane(const NutsShared& S, int k, double
 
 // Analytic likelihoods (one coordinate per lane of wavefront 0).
 template <int TK>
-__device__ __forceinline__ double analytic_loglike(const TargetDesc& t, int D, int lane, double x, double& gl) {
+__device__ __forceinline__ double analytic_loglike(NutsShared& S, const TargetDesc& t, int D, int lane, double x,
+                                                   double& gl) {
     const bool dl = lane < D;
     if (TK == SMCGW_TARGET_GAUSS) {
         gl = dl ? -x : 0.0;
-        return -0.5 * wave_sum(dl ? x * x : 0.0);
+        return -0.5 * dim_sum(S, D, lane, x * x);
     } else if (TK == SMCGW_TARGET_GAUSS_X_GAUSS) {
         const double y = dl ? t.params[lane] : 0.0, s = dl ? t.params[D + lane] : 1.0;
         const double r = (y - x) / s;
         gl = dl ? r / s : 0.0;
-        return wave_sum(dl ? -0.5 * r * r - 0.5 * log(2.0 * PI * s * s) : 0.0);
+        return dim_sum(S, D, lane, -0.5 * r * r - 0.5 * log(2.0 * PI * s * s));
     } else {
         const double m1 = dl ? t.params[lane] : 0.0, m2 = dl ? t.params[D + lane] : 0.0, sg = t.params[2 * D];
-        const double s1 = wave_sum(dl ? (x - m1) * (x - m1) : 0.0);
-        const double s2 = wave_sum(dl ? (x - m2) * (x - m2) : 0.0);
+        double s1, s2;
+        dim_sum2(S, D, lane, (x - m1) * (x - m1), (x - m2) * (x - m2), s1, s2);
         const double c = -0.5 * D * log(2.0 * PI * sg * sg);
         const double l1 = c - 0.5 * s1 / (sg * sg), l2 = c - 0.5 * s2 / (sg * sg);
         const double mx = fmax(l1, l2);
@@ -179,7 +200,7 @@ struct NutsState {
 };
 
 // Start a transition of particle p (wavefront 0): momentum, H0, tree of one point.
-__device__ __forceinline__ void start_transition(NutsShared& S, NutsState& T, const NutsArgs& a, int p, int lane) {
+__device__ __noinline__ void start_transition(NutsShared& S, NutsState& T, const NutsArgs& a, int p, int lane) {
     const int D = a.D;
     const bool dl = lane < D;
     const int kk = dl ? lane : 0;
@@ -187,7 +208,7 @@ __device__ __forceinline__ void start_transition(NutsShared& S, NutsState& T, co
     const double gl = dl ? a.grad[(size_t)p * D + lane] : 0.0;
     const double ll = a.logl[p];
     double gp;
-    const double lpr = wave_sum(dl ? log_prior_lane(S, kk, x, gp) : 0.0);
+    const double lpr = dim_sum(S, D, lane, dl ? log_prior_lane(S, kk, x, gp) : 0.0);
     if (!dl) gp = 0.0;
     const double lp = a.beta * ll + lpr;
     const double g = a.beta * gl + gp;
@@ -203,10 +224,11 @@ __device__ __forceinline__ void start_transition(NutsShared& S, NutsState& T, co
         if (lane < i) accz = fma(-S.L[i * MAXDIM + lane], ri, accz);
     }
     if (!dl) r = 0.0;
-    const double h0 = -lp + kinetic(S, D, lane, r);
+    const double v = minv_apply(S, D, lane, r);
+    const double h0 = -lp + 0.5 * dim_sum(S, D, lane, r * v);
     if (dl) {
-        S.left[0][lane] = x; S.left[1][lane] = r; S.left[2][lane] = g; S.left[3][lane] = gl;
-        S.right[0][lane] = x; S.right[1][lane] = r; S.right[2][lane] = g; S.right[3][lane] = gl;
+        S.left[0][lane] = x; S.left[1][lane] = r; S.left[2][lane] = g; S.left[3][lane] = gl; S.left[4][lane] = v;
+        S.right[0][lane] = x; S.right[1][lane] = r; S.right[2][lane] = g; S.right[3][lane] = gl; S.right[4][lane] = v;
         S.prop[0][lane] = x; S.prop[1][lane] = gl;
         T.rho[lane] = r;
     }
@@ -232,7 +254,7 @@ __device__ __forceinline__ void start_transition(NutsShared& S, NutsState& T, co
 // CMD_EVAL with the new position in T.x (and the source parameters in S.th),
 // or CMD_DONE when the transition is complete.
 template <int TK>
-__device__ __forceinline__ int pre_leaf(NutsShared& S, NutsState& T, const NutsArgs& a, int p, int lane) {
+__device__ __noinline__ int pre_leaf(NutsShared& S, NutsState& T, const NutsArgs& a, int p, int lane) {
     const int D = a.D;
     const bool dl = lane < D;
     int state = T.state;
@@ -289,7 +311,7 @@ __device__ __forceinline__ int pre_leaf(NutsShared& S, NutsState& T, const NutsA
 // Second half of the leaf (wavefront 0): momentum half-step with the new
 // gradient, energy, divergence, progressive sampling, U-turn checks of the
 // nodes this leaf completes, and the merge when the subtree is complete.
-__device__ __forceinline__ void post_leaf(NutsShared& S, NutsState& T, const NutsArgs& a, int p, int lane) {
+__device__ __noinline__ void post_leaf(NutsShared& S, NutsState& T, const NutsArgs& a, int p, int lane) {
     const int D = a.D;
     const bool dl = lane < D;
     const int kk = dl ? lane : 0;
@@ -297,15 +319,16 @@ __device__ __forceinline__ void post_leaf(NutsShared& S, NutsState& T, const Nut
     const double gl = dl ? T.gl_new[lane] : 0.0;
     const double x = dl ? T.x[lane] : 0.0;
     double gp;
-    const double lpr = wave_sum(dl ? log_prior_lane(S, kk, x, gp) : 0.0);
+    const double lpr = dim_sum(S, D, lane, dl ? log_prior_lane(S, kk, x, gp) : 0.0);
     if (!dl) gp = 0.0;
     const double lp = a.beta * ll + lpr;
     const double g = a.beta * gl + gp;
     const double eps = T.eps;
     const double r = dl ? fma(0.5 * eps, g, T.r[lane]) : 0.0;
+    const double v = minv_apply(S, D, lane, r);   // velocity of this leaf: energy and every U-turn check
     const int j = T.j, n = T.n;
     const double h0 = T.h0;
-    const double dh = -lp + kinetic(S, D, lane, r) - h0;
+    const double dh = -lp + 0.5 * dim_sum(S, D, lane, r * v) - h0;
     const bool finite = (dh == dh) && dh != INFINITY && dh != -INFINITY;
     double acc_sum = T.acc_sum + (finite ? fmin(1.0, exp(-dh)) : 0.0);
     double srho = dl ? T.srho[lane] : 0.0;
@@ -319,7 +342,7 @@ __device__ __forceinline__ void post_leaf(NutsShared& S, NutsState& T, const Nut
         ok = false;
     } else {
         for (int l = 1; l <= j; ++l)
-            if ((n & ((1 << l) - 1)) == 0 && dl) { S.ck_rho[l][lane] = srho; S.ck_r[l][lane] = r; }
+            if ((n & ((1 << l) - 1)) == 0 && dl) { S.ck_rho[l][lane] = srho; S.ck_v[l][lane] = v; }
         srho += r;
         const double lw = -dh;
         const double nlw = log_add_exp(sub_logw, lw);
@@ -335,9 +358,12 @@ __device__ __forceinline__ void post_leaf(NutsShared& S, NutsState& T, const Nut
             __builtin_amdgcn_wave_barrier();
             for (int l = 1; l <= j && ok; ++l)
                 if (((n + 1) & ((1 << l) - 1)) == 0) {
+                    // node = leaves n+1-2^l .. n: rho.v_first > 0 and rho.v_last > 0
                     const double nr = srho - (dl ? S.ck_rho[l][lane] : 0.0);
-                    const double r0 = dl ? S.ck_r[l][lane] : 0.0;
-                    if (!no_uturn(S, D, lane, nr, r0, r)) ok = false;
+                    const double v0 = dl ? S.ck_v[l][lane] : 0.0;
+                    double sa, sb;
+                    dim_sum2(S, D, lane, nr * v0, nr * v, sa, sb);
+                    if (!(sa > 0.0 && sb > 0.0)) ok = false;
                 }
         }
     }
@@ -357,15 +383,17 @@ __device__ __forceinline__ void post_leaf(NutsShared& S, NutsState& T, const Nut
         const int side = T.dir > 0 ? 1 : 0;
         if (dl) {
             double (*E)[MAXDIM] = side ? S.right : S.left;
-            E[0][lane] = x; E[1][lane] = r; E[2][lane] = g; E[3][lane] = gl;
+            E[0][lane] = x; E[1][lane] = r; E[2][lane] = g; E[3][lane] = gl; E[4][lane] = v;
             T.rho[lane] = rho;
         }
         if (lane == 0) { S.end_ll[side] = ll; S.end_lp[side] = lp; }
         __builtin_amdgcn_wave_barrier();
         bool stop = false;
         if (a.uturn) {
-            const double rl = dl ? S.left[1][lane] : 0.0, rr = dl ? S.right[1][lane] : 0.0;
-            stop = !no_uturn(S, D, lane, rho, rl, rr);
+            const double vl = dl ? S.left[4][lane] : 0.0, vr = dl ? S.right[4][lane] : 0.0;
+            double sa, sb;
+            dim_sum2(S, D, lane, rho * vl, rho * vr, sa, sb);
+            stop = !(sa > 0.0 && sb > 0.0);
         }
         if (stop) {
             state = ST_DONE;
@@ -385,7 +413,7 @@ __device__ __forceinline__ void post_leaf(NutsShared& S, NutsState& T, const Nut
     }
 }
 
-__device__ __forceinline__ void write_outputs(NutsShared& S, NutsState& T, const NutsArgs& a, int p, int lane) {
+__device__ __noinline__ void write_outputs(NutsShared& S, NutsState& T, const NutsArgs& a, int p, int lane) {
     const int D = a.D;
     __builtin_amdgcn_wave_barrier();
     if (lane < D) {
@@ -399,6 +427,37 @@ __device__ __forceinline__ void write_outputs(NutsShared& S, NutsState& T, const
         if (a.div_out) a.div_out[p] = (uint8_t)T.div;
         if (a.acc_out) a.acc_out[p] = T.nlf > 0 ? T.acc_sum / T.nlf : 0.0;
     }
+}
+
+// Prologue pieces of one leaf (kept out of line so their registers do not
+// constrain the bin loop).
+__device__ __noinline__ void leaf_prep_intrinsic(const DevEvent* ev, NutsShared& S, int lane) {
+    prep_intrinsic_n<1>(*ev, S.th, S.cb, lane, lane == 0);
+}
+
+__device__ __noinline__ void leaf_prep_extrinsic(const DevEvent* ev, NutsShared& S, int lane) {
+    if (lane == 0) prep_extrinsic_common(S.th, S.cb);
+    prep_extrinsic_det(*ev, S.th, S.cb, lane);
+}
+
+// Epilogue of one leaf (wavefront 0): sum the wavefronts' moments, logL and
+// the gradient over the sampled coordinates.
+template <int WAVES>
+__device__ __noinline__ void leaf_finish(const DevEvent* ev, NutsShared& S, NutsState& T, int D, int lane) {
+    double mt[MOM_SIZE];
+    for (int i = 0; i < MOM_SIZE; ++i) {
+        double s = S.mom[0][i];
+        for (int w = 1; w < WAVES; ++w) s += S.mom[w][i];
+        mt[i] = s;
+    }
+    double g11[NPAR];
+    const double ll = finish_particle(*ev, S.cb, mt, g11);
+    const int src = lane < D ? S.pidx[lane] : 0;
+    double v = 0.0;
+#pragma unroll
+    for (int q = 0; q < NPAR; ++q) v = (src == q) ? g11[q] : v;
+    if (lane < D) T.gl_new[lane] = v;
+    if (lane == 0) T.ll_new = ll;
 }
 
 template <int NDET, int PREC, int TK, int WAVES>
@@ -419,6 +478,11 @@ __global__ __launch_bounds__(WAVES * 64, (WAVES == 1 ? 2 : 4)) void nuts_kernel(
         for (int k = 0; k < MAXDIM; ++k) {
             S.plo[k] = pri.lo[k]; S.phi[k] = pri.hi[k]; S.pbnd[k] = pri.bnd[k]; S.pkind[k] = pri.kind[k];
             S.pidx[k] = pm.idx[k];
+            const double lo = pri.lo[k], hi = pri.hi[k];
+            S.pnorm[k] = k >= D ? 0.0
+                       : pri.kind[k] == SMCGW_PRIOR_UNIFORM ? -log(hi - lo)
+                       : pri.kind[k] == SMCGW_PRIOR_LOGUNIFORM ? -log(log(hi / lo))
+                       : pri.kind[k] == SMCGW_PRIOR_GAUSSIAN ? -0.5 * log(2.0 * PI * hi * hi) : 0.0;
         }
         for (int k = 0; k < NPAR; ++k) S.pfixed[k] = pm.fixed[k];
     }
@@ -428,6 +492,7 @@ __global__ __launch_bounds__(WAVES * 64, (WAVES == 1 ? 2 : 4)) void nuts_kernel(
         double s = 0.0;
         for (int m = 0; m < D; ++m) s = fma(S.L[r * MAXDIM + m], S.L[c * MAXDIM + m], s);
         S.Minv[i] = s;
+        S.LT[i] = S.L[c * MAXDIM + r];
     }
     __syncthreads();
 
@@ -450,8 +515,10 @@ __global__ __launch_bounds__(WAVES * 64, (WAVES == 1 ? 2 : 4)) void nuts_kernel(
             if (__builtin_amdgcn_readfirstlane(S.cmd) == CMD_DONE) break;
 
             if (TK == SMCGW_TARGET_GW) {
-                if (wave == 0 && lane == 0) prep_intrinsic(*ev, S.th, S.cb);
-                if (wave == (WAVES > 1 ? 1 : 0) && lane == 0) prep_extrinsic(*ev, S.th, S.cb);
+                // prologue: one intrinsic tangent direction per lane of wavefront 0,
+                // one detector per lane of wavefront 1
+                if (wave == 0 && lane < 4) leaf_prep_intrinsic(ev, S, lane);
+                if (wave == (WAVES > 1 ? 1 : 0) && lane < MAXDET) leaf_prep_extrinsic(ev, S, lane);
                 __syncthreads();
                 {
                     const BinCoef k = load_coef(S.cb);
@@ -464,25 +531,10 @@ __global__ __launch_bounds__(WAVES * 64, (WAVES == 1 ? 2 : 4)) void nuts_kernel(
                         for (int i = 0; i < MOM_SIZE; ++i) S.mom[wave][i] = m[i];
                 }
                 __syncthreads();
-                if (wave == 0) {
-                    double mt[MOM_SIZE];
-                    for (int i = 0; i < MOM_SIZE; ++i) {
-                        double s = S.mom[0][i];
-                        for (int w = 1; w < WAVES; ++w) s += S.mom[w][i];
-                        mt[i] = s;
-                    }
-                    double g11[NPAR];
-                    const double ll = finish_particle(*ev, S.cb, mt, g11);
-                    const int src = lane < D ? S.pidx[lane] : 0;
-                    double v = 0.0;
-#pragma unroll
-                    for (int q = 0; q < NPAR; ++q) v = (src == q) ? g11[q] : v;
-                    if (lane < D) T.gl_new[lane] = v;
-                    if (lane == 0) T.ll_new = ll;
-                }
+                if (wave == 0) leaf_finish<WAVES>(ev, S, T, D, lane);
             } else if (wave == 0) {
                 double gl;
-                const double ll = analytic_loglike<TK>(tgt, D, lane, lane < D ? T.x[lane] : 0.0, gl);
+                const double ll = analytic_loglike<TK>(S, tgt, D, lane, lane < D ? T.x[lane] : 0.0, gl);
                 if (lane < D) T.gl_new[lane] = gl;
                 if (lane == 0) T.ll_new = ll;
             }
