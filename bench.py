@@ -103,15 +103,16 @@ def run_smc_steps(smcgw, ctx, theta, precision, args, n_warm, n_steps, time_kern
     """SMC iterations from prior draws; returns (evals, seconds, nuts kernel ms, launches, per-step stats)."""
     import torch
     logl, grad = ctx.target_loglike_grad(theta, precision=precision)
-    beta, it = 0.0, 0
+    beta, it, hint = 0.0, 0, None
     stats = []
 
     def one_step():
-        nonlocal beta, it
-        b, dz, _ = ctx.smc_reweight_resample(theta, logl, grad, beta, args.alpha, args.seed, it)
+        nonlocal beta, it, hint
+        b, dz, _ = ctx.smc_reweight_resample(theta, logl, grad, beta, args.alpha, args.seed, it, carry=hint)
         _, L, _ = ctx.mass_matrix(theta, 0.0)
         out = ctx.nuts_step(theta, logl, grad, L, step=args.step, beta=b, seed=args.seed, iteration=it,
-                            max_depth=args.max_depth, precision=precision)
+                            max_depth=args.max_depth, precision=precision, work_hint=hint)
+        hint = None if args.no_hint else out["n_leapfrog"]
         beta = b
         it += 1
         return out
@@ -154,6 +155,12 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the side measurements")
+    ap.add_argument("--no-hint", action="store_true", help="start particles in index order (no work hint)")
+    ap.add_argument("--priority", type=int, choices=[0, 1], default=1,
+                    help="depth-driven wavefront priority in the NUTS kernel")
+    ap.add_argument("--waves", type=int, choices=[0, 2, 4, 8], default=0, help="wavefronts per NUTS slot")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one 256 MiB device copy (reference dispatch for memory-traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); splitting particles across GPUs is "
@@ -172,6 +179,8 @@ def main():
     if args.mode == "smc":
         P = args.particles or 2048
         ctx, x_np, x = smc_setup(smcgw, synth, ev, P)
+        ctx.set_option(smcgw.OPT_NUTS_PRIORITY, args.priority)
+        ctx.set_option(smcgw.OPT_NUTS_WAVES, args.waves)
         evals, dt, k_ms, k_n, betas, hist = run_smc_steps(smcgw, ctx, x, prec, args, args.warmup, args.steps, True)
         value = evals / dt
         kernel_s = k_ms / 1e3
@@ -180,7 +189,7 @@ def main():
             f"{k_ms / max(k_n, 1):.2f} ms x {k_n}; betas {betas}")
         roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TLANEOPS, 3),
                     "unit": "Tlane-op/s", "frac": round(achieved / VALU_PEAK_TLANEOPS, 4), "traffic": None,
-                    "kernel": f"nuts_kernel<3,{'MIXED' if prec == smcgw.MIXED else 'PLAIN_FP64'},GW,4>",
+                    "kernel": f"nuts_kernel<3,{'MIXED' if prec == smcgw.MIXED else 'PLAIN_FP64'},GW,{args.waves or 4}>",
                     "kernel_ms": round(k_ms / max(k_n, 1), 3), "ops_per_particle_bin": ops,
                     "evals_in_kernel": evals}
         extra["betas"] = [round(b, 8) for b in betas]
@@ -193,6 +202,8 @@ def main():
         if not args.no_extra:
             # the plain-FP64 sampler on the same iterations, and the batched-likelihood kernel rates
             ctx2, _, x2 = smc_setup(smcgw, synth, ev, P)
+            ctx2.set_option(smcgw.OPT_NUTS_PRIORITY, args.priority)
+            ctx2.set_option(smcgw.OPT_NUTS_WAVES, args.waves)
             e2, d2, _, _, _, _ = run_smc_steps(smcgw, ctx2, x2, smcgw.PLAIN_FP64 if prec == smcgw.MIXED else smcgw.MIXED,
                                                args, args.warmup, max(2, args.steps // 2), False)
             extra["other_precision_in_sampler_evals_per_s"] = round(e2 / d2, 1)
@@ -254,6 +265,14 @@ def main():
             torch.cuda.synchronize()
             extra[name + "_evals_per_s"] = round(Pl * 10 / (time.perf_counter() - t1), 1)
         ctxl.close()
+
+    if args.copy_probe:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")   # 256 MiB
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -182,12 +182,17 @@ int smcgw_mass_matrix(smcgw_ctx *ctx, int P, int D, const double *theta, double 
  * and grad [P][D] (device) hold the current point, its likelihood and the
  * likelihood gradient on entry and the selected point on exit.  chol [D][D]
  * (device) is the Cholesky factor of M^{-1}.  max_depth_per_particle [P]
- * (device, NULL = params->max_depth) caps each tree.  Per-particle
- * diagnostics (device, each may be NULL): doublings done, leapfrog steps,
- * divergence flag, mean acceptance statistic. */
+ * (device, NULL = params->max_depth) caps each tree.  work_hint [P]
+ * (device, NULL = particle order) is a predicted leapfrog count per particle,
+ * e.g. the n_leapfrog of its ancestor's previous transition: particles start
+ * in descending order of floor(log2(hint)) so that the longest trees do not
+ * start last.  It changes only the schedule; every output is the same for
+ * any hint.  Per-particle diagnostics (device, each may be NULL): doublings
+ * done, leapfrog steps, divergence flag, mean acceptance statistic. */
 int smcgw_nuts_step(smcgw_ctx *ctx, int P, int D, double *theta, double *logl, double *grad, const double *chol,
-                    const smcgw_nuts_params *params, const int32_t *max_depth_per_particle, int precision,
-                    int32_t *depth, int32_t *n_leapfrog, uint8_t *divergent, double *accept_stat);
+                    const smcgw_nuts_params *params, const int32_t *max_depth_per_particle,
+                    const int32_t *work_hint, int precision, int32_t *depth, int32_t *n_leapfrog,
+                    uint8_t *divergent, double *accept_stat);
 
 /* Reweighting, adaptive temperature and multinomial resampling of one SMC
  * iteration (Sec. 3, Eqs. 4-6): beta_next solves ESS(beta) = alpha P by
@@ -195,19 +200,27 @@ int smcgw_nuts_step(smcgw_ctx *ctx, int P, int D, double *theta, double *logl, d
  * evidence increment log(Z_t/Z_{t-1}) = log mean_i L_i^(beta_next-beta_prev)
  * (Sec. 3.1, Eq. 7) is accumulated in FP64.  Ancestors are drawn with
  * Philox uniforms keyed by (seed, iteration) and theta [P][D], logl [P],
- * grad [P][D] (device) are gathered in place; ancestors [P] (device) receives
- * the indices.  Synchronises: *beta_next_host and *dlogz_host are host
- * scalars.  beta_prev = 1 is allowed (beta_next = 1, a resample-only
- * reweighting).  Returns SMCGW_ERR_STALL when beta cannot advance. */
+ * grad [P][D] and carry [P] (device; grad and carry may be NULL) are gathered
+ * in place; carry is any per-particle int32 payload that travels with the
+ * particles (e.g. the last transition's leapfrog counts, as a work hint).
+ * ancestors [P] (device) receives the indices.  Synchronises:
+ * *beta_next_host and *dlogz_host are host scalars.  beta_prev = 1 is
+ * allowed (beta_next = 1, a resample-only reweighting).  Returns
+ * SMCGW_ERR_STALL when beta cannot advance. */
 int smcgw_smc_reweight_resample(smcgw_ctx *ctx, int P, int D, double beta_prev, double alpha, uint64_t seed,
-                                uint64_t iteration, double *theta, double *logl, double *grad, int32_t *ancestors,
-                                double *beta_next_host, double *dlogz_host);
+                                uint64_t iteration, double *theta, double *logl, double *grad, int32_t *carry,
+                                int32_t *ancestors, double *beta_next_host, double *dlogz_host);
 
 /* ------------------------------------------------------------ options
  * Launch-shape options of a context (chosen by the autotuner or by hand).
  *   SMCGW_OPT_NUTS_WAVES: wavefronts that share one particle's bin loop in the
- *     persistent NUTS kernel (2, 4 or 8; 0 = the library default of 4). */
-enum { SMCGW_OPT_NUTS_WAVES = 0 };
+ *     persistent NUTS kernel (2, 4 or 8; 0 = the library default of 4).
+ *   SMCGW_OPT_NUTS_PRIORITY: 1 (default) raises the issue priority of a
+ *     slot's wavefronts as its tree deepens, so the longest trajectories of
+ *     a transition run ahead of the short ones that share their compute
+ *     unit; 0 keeps every wavefront at the same priority.  Scheduling only:
+ *     the outputs do not depend on it. */
+enum { SMCGW_OPT_NUTS_WAVES = 0, SMCGW_OPT_NUTS_PRIORITY = 1 };
 int smcgw_set_option(smcgw_ctx *ctx, int option, int64_t value);
 
 /* ------------------------------------------------------------ timing

@@ -138,6 +138,10 @@ extern "C" int smcgw_set_option(smcgw_ctx* c, int option, int64_t value) {
         if (value != 0 && value != 2 && value != 4 && value != 8) return SMCGW_ERR_INVALID;
         c->nuts_waves = (int)value;
         return SMCGW_OK;
+    case SMCGW_OPT_NUTS_PRIORITY:
+        if (value != 0 && value != 1) return SMCGW_ERR_INVALID;
+        c->nuts_priority = (int)value;
+        return SMCGW_OK;
     default:
         return SMCGW_ERR_INVALID;
     }

@@ -43,6 +43,9 @@ struct smcgw_ctx {
     // sampler scratch
     void* d_queue = nullptr;               // work-queue counter of the persistent kernels
     int nuts_waves = 0;                    // wavefronts per NUTS slot (0: default)
+    int nuts_priority = 1;                 // depth-driven wavefront priority in the NUTS kernel
+    int32_t* d_order = nullptr;            // NUTS start order built from a work hint
+    int order_cap = 0;
     std::unordered_map<const void*, int> resident;   // resident workgroups per device, per kernel
     const int32_t* ev_of_p = nullptr;      // caller-owned event index per particle (NULL: event 0)
     void* d_sampler = nullptr;
@@ -57,7 +60,10 @@ struct smcgw_ctx {
         hipFree(d_target_params);
         hipFree(d_sampler);
         hipFree(d_queue);
+        hipFree(d_order);
         d_queue = nullptr;
+        d_order = nullptr;
+        order_cap = 0;
         if (h_pinned) hipHostFree(h_pinned);
         d_target_params = nullptr;
         d_sampler = nullptr;

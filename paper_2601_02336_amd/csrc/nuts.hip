@@ -47,6 +47,8 @@ struct NutsArgs {
     int n_events;
     const int32_t* ev_of_p;
     int* queue;
+    const int32_t* order;   // start order of the particles (NULL: index order)
+    int priority;           // raise wavefront priority with the tree depth
 };
 
 constexpr int MAX_WAVES = 8;
@@ -429,6 +431,16 @@ __device__ __noinline__ void write_outputs(NutsShared& S, NutsState& T, const Nu
     }
 }
 
+// Issue priority of the slot's wavefronts while doubling j runs: a tree that
+// has reached 2^3, 2^4, 2^5 leaves outranks the shallower trees sharing its
+// SIMDs, so the transitions that decide when the launch ends go first.
+__device__ __forceinline__ void tree_priority(int j) {
+    if (j >= 5) __builtin_amdgcn_s_setprio(3);
+    else if (j == 4) __builtin_amdgcn_s_setprio(2);
+    else if (j == 3) __builtin_amdgcn_s_setprio(1);
+    else __builtin_amdgcn_s_setprio(0);
+}
+
 // Prologue pieces of one leaf (kept out of line so their registers do not
 // constrain the bin loop).
 __device__ __noinline__ void leaf_prep_intrinsic(const DevEvent* ev, NutsShared& S, int lane) {
@@ -444,14 +456,15 @@ __device__ __noinline__ void leaf_prep_extrinsic(const DevEvent* ev, NutsShared&
 // the gradient over the sampled coordinates.
 template <int WAVES>
 __device__ __noinline__ void leaf_finish(const DevEvent* ev, NutsShared& S, NutsState& T, int D, int lane) {
-    double mt[MOM_SIZE];
-    for (int i = 0; i < MOM_SIZE; ++i) {
-        double s = S.mom[0][i];
-        for (int w = 1; w < WAVES; ++w) s += S.mom[w][i];
-        mt[i] = s;
+    // wavefront totals of the moments, in wavefront order, into S.mom[0]
+    if (lane < MOM_SIZE) {
+        double s = S.mom[0][lane];
+        for (int w = 1; w < WAVES; ++w) s += S.mom[w][lane];
+        S.mom[0][lane] = s;
     }
+    __builtin_amdgcn_wave_barrier();
     double g11[NPAR];
-    const double ll = finish_particle(*ev, S.cb, mt, g11);
+    const double ll = finish_particle(*ev, S.cb, S.mom[0], g11);
     const int src = lane < D ? S.pidx[lane] : 0;
     double v = 0.0;
 #pragma unroll
@@ -497,7 +510,10 @@ __global__ __launch_bounds__(WAVES * 64, (WAVES == 1 ? 2 : 4)) void nuts_kernel(
     __syncthreads();
 
     for (;;) {
-        if (tid == 0) S.p = __hip_atomic_fetch_add(a.queue, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (tid == 0) {
+            const int q = __hip_atomic_fetch_add(a.queue, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            S.p = (q < a.P && a.order) ? a.order[q] : q;
+        }
         __syncthreads();
         const int p = __builtin_amdgcn_readfirstlane(S.p);
         if (p >= a.P) break;
@@ -513,6 +529,7 @@ __global__ __launch_bounds__(WAVES * 64, (WAVES == 1 ? 2 : 4)) void nuts_kernel(
             }
             __syncthreads();
             if (__builtin_amdgcn_readfirstlane(S.cmd) == CMD_DONE) break;
+            if (a.priority) tree_priority(__builtin_amdgcn_readfirstlane(T.j));
 
             if (TK == SMCGW_TARGET_GW) {
                 // prologue: one intrinsic tangent direction per lane of wavefront 0,
@@ -543,8 +560,69 @@ __global__ __launch_bounds__(WAVES * 64, (WAVES == 1 ? 2 : 4)) void nuts_kernel(
                 post_leaf(S, T, a, p, lane);
             }
         }
+        if (a.priority) __builtin_amdgcn_s_setprio(0);
         if (wave == 0) write_outputs(S, T, a, p, lane);
         __syncthreads();
+    }
+}
+
+// Start order from a work hint: particles sorted by descending bucket
+// floor(log2(hint)) + 1 (0 for hint <= 0), stable in the particle index.
+// One workgroup; thread t owns the contiguous index chunk [t*ch, (t+1)*ch).
+constexpr int ORDER_THREADS = 1024;
+constexpr int ORDER_BUCKETS = 16;
+
+__device__ __forceinline__ int hint_bucket(int32_t h) { return h <= 0 ? 0 : min(ORDER_BUCKETS - 1, 32 - __clz(h)); }
+
+__global__ __launch_bounds__(ORDER_THREADS) void order_kernel(const int32_t* __restrict__ hint, int P,
+                                                              int32_t* __restrict__ order) {
+    __shared__ int wsum[ORDER_THREADS / 64][ORDER_BUCKETS];
+    __shared__ int base[ORDER_THREADS / 64][ORDER_BUCKETS];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int ch = (P + ORDER_THREADS - 1) / ORDER_THREADS;
+    const int lo = min(P, tid * ch), hi = min(P, lo + ch);
+    int cnt[ORDER_BUCKETS];
+#pragma unroll
+    for (int k = 0; k < ORDER_BUCKETS; ++k) cnt[k] = 0;
+    for (int i = lo; i < hi; ++i) {
+        const int b = hint_bucket(hint[i]);
+#pragma unroll
+        for (int k = 0; k < ORDER_BUCKETS; ++k) cnt[k] += (b == k);
+    }
+    // exclusive offsets of this thread inside each bucket: lanes, then wavefronts
+    int off[ORDER_BUCKETS];
+#pragma unroll
+    for (int k = 0; k < ORDER_BUCKETS; ++k) {
+        int inc = cnt[k];
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int t = __shfl_up(inc, o);
+            if (lane >= o) inc += t;
+        }
+        off[k] = inc - cnt[k];
+        if (lane == 63) wsum[wave][k] = inc;
+    }
+    __syncthreads();
+    if (tid == 0) {   // bucket starts in descending bucket order, then wavefront order inside a bucket
+        int start = 0;
+        for (int k = ORDER_BUCKETS - 1; k >= 0; --k) {
+            for (int w = 0; w < ORDER_THREADS / 64; ++w) {
+                base[w][k] = start;
+                start += wsum[w][k];
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < ORDER_BUCKETS; ++k) off[k] += base[wave][k];
+    for (int i = lo; i < hi; ++i) {
+        const int b = hint_bucket(hint[i]);
+        int pos = 0;
+#pragma unroll
+        for (int k = 0; k < ORDER_BUCKETS; ++k) {
+            if (b == k) { pos = off[k]; ++off[k]; }
+        }
+        order[pos] = i;
     }
 }
 
@@ -599,8 +677,8 @@ int launch_gw(smcgw_ctx* c, int precision, const NutsArgs& a, const PriorDesc& p
 
 extern "C" int smcgw_nuts_step(smcgw_ctx* c, int P, int D, double* theta, double* logl, double* grad,
                                const double* chol, const smcgw_nuts_params* prm,
-                               const int32_t* max_depth_per_particle, int precision, int32_t* depth,
-                               int32_t* n_leapfrog, uint8_t* divergent, double* accept_stat) {
+                               const int32_t* max_depth_per_particle, const int32_t* work_hint, int precision,
+                               int32_t* depth, int32_t* n_leapfrog, uint8_t* divergent, double* accept_stat) {
     if (!c || !prm || P < 0 || D <= 0 || D > MAXDIM || (P > 0 && (!theta || !logl || !grad || !chol)))
         return SMCGW_ERR_INVALID;
     if (precision != SMCGW_PLAIN_FP64 && precision != SMCGW_MIXED) return SMCGW_ERR_INVALID;
@@ -617,6 +695,17 @@ extern "C" int smcgw_nuts_step(smcgw_ctx* c, int P, int D, double* theta, double
     if (P == 0) return SMCGW_OK;
     hipSetDevice(c->device);
     if (!c->d_queue && hipMalloc(&c->d_queue, 256) != hipSuccess) return SMCGW_ERR_OOM;
+    if (work_hint) {
+        if (P > c->order_cap) {
+            hipFree(c->d_order);
+            c->d_order = nullptr;
+            c->order_cap = 0;
+            if (hipMalloc(&c->d_order, (size_t)P * sizeof(int32_t)) != hipSuccess) return SMCGW_ERR_OOM;
+            c->order_cap = P;
+        }
+        hipLaunchKernelGGL(order_kernel, dim3(1), dim3(ORDER_THREADS), 0, c->stream, work_hint, P, c->d_order);
+        if (hipGetLastError() != hipSuccess) return SMCGW_ERR_HIP;
+    }
     NutsArgs a;
     a.P = P;
     a.D = D;
@@ -640,6 +729,8 @@ extern "C" int smcgw_nuts_step(smcgw_ctx* c, int P, int D, double* theta, double
     a.n_events = (int)c->events.size();
     a.ev_of_p = c->ev_of_p;
     a.queue = (int*)c->d_queue;
+    a.order = work_hint ? c->d_order : nullptr;
+    a.priority = c->nuts_priority;
     const TargetDesc t = c->target;
     switch (kind) {
     case SMCGW_TARGET_GW:

@@ -17,30 +17,58 @@ using namespace smcgw;
 namespace smcgw {
 
 constexpr int SMC_THREADS = 1024;
+constexpr int SMC_WAVES = SMC_THREADS / 64;
+// Bisection levels resolved per pass over the particles: every pass evaluates
+// the ESS at all 2^RW_LEVELS - 1 midpoints the next RW_LEVELS bisection steps
+// could visit (plus one spare candidate), so the walk down that subtree
+// repeats the sequential bisection's decisions exactly.
+constexpr int RW_LEVELS = 4;
+constexpr int RW_CAND = 1 << RW_LEVELS;
+constexpr int RW_THREADS = 512;   // 32 FP64 accumulators per thread need the larger register budget
 
-// Fixed-order workgroup sum of one double per thread (result valid in all threads).
-__device__ __forceinline__ double block_sum(double v, double* sh) {
-    sh[threadIdx.x] = v;
-    __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-        __syncthreads();
-    }
-    const double r = sh[0];
-    __syncthreads();
-    return r;
+// Fixed-order sum over the 64 lanes of a wavefront (butterfly; every lane gets
+// the same bits).
+__device__ __forceinline__ double wave_total(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
 }
 
-__device__ __forceinline__ double block_max(double v, double* sh) {
-    sh[threadIdx.x] = v;
-    __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
-        __syncthreads();
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+
+// Workgroup sums of K values per thread: wavefront butterflies, then the
+// wavefront totals added in wavefront order.  tot[k] is valid in all threads
+// after the call; red must hold K * (blockDim.x / 64) doubles.
+template <int K>
+__device__ __forceinline__ void block_sums(double (&v)[K], double* red, double* tot) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const double t = wave_total(v[k]);
+        if (lane == 0) red[k * nw + wave] = t;
     }
-    const double r = sh[0];
     __syncthreads();
-    return r;
+    if ((int)threadIdx.x < K) {
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += red[threadIdx.x * nw + w];
+        tot[threadIdx.x] = s;
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ double block_max(double v, double* red) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    v = wave_max(v);
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double m = red[0];
+    for (int w = 1; w < nw; ++w) m = fmax(m, red[w]);
+    __syncthreads();
+    return m;
 }
 
 // log-likelihood with NaN mapped to -inf (zero weight)
@@ -49,63 +77,102 @@ __device__ __forceinline__ double ll_at(const double* logl, int i) {
     return v == v ? v : -INFINITY;
 }
 
-// ESS of w_i = exp(db (logL_i - lmax)): (sum w)^2 / sum w^2.
-__device__ double ess_at(const double* logl, int P, double db, double lmax, double* sh) {
-    double s1 = 0.0, s2 = 0.0;
-    for (int i = threadIdx.x; i < P; i += blockDim.x) {
-        const double w = exp(db * (ll_at(logl, i) - lmax));
-        s1 += w;
-        s2 += w * w;
-    }
-    s1 = block_sum(s1, sh);
-    s2 = block_sum(s2, sh);
-    return s1 * s1 / s2;
-}
+// w = L^db / Lmax^db for e = logL - logLmax <= 0; db = 0 gives 1 for every
+// particle (equal weights), also where L = 0.
+__device__ __forceinline__ double incr_weight(double db, double e) { return db == 0.0 ? 1.0 : exp(db * e); }
 
-// One workgroup: beta_next by bisection, evidence increment, normalised
-// weights and their inclusive prefix sum (fixed order).  out[0] = beta_next,
-// out[1] = log(Z_t / Z_{t-1}).  Non-finite logL count as zero weight.
-__global__ __launch_bounds__(SMC_THREADS) void reweight_kernel(const double* __restrict__ logl, int P,
-                                                               double beta_prev, double alpha,
-                                                               double* __restrict__ cum, double* __restrict__ out) {
-    __shared__ double sh[SMC_THREADS];
+// One workgroup: beta_next by bisection on the ESS, the evidence increment,
+// normalised weights and their inclusive prefix sum (fixed order).
+// out[0] = beta_next, out[1] = log(Z_t / Z_{t-1}), out[2] = cum[P-1].
+// Non-finite logL count as zero weight.
+__global__ __launch_bounds__(RW_THREADS) void reweight_kernel(const double* __restrict__ logl, int P,
+                                                              double beta_prev, double alpha,
+                                                              double* __restrict__ cum, double* __restrict__ out) {
+    __shared__ double red[2 * RW_CAND * (RW_THREADS / 64)];
+    __shared__ double tot[2 * RW_CAND];
+    __shared__ double cand[RW_CAND];
+    __shared__ double scan[RW_THREADS / 64 + 1];
     double lm = -INFINITY;
-    for (int i = threadIdx.x; i < P; i += blockDim.x)
-        if (isfinite(logl[i])) lm = fmax(lm, logl[i]);
-    const double lmax = block_max(lm, sh);
+    for (int i = threadIdx.x; i < P; i += blockDim.x) lm = fmax(lm, ll_at(logl, i));
+    const double lmax = block_max(lm, red);
+    if (!(lmax > -INFINITY)) {   // no particle with a finite likelihood: nothing to reweight
+        for (int i = threadIdx.x; i < P; i += blockDim.x) cum[i] = 0.0;
+        if (threadIdx.x == 0) { out[0] = beta_prev; out[1] = -INFINITY; out[2] = 0.0; }
+        return;
+    }
     const double target = alpha * (double)P;
-    double beta;
-    if (ess_at(logl, P, 1.0 - beta_prev, lmax, sh) >= target) {
-        beta = 1.0;
-    } else {
-        double lo = beta_prev, hi = 1.0;
-        for (int it = 0; it < 100 && hi - lo > 1e-14; ++it) {
-            const double mid = 0.5 * (lo + hi);
-            if (ess_at(logl, P, mid - beta_prev, lmax, sh) >= target) lo = mid; else hi = mid;
+    // Candidate 0 of the first pass is beta = 1; candidates 1..15 are the
+    // bisection midpoints in heap order (children of n: 2n below, 2n+1 above).
+    double lo = beta_prev, hi = 1.0, beta = -1.0;
+    int it = 0;
+    for (int pass = 0; beta < 0.0; ++pass) {
+        double a[RW_CAND], b[RW_CAND], mid[RW_CAND];
+        a[1] = lo; b[1] = hi;
+#pragma unroll
+        for (int n = 1; n < RW_CAND; ++n) {
+            mid[n] = 0.5 * (a[n] + b[n]);
+            if (2 * n + 1 < RW_CAND) {
+                a[2 * n] = a[n]; b[2 * n] = mid[n];
+                a[2 * n + 1] = mid[n]; b[2 * n + 1] = b[n];
+            }
         }
-        beta = lo;
+        mid[0] = pass == 0 ? 1.0 : mid[1];
+        if (threadIdx.x < RW_CAND) cand[threadIdx.x] = mid[threadIdx.x];   // read after the sums' barriers
+        double s[2 * RW_CAND];
+#pragma unroll
+        for (int n = 0; n < 2 * RW_CAND; ++n) s[n] = 0.0;
+        for (int i = threadIdx.x; i < P; i += blockDim.x) {
+            const double e = ll_at(logl, i) - lmax;
+#pragma unroll
+            for (int n = 0; n < RW_CAND; ++n) {
+                const double w = incr_weight(mid[n] - beta_prev, e);
+                s[2 * n] += w;
+                s[2 * n + 1] += w * w;
+            }
+        }
+        block_sums<2 * RW_CAND>(s, red, tot);
+        if (pass == 0 && tot[0] * tot[0] / tot[1] >= target) { beta = 1.0; break; }
+        int n = 1;
+        for (int lev = 0; lev < RW_LEVELS; ++lev) {
+            if (!(it < 100 && hi - lo > 1e-14)) { beta = lo; break; }
+            if (tot[2 * n] * tot[2 * n] / tot[2 * n + 1] >= target) { lo = cand[n]; n = 2 * n + 1; }
+            else { hi = cand[n]; n = 2 * n; }
+            ++it;
+        }
     }
     const double db = beta - beta_prev;
     // log-sum-exp of db logL (max of db logL is db lmax for db >= 0)
-    double s = 0.0;
-    for (int i = threadIdx.x; i < P; i += blockDim.x) s += exp(db * (ll_at(logl, i) - lmax));
-    const double tot = block_sum(s, sh);
-    const double lse = db * lmax + log(tot);
-    // prefix sum: thread t owns the contiguous chunk [t*ch, (t+1)*ch)
+    double s1[1] = {0.0};
+    for (int i = threadIdx.x; i < P; i += blockDim.x) s1[0] += incr_weight(db, ll_at(logl, i) - lmax);
+    block_sums<1>(s1, red, tot);
+    const double lse = db * lmax + log(tot[0]);
+    // inclusive prefix sum: thread t owns the contiguous chunk [t*ch, (t+1)*ch)
     const int ch = (P + blockDim.x - 1) / blockDim.x;
-    const int a = threadIdx.x * ch, b = min(P, a + ch);
+    const int lo_i = threadIdx.x * ch, hi_i = min(P, lo_i + ch);
     double loc = 0.0;
-    for (int i = a; i < b; ++i) loc += exp(db * ll_at(logl, i) - lse);
-    sh[threadIdx.x] = loc;
+    const double inv_tot = 1.0 / tot[0];   // normalised weight: exp(db (logL - lmax)) / sum
+    for (int i = lo_i; i < hi_i; ++i) loc += incr_weight(db, ll_at(logl, i) - lmax) * inv_tot;
+    // exclusive scan of the chunk totals: lanes (shuffle ladder), then wavefronts
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double inc = loc;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const double t = __shfl_up(inc, o);
+        if (lane >= o) inc += t;
+    }
+    if (lane == 63) red[wave] = inc;
     __syncthreads();
     if (threadIdx.x == 0) {
         double run = 0.0;
-        for (int t = 0; t < (int)blockDim.x; ++t) { const double v = sh[t]; sh[t] = run; run += v; }
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) { scan[w] = run; run += red[w]; }
+        scan[blockDim.x >> 6] = run;
     }
     __syncthreads();
-    double run = sh[threadIdx.x];
-    for (int i = a; i < b; ++i) {
-        run += exp(db * ll_at(logl, i) - lse);
+    double ex = __shfl_up(inc, 1);
+    if (lane == 0) ex = 0.0;
+    double run = scan[wave] + ex;
+    for (int i = lo_i; i < hi_i; ++i) {
+        run += incr_weight(db, ll_at(logl, i) - lmax) * inv_tot;
         cum[i] = run;
     }
     __syncthreads();
@@ -136,8 +203,9 @@ __global__ __launch_bounds__(256) void ancestors_kernel(const double* __restrict
 
 __global__ __launch_bounds__(256) void gather_kernel(const int32_t* __restrict__ anc, int P, int D,
                                                      const double* __restrict__ x, const double* __restrict__ ll,
-                                                     const double* __restrict__ g, double* __restrict__ xo,
-                                                     double* __restrict__ llo, double* __restrict__ go) {
+                                                     const double* __restrict__ g, const int32_t* __restrict__ cy,
+                                                     double* __restrict__ xo, double* __restrict__ llo,
+                                                     double* __restrict__ go, int32_t* __restrict__ cyo) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= P) return;
     const int a = anc[i];
@@ -145,48 +213,78 @@ __global__ __launch_bounds__(256) void gather_kernel(const int32_t* __restrict__
     llo[i] = ll[a];
     if (g)
         for (int k = 0; k < D; ++k) go[(size_t)i * D + k] = g[(size_t)a * D + k];
+    if (cy) cyo[i] = cy[a];
 }
 
 __global__ __launch_bounds__(256) void copy_back_kernel(int P, int D, const double* __restrict__ xo,
                                                         const double* __restrict__ llo, const double* __restrict__ go,
-                                                        double* __restrict__ x, double* __restrict__ ll,
-                                                        double* __restrict__ g) {
+                                                        const int32_t* __restrict__ cyo, double* __restrict__ x,
+                                                        double* __restrict__ ll, double* __restrict__ g,
+                                                        int32_t* __restrict__ cy) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= P) return;
     for (int k = 0; k < D; ++k) x[(size_t)i * D + k] = xo[(size_t)i * D + k];
     ll[i] = llo[i];
     if (g)
         for (int k = 0; k < D; ++k) g[(size_t)i * D + k] = go[(size_t)i * D + k];
+    if (cy) cy[i] = cyo[i];
 }
 
 // Population mean and covariance (two passes, fixed order), diagonal
 // shrinkage and Cholesky; status[0] = 1 when a diagonal fallback was used.
-__global__ __launch_bounds__(256) void mass_matrix_kernel(const double* __restrict__ x, int P, int D, double shrink,
-                                                          double* __restrict__ inv, double* __restrict__ L,
-                                                          int* __restrict__ status) {
-    __shared__ double sh[256];
+constexpr int MM_CHUNK = 16;   // covariance entries accumulated per pass over the particles
+static_assert(MAXDIM <= MM_CHUNK, "the mean pass reuses the chunk's reduction buffers");
+
+__global__ __launch_bounds__(SMC_THREADS) void mass_matrix_kernel(const double* __restrict__ x, int P, int D,
+                                                                  double shrink, double* __restrict__ inv,
+                                                                  double* __restrict__ L, int* __restrict__ status) {
+    __shared__ double red[MM_CHUNK * SMC_WAVES];
+    __shared__ double tot[MM_CHUNK];
     __shared__ double mu[MAXDIM];
     __shared__ double cov[MAXDIM * MAXDIM];
     __shared__ double l[MAXDIM * MAXDIM];
-    for (int k = 0; k < D; ++k) {
-        double s = 0.0;
-        for (int i = threadIdx.x; i < P; i += blockDim.x) s += x[(size_t)i * D + k];
-        s = block_sum(s, sh);
-        if (threadIdx.x == 0) mu[k] = s / P;
+    {
+        double s[MAXDIM];
+#pragma unroll
+        for (int k = 0; k < MAXDIM; ++k) s[k] = 0.0;
+        for (int i = threadIdx.x; i < P; i += blockDim.x)
+#pragma unroll
+            for (int k = 0; k < MAXDIM; ++k)
+                if (k < D) s[k] += x[(size_t)i * D + k];
+        block_sums<MAXDIM>(s, red, tot);
+        if ((int)threadIdx.x < D) mu[threadIdx.x] = tot[threadIdx.x] / P;
+        __syncthreads();
     }
-    __syncthreads();
-    for (int a = 0; a < D; ++a)
-        for (int b = 0; b <= a; ++b) {
-            double s = 0.0;
-            for (int i = threadIdx.x; i < P; i += blockDim.x)
-                s += (x[(size_t)i * D + a] - mu[a]) * (x[(size_t)i * D + b] - mu[b]);
-            s = block_sum(s, sh);
-            if (threadIdx.x == 0) {
-                const double v = s / (P - 1);
-                cov[a * D + b] = v;
-                cov[b * D + a] = v;
+    // lower triangle (a >= b) in row order, MM_CHUNK entries per pass
+    const int n_ent = D * (D + 1) / 2;
+    for (int e0 = 0; e0 < n_ent; e0 += MM_CHUNK) {
+        int ea[MM_CHUNK], eb[MM_CHUNK];
+        {
+            int a = 0, b = 0;   // entry e0 -> (a, b)
+            while (a * (a + 1) / 2 + a < e0) ++a;
+            b = e0 - a * (a + 1) / 2;
+#pragma unroll
+            for (int j = 0; j < MM_CHUNK; ++j) {
+                ea[j] = a; eb[j] = b;
+                if (++b > a) { ++a; b = 0; }
             }
         }
+        double s[MM_CHUNK];
+#pragma unroll
+        for (int j = 0; j < MM_CHUNK; ++j) s[j] = 0.0;
+        for (int i = threadIdx.x; i < P; i += blockDim.x) {
+            const double* xi = x + (size_t)i * D;
+#pragma unroll
+            for (int j = 0; j < MM_CHUNK; ++j)
+                if (e0 + j < n_ent) s[j] += (xi[ea[j]] - mu[ea[j]]) * (xi[eb[j]] - mu[eb[j]]);
+        }
+        block_sums<MM_CHUNK>(s, red, tot);
+        if ((int)threadIdx.x < MM_CHUNK && e0 + (int)threadIdx.x < n_ent) {
+            const double v = tot[threadIdx.x] / (P - 1);
+            cov[ea[threadIdx.x] * D + eb[threadIdx.x]] = v;
+            cov[eb[threadIdx.x] * D + ea[threadIdx.x]] = v;
+        }
+    }
     __syncthreads();
     if (threadIdx.x != 0) return;
     for (int k = 0; k < D; ++k) cov[k * D + k] *= (1.0 + shrink);
@@ -324,7 +422,7 @@ extern "C" int smcgw_mass_matrix(smcgw_ctx* c, int P, int D, const double* theta
     int* st = (int*)sampler_scratch(c, 64);
     double* hp = pinned(c);
     if (!st || !hp) return SMCGW_ERR_OOM;
-    hipLaunchKernelGGL(mass_matrix_kernel, dim3(1), dim3(256), 0, c->stream, theta, P, D, shrink, inv_mass, chol, st);
+    hipLaunchKernelGGL(mass_matrix_kernel, dim3(1), dim3(SMC_THREADS), 0, c->stream, theta, P, D, shrink, inv_mass, chol, st);
     if (hipGetLastError() != hipSuccess) return SMCGW_ERR_HIP;
     if (hipMemcpyAsync(hp, st, sizeof(int), hipMemcpyDeviceToHost, c->stream) || hipStreamSynchronize(c->stream))
         return SMCGW_ERR_HIP;
@@ -335,7 +433,8 @@ extern "C" int smcgw_mass_matrix(smcgw_ctx* c, int P, int D, const double* theta
 
 extern "C" int smcgw_smc_reweight_resample(smcgw_ctx* c, int P, int D, double beta_prev, double alpha, uint64_t seed,
                                            uint64_t iteration, double* theta, double* logl, double* grad,
-                                           int32_t* ancestors, double* beta_next_host, double* dlogz_host) {
+                                           int32_t* carry, int32_t* ancestors, double* beta_next_host,
+                                           double* dlogz_host) {
     if (!c || P < 1 || D <= 0 || D > MAXDIM || !theta || !logl || !ancestors || !beta_next_host || !dlogz_host)
         return SMCGW_ERR_INVALID;
     if (!(alpha > 0.0 && alpha <= 1.0) || !(beta_prev >= 0.0 && beta_prev <= 1.0)) return SMCGW_ERR_INVALID;
@@ -344,7 +443,8 @@ extern "C" int smcgw_smc_reweight_resample(smcgw_ctx* c, int P, int D, double be
     const size_t off_x = off_cum + (size_t)P * sizeof(double);
     const size_t off_ll = off_x + (size_t)P * D * sizeof(double);
     const size_t off_g = off_ll + (size_t)P * sizeof(double);
-    const size_t bytes = off_g + (size_t)P * D * sizeof(double);
+    const size_t off_cy = off_g + (size_t)P * D * sizeof(double);
+    const size_t bytes = off_cy + (size_t)P * sizeof(int32_t);
     char* s = (char*)sampler_scratch(c, bytes);
     double* hp = pinned(c);
     if (!s || !hp) return SMCGW_ERR_OOM;
@@ -353,11 +453,13 @@ extern "C" int smcgw_smc_reweight_resample(smcgw_ctx* c, int P, int D, double be
     double* xo = (double*)(s + off_x);
     double* llo = (double*)(s + off_ll);
     double* go = (double*)(s + off_g);
-    hipLaunchKernelGGL(reweight_kernel, dim3(1), dim3(SMC_THREADS), 0, c->stream, logl, P, beta_prev, alpha, cum, out);
+    int32_t* cyo = (int32_t*)(s + off_cy);
+    hipLaunchKernelGGL(reweight_kernel, dim3(1), dim3(RW_THREADS), 0, c->stream, logl, P, beta_prev, alpha, cum, out);
     const dim3 g((P + 255) / 256), b(256);
     hipLaunchKernelGGL(ancestors_kernel, g, b, 0, c->stream, cum, out, P, seed, iteration, ancestors);
-    hipLaunchKernelGGL(gather_kernel, g, b, 0, c->stream, ancestors, P, D, theta, logl, grad, xo, llo, go);
-    hipLaunchKernelGGL(copy_back_kernel, g, b, 0, c->stream, P, D, xo, llo, go, theta, logl, grad);
+    hipLaunchKernelGGL(gather_kernel, g, b, 0, c->stream, ancestors, P, D, theta, logl, grad, carry, xo, llo, go,
+                       cyo);
+    hipLaunchKernelGGL(copy_back_kernel, g, b, 0, c->stream, P, D, xo, llo, go, cyo, theta, logl, grad, carry);
     if (hipGetLastError() != hipSuccess) return SMCGW_ERR_HIP;
     if (hipMemcpyAsync(hp, out, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream) ||
         hipStreamSynchronize(c->stream))

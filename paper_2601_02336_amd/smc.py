@@ -31,6 +31,7 @@ class SmcConfig:
     precision: int = smcgw.MIXED
     uturn: bool = True
     record: bool = False          # keep each iteration's population (for replay checks)
+    work_hint: bool = True        # start the particles whose ancestors took the longest trees first
 
 
 @dataclasses.dataclass
@@ -56,16 +57,18 @@ def run_smc(ctx: "smcgw.Context", theta0: torch.Tensor, cfg: SmcConfig) -> SmcRe
     beta, logz = 0.0, 0.0
     betas, dlogzs, nlf, depths, divs = [], [], [], [], []
     pops = [] if cfg.record else None
+    hint = None   # leapfrog counts of the last transition, resampled with the particles
     t0 = time.perf_counter()
     it = 0
     while beta < 1.0 and it < cfg.max_iter:
         if cfg.record:
             pops.append(theta.clone())
-        b, dz, _ = ctx.smc_reweight_resample(theta, logl, grad, beta, cfg.alpha, cfg.seed, it)
+        b, dz, _ = ctx.smc_reweight_resample(theta, logl, grad, beta, cfg.alpha, cfg.seed, it, carry=hint)
         logz += dz
         _, L, _ = ctx.mass_matrix(theta, cfg.shrink)
         out = ctx.nuts_step(theta, logl, grad, L, step=cfg.step, beta=b, seed=cfg.seed, iteration=it,
-                            max_depth=cfg.max_depth, uturn=cfg.uturn, precision=cfg.precision)
+                            max_depth=cfg.max_depth, uturn=cfg.uturn, precision=cfg.precision, work_hint=hint)
+        hint = out["n_leapfrog"] if cfg.work_hint else None
         betas.append(b)
         dlogzs.append(dz)
         nlf.append(int(out["n_leapfrog"].sum().item()))

@@ -23,6 +23,7 @@ ERR_INVALID, ERR_SHAPE, ERR_HIP, ERR_OOM, ERR_NOT_INIT, ERR_STALL = -1, -2, -3, 
 PLAIN_FP64, MIXED = 0, 1
 KERNEL_BINS, KERNEL_PREP, KERNEL_FINISH, KERNEL_NUTS, KERNEL_SMC = 0, 1, 2, 3, 4
 OPT_NUTS_WAVES = 0
+OPT_NUTS_PRIORITY = 1
 
 
 class SmcgwError(RuntimeError):
@@ -77,11 +78,11 @@ def lib():
         L.smcgw_waveform.argtypes = [vp, i, vp, vp]
         L.smcgw_target_loglike_grad.argtypes = [vp, i, vp, vp, vp, i]
         L.smcgw_mass_matrix.argtypes = [vp, i, i, vp, d, vp, vp]
-        L.smcgw_nuts_step.argtypes = [vp, i, i, vp, vp, vp, vp, C.POINTER(NutsParams), vp, i, vp, vp, vp, vp]
+        L.smcgw_nuts_step.argtypes = [vp, i, i, vp, vp, vp, vp, C.POINTER(NutsParams), vp, vp, i, vp, vp, vp, vp]
         L.smcgw_timing_enable.argtypes = [vp, i]
         L.smcgw_set_option.argtypes = [vp, i, C.c_int64]
         L.smcgw_timing_read.argtypes = [vp, i, C.POINTER(d), C.POINTER(C.c_int64)]
-        L.smcgw_smc_reweight_resample.argtypes = [vp, i, i, d, d, u64, u64, vp, vp, vp, vp,
+        L.smcgw_smc_reweight_resample.argtypes = [vp, i, i, d, d, u64, u64, vp, vp, vp, vp, vp,
                                                   C.POINTER(d), C.POINTER(d)]
         _lib = L
     return _lib
@@ -242,7 +243,7 @@ class Context:
     def nuts_step(self, theta: torch.Tensor, logl: torch.Tensor, grad: torch.Tensor, chol: torch.Tensor,
                   step: float, beta: float, seed: int, iteration: int, max_depth: int = 10, uturn: bool = True,
                   max_delta_h: float = 1000.0, max_depth_per_particle: Optional[torch.Tensor] = None,
-                  precision: int = MIXED, diagnostics: bool = True):
+                  precision: int = MIXED, diagnostics: bool = True, work_hint: Optional[torch.Tensor] = None):
         theta = _dev(theta, torch.float64, "theta")
         P, D = theta.shape
         prm = NutsParams(step, beta, max_delta_h, max_depth, 1 if uturn else 0, seed, iteration)
@@ -255,16 +256,18 @@ class Context:
                        accept_stat=torch.zeros(P, dtype=torch.float64, device=dev))
         if max_depth_per_particle is not None:
             _dev(max_depth_per_particle, torch.int32, "max_depth_per_particle")
+        if work_hint is not None:
+            _dev(work_hint, torch.int32, "work_hint")
         self._stream()
         _check("smcgw_nuts_step", lib().smcgw_nuts_step(
             self._h, P, D, _ptr(theta), _ptr(logl), _ptr(grad), _ptr(chol), C.byref(prm),
-            _ptr(max_depth_per_particle), precision, _ptr(out.get("depth")), _ptr(out.get("n_leapfrog")),
+            _ptr(max_depth_per_particle), _ptr(work_hint), precision, _ptr(out.get("depth")), _ptr(out.get("n_leapfrog")),
             _ptr(out.get("divergent")), _ptr(out.get("accept_stat"))))
         return out
 
     def smc_reweight_resample(self, theta: torch.Tensor, logl: torch.Tensor, grad: Optional[torch.Tensor],
                               beta_prev: float, alpha: float, seed: int, iteration: int,
-                              ancestors: Optional[torch.Tensor] = None):
+                              ancestors: Optional[torch.Tensor] = None, carry: Optional[torch.Tensor] = None):
         theta = _dev(theta, torch.float64, "theta")
         P, D = theta.shape
         if ancestors is None:
@@ -272,8 +275,11 @@ class Context:
         b = C.c_double()
         dz = C.c_double()
         self._stream()
+        if carry is not None:
+            _dev(carry, torch.int32, "carry")
         rc = lib().smcgw_smc_reweight_resample(self._h, P, D, beta_prev, alpha, seed, iteration, _ptr(theta),
-                                               _ptr(logl), _ptr(grad), _ptr(ancestors), C.byref(b), C.byref(dz))
+                                               _ptr(logl), _ptr(grad), _ptr(carry), _ptr(ancestors), C.byref(b),
+                                               C.byref(dz))
         _check("smcgw_smc_reweight_resample", rc)
         return b.value, dz.value, ancestors
 

@@ -180,3 +180,40 @@ def test_gw_three_detector_parity(smc):
     ok = _agree(got, ref, 1e-6)
     print(f"gw 3-det plain: agree {ok.mean():.3f}, depths {np.bincount(ref['depth'])}", flush=True)
     assert ok.mean() >= 11 / 12
+
+
+def test_schedule_does_not_change_results(smc):
+    """Start order (work hint) and depth-driven wavefront priority only reorder work: every output is
+    bitwise the same.  1500 particles with ragged hints also exercise the order kernel's chunking."""
+    ev = event(synth.SPEC_8S)
+    idx = list(range(11))
+    full = synth.gw_prior_for(ev)
+    b = [full[i] for i in idx]
+    rng = np.random.default_rng(3)
+    P = 1500
+    x = synth.prior_draw(rng, P, b)
+    _, _, L = O.mass_matrix(synth.prior_draw(rng, 4000, b), 0.0)
+    c = smc.Context(0)
+    c.add_event(ev)
+    c.set_param_map(idx, ev.theta_inj)
+    c.set_prior(b)
+    c.set_target(synth.TARGET_GW, 11)
+    xt = torch.tensor(x, device="cuda")
+    ll, g = c.target_loglike_grad(xt, precision=smc.MIXED)
+    Lt = torch.tensor(L * 0.05, device="cuda")
+    hint = torch.tensor(rng.integers(-3, 3000, size=P), dtype=torch.int32, device="cuda")
+    runs = []
+    for prio, h in ((0, None), (1, None), (1, hint), (0, hint)):
+        c.set_option(smc.OPT_NUTS_PRIORITY, prio)
+        xs, ls, gs = xt.clone(), ll.clone(), g.clone()
+        o = c.nuts_step(xs, ls, gs, Lt, step=0.25, beta=0.05, seed=5, iteration=2, max_depth=6,
+                        precision=smc.MIXED, work_hint=h)
+        torch.cuda.synchronize()
+        runs.append([xs.cpu().numpy(), ls.cpu().numpy(), gs.cpu().numpy()] +
+                    [o[k].cpu().numpy() for k in ("depth", "n_leapfrog", "divergent", "accept_stat")])
+    c.close()
+    print(f"depths {np.bincount(runs[0][3])}", flush=True)
+    assert runs[0][4].min() >= 1
+    for r in runs[1:]:
+        for a, b_ in zip(r, runs[0]):
+            np.testing.assert_array_equal(a, b_)

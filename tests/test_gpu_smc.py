@@ -77,3 +77,55 @@ def test_mass_matrix_matches_oracle(ctx):
     # degenerate population -> diagonal fallback, flagged
     inv, L, rc = ctx.mass_matrix(torch.ones((64, 3), dtype=torch.float64, device="cuda"), 0.0)
     assert rc == 1 and torch.all(torch.isfinite(L))
+
+
+def test_resample_carries_payload(ctx):
+    """The int32 payload travels with the particles: carry_after[i] = carry_before[ancestor_i]."""
+    P, D = 3000, 5
+    rng = np.random.default_rng(4)
+    logl = rng.normal(size=P) * 20
+    x = torch.tensor(rng.normal(size=(P, D)), device="cuda")
+    lt = torch.tensor(logl, device="cuda")
+    cy0 = rng.integers(0, 1 << 30, size=P).astype(np.int32)
+    cy = torch.tensor(cy0, device="cuda")
+    b, dz, anc = ctx.smc_reweight_resample(x, lt, None, 0.0, 0.7, 9, 1, carry=cy)
+    a = anc.cpu().numpy()
+    assert a.min() >= 0 and a.max() < P
+    np.testing.assert_array_equal(cy.cpu().numpy(), cy0[a])
+    np.testing.assert_array_equal(lt.cpu().numpy(), logl[a])
+
+
+def test_reweight_at_beta_one_keeps_equal_weights(ctx):
+    """beta_prev = 1: the increment L^0 is 1 for every particle (also L = 0), so log Z does not move and
+    the resampling is uniform."""
+    P = 4096
+    rng = np.random.default_rng(6)
+    logl = rng.normal(size=P) * 5
+    logl[::5] = -np.inf
+    x = torch.tensor(rng.normal(size=(P, 2)), device="cuda")
+    b, dz, anc = ctx.smc_reweight_resample(x, torch.tensor(logl, device="cuda"), None, 1.0, 0.95, 3, 2)
+    a = anc.cpu().numpy()
+    assert b == 1.0 and dz == 0.0
+    assert a.min() >= 0 and a.max() < P
+    # uniform multinomial: the dead fifth is drawn about a fifth of the time
+    assert abs(np.mean(a % 5 == 0) - 0.2) < 0.03
+
+
+def test_reweight_single_particle(ctx):
+    x = torch.zeros((1, 3), dtype=torch.float64, device="cuda")
+    ll = torch.tensor([-12.5], dtype=torch.float64, device="cuda")
+    b, dz, anc = ctx.smc_reweight_resample(x, ll, None, 0.2, 0.9, 1, 0)
+    assert b == 1.0 and abs(dz - 0.8 * -12.5) < 1e-13 and int(anc[0]) == 0
+
+
+@pytest.mark.parametrize("P,D", [(2, 1), (5000, 16), (777, 7)])
+def test_mass_matrix_edge_shapes(ctx, P, D):
+    """Smallest population, the largest dimension and a ragged triangle (28 entries) of the covariance."""
+    rng = np.random.default_rng(P + D)
+    A = rng.normal(size=(D, D)) + 3 * np.eye(D)
+    x = rng.normal(size=(P, D)) @ A.T
+    rc_ref, inv_ref, L_ref = O.mass_matrix(x, 0.01)
+    inv, L, rc = ctx.mass_matrix(torch.tensor(x, device="cuda"), 0.01)
+    assert rc == rc_ref
+    np.testing.assert_allclose(inv.cpu().numpy(), inv_ref, rtol=1e-10, atol=1e-12 * np.abs(inv_ref).max())
+    np.testing.assert_allclose(L.cpu().numpy(), L_ref, rtol=1e-9, atol=1e-12 * np.abs(L_ref).max())
