@@ -47,7 +47,7 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def build_event(smcgw, synth):
+def build_event(smcgw, synth, spec=None):
     """Seeded injection built with the HIP library itself (waveform + <h|h>)."""
 
     def zero_ll(ev, th):
@@ -67,7 +67,7 @@ def build_event(smcgw, synth):
         c.close()
         return h[..., 0] + 1j * h[..., 1]
 
-    return synth.make_event(synth.SPEC_8S, wf, zero_ll)
+    return synth.make_event(spec or synth.SPEC_8S, wf, zero_ll)
 
 
 def cpu_baseline(ev, synth, x_all, budget_s=12.0):
@@ -86,6 +86,69 @@ def cpu_baseline(ev, synth, x_all, budget_s=12.0):
     return {"value": done / elapsed, "unit": "evals/s", "cores": threads, "kind": "oracle",
             "sample": f"{done} particles of the same 3-detector 8033-bin event, logL + 11-component gradient "
                       f"(forward-mode dual numbers, FP64), {elapsed:.1f} s on {threads} threads"}
+
+
+def run_batch(smcgw, synth, args):
+    """Eight events (two each of 4, 8, 16, 32 s; 4017-64897 bins) and 16384 particles in one persistent
+    NUTS launch per step, forced depths d ~ U{1..10} with the U-turn check off (exact work per step)."""
+    import torch
+    specs = synth.ragged_specs()
+    evs = [build_event(smcgw, synth, s) for s in specs]
+    P = args.particles or 16384
+    rng = np.random.default_rng(1002)
+    dls = [float(e.theta_inj[4]) for e in evs]
+    bounds = synth.gw_bounds(min(dls) / 5, max(dls) * 5)
+    ctx = smcgw.Context(0)
+    for e in evs:
+        ctx.add_event(e)
+    ctx.set_prior(bounds)
+    ctx.set_target(synth.TARGET_GW, 11)
+    ctx.set_option(smcgw.OPT_NUTS_PRIORITY, args.priority)
+    ctx.set_option(smcgw.OPT_NUTS_WAVES, args.waves)
+    eop_np = (np.arange(P) % len(evs)).astype(np.int32)
+    eop = torch.tensor(eop_np, device="cuda")
+    ctx.set_event_map(eop)
+    md = torch.tensor(rng.integers(1, 11, size=P).astype(np.int32), device="cuda")
+    x = torch.tensor(synth.prior_draw(rng, P, bounds), device="cuda")
+    prec = smcgw.MIXED if args.precision == "mixed" else smcgw.PLAIN_FP64
+    logl, grad = ctx.target_loglike_grad(x, precision=prec)
+    _, L, _ = ctx.mass_matrix(torch.tensor(synth.prior_draw(rng, 4096, bounds), device="cuda"), 0.0)
+    L = (L * 0.05).contiguous()
+    bins = torch.tensor([e.n for e in evs], dtype=torch.int64, device="cuda")[eop.long()]
+
+    def step(i, uturn):
+        return ctx.nuts_step(x, logl, grad, L, step=0.2, beta=0.005, seed=3, iteration=i, max_depth=10,
+                             max_depth_per_particle=None if uturn else md, uturn=uturn, precision=prec)
+
+    div = 0
+    for i in range(args.warmup):
+        out = step(i, False)
+        (out["n_leapfrog"].long() * bins).sum()
+        div += int(out["divergent"].sum().item())
+    torch.cuda.synchronize()
+    ctx.timing_read(smcgw.KERNEL_NUTS)
+    ctx.timing(smcgw.KERNEL_NUTS)
+    evals = torch.zeros((), dtype=torch.int64, device="cuda")
+    bin_evals = torch.zeros((), dtype=torch.int64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        out = step(args.warmup + i, False)
+        evals += out["n_leapfrog"].sum()
+        bin_evals += (out["n_leapfrog"].long() * bins).sum()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.timing()
+    k_ms, k_n = ctx.timing_read(smcgw.KERNEL_NUTS)
+    n_ev, n_be = int(evals.item()), int(bin_evals.item())
+    # natural U-turn transitions from the same state, for context
+    t1 = time.perf_counter()
+    nat = 0
+    for i in range(2):
+        nat += int(step(1000 + i, True)["n_leapfrog"].sum().item())
+    dt_nat = time.perf_counter() - t1
+    return dict(P=P, evals=n_ev, bin_evals=n_be, dt=dt, k_ms=k_ms, k_n=k_n, nat_rate=nat / dt_nat,
+                bins=[e.n for e in evs], divergent_warmup=div)
 
 
 def smc_setup(smcgw, synth, ev, P, seed=7):
@@ -145,7 +208,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=8)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--mode", choices=["smc", "loglike"], default="smc",
+    ap.add_argument("--mode", choices=["smc", "loglike", "batch"], default="smc",
                     help="smc: one SMC-NUTS iteration per step; loglike: one batched logL+grad per step")
     ap.add_argument("--particles", type=int, default=None)
     ap.add_argument("--precision", choices=["mixed", "plain"], default="mixed")
@@ -208,6 +271,29 @@ def main():
                                                args, args.warmup, max(2, args.steps // 2), False)
             extra["other_precision_in_sampler_evals_per_s"] = round(e2 / d2, 1)
             ctx2.close()
+    elif args.mode == "batch":
+        r = run_batch(smcgw, synth, args)
+        P = r["P"]
+        value = r["evals"] / r["dt"]
+        kernel_s = r["k_ms"] / 1e3
+        achieved = ops * r["bin_evals"] / kernel_s / 1e12
+        log(f"batch {args.precision}: {r['evals']} evals ({r['bin_evals']} particle-bins) in {r['dt']:.3f} s -> "
+            f"{value:.4g} evals/s; nuts kernel {r['k_ms'] / max(r['k_n'], 1):.2f} ms x {r['k_n']}")
+        roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TLANEOPS, 3),
+                    "unit": "Tlane-op/s", "frac": round(achieved / VALU_PEAK_TLANEOPS, 4), "traffic": None,
+                    "kernel": f"nuts_kernel<3,{'MIXED' if prec == smcgw.MIXED else 'PLAIN_FP64'},GW,{args.waves or 4}>",
+                    "kernel_ms": round(r["k_ms"] / max(r["k_n"], 1), 3), "ops_per_particle_bin": ops,
+                    "evals_in_kernel": r["evals"]}
+        extra["particle_bins_per_s"] = round(r["bin_evals"] / r["dt"], 1)
+        extra["natural_uturn_evals_per_s"] = round(r["nat_rate"], 1)
+        extra["event_bins"] = r["bins"]
+        extra["divergent_in_warmup_step"] = r["divergent_warmup"]
+        ms_step = 1e3 * r["dt"] / args.steps
+        workload = (f"persistent NUTS batch: 8 three-detector events (two each of 4, 8, 16, 32 s; "
+                    f"{min(r['bins'])}-{max(r['bins'])} bins) in one launch, 11 params, {P} particles, forced tree "
+                    f"depths d ~ U{{1..10}} with the U-turn check off (2^d - 1 leapfrog steps each)")
+        ctx = None
+        x_np = synth.prior_draw(np.random.default_rng(7), 64, synth.gw_prior_for(ev))
     else:
         P = args.particles or 4096
         ctx = smcgw.Context(0)
@@ -284,11 +370,13 @@ def main():
            "scaling": "weak", "vs_baseline": None,
            "dtype": "f64+f32" if prec == smcgw.MIXED else "f64",
            "data": "synthetic",
-           "config": {"workload": workload, "particles": P, "bins": ev.n, "detectors": ev.n_det, "params": 11,
+           "config": {"workload": workload, "particles": P,
+                      "bins": extra.get("event_bins", ev.n), "detectors": ev.n_det, "params": 11,
                       "precision": args.precision, "mode": args.mode},
            "roofline": roofline, "cpu_baseline": cpu, "extra": extra}
     print(json.dumps(out), flush=True)
-    ctx.close()
+    if ctx is not None:
+        ctx.close()
 
 
 if __name__ == "__main__":
