@@ -55,79 +55,92 @@ __device__ __forceinline__ BinCoef load_coef(const double* cb) {
     return k;
 }
 
-// Chunk cursor of a wavefront: 64-bin chunks of the blocks blk0, blk0 + step, ...
-struct ChunkCursor {
-    int blk, s;   // block and chunk within the block (0 .. BIN_KB-1)
-    __device__ __forceinline__ int bin(int lane) const { return blk * TABLE_PAD + 64 * s + lane; }
-    __device__ __forceinline__ bool advance(int blk_step, int nblk) {
-        if (++s == BIN_KB) { s = 0; blk += blk_step; }
-        return blk < nblk;
-    }
+// Table pointers in the global address space (plain global loads, not flat).
+typedef const __attribute__((address_space(1))) double GDouble;
+typedef const __attribute__((address_space(1))) unsigned long long GU64;
+
+// Per-lane inputs of one bin: f, f^-1/3, ln f and the detectors' whitened data.
+template <int NDET, class U>
+struct BinIn {
+    double f, w, l;
+    U u[NDET];
 };
+
+__device__ __forceinline__ void load_u(float2& v, GU64* u, size_t i) { v = __builtin_bit_cast(float2, u[i]); }
+__device__ __forceinline__ void load_u(double2& v, GU64* u, size_t i) {
+    v.x = __builtin_bit_cast(double, u[2 * i]);
+    v.y = __builtin_bit_cast(double, u[2 * i + 1]);
+}
+
+template <int NDET, class U>
+__device__ __forceinline__ void load_bin(BinIn<NDET, U>& x, GDouble* fwl, GU64* u, int npad, int j) {
+    x.f = fwl[(size_t)ROW_F * npad + j];
+    x.w = fwl[(size_t)ROW_W * npad + j];
+    x.l = fwl[(size_t)ROW_LN * npad + j];
+#pragma unroll
+    for (int d = 0; d < NDET; ++d) load_u(x.u[d], u, (size_t)d * npad + j);
+}
+
+// A wavefront visits the blocks blk0, blk0 + blk_step, ... of the padded
+// table; each block is BIN_KB chunks of 64 bins (one bin per lane of a
+// chunk).  The chunks run through two register buffers in turn (U chunks
+// each): while one buffer is computed the other one's table entries are in
+// flight, with no register copies between them.  U = 2 gives each lane two
+// independent bins per step (more instruction-level parallelism, more
+// registers).  Partial sums are accumulated in chunk order, so the result does
+// not depend on U.
+template <int U, class In, class Acc>
+__device__ __forceinline__ void bin_loop(Acc& A, const BinCoef& k, GDouble* fwl, GU64* u, int npad, int blk0,
+                                         int blk_step, int nblk) {
+    static_assert(BIN_KB % (2 * U) == 0, "a block holds a whole number of buffer pairs");
+    const int lane = threadIdx.x & 63;
+    const int nc = blk0 < nblk ? ((nblk - blk0 + blk_step - 1) / blk_step) * BIN_KB : 0;   // this wave's chunks
+    auto bin_of = [&](int c) { return (blk0 + (c / BIN_KB) * blk_step) * TABLE_PAD + 64 * (c % BIN_KB) + lane; };
+    In a[U], b[U];
+    if (nc > 0) {
+#pragma unroll
+        for (int h = 0; h < U; ++h) load_bin(a[h], fwl, u, npad, bin_of(h));
+    }
+    for (int c = 0; c < nc; c += 2 * U) {
+#pragma unroll
+        for (int h = 0; h < U; ++h) load_bin(b[h], fwl, u, npad, bin_of(c + U + h));
+#pragma unroll
+        for (int h = 0; h < U; ++h) A.bin(k, a[h]);
+        if ((c + U) % BIN_KB == 0) A.flush();
+        if (c + 2 * U < nc) {
+#pragma unroll
+            for (int h = 0; h < U; ++h) load_bin(a[h], fwl, u, npad, bin_of(c + 2 * U + h));
+        }
+#pragma unroll
+        for (int h = 0; h < U; ++h) A.bin(k, b[h]);
+        if ((c + 2 * U) % BIN_KB == 0) A.flush();
+    }
+}
 
 // MIXED: FP64 phase and argument reduction, FP32 sin/cos, complex products and
 // per-lane partial sums (flushed into FP64 once per block), FP64 basis moments.
-// The table entries of the next chunk are loaded while the current one is
-// computed.
 template <int NDET>
-__device__ __forceinline__ void bins_mixed_wave(const DevEvent* __restrict__ ev, const BinCoef& k, int blk0,
-                                                int blk_step, double mom[MOM_SIZE]) {
-    const int lane = threadIdx.x & 63;
-    const int npad = ev->n_pad;
-    const int nblk = npad / TABLE_PAD;
-    const double* __restrict__ fwl = ev->fwl;
-    const float2* __restrict__ u = ev->u32;
+struct MixedAcc {
     float pr[NDET], pim[NDET];
-#pragma unroll
-    for (int d = 0; d < NDET; ++d) { pr[d] = (float)k.pr[d]; pim[d] = (float)k.pi[d]; }
     double Zr[NDET], Zi[NDET], T[NDET], G[NCOEF];
     float zr[NDET], zi[NDET], tq[NDET];
-#pragma unroll
-    for (int d = 0; d < NDET; ++d) { Zr[d] = 0.0; Zi[d] = 0.0; T[d] = 0.0; zr[d] = 0.f; zi[d] = 0.f; tq[d] = 0.f; }
-#pragma unroll
-    for (int b = 0; b < NCOEF; ++b) G[b] = 0.0;
-    ChunkCursor cur{blk0, 0};
-    bool more = blk0 < nblk;
-    double nf = 0.0, nw = 0.0, nl = 0.0;
-    float2 nu[NDET];
-    if (more) {
-        const int j = cur.bin(lane);
-        nf = fwl[(size_t)ROW_F * npad + j];
-        nw = fwl[(size_t)ROW_W * npad + j];
-        nl = fwl[(size_t)ROW_LN * npad + j];
-#pragma unroll
-        for (int d = 0; d < NDET; ++d) nu[d] = u[(size_t)d * npad + j];
-    }
-    while (more) {
-        const double f = nf, w = nw, lnf = nl;
-        float2 uu[NDET];
-#pragma unroll
-        for (int d = 0; d < NDET; ++d) uu[d] = nu[d];
-        const bool flush = (cur.s == BIN_KB - 1);
-        more = cur.advance(blk_step, nblk);
-        if (more) {
-            const int j = cur.bin(lane);
-            nf = fwl[(size_t)ROW_F * npad + j];
-            nw = fwl[(size_t)ROW_W * npad + j];
-            nl = fwl[(size_t)ROW_LN * npad + j];
-#pragma unroll
-            for (int d = 0; d < NDET; ++d) nu[d] = u[(size_t)d * npad + j];
-        }
+
+    __device__ __forceinline__ void bin(const BinCoef& k, const BinIn<NDET, float2>& x) {
         double B[NBASIS];
-        basis_rows(f, w, lnf, B);
+        basis_rows(x.f, x.w, x.l, B);
         double ph = k.c[0];
 #pragma unroll
         for (int b = 0; b < NBASIS; ++b) ph = fma(k.c[1 + b], B[b], ph);
-        const float ff = (float)f;
+        const float ff = (float)x.f;
         float psib;
 #pragma unroll
         for (int d = 0; d < NDET; ++d) {
-            const double phd = fma(f, k.tau[d], ph);
-            const float x = (float)(phd - rint(phd));
+            const double phd = fma(x.f, k.tau[d], ph);
+            const float xr = (float)(phd - rint(phd));
             float sn, cs;
-            sincos_rev_hw(x, sn, cs);
-            const float sr = fmaf(uu[d].x, cs, uu[d].y * sn);    // u e^{-2 pi i x}
-            const float si = fmaf(uu[d].y, cs, -uu[d].x * sn);
+            sincos_rev_hw(xr, sn, cs);
+            const float sr = fmaf(x.u[d].x, cs, x.u[d].y * sn);    // u e^{-2 pi i x}
+            const float si = fmaf(x.u[d].y, cs, -x.u[d].x * sn);
             zr[d] += sr;
             zi[d] += si;
             const float q = fmaf(pr[d], si, pim[d] * sr);
@@ -138,100 +151,98 @@ __device__ __forceinline__ void bins_mixed_wave(const DevEvent* __restrict__ ev,
         G[0] += pb;
 #pragma unroll
         for (int b = 0; b < NBASIS; ++b) G[1 + b] = fma(pb, B[b], G[1 + b]);
-        if (flush) {
+    }
+
+    __device__ __forceinline__ void flush() {
 #pragma unroll
-            for (int d = 0; d < NDET; ++d) {
-                Zr[d] += zr[d]; Zi[d] += zi[d]; T[d] += tq[d];
-                zr[d] = 0.f; zi[d] = 0.f; tq[d] = 0.f;
-            }
+        for (int d = 0; d < NDET; ++d) {
+            Zr[d] += zr[d]; Zi[d] += zi[d]; T[d] += tq[d];
+            zr[d] = 0.f; zi[d] = 0.f; tq[d] = 0.f;
         }
     }
+};
+
+template <int NDET, int U = 1>
+__device__ __forceinline__ void bins_mixed_wave(const DevEvent* __restrict__ ev, const BinCoef& k, int blk0,
+                                                int blk_step, double mom[MOM_SIZE]) {
+    const int npad = ev->n_pad;
+    MixedAcc<NDET> A;
+#pragma unroll
+    for (int d = 0; d < NDET; ++d) {
+        A.pr[d] = (float)k.pr[d]; A.pim[d] = (float)k.pi[d];
+        A.Zr[d] = 0.0; A.Zi[d] = 0.0; A.T[d] = 0.0; A.zr[d] = 0.f; A.zi[d] = 0.f; A.tq[d] = 0.f;
+    }
+#pragma unroll
+    for (int b = 0; b < NCOEF; ++b) A.G[b] = 0.0;
+    bin_loop<U, BinIn<NDET, float2>>(A, k, (GDouble*)ev->fwl, (GU64*)ev->u32, npad, blk0, blk_step,
+                                     npad / TABLE_PAD);
 #pragma unroll
     for (int i = 0; i < MOM_SIZE; ++i) mom[i] = 0.0;
 #pragma unroll
     for (int d = 0; d < NDET; ++d) {
-        mom[MOM_ZR + d] = wave_sum(Zr[d] + zr[d]);
-        mom[MOM_ZI + d] = wave_sum(Zi[d] + zi[d]);
-        mom[MOM_T + d] = wave_sum(T[d] + tq[d]);
+        mom[MOM_ZR + d] = wave_sum(A.Zr[d] + A.zr[d]);
+        mom[MOM_ZI + d] = wave_sum(A.Zi[d] + A.zi[d]);
+        mom[MOM_T + d] = wave_sum(A.T[d] + A.tq[d]);
     }
 #pragma unroll
-    for (int b = 0; b < NCOEF; ++b) mom[MOM_G + b] = wave_sum(G[b]);
+    for (int b = 0; b < NCOEF; ++b) mom[MOM_G + b] = wave_sum(A.G[b]);
 }
 
 // PLAIN_FP64: the same algebra in FP64 throughout.
 template <int NDET>
-__device__ __forceinline__ void bins_fp64_wave(const DevEvent* __restrict__ ev, const BinCoef& k, int blk0,
-                                               int blk_step, double mom[MOM_SIZE]) {
-    const int lane = threadIdx.x & 63;
-    const int npad = ev->n_pad;
-    const int nblk = npad / TABLE_PAD;
-    const double* __restrict__ fwl = ev->fwl;
-    const double2* __restrict__ u = ev->u64;
+struct Fp64Acc {
     double Zr[NDET], Zi[NDET], T[NDET], G[NCOEF];
-#pragma unroll
-    for (int d = 0; d < NDET; ++d) { Zr[d] = 0.0; Zi[d] = 0.0; T[d] = 0.0; }
-#pragma unroll
-    for (int b = 0; b < NCOEF; ++b) G[b] = 0.0;
-    ChunkCursor cur{blk0, 0};
-    bool more = blk0 < nblk;
-    double nf = 0.0, nw = 0.0, nl = 0.0;
-    double2 nu[NDET];
-    if (more) {
-        const int j = cur.bin(lane);
-        nf = fwl[(size_t)ROW_F * npad + j];
-        nw = fwl[(size_t)ROW_W * npad + j];
-        nl = fwl[(size_t)ROW_LN * npad + j];
-#pragma unroll
-        for (int d = 0; d < NDET; ++d) nu[d] = u[(size_t)d * npad + j];
-    }
-    while (more) {
-        const double f = nf, w = nw, lnf = nl;
-        double2 uu[NDET];
-#pragma unroll
-        for (int d = 0; d < NDET; ++d) uu[d] = nu[d];
-        more = cur.advance(blk_step, nblk);
-        if (more) {
-            const int j = cur.bin(lane);
-            nf = fwl[(size_t)ROW_F * npad + j];
-            nw = fwl[(size_t)ROW_W * npad + j];
-            nl = fwl[(size_t)ROW_LN * npad + j];
-#pragma unroll
-            for (int d = 0; d < NDET; ++d) nu[d] = u[(size_t)d * npad + j];
-        }
+
+    __device__ __forceinline__ void bin(const BinCoef& k, const BinIn<NDET, double2>& x) {
         double B[NBASIS];
-        basis_rows(f, w, lnf, B);
+        basis_rows(x.f, x.w, x.l, B);
         double ph = k.c[0];
 #pragma unroll
         for (int b = 0; b < NBASIS; ++b) ph = fma(k.c[1 + b], B[b], ph);
         double psib;
 #pragma unroll
         for (int d = 0; d < NDET; ++d) {
-            const double phd = fma(f, k.tau[d], ph);
-            const double x = phd - rint(phd);
+            const double phd = fma(x.f, k.tau[d], ph);
+            const double xr = phd - rint(phd);
             double sn, cs;
-            sincospi(2.0 * x, &sn, &cs);
-            const double sr = fma(uu[d].x, cs, uu[d].y * sn);
-            const double si = fma(uu[d].y, cs, -uu[d].x * sn);
+            sincospi(2.0 * xr, &sn, &cs);
+            const double sr = fma(x.u[d].x, cs, x.u[d].y * sn);
+            const double si = fma(x.u[d].y, cs, -x.u[d].x * sn);
             Zr[d] += sr;
             Zi[d] += si;
             const double q = fma(k.pr[d], si, k.pi[d] * sr);
             psib = (d == 0) ? q : psib + q;
-            T[d] = fma(q, f, T[d]);
+            T[d] = fma(q, x.f, T[d]);
         }
         G[0] += psib;
 #pragma unroll
         for (int b = 0; b < NBASIS; ++b) G[1 + b] = fma(psib, B[b], G[1 + b]);
     }
+
+    __device__ __forceinline__ void flush() {}
+};
+
+template <int NDET, int U = 1>
+__device__ __forceinline__ void bins_fp64_wave(const DevEvent* __restrict__ ev, const BinCoef& k, int blk0,
+                                               int blk_step, double mom[MOM_SIZE]) {
+    const int npad = ev->n_pad;
+    Fp64Acc<NDET> A;
+#pragma unroll
+    for (int d = 0; d < NDET; ++d) { A.Zr[d] = 0.0; A.Zi[d] = 0.0; A.T[d] = 0.0; }
+#pragma unroll
+    for (int b = 0; b < NCOEF; ++b) A.G[b] = 0.0;
+    bin_loop<U, BinIn<NDET, double2>>(A, k, (GDouble*)ev->fwl, (GU64*)ev->u64, npad, blk0, blk_step,
+                                      npad / TABLE_PAD);
 #pragma unroll
     for (int i = 0; i < MOM_SIZE; ++i) mom[i] = 0.0;
 #pragma unroll
     for (int d = 0; d < NDET; ++d) {
-        mom[MOM_ZR + d] = wave_sum(Zr[d]);
-        mom[MOM_ZI + d] = wave_sum(Zi[d]);
-        mom[MOM_T + d] = wave_sum(T[d]);
+        mom[MOM_ZR + d] = wave_sum(A.Zr[d]);
+        mom[MOM_ZI + d] = wave_sum(A.Zi[d]);
+        mom[MOM_T + d] = wave_sum(A.T[d]);
     }
 #pragma unroll
-    for (int b = 0; b < NCOEF; ++b) mom[MOM_G + b] = wave_sum(G[b]);
+    for (int b = 0; b < NCOEF; ++b) mom[MOM_G + b] = wave_sum(A.G[b]);
 }
 
 template <int NDET>

@@ -52,6 +52,10 @@ struct NutsArgs {
 };
 
 constexpr int MAX_WAVES = 8;
+// Bins per lane per step of the leaf's bin loop, and the wavefronts per SIMD
+// the register budget is sized for (4: 128 VGPRs, 3: 168, 2: 256).
+constexpr int NUTS_UNROLL = 1;
+constexpr int NUTS_WAVES_PER_SIMD = 3;
 constexpr int MAXD1 = SMCGW_MAX_DEPTH + 1;
 
 struct NutsShared {
@@ -474,7 +478,7 @@ __device__ __noinline__ void leaf_finish(const DevEvent* ev, NutsShared& S, Nuts
 }
 
 template <int NDET, int PREC, int TK, int WAVES>
-__global__ __launch_bounds__(WAVES * 64, (WAVES == 1 ? 2 : 4)) void nuts_kernel(NutsArgs a, PriorDesc pri, ParamMap pm,
+__global__ __launch_bounds__(WAVES * 64, (WAVES == 1 ? 2 : NUTS_WAVES_PER_SIMD)) void nuts_kernel(NutsArgs a, PriorDesc pri, ParamMap pm,
                                                                              TargetDesc tgt) {
     __shared__ NutsShared S;
     __shared__ NutsState T;
@@ -541,9 +545,9 @@ __global__ __launch_bounds__(WAVES * 64, (WAVES == 1 ? 2 : 4)) void nuts_kernel(
                     const BinCoef k = load_coef(S.cb);
                     double m[MOM_SIZE];
                     if (PREC == SMCGW_MIXED)
-                        bins_mixed_wave<NDET>(ev, k, wave, WAVES, m);
+                        bins_mixed_wave<NDET, NUTS_UNROLL>(ev, k, wave, WAVES, m);
                     else
-                        bins_fp64_wave<NDET>(ev, k, wave, WAVES, m);
+                        bins_fp64_wave<NDET, NUTS_UNROLL>(ev, k, wave, WAVES, m);
                     if (lane == 0)
                         for (int i = 0; i < MOM_SIZE; ++i) S.mom[wave][i] = m[i];
                 }
