@@ -75,9 +75,11 @@ struct NutsShared {
     int pbnd[MAXDIM], pkind[MAXDIM];
     int pidx[MAXDIM];                            // sampled coordinate -> source parameter
     double pfixed[NPAR];
+    DevEvent ev;                                 // event of the current particle
     int p;
     int cmd;
 };
+static_assert(sizeof(DevEvent) % 8 == 0, "the event descriptor is copied in 8-byte words");
 
 enum { ST_START = 0, ST_SUBTREE = 1, ST_DONE = 2 };
 enum { CMD_EVAL = 0, CMD_DONE = 1 };
@@ -482,6 +484,7 @@ __global__ __launch_bounds__(WAVES * 64, (WAVES == 1 ? 2 : NUTS_WAVES_PER_SIMD))
                                                                              TargetDesc tgt) {
     __shared__ NutsShared S;
     __shared__ NutsState T;
+    __shared__ NutsArgs A;   // the arguments as the out-of-line tree steps read them (LDS, not a stack copy)
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -492,6 +495,7 @@ __global__ __launch_bounds__(WAVES * 64, (WAVES == 1 ? 2 : NUTS_WAVES_PER_SIMD))
         S.L[i] = (r < D && c < D) ? a.chol[r * D + c] : 0.0;
     }
     if (tid == 0) {
+        A = a;
         for (int k = 0; k < MAXDIM; ++k) {
             S.plo[k] = pri.lo[k]; S.phi[k] = pri.hi[k]; S.pbnd[k] = pri.bnd[k]; S.pkind[k] = pri.kind[k];
             S.pidx[k] = pm.idx[k];
@@ -513,6 +517,7 @@ __global__ __launch_bounds__(WAVES * 64, (WAVES == 1 ? 2 : NUTS_WAVES_PER_SIMD))
     }
     __syncthreads();
 
+    int ev_cached = -1;   // event whose descriptor S.ev holds
     for (;;) {
         if (tid == 0) {
             const int q = __hip_atomic_fetch_add(a.queue, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -521,14 +526,24 @@ __global__ __launch_bounds__(WAVES * 64, (WAVES == 1 ? 2 : NUTS_WAVES_PER_SIMD))
         __syncthreads();
         const int p = __builtin_amdgcn_readfirstlane(S.p);
         if (p >= a.P) break;
-        const DevEvent* ev = nullptr;
-        if (TK == SMCGW_TARGET_GW)
-            ev = a.events + __builtin_amdgcn_readfirstlane(event_index(a.ev_of_p, p, a.n_events));
-        if (wave == 0) start_transition(S, T, a, p, lane);
+        // The particle's event descriptor is copied into LDS (all threads, ordered
+        // before its first use by the barrier that follows pre_leaf), so the
+        // leaf's serial phases read it without a round trip to the L2.
+        const DevEvent* ev = &S.ev;
+        if (TK == SMCGW_TARGET_GW) {
+            const int e = __builtin_amdgcn_readfirstlane(event_index(a.ev_of_p, p, a.n_events));
+            if (e != ev_cached) {   // uniform over the workgroup
+                const unsigned long long* src = (const unsigned long long*)(a.events + e);
+                unsigned long long* dst = (unsigned long long*)&S.ev;
+                for (int i = tid; i < (int)(sizeof(DevEvent) / 8); i += blockDim.x) dst[i] = src[i];
+                ev_cached = e;
+            }
+        }
+        if (wave == 0) start_transition(S, T, A, p, lane);
 
         for (;;) {
             if (wave == 0) {
-                const int cmd = pre_leaf<TK>(S, T, a, p, lane);
+                const int cmd = pre_leaf<TK>(S, T, A, p, lane);
                 if (lane == 0) S.cmd = cmd;
             }
             __syncthreads();
@@ -561,11 +576,11 @@ __global__ __launch_bounds__(WAVES * 64, (WAVES == 1 ? 2 : NUTS_WAVES_PER_SIMD))
             }
             if (wave == 0) {
                 __builtin_amdgcn_wave_barrier();
-                post_leaf(S, T, a, p, lane);
+                post_leaf(S, T, A, p, lane);
             }
         }
         if (a.priority) __builtin_amdgcn_s_setprio(0);
-        if (wave == 0) write_outputs(S, T, a, p, lane);
+        if (wave == 0) write_outputs(S, T, A, p, lane);
         __syncthreads();
     }
 }
