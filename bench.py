@@ -169,11 +169,12 @@ def run_smc_steps(smcgw, ctx, theta, precision, args, n_warm, n_steps, time_kern
     logl, grad = ctx.target_loglike_grad(theta, precision=precision)
     beta, it, hint = 0.0, 0, None
     stats = []
+    mm_status = torch.zeros(1, dtype=torch.int32, device="cuda")
 
     def one_step():
         nonlocal beta, it, hint
         b, dz, _ = ctx.smc_reweight_resample(theta, logl, grad, beta, args.alpha, args.seed, it, carry=hint)
-        _, L, _ = ctx.mass_matrix(theta, 0.0)
+        _, L, _ = ctx.mass_matrix(theta, 0.0, status=mm_status)
         out = ctx.nuts_step(theta, logl, grad, L, step=args.step, beta=b, seed=args.seed, iteration=it,
                             max_depth=args.max_depth, precision=precision, work_hint=hint)
         hint = None if args.no_hint else out["n_leapfrog"]

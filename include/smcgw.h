@@ -170,10 +170,12 @@ int smcgw_waveform(smcgw_ctx *ctx, int event_id, const double *theta11, double *
  * geometry", read as the population covariance): inv_mass = cov(theta) with
  * the diagonal scaled by (1 + shrink), chol its lower Cholesky factor
  * (M^{-1} = chol chol^T).  theta [P][D], inv_mass [D][D], chol [D][D] are
- * device arrays.  Synchronises; returns SMCGW_WARN_FALLBACK when the
- * covariance was not positive definite and a diagonal was used. */
+ * device arrays.  status_device (device int32, may be NULL) receives 1 when
+ * the covariance was not positive definite and a diagonal was used, else 0;
+ * with it the call is asynchronous and returns SMCGW_OK.  Without it the
+ * call synchronises and returns SMCGW_WARN_FALLBACK in that case. */
 int smcgw_mass_matrix(smcgw_ctx *ctx, int P, int D, const double *theta, double shrink, double *inv_mass,
-                      double *chol);
+                      double *chol, int32_t *status_device);
 
 /* One No-U-Turn transition per particle (Sec. 4: momentum r ~ N(0, M),
  * Hamiltonian H = -log p_t + r^T M^{-1} r / 2, leapfrog Eqs. 11-13,

@@ -20,8 +20,8 @@ constexpr int SMC_THREADS = 1024;
 constexpr int SMC_WAVES = SMC_THREADS / 64;
 // Bisection levels resolved per pass over the particles: every pass evaluates
 // the ESS at all 2^RW_LEVELS - 1 midpoints the next RW_LEVELS bisection steps
-// could visit (plus one spare candidate), so the walk down that subtree
-// repeats the sequential bisection's decisions exactly.
+// could visit (and, in the first pass, at beta = 1), so the walk down that
+// subtree takes the sequential bisection's decisions.
 constexpr int RW_LEVELS = 4;
 constexpr int RW_CAND = 1 << RW_LEVELS;
 constexpr int RW_THREADS = 512;   // 32 FP64 accumulators per thread need the larger register budget
@@ -101,8 +101,13 @@ __global__ __launch_bounds__(RW_THREADS) void reweight_kernel(const double* __re
         return;
     }
     const double target = alpha * (double)P;
-    // Candidate 0 of the first pass is beta = 1; candidates 1..15 are the
-    // bisection midpoints in heap order (children of n: 2n below, 2n+1 above).
+    // Each pass resolves RW_LEVELS bisection levels below [lo, hi].  The
+    // midpoints those levels can visit are lo + k h, k = 1..15, h = (hi - lo)/16
+    // (slot k); they are computed exactly as the sequential bisection computes
+    // them (heap node n: children 2n below, 2n+1 above) and stored by node for
+    // the walk.  A particle's weights on the grid are a geometric sequence,
+    // w_k = exp((lo - beta_prev) e) exp(h e)^k, so a pass costs two exps per
+    // particle.  Slot 0 of the first pass holds beta = 1.
     double lo = beta_prev, hi = 1.0, beta = -1.0;
     int it = 0;
     for (int pass = 0; beta < 0.0; ++pass) {
@@ -116,18 +121,27 @@ __global__ __launch_bounds__(RW_THREADS) void reweight_kernel(const double* __re
                 a[2 * n + 1] = mid[n]; b[2 * n + 1] = b[n];
             }
         }
-        mid[0] = pass == 0 ? 1.0 : mid[1];
-        if (threadIdx.x < RW_CAND) cand[threadIdx.x] = mid[threadIdx.x];   // read after the sums' barriers
+        if (threadIdx.x < RW_CAND) cand[threadIdx.x] = threadIdx.x == 0 ? 1.0 : mid[threadIdx.x];
+        const double h = (hi - lo) * (1.0 / RW_CAND);
+        const double d0 = lo - beta_prev;
         double s[2 * RW_CAND];
 #pragma unroll
         for (int n = 0; n < 2 * RW_CAND; ++n) s[n] = 0.0;
         for (int i = threadIdx.x; i < P; i += blockDim.x) {
             const double e = ll_at(logl, i) - lmax;
+            if (e == -INFINITY) continue;   // zero weight at every candidate (db > 0)
+            if (pass == 0) {
+                const double w1 = exp((1.0 - beta_prev) * e);
+                s[0] += w1;
+                s[1] += w1 * w1;
+            }
+            const double r = exp(h * e);
+            double w = exp(d0 * e);
 #pragma unroll
-            for (int n = 0; n < RW_CAND; ++n) {
-                const double w = incr_weight(mid[n] - beta_prev, e);
-                s[2 * n] += w;
-                s[2 * n + 1] += w * w;
+            for (int k = 1; k < RW_CAND; ++k) {
+                w *= r;
+                s[2 * k] += w;
+                s[2 * k + 1] += w * w;
             }
         }
         block_sums<2 * RW_CAND>(s, red, tot);
@@ -135,7 +149,8 @@ __global__ __launch_bounds__(RW_THREADS) void reweight_kernel(const double* __re
         int n = 1;
         for (int lev = 0; lev < RW_LEVELS; ++lev) {
             if (!(it < 100 && hi - lo > 1e-14)) { beta = lo; break; }
-            if (tot[2 * n] * tot[2 * n] / tot[2 * n + 1] >= target) { lo = cand[n]; n = 2 * n + 1; }
+            const int k = (2 * (n - (1 << lev)) + 1) << (RW_LEVELS - 1 - lev);   // grid slot of node n
+            if (tot[2 * k] * tot[2 * k] / tot[2 * k + 1] >= target) { lo = cand[n]; n = 2 * n + 1; }
             else { hi = cand[n]; n = 2 * n; }
             ++it;
         }
@@ -230,11 +245,25 @@ __global__ __launch_bounds__(256) void copy_back_kernel(int P, int D, const doub
     if (cy) cy[i] = cyo[i];
 }
 
+// Covariance entries (a, b), b <= a < MAXDIM, in row order, MM_CHUNK per pass
+// over the particles; the table is a compile-time constant, so every index is
+// a literal after unrolling and a particle's centred row stays in registers.
+constexpr int MM_CHUNK = 17;
+constexpr int MM_ENTRIES = MAXDIM * (MAXDIM + 1) / 2;
+static_assert(MM_ENTRIES % MM_CHUNK == 0, "whole chunks");
+static_assert(MAXDIM <= MM_CHUNK, "the mean pass reuses the chunk's reduction buffers");
+struct TriTable {
+    int a[MM_ENTRIES], b[MM_ENTRIES];
+    constexpr TriTable() : a(), b() {
+        int e = 0;
+        for (int i = 0; i < MAXDIM; ++i)
+            for (int j = 0; j <= i; ++j) { a[e] = i; b[e] = j; ++e; }
+    }
+};
+constexpr TriTable TRI{};
+
 // Population mean and covariance (two passes, fixed order), diagonal
 // shrinkage and Cholesky; status[0] = 1 when a diagonal fallback was used.
-constexpr int MM_CHUNK = 16;   // covariance entries accumulated per pass over the particles
-static_assert(MAXDIM <= MM_CHUNK, "the mean pass reuses the chunk's reduction buffers");
-
 __global__ __launch_bounds__(SMC_THREADS) void mass_matrix_kernel(const double* __restrict__ x, int P, int D,
                                                                   double shrink, double* __restrict__ inv,
                                                                   double* __restrict__ L, int* __restrict__ status) {
@@ -243,6 +272,7 @@ __global__ __launch_bounds__(SMC_THREADS) void mass_matrix_kernel(const double* 
     __shared__ double mu[MAXDIM];
     __shared__ double cov[MAXDIM * MAXDIM];
     __shared__ double l[MAXDIM * MAXDIM];
+    __shared__ int bad;
     {
         double s[MAXDIM];
 #pragma unroll
@@ -255,63 +285,71 @@ __global__ __launch_bounds__(SMC_THREADS) void mass_matrix_kernel(const double* 
         if ((int)threadIdx.x < D) mu[threadIdx.x] = tot[threadIdx.x] / P;
         __syncthreads();
     }
-    // lower triangle (a >= b) in row order, MM_CHUNK entries per pass
-    const int n_ent = D * (D + 1) / 2;
-    for (int e0 = 0; e0 < n_ent; e0 += MM_CHUNK) {
-        int ea[MM_CHUNK], eb[MM_CHUNK];
-        {
-            int a = 0, b = 0;   // entry e0 -> (a, b)
-            while (a * (a + 1) / 2 + a < e0) ++a;
-            b = e0 - a * (a + 1) / 2;
+    double m[MAXDIM];
 #pragma unroll
-            for (int j = 0; j < MM_CHUNK; ++j) {
-                ea[j] = a; eb[j] = b;
-                if (++b > a) { ++a; b = 0; }
-            }
-        }
+    for (int k = 0; k < MAXDIM; ++k) m[k] = k < D ? mu[k] : 0.0;
+#pragma unroll
+    for (int e0 = 0; e0 < MM_ENTRIES; e0 += MM_CHUNK) {
+        if (TRI.a[e0] >= D) break;   // rows below are beyond the dimension
         double s[MM_CHUNK];
 #pragma unroll
         for (int j = 0; j < MM_CHUNK; ++j) s[j] = 0.0;
         for (int i = threadIdx.x; i < P; i += blockDim.x) {
-            const double* xi = x + (size_t)i * D;
+            double xc[MAXDIM];
 #pragma unroll
-            for (int j = 0; j < MM_CHUNK; ++j)
-                if (e0 + j < n_ent) s[j] += (xi[ea[j]] - mu[ea[j]]) * (xi[eb[j]] - mu[eb[j]]);
+            for (int k = 0; k < MAXDIM; ++k) xc[k] = k < D ? x[(size_t)i * D + k] - m[k] : 0.0;
+#pragma unroll
+            for (int j = 0; j < MM_CHUNK; ++j) s[j] += xc[TRI.a[e0 + j]] * xc[TRI.b[e0 + j]];
         }
         block_sums<MM_CHUNK>(s, red, tot);
-        if ((int)threadIdx.x < MM_CHUNK && e0 + (int)threadIdx.x < n_ent) {
-            const double v = tot[threadIdx.x] / (P - 1);
-            cov[ea[threadIdx.x] * D + eb[threadIdx.x]] = v;
-            cov[eb[threadIdx.x] * D + ea[threadIdx.x]] = v;
+        if ((int)threadIdx.x < MM_CHUNK) {
+            const int a = TRI.a[e0 + threadIdx.x], b = TRI.b[e0 + threadIdx.x];
+            if (a < D) {
+                const double v = tot[threadIdx.x] / (P - 1);
+                cov[a * D + b] = v;
+                cov[b * D + a] = v;
+            }
         }
     }
     __syncthreads();
-    if (threadIdx.x != 0) return;
-    for (int k = 0; k < D; ++k) cov[k * D + k] *= (1.0 + shrink);
-    for (int i = 0; i < D * D; ++i) l[i] = 0.0;
-    int bad = 0;
-    for (int j = 0; j < D && !bad; ++j) {
-        double s = cov[j * D + j];
-        for (int k = 0; k < j; ++k) s -= l[j * D + k] * l[j * D + k];
-        if (!(s > 0.0)) { bad = 1; break; }
-        l[j * D + j] = sqrt(s);
-        for (int i = j + 1; i < D; ++i) {
-            double t = cov[i * D + j];
-            for (int k = 0; k < j; ++k) t -= l[i * D + k] * l[j * D + k];
-            l[i * D + j] = t / l[j * D + j];
+    // Cholesky on wavefront 0, one row per lane: column j needs the finished
+    // columns < j of rows j and i, read from LDS.
+    if (threadIdx.x >= 64) return;
+    const int lane = threadIdx.x;
+    if (lane < D) cov[lane * D + lane] *= (1.0 + shrink);
+    for (int i = lane; i < D * D; i += 64) l[i] = 0.0;
+    if (lane == 0) bad = 0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    for (int j = 0; j < D; ++j) {
+        double sjj = cov[j * D + j];
+        for (int k = 0; k < j; ++k) sjj -= l[j * D + k] * l[j * D + k];
+        if (!(sjj > 0.0)) { if (lane == 0) bad = 1; break; }   // uniform: every lane computes sjj
+        const double ljj = sqrt(sjj);
+        if (lane > j && lane < D) {
+            double t = cov[lane * D + j];
+            for (int k = 0; k < j; ++k) t -= l[lane * D + k] * l[j * D + k];
+            l[lane * D + j] = t / ljj;
         }
+        if (lane == j) l[j * D + j] = ljj;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
     }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
     if (bad) {
-        for (int i = 0; i < D * D; ++i) l[i] = 0.0;
-        for (int k = 0; k < D; ++k) {
-            double v = cov[k * D + k];
+        for (int i = lane; i < D * D; i += 64) l[i] = 0.0;
+        __builtin_amdgcn_wave_barrier();
+        if (lane < D) {
+            double v = cov[lane * D + lane];
             if (!(v > 0.0)) v = 1.0;
-            for (int b = 0; b < D; ++b) cov[k * D + b] = (b == k) ? v : 0.0;
-            l[k * D + k] = sqrt(v);
+            for (int b = 0; b < D; ++b) cov[lane * D + b] = (b == lane) ? v : 0.0;
+            l[lane * D + lane] = sqrt(v);
         }
+        __builtin_amdgcn_wave_barrier();
     }
-    for (int i = 0; i < D * D; ++i) { inv[i] = cov[i]; L[i] = l[i]; }
-    status[0] = bad;
+    for (int i = lane; i < D * D; i += 64) { inv[i] = cov[i]; L[i] = l[i]; }
+    if (lane == 0) status[0] = bad;
 }
 
 // Analytic test likelihoods, one particle per lane (same definitions as the
@@ -415,15 +453,21 @@ extern "C" int smcgw_set_target(smcgw_ctx* c, int kind, int dim, const double* p
 }
 
 extern "C" int smcgw_mass_matrix(smcgw_ctx* c, int P, int D, const double* theta, double shrink, double* inv_mass,
-                                 double* chol) {
+                                 double* chol, int32_t* status_device) {
     if (!c || !theta || !inv_mass || !chol || P < 2 || D <= 0 || D > MAXDIM || !(shrink >= 0.0))
         return SMCGW_ERR_INVALID;
     hipSetDevice(c->device);
-    int* st = (int*)sampler_scratch(c, 64);
-    double* hp = pinned(c);
-    if (!st || !hp) return SMCGW_ERR_OOM;
-    hipLaunchKernelGGL(mass_matrix_kernel, dim3(1), dim3(SMC_THREADS), 0, c->stream, theta, P, D, shrink, inv_mass, chol, st);
+    int* st = status_device;
+    double* hp = nullptr;
+    if (!st) {
+        st = (int*)sampler_scratch(c, 64);
+        hp = pinned(c);
+        if (!st || !hp) return SMCGW_ERR_OOM;
+    }
+    hipLaunchKernelGGL(mass_matrix_kernel, dim3(1), dim3(SMC_THREADS), 0, c->stream, theta, P, D, shrink, inv_mass,
+                       chol, st);
     if (hipGetLastError() != hipSuccess) return SMCGW_ERR_HIP;
+    if (status_device) return SMCGW_OK;
     if (hipMemcpyAsync(hp, st, sizeof(int), hipMemcpyDeviceToHost, c->stream) || hipStreamSynchronize(c->stream))
         return SMCGW_ERR_HIP;
     int s;

@@ -48,6 +48,7 @@ class SmcResult:
     divergent: List[int]
     seconds: float
     populations: Optional[List[torch.Tensor]] = None   # population entering each reweight
+    mass_matrix_fallbacks: int = 0                      # iterations whose covariance needed the diagonal
 
 
 def run_smc(ctx: "smcgw.Context", theta0: torch.Tensor, cfg: SmcConfig) -> SmcResult:
@@ -56,8 +57,10 @@ def run_smc(ctx: "smcgw.Context", theta0: torch.Tensor, cfg: SmcConfig) -> SmcRe
     logl, grad = ctx.target_loglike_grad(theta, precision=cfg.precision)
     beta, logz = 0.0, 0.0
     betas, dlogzs, nlf, depths, divs = [], [], [], [], []
+    fallbacks = 0
     pops = [] if cfg.record else None
     hint = None   # leapfrog counts of the last transition, resampled with the particles
+    mm_status = torch.zeros(1, dtype=torch.int32, device=theta.device)   # 1: diagonal mass-matrix fallback
     t0 = time.perf_counter()
     it = 0
     while beta < 1.0 and it < cfg.max_iter:
@@ -65,7 +68,7 @@ def run_smc(ctx: "smcgw.Context", theta0: torch.Tensor, cfg: SmcConfig) -> SmcRe
             pops.append(theta.clone())
         b, dz, _ = ctx.smc_reweight_resample(theta, logl, grad, beta, cfg.alpha, cfg.seed, it, carry=hint)
         logz += dz
-        _, L, _ = ctx.mass_matrix(theta, cfg.shrink)
+        _, L, _ = ctx.mass_matrix(theta, cfg.shrink, status=mm_status)
         out = ctx.nuts_step(theta, logl, grad, L, step=cfg.step, beta=b, seed=cfg.seed, iteration=it,
                             max_depth=cfg.max_depth, uturn=cfg.uturn, precision=cfg.precision, work_hint=hint)
         hint = out["n_leapfrog"] if cfg.work_hint else None
@@ -74,7 +77,9 @@ def run_smc(ctx: "smcgw.Context", theta0: torch.Tensor, cfg: SmcConfig) -> SmcRe
         nlf.append(int(out["n_leapfrog"].sum().item()))
         depths.append(float(out["depth"].double().mean().item()))
         divs.append(int(out["divergent"].sum().item()))
+        fallbacks += int(mm_status.item())
         beta = b
         it += 1
     torch.cuda.synchronize()
-    return SmcResult(logz, betas, dlogzs, it, theta, logl, grad, nlf, depths, divs, time.perf_counter() - t0, pops)
+    return SmcResult(logz, betas, dlogzs, it, theta, logl, grad, nlf, depths, divs, time.perf_counter() - t0, pops,
+                     fallbacks)

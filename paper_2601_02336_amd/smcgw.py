@@ -77,7 +77,7 @@ def lib():
         L.smcgw_loglike_grad.argtypes = [vp, i, vp, vp, vp, vp, i]
         L.smcgw_waveform.argtypes = [vp, i, vp, vp]
         L.smcgw_target_loglike_grad.argtypes = [vp, i, vp, vp, vp, i]
-        L.smcgw_mass_matrix.argtypes = [vp, i, i, vp, d, vp, vp]
+        L.smcgw_mass_matrix.argtypes = [vp, i, i, vp, d, vp, vp, vp]
         L.smcgw_nuts_step.argtypes = [vp, i, i, vp, vp, vp, vp, C.POINTER(NutsParams), vp, vp, i, vp, vp, vp, vp]
         L.smcgw_timing_enable.argtypes = [vp, i]
         L.smcgw_set_option.argtypes = [vp, i, C.c_int64]
@@ -230,14 +230,18 @@ class Context:
         _check("smcgw_waveform", lib().smcgw_waveform(self._h, event_id, th.ctypes.data_as(C.c_void_p), _ptr(h)))
         return h
 
-    def mass_matrix(self, theta: torch.Tensor, shrink: float = 0.0):
+    def mass_matrix(self, theta: torch.Tensor, shrink: float = 0.0, status: Optional[torch.Tensor] = None):
+        """(inv_mass, chol, rc).  With a device int32 `status` tensor the call does not synchronise:
+        the fallback flag lands in status[0] and rc is OK."""
         theta = _dev(theta, torch.float64, "theta")
         P, D = theta.shape
         inv = torch.empty((D, D), dtype=torch.float64, device=theta.device)
         L = torch.empty_like(inv)
+        if status is not None:
+            _dev(status, torch.int32, "status")
         self._stream()
         rc = _check("smcgw_mass_matrix", lib().smcgw_mass_matrix(self._h, P, D, _ptr(theta), shrink, _ptr(inv),
-                                                                 _ptr(L)), allow=(OK, WARN_FALLBACK))
+                                                                 _ptr(L), _ptr(status)), allow=(OK, WARN_FALLBACK))
         return inv, L, rc
 
     def nuts_step(self, theta: torch.Tensor, logl: torch.Tensor, grad: torch.Tensor, chol: torch.Tensor,
@@ -250,10 +254,11 @@ class Context:
         dev = theta.device
         out = {}
         if diagnostics:
-            out = dict(depth=torch.zeros(P, dtype=torch.int32, device=dev),
-                       n_leapfrog=torch.zeros(P, dtype=torch.int32, device=dev),
-                       divergent=torch.zeros(P, dtype=torch.uint8, device=dev),
-                       accept_stat=torch.zeros(P, dtype=torch.float64, device=dev))
+            # the kernel writes every particle's entry
+            out = dict(depth=torch.empty(P, dtype=torch.int32, device=dev),
+                       n_leapfrog=torch.empty(P, dtype=torch.int32, device=dev),
+                       divergent=torch.empty(P, dtype=torch.uint8, device=dev),
+                       accept_stat=torch.empty(P, dtype=torch.float64, device=dev))
         if max_depth_per_particle is not None:
             _dev(max_depth_per_particle, torch.int32, "max_depth_per_particle")
         if work_hint is not None:

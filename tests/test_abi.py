@@ -44,4 +44,4 @@ def test_invalid_arguments_rejected_without_gpu():
     lib = ctypes.CDLL(LIB)
     assert lib.smcgw_create(None, 0, None) == -1
     assert lib.smcgw_loglike_grad(None, 1, None, None, None, None, 1) == -1
-    assert lib.smcgw_mass_matrix(None, 2, 2, None, ctypes.c_double(0.0), None, None) == -1
+    assert lib.smcgw_mass_matrix(None, 2, 2, None, ctypes.c_double(0.0), None, None, None) == -1

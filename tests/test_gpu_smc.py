@@ -77,6 +77,15 @@ def test_mass_matrix_matches_oracle(ctx):
     # degenerate population -> diagonal fallback, flagged
     inv, L, rc = ctx.mass_matrix(torch.ones((64, 3), dtype=torch.float64, device="cuda"), 0.0)
     assert rc == 1 and torch.all(torch.isfinite(L))
+    # asynchronous form: the flag lands in a device int
+    st = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+    inv2, L2, rc = ctx.mass_matrix(torch.ones((64, 3), dtype=torch.float64, device="cuda"), 0.0, status=st)
+    assert rc == 0 and int(st.item()) == 1
+    assert torch.equal(L2, L) and torch.equal(inv2, inv)
+    x = torch.tensor(np.random.default_rng(5).normal(size=(300, 4)), device="cuda")
+    _, L3, _ = ctx.mass_matrix(x, 0.0, status=st)
+    _, L4, rc4 = ctx.mass_matrix(x, 0.0)
+    assert int(st.item()) == 0 and rc4 == 0 and torch.equal(L3, L4)
 
 
 def test_resample_carries_payload(ctx):
