@@ -5,7 +5,7 @@
 // a block, TABLE_PAD/64 bins per lane) starting at block `blk0` with stride
 // `blk_step`; the per-bin tables are read coalesced and shared by every
 // particle.  Moments (see likelihood.hip) are returned wave-summed in FP64:
-// every lane holds the totals of the blocks the wavefront visited.
+// lane TOTAL_LANE holds the totals of the blocks the wavefront visited.
 #pragma once
 
 #include "common.h"
@@ -28,11 +28,6 @@ __device__ __forceinline__ double uniform_d(double v) {
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
 
 // sin(2 pi x), cos(2 pi x) for |x| <= 1/2 on the hardware transcendental unit
 // (v_sin_f32 / v_cos_f32 take their argument in revolutions).
@@ -180,12 +175,12 @@ __device__ __forceinline__ void bins_mixed_wave(const DevEvent* __restrict__ ev,
     for (int i = 0; i < MOM_SIZE; ++i) mom[i] = 0.0;
 #pragma unroll
     for (int d = 0; d < NDET; ++d) {
-        mom[MOM_ZR + d] = wave_sum(A.Zr[d] + A.zr[d]);
-        mom[MOM_ZI + d] = wave_sum(A.Zi[d] + A.zi[d]);
-        mom[MOM_T + d] = wave_sum(A.T[d] + A.tq[d]);
+        mom[MOM_ZR + d] = wave_total(A.Zr[d] + A.zr[d]);
+        mom[MOM_ZI + d] = wave_total(A.Zi[d] + A.zi[d]);
+        mom[MOM_T + d] = wave_total(A.T[d] + A.tq[d]);
     }
 #pragma unroll
-    for (int b = 0; b < NCOEF; ++b) mom[MOM_G + b] = wave_sum(A.G[b]);
+    for (int b = 0; b < NCOEF; ++b) mom[MOM_G + b] = wave_total(A.G[b]);
 }
 
 // PLAIN_FP64: the same algebra in FP64 throughout.
@@ -237,12 +232,12 @@ __device__ __forceinline__ void bins_fp64_wave(const DevEvent* __restrict__ ev, 
     for (int i = 0; i < MOM_SIZE; ++i) mom[i] = 0.0;
 #pragma unroll
     for (int d = 0; d < NDET; ++d) {
-        mom[MOM_ZR + d] = wave_sum(A.Zr[d]);
-        mom[MOM_ZI + d] = wave_sum(A.Zi[d]);
-        mom[MOM_T + d] = wave_sum(A.T[d]);
+        mom[MOM_ZR + d] = wave_total(A.Zr[d]);
+        mom[MOM_ZI + d] = wave_total(A.Zi[d]);
+        mom[MOM_T + d] = wave_total(A.T[d]);
     }
 #pragma unroll
-    for (int b = 0; b < NCOEF; ++b) mom[MOM_G + b] = wave_sum(A.G[b]);
+    for (int b = 0; b < NCOEF; ++b) mom[MOM_G + b] = wave_total(A.G[b]);
 }
 
 template <int NDET>

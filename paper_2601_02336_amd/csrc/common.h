@@ -42,6 +42,41 @@ __device__ __forceinline__ void basis_rows(double f, double w, double lnf, doubl
     B[B_P23] = u * u;
 }
 
+// Cross-lane moves through the VALU's data-parallel-primitive (DPP) lanes:
+// no LDS round trip, unlike a shuffle.  A double moves as two 32-bit halves.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xf, 0xf, false);
+    const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Sum over the 64 lanes of a wavefront in a fixed order: pairs and quads
+// (quad permutations), rows of 16 (row rotations by 4 and 8), then the rows
+// through the row-15 and row-31 broadcasts.  The total is valid in lane 63
+// only (TOTAL_LANE).
+constexpr int TOTAL_LANE = 63;
+__device__ __forceinline__ double wave_total(double v) {
+    v += dpp_move<0xb1>(v);    // quad_perm [1,0,3,2]
+    v += dpp_move<0x4e>(v);    // quad_perm [2,3,0,1]
+    v += dpp_move<0x124>(v);   // row_ror:4
+    v += dpp_move<0x128>(v);   // row_ror:8
+    v += dpp_move<0x142>(v);   // row_bcast:15
+    v += dpp_move<0x143>(v);   // row_bcast:31
+    return v;
+}
+
+__device__ __forceinline__ double wave_max_total(double v) {
+    v = fmax(v, dpp_move<0xb1>(v));
+    v = fmax(v, dpp_move<0x4e>(v));
+    v = fmax(v, dpp_move<0x124>(v));
+    v = fmax(v, dpp_move<0x128>(v));
+    v = fmax(v, dpp_move<0x142>(v));
+    v = fmax(v, dpp_move<0x143>(v));
+    return v;
+}
+
 // Device view of one event's bin tables (frequency-major, padded to n_pad).
 struct DevEvent {
     int n_bins, n_pad, n_det, pn_order;

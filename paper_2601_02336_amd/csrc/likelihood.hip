@@ -52,7 +52,7 @@ __global__ __launch_bounds__(256) void bins_mixed_kernel(const DevEvent* __restr
     const BinCoef k = load_coef(cb + (size_t)p * CB_SIZE);
     double m[MOM_SIZE];
     bins_mixed_wave<NDET, BINS_UNROLL>(evs + e, k, 0, 1, m);
-    if ((threadIdx.x & 63) == 0)
+    if ((threadIdx.x & 63) == TOTAL_LANE)
         for (int i = 0; i < MOM_SIZE; ++i) mom[(size_t)p * MOM_SIZE + i] = m[i];
 }
 
@@ -67,7 +67,7 @@ __global__ __launch_bounds__(256) void bins_fp64_kernel(const DevEvent* __restri
     const BinCoef k = load_coef(cb + (size_t)p * CB_SIZE);
     double m[MOM_SIZE];
     bins_fp64_wave<NDET, BINS_UNROLL>(evs + e, k, 0, 1, m);
-    if ((threadIdx.x & 63) == 0)
+    if ((threadIdx.x & 63) == TOTAL_LANE)
         for (int i = 0; i < MOM_SIZE; ++i) mom[(size_t)p * MOM_SIZE + i] = m[i];
 }
 

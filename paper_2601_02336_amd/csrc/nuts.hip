@@ -563,7 +563,7 @@ __global__ __launch_bounds__(WAVES * 64, (WAVES == 1 ? 2 : NUTS_WAVES_PER_SIMD))
                         bins_mixed_wave<NDET, NUTS_UNROLL>(ev, k, wave, WAVES, m);
                     else
                         bins_fp64_wave<NDET, NUTS_UNROLL>(ev, k, wave, WAVES, m);
-                    if (lane == 0)
+                    if (lane == TOTAL_LANE)
                         for (int i = 0; i < MOM_SIZE; ++i) S.mom[wave][i] = m[i];
                 }
                 __syncthreads();

@@ -26,22 +26,9 @@ constexpr int RW_LEVELS = 4;
 constexpr int RW_CAND = 1 << RW_LEVELS;
 constexpr int RW_THREADS = 512;   // 32 FP64 accumulators per thread need the larger register budget
 
-// Fixed-order sum over the 64 lanes of a wavefront (butterfly; every lane gets
-// the same bits).
-__device__ __forceinline__ double wave_total(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
 
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-    return v;
-}
-
-// Workgroup sums of K values per thread: wavefront butterflies, then the
-// wavefront totals added in wavefront order.  tot[k] is valid in all threads
+// Workgroup sums of K values per thread: wavefront totals (DPP), then added
+// in wavefront order.  tot[k] is valid in all threads
 // after the call; red must hold K * (blockDim.x / 64) doubles.
 template <int K>
 __device__ __forceinline__ void block_sums(double (&v)[K], double* red, double* tot) {
@@ -49,7 +36,7 @@ __device__ __forceinline__ void block_sums(double (&v)[K], double* red, double* 
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const double t = wave_total(v[k]);
-        if (lane == 0) red[k * nw + wave] = t;
+        if (lane == TOTAL_LANE) red[k * nw + wave] = t;
     }
     __syncthreads();
     if ((int)threadIdx.x < K) {
@@ -62,8 +49,8 @@ __device__ __forceinline__ void block_sums(double (&v)[K], double* red, double* 
 
 __device__ __forceinline__ double block_max(double v, double* red) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    v = wave_max(v);
-    if (lane == 0) red[wave] = v;
+    v = wave_max_total(v);
+    if (lane == TOTAL_LANE) red[wave] = v;
     __syncthreads();
     double m = red[0];
     for (int w = 1; w < nw; ++w) m = fmax(m, red[w]);
