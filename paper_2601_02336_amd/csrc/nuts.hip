@@ -81,7 +81,6 @@ struct NutsShared {
 };
 static_assert(sizeof(DevEvent) % 8 == 0, "the event descriptor is copied in 8-byte words");
 
-enum { ST_START = 0, ST_SUBTREE = 1, ST_DONE = 2 };
 enum { CMD_EVAL = 0, CMD_DONE = 1 };
 
 __device__ __forceinline__ double log_add_exp(double a, double b) {
@@ -198,14 +197,33 @@ __device__ __forceinline__ double analytic_loglike(NutsShared& S, const TargetDe
 }
 
 // Tree state of the slot's current transition (LDS; wavefront 0 only).
+//
+// Leaf pipeline: once the likelihood of leaf k is known, `advance` completes
+// its momentum and moves to leaf k+1 on the assumption that the tree goes on
+// (the position of the next leaf does not depend on the multinomial sampling
+// or the U-turn checks).  `bookkeep` then takes those decisions for leaf k on
+// wavefront 0 while the other wavefronts already run leaf k+1's prologue; if
+// the tree stops, that prologue is discarded.  Every quantity is the one the
+// plain sequential algorithm computes.
 struct NutsState {
-    double x[MAXDIM], r[MAXDIM], g[MAXDIM], gl[MAXDIM];   // the edge being extended
+    double x[MAXDIM], r[MAXDIM];                         // the leaf in flight: position, half-step momentum
     double rho[MAXDIM], srho[MAXDIM];                    // momentum sums of the tree / subtree
-    double gl_new[MAXDIM];                               // likelihood gradient of the last leaf
-    double h0, logw, sub_logw, uacc, acc_sum, eps, ll, lp, prop_ll, sprop_ll, ll_new;
-    int state, j, n, nleaves, depth, nlf, div, dir, md;
+    double gl_new[MAXDIM];                               // likelihood gradient of the leaf in flight
+    double rec[4][MAXDIM];                               // finished leaf: x, r, g (grad log p_t), gl
+    double pgp[MAXDIM];                                  // prior gradient at the leaf in flight
+    double plp;                                          // log prior at the leaf in flight
+    double h0, logw, sub_logw, uacc, uacc_next, acc_sum, eps, prop_ll, sprop_ll, ll_new, rec_ll, rec_lp;
+    int first, stop, j, n, nleaves, depth, nlf, div, dir, dir_next, md;
     uint32_t leafc;
 };
+
+// Direction and merge uniform of doubling j (Philox stream DOUBLING).
+__device__ __forceinline__ void doubling_draw(const NutsArgs& a, int p, int j, int& dir, double& uacc) {
+    double ud0, ud1;
+    rng_uniform2(a.seed, (uint32_t)j, (uint32_t)p, a.iteration, RNG_DOUBLING, ud0, ud1);
+    dir = (ud0 < 0.5) ? -1 : 1;
+    uacc = ud1;
+}
 
 // Start a transition of particle p (wavefront 0): momentum, H0, tree of one point.
 __device__ __noinline__ void start_transition(NutsShared& S, NutsState& T, const NutsArgs& a, int p, int lane) {
@@ -239,7 +257,13 @@ __device__ __noinline__ void start_transition(NutsShared& S, NutsState& T, const
         S.right[0][lane] = x; S.right[1][lane] = r; S.right[2][lane] = g; S.right[3][lane] = gl; S.right[4][lane] = v;
         S.prop[0][lane] = x; S.prop[1][lane] = gl;
         T.rho[lane] = r;
+        T.srho[lane] = 0.0;
     }
+    const int md = a.md_per_p ? min(a.md_per_p[p], SMCGW_MAX_DEPTH) : a.max_depth;
+    int dir0 = 1, dir1 = 1;
+    double ua0 = 0.0, ua1 = 0.0;
+    if (md > 0) doubling_draw(a, p, 0, dir0, ua0);
+    if (md > 1) doubling_draw(a, p, 1, dir1, ua1);
     if (lane == 0) {
         S.end_ll[0] = S.end_ll[1] = ll;
         S.end_lp[0] = S.end_lp[1] = lp;
@@ -247,65 +271,71 @@ __device__ __noinline__ void start_transition(NutsShared& S, NutsState& T, const
         T.h0 = h0;
         T.logw = 0.0;
         T.acc_sum = 0.0;
-        T.state = ST_START;
+        T.first = 1;
+        T.stop = 0;
         T.j = 0;
+        T.n = 0;
+        T.nleaves = 1;
+        T.sub_logw = -INFINITY;
         T.depth = 0;
         T.nlf = 0;
         T.div = 0;
         T.leafc = 0;
-        T.md = a.md_per_p ? min(a.md_per_p[p], SMCGW_MAX_DEPTH) : a.max_depth;
+        T.md = md;
+        T.dir = dir0;
+        T.uacc = ua0;
+        T.dir_next = dir1;
+        T.uacc_next = ua1;
     }
 }
 
-// Advance to the next leaf (wavefront 0): start a doubling if needed, then the
-// first momentum half-step, the position step and the boundary maps.  Returns
-// CMD_EVAL with the new position in T.x (and the source parameters in S.th),
-// or CMD_DONE when the transition is complete.
+// Complete the leaf in flight (momentum full step with its gradient) into the
+// record for `bookkeep`, then take the leapfrog step to the next leaf: the
+// next one in the current subtree, else the first leaf of the next doubling
+// from the tree end on its side.  Returns CMD_DONE when no leaf follows (the
+// depth limit, or no doubling at all).
 template <int TK>
-__device__ __noinline__ int pre_leaf(NutsShared& S, NutsState& T, const NutsArgs& a, int p, int lane) {
+__device__ __noinline__ int advance(NutsShared& S, NutsState& T, const NutsArgs& a, int lane) {
     const int D = a.D;
     const bool dl = lane < D;
-    int state = T.state;
-    if (state == ST_START) {
-        const int j = T.j;
-        if (j < T.md) {
-            double ud0, ud1;
-            rng_uniform2(a.seed, (uint32_t)j, (uint32_t)p, a.iteration, RNG_DOUBLING, ud0, ud1);
-            const int dir = (ud0 < 0.5) ? -1 : 1;
-            const int side = dir > 0 ? 1 : 0;
-            if (dl) {
-                const double (*E)[MAXDIM] = side ? S.right : S.left;
-                T.x[lane] = E[0][lane]; T.r[lane] = E[1][lane]; T.g[lane] = E[2][lane]; T.gl[lane] = E[3][lane];
-                S.sprop[0][lane] = E[0][lane];
-                S.sprop[1][lane] = E[3][lane];
-                T.srho[lane] = 0.0;
+    double xs, rs, gs;   // start point of the next leapfrog step
+    int dir;
+    if (T.first) {
+        if (T.md < 1) return CMD_DONE;
+        xs = dl ? S.left[0][lane] : 0.0;
+        rs = dl ? S.left[1][lane] : 0.0;
+        gs = dl ? S.left[2][lane] : 0.0;
+        dir = T.dir;
+    } else {
+        const double ll = T.ll_new;
+        const double gl = dl ? T.gl_new[lane] : 0.0;
+        const double x = dl ? T.x[lane] : 0.0;
+        const double lp = a.beta * ll + T.plp;
+        const double g = a.beta * gl + (dl ? T.pgp[lane] : 0.0);
+        const double r = dl ? fma(0.5 * T.eps, g, T.r[lane]) : 0.0;
+        if (dl) { T.rec[0][lane] = x; T.rec[1][lane] = r; T.rec[2][lane] = g; T.rec[3][lane] = gl; }
+        if (lane == 0) { T.rec_ll = ll; T.rec_lp = lp; }
+        if (T.n + 1 < T.nleaves) {
+            xs = x; rs = r; gs = g;
+            dir = T.dir;
+        } else if (T.j + 1 < T.md) {
+            dir = T.dir_next;
+            if (dir == T.dir) {
+                xs = x; rs = r; gs = g;
+            } else {
+                const double (*E)[MAXDIM] = dir > 0 ? S.right : S.left;
+                xs = dl ? E[0][lane] : 0.0; rs = dl ? E[1][lane] : 0.0; gs = dl ? E[2][lane] : 0.0;
             }
-            const double ell = S.end_ll[side], elp = S.end_lp[side];
-            __builtin_amdgcn_wave_barrier();
-            if (lane == 0) {
-                T.dir = dir;
-                T.uacc = ud1;
-                T.ll = ell;
-                T.lp = elp;
-                T.sprop_ll = ell;
-                T.sub_logw = -INFINITY;
-                T.n = 0;
-                T.nleaves = 1 << j;
-                T.state = ST_SUBTREE;
-            }
-            state = ST_SUBTREE;
         } else {
-            if (lane == 0) T.state = ST_DONE;
-            state = ST_DONE;
+            return CMD_DONE;
         }
     }
-    if (state != ST_SUBTREE) return CMD_DONE;
-    __builtin_amdgcn_wave_barrier();
-    const double eps = T.dir * a.step;
-    double r = dl ? fma(0.5 * eps, T.g[lane], T.r[lane]) : 0.0;
+    const double eps = dir * a.step;
+    double r = dl ? fma(0.5 * eps, gs, rs) : 0.0;
     const double v = minv_apply(S, D, lane, r);
-    double x = dl ? fma(eps, v, T.x[lane]) : 0.0;
+    double x = dl ? fma(eps, v, xs) : 0.0;
     if (dl) boundary_lane(S, lane, x, r);
+    __builtin_amdgcn_wave_barrier();
     if (dl) { T.x[lane] = x; T.r[lane] = r; }
     if (lane == 0) T.eps = eps;
     if (TK == SMCGW_TARGET_GW) {
@@ -316,23 +346,32 @@ __device__ __noinline__ int pre_leaf(NutsShared& S, NutsState& T, const NutsArgs
     return CMD_EVAL;
 }
 
-// Second half of the leaf (wavefront 0): momentum half-step with the new
-// gradient, energy, divergence, progressive sampling, U-turn checks of the
-// nodes this leaf completes, and the merge when the subtree is complete.
-__device__ __noinline__ void post_leaf(NutsShared& S, NutsState& T, const NutsArgs& a, int p, int lane) {
+// Log prior and its gradient at the leaf in flight (used by the next `advance`).
+__device__ __noinline__ void prior_in_flight(NutsShared& S, NutsState& T, int D, int lane) {
+    const bool dl = lane < D;
+    double gp;
+    const double lpr = dim_sum(S, D, lane, dl ? log_prior_lane(S, lane, T.x[lane], gp) : 0.0);
+    if (dl) T.pgp[lane] = gp;
+    if (lane == 0) T.plp = lpr;
+}
+
+// Decisions for the finished leaf (wavefront 0): energy, divergence,
+// progressive sampling, U-turn checks of the nodes it completes, the merge
+// when its subtree is complete, and the set-up of the next doubling.  Sets
+// T.stop when the transition ends here.
+__device__ __noinline__ void bookkeep(NutsShared& S, NutsState& T, const NutsArgs& a, int p, int lane) {
+    if (T.first) {
+        __builtin_amdgcn_wave_barrier();
+        if (lane == 0) T.first = 0;
+        return;
+    }
     const int D = a.D;
     const bool dl = lane < D;
-    const int kk = dl ? lane : 0;
-    const double ll = T.ll_new;
-    const double gl = dl ? T.gl_new[lane] : 0.0;
-    const double x = dl ? T.x[lane] : 0.0;
-    double gp;
-    const double lpr = dim_sum(S, D, lane, dl ? log_prior_lane(S, kk, x, gp) : 0.0);
-    if (!dl) gp = 0.0;
-    const double lp = a.beta * ll + lpr;
-    const double g = a.beta * gl + gp;
-    const double eps = T.eps;
-    const double r = dl ? fma(0.5 * eps, g, T.r[lane]) : 0.0;
+    const double x = dl ? T.rec[0][lane] : 0.0;
+    const double r = dl ? T.rec[1][lane] : 0.0;
+    const double g = dl ? T.rec[2][lane] : 0.0;
+    const double gl = dl ? T.rec[3][lane] : 0.0;
+    const double ll = T.rec_ll, lp = T.rec_lp;
     const double v = minv_apply(S, D, lane, r);   // velocity of this leaf: energy and every U-turn check
     const int j = T.j, n = T.n;
     const double h0 = T.h0;
@@ -375,20 +414,21 @@ __device__ __noinline__ void post_leaf(NutsShared& S, NutsState& T, const NutsAr
                 }
         }
     }
-    int state = ST_SUBTREE, depth = T.depth, jn = j, nn = n;
-    double logw = T.logw, prop_ll = T.prop_ll;
+    int depth = T.depth, jn = j, nn = n, dir = T.dir, dir_next = T.dir_next;
+    double logw = T.logw, prop_ll = T.prop_ll, uacc = T.uacc, uacc_next = T.uacc_next;
+    bool stop = false;
     if (!ok) {
-        state = ST_DONE;
+        stop = true;
     } else if (n + 1 == T.nleaves) {
         depth = j + 1;
         __builtin_amdgcn_wave_barrier();
-        if (T.uacc < exp(sub_logw - logw)) {
+        if (uacc < exp(sub_logw - logw)) {
             if (dl) { S.prop[0][lane] = S.sprop[0][lane]; S.prop[1][lane] = S.sprop[1][lane]; }
             prop_ll = sprop_ll;
         }
         logw = log_add_exp(logw, sub_logw);
         const double rho = (dl ? T.rho[lane] : 0.0) + srho;
-        const int side = T.dir > 0 ? 1 : 0;
+        const int side = dir > 0 ? 1 : 0;
         if (dl) {
             double (*E)[MAXDIM] = side ? S.right : S.left;
             E[0][lane] = x; E[1][lane] = r; E[2][lane] = g; E[3][lane] = gl; E[4][lane] = v;
@@ -396,27 +436,33 @@ __device__ __noinline__ void post_leaf(NutsShared& S, NutsState& T, const NutsAr
         }
         if (lane == 0) { S.end_ll[side] = ll; S.end_lp[side] = lp; }
         __builtin_amdgcn_wave_barrier();
-        bool stop = false;
         if (a.uturn) {
             const double vl = dl ? S.left[4][lane] : 0.0, vr = dl ? S.right[4][lane] : 0.0;
             double sa, sb;
             dim_sum2(S, D, lane, rho * vl, rho * vr, sa, sb);
             stop = !(sa > 0.0 && sb > 0.0);
         }
-        if (stop) {
-            state = ST_DONE;
-        } else {
+        if (!stop && j + 1 >= T.md) stop = true;   // depth limit
+        if (!stop) {
+            // next doubling j + 1
             jn = j + 1;
-            state = ST_START;
+            nn = 0;
+            dir = dir_next;
+            uacc = uacc_next;
+            srho = 0.0;
+            sub_logw = -INFINITY;
+            if (jn + 1 < T.md) doubling_draw(a, p, jn + 1, dir_next, uacc_next);
         }
     } else {
         nn = n + 1;
     }
-    if (dl) { T.r[lane] = r; T.g[lane] = g; T.gl[lane] = gl; T.srho[lane] = srho; }
+    if (dl) T.srho[lane] = srho;
     __builtin_amdgcn_wave_barrier();
     if (lane == 0) {
-        T.ll = ll; T.lp = lp; T.acc_sum = acc_sum; T.sub_logw = sub_logw; T.sprop_ll = sprop_ll; T.leafc = leafc;
-        T.div = div; T.state = state; T.depth = depth; T.j = jn; T.n = nn; T.logw = logw; T.prop_ll = prop_ll;
+        T.acc_sum = acc_sum; T.sub_logw = sub_logw; T.sprop_ll = sprop_ll; T.leafc = leafc;
+        T.div = div; T.stop = stop ? 1 : 0; T.depth = depth; T.j = jn; T.n = nn; T.logw = logw; T.prop_ll = prop_ll;
+        T.dir = dir; T.dir_next = dir_next; T.uacc = uacc; T.uacc_next = uacc_next;
+        T.nleaves = 1 << jn;
         T.nlf = T.nlf + 1;
     }
 }
@@ -527,7 +573,7 @@ __global__ __launch_bounds__(WAVES * 64, (WAVES == 1 ? 2 : NUTS_WAVES_PER_SIMD))
         const int p = __builtin_amdgcn_readfirstlane(S.p);
         if (p >= a.P) break;
         // The particle's event descriptor is copied into LDS (all threads, ordered
-        // before its first use by the barrier that follows pre_leaf), so the
+        // before its first use by the barrier that follows advance), so the
         // leaf's serial phases read it without a round trip to the L2.
         const DevEvent* ev = &S.ev;
         if (TK == SMCGW_TARGET_GW) {
@@ -541,21 +587,31 @@ __global__ __launch_bounds__(WAVES * 64, (WAVES == 1 ? 2 : NUTS_WAVES_PER_SIMD))
         }
         if (wave == 0) start_transition(S, T, A, p, lane);
 
+        // Wavefronts of the leaf prologue: intrinsic and extrinsic parts on
+        // wavefronts 1 and 2 while wavefront 0 books the previous leaf (both on
+        // wavefront 1 when the slot has two).
+        constexpr int W_INTR = WAVES > 1 ? 1 : 0;
+        constexpr int W_EXTR = WAVES > 2 ? 2 : W_INTR;
         for (;;) {
             if (wave == 0) {
-                const int cmd = pre_leaf<TK>(S, T, A, p, lane);
+                const int cmd = advance<TK>(S, T, A, lane);
                 if (lane == 0) S.cmd = cmd;
             }
             __syncthreads();
-            if (__builtin_amdgcn_readfirstlane(S.cmd) == CMD_DONE) break;
+            const int cmd = __builtin_amdgcn_readfirstlane(S.cmd);
+            if (wave == 0) {
+                bookkeep(S, T, A, p, lane);
+                if (cmd == CMD_EVAL) prior_in_flight(S, T, D, lane);
+            }
+            if (TK == SMCGW_TARGET_GW && cmd == CMD_EVAL) {
+                if (wave == W_INTR && lane < 4) leaf_prep_intrinsic(ev, S, lane);
+                if (wave == W_EXTR && lane < MAXDET) leaf_prep_extrinsic(ev, S, lane);
+            }
+            __syncthreads();
+            if (cmd == CMD_DONE || __builtin_amdgcn_readfirstlane(T.stop)) break;
             if (a.priority) tree_priority(__builtin_amdgcn_readfirstlane(T.j));
 
             if (TK == SMCGW_TARGET_GW) {
-                // prologue: one intrinsic tangent direction per lane of wavefront 0,
-                // one detector per lane of wavefront 1
-                if (wave == 0 && lane < 4) leaf_prep_intrinsic(ev, S, lane);
-                if (wave == (WAVES > 1 ? 1 : 0) && lane < MAXDET) leaf_prep_extrinsic(ev, S, lane);
-                __syncthreads();
                 {
                     const BinCoef k = load_coef(S.cb);
                     double m[MOM_SIZE];
@@ -573,10 +629,6 @@ __global__ __launch_bounds__(WAVES * 64, (WAVES == 1 ? 2 : NUTS_WAVES_PER_SIMD))
                 const double ll = analytic_loglike<TK>(S, tgt, D, lane, lane < D ? T.x[lane] : 0.0, gl);
                 if (lane < D) T.gl_new[lane] = gl;
                 if (lane == 0) T.ll_new = ll;
-            }
-            if (wave == 0) {
-                __builtin_amdgcn_wave_barrier();
-                post_leaf(S, T, A, p, lane);
             }
         }
         if (a.priority) __builtin_amdgcn_s_setprio(0);
