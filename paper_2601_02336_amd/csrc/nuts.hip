@@ -63,6 +63,8 @@ struct NutsShared {
     double LT[MAXDIM * MAXDIM];                  // transpose of L
     double Minv[MAXDIM * MAXDIM];
     double vec[MAXDIM], red[2][MAXDIM];          // cross-lane exchange of wavefront 0
+    double pred[MAXDIM];                         // cross-lane exchange of the auxiliary wavefront
+    double utr[2][MAXD1][MAXDIM];                // U-turn dot-product terms of every level
     double cb[CB_SIZE];
     double mom[MAX_WAVES][MOM_SIZE];
     double th[NPAR];
@@ -83,11 +85,13 @@ static_assert(sizeof(DevEvent) % 8 == 0, "the event descriptor is copied in 8-by
 
 enum { CMD_EVAL = 0, CMD_DONE = 1 };
 
+// log(e^a + e^b) = m + log(e^{a-m} + e^{b-m}) with m = max(a, b); the term of
+// the larger argument is exp(0) = 1 exactly, so one exp suffices.
 __device__ __forceinline__ double log_add_exp(double a, double b) {
     if (a == -INFINITY) return b;
     if (b == -INFINITY) return a;
     const double m = fmax(a, b);
-    return m + log(exp(a - m) + exp(b - m));
+    return m + log(1.0 + exp(fmin(a, b) - m));
 }
 
 // Cross-lane operations of wavefront 0 over the coordinate lanes 0..D-1, done
@@ -98,14 +102,18 @@ __device__ __forceinline__ double log_add_exp(double a, double b) {
 // reads.
 
 // Sum over the coordinate lanes of v.
-__device__ __forceinline__ double dim_sum(NutsShared& S, int D, int lane, double v) {
-    if (lane < MAXDIM) S.red[0][lane] = (lane < D) ? v : 0.0;
+__device__ __forceinline__ double dim_sum_at(double* red, int D, int lane, double v) {
+    if (lane < MAXDIM) red[lane] = (lane < D) ? v : 0.0;
     __builtin_amdgcn_wave_barrier();
     double s = 0.0;
 #pragma unroll
-    for (int m = 0; m < MAXDIM; ++m) s += S.red[0][m];
+    for (int m = 0; m < MAXDIM; ++m) s += red[m];
     __builtin_amdgcn_wave_barrier();
     return s;
+}
+
+__device__ __forceinline__ double dim_sum(NutsShared& S, int D, int lane, double v) {
+    return dim_sum_at(S.red[0], D, lane, v);
 }
 
 // Two sums at once.
@@ -212,8 +220,9 @@ struct NutsState {
     double rec[4][MAXDIM];                               // finished leaf: x, r, g (grad log p_t), gl
     double pgp[MAXDIM];                                  // prior gradient at the leaf in flight
     double plp;                                          // log prior at the leaf in flight
+    double ul[2];                                        // leaf uniforms, by leaf index parity
     double h0, logw, sub_logw, uacc, uacc_next, acc_sum, eps, prop_ll, sprop_ll, ll_new, rec_ll, rec_lp;
-    int first, stop, j, n, nleaves, depth, nlf, div, dir, dir_next, md;
+    int first, stop, j, n, nleaves, depth, nlf, div, dir, dir_next, md, inflight;
     uint32_t leafc;
 };
 
@@ -330,6 +339,7 @@ __device__ __noinline__ int advance(NutsShared& S, NutsState& T, const NutsArgs&
             return CMD_DONE;
         }
     }
+    if (lane == 0) T.inflight = T.first ? 0 : T.nlf + 1;   // leaf index of the next leaf
     const double eps = dir * a.step;
     double r = dl ? fma(0.5 * eps, gs, rs) : 0.0;
     const double v = minv_apply(S, D, lane, r);
@@ -346,13 +356,20 @@ __device__ __noinline__ int advance(NutsShared& S, NutsState& T, const NutsArgs&
     return CMD_EVAL;
 }
 
-// Log prior and its gradient at the leaf in flight (used by the next `advance`).
-__device__ __noinline__ void prior_in_flight(NutsShared& S, NutsState& T, int D, int lane) {
+// Work on the leaf in flight that `bookkeep` does not wait for (run on an
+// otherwise idle wavefront): the log prior and its gradient at its position
+// (used by the next `advance`) and the uniform of its progressive sampling
+// step (leaf index = leaves booked before it, the Philox LEAF counter).
+__device__ __noinline__ void aux_in_flight(NutsShared& S, NutsState& T, const NutsArgs& a, int p, int lane) {
+    const int D = a.D;
     const bool dl = lane < D;
     double gp;
-    const double lpr = dim_sum(S, D, lane, dl ? log_prior_lane(S, lane, T.x[lane], gp) : 0.0);
+    const double lpr = dim_sum_at(S.pred, D, lane, dl ? log_prior_lane(S, lane, T.x[lane], gp) : 0.0);
     if (dl) T.pgp[lane] = gp;
-    if (lane == 0) T.plp = lpr;
+    const int idx = T.inflight;
+    double ul0, ul1;
+    rng_uniform2(a.seed, (uint32_t)idx, (uint32_t)p, a.iteration, RNG_LEAF, ul0, ul1);
+    if (lane == 0) { T.plp = lpr; T.ul[idx & 1] = ul0; }
 }
 
 // Decisions for the finished leaf (wavefront 0): energy, divergence,
@@ -393,25 +410,34 @@ __device__ __noinline__ void bookkeep(NutsShared& S, NutsState& T, const NutsArg
         srho += r;
         const double lw = -dh;
         const double nlw = log_add_exp(sub_logw, lw);
-        double ul0, ul1;
-        rng_uniform2(a.seed, leafc, (uint32_t)p, a.iteration, RNG_LEAF, ul0, ul1);
+        const double ul0 = T.ul[leafc & 1];   // drawn while this leaf was in flight
         ++leafc;
         if (ul0 < exp(lw - nlw)) {
             if (dl) { S.sprop[0][lane] = x; S.sprop[1][lane] = gl; }
             sprop_ll = ll;
         }
         sub_logw = nlw;
-        if (a.uturn) {
+        if (a.uturn && j > 0 && ((n + 1) & 1) == 0) {
+            // nodes completed by this leaf: level l covers leaves n+1-2^l .. n and
+            // needs rho.v_first > 0 and rho.v_last > 0.  All levels at once: the
+            // coordinate lanes write their terms, lane l sums level l in
+            // coordinate order.
             __builtin_amdgcn_wave_barrier();
-            for (int l = 1; l <= j && ok; ++l)
-                if (((n + 1) & ((1 << l) - 1)) == 0) {
-                    // node = leaves n+1-2^l .. n: rho.v_first > 0 and rho.v_last > 0
-                    const double nr = srho - (dl ? S.ck_rho[l][lane] : 0.0);
-                    const double v0 = dl ? S.ck_v[l][lane] : 0.0;
-                    double sa, sb;
-                    dim_sum2(S, D, lane, nr * v0, nr * v, sa, sb);
-                    if (!(sa > 0.0 && sb > 0.0)) ok = false;
+            if (dl)
+                for (int l = 1; l <= j; ++l) {
+                    const double nr = srho - S.ck_rho[l][lane];
+                    S.utr[0][l][lane] = nr * S.ck_v[l][lane];
+                    S.utr[1][l][lane] = nr * v;
                 }
+            __builtin_amdgcn_wave_barrier();
+            bool fail = false;
+            if (lane >= 1 && lane <= j && ((n + 1) & ((1 << lane) - 1)) == 0) {
+                double sa = 0.0, sb = 0.0;
+                for (int m = 0; m < D; ++m) { sa += S.utr[0][lane][m]; sb += S.utr[1][lane][m]; }
+                fail = !(sa > 0.0 && sb > 0.0);
+            }
+            if (__ballot(fail) != 0) ok = false;
+            __builtin_amdgcn_wave_barrier();
         }
     }
     int depth = T.depth, jn = j, nn = n, dir = T.dir, dir_next = T.dir_next;
@@ -592,6 +618,7 @@ __global__ __launch_bounds__(WAVES * 64, (WAVES == 1 ? 2 : NUTS_WAVES_PER_SIMD))
         // wavefront 1 when the slot has two).
         constexpr int W_INTR = WAVES > 1 ? 1 : 0;
         constexpr int W_EXTR = WAVES > 2 ? 2 : W_INTR;
+        constexpr int W_AUX = WAVES > 3 ? 3 : 0;
         for (;;) {
             if (wave == 0) {
                 const int cmd = advance<TK>(S, T, A, lane);
@@ -599,10 +626,8 @@ __global__ __launch_bounds__(WAVES * 64, (WAVES == 1 ? 2 : NUTS_WAVES_PER_SIMD))
             }
             __syncthreads();
             const int cmd = __builtin_amdgcn_readfirstlane(S.cmd);
-            if (wave == 0) {
-                bookkeep(S, T, A, p, lane);
-                if (cmd == CMD_EVAL) prior_in_flight(S, T, D, lane);
-            }
+            if (wave == 0) bookkeep(S, T, A, p, lane);
+            if (wave == W_AUX && cmd == CMD_EVAL) aux_in_flight(S, T, A, p, lane);
             if (TK == SMCGW_TARGET_GW && cmd == CMD_EVAL) {
                 if (wave == W_INTR && lane < 4) leaf_prep_intrinsic(ev, S, lane);
                 if (wave == W_EXTR && lane < MAXDET) leaf_prep_extrinsic(ev, S, lane);
