@@ -44,8 +44,8 @@ __device__ __forceinline__ BinCoef load_coef(const double* cb) {
 #pragma unroll
     for (int d = 0; d < MAXDET; ++d) {
         k.tau[d] = uniform_d(cb[CB_TAU + d]);
-        k.pr[d] = uniform_d(cb[CB_PR + d]);
-        k.pi[d] = uniform_d(cb[CB_PI + d]);
+        k.pr[d] = uniform_d(cb[CB_PR + d] * cb[CB_AMP]);
+        k.pi[d] = uniform_d(cb[CB_PI + d] * cb[CB_AMP]);
     }
     return k;
 }
@@ -255,10 +255,11 @@ __device__ __forceinline__ double finish_particle(const DevEvent& ev, const doub
                                                   double g[NPAR]) {
     double ll = -0.5 * ev.dd;
     double dlnca = 0.0, sum_t = 0.0;
+    const double amp = c[CB_AMP];          // P'_d = amp P_d
     double gp[4] = {0.0, 0.0, 0.0, 0.0};   // iota, psi, ra, dec through P'_d
     for (int k = 0; k < NPAR; ++k) g[k] = 0.0;
     for (int d = 0; d < ev.n_det; ++d) {
-        const double pr = c[CB_PR + d], pi = c[CB_PI + d];
+        const double pr = c[CB_PR + d] * amp, pi = c[CB_PI + d] * amp;
         const double zr = m[MOM_ZR + d], zi = m[MOM_ZI + d], h = ev.hnorm[d];
         const double re = pr * zr - pi * zi;
         const double p2 = pr * pr + pi * pi;
@@ -266,7 +267,7 @@ __device__ __forceinline__ double finish_particle(const DevEvent& ev, const doub
         dlnca += re - p2 * h;
         const double ar = zr - h * pr, ai = -zi - h * pi;   // dlogL / d(Re P', Im P')
 #pragma unroll
-        for (int k = 0; k < 4; ++k) gp[k] += ar * c[CB_DPR + 4 * d + k] + ai * c[CB_DPI + 4 * d + k];
+        for (int k = 0; k < 4; ++k) gp[k] += amp * (ar * c[CB_DPR + 4 * d + k] + ai * c[CB_DPI + 4 * d + k]);
         const double t = m[MOM_T + d];
         sum_t += t;
         g[P_RA] += TWO_PI * t * c[CB_DTAU + 2 * d];

@@ -159,75 +159,112 @@ __device__ __forceinline__ void prep_intrinsic(const DevEvent& ev, const double 
 // their Jacobians (zeros for d >= n_det).
 // F+ = A cos 2psi + B sin 2psi, Fx = B cos 2psi - A sin 2psi with
 // A = p.Dp - q.Dq, B = 2 p.Dq for the polarisation frame (p, q) at psi = 0.
-__device__ __forceinline__ void prep_extrinsic_det(const DevEvent& ev, const double th[NPAR], double* cb, int d) {
-    if (d >= ev.n_det) {
-        cb[CB_TAU + d] = 0.0; cb[CB_PR + d] = 0.0; cb[CB_PI + d] = 0.0;
-        for (int k = 0; k < 2; ++k) cb[CB_DTAU + 2 * d + k] = 0.0;
-        for (int k = 0; k < 4; ++k) { cb[CB_DPR + 4 * d + k] = 0.0; cb[CB_DPI + 4 * d + k] = 0.0; }
-        return;
-    }
-    typedef Dv<2> D2;
-    const D2 phi = dvar<2>(th[P_RA] - ev.gmst, 0);
-    const D2 dec = dvar<2>(th[P_DEC], 1);
-    double sp, cp, sd, cd;
-    sincos(phi.v, &sp, &cp);
-    sincos(dec.v, &sd, &cd);
-    const D2 sphi = scale_chain(phi, sp, cp), cphi = scale_chain(phi, cp, -sp);
-    const D2 sdec = scale_chain(dec, sd, cd), cdec = scale_chain(dec, cd, -sd);
-    const D2 pv[3] = {sphi, dconst<2>(0.0) - cphi, dconst<2>(0.0)};
-    const D2 qv[3] = {dconst<2>(0.0) - cphi * sdec, dconst<2>(0.0) - sphi * sdec, cdec};
-    const D2 nv[3] = {cdec * cphi, cdec * sphi, sdec};
-    double s2, c2;
-    sincos(2.0 * th[P_PSI], &s2, &c2);
-    double si, ci;
-    sincos(th[P_IOTA], &si, &ci);
-    const double pp = 0.5 * (1.0 + ci * ci);
+// The extrinsic transcendentals shared by all detectors: sin / cos of
+// ra - gmst, dec, 2 psi and iota.
+struct ExtAngles {
+    double sc[4][2];   // (sin, cos) of ra - gmst, dec, 2 psi, iota
+};
+enum { ANG_PHI = 0, ANG_DEC = 1, ANG_PSI2 = 2, ANG_IOTA = 3, ANG_COUNT = 4 };
+
+__device__ __forceinline__ double extrinsic_angle(const DevEvent& ev, const double th[NPAR], int k) {
+    return k == ANG_PHI ? th[P_RA] - ev.gmst : k == ANG_DEC ? th[P_DEC] : k == ANG_PSI2 ? 2.0 * th[P_PSI] : th[P_IOTA];
+}
+
+__device__ __forceinline__ double extrinsic_amplitude(const DevEvent& ev, const double th[NPAR]) {
     const double camp = 0.45643546458763842789 /* sqrt(5/24) */ * 0.46619407703541166 /* pi^-2/3 */
                       * exp((5.0 / 6.0) * log(th[P_MC] * ev.t_sun)) * ev.c_light / (th[P_DL] * ev.mpc_m);
-    const double S = camp * ev.u_scale;
-    D2 Dp[3], Dq[3];
+    return camp * ev.u_scale;
+}
+
+__device__ __forceinline__ ExtAngles extrinsic_angles(const DevEvent& ev, const double th[NPAR]) {
+    ExtAngles a;
+#pragma unroll
+    for (int k = 0; k < ANG_COUNT; ++k) sincos(extrinsic_angle(ev, th, k), &a.sc[k][0], &a.sc[k][1]);
+    return a;
+}
+
+// Detector d's delay, complex projection P_d (without the amplitude, which
+// prep_extrinsic_common writes once) and their Jacobians from the shared
+// transcendentals (zeros for d >= n_det).  The (ra, dec)
+// derivatives are carried as N tangents starting at k0 (N = 2, k0 = 0: both);
+// values and the iota / psi derivatives are written when write_values.
+template <int N>
+__device__ __forceinline__ void prep_extrinsic_det_n(const DevEvent& ev, const double th[NPAR], const ExtAngles& ang,
+                                                     double* cb, int d, int k0, bool write_values) {
+    if (d >= ev.n_det) {
+        if (write_values) {
+            cb[CB_TAU + d] = 0.0; cb[CB_PR + d] = 0.0; cb[CB_PI + d] = 0.0;
+            for (int k = 0; k < 2; ++k) { cb[CB_DPR + 4 * d + k] = 0.0; cb[CB_DPI + 4 * d + k] = 0.0; }
+        }
+#pragma unroll
+        for (int t = 0; t < N; ++t) {
+            cb[CB_DTAU + 2 * d + k0 + t] = 0.0;
+            cb[CB_DPR + 4 * d + 2 + k0 + t] = 0.0;
+            cb[CB_DPI + 4 * d + 2 + k0 + t] = 0.0;
+        }
+        return;
+    }
+    typedef Dv<N> DN;
+    const DN phi = seed<N>(th[P_RA] - ev.gmst, 0, k0);
+    const DN dec = seed<N>(th[P_DEC], 1, k0);
+    const double sp = ang.sc[ANG_PHI][0], cp = ang.sc[ANG_PHI][1];
+    const double sd = ang.sc[ANG_DEC][0], cd = ang.sc[ANG_DEC][1];
+    const DN sphi = scale_chain(phi, sp, cp), cphi = scale_chain(phi, cp, -sp);
+    const DN sdec = scale_chain(dec, sd, cd), cdec = scale_chain(dec, cd, -sd);
+    const DN pv[3] = {sphi, dconst<N>(0.0) - cphi, dconst<N>(0.0)};
+    const DN qv[3] = {dconst<N>(0.0) - cphi * sdec, dconst<N>(0.0) - sphi * sdec, cdec};
+    const DN nv[3] = {cdec * cphi, cdec * sphi, sdec};
+    const double s2 = ang.sc[ANG_PSI2][0], c2 = ang.sc[ANG_PSI2][1];
+    const double si = ang.sc[ANG_IOTA][0], ci = ang.sc[ANG_IOTA][1];
+    const double pp = 0.5 * (1.0 + ci * ci);
+    DN Dp[3], Dq[3];
     for (int i = 0; i < 3; ++i) {
-        Dp[i] = dconst<2>(0.0);
-        Dq[i] = dconst<2>(0.0);
+        Dp[i] = dconst<N>(0.0);
+        Dq[i] = dconst<N>(0.0);
         for (int j = 0; j < 3; ++j) {
             Dp[i] = Dp[i] + ev.resp[d][i][j] * pv[j];
             Dq[i] = Dq[i] + ev.resp[d][i][j] * qv[j];
         }
     }
-    D2 A = dconst<2>(0.0), B = dconst<2>(0.0), nr = dconst<2>(0.0);
+    DN A = dconst<N>(0.0), B = dconst<N>(0.0), nr = dconst<N>(0.0);
     for (int i = 0; i < 3; ++i) {
         A = A + (pv[i] * Dp[i] - qv[i] * Dq[i]);
         B = B + 2.0 * (pv[i] * Dq[i]);
         nr = nr + ev.pos[d][i] * nv[i];
     }
-    const D2 fp = c2 * A + s2 * B;
-    const D2 fx = c2 * B - s2 * A;
-    const D2 dt = (-1.0 / ev.c_light) * nr;
-    cb[CB_TAU + d] = th[P_TC] + dt.v;
-    cb[CB_DTAU + 2 * d + 0] = dt.d[0];
-    cb[CB_DTAU + 2 * d + 1] = dt.d[1];
-    // P = F+ (1 + cos^2 i)/2 - i Fx cos i
-    cb[CB_PR + d] = S * pp * fp.v;
-    cb[CB_PI + d] = -S * ci * fx.v;
-    cb[CB_DPR + 4 * d + 0] = -S * ci * si * fp.v;            // iota
-    cb[CB_DPI + 4 * d + 0] = S * si * fx.v;
-    cb[CB_DPR + 4 * d + 1] = S * pp * 2.0 * fx.v;            // psi: dF+/dpsi = 2 Fx
-    cb[CB_DPI + 4 * d + 1] = S * ci * 2.0 * fp.v;            //      dFx/dpsi = -2 F+
-    cb[CB_DPR + 4 * d + 2] = S * pp * fp.d[0];               // ra
-    cb[CB_DPI + 4 * d + 2] = -S * ci * fx.d[0];
-    cb[CB_DPR + 4 * d + 3] = S * pp * fp.d[1];               // dec
-    cb[CB_DPI + 4 * d + 3] = -S * ci * fx.d[1];
+    const DN fp = c2 * A + s2 * B;
+    const DN fx = c2 * B - s2 * A;
+    const DN dt = (-1.0 / ev.c_light) * nr;
+    if (write_values) {
+        cb[CB_TAU + d] = th[P_TC] + dt.v;
+        // P = F+ (1 + cos^2 i)/2 - i Fx cos i
+        cb[CB_PR + d] = pp * fp.v;
+        cb[CB_PI + d] = -ci * fx.v;
+        cb[CB_DPR + 4 * d + 0] = -ci * si * fp.v;            // iota
+        cb[CB_DPI + 4 * d + 0] = si * fx.v;
+        cb[CB_DPR + 4 * d + 1] = pp * 2.0 * fx.v;            // psi: dF+/dpsi = 2 Fx
+        cb[CB_DPI + 4 * d + 1] = ci * 2.0 * fp.v;            //      dFx/dpsi = -2 F+
+    }
+#pragma unroll
+    for (int t = 0; t < N; ++t) {                             // ra (k = 0), dec (k = 1)
+        cb[CB_DTAU + 2 * d + k0 + t] = dt.d[t];
+        cb[CB_DPR + 4 * d + 2 + k0 + t] = pp * fp.d[t];
+        cb[CB_DPI + 4 * d + 2 + k0 + t] = -ci * fx.d[t];
+    }
 }
 
-// Entries shared by all detectors: derivatives of ln C_A.
-__device__ __forceinline__ void prep_extrinsic_common(const double th[NPAR], double* cb) {
+// Entries shared by all detectors: the amplitude C_A u_scale and the
+// derivatives of ln C_A.
+__device__ __forceinline__ void prep_extrinsic_common(const DevEvent& ev, const double th[NPAR], double* cb) {
+    cb[CB_AMP] = extrinsic_amplitude(ev, th);
     cb[CB_DLNCA_MC] = (5.0 / 6.0) / th[P_MC];
     cb[CB_DLNCA_DL] = -1.0 / th[P_DL];
 }
 
 __device__ __forceinline__ void prep_extrinsic(const DevEvent& ev, const double th[NPAR], double* cb) {
-    prep_extrinsic_common(th, cb);
-    for (int d = 0; d < MAXDET; ++d) prep_extrinsic_det(ev, th, cb, d);
+    prep_extrinsic_common(ev, th, cb);
+    const ExtAngles ang = extrinsic_angles(ev, th);
+    for (int d = 0; d < MAXDET; ++d) prep_extrinsic_det_n<2>(ev, th, ang, cb, d, 0, true);
 }
 
 __device__ __forceinline__ void expand_params(const ParamMap& pm, const double* x, double th[NPAR]) {

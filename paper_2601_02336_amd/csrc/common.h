@@ -105,18 +105,19 @@ struct ParamMap {
 enum {
     CB_C = 0,                            // NCOEF phase coefficients (cycles): const, then basis rows
     CB_TAU = CB_C + NCOEF,               // MAXDET: t_c + delay of each detector
-    CB_PR = CB_TAU + MAXDET,             // MAXDET: Re of C_A u_scale P_d
-    CB_PI = CB_PR + MAXDET,              // MAXDET: Im of C_A u_scale P_d
+    CB_PR = CB_TAU + MAXDET,             // MAXDET: Re P_d (times CB_AMP in use)
+    CB_PI = CB_PR + MAXDET,              // MAXDET: Im P_d
     CB_BINS = CB_PI + MAXDET,
     CB_DC = CB_BINS,                     // [NCOEF][4]: d c_b / d(Mc, q, chi1, chi2)
     CB_DTAU = CB_DC + 4 * NCOEF,         // [MAXDET][2]: d tau_d / d(ra, dec)
-    CB_DPR = CB_DTAU + 2 * MAXDET,       // [MAXDET][4]: d Re P'_d / d(iota, psi, ra, dec)
-    CB_DPI = CB_DPR + 4 * MAXDET,        // [MAXDET][4]: d Im P'_d / d(iota, psi, ra, dec)
+    CB_DPR = CB_DTAU + 2 * MAXDET,       // [MAXDET][4]: d Re P_d / d(iota, psi, ra, dec)
+    CB_DPI = CB_DPR + 4 * MAXDET,        // [MAXDET][4]: d Im P_d / d(iota, psi, ra, dec)
     CB_DLNCA_MC = CB_DPI + 4 * MAXDET,   // d ln C_A / d Mc
     CB_DLNCA_DL = CB_DLNCA_MC + 1,       // d ln C_A / d d_L
+    CB_AMP = CB_DLNCA_DL + 1,            // C_A u_scale: the projection P'_d = CB_AMP P_d
     CB_SIZE = 104
 };
-static_assert(CB_DLNCA_DL < CB_SIZE, "coefficient block overflow");
+static_assert(CB_AMP < CB_SIZE, "coefficient block overflow");
 
 // Per-particle bin moments written by the bin loop (FP64).
 enum {

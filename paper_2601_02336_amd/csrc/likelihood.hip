@@ -97,7 +97,7 @@ __global__ __launch_bounds__(256) void waveform_kernel(const DevEvent* __restric
     basis_rows(f, ev.fwl[(size_t)ROW_W * ev.n_pad + j], ev.fwl[(size_t)ROW_LN * ev.n_pad + j], B);
     double ph = c[CB_C];
     for (int b = 0; b < NBASIS; ++b) ph = fma(c[CB_C + 1 + b], B[b], ph);
-    const double a = pow(f, -7.0 / 6.0) / ev.u_scale;
+    const double a = pow(f, -7.0 / 6.0) / ev.u_scale * c[CB_AMP];
     for (int d = 0; d < n_det; ++d) {
         const double phd = fma(f, c[CB_TAU + d], ph);
         const double x = phd - rint(phd);

@@ -64,6 +64,7 @@ struct NutsShared {
     double Minv[MAXDIM * MAXDIM];
     double vec[MAXDIM], red[2][MAXDIM];          // cross-lane exchange of wavefront 0
     double pred[MAXDIM];                         // cross-lane exchange of the auxiliary wavefront
+    ExtAngles ang;                               // extrinsic transcendentals of the leaf in flight
     double utr[2][MAXD1][MAXDIM];                // U-turn dot-product terms of every level
     double cb[CB_SIZE];
     double mom[MAX_WAVES][MOM_SIZE];
@@ -357,10 +358,14 @@ __device__ __noinline__ int advance(NutsShared& S, NutsState& T, const NutsArgs&
 }
 
 // Work on the leaf in flight that `bookkeep` does not wait for (run on an
-// otherwise idle wavefront): the log prior and its gradient at its position
-// (used by the next `advance`) and the uniform of its progressive sampling
-// step (leaf index = leaves booked before it, the Philox LEAF counter).
-__device__ __noinline__ void aux_in_flight(NutsShared& S, NutsState& T, const NutsArgs& a, int p, int lane) {
+// otherwise idle wavefront): its amplitude entries of the coefficient block,
+// the log prior and its gradient at its position (used by the next
+// `advance`) and the uniform of its progressive sampling step (leaf index =
+// leaves booked before it, the Philox LEAF counter).
+template <int TK>
+__device__ __noinline__ void aux_in_flight(const DevEvent* ev, NutsShared& S, NutsState& T, const NutsArgs& a, int p,
+                                           int lane) {
+    if (TK == SMCGW_TARGET_GW && lane == 0) prep_extrinsic_common(*ev, S.th, S.cb);
     const int D = a.D;
     const bool dl = lane < D;
     double gp;
@@ -525,9 +530,25 @@ __device__ __noinline__ void leaf_prep_intrinsic(const DevEvent* ev, NutsShared&
     prep_intrinsic_n<1>(*ev, S.th, S.cb, lane, lane == 0);
 }
 
+// Extrinsic prologue on one wavefront: lanes 0-3 take one sin / cos each (in
+// parallel), then lane d (d < MAXDET) builds detector d with its ra
+// derivatives and lane MAXDET + d the dec derivatives of the same detector
+// (one tangent per lane keeps each lane's chain short).  The amplitude is
+// computed on the auxiliary wavefront.
 __device__ __noinline__ void leaf_prep_extrinsic(const DevEvent* ev, NutsShared& S, int lane) {
-    if (lane == 0) prep_extrinsic_common(S.th, S.cb);
-    prep_extrinsic_det(*ev, S.th, S.cb, lane);
+    if (lane < ANG_COUNT) {
+        double sn, cs;
+        sincos(extrinsic_angle(*ev, S.th, lane), &sn, &cs);
+        S.ang.sc[lane][0] = sn;
+        S.ang.sc[lane][1] = cs;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (lane < 2 * MAXDET) {
+        const ExtAngles ang = S.ang;
+        const int k = lane / MAXDET;
+        prep_extrinsic_det_n<1>(*ev, S.th, ang, S.cb, lane - k * MAXDET, k, k == 0);
+    }
 }
 
 // Epilogue of one leaf (wavefront 0): sum the wavefronts' moments, logL and
@@ -627,10 +648,10 @@ __global__ __launch_bounds__(WAVES * 64, (WAVES == 1 ? 2 : NUTS_WAVES_PER_SIMD))
             __syncthreads();
             const int cmd = __builtin_amdgcn_readfirstlane(S.cmd);
             if (wave == 0) bookkeep(S, T, A, p, lane);
-            if (wave == W_AUX && cmd == CMD_EVAL) aux_in_flight(S, T, A, p, lane);
+            if (wave == W_AUX && cmd == CMD_EVAL) aux_in_flight<TK>(ev, S, T, A, p, lane);
             if (TK == SMCGW_TARGET_GW && cmd == CMD_EVAL) {
                 if (wave == W_INTR && lane < 4) leaf_prep_intrinsic(ev, S, lane);
-                if (wave == W_EXTR && lane < MAXDET) leaf_prep_extrinsic(ev, S, lane);
+                if (wave == W_EXTR && lane < 8) leaf_prep_extrinsic(ev, S, lane);
             }
             __syncthreads();
             if (cmd == CMD_DONE || __builtin_amdgcn_readfirstlane(T.stop)) break;
