@@ -223,7 +223,7 @@ def main():
     ap.add_argument("--no-hint", action="store_true", help="start particles in index order (no work hint)")
     ap.add_argument("--priority", type=int, choices=[0, 1], default=1,
                     help="depth-driven wavefront priority in the NUTS kernel")
-    ap.add_argument("--waves", type=int, choices=[0, 2, 4, 8], default=0, help="wavefronts per NUTS slot")
+    ap.add_argument("--waves", type=int, choices=[0, 2, 4, 6, 8], default=0, help="wavefronts per NUTS slot")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 256 MiB device copy (reference dispatch for memory-traffic counters)")
     args = ap.parse_args()

@@ -135,7 +135,7 @@ extern "C" int smcgw_set_option(smcgw_ctx* c, int option, int64_t value) {
     if (!c) return SMCGW_ERR_INVALID;
     switch (option) {
     case SMCGW_OPT_NUTS_WAVES:
-        if (value != 0 && value != 2 && value != 4 && value != 8) return SMCGW_ERR_INVALID;
+        if (value != 0 && value != 2 && value != 4 && value != 6 && value != 8) return SMCGW_ERR_INVALID;
         c->nuts_waves = (int)value;
         return SMCGW_OK;
     case SMCGW_OPT_NUTS_PRIORITY:

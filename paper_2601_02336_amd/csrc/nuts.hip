@@ -222,8 +222,10 @@ struct NutsState {
     double pgp[MAXDIM];                                  // prior gradient at the leaf in flight
     double plp;                                          // log prior at the leaf in flight
     double ul[2];                                        // leaf uniforms, by leaf index parity
-    double h0, logw, sub_logw, uacc, uacc_next, acc_sum, eps, prop_ll, sprop_ll, ll_new, rec_ll, rec_lp;
-    int first, stop, j, n, nleaves, depth, nlf, div, dir, dir_next, md, inflight;
+    double dtab_u[MAXD1];                                // merge uniform of each doubling
+    int dtab_dir[MAXD1];                                 // direction of each doubling
+    double h0, logw, sub_logw, uacc, acc_sum, eps, prop_ll, sprop_ll, ll_new, rec_ll, rec_lp;
+    int first, stop, j, n, nleaves, depth, nlf, div, dir, md, inflight;
     uint32_t leafc;
 };
 
@@ -270,10 +272,18 @@ __device__ __noinline__ void start_transition(NutsShared& S, NutsState& T, const
         T.srho[lane] = 0.0;
     }
     const int md = a.md_per_p ? min(a.md_per_p[p], SMCGW_MAX_DEPTH) : a.max_depth;
-    int dir0 = 1, dir1 = 1;
-    double ua0 = 0.0, ua1 = 0.0;
-    if (md > 0) doubling_draw(a, p, 0, dir0, ua0);
-    if (md > 1) doubling_draw(a, p, 1, dir1, ua1);
+    // every doubling's draws at once, one per lane
+    if (lane < md) {
+        int dj;
+        double uj;
+        doubling_draw(a, p, lane, dj, uj);
+        T.dtab_dir[lane] = dj;
+        T.dtab_u[lane] = uj;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const int dir0 = md > 0 ? T.dtab_dir[0] : 1;
+    const double ua0 = md > 0 ? T.dtab_u[0] : 0.0;
     if (lane == 0) {
         S.end_ll[0] = S.end_ll[1] = ll;
         S.end_lp[0] = S.end_lp[1] = lp;
@@ -294,8 +304,6 @@ __device__ __noinline__ void start_transition(NutsShared& S, NutsState& T, const
         T.md = md;
         T.dir = dir0;
         T.uacc = ua0;
-        T.dir_next = dir1;
-        T.uacc_next = ua1;
     }
 }
 
@@ -329,7 +337,7 @@ __device__ __noinline__ int advance(NutsShared& S, NutsState& T, const NutsArgs&
             xs = x; rs = r; gs = g;
             dir = T.dir;
         } else if (T.j + 1 < T.md) {
-            dir = T.dir_next;
+            dir = T.dtab_dir[T.j + 1];
             if (dir == T.dir) {
                 xs = x; rs = r; gs = g;
             } else {
@@ -445,8 +453,8 @@ __device__ __noinline__ void bookkeep(NutsShared& S, NutsState& T, const NutsArg
             __builtin_amdgcn_wave_barrier();
         }
     }
-    int depth = T.depth, jn = j, nn = n, dir = T.dir, dir_next = T.dir_next;
-    double logw = T.logw, prop_ll = T.prop_ll, uacc = T.uacc, uacc_next = T.uacc_next;
+    int depth = T.depth, jn = j, nn = n, dir = T.dir;
+    double logw = T.logw, prop_ll = T.prop_ll, uacc = T.uacc;
     bool stop = false;
     if (!ok) {
         stop = true;
@@ -478,11 +486,10 @@ __device__ __noinline__ void bookkeep(NutsShared& S, NutsState& T, const NutsArg
             // next doubling j + 1
             jn = j + 1;
             nn = 0;
-            dir = dir_next;
-            uacc = uacc_next;
+            dir = T.dtab_dir[jn];
+            uacc = T.dtab_u[jn];
             srho = 0.0;
             sub_logw = -INFINITY;
-            if (jn + 1 < T.md) doubling_draw(a, p, jn + 1, dir_next, uacc_next);
         }
     } else {
         nn = n + 1;
@@ -492,7 +499,7 @@ __device__ __noinline__ void bookkeep(NutsShared& S, NutsState& T, const NutsArg
     if (lane == 0) {
         T.acc_sum = acc_sum; T.sub_logw = sub_logw; T.sprop_ll = sprop_ll; T.leafc = leafc;
         T.div = div; T.stop = stop ? 1 : 0; T.depth = depth; T.j = jn; T.n = nn; T.logw = logw; T.prop_ll = prop_ll;
-        T.dir = dir; T.dir_next = dir_next; T.uacc = uacc; T.uacc_next = uacc_next;
+        T.dir = dir; T.uacc = uacc;
         T.nleaves = 1 << jn;
         T.nlf = T.nlf + 1;
     }
@@ -785,6 +792,7 @@ int launch_gw(smcgw_ctx* c, int precision, const NutsArgs& a, const PriorDesc& p
               const TargetDesc& t) {
     switch (c->nuts_waves) {
     case 2: return launch_gw_w<NDET, 2>(c, precision, a, pri, pm, t);
+    case 6: return launch_gw_w<NDET, 6>(c, precision, a, pri, pm, t);
     case 8: return launch_gw_w<NDET, 8>(c, precision, a, pri, pm, t);
     default: return launch_gw_w<NDET, 4>(c, precision, a, pri, pm, t);
     }
