@@ -47,6 +47,43 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_nuts_smc_3det_8033bins_2048p.txt")
+
+
+def kernel_source_hash():
+    """SHA-256 over the sources the HIP library is built from (and its build flags)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_2601_02336_amd", "csrc", "*.hip")) +
+                   glob.glob(os.path.join(ROOT, "paper_2601_02336_amd", "csrc", "*.h"))) + \
+        [os.path.join(ROOT, "include", "smcgw.h"), os.path.join(ROOT, "paper_2601_02336_amd", "build.py")]
+    for path in files:
+        h.update(os.path.basename(path).encode())
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def default_smc_workload(args, P):
+    """The counters were taken on the default SMC bench run only."""
+    return (P == 2048 and args.steps == 8 and args.warmup == 2 and args.alpha == 0.95 and args.step == 0.5
+            and args.max_depth == 10 and args.seed == 1 and not args.no_hint and args.priority == 1)
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch from the committed counter summary, or None when it was taken on other
+    kernel sources (or for another kernel)."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            kv = dict(line.strip().split("=", 1) for line in f if "=" in line and not line.startswith("#"))
+    except OSError:
+        return None
+    if kv.get("kernel") != kernel or kv.get("source_sha256") != kernel_source_hash():
+        return None
+    return int(kv["traffic_bytes_per_launch"])
+
+
 def build_event(smcgw, synth, spec=None):
     """Seeded injection built with the HIP library itself (waveform + <h|h>)."""
 
@@ -252,10 +289,11 @@ def main():
         achieved = ops * ev.n * evals / kernel_s / 1e12
         log(f"smc {args.precision}: {evals} evals in {dt:.3f} s -> {value:.4g} evals/s; nuts kernel "
             f"{k_ms / max(k_n, 1):.2f} ms x {k_n}; betas {betas}")
+        kname = f"nuts_kernel<3,{'MIXED' if prec == smcgw.MIXED else 'PLAIN_FP64'},GW,{args.waves or 4}>"
         roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TLANEOPS, 3),
-                    "unit": "Tlane-op/s", "frac": round(achieved / VALU_PEAK_TLANEOPS, 4), "traffic": None,
-                    "kernel": f"nuts_kernel<3,{'MIXED' if prec == smcgw.MIXED else 'PLAIN_FP64'},GW,{args.waves or 4}>",
-                    "kernel_ms": round(k_ms / max(k_n, 1), 3), "ops_per_particle_bin": ops,
+                    "unit": "Tlane-op/s", "frac": round(achieved / VALU_PEAK_TLANEOPS, 4),
+                    "traffic": measured_traffic(kname) if default_smc_workload(args, P) else None,
+                    "kernel": kname, "kernel_ms": round(k_ms / max(k_n, 1), 3), "ops_per_particle_bin": ops,
                     "evals_in_kernel": evals}
         extra["betas"] = [round(b, 8) for b in betas]
         extra["depth_histograms"] = hist
