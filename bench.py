@@ -154,6 +154,13 @@ def run_batch(smcgw, synth, args):
     L = (L * 0.05).contiguous()
     bins = torch.tensor([e.n for e in evs], dtype=torch.int64, device="cuda")[eop.long()]
 
+    tuned = None
+    if args.waves == 0:
+        # slot width picked by the library's autotuner on this batch (depth-5 trees, inputs untouched)
+        tuned = ctx.autotune_nuts(x, logl, grad, L, step=0.2, beta=0.005, seed=3, iteration=10 ** 6, max_depth=5,
+                                  uturn=False, precision=prec, trials=2)
+        log(f"autotuned NUTS slot width {tuned[0]} (median ms by width {tuned[1]})")
+
     def step(i, uturn):
         return ctx.nuts_step(x, logl, grad, L, step=0.2, beta=0.005, seed=3, iteration=i, max_depth=10,
                              max_depth_per_particle=None if uturn else md, uturn=uturn, precision=prec)
@@ -186,7 +193,7 @@ def run_batch(smcgw, synth, args):
         nat += int(step(1000 + i, True)["n_leapfrog"].sum().item())
     dt_nat = time.perf_counter() - t1
     return dict(P=P, evals=n_ev, bin_evals=n_be, dt=dt, k_ms=k_ms, k_n=k_n, nat_rate=nat / dt_nat,
-                bins=[e.n for e in evs], divergent_warmup=div)
+                bins=[e.n for e in evs], divergent_warmup=div, tuned=tuned)
 
 
 def smc_setup(smcgw, synth, ev, P, seed=7):
@@ -321,13 +328,17 @@ def main():
             f"{value:.4g} evals/s; nuts kernel {r['k_ms'] / max(r['k_n'], 1):.2f} ms x {r['k_n']}")
         roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TLANEOPS, 3),
                     "unit": "Tlane-op/s", "frac": round(achieved / VALU_PEAK_TLANEOPS, 4), "traffic": None,
-                    "kernel": f"nuts_kernel<3,{'MIXED' if prec == smcgw.MIXED else 'PLAIN_FP64'},GW,{args.waves or 4}>",
+                    "kernel": f"nuts_kernel<3,{'MIXED' if prec == smcgw.MIXED else 'PLAIN_FP64'},GW,"
+                              f"{args.waves or (r['tuned'][0] if r['tuned'] else 4)}>",
                     "kernel_ms": round(r["k_ms"] / max(r["k_n"], 1), 3), "ops_per_particle_bin": ops,
                     "evals_in_kernel": r["evals"]}
         extra["particle_bins_per_s"] = round(r["bin_evals"] / r["dt"], 1)
         extra["natural_uturn_evals_per_s"] = round(r["nat_rate"], 1)
         extra["event_bins"] = r["bins"]
         extra["divergent_in_warmup_step"] = r["divergent_warmup"]
+        if r["tuned"]:
+            extra["autotuned_slot_width"] = r["tuned"][0]
+            extra["autotune_median_ms_by_width"] = {str(k): round(v, 3) for k, v in r["tuned"][1].items()}
         ms_step = 1e3 * r["dt"] / args.steps
         workload = (f"persistent NUTS batch: 8 three-detector events (two each of 4, 8, 16, 32 s; "
                     f"{min(r['bins'])}-{max(r['bins'])} bins) in one launch, 11 params, {P} particles, forced tree "

@@ -225,6 +225,19 @@ int smcgw_smc_reweight_resample(smcgw_ctx *ctx, int P, int D, double beta_prev, 
 enum { SMCGW_OPT_NUTS_WAVES = 0, SMCGW_OPT_NUTS_PRIORITY = 1 };
 int smcgw_set_option(smcgw_ctx *ctx, int option, int64_t value);
 
+/* Autotuner of the NUTS slot width: runs `trials` transitions of the given
+ * batch (same arguments as smcgw_nuts_step, without diagnostics) for every
+ * width 2, 4, 6 and 8 on device copies of theta / logl / grad, times each
+ * launch with HIP events, and keeps the width with the shortest median time
+ * (SMCGW_OPT_NUTS_WAVES).  The caller's arrays are not modified.  The width
+ * changes the rounding order of the bin sums (not the method), so outputs
+ * after tuning equal those of a run with that width set by hand.
+ * Synchronises; *best_waves and times_ms[4] (host, may be NULL) receive the
+ * choice and the median time of each width. */
+int smcgw_autotune_nuts(smcgw_ctx *ctx, int P, int D, const double *theta, const double *logl, const double *grad,
+                        const double *chol, const smcgw_nuts_params *params, int precision, int trials,
+                        int *best_waves, double *times_ms);
+
 /* ------------------------------------------------------------ timing
  * Kernel timing for measurement: HIP events are recorded on the context's
  * stream around every launch of the kernel classes whose bit is set in

@@ -879,3 +879,62 @@ extern "C" int smcgw_nuts_step(smcgw_ctx* c, int P, int D, double* theta, double
         return SMCGW_ERR_INVALID;
     }
 }
+
+extern "C" int smcgw_autotune_nuts(smcgw_ctx* c, int P, int D, const double* theta, const double* logl,
+                                   const double* grad, const double* chol, const smcgw_nuts_params* prm, int precision,
+                                   int trials, int* best_waves, double* times_ms) {
+    if (!c || !prm || P < 1 || D <= 0 || D > MAXDIM || !theta || !logl || !grad || !chol || trials < 1 || trials > 16)
+        return SMCGW_ERR_INVALID;
+    hipSetDevice(c->device);
+    const size_t nx = (size_t)P * D * sizeof(double), nl = (size_t)P * sizeof(double);
+    double *x = nullptr, *l = nullptr, *g = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = SMCGW_OK;
+    if (hipMalloc(&x, nx) != hipSuccess || hipMalloc(&l, nl) != hipSuccess || hipMalloc(&g, nx) != hipSuccess ||
+        hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        rc = SMCGW_ERR_OOM;
+    const int widths[4] = {2, 4, 6, 8};
+    double med[4] = {0.0, 0.0, 0.0, 0.0};
+    const int saved = c->nuts_waves;
+    for (int w = 0; w < 4 && rc == SMCGW_OK; ++w) {
+        c->nuts_waves = widths[w];
+        float t[16];
+        for (int k = 0; k < trials && rc == SMCGW_OK; ++k) {
+            if (hipMemcpyAsync(x, theta, nx, hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
+                hipMemcpyAsync(l, logl, nl, hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
+                hipMemcpyAsync(g, grad, nx, hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
+                hipEventRecord(e0, c->stream) != hipSuccess) {
+                rc = SMCGW_ERR_HIP;
+                break;
+            }
+            rc = smcgw_nuts_step(c, P, D, x, l, g, chol, prm, nullptr, nullptr, precision, nullptr, nullptr, nullptr,
+                                 nullptr);
+            if (rc != SMCGW_OK) break;
+            if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&t[k], e0, e1) != hipSuccess)
+                rc = SMCGW_ERR_HIP;
+        }
+        if (rc == SMCGW_OK) {
+            std::sort(t, t + trials);
+            med[w] = t[trials / 2];
+        }
+    }
+    int best = saved;
+    if (rc == SMCGW_OK) {
+        int bi = 0;
+        for (int w = 1; w < 4; ++w)
+            if (med[w] < med[bi]) bi = w;
+        best = widths[bi];
+        if (best_waves) *best_waves = best;
+        if (times_ms)
+            for (int w = 0; w < 4; ++w) times_ms[w] = med[w];
+    }
+    c->nuts_waves = best;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(x);
+    (void)hipFree(l);
+    (void)hipFree(g);
+    return rc;
+}
+

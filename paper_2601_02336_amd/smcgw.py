@@ -80,6 +80,8 @@ def lib():
         L.smcgw_mass_matrix.argtypes = [vp, i, i, vp, d, vp, vp, vp]
         L.smcgw_nuts_step.argtypes = [vp, i, i, vp, vp, vp, vp, C.POINTER(NutsParams), vp, vp, i, vp, vp, vp, vp]
         L.smcgw_timing_enable.argtypes = [vp, i]
+        L.smcgw_autotune_nuts.argtypes = [vp, i, i, vp, vp, vp, vp, C.POINTER(NutsParams), i, i, C.POINTER(i),
+                                          C.POINTER(d)]
         L.smcgw_set_option.argtypes = [vp, i, C.c_int64]
         L.smcgw_timing_read.argtypes = [vp, i, C.POINTER(d), C.POINTER(C.c_int64)]
         L.smcgw_smc_reweight_resample.argtypes = [vp, i, i, d, d, u64, u64, vp, vp, vp, vp, vp,
@@ -269,6 +271,22 @@ class Context:
             _ptr(max_depth_per_particle), _ptr(work_hint), precision, _ptr(out.get("depth")), _ptr(out.get("n_leapfrog")),
             _ptr(out.get("divergent")), _ptr(out.get("accept_stat"))))
         return out
+
+    def autotune_nuts(self, theta: torch.Tensor, logl: torch.Tensor, grad: torch.Tensor, chol: torch.Tensor,
+                      step: float, beta: float, seed: int, iteration: int, max_depth: int = 10, uturn: bool = True,
+                      max_delta_h: float = 1000.0, precision: int = MIXED, trials: int = 3):
+        """Pick the NUTS slot width by timing transitions of this batch (inputs untouched).
+        Returns (best width, {width: median ms})."""
+        theta = _dev(theta, torch.float64, "theta")
+        P, D = theta.shape
+        prm = NutsParams(step, beta, max_delta_h, max_depth, 1 if uturn else 0, seed, iteration)
+        best = C.c_int(0)
+        times = (C.c_double * 4)()
+        self._stream()
+        _check("smcgw_autotune_nuts", lib().smcgw_autotune_nuts(
+            self._h, P, D, _ptr(theta), _ptr(logl), _ptr(grad), _ptr(chol), C.byref(prm), precision, trials,
+            C.byref(best), times))
+        return best.value, dict(zip((2, 4, 6, 8), list(times)))
 
     def smc_reweight_resample(self, theta: torch.Tensor, logl: torch.Tensor, grad: Optional[torch.Tensor],
                               beta_prev: float, alpha: float, seed: int, iteration: int,

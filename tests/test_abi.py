@@ -45,3 +45,6 @@ def test_invalid_arguments_rejected_without_gpu():
     assert lib.smcgw_create(None, 0, None) == -1
     assert lib.smcgw_loglike_grad(None, 1, None, None, None, None, 1) == -1
     assert lib.smcgw_mass_matrix(None, 2, 2, None, ctypes.c_double(0.0), None, None, None) == -1
+    assert lib.smcgw_autotune_nuts(None, 1, 1, None, None, None, None, None, 1, 1, None, None) == -1
+    assert lib.smcgw_nuts_step(None, 1, 1, None, None, None, None, None, None, None, 1, None, None, None, None) == -1
+    assert lib.smcgw_set_option(None, 0, ctypes.c_int64(4)) == -1

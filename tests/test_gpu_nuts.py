@@ -217,3 +217,36 @@ def test_schedule_does_not_change_results(smc):
     for r in runs[1:]:
         for a, b_ in zip(r, runs[0]):
             np.testing.assert_array_equal(a, b_)
+
+
+def test_autotune_keeps_inputs_and_sets_width(smc):
+    """The autotuner times every slot width on copies; afterwards a transition equals one run with the chosen
+    width set by hand, bitwise."""
+    ev = event(synth.SPEC_8S)
+    b = synth.gw_prior_for(ev)
+    rng = np.random.default_rng(9)
+    P = 700
+    x = torch.tensor(synth.prior_draw(rng, P, b), device="cuda")
+    _, _, L = O.mass_matrix(synth.prior_draw(rng, 4000, b), 0.0)
+    Lt = torch.tensor(L * 0.05, device="cuda")
+    c = smc.Context(0)
+    c.add_event(ev)
+    c.set_prior(b)
+    c.set_target(synth.TARGET_GW, 11)
+    ll, g = c.target_loglike_grad(x, precision=smc.MIXED)
+    x0, ll0, g0 = x.clone(), ll.clone(), g.clone()
+    best, times = c.autotune_nuts(x, ll, g, Lt, step=0.25, beta=0.05, seed=2, iteration=0, max_depth=6, trials=2)
+    print(f"autotune: best {best}, times {times}", flush=True)
+    assert best in (2, 4, 6, 8) and all(t > 0 for t in times.values()) and times[best] == min(times.values())
+    assert torch.equal(x, x0) and torch.equal(ll, ll0) and torch.equal(g, g0)
+    runs = []
+    for set_by_hand in (False, True):
+        if set_by_hand:
+            c.set_option(smc.OPT_NUTS_WAVES, best)
+        xs, ls, gs = x0.clone(), ll0.clone(), g0.clone()
+        c.nuts_step(xs, ls, gs, Lt, step=0.25, beta=0.05, seed=2, iteration=1, max_depth=6, precision=smc.MIXED)
+        torch.cuda.synchronize()
+        runs.append((xs.cpu().numpy(), ls.cpu().numpy()))
+    c.close()
+    np.testing.assert_array_equal(runs[0][0], runs[1][0])
+    np.testing.assert_array_equal(runs[0][1], runs[1][1])
