@@ -95,6 +95,10 @@ typedef struct {
     int32_t uturn;         /* 1: stop at a U-turn; 0: always build to the depth limit */
     uint64_t seed;         /* Philox4x32-10 key */
     uint64_t iteration;    /* SMC iteration (part of the Philox counter) */
+    int32_t chol_per_particle;   /* 0: chol is one [D][D] factor for all particles;
+                                    1: chol is [P][D][D], one factor per particle
+                                    (smcgw_local_metric) */
+    int32_t reserved;            /* must be 0 */
 } smcgw_nuts_params;
 
 /* Message for a status code (static storage). */
@@ -177,13 +181,33 @@ int smcgw_waveform(smcgw_ctx *ctx, int event_id, const double *theta11, double *
 int smcgw_mass_matrix(smcgw_ctx *ctx, int P, int D, const double *theta, double shrink, double *inv_mass,
                       double *chol, int32_t *status_device);
 
+/* Per-particle local metric (Sec. 5, "Exploitation of local geometry": at
+ * the start of each SMC iteration every particle's mass matrix is set to the
+ * Hessian of the tempered posterior at the particle and held fixed during
+ * the mutation).  Read as the Gauss-Newton Hessian
+ *   M_i = beta F(theta_i) + diag(prior precision),
+ * F the Fisher matrix <dh/dtheta_k | dh/dtheta_l> of the event likelihood
+ * (Sec. 2, Eq. 2) over the sampled coordinates, the prior precision
+ * 12/(hi-lo)^2 (uniform), the inverse variance (log-uniform), 1/sigma^2
+ * (Gaussian) or 0 (flat).  chol [P][D][D] receives the lower Cholesky
+ * factor of M_i^{-1} (the layout smcgw_nuts_step takes with
+ * chol_per_particle = 1); fisher [P][D][D] (may be NULL) receives F.  A
+ * particle whose M_i or M_i^{-1} is not numerically positive definite gets
+ * fallback_chol [D][D] (NULL: the identity) and status [P] = 1 (status may
+ * be NULL; 0 otherwise).  All arrays are device arrays; beta in [0, 1].
+ * Needs the GW target, a prior and a parameter map of dimension D.
+ * Asynchronous on the context's stream. */
+int smcgw_local_metric(smcgw_ctx *ctx, int P, int D, const double *theta, double beta, const double *fallback_chol,
+                       double *chol, double *fisher, int32_t *status);
+
 /* One No-U-Turn transition per particle (Sec. 4: momentum r ~ N(0, M),
  * Hamiltonian H = -log p_t + r^T M^{-1} r / 2, leapfrog Eqs. 11-13,
  * reflective / periodic boundaries of Sec. 5; multinomial trajectory
  * sampling with the generalised U-turn criterion).  theta [P][D], logl [P]
  * and grad [P][D] (device) hold the current point, its likelihood and the
  * likelihood gradient on entry and the selected point on exit.  chol [D][D]
- * (device) is the Cholesky factor of M^{-1}.  max_depth_per_particle [P]
+ * (device) is the Cholesky factor of M^{-1}, or chol [P][D][D] one factor
+ * per particle when params->chol_per_particle = 1.  max_depth_per_particle [P]
  * (device, NULL = params->max_depth) caps each tree.  work_hint [P]
  * (device, NULL = particle order) is a predicted leapfrog count per particle,
  * e.g. the n_leapfrog of its ancestor's previous transition: particles start

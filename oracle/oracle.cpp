@@ -674,9 +674,11 @@ int orc_leapfrog(const orc_target* t, double beta, const double* chol, double ep
 
 // One NUTS transition for each of P particles.  logl / grad are the
 // likelihood and its gradient at x (updated with the selected point).
+// chol is one [D][D] factor of M^{-1} shared by all particles, or, with
+// chol_per_particle, [P][D][D] (one factor per particle).
 int orc_nuts_step(const orc_target* t, int P, double* x, double* logl, double* grad, const double* chol,
-                  double step, int max_depth, const int32_t* max_depth_per_particle, int uturn, double max_dh,
-                  double beta, uint64_t seed, uint64_t iteration,
+                  int chol_per_particle, double step, int max_depth, const int32_t* max_depth_per_particle, int uturn,
+                  double max_dh, double beta, uint64_t seed, uint64_t iteration,
                   int32_t* depth, int32_t* n_leapfrog, uint8_t* divergent, double* accept_stat) {
     const int D = t->dim;
 #pragma omp parallel for schedule(dynamic, 1)
@@ -685,7 +687,8 @@ int orc_nuts_step(const orc_target* t, int P, double* x, double* logl, double* g
         for (int k = 0; k < D; ++k) s.x[k] = x[(size_t)i * D + k];
         eval_state(*t, beta, s);
         const int md = max_depth_per_particle ? max_depth_per_particle[i] : max_depth;
-        const NutsOut o = nuts_transition(*t, beta, chol, step, md, uturn, max_dh, seed, iteration, (uint32_t)i, s);
+        const double* Li = chol_per_particle ? chol + (size_t)i * D * D : chol;
+        const NutsOut o = nuts_transition(*t, beta, Li, step, md, uturn, max_dh, seed, iteration, (uint32_t)i, s);
         logl[i] = s.logl;
         for (int k = 0; k < D; ++k) { x[(size_t)i * D + k] = s.x[k]; if (grad) grad[(size_t)i * D + k] = s.gl[k]; }
         if (depth) depth[i] = o.depth;
@@ -777,6 +780,113 @@ int orc_mass_matrix(int P, int D, const double* x, double shrink, double* inv_ma
     return status;
 }
 
+// Local-geometry metric of Sec. 5 ("Exploitation of local geometry"): the
+// mass matrix of each particle is the Hessian of the tempered posterior's
+// negative log density at the particle, read as beta F + diag(prior
+// precision), with F the Fisher (Gauss-Newton) matrix of the likelihood,
+// F_kl = sum_d 4 df sum_j Re(conj(dh_dj/dtheta_k) dh_dj/dtheta_l) / S_dj,
+// from 11-tangent dual numbers of the strain, and the prior precision the
+// inverse variance of each coordinate's prior (uniform (hi-lo)^2/12,
+// log-uniform its variance, Gaussian sigma^2; 0 for a flat prior).  Outputs
+// per particle: fisher [D][D] (may be NULL) and chol [D][D], the lower
+// Cholesky factor of M^{-1}.  GW targets only.  A particle whose M or M^{-1}
+// is not numerically positive definite takes fallback [D][D] (the identity
+// when NULL) and status[i] = 1 (status may be NULL).  Returns the number of
+// such particles.
+int orc_local_metric(const orc_target* t, int P, const double* x, double beta, const double* fallback, double* fisher,
+                     double* chol, int32_t* status) {
+    if (t->kind != 0) return -1;
+    const int D = t->dim;
+    std::vector<double> prec(D, 0.0);
+    for (int k = 0; k < D; ++k) {
+        const orc_bound& b = t->bounds[k];
+        if (b.prior == 1) {
+            prec[k] = 12.0 / ((b.hi - b.lo) * (b.hi - b.lo));
+        } else if (b.prior == 2) {
+            const double lr = std::log(b.hi / b.lo);
+            const double m1 = (b.hi - b.lo) / lr, m2 = (b.hi * b.hi - b.lo * b.lo) / (2.0 * lr);
+            prec[k] = 1.0 / (m2 - m1 * m1);
+        } else if (b.prior == 3) {
+            prec[k] = 1.0 / (b.hi * b.hi);
+        }
+    }
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : bad)
+    for (int i = 0; i < P; ++i) {
+        double th[NP];
+        expand_gw(*t, x + (size_t)i * D, th);
+        D11 td[NP];
+        for (int k = 0; k < NP; ++k) { td[k] = D11(th[k]); td[k].d[k] = 1.0; }
+        const orc_event& ev = *t->ev;
+        double F11[NP][NP] = {};
+        for (int d = 0; d < ev.n_det; ++d)
+            for (int j = 0; j < ev.n_bins; ++j) {
+                const double f = ev.f_low + ev.df * j;
+                const Cx<D11> h = detector_strain(ev, t->dets[d], td, f);
+                const double w = 4.0 * ev.df / t->psd[(size_t)d * ev.n_bins + j];
+                for (int a = 0; a < NP; ++a)
+                    for (int b = 0; b < NP; ++b)
+                        F11[a][b] += w * (h.re.d[a] * h.re.d[b] + h.im.d[a] * h.im.d[b]);
+            }
+        std::vector<double> M((size_t)D * D), R((size_t)D * D, 0.0), Minv((size_t)D * D), Lo((size_t)D * D, 0.0);
+        for (int a = 0; a < D; ++a)
+            for (int b = 0; b < D; ++b) {
+                const int ia = t->param_index ? t->param_index[a] : a, ib = t->param_index ? t->param_index[b] : b;
+                if (fisher) fisher[(size_t)i * D * D + a * D + b] = F11[ia][ib];
+                M[a * D + b] = beta * F11[ia][ib] + (a == b ? prec[a] : 0.0);
+            }
+        // M = R R^T, then M^{-1} column by column (R y = e_j, R^T z = y), then M^{-1} = L L^T.
+        bool ok = true;
+        for (int j = 0; j < D && ok; ++j) {
+            double sjj = M[j * D + j];
+            for (int k = 0; k < j; ++k) sjj -= R[j * D + k] * R[j * D + k];
+            if (!(sjj > 0.0)) { ok = false; break; }
+            R[j * D + j] = std::sqrt(sjj);
+            for (int r = j + 1; r < D; ++r) {
+                double v = M[r * D + j];
+                for (int k = 0; k < j; ++k) v -= R[r * D + k] * R[j * D + k];
+                R[r * D + j] = v / R[j * D + j];
+            }
+        }
+        if (ok) {
+            for (int c = 0; c < D; ++c) {
+                double y[32], z[32];
+                for (int r = 0; r < D; ++r) {
+                    double v = (r == c) ? 1.0 : 0.0;
+                    for (int k = 0; k < r; ++k) v -= R[r * D + k] * y[k];
+                    y[r] = v / R[r * D + r];
+                }
+                for (int r = D - 1; r >= 0; --r) {
+                    double v = y[r];
+                    for (int k = r + 1; k < D; ++k) v -= R[k * D + r] * z[k];
+                    z[r] = v / R[r * D + r];
+                }
+                for (int r = 0; r < D; ++r) Minv[r * D + c] = z[r];
+            }
+            for (int j = 0; j < D && ok; ++j) {
+                double sjj = Minv[j * D + j];
+                for (int k = 0; k < j; ++k) sjj -= Lo[j * D + k] * Lo[j * D + k];
+                if (!(sjj > 0.0)) { ok = false; break; }
+                Lo[j * D + j] = std::sqrt(sjj);
+                for (int r = j + 1; r < D; ++r) {
+                    double v = Minv[r * D + j];
+                    for (int k = 0; k < j; ++k) v -= Lo[r * D + k] * Lo[j * D + k];
+                    Lo[r * D + j] = v / Lo[j * D + j];
+                }
+            }
+        }
+        // A particle whose M or M^{-1} is not numerically positive definite
+        // takes the fallback factor (the identity when none is given).
+        if (!ok) {
+            bad += 1;
+            for (int k = 0; k < D * D; ++k) Lo[k] = fallback ? fallback[k] : (k % (D + 1) == 0 ? 1.0 : 0.0);
+        }
+        if (status) status[i] = ok ? 0 : 1;
+        for (int k = 0; k < D * D; ++k) chol[(size_t)i * D * D + k] = Lo[k];
+    }
+    return bad;
+}
+
 // A full SMC run: adaptive tempering, multinomial resampling, covariance mass
 // matrix, one NUTS transition per iteration; stops after mutating at beta = 1.
 // x [P][D] holds the prior draws on entry and the final population on exit.
@@ -802,7 +912,7 @@ int orc_smc_run(const orc_target* t, int P, double* x, double alpha, double step
         }
         std::copy(xn.begin(), xn.end(), x);
         orc_mass_matrix(P, D, x, shrink, inv.data(), L.data());
-        orc_nuts_step(t, P, x, ll2.data(), nullptr, L.data(), step, max_depth, nullptr, 1, 1000.0, bn, seed,
+        orc_nuts_step(t, P, x, ll2.data(), nullptr, L.data(), 0, step, max_depth, nullptr, 1, 1000.0, bn, seed,
                       (uint64_t)it, nullptr, nullptr, nullptr, nullptr);
         std::copy(ll2.begin(), ll2.end(), logl.begin());
         beta = bn;

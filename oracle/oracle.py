@@ -222,8 +222,10 @@ def nuts_step(target: Target, x, chol, step: float, max_depth: int, beta: float,
     div = np.zeros(P, np.uint8)
     acc = np.zeros(P)
     mdp = None if max_depth_per_particle is None else np.ascontiguousarray(max_depth_per_particle, np.int32)
-    lib().orc_nuts_step(target.ptr, C.c_int(P), _dp(x), _dp(logl), _dp(grad), _dp(_f64(chol)), C.c_double(step),
-                        C.c_int(max_depth), _ip(mdp), C.c_int(1 if uturn else 0), C.c_double(max_dh),
+    chol = _f64(chol)
+    per_particle = 1 if chol.ndim == 3 else 0   # [P][D][D]: one factor per particle
+    lib().orc_nuts_step(target.ptr, C.c_int(P), _dp(x), _dp(logl), _dp(grad), _dp(chol), C.c_int(per_particle),
+                        C.c_double(step), C.c_int(max_depth), _ip(mdp), C.c_int(1 if uturn else 0), C.c_double(max_dh),
                         C.c_double(beta), C.c_uint64(seed), C.c_uint64(iteration), _ip(depth), _ip(nlf),
                         div.ctypes.data_as(C.c_void_p), _dp(acc))
     return dict(x=x, logl=logl, grad=grad, depth=depth, n_leapfrog=nlf, divergent=div, accept_stat=acc)
@@ -244,6 +246,21 @@ def resample(weights, seed: int, iteration: int) -> np.ndarray:
     a = np.zeros(w.size, np.int32)
     lib().orc_resample(C.c_int(w.size), _dp(w), C.c_uint64(seed), C.c_uint64(iteration), _ip(a))
     return a
+
+
+def local_metric(target: Target, x, beta: float, want_fisher: bool = True, fallback=None):
+    """Per-particle metric of the tempered posterior (Sec. 5, local geometry): (status [P], fisher [P][D][D],
+    chol [P][D][D]) with chol the lower Cholesky factor of (beta F + diag(prior precision))^{-1}; particles
+    whose matrix is not positive definite get `fallback` (identity when None) and status 1."""
+    x = _f64(x)
+    P, D = x.shape
+    F = np.zeros((P, D, D)) if want_fisher else None
+    L = np.zeros((P, D, D))
+    st = np.zeros(P, dtype=np.int32)
+    fb = None if fallback is None else _f64(fallback)
+    lib().orc_local_metric(target.ptr, C.c_int(P), _dp(x), C.c_double(beta), _dp(fb), _dp(F), _dp(L),
+                           st.ctypes.data_as(C.c_void_p))
+    return st, F, L
 
 
 def mass_matrix(x, shrink: float):

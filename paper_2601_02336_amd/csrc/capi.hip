@@ -219,12 +219,12 @@ extern "C" int smcgw_add_event(smcgw_ctx* c, const smcgw_event_desc* ev, const d
     const double us = umax > 0.0 ? std::ldexp(1.0, (int)std::lround(std::log2(umax))) : 1.0;
 
     hipSetDevice(c->device);
-    double *d_data = nullptr, *d_psd = nullptr, *fwl = nullptr, *sums = nullptr;
+    double *d_data = nullptr, *d_psd = nullptr, *fwl = nullptr, *sums = nullptr, *wmom = nullptr;
     float2* u32 = nullptr;
     double2* u64 = nullptr;
     int rc = SMCGW_OK;
     auto fail = [&](int code) {
-        hipFree(d_data); hipFree(d_psd); hipFree(fwl); hipFree(u32); hipFree(u64); hipFree(sums);
+        hipFree(d_data); hipFree(d_psd); hipFree(fwl); hipFree(u32); hipFree(u64); hipFree(sums); hipFree(wmom);
         return code;
     };
     if (hipMalloc(&d_data, sizeof(double) * 2 * nd * (size_t)n) != hipSuccess ||
@@ -232,12 +232,14 @@ extern "C" int smcgw_add_event(smcgw_ctx* c, const smcgw_event_desc* ev, const d
         hipMalloc(&fwl, sizeof(double) * NROWS * (size_t)npad) != hipSuccess ||
         hipMalloc(&u32, sizeof(float2) * nd * (size_t)npad) != hipSuccess ||
         hipMalloc(&u64, sizeof(double2) * nd * (size_t)npad) != hipSuccess ||
-        hipMalloc(&sums, sizeof(double) * 2 * MAXDET) != hipSuccess)
+        hipMalloc(&sums, sizeof(double) * 2 * MAXDET) != hipSuccess ||
+        hipMalloc(&wmom, sizeof(double) * nd * NGEO * NGEO) != hipSuccess)
         return fail(SMCGW_ERR_OOM);
     if (hipMemcpyAsync(d_data, data_reim, sizeof(double) * 2 * nd * (size_t)n, hipMemcpyHostToDevice, c->stream) ||
         hipMemcpyAsync(d_psd, psd, sizeof(double) * nd * (size_t)n, hipMemcpyHostToDevice, c->stream))
         return fail(SMCGW_ERR_HIP);
-    if (launch_build_tables(d_data, d_psd, nd, n, npad, ev->f_low, ev->df, us, fwl, u32, u64, sums, c->stream))
+    if (launch_build_tables(d_data, d_psd, nd, n, npad, ev->f_low, ev->df, us, fwl, u32, u64, sums, c->stream) ||
+        launch_metric_moments(d_psd, nd, n, ev->f_low, ev->df, us, wmom, c->stream))
         return fail(SMCGW_ERR_HIP);
     double hs[2 * MAXDET];
     if (hipMemcpyAsync(hs, sums, sizeof(double) * 2 * nd, hipMemcpyDeviceToHost, c->stream) ||
@@ -259,6 +261,7 @@ extern "C" int smcgw_add_event(smcgw_ctx* c, const smcgw_event_desc* ev, const d
     de.fwl = fwl;
     de.u32 = u32;
     de.u64 = u64;
+    de.wmom = wmom;
     de.dd = 0.0;
     for (int d = 0; d < nd; ++d) {
         de.hnorm[d] = hs[2 * d] / (us * us);
@@ -279,6 +282,7 @@ extern "C" int smcgw_add_event(smcgw_ctx* c, const smcgw_event_desc* ev, const d
     c->event_bufs.push_back(fwl);
     c->event_bufs.push_back(u32);
     c->event_bufs.push_back(u64);
+    c->event_bufs.push_back(wmom);
     c->n_det = nd;
     if (event_id) *event_id = id;
     (void)rc;

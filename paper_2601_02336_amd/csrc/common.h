@@ -91,7 +91,12 @@ struct DevEvent {
     double ln_pi_tsun;       // ln(pi G Msun / c^3)
     double pos[MAXDET][3];   // detector positions [m]
     double resp[MAXDET][3][3];
+    const double* wmom;      // [n_det][NGEO][NGEO]: sum_j 4 df f^-7/3 / S / u_scale^2 g_a g_b (local metric)
 };
+
+// Functions of f whose combination is the phase of detector d in cycles:
+// g_0 = 1, g_{1+b} = basis row b, g_{NCOEF} = f (the delay term).
+constexpr int NGEO = NCOEF + 1;
 
 // Sampled-coordinate map into the 11 source parameters.
 struct ParamMap {
@@ -138,6 +143,8 @@ __device__ __forceinline__ int event_index(const int32_t* ev_of_p, int p, int n_
 
 // ------------------------------------------------------------- host launchers
 // (each .hip file exposes host functions; kernels stay in their own unit)
+hipError_t launch_metric_moments(const double* d_psd, int n_det, int n_bins, double f_low, double df, double u_scale,
+                                 double* wmom, hipStream_t s);
 hipError_t launch_build_tables(const double* d_data, const double* d_psd, int n_det, int n_bins, int n_pad,
                                double f_low, double df, double u_scale, double* fwl, float2* u32, double2* u64,
                                double* sums, hipStream_t s);

@@ -1,0 +1,249 @@
+// Per-particle local metric (arXiv:2601.02336, Sec. 5, "Exploitation of
+// local geometry"): at the start of an SMC iteration every particle gets its
+// own mass matrix, the Hessian of the tempered posterior's negative log
+// density at the particle, held fixed during the mutation.  Read here as the
+// Gauss-Newton form
+//   M = beta F + diag(prior precision),
+//   F_kl = <dh/dtheta_k | dh/dtheta_l> = sum_d sum_j w_dj Re(conj(dh_dj/dk) dh_dj/dl),
+// which is positive semi-definite by construction and equals the expected
+// Hessian of -log L.
+//
+// No bin loop per particle: with h_dj = P'_d a_j e^{-2 pi i Phi_dj},
+// a_j = f_j^-7/6 / u_scale and Phi_dj = sum_a gamma_a g_a(f_j) a combination
+// of the phase functions g (constant, the basis rows, f),
+//   dh_dj/dk = a_j e^{-2 pi i Phi_dj} (D_dk - 2 pi i P'_d dPhi_dj/dk),
+//   D_dk = dP'_d/dk,
+// so
+//   F_kl = sum_d [ W_d00 Re(conj D_dk D_dl)
+//                + 2 pi (s_dk (W_d g_l)_0 + s_dl (W_d g_k)_0)
+//                + 4 pi^2 |P'_d|^2 g_kd^T W_d g_ld ],
+//   s_dk = Im(conj(D_dk) P'_d),  g_kd[a] = dgamma_a/dtheta_k (detector d),
+// with W_d the per-event moments sum_j w_dj a_j^2 g_a(f_j) g_b(f_j) built once
+// with the bin tables.  Then, per particle, M = R R^T, M^{-1} by column
+// solves, and the lower Cholesky factor of M^{-1} that the NUTS kernel takes.
+#include "coeffs.h"
+#include "common.h"
+#include "context.h"
+
+namespace smcgw {
+
+constexpr int MET_THREADS = 64;   // one wavefront per particle
+constexpr int NPAIR = NPAR * (NPAR + 1) / 2;
+constexpr int MET_SLOTS = (NPAIR + MET_THREADS - 1) / MET_THREADS;
+
+struct PrecDesc {
+    double prec[MAXDIM];   // prior precision of each sampled coordinate
+};
+
+struct MetricShared {
+    double cb[CB_SIZE];
+    double W[NGEO * NGEO];
+    double gam[NPAR][NGEO];   // d gamma_a / d theta_k for the current detector
+    double wg[NPAR][NGEO];    // W_d gamma_k
+    double dr[NPAR], di[NPAR], s[NPAR];
+    double F[NPAR * NPAR];
+    double M[MAXDIM * MAXDIM], R[MAXDIM * MAXDIM], Y[MAXDIM * MAXDIM], Z[MAXDIM * MAXDIM], Lo[MAXDIM * MAXDIM];
+    int bad;
+};
+
+// Phase derivative of source parameter k on phase function a (cycles),
+// detector d.  The phase is c_0 + sum_b c_{1+b} B_b(f) + f tau_d with
+// c_0 containing -phi_c / (2 pi) and tau_d = t_c + delay_d(ra, dec).
+__device__ __forceinline__ double phase_jac(const double* cb, int d, int k, int a) {
+    if (k < 4) return a < NCOEF ? cb[CB_DC + 4 * a + k] : 0.0;
+    if (a == 0) return k == P_PHIC ? -1.0 / TWO_PI : 0.0;
+    if (a != NGEO - 1) return 0.0;
+    return k == P_TC ? 1.0 : k == P_RA ? cb[CB_DTAU + 2 * d] : k == P_DEC ? cb[CB_DTAU + 2 * d + 1] : 0.0;
+}
+
+// Pair index e of the upper triangle (k <= l), row by row.
+__device__ __forceinline__ void pair_of(int e, int& k, int& l) {
+    k = 0;
+    while (e >= NPAR - k) { e -= NPAR - k; ++k; }
+    l = k + e;
+}
+
+// Lower Cholesky factor Lo of the D x D matrix A (row stride MAXDIM), one
+// row per lane; false (uniform over the wavefront) when a pivot is not
+// positive.  Each entry is formed in the textbook order: the matrix entry
+// minus the products of the finished columns, k ascending.
+__device__ bool wave_cholesky(const double* A, double* Lo, int D, int lane) {
+    for (int i = lane; i < MAXDIM * MAXDIM; i += MET_THREADS) Lo[i] = 0.0;
+    __syncthreads();
+    for (int j = 0; j < D; ++j) {
+        double sjj = A[j * MAXDIM + j];
+        for (int k = 0; k < j; ++k) sjj -= Lo[j * MAXDIM + k] * Lo[j * MAXDIM + k];
+        if (!(sjj > 0.0)) return false;
+        const double ljj = sqrt(sjj);
+        if (lane > j && lane < D) {
+            double t = A[lane * MAXDIM + j];
+            for (int k = 0; k < j; ++k) t -= Lo[lane * MAXDIM + k] * Lo[j * MAXDIM + k];
+            Lo[lane * MAXDIM + j] = t / ljj;
+        }
+        if (lane == j) Lo[j * MAXDIM + j] = ljj;
+        __syncthreads();
+    }
+    return true;
+}
+
+__global__ __launch_bounds__(MET_THREADS) void local_metric_kernel(const DevEvent* __restrict__ evs, int n_events,
+                                                                  const int32_t* __restrict__ ev_of_p, ParamMap pm,
+                                                                  PrecDesc pd, int P, const double* __restrict__ theta,
+                                                                  double beta, const double* __restrict__ fallback,
+                                                                  double* __restrict__ chol, double* __restrict__ fisher,
+                                                                  int32_t* __restrict__ status) {
+    __shared__ MetricShared S;
+    const int lane = threadIdx.x;
+    const int p = blockIdx.x;
+    const int D = pm.dim;
+    const DevEvent& ev = evs[event_index(ev_of_p, p, n_events)];
+
+    // coefficient block of the particle (one lane, FP64; the same prologue
+    // as the likelihood)
+    if (lane == 0) {
+        double th[NPAR];
+        expand_params(pm, theta + (size_t)p * D, th);
+        prep_intrinsic(ev, th, S.cb);
+        prep_extrinsic(ev, th, S.cb);
+    }
+    __syncthreads();
+    const double amp = S.cb[CB_AMP];
+
+    double acc[MET_SLOTS];
+#pragma unroll
+    for (int t = 0; t < MET_SLOTS; ++t) acc[t] = 0.0;
+    for (int d = 0; d < ev.n_det; ++d) {
+        const double qr = amp * S.cb[CB_PR + d], qi = amp * S.cb[CB_PI + d];
+        for (int i = lane; i < NGEO * NGEO; i += MET_THREADS) S.W[i] = ev.wmom[(size_t)d * NGEO * NGEO + i];
+        for (int i = lane; i < NPAR * NGEO; i += MET_THREADS) S.gam[i / NGEO][i % NGEO] = phase_jac(S.cb, d, i / NGEO, i % NGEO);
+        if (lane < NPAR) {
+            double xr = 0.0, xi = 0.0;
+            if (lane == P_MC || lane == P_DL) {
+                const double g = lane == P_MC ? S.cb[CB_DLNCA_MC] : S.cb[CB_DLNCA_DL];
+                xr = g * qr;
+                xi = g * qi;
+            } else if (lane == P_IOTA || lane == P_PSI || lane == P_RA || lane == P_DEC) {
+                const int m = lane == P_IOTA ? 0 : lane == P_PSI ? 1 : lane == P_RA ? 2 : 3;
+                xr = amp * S.cb[CB_DPR + 4 * d + m];
+                xi = amp * S.cb[CB_DPI + 4 * d + m];
+            }
+            S.dr[lane] = xr;
+            S.di[lane] = xi;
+            S.s[lane] = xr * qi - xi * qr;
+        }
+        __syncthreads();
+        for (int i = lane; i < NPAR * NGEO; i += MET_THREADS) {
+            const int k = i / NGEO, a = i % NGEO;
+            double v = 0.0;
+            for (int b = 0; b < NGEO; ++b) v = fma(S.W[a * NGEO + b], S.gam[k][b], v);
+            S.wg[k][a] = v;
+        }
+        __syncthreads();
+        const double q2 = qr * qr + qi * qi;
+#pragma unroll
+        for (int t = 0; t < MET_SLOTS; ++t) {
+            const int e = lane + t * MET_THREADS;
+            if (e < NPAIR) {
+                int k, l;
+                pair_of(e, k, l);
+                double gwg = 0.0;
+                for (int a = 0; a < NGEO; ++a) gwg = fma(S.gam[k][a], S.wg[l][a], gwg);
+                acc[t] += S.W[0] * (S.dr[k] * S.dr[l] + S.di[k] * S.di[l])
+                        + TWO_PI * (S.s[k] * S.wg[l][0] + S.s[l] * S.wg[k][0])
+                        + (4.0 * PI * PI) * q2 * gwg;
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int t = 0; t < MET_SLOTS; ++t) {
+        const int e = lane + t * MET_THREADS;
+        if (e < NPAIR) {
+            int k, l;
+            pair_of(e, k, l);
+            S.F[k * NPAR + l] = acc[t];
+            S.F[l * NPAR + k] = acc[t];
+        }
+    }
+    __syncthreads();
+
+    // M over the sampled coordinates
+    for (int i = lane; i < MAXDIM * MAXDIM; i += MET_THREADS) {
+        const int a = i / MAXDIM, b = i % MAXDIM;
+        double v = 0.0;
+        if (a < D && b < D) {
+            const double f = S.F[pm.idx[a] * NPAR + pm.idx[b]];
+            v = beta * f + (a == b ? pd.prec[a] : 0.0);
+            if (fisher) fisher[(size_t)p * D * D + a * D + b] = f;
+        }
+        S.M[i] = v;
+    }
+    __syncthreads();
+    bool ok = wave_cholesky(S.M, S.R, D, lane);
+    if (ok) {
+        // M^{-1} column by column: lane c solves R y = e_c, then R^T z = y.
+        if (lane < D) {
+            const int c = lane;
+            for (int r = 0; r < D; ++r) {
+                double v = (r == c) ? 1.0 : 0.0;
+                for (int k = 0; k < r; ++k) v -= S.R[r * MAXDIM + k] * S.Y[k * MAXDIM + c];
+                S.Y[r * MAXDIM + c] = v / S.R[r * MAXDIM + r];
+            }
+            for (int r = D - 1; r >= 0; --r) {
+                double v = S.Y[r * MAXDIM + c];
+                for (int k = r + 1; k < D; ++k) v -= S.R[k * MAXDIM + r] * S.Z[k * MAXDIM + c];
+                S.Z[r * MAXDIM + c] = v / S.R[r * MAXDIM + r];
+            }
+        }
+        __syncthreads();
+        ok = wave_cholesky(S.Z, S.Lo, D, lane);
+    }
+    for (int i = lane; i < D * D; i += MET_THREADS) {
+        const int a = i / D, b = i % D;
+        chol[(size_t)p * D * D + i] = ok ? S.Lo[a * MAXDIM + b] : fallback ? fallback[i] : (a == b ? 1.0 : 0.0);
+    }
+    if (status && lane == 0) status[p] = ok ? 0 : 1;
+}
+
+// Prior precision of each sampled coordinate: 12 / (hi - lo)^2 (uniform),
+// the inverse variance of the log-uniform density, 1 / sigma^2 (Gaussian),
+// 0 (flat).
+static PrecDesc prior_precision(const PriorDesc& pr) {
+    PrecDesc pd;
+    for (int k = 0; k < MAXDIM; ++k) {
+        double v = 0.0;
+        if (k < pr.dim) {
+            const double lo = pr.lo[k], hi = pr.hi[k];
+            if (pr.kind[k] == SMCGW_PRIOR_UNIFORM) {
+                v = 12.0 / ((hi - lo) * (hi - lo));
+            } else if (pr.kind[k] == SMCGW_PRIOR_LOGUNIFORM) {
+                const double lr = std::log(hi / lo);
+                const double m1 = (hi - lo) / lr, m2 = (hi * hi - lo * lo) / (2.0 * lr);
+                v = 1.0 / (m2 - m1 * m1);
+            } else if (pr.kind[k] == SMCGW_PRIOR_GAUSSIAN) {
+                v = 1.0 / (hi * hi);
+            }
+        }
+        pd.prec[k] = v;
+    }
+    return pd;
+}
+
+}  // namespace smcgw
+
+using namespace smcgw;
+
+extern "C" int smcgw_local_metric(smcgw_ctx* c, int P, int D, const double* theta, double beta,
+                                  const double* fallback_chol, double* chol, double* fisher, int32_t* status) {
+    if (!c || P < 0 || D <= 0 || D > MAXDIM || !(beta >= 0.0 && beta <= 1.0) || (P > 0 && (!theta || !chol)))
+        return SMCGW_ERR_INVALID;
+    if (c->events.empty() || !c->prior_set || c->target.kind != SMCGW_TARGET_GW) return SMCGW_ERR_NOT_INIT;
+    if (c->prior.dim != D || c->pmap.dim != D) return SMCGW_ERR_INVALID;
+    if (P == 0) return SMCGW_OK;
+    hipSetDevice(c->device);
+    const PrecDesc pd = prior_precision(c->prior);
+    hipLaunchKernelGGL(local_metric_kernel, dim3(P), dim3(MET_THREADS), 0, c->stream, c->d_events,
+                       (int)c->events.size(), c->ev_of_p, c->pmap, pd, P, theta, beta, fallback_chol, chol, fisher,
+                       status);
+    return hipGetLastError() == hipSuccess ? SMCGW_OK : SMCGW_ERR_HIP;
+}

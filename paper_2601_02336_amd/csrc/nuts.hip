@@ -49,6 +49,7 @@ struct NutsArgs {
     int* queue;
     const int32_t* order;   // start order of the particles (NULL: index order)
     int priority;           // raise wavefront priority with the tree depth
+    int chol_pp;            // chol holds one [D][D] factor per particle
 };
 
 constexpr int MAX_WAVES = 8;
@@ -579,6 +580,25 @@ __device__ __noinline__ void leaf_finish(const DevEvent* ev, NutsShared& S, Nuts
     if (lane == 0) T.ll_new = ll;
 }
 
+// The Cholesky factor L of M^{-1} ([D][D], row-major) into LDS, zero-padded
+// to MAXDIM; derive_metric then forms M^{-1} = L L^T and L^T from it.
+__device__ __forceinline__ void load_factor(NutsShared& S, const double* chol, int D, int tid) {
+    for (int i = tid; i < MAXDIM * MAXDIM; i += blockDim.x) {
+        const int r = i / MAXDIM, c = i % MAXDIM;
+        S.L[i] = (r < D && c < D) ? chol[r * D + c] : 0.0;
+    }
+}
+
+__device__ __forceinline__ void derive_metric(NutsShared& S, int D, int tid) {
+    for (int i = tid; i < MAXDIM * MAXDIM; i += blockDim.x) {
+        const int r = i / MAXDIM, c = i % MAXDIM;
+        double s = 0.0;
+        for (int m = 0; m < D; ++m) s = fma(S.L[r * MAXDIM + m], S.L[c * MAXDIM + m], s);
+        S.Minv[i] = s;
+        S.LT[i] = S.L[c * MAXDIM + r];
+    }
+}
+
 template <int NDET, int PREC, int TK, int WAVES>
 __global__ __launch_bounds__(WAVES * 64, (WAVES == 1 ? 2 : NUTS_WAVES_PER_SIMD)) void nuts_kernel(NutsArgs a, PriorDesc pri, ParamMap pm,
                                                                              TargetDesc tgt) {
@@ -590,10 +610,7 @@ __global__ __launch_bounds__(WAVES * 64, (WAVES == 1 ? 2 : NUTS_WAVES_PER_SIMD))
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int D = a.D;
 
-    for (int i = tid; i < MAXDIM * MAXDIM; i += blockDim.x) {
-        const int r = i / MAXDIM, c = i % MAXDIM;
-        S.L[i] = (r < D && c < D) ? a.chol[r * D + c] : 0.0;
-    }
+    if (!a.chol_pp) load_factor(S, a.chol, D, tid);
     if (tid == 0) {
         A = a;
         for (int k = 0; k < MAXDIM; ++k) {
@@ -608,14 +625,10 @@ __global__ __launch_bounds__(WAVES * 64, (WAVES == 1 ? 2 : NUTS_WAVES_PER_SIMD))
         for (int k = 0; k < NPAR; ++k) S.pfixed[k] = pm.fixed[k];
     }
     __syncthreads();
-    for (int i = tid; i < MAXDIM * MAXDIM; i += blockDim.x) {
-        const int r = i / MAXDIM, c = i % MAXDIM;
-        double s = 0.0;
-        for (int m = 0; m < D; ++m) s = fma(S.L[r * MAXDIM + m], S.L[c * MAXDIM + m], s);
-        S.Minv[i] = s;
-        S.LT[i] = S.L[c * MAXDIM + r];
+    if (!a.chol_pp) {
+        derive_metric(S, D, tid);
+        __syncthreads();
     }
-    __syncthreads();
 
     int ev_cached = -1;   // event whose descriptor S.ev holds
     for (;;) {
@@ -638,6 +651,12 @@ __global__ __launch_bounds__(WAVES * 64, (WAVES == 1 ? 2 : NUTS_WAVES_PER_SIMD))
                 for (int i = tid; i < (int)(sizeof(DevEvent) / 8); i += blockDim.x) dst[i] = src[i];
                 ev_cached = e;
             }
+        }
+        if (a.chol_pp) {   // the particle's own metric (the previous transition's readers are past a barrier)
+            load_factor(S, a.chol + (size_t)p * D * D, D, tid);
+            __syncthreads();
+            derive_metric(S, D, tid);
+            __syncthreads();
         }
         if (wave == 0) start_transition(S, T, A, p, lane);
 
@@ -808,7 +827,8 @@ extern "C" int smcgw_nuts_step(smcgw_ctx* c, int P, int D, double* theta, double
         return SMCGW_ERR_INVALID;
     if (precision != SMCGW_PLAIN_FP64 && precision != SMCGW_MIXED) return SMCGW_ERR_INVALID;
     if (prm->max_depth < 0 || prm->max_depth > SMCGW_MAX_DEPTH || !(prm->step > 0.0) || !(prm->beta >= 0.0) ||
-        !(prm->max_delta_h > 0.0))
+        !(prm->max_delta_h > 0.0) || (prm->chol_per_particle != 0 && prm->chol_per_particle != 1) ||
+        prm->reserved != 0)
         return SMCGW_ERR_INVALID;
     if (!c->prior_set || c->prior.dim != D) return SMCGW_ERR_NOT_INIT;
     const int kind = c->target.kind;
@@ -856,6 +876,7 @@ extern "C" int smcgw_nuts_step(smcgw_ctx* c, int P, int D, double* theta, double
     a.queue = (int*)c->d_queue;
     a.order = work_hint ? c->d_order : nullptr;
     a.priority = c->nuts_priority;
+    a.chol_pp = prm->chol_per_particle;
     const TargetDesc t = c->target;
     switch (kind) {
     case SMCGW_TARGET_GW:

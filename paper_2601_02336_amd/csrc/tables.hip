@@ -65,6 +65,62 @@ __global__ __launch_bounds__(256) void table_sums_kernel(const double* __restric
     }
 }
 
+// Basis moments of the local metric, one workgroup per detector:
+// W_d[a][b] = sum_j 4 df f_j^-7/3 / S_dj / u_scale^2 g_a(f_j) g_b(f_j) with the
+// phase functions g (g_0 = 1, the basis rows, f).  The metric of a particle
+// is a quadratic form of these per-event sums (the Fisher matrix of a
+// Newtonian-amplitude waveform needs no per-particle bin loop).  Fixed-order
+// sums: per-thread partials, then the threads in index order.
+constexpr int MOM_THREADS = 256;
+constexpr int NGEO_PAIRS = NGEO * (NGEO + 1) / 2;
+
+__global__ __launch_bounds__(MOM_THREADS) void metric_moments_kernel(const double* __restrict__ psd, int n,
+                                                                     double f_low, double df, double inv_us2,
+                                                                     double* __restrict__ wmom) {
+    __shared__ double part[MOM_THREADS];
+    const int d = blockIdx.x;
+    double acc[NGEO_PAIRS];
+#pragma unroll
+    for (int e = 0; e < NGEO_PAIRS; ++e) acc[e] = 0.0;
+    for (int j = threadIdx.x; j < n; j += MOM_THREADS) {
+        const double f = f_low + df * (double)j;
+        const double a = pow(f, -7.0 / 6.0);
+        const double w = 4.0 * df / psd[(size_t)d * n + j] * a * a * inv_us2;
+        double g[NGEO];
+        double B[NBASIS];
+        basis_rows(f, 1.0 / cbrt(f), log(f), B);
+        g[0] = 1.0;
+#pragma unroll
+        for (int b = 0; b < NBASIS; ++b) g[1 + b] = B[b];
+        g[NGEO - 1] = f;
+        int e = 0;
+#pragma unroll
+        for (int x = 0; x < NGEO; ++x)
+#pragma unroll
+            for (int y = 0; y <= x; ++y) acc[e++] += w * g[x] * g[y];
+    }
+    int e = 0;
+    for (int x = 0; x < NGEO; ++x)
+        for (int y = 0; y <= x; ++y) {
+            part[threadIdx.x] = acc[e++];
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                double s = 0.0;
+                for (int t = 0; t < MOM_THREADS; ++t) s += part[t];
+                wmom[((size_t)d * NGEO + x) * NGEO + y] = s;
+                wmom[((size_t)d * NGEO + y) * NGEO + x] = s;
+            }
+            __syncthreads();
+        }
+}
+
+hipError_t launch_metric_moments(const double* d_psd, int n_det, int n_bins, double f_low, double df, double u_scale,
+                                 double* wmom, hipStream_t s) {
+    hipLaunchKernelGGL(metric_moments_kernel, dim3(n_det), dim3(MOM_THREADS), 0, s, d_psd, n_bins, f_low, df,
+                       1.0 / (u_scale * u_scale), wmom);
+    return hipGetLastError();
+}
+
 hipError_t launch_build_tables(const double* d_data, const double* d_psd, int n_det, int n_bins, int n_pad,
                                double f_low, double df, double u_scale, double* fwl, float2* u32, double2* u64,
                                double* sums, hipStream_t s) {

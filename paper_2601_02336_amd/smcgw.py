@@ -49,10 +49,21 @@ class Bounds(C.Structure):
 
 class NutsParams(C.Structure):
     _fields_ = [("step", C.c_double), ("beta", C.c_double), ("max_delta_h", C.c_double),
-                ("max_depth", C.c_int32), ("uturn", C.c_int32), ("seed", C.c_uint64), ("iteration", C.c_uint64)]
+                ("max_depth", C.c_int32), ("uturn", C.c_int32), ("seed", C.c_uint64), ("iteration", C.c_uint64),
+                ("chol_per_particle", C.c_int32), ("reserved", C.c_int32)]
 
 
 _lib = None
+
+
+def _chol_mode(chol: torch.Tensor, P: int, D: int) -> int:
+    """0 for one shared [D][D] factor, 1 for per-particle [P][D][D] factors."""
+    _dev(chol, torch.float64, "chol")
+    if tuple(chol.shape) == (D, D):
+        return 0
+    if tuple(chol.shape) == (P, D, D):
+        return 1
+    raise ValueError(f"chol must be [{D}][{D}] or [{P}][{D}][{D}], got {tuple(chol.shape)}")
 
 
 def lib():
@@ -78,6 +89,7 @@ def lib():
         L.smcgw_waveform.argtypes = [vp, i, vp, vp]
         L.smcgw_target_loglike_grad.argtypes = [vp, i, vp, vp, vp, i]
         L.smcgw_mass_matrix.argtypes = [vp, i, i, vp, d, vp, vp, vp]
+        L.smcgw_local_metric.argtypes = [vp, i, i, vp, d, vp, vp, vp, vp]
         L.smcgw_nuts_step.argtypes = [vp, i, i, vp, vp, vp, vp, C.POINTER(NutsParams), vp, vp, i, vp, vp, vp, vp]
         L.smcgw_timing_enable.argtypes = [vp, i]
         L.smcgw_autotune_nuts.argtypes = [vp, i, i, vp, vp, vp, vp, C.POINTER(NutsParams), i, i, C.POINTER(i),
@@ -246,13 +258,34 @@ class Context:
                                                                  _ptr(L), _ptr(status)), allow=(OK, WARN_FALLBACK))
         return inv, L, rc
 
+    def local_metric(self, theta: torch.Tensor, beta: float, fallback: Optional[torch.Tensor] = None,
+                     fisher: bool = False, status: bool = True):
+        """Per-particle metric factors chol [P][D][D] (lower Cholesky factor of (beta F + prior precision)^-1).
+        Returns (chol, fisher or None, status or None); asynchronous."""
+        theta = _dev(theta, torch.float64, "theta")
+        P, D = theta.shape
+        dev = theta.device
+        L = torch.empty((P, D, D), dtype=torch.float64, device=dev)
+        F = torch.empty((P, D, D), dtype=torch.float64, device=dev) if fisher else None
+        st = torch.empty(P, dtype=torch.int32, device=dev) if status else None
+        if fallback is not None:
+            fallback = _dev(fallback, torch.float64, "fallback")
+            if tuple(fallback.shape) != (D, D):
+                raise ValueError("fallback must be [D][D]")
+        self._stream()
+        _check("smcgw_local_metric", lib().smcgw_local_metric(self._h, P, D, _ptr(theta), beta, _ptr(fallback),
+                                                              _ptr(L), _ptr(F), _ptr(st)))
+        return L, F, st
+
     def nuts_step(self, theta: torch.Tensor, logl: torch.Tensor, grad: torch.Tensor, chol: torch.Tensor,
                   step: float, beta: float, seed: int, iteration: int, max_depth: int = 10, uturn: bool = True,
                   max_delta_h: float = 1000.0, max_depth_per_particle: Optional[torch.Tensor] = None,
                   precision: int = MIXED, diagnostics: bool = True, work_hint: Optional[torch.Tensor] = None):
+        """One NUTS transition per particle; chol is one [D][D] factor of M^-1 or [P][D][D], one per particle."""
         theta = _dev(theta, torch.float64, "theta")
         P, D = theta.shape
-        prm = NutsParams(step, beta, max_delta_h, max_depth, 1 if uturn else 0, seed, iteration)
+        prm = NutsParams(step, beta, max_delta_h, max_depth, 1 if uturn else 0, seed, iteration,
+                         _chol_mode(chol, P, D), 0)
         dev = theta.device
         out = {}
         if diagnostics:
@@ -279,7 +312,8 @@ class Context:
         Returns (best width, {width: median ms})."""
         theta = _dev(theta, torch.float64, "theta")
         P, D = theta.shape
-        prm = NutsParams(step, beta, max_delta_h, max_depth, 1 if uturn else 0, seed, iteration)
+        prm = NutsParams(step, beta, max_delta_h, max_depth, 1 if uturn else 0, seed, iteration,
+                         _chol_mode(chol, P, D), 0)
         best = C.c_int(0)
         times = (C.c_double * 4)()
         self._stream()

@@ -1,0 +1,207 @@
+"""Per-particle local metric (arXiv:2601.02336, Sec. 5, "Exploitation of local geometry") on the GPU:
+parity of the Fisher matrix and of the Cholesky factor of (beta F + prior precision)^{-1} with the oracle,
+the fallback of the degenerate case, NUTS with one factor per particle, and an SMC run with the local metric."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2601_02336_amd import synth
+from paper_2601_02336_amd.synth import Bound
+from oracle import oracle as O
+
+from helpers import CONFIG0_INDEX, event
+
+pytestmark = pytest.mark.gpu
+
+# F: both sides sum the same FP64 products in different orders (the oracle per bin, the kernel through
+# per-event moments, whose quadratic forms cancel by up to ~1e4 against the entry), normalised by
+# sqrt(F_kk F_ll).  L: the factor of M^{-1} inherits cond(M) times that; checked through L^T M L = I with
+# the oracle's M and elementwise against the oracle's factor relative to each column's largest entry.
+TOL_F = 1e-9
+TOL_WHITEN = 1e-6
+TOL_L = 1e-6
+
+
+@pytest.fixture(scope="module")
+def smcgw():
+    from paper_2601_02336_amd import smcgw as m
+    return m
+
+
+def _ctx(smcgw, ev, idx, b, events=None):
+    c = smcgw.Context(0)
+    for e in (events or [ev]):
+        c.add_event(e)
+    c.set_param_map(idx, ev.theta_inj)
+    c.set_prior(b)
+    c.set_target(synth.TARGET_GW, len(idx))
+    return c
+
+
+def _errors(F, L, Fr, Lr, beta, prec):
+    s = np.sqrt(np.abs(np.einsum("pkk->pk", Fr)))
+    ef = float(np.max(np.abs(F - Fr) / (s[:, :, None] * s[:, None, :])))
+    D = L.shape[1]
+    M = beta * Fr + np.diag(prec)[None]
+    W = np.transpose(L, (0, 2, 1)) @ M @ L
+    ew = float(np.max(np.abs(W - np.eye(D)[None])))
+    scale = np.max(np.abs(Lr), axis=1, keepdims=True)
+    el = float(np.max(np.abs(L - Lr) / scale))
+    return ef, ew, el
+
+
+def _prec(bounds):
+    out = []
+    for b in bounds:
+        if b.prior == synth.PRIOR_UNIFORM:
+            out.append(12.0 / (b.hi - b.lo) ** 2)
+        elif b.prior == synth.PRIOR_LOGUNIFORM:
+            lr = np.log(b.hi / b.lo)
+            m1, m2 = (b.hi - b.lo) / lr, (b.hi ** 2 - b.lo ** 2) / (2 * lr)
+            out.append(1.0 / (m2 - m1 * m1))
+        elif b.prior == synth.PRIOR_GAUSSIAN:
+            out.append(1.0 / b.hi ** 2)
+        else:
+            out.append(0.0)
+    return np.array(out)
+
+
+@pytest.mark.parametrize("beta", [1.0, 0.02])
+def test_local_metric_parity_three_detectors(smcgw, beta):
+    """3 detectors, 8033 bins, all 11 parameters, 130 particles (three full wavefront batches and a tail)."""
+    ev = event(synth.SPEC_8S)
+    idx = list(range(11))
+    b = synth.gw_prior_for(ev)
+    x = synth.prior_draw(np.random.default_rng(41), 130, b)
+    st, Fr, Lr = O.local_metric(O.gw_target(ev, param_index=idx), x, beta)
+    assert not st.any()
+    c = _ctx(smcgw, ev, idx, b)
+    L, F, sg = c.local_metric(torch.tensor(x, device="cuda"), beta, fisher=True)
+    torch.cuda.synchronize()
+    L, F, sg = L.cpu().numpy(), F.cpu().numpy(), sg.cpu().numpy()
+    c.close()
+    ef, ew, el = _errors(F, L, Fr, Lr, beta, _prec(b))
+    print(f"beta {beta}: F err {ef:.2e}, |L^T M L - I| {ew:.2e}, L err {el:.2e}", flush=True)
+    assert not sg.any()
+    assert ef <= TOL_F and ew <= TOL_WHITEN and el <= TOL_L
+    assert np.array_equal(L, np.tril(L))
+
+
+def test_local_metric_subset_and_event_map(smcgw):
+    """Four sampled coordinates, two events of different lengths picked per particle."""
+    evs = [event(s) for s in synth.ragged_specs()[:4:2]]   # 4 s and 8 s, 3 detectors
+    idx = CONFIG0_INDEX
+    full = synth.gw_prior_for(evs[0])
+    b = [full[i] for i in idx]
+    P = 70
+    x = synth.prior_draw(np.random.default_rng(42), P, b)
+    emap = (np.arange(P) % 2).astype(np.int32)
+    c = _ctx(smcgw, evs[0], idx, b, events=evs)
+    em = torch.tensor(emap, device="cuda")
+    c.set_event_map(em)
+    L, F, sg = c.local_metric(torch.tensor(x, device="cuda"), 0.5, fisher=True)
+    torch.cuda.synchronize()
+    L, F = L.cpu().numpy(), F.cpu().numpy()
+    c.close()
+    Fr = np.zeros_like(F)
+    Lr = np.zeros_like(L)
+    for e in range(2):
+        sel = emap == e
+        t = O.gw_target(evs[e], param_index=idx, bounds=full, fixed11=evs[0].theta_inj)
+        st, Fr[sel], Lr[sel] = O.local_metric(t, x[sel], 0.5)
+        assert not st.any()
+    ef, ew, el = _errors(F, L, Fr, Lr, 0.5, _prec(b))
+    print(f"two events: F err {ef:.2e}, whitening {ew:.2e}, L err {el:.2e}", flush=True)
+    assert ef <= TOL_F and ew <= TOL_WHITEN and el <= TOL_L
+
+
+def test_local_metric_fallback(smcgw):
+    """Flat priors at beta = 0: M = 0, every particle takes the fallback (identity when none is given)."""
+    ev = event(synth.SPEC_SMALL)
+    idx = [0, 1, 9]
+    b = [Bound(20.0, 40.0, synth.BND_NONE, synth.PRIOR_FLAT), Bound(0.5, 1.0, synth.BND_NONE, synth.PRIOR_FLAT),
+         Bound(-0.1, 0.1, synth.BND_NONE, synth.PRIOR_FLAT)]
+    x = torch.tensor([[30.0, 0.8, 0.0], [25.0, 0.6, 0.01], [35.0, 0.9, -0.02]], device="cuda", dtype=torch.float64)
+    c = _ctx(smcgw, ev, idx, b)
+    L, _, st = c.local_metric(x, 0.0)
+    assert st.tolist() == [1, 1, 1]
+    assert torch.equal(L.cpu(), torch.eye(3, dtype=torch.float64).expand(3, 3, 3))
+    fb = torch.tensor([[2.0, 0.0, 0.0], [0.5, 1.0, 0.0], [0.0, 0.0, 3.0]], device="cuda", dtype=torch.float64)
+    L, _, st = c.local_metric(x, 0.0, fallback=fb)
+    assert st.tolist() == [1, 1, 1] and torch.equal(L, fb.expand(3, 3, 3))
+    L, _, st = c.local_metric(x, 1.0)
+    assert st.tolist() == [0, 0, 0]
+    # empty batch
+    L, _, st = c.local_metric(x[:0], 1.0)
+    assert L.shape == (0, 3, 3)
+    c.close()
+
+
+def _nuts_pp(smcgw, ev, idx, P, beta, max_depth, precision, step, seed=9):
+    full = synth.gw_prior_for(ev)
+    b = [full[i] for i in idx]
+    x = synth.prior_draw(np.random.default_rng(seed), P, b)
+    t = O.gw_target(ev, param_index=idx)
+    ll, g = O.loglike_grad(t, x)
+    st, _, L = O.local_metric(t, x, beta, want_fisher=False)
+    assert not st.any()
+    ref = O.nuts_step(t, x, L, step, max_depth, beta, seed=seed, iteration=2)
+    c = _ctx(smcgw, ev, idx, b)
+    xt, lt, gt = (torch.tensor(v, device="cuda") for v in (x, ll, g))
+    out = c.nuts_step(xt, lt, gt, torch.tensor(L, device="cuda"), step=step, beta=beta, seed=seed, iteration=2,
+                      max_depth=max_depth, precision=precision)
+    torch.cuda.synchronize()
+    got = {k: v.cpu().numpy() for k, v in out.items()}
+    got.update(x=xt.cpu().numpy(), logl=lt.cpu().numpy())
+    c.close()
+    same_tree = (got["depth"] == ref["depth"]) & (got["n_leapfrog"] == ref["n_leapfrog"])
+    close = np.all(np.abs(got["x"] - ref["x"]) <= 1e-6 * (1 + np.abs(ref["x"])), axis=1)
+    return got, ref, same_tree & close
+
+
+def test_nuts_per_particle_factor_parity(smcgw):
+    """One transition with each particle's own local-metric factor (the oracle's factors on both sides)."""
+    ev = event(synth.SPEC_SMALL)
+    got, ref, ok = _nuts_pp(smcgw, ev, CONFIG0_INDEX, 96, 0.3, 6, smcgw.PLAIN_FP64, 0.4)
+    print(f"per-particle factors, 1 det: agree {ok.mean():.3f}, depths {np.bincount(ref['depth'])}, "
+          f"divergent {int(ref['divergent'].sum())}", flush=True)
+    assert ok.mean() >= 0.97
+    np.testing.assert_allclose(got["logl"][ok], ref["logl"][ok], rtol=1e-10)
+    ev3 = event(synth.SPEC_8S)
+    got, ref, ok = _nuts_pp(smcgw, ev3, list(range(11)), 16, 0.05, 5, smcgw.PLAIN_FP64, 0.3)
+    print(f"per-particle factors, 3 det 11 params: agree {ok.mean():.3f}, depths {np.bincount(ref['depth'])}",
+          flush=True)
+    assert ok.mean() >= 15 / 16
+
+
+def test_smc_with_local_metric(smcgw):
+    """1-detector event, (Mc, q, t_c, phi_c), 256 particles: the local-metric run reaches beta = 1, needs no
+    fallback, its log Z equals the oracle's FP64 replay of its own populations, and it concentrates at the
+    injection."""
+    from paper_2601_02336_amd import smc
+    ev = event(synth.SPEC_SMALL)
+    idx = CONFIG0_INDEX
+    full = synth.gw_prior_for(ev)
+    b = [full[i] for i in idx]
+    x0 = torch.tensor(synth.prior_draw(np.random.default_rng(11), 256, b), device="cuda")
+    lz = {}
+    for metric in ("population", "local"):
+        c = _ctx(smcgw, ev, idx, b)
+        cfg = smc.SmcConfig(alpha=0.5, step=0.5, max_depth=6, seed=1, precision=smcgw.PLAIN_FP64, record=True,
+                            metric=metric)
+        r = smc.run_smc(c, x0, cfg)
+        c.close()
+        t = O.gw_target(ev, param_index=idx)
+        beta, ref = 0.0, 0.0
+        for pop in r.populations:
+            ll = O.loglike_grad(t, pop.cpu().numpy(), want_grad=False)
+            _, beta, dz, _ = O.smc_reweight(ll, beta, 0.5)
+            ref += dz
+        print(f"{metric}: log Z {r.logz:.5f} (replay {ref:.5f}), {r.n_iter} iterations, "
+              f"{sum(r.n_leapfrog)} leapfrog steps, {sum(r.divergent)} divergent, "
+              f"local fallbacks {r.local_metric_fallbacks}", flush=True)
+        assert r.betas[-1] == 1.0
+        assert abs(r.logz - ref) <= 1e-8
+        assert abs(np.median(r.theta.cpu().numpy()[:, 0]) - ev.theta_inj[0]) < 1.0
+        lz[metric] = r.logz
+    assert lz and r.local_metric_fallbacks == 0
