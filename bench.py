@@ -207,8 +207,9 @@ def smc_setup(smcgw, synth, ev, P, seed=7):
     return ctx, x_np, torch.tensor(x_np, device="cuda")
 
 
-def run_smc_steps(smcgw, ctx, theta, precision, args, n_warm, n_steps, time_kernels):
-    """SMC iterations from prior draws; returns (evals, seconds, nuts kernel ms, launches, per-step stats)."""
+def run_smc_steps(smcgw, ctx, theta, precision, args, n_warm, n_steps, time_kernels, metric="population"):
+    """SMC iterations from prior draws; returns (evals, seconds, nuts kernel ms, launches, betas, depth
+    histograms, local-metric kernel ms and launches)."""
     import torch
     logl, grad = ctx.target_loglike_grad(theta, precision=precision)
     beta, it, hint = 0.0, 0, None
@@ -219,6 +220,8 @@ def run_smc_steps(smcgw, ctx, theta, precision, args, n_warm, n_steps, time_kern
         nonlocal beta, it, hint
         b, dz, _ = ctx.smc_reweight_resample(theta, logl, grad, beta, args.alpha, args.seed, it, carry=hint)
         _, L, _ = ctx.mass_matrix(theta, 0.0, status=mm_status)
+        if metric == "local":
+            L, _, _ = ctx.local_metric(theta, b, fallback=L, status=False)
         out = ctx.nuts_step(theta, logl, grad, L, step=args.step, beta=b, seed=args.seed, iteration=it,
                             max_depth=args.max_depth, precision=precision, work_hint=hint)
         hint = None if args.no_hint else out["n_leapfrog"]
@@ -233,8 +236,9 @@ def run_smc_steps(smcgw, ctx, theta, precision, args, n_warm, n_steps, time_kern
     nlf.zero_()
     torch.cuda.synchronize()
     ctx.timing_read(smcgw.KERNEL_NUTS)
+    ctx.timing_read(smcgw.KERNEL_METRIC)
     if time_kernels:
-        ctx.timing(smcgw.KERNEL_NUTS)
+        ctx.timing(smcgw.KERNEL_NUTS, smcgw.KERNEL_METRIC)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(n_steps):
@@ -245,8 +249,9 @@ def run_smc_steps(smcgw, ctx, theta, precision, args, n_warm, n_steps, time_kern
     dt = time.perf_counter() - t0
     ctx.timing()
     k_ms, k_n = ctx.timing_read(smcgw.KERNEL_NUTS)
+    m_ms, m_n = ctx.timing_read(smcgw.KERNEL_METRIC)
     depth_hist = [np.bincount(d.cpu().numpy(), minlength=args.max_depth + 1).tolist() for _, d in stats]
-    return int(nlf.item()), dt, k_ms, k_n, [b for b, _ in stats], depth_hist
+    return int(nlf.item()), dt, k_ms, k_n, [b for b, _ in stats], depth_hist, m_ms, m_n
 
 
 def main():
@@ -290,7 +295,8 @@ def main():
         ctx, x_np, x = smc_setup(smcgw, synth, ev, P)
         ctx.set_option(smcgw.OPT_NUTS_PRIORITY, args.priority)
         ctx.set_option(smcgw.OPT_NUTS_WAVES, args.waves)
-        evals, dt, k_ms, k_n, betas, hist = run_smc_steps(smcgw, ctx, x, prec, args, args.warmup, args.steps, True)
+        evals, dt, k_ms, k_n, betas, hist, _, _ = run_smc_steps(smcgw, ctx, x, prec, args, args.warmup, args.steps,
+                                                                True)
         value = evals / dt
         kernel_s = k_ms / 1e3
         achieved = ops * ev.n * evals / kernel_s / 1e12
@@ -314,10 +320,24 @@ def main():
             ctx2, _, x2 = smc_setup(smcgw, synth, ev, P)
             ctx2.set_option(smcgw.OPT_NUTS_PRIORITY, args.priority)
             ctx2.set_option(smcgw.OPT_NUTS_WAVES, args.waves)
-            e2, d2, _, _, _, _ = run_smc_steps(smcgw, ctx2, x2, smcgw.PLAIN_FP64 if prec == smcgw.MIXED else smcgw.MIXED,
-                                               args, args.warmup, max(2, args.steps // 2), False)
+            e2, d2, _, _, _, _, _, _ = run_smc_steps(smcgw, ctx2, x2,
+                                                     smcgw.PLAIN_FP64 if prec == smcgw.MIXED else smcgw.MIXED,
+                                                     args, args.warmup, max(2, args.steps // 2), False)
             extra["other_precision_in_sampler_evals_per_s"] = round(e2 / d2, 1)
             ctx2.close()
+            # the same iterations with the per-particle local metric (beta F + prior precision) in place of
+            # the population covariance: sampler rate and the metric kernel's own time
+            ctx3, _, x3 = smc_setup(smcgw, synth, ev, P)
+            ctx3.set_option(smcgw.OPT_NUTS_PRIORITY, args.priority)
+            ctx3.set_option(smcgw.OPT_NUTS_WAVES, args.waves)
+            e3, d3, k3, n3, b3, _, m3, mn3 = run_smc_steps(smcgw, ctx3, x3, prec, args, args.warmup, args.steps,
+                                                           True, metric="local")
+            extra["local_metric_sampler"] = {
+                "evals_per_s": round(e3 / d3, 1), "ms_per_step": round(1e3 * d3 / args.steps, 4),
+                "leapfrog_per_step": round(e3 / args.steps, 1), "nuts_kernel_ms": round(k3 / max(n3, 1), 3),
+                "metric_kernel_ms": round(m3 / max(mn3, 1), 4), "metric_launches": mn3,
+                "betas": [round(b, 8) for b in b3]}
+            ctx3.close()
     elif args.mode == "batch":
         r = run_batch(smcgw, synth, args)
         P = r["P"]

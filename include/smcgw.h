@@ -269,7 +269,7 @@ int smcgw_autotune_nuts(smcgw_ctx *ctx, int P, int D, const double *theta, const
  * smcgw_timing_read synchronises, returns the summed duration [ms] and the
  * launch count of one class since the last read, and resets that class. */
 enum { SMCGW_KERNEL_BINS = 0, SMCGW_KERNEL_PREP = 1, SMCGW_KERNEL_FINISH = 2, SMCGW_KERNEL_NUTS = 3,
-       SMCGW_KERNEL_SMC = 4, SMCGW_KERNEL_CLASSES = 5 };
+       SMCGW_KERNEL_SMC = 4, SMCGW_KERNEL_METRIC = 5, SMCGW_KERNEL_CLASSES = 6 };
 int smcgw_timing_enable(smcgw_ctx *ctx, int class_mask);
 int smcgw_timing_read(smcgw_ctx *ctx, int kernel_class, double *total_ms, int64_t *launches);
 

@@ -43,7 +43,6 @@ struct MetricShared {
     double dr[NPAR], di[NPAR], s[NPAR];
     double F[NPAR * NPAR];
     double M[MAXDIM * MAXDIM], R[MAXDIM * MAXDIM], Y[MAXDIM * MAXDIM], Z[MAXDIM * MAXDIM], Lo[MAXDIM * MAXDIM];
-    int bad;
 };
 
 // Phase derivative of source parameter k on phase function a (cycles),
@@ -242,6 +241,7 @@ extern "C" int smcgw_local_metric(smcgw_ctx* c, int P, int D, const double* thet
     if (P == 0) return SMCGW_OK;
     hipSetDevice(c->device);
     const PrecDesc pd = prior_precision(c->prior);
+    TimedLaunch tl(c, SMCGW_KERNEL_METRIC);
     hipLaunchKernelGGL(local_metric_kernel, dim3(P), dim3(MET_THREADS), 0, c->stream, c->d_events,
                        (int)c->events.size(), c->ev_of_p, c->pmap, pd, P, theta, beta, fallback_chol, chol, fisher,
                        status);

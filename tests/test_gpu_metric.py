@@ -174,34 +174,55 @@ def test_nuts_per_particle_factor_parity(smcgw):
     assert ok.mean() >= 15 / 16
 
 
+def _golden_logz():
+    import os
+    vals = {}
+    path = os.path.join(os.path.dirname(__file__), "golden", "evidence_spec_small_mc_q_tc_phic.txt")
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            k, v = line.split()
+            vals[k] = float(v)
+    return vals["logz"], vals["stderr"]
+
+
 def test_smc_with_local_metric(smcgw):
-    """1-detector event, (Mc, q, t_c, phi_c), 256 particles: the local-metric run reaches beta = 1, needs no
-    fallback, its log Z equals the oracle's FP64 replay of its own populations, and it concentrates at the
-    injection."""
+    """1-detector event, (Mc, q, t_c, phi_c), 2048 particles, alpha = 0.5: every local-metric run reaches
+    beta = 1 without fallbacks and its log Z equals the oracle's FP64 replay of its own populations.  Against
+    the importance-sampling evidence of tests/golden (written with the oracle only): the mean of four seeds
+    within 0.3 and every run within 0.6 (the run-to-run spread of this configuration is about 0.17).
+    The population-covariance metric is run beside it for the record: on this curved posterior its
+    mutations diverge and its evidence scatters by several units between seeds."""
     from paper_2601_02336_amd import smc
     ev = event(synth.SPEC_SMALL)
     idx = CONFIG0_INDEX
     full = synth.gw_prior_for(ev)
     b = [full[i] for i in idx]
-    x0 = torch.tensor(synth.prior_draw(np.random.default_rng(11), 256, b), device="cuda")
-    lz = {}
-    for metric in ("population", "local"):
-        c = _ctx(smcgw, ev, idx, b)
-        cfg = smc.SmcConfig(alpha=0.5, step=0.5, max_depth=6, seed=1, precision=smcgw.PLAIN_FP64, record=True,
-                            metric=metric)
-        r = smc.run_smc(c, x0, cfg)
-        c.close()
-        t = O.gw_target(ev, param_index=idx)
-        beta, ref = 0.0, 0.0
-        for pop in r.populations:
-            ll = O.loglike_grad(t, pop.cpu().numpy(), want_grad=False)
-            _, beta, dz, _ = O.smc_reweight(ll, beta, 0.5)
-            ref += dz
-        print(f"{metric}: log Z {r.logz:.5f} (replay {ref:.5f}), {r.n_iter} iterations, "
-              f"{sum(r.n_leapfrog)} leapfrog steps, {sum(r.divergent)} divergent, "
-              f"local fallbacks {r.local_metric_fallbacks}", flush=True)
-        assert r.betas[-1] == 1.0
-        assert abs(r.logz - ref) <= 1e-8
+    ref_logz, ref_se = _golden_logz()
+    t = O.gw_target(ev, param_index=idx)
+    got = {}
+    for metric, seeds in (("population", (1, 2)), ("local", (1, 2, 3, 4))):
+        for seed in seeds:
+            x0 = torch.tensor(synth.prior_draw(np.random.default_rng(10 + seed), 2048, b), device="cuda")
+            c = _ctx(smcgw, ev, idx, b)
+            cfg = smc.SmcConfig(alpha=0.5, step=0.5, max_depth=8, seed=seed, precision=smcgw.PLAIN_FP64,
+                                record=True, metric=metric)
+            r = smc.run_smc(c, x0, cfg)
+            c.close()
+            beta, replay = 0.0, 0.0
+            for pop in r.populations:
+                ll = O.loglike_grad(t, pop.cpu().numpy(), want_grad=False)
+                _, beta, dz, _ = O.smc_reweight(ll, beta, 0.5)
+                replay += dz
+            print(f"{metric} seed {seed}: log Z {r.logz:.4f} (replay {replay:.4f}, reference {ref_logz:.4f} +- "
+                  f"{ref_se:.4f}), {r.n_iter} iterations, {sum(r.n_leapfrog)} leapfrog steps, "
+                  f"{sum(r.divergent)} divergent, local fallbacks {r.local_metric_fallbacks}", flush=True)
+            assert r.betas[-1] == 1.0
+            assert abs(r.logz - replay) <= 1e-8
+            got.setdefault(metric, []).append(r)
+    for r in got["local"]:
+        assert r.local_metric_fallbacks == 0
+        assert abs(r.logz - ref_logz) <= 0.6
         assert abs(np.median(r.theta.cpu().numpy()[:, 0]) - ev.theta_inj[0]) < 1.0
-        lz[metric] = r.logz
-    assert lz and r.local_metric_fallbacks == 0
+    mean = float(np.mean([r.logz for r in got["local"]]))
+    print(f"local metric: mean log Z {mean:.4f}, reference {ref_logz:.4f}", flush=True)
+    assert abs(mean - ref_logz) <= 0.3
