@@ -19,17 +19,17 @@
 //                + 4 pi^2 |P'_d|^2 g_kd^T W_d g_ld ],
 //   s_dk = Im(conj(D_dk) P'_d),  g_kd[a] = dgamma_a/dtheta_k (detector d),
 // with W_d the per-event moments sum_j w_dj a_j^2 g_a(f_j) g_b(f_j) built once
-// with the bin tables.  Then, per particle, M = R R^T, M^{-1} by column
-// solves, and the lower Cholesky factor of M^{-1} that the NUTS kernel takes.
+// with the bin tables.  Then, per particle, the lower Cholesky factor of
+// M^{-1} that the NUTS kernel takes.
 #include "coeffs.h"
 #include "common.h"
 #include "context.h"
 
 namespace smcgw {
 
-constexpr int MET_THREADS = 64;   // one wavefront per particle
+constexpr int MET_THREADS = 128;   // two wavefronts per particle
 constexpr int NPAIR = NPAR * (NPAR + 1) / 2;
-constexpr int MET_SLOTS = (NPAIR + MET_THREADS - 1) / MET_THREADS;
+static_assert(NPAIR <= MET_THREADS && NPAR * NGEO <= MET_THREADS, "one thread per pair and per Jacobian entry");
 
 struct PrecDesc {
     double prec[MAXDIM];   // prior precision of each sampled coordinate
@@ -37,12 +37,13 @@ struct PrecDesc {
 
 struct MetricShared {
     double cb[CB_SIZE];
-    double W[NGEO * NGEO];
+    double W[MAXDET * NGEO * NGEO];
     double gam[NPAR][NGEO];   // d gamma_a / d theta_k for the current detector
     double wg[NPAR][NGEO];    // W_d gamma_k
     double dr[NPAR], di[NPAR], s[NPAR];
     double F[NPAR * NPAR];
-    double M[MAXDIM * MAXDIM], R[MAXDIM * MAXDIM], Y[MAXDIM * MAXDIM], Z[MAXDIM * MAXDIM], Lo[MAXDIM * MAXDIM];
+    double M[MAXDIM * MAXDIM], R[MAXDIM * MAXDIM], Y[MAXDIM * MAXDIM];
+    ExtAngles ang;
 };
 
 // Phase derivative of source parameter k on phase function a (cycles),
@@ -63,28 +64,36 @@ __device__ __forceinline__ void pair_of(int e, int& k, int& l) {
 }
 
 // Lower Cholesky factor Lo of the D x D matrix A (row stride MAXDIM), one
-// row per lane; false (uniform over the wavefront) when a pivot is not
+// row per thread; false (uniform over the workgroup) when a pivot is not
 // positive.  Each entry is formed in the textbook order: the matrix entry
 // minus the products of the finished columns, k ascending.
-__device__ bool wave_cholesky(const double* A, double* Lo, int D, int lane) {
-    for (int i = lane; i < MAXDIM * MAXDIM; i += MET_THREADS) Lo[i] = 0.0;
+__device__ bool block_cholesky(const double* A, double* Lo, int D, int tid) {
+    for (int i = tid; i < MAXDIM * MAXDIM; i += MET_THREADS) Lo[i] = 0.0;
     __syncthreads();
     for (int j = 0; j < D; ++j) {
         double sjj = A[j * MAXDIM + j];
         for (int k = 0; k < j; ++k) sjj -= Lo[j * MAXDIM + k] * Lo[j * MAXDIM + k];
         if (!(sjj > 0.0)) return false;
         const double ljj = sqrt(sjj);
-        if (lane > j && lane < D) {
-            double t = A[lane * MAXDIM + j];
-            for (int k = 0; k < j; ++k) t -= Lo[lane * MAXDIM + k] * Lo[j * MAXDIM + k];
-            Lo[lane * MAXDIM + j] = t / ljj;
+        if (tid > j && tid < D) {
+            double t = A[tid * MAXDIM + j];
+            for (int k = 0; k < j; ++k) t -= Lo[tid * MAXDIM + k] * Lo[j * MAXDIM + k];
+            Lo[tid * MAXDIM + j] = t / ljj;
         }
-        if (lane == j) Lo[j * MAXDIM + j] = ljj;
+        if (tid == j) Lo[j * MAXDIM + j] = ljj;
         __syncthreads();
     }
     return true;
 }
 
+// One workgroup of two wavefronts per particle.  The coefficient block is
+// built as in the NUTS leaf: the intrinsic part with one tangent per lane on
+// wavefront 0, the extrinsic part (shared sin / cos in parallel lanes, then
+// one detector and tangent per lane) on wavefront 1.  The lower Cholesky
+// factor of M^{-1} comes from the order-reversed matrix: with J the
+// reversal permutation and J M J = R R^T, M^{-1} = (J R^-T J)(J R^-T J)^T and
+// J R^-T J is lower triangular with a positive diagonal, so it is that
+// factor; it needs one Cholesky and one triangular inverse.
 __global__ __launch_bounds__(MET_THREADS) void local_metric_kernel(const DevEvent* __restrict__ evs, int n_events,
                                                                   const int32_t* __restrict__ ev_of_p, ParamMap pm,
                                                                   PrecDesc pd, int P, const double* __restrict__ theta,
@@ -92,116 +101,128 @@ __global__ __launch_bounds__(MET_THREADS) void local_metric_kernel(const DevEven
                                                                   double* __restrict__ chol, double* __restrict__ fisher,
                                                                   int32_t* __restrict__ status) {
     __shared__ MetricShared S;
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int p = blockIdx.x;
     const int D = pm.dim;
     const DevEvent& ev = evs[event_index(ev_of_p, p, n_events)];
+    const int n_det = ev.n_det;
 
-    // coefficient block of the particle (one lane, FP64; the same prologue
-    // as the likelihood)
-    if (lane == 0) {
+    for (int i = tid; i < n_det * NGEO * NGEO; i += MET_THREADS) S.W[i] = ev.wmom[i];
+    if (wave == 0 && lane < 4) {
         double th[NPAR];
         expand_params(pm, theta + (size_t)p * D, th);
-        prep_intrinsic(ev, th, S.cb);
-        prep_extrinsic(ev, th, S.cb);
+        prep_intrinsic_n<1>(ev, th, S.cb, lane, lane == 0);
+    } else if (wave == 1) {
+        double th[NPAR];
+        if (lane <= 2 * MAXDET) expand_params(pm, theta + (size_t)p * D, th);
+        if (lane < ANG_COUNT) {
+            double sn, cs;
+            sincos(extrinsic_angle(ev, th, lane), &sn, &cs);
+            S.ang.sc[lane][0] = sn;
+            S.ang.sc[lane][1] = cs;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (lane < 2 * MAXDET) {
+            const ExtAngles ang = S.ang;
+            const int k = lane / MAXDET;
+            prep_extrinsic_det_n<1>(ev, th, ang, S.cb, lane - k * MAXDET, k, k == 0);
+        } else if (lane == 2 * MAXDET) {
+            prep_extrinsic_common(ev, th, S.cb);
+        }
     }
     __syncthreads();
     const double amp = S.cb[CB_AMP];
 
-    double acc[MET_SLOTS];
-#pragma unroll
-    for (int t = 0; t < MET_SLOTS; ++t) acc[t] = 0.0;
-    for (int d = 0; d < ev.n_det; ++d) {
+    double acc = 0.0;   // F entry of pair tid (k <= l)
+    for (int d = 0; d < n_det; ++d) {
+        const double* W = S.W + d * NGEO * NGEO;
         const double qr = amp * S.cb[CB_PR + d], qi = amp * S.cb[CB_PI + d];
-        for (int i = lane; i < NGEO * NGEO; i += MET_THREADS) S.W[i] = ev.wmom[(size_t)d * NGEO * NGEO + i];
-        for (int i = lane; i < NPAR * NGEO; i += MET_THREADS) S.gam[i / NGEO][i % NGEO] = phase_jac(S.cb, d, i / NGEO, i % NGEO);
-        if (lane < NPAR) {
+        if (tid < NPAR * NGEO) S.gam[tid / NGEO][tid % NGEO] = phase_jac(S.cb, d, tid / NGEO, tid % NGEO);
+        if (tid < NPAR) {
             double xr = 0.0, xi = 0.0;
-            if (lane == P_MC || lane == P_DL) {
-                const double g = lane == P_MC ? S.cb[CB_DLNCA_MC] : S.cb[CB_DLNCA_DL];
+            if (tid == P_MC || tid == P_DL) {
+                const double g = tid == P_MC ? S.cb[CB_DLNCA_MC] : S.cb[CB_DLNCA_DL];
                 xr = g * qr;
                 xi = g * qi;
-            } else if (lane == P_IOTA || lane == P_PSI || lane == P_RA || lane == P_DEC) {
-                const int m = lane == P_IOTA ? 0 : lane == P_PSI ? 1 : lane == P_RA ? 2 : 3;
+            } else if (tid == P_IOTA || tid == P_PSI || tid == P_RA || tid == P_DEC) {
+                const int m = tid == P_IOTA ? 0 : tid == P_PSI ? 1 : tid == P_RA ? 2 : 3;
                 xr = amp * S.cb[CB_DPR + 4 * d + m];
                 xi = amp * S.cb[CB_DPI + 4 * d + m];
             }
-            S.dr[lane] = xr;
-            S.di[lane] = xi;
-            S.s[lane] = xr * qi - xi * qr;
+            S.dr[tid] = xr;
+            S.di[tid] = xi;
+            S.s[tid] = xr * qi - xi * qr;
         }
         __syncthreads();
-        for (int i = lane; i < NPAR * NGEO; i += MET_THREADS) {
-            const int k = i / NGEO, a = i % NGEO;
+        if (tid < NPAR * NGEO) {
+            const int k = tid / NGEO, a = tid % NGEO;
             double v = 0.0;
-            for (int b = 0; b < NGEO; ++b) v = fma(S.W[a * NGEO + b], S.gam[k][b], v);
+            for (int b = 0; b < NGEO; ++b) v = fma(W[a * NGEO + b], S.gam[k][b], v);
             S.wg[k][a] = v;
         }
         __syncthreads();
-        const double q2 = qr * qr + qi * qi;
-#pragma unroll
-        for (int t = 0; t < MET_SLOTS; ++t) {
-            const int e = lane + t * MET_THREADS;
-            if (e < NPAIR) {
-                int k, l;
-                pair_of(e, k, l);
-                double gwg = 0.0;
-                for (int a = 0; a < NGEO; ++a) gwg = fma(S.gam[k][a], S.wg[l][a], gwg);
-                acc[t] += S.W[0] * (S.dr[k] * S.dr[l] + S.di[k] * S.di[l])
-                        + TWO_PI * (S.s[k] * S.wg[l][0] + S.s[l] * S.wg[k][0])
-                        + (4.0 * PI * PI) * q2 * gwg;
-            }
+        if (tid < NPAIR) {
+            int k, l;
+            pair_of(tid, k, l);
+            double gwg = 0.0;
+            for (int a = 0; a < NGEO; ++a) gwg = fma(S.gam[k][a], S.wg[l][a], gwg);
+            acc += W[0] * (S.dr[k] * S.dr[l] + S.di[k] * S.di[l])
+                 + TWO_PI * (S.s[k] * S.wg[l][0] + S.s[l] * S.wg[k][0])
+                 + (4.0 * PI * PI) * (qr * qr + qi * qi) * gwg;
         }
         __syncthreads();
     }
-#pragma unroll
-    for (int t = 0; t < MET_SLOTS; ++t) {
-        const int e = lane + t * MET_THREADS;
-        if (e < NPAIR) {
-            int k, l;
-            pair_of(e, k, l);
-            S.F[k * NPAR + l] = acc[t];
-            S.F[l * NPAR + k] = acc[t];
-        }
+    if (tid < NPAIR) {
+        int k, l;
+        pair_of(tid, k, l);
+        S.F[k * NPAR + l] = acc;
+        S.F[l * NPAR + k] = acc;
     }
     __syncthreads();
 
-    // M over the sampled coordinates
-    for (int i = lane; i < MAXDIM * MAXDIM; i += MET_THREADS) {
+    // J M J over the sampled coordinates (rows and columns in reverse order)
+    for (int i = tid; i < MAXDIM * MAXDIM; i += MET_THREADS) {
         const int a = i / MAXDIM, b = i % MAXDIM;
         double v = 0.0;
         if (a < D && b < D) {
-            const double f = S.F[pm.idx[a] * NPAR + pm.idx[b]];
-            v = beta * f + (a == b ? pd.prec[a] : 0.0);
-            if (fisher) fisher[(size_t)p * D * D + a * D + b] = f;
+            const int ra = D - 1 - a, rb = D - 1 - b;
+            const double f = S.F[pm.idx[ra] * NPAR + pm.idx[rb]];
+            v = beta * f + (a == b ? pd.prec[ra] : 0.0);
+            if (fisher) fisher[(size_t)p * D * D + ra * D + rb] = f;
         }
         S.M[i] = v;
     }
     __syncthreads();
-    bool ok = wave_cholesky(S.M, S.R, D, lane);
+    bool ok = block_cholesky(S.M, S.R, D, tid);
     if (ok) {
-        // M^{-1} column by column: lane c solves R y = e_c, then R^T z = y.
-        if (lane < D) {
-            const int c = lane;
+        // X = R^{-1}, thread c solving column c by forward substitution
+        if (tid < D) {
+            const int c = tid;
             for (int r = 0; r < D; ++r) {
                 double v = (r == c) ? 1.0 : 0.0;
-                for (int k = 0; k < r; ++k) v -= S.R[r * MAXDIM + k] * S.Y[k * MAXDIM + c];
-                S.Y[r * MAXDIM + c] = v / S.R[r * MAXDIM + r];
-            }
-            for (int r = D - 1; r >= 0; --r) {
-                double v = S.Y[r * MAXDIM + c];
-                for (int k = r + 1; k < D; ++k) v -= S.R[k * MAXDIM + r] * S.Z[k * MAXDIM + c];
-                S.Z[r * MAXDIM + c] = v / S.R[r * MAXDIM + r];
+                for (int k = c; k < r; ++k) v -= S.R[r * MAXDIM + k] * S.Y[k * MAXDIM + c];
+                S.Y[r * MAXDIM + c] = r < c ? 0.0 : v / S.R[r * MAXDIM + r];
             }
         }
         __syncthreads();
-        ok = wave_cholesky(S.Z, S.Lo, D, lane);
     }
-    for (int i = lane; i < D * D; i += MET_THREADS) {
+    // factor L[i][j] = X[D-1-j][D-1-i]; a non-finite entry takes the fallback too
+    bool bad_entry = false;
+    if (ok)
+        for (int i = tid; i < D * D; i += MET_THREADS) {
+            const double v = S.Y[(D - 1 - i % D) * MAXDIM + (D - 1 - i / D)];
+            bad_entry |= !isfinite(v);
+        }
+    ok = ok && !__syncthreads_or(bad_entry);
+    for (int i = tid; i < D * D; i += MET_THREADS) {
         const int a = i / D, b = i % D;
-        chol[(size_t)p * D * D + i] = ok ? S.Lo[a * MAXDIM + b] : fallback ? fallback[i] : (a == b ? 1.0 : 0.0);
+        chol[(size_t)p * D * D + i] = ok ? S.Y[(D - 1 - b) * MAXDIM + (D - 1 - a)]
+                                    : fallback ? fallback[i] : (a == b ? 1.0 : 0.0);
     }
-    if (status && lane == 0) status[p] = ok ? 0 : 1;
+    if (status && tid == 0) status[p] = ok ? 0 : 1;
 }
 
 // Prior precision of each sampled coordinate: 12 / (hi - lo)^2 (uniform),
