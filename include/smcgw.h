@@ -237,6 +237,25 @@ int smcgw_smc_reweight_resample(smcgw_ctx *ctx, int P, int D, double beta_prev, 
                                 uint64_t iteration, double *theta, double *logl, double *grad, int32_t *carry,
                                 int32_t *ancestors, double *beta_next_host, double *dlogz_host);
 
+/* Sample recycling (Sec. 5, "Samples recycling"): the populations left by
+ * the mutations of iterations t = 1..T are pooled and read as draws of the
+ * mixture (1/T) sum_t p_t, with p_t = L^beta_t pi / Z_t normalised by the
+ * evidence reached at iteration t.  Each pooled point gets the weight of the
+ * final target against the mixture,
+ *   log w = log L - log Z_T - log((1/T) sum_t L^beta_t / Z_t)
+ * (NaN or -inf log L: weight zero), and rejection sampling keeps point i when
+ * its Philox uniform (seed; index 0, particle i, iteration 0) is below
+ * w_i / max w, giving i.i.d. draws of p_T.  logl [T][N] (device) holds the
+ * log-likelihoods of the pooled points (pool index i = t N + n);
+ * betas_host [T] and logz_host [T] (host) the temperatures and running log
+ * evidence of the iterations.  logw [T*N] (device) receives the log weights,
+ * kept [T*N] (device) the kept pool indices in increasing order, of which
+ * there are *n_kept_host; *ess_host receives (sum w)^2 / sum w^2.
+ * T*N must not exceed 2^31 - 1.  Synchronises. */
+int smcgw_recycle(smcgw_ctx *ctx, int T, int N, const double *logl, const double *betas_host,
+                  const double *logz_host, uint64_t seed, double *logw, int32_t *kept, int64_t *n_kept_host,
+                  double *ess_host);
+
 /* ------------------------------------------------------------ options
  * Launch-shape options of a context (chosen by the autotuner or by hand).
  *   SMCGW_OPT_NUTS_WAVES: wavefronts that share one particle's bin loop in the

@@ -382,7 +382,7 @@ void philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t 
     out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
-enum { PURPOSE_MOMENTUM = 1, PURPOSE_DOUBLING = 2, PURPOSE_LEAF = 3, PURPOSE_RESAMPLE = 4 };
+enum { PURPOSE_MOMENTUM = 1, PURPOSE_DOUBLING = 2, PURPOSE_LEAF = 3, PURPOSE_RESAMPLE = 4, PURPOSE_RECYCLE = 5 };
 
 // Two uniforms in [0, 1) with 53 random bits each.
 void uniforms2(uint64_t seed, uint32_t index, uint32_t particle, uint64_t iteration, uint32_t purpose, double u[2]) {
@@ -885,6 +885,49 @@ int orc_local_metric(const orc_target* t, int P, const double* x, double beta, c
         for (int k = 0; k < D * D; ++k) chol[(size_t)i * D * D + k] = Lo[k];
     }
     return bad;
+}
+
+// Sample recycling (Sec. 5, "Samples recycling"): the populations left by the
+// mutations of iterations t = 1..T are pooled and read as draws of the
+// mixture (1/T) sum_t p_t, each p_t = L^beta_t pi / Z_t normalised with the
+// evidence reached at iteration t.  A pooled point's importance weight for
+// the final target p_T = L pi / Z_T against that mixture is
+//   w = (L / Z_T) / ((1/T) sum_t L^beta_t / Z_t)
+// (the prior cancels); rejection sampling then keeps point i when
+// u_i < w_i / max_j w_j, giving i.i.d. draws of p_T.  logl [T][N] (NaN or
+// -inf: weight zero), betas [T], logz [T] = log Z_t.  Outputs: logw [T*N],
+// accepted [T*N] (the kept pool indices in increasing order, *n_accepted of
+// them) and *ess = (sum w)^2 / sum w^2.  u_i is the first uniform of the
+// Philox pair (seed; index 0, particle i, iteration 0, purpose RECYCLE).
+int orc_recycle(int T, int N, const double* logl, const double* betas, const double* logz, uint64_t seed,
+                double* logw, int32_t* accepted, int* n_accepted, double* ess) {
+    if (T < 1 || N < 1) return -1;
+    const size_t n = (size_t)T * N;
+    for (size_t i = 0; i < n; ++i) {
+        const double l = logl[i];
+        if (!(l > -INFINITY)) { logw[i] = -INFINITY; continue; }   // also NaN
+        double m = -INFINITY;
+        for (int t = 0; t < T; ++t) m = std::max(m, betas[t] * l - logz[t]);
+        double s = 0.0;
+        for (int t = 0; t < T; ++t) s += std::exp(betas[t] * l - logz[t] - m);
+        const double log_mix = m + std::log(s) - std::log((double)T);
+        logw[i] = l - logz[T - 1] - log_mix;
+    }
+    double wmax = -INFINITY;
+    for (size_t i = 0; i < n; ++i) wmax = std::max(wmax, logw[i]);
+    double s1 = 0.0, s2 = 0.0;
+    int k = 0;
+    for (size_t i = 0; i < n; ++i) {
+        const double w = std::exp(logw[i] - wmax);
+        s1 += w;
+        s2 += w * w;
+        double u[2];
+        uniforms2(seed, 0u, (uint32_t)i, 0u, PURPOSE_RECYCLE, u);
+        if (u[0] < w) accepted[k++] = (int32_t)i;
+    }
+    *n_accepted = k;
+    *ess = s2 > 0.0 ? s1 * s1 / s2 : 0.0;
+    return 0;
 }
 
 // A full SMC run: adaptive tempering, multinomial resampling, covariance mass

@@ -263,6 +263,23 @@ def local_metric(target: Target, x, beta: float, want_fisher: bool = True, fallb
     return st, F, L
 
 
+def recycle(logl, betas, logz, seed: int):
+    """Sample recycling (Sec. 5): logl [T][N] of the populations after each iteration's mutation, betas [T],
+    logz [T] (running log evidence).  Returns (logw [T*N], accepted pool indices, Kish ESS)."""
+    ll = _f64(logl)
+    T, N = ll.shape
+    b = _f64(betas)
+    z = _f64(logz)
+    logw = np.zeros(T * N)
+    acc = np.zeros(T * N, np.int32)
+    k = C.c_int()
+    ess = C.c_double()
+    rc = lib().orc_recycle(C.c_int(T), C.c_int(N), _dp(ll), _dp(b), _dp(z), C.c_uint64(seed), _dp(logw), _ip(acc),
+                           C.byref(k), C.byref(ess))
+    assert rc == 0
+    return logw, acc[:k.value].copy(), ess.value
+
+
 def mass_matrix(x, shrink: float):
     x = _f64(x)
     P, D = x.shape

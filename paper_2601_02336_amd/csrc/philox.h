@@ -9,7 +9,7 @@
 
 namespace smcgw {
 
-enum { RNG_MOMENTUM = 1, RNG_DOUBLING = 2, RNG_LEAF = 3, RNG_RESAMPLE = 4 };
+enum { RNG_MOMENTUM = 1, RNG_DOUBLING = 2, RNG_LEAF = 3, RNG_RESAMPLE = 4, RNG_RECYCLE = 5 };
 
 __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
                                               uint32_t k1, uint32_t out[4]) {

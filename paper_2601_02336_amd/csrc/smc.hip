@@ -1,11 +1,13 @@
 // SMC kernels: adaptive tempering, evidence increment, multinomial
-// resampling with gather (arXiv:2601.02336, Sec. 3, Eqs. 4-8) and the
-// population mass matrix (Sec. 5, covariance reading of the metric).
+// resampling with gather (arXiv:2601.02336, Sec. 3, Eqs. 4-8), the
+// population mass matrix (Sec. 5, covariance reading of the metric) and
+// sample recycling (Sec. 5, "Samples recycling").
 //
 // All reductions run inside one workgroup in a fixed order (no atomics), in
 // FP64, so beta, the evidence increment and the ancestors are reproducible.
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 
 #include "common.h"
@@ -374,6 +376,88 @@ __global__ __launch_bounds__(256) void analytic_loglike_kernel(int kind, int P, 
     logl[i] = ll;
 }
 
+// Sample recycling (Sec. 5, "Samples recycling").  The populations left by
+// the mutations of iterations t = 1..T form a pool read as draws of the
+// mixture (1/T) sum_t p_t, p_t = L^beta_t pi / Z_t.  Point i's weight for the
+// final target against the mixture is
+//   log w_i = log L_i - log Z_T - log((1/T) sum_t L_i^beta_t / Z_t),
+// one lane per point (the prior cancels; NaN or -inf log L: weight zero).
+__global__ __launch_bounds__(256) void recycle_weights_kernel(const double* __restrict__ logl, int n, int T,
+                                                              const double* __restrict__ bz,
+                                                              double* __restrict__ logw) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double l = logl[i];
+    if (!(l > -INFINITY)) {
+        logw[i] = -INFINITY;
+        return;
+    }
+    const double* betas = bz;
+    const double* logz = bz + T;
+    double m = -INFINITY;
+    for (int t = 0; t < T; ++t) m = fmax(m, betas[t] * l - logz[t]);
+    double s = 0.0;
+    for (int t = 0; t < T; ++t) s += exp(betas[t] * l - logz[t] - m);
+    logw[i] = l - logz[T - 1] - (m + log(s) - log((double)T));
+}
+
+// Rejection sampling over the pool in one workgroup: point i is kept when
+// its Philox uniform (index 0, particle i, iteration 0, purpose RECYCLE) is
+// below w_i / max w.  Thread t owns the contiguous chunk [t ch, (t+1) ch), so
+// the kept indices come out in increasing order after an exclusive scan of
+// the per-thread counts.  out[0] = kept count, out[1] = Kish ESS
+// (sum w)^2 / sum w^2, out[2] = max log w.
+__global__ __launch_bounds__(SMC_THREADS) void recycle_select_kernel(const double* __restrict__ logw, int n,
+                                                                     uint64_t seed, int32_t* __restrict__ kept,
+                                                                     double* __restrict__ out) {
+    __shared__ double red[2 * SMC_WAVES];
+    __shared__ double tot[2];
+    __shared__ int cnt[SMC_THREADS + 1];
+    const int tid = threadIdx.x;
+    const int ch = (n + SMC_THREADS - 1) / SMC_THREADS;
+    const int i0 = min(n, tid * ch), i1 = min(n, i0 + ch);
+    double m = -INFINITY;
+    for (int i = i0; i < i1; ++i) m = fmax(m, logw[i]);
+    const double wmax = block_max(m, red);
+    const bool any = wmax > -INFINITY;
+    double v[2] = {0.0, 0.0};
+    int k = 0;
+    if (any)
+        for (int i = i0; i < i1; ++i) {
+            const double w = exp(logw[i] - wmax);
+            v[0] += w;
+            v[1] += w * w;
+            double u, u1;
+            rng_uniform2(seed, 0u, (uint32_t)i, 0, RNG_RECYCLE, u, u1);
+            k += u < w ? 1 : 0;
+        }
+    block_sums<2>(v, red, tot);
+    cnt[tid] = k;
+    __syncthreads();
+    if (tid == 0) {
+        int s = 0;
+        for (int t = 0; t < SMC_THREADS; ++t) {
+            const int c = cnt[t];
+            cnt[t] = s;
+            s += c;
+        }
+        cnt[SMC_THREADS] = s;
+    }
+    __syncthreads();
+    int o = cnt[tid];
+    if (any)
+        for (int i = i0; i < i1; ++i) {
+            double u, u1;
+            rng_uniform2(seed, 0u, (uint32_t)i, 0, RNG_RECYCLE, u, u1);
+            if (u < exp(logw[i] - wmax)) kept[o++] = i;
+        }
+    if (tid == 0) {
+        out[0] = (double)cnt[SMC_THREADS];
+        out[1] = tot[1] > 0.0 ? tot[0] * tot[0] / tot[1] : 0.0;
+        out[2] = wmax;
+    }
+}
+
 // Scratch of the sampler entry points (device), grown on demand.
 void* sampler_scratch(smcgw_ctx* c, size_t bytes) {
     if (bytes <= c->sampler_bytes) return c->d_sampler;
@@ -512,4 +596,33 @@ extern "C" int smcgw_target_loglike_grad(smcgw_ctx* c, int P, const double* thet
     hipLaunchKernelGGL(analytic_loglike_kernel, dim3((P + 255) / 256), dim3(256), 0, c->stream, c->target.kind, P,
                        c->target.dim, c->target.params, theta, logl, grad);
     return hipGetLastError() == hipSuccess ? SMCGW_OK : SMCGW_ERR_HIP;
+}
+
+extern "C" int smcgw_recycle(smcgw_ctx* c, int T, int N, const double* logl, const double* betas_host,
+                             const double* logz_host, uint64_t seed, double* logw, int32_t* kept,
+                             int64_t* n_kept_host, double* ess_host) {
+    if (!c || T < 1 || N < 1 || (int64_t)T * N > INT32_MAX || !logl || !betas_host || !logz_host || !logw || !kept ||
+        !n_kept_host || !ess_host)
+        return SMCGW_ERR_INVALID;
+    for (int t = 0; t < T; ++t)
+        if (!(betas_host[t] >= 0.0 && betas_host[t] <= 1.0) || !std::isfinite(logz_host[t])) return SMCGW_ERR_INVALID;
+    hipSetDevice(c->device);
+    const int n = T * N;
+    char* s = (char*)sampler_scratch(c, 64 * sizeof(double) + 2 * (size_t)T * sizeof(double));
+    double* hp = pinned(c);
+    if (!s || !hp) return SMCGW_ERR_OOM;
+    double* out = (double*)s;
+    double* bz = out + 64;
+    if (hipMemcpyAsync(bz, betas_host, T * sizeof(double), hipMemcpyHostToDevice, c->stream) ||
+        hipMemcpyAsync(bz + T, logz_host, T * sizeof(double), hipMemcpyHostToDevice, c->stream))
+        return SMCGW_ERR_HIP;
+    hipLaunchKernelGGL(recycle_weights_kernel, dim3((n + 255) / 256), dim3(256), 0, c->stream, logl, n, T, bz, logw);
+    hipLaunchKernelGGL(recycle_select_kernel, dim3(1), dim3(SMC_THREADS), 0, c->stream, logw, n, seed, kept, out);
+    if (hipGetLastError() != hipSuccess) return SMCGW_ERR_HIP;
+    if (hipMemcpyAsync(hp, out, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream) ||
+        hipStreamSynchronize(c->stream))
+        return SMCGW_ERR_HIP;
+    *n_kept_host = (int64_t)hp[0];
+    *ess_host = hp[1];
+    return SMCGW_OK;
 }

@@ -33,6 +33,7 @@ class SmcConfig:
     record: bool = False          # keep each iteration's population (for replay checks)
     work_hint: bool = True        # start the particles whose ancestors took the longest trees first
     metric: str = "population"    # "population": one covariance metric; "local": one metric per particle
+    recycle: bool = False         # pool every iteration's population and draw i.i.d. samples from it
 
 
 @dataclasses.dataclass
@@ -51,6 +52,8 @@ class SmcResult:
     populations: Optional[List[torch.Tensor]] = None   # population entering each reweight
     mass_matrix_fallbacks: int = 0                      # iterations whose covariance needed the diagonal
     local_metric_fallbacks: int = 0                     # particles whose local metric was not positive definite
+    recycled: Optional[torch.Tensor] = None             # i.i.d. posterior draws from the recycled pool
+    recycled_ess: float = 0.0                           # Kish ESS of the pool's recycling weights
 
 
 def run_smc(ctx: "smcgw.Context", theta0: torch.Tensor, cfg: SmcConfig) -> SmcResult:
@@ -63,6 +66,7 @@ def run_smc(ctx: "smcgw.Context", theta0: torch.Tensor, cfg: SmcConfig) -> SmcRe
     betas, dlogzs, nlf, depths, divs = [], [], [], [], []
     fallbacks = 0
     local_bad = []
+    pool_x, pool_ll = [], []
     pops = [] if cfg.record else None
     hint = None   # leapfrog counts of the last transition, resampled with the particles
     mm_status = torch.zeros(1, dtype=torch.int32, device=theta.device)   # 1: diagonal mass-matrix fallback
@@ -81,6 +85,9 @@ def run_smc(ctx: "smcgw.Context", theta0: torch.Tensor, cfg: SmcConfig) -> SmcRe
         out = ctx.nuts_step(theta, logl, grad, L, step=cfg.step, beta=b, seed=cfg.seed, iteration=it,
                             max_depth=cfg.max_depth, uturn=cfg.uturn, precision=cfg.precision, work_hint=hint)
         hint = out["n_leapfrog"] if cfg.work_hint else None
+        if cfg.recycle:
+            pool_x.append(theta.clone())
+            pool_ll.append(logl.clone())
         betas.append(b)
         dlogzs.append(dz)
         nlf.append(int(out["n_leapfrog"].sum().item()))
@@ -89,7 +96,16 @@ def run_smc(ctx: "smcgw.Context", theta0: torch.Tensor, cfg: SmcConfig) -> SmcRe
         fallbacks += int(mm_status.item())
         beta = b
         it += 1
+    recycled, ress = None, 0.0
+    if cfg.recycle and pool_ll:
+        # Sec. 5, "Samples recycling": every mutated population is a draw of its p_t
+        running, acc = [], 0.0
+        for dz in dlogzs:
+            acc += dz
+            running.append(acc)
+        _, kept, ress = ctx.recycle(torch.stack(pool_ll), betas, running, cfg.seed)
+        recycled = torch.cat(pool_x)[kept.long()]
     torch.cuda.synchronize()
     n_local_bad = int(sum(int(x.item()) for x in local_bad))
     return SmcResult(logz, betas, dlogzs, it, theta, logl, grad, nlf, depths, divs, time.perf_counter() - t0, pops,
-                     fallbacks, n_local_bad)
+                     fallbacks, n_local_bad, recycled, ress)

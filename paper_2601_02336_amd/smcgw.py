@@ -90,6 +90,7 @@ def lib():
         L.smcgw_target_loglike_grad.argtypes = [vp, i, vp, vp, vp, i]
         L.smcgw_mass_matrix.argtypes = [vp, i, i, vp, d, vp, vp, vp]
         L.smcgw_local_metric.argtypes = [vp, i, i, vp, d, vp, vp, vp, vp]
+        L.smcgw_recycle.argtypes = [vp, i, i, vp, vp, vp, u64, vp, vp, C.POINTER(C.c_int64), C.POINTER(d)]
         L.smcgw_nuts_step.argtypes = [vp, i, i, vp, vp, vp, vp, C.POINTER(NutsParams), vp, vp, i, vp, vp, vp, vp]
         L.smcgw_timing_enable.argtypes = [vp, i]
         L.smcgw_autotune_nuts.argtypes = [vp, i, i, vp, vp, vp, vp, C.POINTER(NutsParams), i, i, C.POINTER(i),
@@ -276,6 +277,25 @@ class Context:
         _check("smcgw_local_metric", lib().smcgw_local_metric(self._h, P, D, _ptr(theta), beta, _ptr(fallback),
                                                               _ptr(L), _ptr(F), _ptr(st)))
         return L, F, st
+
+    def recycle(self, logl_pool: torch.Tensor, betas: Sequence[float], logz: Sequence[float], seed: int):
+        """Sample recycling over the pool logl_pool [T][N] (device): returns (log weights [T*N], kept pool
+        indices (device int32, increasing), Kish ESS).  Synchronises."""
+        logl_pool = _dev(logl_pool, torch.float64, "logl_pool")
+        T, N = logl_pool.shape
+        b = np.ascontiguousarray(betas, dtype=np.float64)
+        z = np.ascontiguousarray(logz, dtype=np.float64)
+        if b.shape != (T,) or z.shape != (T,):
+            raise ValueError("betas and logz need one entry per pooled iteration")
+        logw = torch.empty(T * N, dtype=torch.float64, device=logl_pool.device)
+        kept = torch.empty(T * N, dtype=torch.int32, device=logl_pool.device)
+        nk = C.c_int64()
+        ess = C.c_double()
+        self._stream()
+        _check("smcgw_recycle", lib().smcgw_recycle(self._h, T, N, _ptr(logl_pool), b.ctypes.data_as(C.c_void_p),
+                                                    z.ctypes.data_as(C.c_void_p), seed, _ptr(logw), _ptr(kept),
+                                                    C.byref(nk), C.byref(ess)))
+        return logw, kept[:nk.value], ess.value
 
     def nuts_step(self, theta: torch.Tensor, logl: torch.Tensor, grad: torch.Tensor, chol: torch.Tensor,
                   step: float, beta: float, seed: int, iteration: int, max_depth: int = 10, uturn: bool = True,
