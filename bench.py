@@ -332,6 +332,15 @@ def main():
             ctx3.set_option(smcgw.OPT_NUTS_WAVES, args.waves)
             e3, d3, k3, n3, b3, _, m3, mn3 = run_smc_steps(smcgw, ctx3, x3, prec, args, args.warmup, args.steps,
                                                            True, metric="local")
+            # sample recycling over a pool of 30 iterations of this population size (post-processing)
+            pool = torch.randn(30, P, dtype=torch.float64, device="cuda") - 50.0
+            bts = [min(1.0, 0.001 * 1.3 ** t) for t in range(29)] + [1.0]
+            lzs = [-0.1 * t for t in range(30)]
+            ctx3.recycle(pool, bts, lzs, 1)
+            t_r = time.perf_counter()
+            for _ in range(5):
+                _, kept_r, _ = ctx3.recycle(pool, bts, lzs, 1)
+            extra["recycle_ms_30x%d" % P] = round(1e3 * (time.perf_counter() - t_r) / 5, 4)
             extra["local_metric_sampler"] = {
                 "evals_per_s": round(e3 / d3, 1), "ms_per_step": round(1e3 * d3 / args.steps, 4),
                 "leapfrog_per_step": round(e3 / args.steps, 1), "nuts_kernel_ms": round(k3 / max(n3, 1), 3),
