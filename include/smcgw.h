@@ -123,6 +123,34 @@ int smcgw_set_stream(smcgw_ctx *ctx, void *hip_stream);
 int smcgw_add_event(smcgw_ctx *ctx, const smcgw_event_desc *ev, const double *data_reim, const double *psd,
                     const smcgw_detector *dets, int *event_id);
 
+/* Relative-binning event (Zackay, Dai & Venumadhav 2018, arXiv:1806.08792;
+ * the long-segment mitigation the paper names, Secs. 2 and 7).  The data sum
+ * of the likelihood of Sec. 2, Eq. 2 is evaluated only at the bin edges: with
+ * a fiducial parameter point theta0 (11 source parameters, host) the ratio
+ * h / h0 is taken linear in f inside each bin, so the per-bin data collapse
+ * into summary data per edge, built once here on the device over the full
+ * grid.  <h|h> and <d|d> keep their values over every bin (|h|^2 of this
+ * waveform does not depend on the phase).  Edges come from
+ * smcgw_rb_edges(eps): eps is the allowed growth of the phase-difference
+ * bound inside one bin (0.1: about 300 bins and logL errors of order 1e-2
+ * near the fiducial point; 0.5: about 60 bins).  The event then serves every
+ * entry point like one added with smcgw_add_event (smcgw_waveform returns
+ * the strain at the edges).  Arguments as smcgw_add_event; *n_edges (may
+ * be NULL) receives the edge count.  Synchronises. */
+int smcgw_add_event_rb(smcgw_ctx *ctx, const smcgw_event_desc *ev, const double *data_reim, const double *psd,
+                       const smcgw_detector *dets, const double *theta0, double eps, int *event_id, int *n_edges);
+
+/* Relative-binning edges for a grid f_j = f_low + j df, j < n_bins (host
+ * only, no context): the phase-difference bound
+ *   dpsi(f) = 2 pi sum_k sgn(g_k) (f / f*_k)^g_k,  g = -5/3, -2/3, 1, 5/3, 7/3,
+ * f*_k = f_low for negative and the last grid frequency for positive g_k, is
+ * cut into B = ceil(growth / eps) steps of equal growth (at most n_bins - 1);
+ * edge k (0 < k < B) is the first grid index where the bound has grown by k
+ * steps, edge 0 is index 0 and edge B the last index; repeated indices are
+ * dropped.  Writes the grid indices to edges [cap] and returns their count,
+ * or a negative status. */
+int smcgw_rb_edges(double f_low, double df, int n_bins, double eps, int32_t *edges, int cap);
+
 /* Event of every particle for the sampler entry points: event_of_particle
  * [P] is a caller-owned DEVICE array that must stay valid while the
  * sampler runs (NULL: every particle uses event 0; indices outside the

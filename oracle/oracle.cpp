@@ -81,6 +81,11 @@ struct orc_target {
     const double* psd;              // [n_det][N]
     const int32_t* param_index;     // [dim] -> index in the 11 GW parameters
     const double* fixed11;          // values of the 11 GW parameters not sampled
+    // Relative binning (GW only; rb_n_edges = 0: the likelihood on every bin).
+    int32_t rb_n_edges, rb_reserved;
+    const int32_t* rb_edges;        // [rb_n_edges] grid indices of the bin edges
+    const double* rb_sum;           // [n_det][rb_n_edges - 1][4]: Re A0, Im A0, Re A1, Im A1 of each bin
+    const double* rb_h0;            // [n_det][rb_n_edges][2]: fiducial strain at the edges
 };
 
 }  // extern "C"
@@ -280,6 +285,45 @@ T gw_loglike(const orc_event& ev, const orc_detector* dets, const double* data_r
     return -0.5 * 4.0 * ev.df * total;
 }
 
+// Relative binning (Zackay, Dai & Venumadhav 2018, arXiv:1806.08792; the
+// long-segment mitigation named in Secs. 2 and 7).  With a fiducial strain h0
+// and the ratio r = h / h0 taken linear in f inside each bin b = [f_b, f_b+1],
+//   <d|h> = Re sum_d sum_b [A0_db r_d(f_b) + A1_db (r_d(f_b+1) - r_d(f_b)) / (f_b+1 - f_b)],
+//   A0_db = sum_{j in b} 4 df conj(d_dj) h0_dj / S_dj,  A1_db = the same weighted by (f_j - f_b);
+// <h|h> and <d|d> are summed over every bin.  Bin b holds the grid points
+// [edge_b, edge_b+1) (the last bin also its end point).
+template <class T>
+T gw_loglike_rb(const orc_target& t, const T th[NP]) {
+    const orc_event& ev = *t.ev;
+    const int n = ev.n_bins, ne = t.rb_n_edges, nb = ne - 1;
+    T dh(0.0), hh(0.0);
+    double dd = 0.0;
+    for (int d = 0; d < ev.n_det; ++d) {
+        std::vector<Cx<T>> r(ne);
+        for (int e = 0; e < ne; ++e) {
+            const double f = ev.f_low + ev.df * t.rb_edges[e];
+            const Cx<T> h = detector_strain(ev, t.dets[d], th, f);
+            const double* h0 = t.rb_h0 + 2 * ((size_t)d * ne + e);
+            const double m = h0[0] * h0[0] + h0[1] * h0[1];
+            r[e] = {(h.re * h0[0] + h.im * h0[1]) / m, (h.im * h0[0] - h.re * h0[1]) / m};   // h conj(h0) / |h0|^2
+        }
+        for (int b = 0; b < nb; ++b) {
+            const double* a = t.rb_sum + 4 * ((size_t)d * nb + b);
+            const double wb = ev.df * (t.rb_edges[b + 1] - t.rb_edges[b]);
+            const Cx<T> slope = {(r[b + 1].re - r[b].re) / wb, (r[b + 1].im - r[b].im) / wb};
+            dh = dh + (a[0] * r[b].re - a[1] * r[b].im) + (a[2] * slope.re - a[3] * slope.im);
+        }
+        for (int j = 0; j < n; ++j) {
+            const Cx<T> h = detector_strain(ev, t.dets[d], th, ev.f_low + ev.df * j);
+            const double w = 4.0 * ev.df / t.psd[(size_t)d * n + j];
+            hh = hh + w * (h.re * h.re + h.im * h.im);
+            const double* x = t.data_reim + 2 * ((size_t)d * n + j);
+            dd += w * (x[0] * x[0] + x[1] * x[1]);
+        }
+    }
+    return dh - 0.5 * hh - 0.5 * dd;
+}
+
 // --------------------------------------------------------------- targets
 typedef Dual<NP> D11;
 
@@ -295,10 +339,13 @@ double target_loglike(const orc_target& t, const double* x, double* grad) {
     case 0: {
         double th[NP];
         expand_gw(t, x, th);
-        if (!grad) return gw_loglike<double>(*t.ev, t.dets, t.data_reim, t.psd, th);
+        if (!grad)
+            return t.rb_n_edges > 0 ? gw_loglike_rb<double>(t, th)
+                                    : gw_loglike<double>(*t.ev, t.dets, t.data_reim, t.psd, th);
         D11 td[NP];
         for (int k = 0; k < NP; ++k) { td[k] = D11(th[k]); td[k].d[k] = 1.0; }
-        const D11 l = gw_loglike<D11>(*t.ev, t.dets, t.data_reim, t.psd, td);
+        const D11 l = t.rb_n_edges > 0 ? gw_loglike_rb<D11>(t, td)
+                                       : gw_loglike<D11>(*t.ev, t.dets, t.data_reim, t.psd, td);
         for (int k = 0; k < D; ++k) grad[k] = l.d[t.param_index ? t.param_index[k] : k];
         return l.v;
     }
@@ -927,6 +974,81 @@ int orc_recycle(int T, int N, const double* logl, const double* betas, const dou
     }
     *n_accepted = k;
     *ess = s2 > 0.0 ? s1 * s1 / s2 : 0.0;
+    return 0;
+}
+
+// Bin edges of relative binning (criterion of Zackay, Dai & Venumadhav 2018):
+// the phase difference between waveforms that the prior allows is bounded by
+//   dpsi(f) = 2 pi chi sum_k sgn(g_k) (f / f*_k)^g_k,
+//   g_k in {-5/3, -2/3, 1, 5/3, 7/3},  f*_k = f_min (g_k < 0) or f_max (g_k > 0),
+// with chi = 1 (each power law moves the phase by at most 2 pi where it is
+// largest); dpsi grows monotonically.  The band is cut into
+// B = ceil((dpsi(f_max) - dpsi(f_min)) / eps) bins of equal growth: edge k
+// (0 < k < B) is the first grid point with dpsi - dpsi(f_min) >= k/B of the
+// total; edge 0 is the first grid point, edge B the last.  Repeated edges are
+// dropped.  Writes at most cap edges (grid indices); returns their number or
+// -1 on bad arguments.
+int orc_rb_edges(double f_low, double df, int n, double eps, int32_t* edges, int cap) {
+    if (n < 2 || !(df > 0.0) || !(f_low > 0.0) || !(eps > 0.0) || cap < 2) return -1;
+    const double g[5] = {-5.0 / 3.0, -2.0 / 3.0, 1.0, 5.0 / 3.0, 7.0 / 3.0};
+    const double fmin = f_low, fmax = f_low + df * (n - 1);
+    auto dpsi = [&](double f) {
+        double s = 0.0;
+        for (int k = 0; k < 5; ++k) s += (g[k] < 0 ? -1.0 : 1.0) * std::pow(f / (g[k] < 0 ? fmin : fmax), g[k]);
+        return 2.0 * PI * s;
+    };
+    const double p0 = dpsi(fmin), total = dpsi(fmax) - p0;
+    long nb = (long)std::ceil(total / eps);
+    if (nb < 1) nb = 1;
+    if (nb > n - 1) nb = n - 1;
+    int m = 0;
+    edges[m++] = 0;
+    int j = 0;
+    for (long k = 1; k < nb; ++k) {
+        const double target = total * (double)k / (double)nb;
+        while (j < n - 1 && dpsi(f_low + df * j) - p0 < target) ++j;
+        if (j >= n - 1) break;
+        if (j > edges[m - 1]) {
+            if (m >= cap - 1) return -1;
+            edges[m++] = j;
+        }
+    }
+    edges[m++] = n - 1;
+    return m;
+}
+
+// Summary data of relative binning for the fiducial parameters theta0 (11):
+// sums [n_det][n_edges - 1][4] (A0, A1 of every bin, see gw_loglike_rb) and
+// h0 [n_det][n_edges][2] (the fiducial strain at the edges).
+int orc_rb_prepare(const orc_event* ev, const orc_detector* dets, const double* data_reim, const double* psd,
+                   const double* theta0, int n_edges, const int32_t* edges, double* sums, double* h0) {
+    if (n_edges < 2) return -1;
+    const int n = ev->n_bins, nb = n_edges - 1;
+    for (int d = 0; d < ev->n_det; ++d) {
+        for (int e = 0; e < n_edges; ++e) {
+            const Cx<double> h = detector_strain<double>(*ev, dets[d], theta0, ev->f_low + ev->df * edges[e]);
+            h0[2 * ((size_t)d * n_edges + e)] = h.re;
+            h0[2 * ((size_t)d * n_edges + e) + 1] = h.im;
+        }
+        for (int b = 0; b < nb; ++b) {
+            const int j0 = edges[b], j1 = (b == nb - 1) ? edges[b + 1] + 1 : edges[b + 1];
+            const double fb = ev->f_low + ev->df * j0;
+            double a[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int j = j0; j < j1; ++j) {
+                const double f = ev->f_low + ev->df * j;
+                const Cx<double> hz = detector_strain<double>(*ev, dets[d], theta0, f);
+                const double* x = data_reim + 2 * ((size_t)d * n + j);
+                const double w = 4.0 * ev->df / psd[(size_t)d * n + j];
+                const double re = w * (x[0] * hz.re + x[1] * hz.im);   // 4 df conj(d) h0 / S
+                const double im = w * (x[0] * hz.im - x[1] * hz.re);
+                a[0] += re;
+                a[1] += im;
+                a[2] += re * (f - fb);
+                a[3] += im * (f - fb);
+            }
+            for (int k = 0; k < 4; ++k) sums[4 * ((size_t)d * nb + b) + k] = a[k];
+        }
+    }
     return 0;
 }
 

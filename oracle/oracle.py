@@ -48,7 +48,9 @@ class OrcTarget(C.Structure):
                 ("params", C.POINTER(C.c_double)), ("ev", C.POINTER(OrcEvent)),
                 ("dets", C.POINTER(OrcDetector)), ("data_reim", C.POINTER(C.c_double)),
                 ("psd", C.POINTER(C.c_double)), ("param_index", C.POINTER(C.c_int32)),
-                ("fixed11", C.POINTER(C.c_double))]
+                ("fixed11", C.POINTER(C.c_double)),
+                ("rb_n_edges", C.c_int32), ("rb_reserved", C.c_int32), ("rb_edges", C.POINTER(C.c_int32)),
+                ("rb_sum", C.POINTER(C.c_double)), ("rb_h0", C.POINTER(C.c_double))]
 
 
 _lib = None
@@ -164,11 +166,47 @@ def waveform(ev, theta11) -> np.ndarray:
     return h[..., 0] + 1j * h[..., 1]
 
 
-def gw_target(ev, param_index: Optional[Sequence[int]] = None, bounds=None, fixed11=None) -> Target:
+def gw_target(ev, param_index: Optional[Sequence[int]] = None, bounds=None, fixed11=None, rb=None) -> Target:
+    """The event likelihood over the sampled coordinates; with rb (from rb_prepare) the relative-binning one."""
     idx = list(range(11)) if param_index is None else list(param_index)
     full = synth.gw_prior_for(ev) if bounds is None else bounds
     b = [full[i] for i in idx] if len(full) == 11 and len(idx) != 11 else full
-    return Target(synth.TARGET_GW, len(idx), b, event=ev, param_index=idx, fixed11=fixed11)
+    t = Target(synth.TARGET_GW, len(idx), b, event=ev, param_index=idx, fixed11=fixed11)
+    if rb is not None:
+        edges = np.ascontiguousarray(rb["edges"], np.int32)
+        sums = _f64(rb["sums"])
+        h0 = _f64(rb["h0"])
+        t.keep += [edges, sums, h0]
+        t.t.rb_n_edges = len(edges)
+        t.t.rb_edges = _ip(edges)
+        t.t.rb_sum = _dp(sums)
+        t.t.rb_h0 = _dp(h0)
+    return t
+
+
+def rb_edges(f_low: float, df: float, n: int, eps: float) -> np.ndarray:
+    """Grid indices of the relative-binning edges for phase tolerance eps."""
+    cap = n + 1
+    out = np.zeros(cap, np.int32)
+    m = lib().orc_rb_edges(C.c_double(f_low), C.c_double(df), C.c_int(n), C.c_double(eps), _ip(out), C.c_int(cap))
+    if m < 0:
+        raise ValueError("bad relative-binning arguments")
+    return out[:m].copy()
+
+
+def rb_prepare(ev, theta0, eps: float):
+    """Edges and summary data of relative binning around the fiducial parameters theta0 (11)."""
+    edges = rb_edges(ev.f_low, ev.df, ev.n, eps)
+    e, dets = event_structs(ev)
+    data = _f64(ev.data_reim())
+    psd = _f64(ev.psd)
+    ne = len(edges)
+    sums = np.zeros((ev.n_det, ne - 1, 4))
+    h0 = np.zeros((ev.n_det, ne, 2))
+    rc = lib().orc_rb_prepare(C.byref(e), C.cast(dets, C.POINTER(OrcDetector)), _dp(data), _dp(psd), _dp(_f64(theta0)),
+                              C.c_int(ne), _ip(edges), _dp(sums), _dp(h0))
+    assert rc == 0
+    return dict(edges=edges, sums=sums, h0=h0)
 
 
 def loglike_grad(target: Target, x: np.ndarray, want_grad: bool = True):

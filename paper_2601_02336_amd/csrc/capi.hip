@@ -197,14 +197,11 @@ static void site_geometry(const smcgw_detector& s, double pos[3], double resp[3]
         for (int j = 0; j < 3; ++j) resp[i][j] = 0.5 * (x[i] * x[j] - y[i] * y[j]);
 }
 
-extern "C" int smcgw_add_event(smcgw_ctx* c, const smcgw_event_desc* ev, const double* data_reim, const double* psd,
-                               const smcgw_detector* dets, int* event_id) {
-    if (!c || !ev || !data_reim || !psd || !dets) return SMCGW_ERR_INVALID;
-    if (ev->n_bins <= 0 || ev->n_det <= 0 || ev->n_det > MAXDET || !(ev->df > 0.0) || !(ev->f_low > 0.0) ||
-        ev->pn_order < 0 || ev->pn_order > 7)
-        return SMCGW_ERR_SHAPE;
-    if ((int)c->events.size() >= SMCGW_MAX_EVENTS) return SMCGW_ERR_SHAPE;
-    if (!c->events.empty() && ev->n_det != c->n_det) return SMCGW_ERR_SHAPE;
+namespace smcgw {
+// Builds the full-grid tables of one event on the device (synchronises).  On
+// success de describes them and bufs holds fwl, u32, u64 and wmom.
+static int build_event(smcgw_ctx* c, const smcgw_event_desc* ev, const double* data_reim, const double* psd,
+                       const smcgw_detector* dets, DevEvent& de, void* bufs[4]) {
     const int n = ev->n_bins, nd = ev->n_det;
     const int npad = ((n + TABLE_PAD - 1) / TABLE_PAD) * TABLE_PAD;
     // Power-of-two scale of the whitened data, so the FP32 table sits near unit magnitude.
@@ -222,7 +219,6 @@ extern "C" int smcgw_add_event(smcgw_ctx* c, const smcgw_event_desc* ev, const d
     double *d_data = nullptr, *d_psd = nullptr, *fwl = nullptr, *sums = nullptr, *wmom = nullptr;
     float2* u32 = nullptr;
     double2* u64 = nullptr;
-    int rc = SMCGW_OK;
     auto fail = [&](int code) {
         hipFree(d_data); hipFree(d_psd); hipFree(fwl); hipFree(u32); hipFree(u64); hipFree(sums); hipFree(wmom);
         return code;
@@ -248,9 +244,7 @@ extern "C" int smcgw_add_event(smcgw_ctx* c, const smcgw_event_desc* ev, const d
     hipFree(d_data);
     hipFree(d_psd);
     hipFree(sums);
-    d_data = d_psd = sums = nullptr;
 
-    DevEvent de;
     std::memset(&de, 0, sizeof(de));
     de.n_bins = n;
     de.n_pad = npad;
@@ -274,19 +268,145 @@ extern "C" int smcgw_add_event(smcgw_ctx* c, const smcgw_event_desc* ev, const d
     de.mpc_m = ev->mpc_m;
     de.c_light = ev->c_light;
     de.gmst = ev->gmst;
+    bufs[0] = fwl;
+    bufs[1] = u32;
+    bufs[2] = u64;
+    bufs[3] = wmom;
+    return SMCGW_OK;
+}
+
+static int check_event_desc(smcgw_ctx* c, const smcgw_event_desc* ev) {
+    if (ev->n_bins <= 0 || ev->n_det <= 0 || ev->n_det > MAXDET || !(ev->df > 0.0) || !(ev->f_low > 0.0) ||
+        ev->pn_order < 0 || ev->pn_order > 7)
+        return SMCGW_ERR_SHAPE;
+    if ((int)c->events.size() >= SMCGW_MAX_EVENTS) return SMCGW_ERR_SHAPE;
+    if (!c->events.empty() && ev->n_det != c->n_det) return SMCGW_ERR_SHAPE;
+    return SMCGW_OK;
+}
+
+static int register_event(smcgw_ctx* c, const DevEvent& de, void* const bufs[4], int* event_id) {
     const int id = (int)c->events.size();
     if (hipMemcpyAsync(c->d_events + id, &de, sizeof(de), hipMemcpyHostToDevice, c->stream) ||
+        hipStreamSynchronize(c->stream)) {
+        for (int k = 0; k < 4; ++k) hipFree(bufs[k]);
+        return SMCGW_ERR_HIP;
+    }
+    c->events.push_back(de);
+    for (int k = 0; k < 4; ++k) c->event_bufs.push_back(bufs[k]);
+    c->n_det = de.n_det;
+    if (event_id) *event_id = id;
+    return SMCGW_OK;
+}
+}  // namespace smcgw
+
+extern "C" int smcgw_add_event(smcgw_ctx* c, const smcgw_event_desc* ev, const double* data_reim, const double* psd,
+                               const smcgw_detector* dets, int* event_id) {
+    if (!c || !ev || !data_reim || !psd || !dets) return SMCGW_ERR_INVALID;
+    int rc = check_event_desc(c, ev);
+    if (rc) return rc;
+    DevEvent de;
+    void* bufs[4];
+    rc = build_event(c, ev, data_reim, psd, dets, de, bufs);
+    if (rc) return rc;
+    return register_event(c, de, bufs, event_id);
+}
+
+// Relative-binning edges (host): the phase-difference bound
+//   dpsi(f) = 2 pi sum_k sgn(g_k) (f / f*_k)^g_k,  g = -5/3, -2/3, 1, 5/3, 7/3,
+// f*_k the band's lower end for negative and its upper end for positive
+// exponents, is cut into B = ceil(total growth / eps) steps of equal growth;
+// edge k is the first grid point that reaches k of them.
+extern "C" int smcgw_rb_edges(double f_low, double df, int n_bins, double eps, int32_t* edges, int cap) {
+    if (n_bins < 2 || !(df > 0.0) || !(f_low > 0.0) || !(eps > 0.0) || !edges || cap < 2) return SMCGW_ERR_INVALID;
+    static const double expo[5] = {-5.0 / 3.0, -2.0 / 3.0, 1.0, 5.0 / 3.0, 7.0 / 3.0};
+    const double f_hi = f_low + df * (n_bins - 1);
+    auto bound = [&](double f) {
+        double s = 0.0;
+        for (double g : expo) s += g < 0.0 ? -std::pow(f / f_low, g) : std::pow(f / f_hi, g);
+        return 2.0 * M_PI * s;
+    };
+    const double base = bound(f_low), growth = bound(f_hi) - base;
+    const long steps = std::min<long>(std::max<long>(1, (long)std::ceil(growth / eps)), n_bins - 1);
+    int count = 1;
+    edges[0] = 0;
+    int j = 0;
+    for (long k = 1; k < steps; ++k) {
+        const double level = growth * (double)k / (double)steps;
+        while (j < n_bins - 1 && bound(f_low + df * j) - base < level) ++j;
+        if (j >= n_bins - 1) break;
+        if (j == edges[count - 1]) continue;
+        if (count >= cap - 1) return SMCGW_ERR_SHAPE;
+        edges[count++] = j;
+    }
+    edges[count++] = n_bins - 1;
+    return count;
+}
+
+extern "C" int smcgw_add_event_rb(smcgw_ctx* c, const smcgw_event_desc* ev, const double* data_reim,
+                                  const double* psd, const smcgw_detector* dets, const double* theta0, double eps,
+                                  int* event_id, int* n_edges) {
+    if (!c || !ev || !data_reim || !psd || !dets || !theta0 || !(eps > 0.0)) return SMCGW_ERR_INVALID;
+    int rc = check_event_desc(c, ev);
+    if (rc) return rc;
+    if (ev->n_bins < 2) return SMCGW_ERR_SHAPE;
+    std::vector<int32_t> ej(ev->n_bins + 1);
+    const int ne = smcgw_rb_edges(ev->f_low, ev->df, ev->n_bins, eps, ej.data(), (int)ej.size());
+    if (ne < 2) return ne < 0 ? ne : SMCGW_ERR_SHAPE;
+    DevEvent full;
+    void* fb[4];
+    rc = build_event(c, ev, data_reim, psd, dets, full, fb);
+    if (rc) return rc;
+    const int n = ev->n_bins, nd = ev->n_det, id = (int)c->events.size();
+    const int npad = ((ne + TABLE_PAD - 1) / TABLE_PAD) * TABLE_PAD;
+    double *fwl = nullptr, *cb0 = nullptr, *th0 = nullptr;
+    float2* u32 = nullptr;
+    double2 *u64 = nullptr, *v = nullptr, *a0 = nullptr, *a1 = nullptr;
+    int32_t *d_edges = nullptr, *d_id = nullptr;
+    auto release = [&]() {
+        hipFree(v); hipFree(a0); hipFree(a1); hipFree(d_edges); hipFree(cb0); hipFree(th0); hipFree(d_id);
+        hipFree(fb[0]); hipFree(fb[1]); hipFree(fb[2]);
+    };
+    auto fail = [&](int code) {
+        release();
+        hipFree(fb[3]); hipFree(fwl); hipFree(u32); hipFree(u64);
+        return code;
+    };
+    if (hipMalloc(&fwl, sizeof(double) * NROWS * (size_t)npad) != hipSuccess ||
+        hipMalloc(&u32, sizeof(float2) * nd * (size_t)npad) != hipSuccess ||
+        hipMalloc(&u64, sizeof(double2) * nd * (size_t)npad) != hipSuccess ||
+        hipMalloc(&v, sizeof(double2) * nd * (size_t)n) != hipSuccess ||
+        hipMalloc(&a0, sizeof(double2) * nd * (size_t)(ne - 1)) != hipSuccess ||
+        hipMalloc(&a1, sizeof(double2) * nd * (size_t)(ne - 1)) != hipSuccess ||
+        hipMalloc(&d_edges, sizeof(int32_t) * ne) != hipSuccess ||
+        hipMalloc(&cb0, sizeof(double) * CB_SIZE) != hipSuccess ||
+        hipMalloc(&th0, sizeof(double) * NPAR) != hipSuccess || hipMalloc(&d_id, sizeof(int32_t)) != hipSuccess)
+        return fail(SMCGW_ERR_OOM);
+    // The fiducial coefficient block comes from the likelihood's own prologue,
+    // with the full event parked in the slot the new event will take.
+    ParamMap pm;
+    pm.dim = NPAR;
+    for (int k = 0; k < NPAR; ++k) { pm.idx[k] = k; pm.fixed[k] = 0.0; }
+    if (hipMemcpyAsync(c->d_events + id, &full, sizeof(full), hipMemcpyHostToDevice, c->stream) ||
+        hipMemcpyAsync(d_id, &id, sizeof(int32_t), hipMemcpyHostToDevice, c->stream) ||
+        hipMemcpyAsync(th0, theta0, sizeof(double) * NPAR, hipMemcpyHostToDevice, c->stream) ||
+        hipMemcpyAsync(d_edges, ej.data(), sizeof(int32_t) * ne, hipMemcpyHostToDevice, c->stream))
+        return fail(SMCGW_ERR_HIP);
+    if (launch_prep(c->d_events, id + 1, d_id, pm, 1, th0, cb0, c->stream) ||
+        launch_rb_tables((const double*)fb[0], (const double2*)fb[2], n, full.n_pad, nd, cb0, d_edges, ne, v, a0, a1,
+                         npad, fwl, u32, u64, c->stream) ||
         hipStreamSynchronize(c->stream))
         return fail(SMCGW_ERR_HIP);
-    c->events.push_back(de);
-    c->event_bufs.push_back(fwl);
-    c->event_bufs.push_back(u32);
-    c->event_bufs.push_back(u64);
-    c->event_bufs.push_back(wmom);
-    c->n_det = nd;
-    if (event_id) *event_id = id;
-    (void)rc;
-    return SMCGW_OK;
+    release();
+    DevEvent de = full;
+    de.n_bins = ne;
+    de.n_pad = npad;
+    de.fwl = fwl;
+    de.u32 = u32;
+    de.u64 = u64;
+    void* bufs[4] = {fwl, u32, u64, fb[3]};
+    rc = register_event(c, de, bufs, event_id);
+    if (rc == SMCGW_OK && n_edges) *n_edges = ne;
+    return rc;
 }
 
 extern "C" int smcgw_set_event_map(smcgw_ctx* c, const int32_t* event_of_particle) {

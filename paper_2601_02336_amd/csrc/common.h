@@ -145,6 +145,9 @@ __device__ __forceinline__ int event_index(const int32_t* ev_of_p, int p, int n_
 // (each .hip file exposes host functions; kernels stay in their own unit)
 hipError_t launch_metric_moments(const double* d_psd, int n_det, int n_bins, double f_low, double df, double u_scale,
                                  double* wmom, hipStream_t s);
+hipError_t launch_rb_tables(const double* fwl_full, const double2* u64_full, int n, int npad_full, int n_det,
+                            const double* cb0, const int32_t* edges, int ne, double2* v, double2* a0, double2* a1,
+                            int npad, double* fwl, float2* u32, double2* u64, hipStream_t s);
 hipError_t launch_build_tables(const double* d_data, const double* d_psd, int n_det, int n_bins, int n_pad,
                                double f_low, double df, double u_scale, double* fwl, float2* u32, double2* u64,
                                double* sums, hipStream_t s);

@@ -56,6 +56,15 @@ class NutsParams(C.Structure):
 _lib = None
 
 
+def rb_edges(f_low: float, df: float, n_bins: int, eps: float) -> np.ndarray:
+    """Grid indices of the relative-binning edges (host computation, no device needed)."""
+    out = np.zeros(n_bins + 1, dtype=np.int32)
+    m = lib().smcgw_rb_edges(f_low, df, n_bins, eps, out.ctypes.data_as(C.c_void_p), len(out))
+    if m < 0:
+        raise RuntimeError(f"smcgw_rb_edges: {lib().smcgw_status_string(m).decode()}")
+    return out[:m].copy()
+
+
 def _chol_mode(chol: torch.Tensor, P: int, D: int) -> int:
     """0 for one shared [D][D] factor, 1 for per-particle [P][D][D] factors."""
     _dev(chol, torch.float64, "chol")
@@ -90,6 +99,9 @@ def lib():
         L.smcgw_target_loglike_grad.argtypes = [vp, i, vp, vp, vp, i]
         L.smcgw_mass_matrix.argtypes = [vp, i, i, vp, d, vp, vp, vp]
         L.smcgw_local_metric.argtypes = [vp, i, i, vp, d, vp, vp, vp, vp]
+        L.smcgw_add_event_rb.argtypes = [vp, C.POINTER(EventDesc), vp, vp, C.POINTER(Detector), vp, d,
+                                         C.POINTER(i), C.POINTER(i)]
+        L.smcgw_rb_edges.argtypes = [d, d, i, d, vp, i]
         L.smcgw_recycle.argtypes = [vp, i, i, vp, vp, vp, u64, vp, vp, C.POINTER(C.c_int64), C.POINTER(d)]
         L.smcgw_nuts_step.argtypes = [vp, i, i, vp, vp, vp, vp, C.POINTER(NutsParams), vp, vp, i, vp, vp, vp, vp]
         L.smcgw_timing_enable.argtypes = [vp, i]
@@ -181,6 +193,24 @@ class Context:
                                                         psd.ctypes.data_as(C.c_void_p), dets, C.byref(eid)))
         self.events.append(ev)
         return eid.value
+
+    def add_event_rb(self, ev: "synth.Event", theta0: Sequence[float], eps: float = 0.1):
+        """Relative-binning event around the fiducial point theta0 (11); returns (event id, edge count)."""
+        desc = EventDesc(ev.f_low, ev.df, ev.n, ev.n_det, ev.gmst, ev.t_sun, ev.mpc_m, ev.c_light, ev.pn_order, 0)
+        dets = (Detector * ev.n_det)(*[Detector(*s.as_tuple()) for s in ev.sites])
+        data = np.ascontiguousarray(ev.data_reim(), dtype=np.float64)
+        psd = np.ascontiguousarray(ev.psd, dtype=np.float64)
+        th0 = np.ascontiguousarray(theta0, dtype=np.float64)
+        if th0.shape != (11,):
+            raise ValueError("theta0 holds the 11 source parameters")
+        eid = C.c_int()
+        ne = C.c_int()
+        self._stream()
+        _check("smcgw_add_event_rb", lib().smcgw_add_event_rb(
+            self._h, C.byref(desc), data.ctypes.data_as(C.c_void_p), psd.ctypes.data_as(C.c_void_p), dets,
+            th0.ctypes.data_as(C.c_void_p), eps, C.byref(eid), C.byref(ne)))
+        self.events.append(ev)
+        return eid.value, ne.value
 
     def set_event_map(self, event_of_particle: Optional[torch.Tensor]):
         """Device int32 [P] event index per particle for the sampler calls (kept alive here)."""

@@ -1,0 +1,161 @@
+"""Relative-binning events on the GPU (Zackay, Dai & Venumadhav 2018; the long-segment mitigation of
+arXiv:2601.02336, Secs. 2 and 7): parity of the likelihood and gradient with the oracle's relative-binning
+likelihood, the 128 s segment, NUTS on a relative-binning event, a batch mixing full and relative-binning
+events, and the SMC evidence against the reference of tests/golden."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2601_02336_amd import synth
+from oracle import oracle as O
+
+from helpers import CONFIG0_INDEX, TOL, event, grad_err, logl_rel_err, widths
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def smcgw():
+    from paper_2601_02336_amd import smcgw as m
+    return m
+
+
+def _points(ev, idx, n_far, n_near, seed):
+    """Prior draws and points near the fiducial (injection) point."""
+    full = synth.gw_prior_for(ev)
+    b = [full[i] for i in idx]
+    rng = np.random.default_rng(seed)
+    far = synth.prior_draw(rng, n_far, b)
+    x0 = ev.theta_inj[idx]
+    w = widths(b)
+    near = x0 + 1e-3 * w * rng.standard_normal((n_near, len(idx)))
+    lo = np.array([q.lo for q in b]); hi = np.array([q.hi for q in b])
+    near = np.clip(near, lo + 1e-9 * w, hi - 1e-9 * w)
+    return np.concatenate([far, near]), b
+
+
+@pytest.mark.parametrize("eps", [0.1, 0.5])
+def test_rb_likelihood_parity(smcgw, eps):
+    ev = event(synth.SPEC_8S)
+    idx = list(range(11))
+    x, b = _points(ev, idx, 64, 66, 31)
+    rb = O.rb_prepare(ev, ev.theta_inj, eps)
+    ll_ref, g_ref = O.loglike_grad(O.gw_target(ev, rb=rb), x)
+    c = smcgw.Context(0)
+    eid, ne = c.add_event_rb(ev, ev.theta_inj, eps)
+    assert ne == len(rb["edges"])
+    xt = torch.tensor(x, device="cuda")
+    for name, prec in (("plain", smcgw.PLAIN_FP64), ("mixed", smcgw.MIXED)):
+        ll, g = c.loglike_grad(xt, precision=prec)
+        ll, g = ll.cpu().numpy(), g.cpu().numpy()
+        el, eg = logl_rel_err(ll, ll_ref), grad_err(g, g_ref, widths(b))
+        print(f"eps {eps} ({ne} edges) {name}: logL rel err {el:.2e}, grad err {eg:.2e}", flush=True)
+        assert el <= TOL[name]["logl"] and eg <= TOL[name]["grad"]
+    # near the fiducial point the relative-binning logL follows the full one
+    ll_full = O.loglike_grad(O.gw_target(ev), x[64:], want_grad=False)
+    ll_rb = c.loglike_grad(xt[64:], precision=smcgw.PLAIN_FP64, want_grad=False).cpu().numpy()
+    print(f"eps {eps}: |logL_rb - logL| near the fiducial point <= {np.max(np.abs(ll_rb - ll_full)):.2e}", flush=True)
+    assert np.max(np.abs(ll_rb - ll_full)) < (0.05 if eps == 0.1 else 0.5)
+    c.close()
+
+
+def test_rb_long_segment_parity(smcgw):
+    """128 s at 20-2048 Hz (259585 bins) folded onto ~310 edges."""
+    ev = event(synth.SPEC_128S)
+    idx = list(range(11))
+    x, b = _points(ev, idx, 2, 2, 32)
+    rb = O.rb_prepare(ev, ev.theta_inj, 0.1)
+    ll_ref, g_ref = O.loglike_grad(O.gw_target(ev, rb=rb), x)
+    c = smcgw.Context(0)
+    eid, ne = c.add_event_rb(ev, ev.theta_inj, 0.1)
+    for name, prec in (("plain", smcgw.PLAIN_FP64), ("mixed", smcgw.MIXED)):
+        ll, g = c.loglike_grad(torch.tensor(x, device="cuda"), precision=prec)
+        el, eg = logl_rel_err(ll.cpu().numpy(), ll_ref), grad_err(g.cpu().numpy(), g_ref, widths(b))
+        print(f"128 s, {ne} edges, {name}: logL rel err {el:.2e}, grad err {eg:.2e}", flush=True)
+        assert el <= TOL[name]["logl"] and eg <= TOL[name]["grad"]
+    c.close()
+
+
+def test_rb_and_full_events_share_a_launch(smcgw):
+    """Event map over a full event and a relative-binning one: each particle's result equals the one of a
+    context holding only its event."""
+    ev = event(synth.SPEC_8S)
+    idx = list(range(11))
+    x, _ = _points(ev, idx, 40, 40, 33)
+    xt = torch.tensor(x, device="cuda")
+    emap = torch.tensor(np.arange(80) % 2, dtype=torch.int32, device="cuda")
+    c = smcgw.Context(0)
+    c.add_event(ev)
+    c.add_event_rb(ev, ev.theta_inj, 0.1)
+    ll, g = c.loglike_grad(xt, event_of_particle=emap, precision=smcgw.PLAIN_FP64)
+    c1 = smcgw.Context(0)
+    c1.add_event(ev)
+    l1, g1 = c1.loglike_grad(xt, precision=smcgw.PLAIN_FP64)
+    c2 = smcgw.Context(0)
+    c2.add_event_rb(ev, ev.theta_inj, 0.1)
+    l2, g2 = c2.loglike_grad(xt, precision=smcgw.PLAIN_FP64)
+    even = slice(0, None, 2)
+    odd = slice(1, None, 2)
+    assert torch.equal(ll[even], l1[even]) and torch.equal(ll[odd], l2[odd])
+    assert torch.equal(g[even], g1[even]) and torch.equal(g[odd], g2[odd])
+    for cc in (c, c1, c2):
+        cc.close()
+
+
+def test_nuts_on_rb_event_parity(smcgw):
+    ev = event(synth.SPEC_SMALL)
+    idx = CONFIG0_INDEX
+    full = synth.gw_prior_for(ev)
+    b = [full[i] for i in idx]
+    rng = np.random.default_rng(7)
+    x = synth.prior_draw(rng, 48, b)
+    rb = O.rb_prepare(ev, ev.theta_inj, 0.1)
+    t = O.gw_target(ev, param_index=idx, rb=rb)
+    ll, g = O.loglike_grad(t, x)
+    _, _, L = O.mass_matrix(synth.prior_draw(rng, 4000, b), 0.0)
+    L = L * 0.05
+    ref = O.nuts_step(t, x, L, 0.25, 6, 0.3, seed=7, iteration=1)
+    c = smcgw.Context(0)
+    c.add_event_rb(ev, ev.theta_inj, 0.1)
+    c.set_param_map(idx, ev.theta_inj)
+    c.set_prior(b)
+    c.set_target(synth.TARGET_GW, len(idx))
+    xt, lt, gt = (torch.tensor(v, device="cuda") for v in (x, ll, g))
+    out = c.nuts_step(xt, lt, gt, torch.tensor(L, device="cuda"), step=0.25, beta=0.3, seed=7, iteration=1,
+                      max_depth=6, precision=smcgw.PLAIN_FP64)
+    torch.cuda.synchronize()
+    got = {k: v.cpu().numpy() for k, v in out.items()}
+    xg = xt.cpu().numpy()
+    c.close()
+    same = (got["depth"] == ref["depth"]) & (got["n_leapfrog"] == ref["n_leapfrog"])
+    close = np.all(np.abs(xg - ref["x"]) <= 1e-6 * (1 + np.abs(ref["x"])), axis=1)
+    ok = same & close
+    print(f"NUTS on the relative-binning event: agree {ok.mean():.3f}, depths {np.bincount(ref['depth'])}", flush=True)
+    assert ok.mean() >= 0.97
+
+
+def test_smc_evidence_with_relative_binning(smcgw):
+    """The local-metric SMC run on the relative-binning event (eps 0.1, fiducial = injection) against the
+    importance-sampling evidence of the full likelihood (tests/golden): mean of two seeds within 0.3."""
+    from paper_2601_02336_amd import smc
+    from test_gpu_metric import _golden_logz
+    ev = event(synth.SPEC_SMALL)
+    idx = CONFIG0_INDEX
+    full = synth.gw_prior_for(ev)
+    b = [full[i] for i in idx]
+    ref, _ = _golden_logz()
+    vals = []
+    for seed in (1, 2):
+        c = smcgw.Context(0)
+        _, ne = c.add_event_rb(ev, ev.theta_inj, 0.1)
+        c.set_param_map(idx, ev.theta_inj)
+        c.set_prior(b)
+        c.set_target(synth.TARGET_GW, len(idx))
+        x0 = torch.tensor(synth.prior_draw(np.random.default_rng(10 + seed), 2048, b), device="cuda")
+        r = smc.run_smc(c, x0, smc.SmcConfig(alpha=0.5, step=0.5, max_depth=8, seed=seed, metric="local"))
+        c.close()
+        print(f"relative binning ({ne} edges), seed {seed}: log Z {r.logz:.4f} (reference {ref:.4f}), "
+              f"{r.n_iter} iterations, {sum(r.n_leapfrog)} leapfrog steps, {r.seconds:.2f} s", flush=True)
+        assert r.betas[-1] == 1.0
+        vals.append(r.logz)
+    assert abs(np.mean(vals) - ref) <= 0.3
