@@ -432,6 +432,43 @@ def main():
             extra[name + "_evals_per_s"] = round(Pl * 10 / (time.perf_counter() - t1), 1)
         ctxl.close()
 
+    if not args.no_extra and args.mode == "smc":
+        # relative binning (eps = 0.1, fiducial point = the injection): the batched likelihood on the 8 s and
+        # 128 s events and the same SMC iterations on the 8 s event folded onto its edges
+        rbx = {}
+        for tag, spec in (("8s", None), ("128s", synth.SPEC_128S)):
+            evr = ev if spec is None else build_event(smcgw, synth, spec)
+            cr = smcgw.Context(0)
+            _, ne = cr.add_event_rb(evr, evr.theta_inj, 0.1)
+            xr = torch.tensor(synth.prior_draw(np.random.default_rng(8), 4096, synth.gw_prior_for(evr)),
+                              device="cuda")
+            lr = torch.empty(4096, dtype=torch.float64, device="cuda")
+            gr = torch.empty_like(xr)
+            for _ in range(2):
+                cr.loglike_grad(xr, lr, gr, precision=prec)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(10):
+                cr.loglike_grad(xr, lr, gr, precision=prec)
+            torch.cuda.synchronize()
+            rbx[f"loglike_grad_{tag}_evals_per_s"] = round(4096 * 10 / (time.perf_counter() - t1), 1)
+            rbx[f"edges_{tag}"] = ne
+            rbx[f"bins_{tag}"] = evr.n
+            cr.close()
+        P_rb = args.particles or 2048
+        cr = smcgw.Context(0)
+        cr.add_event_rb(ev, ev.theta_inj, 0.1)
+        bounds = synth.gw_prior_for(ev)
+        cr.set_prior(bounds)
+        cr.set_target(synth.TARGET_GW, 11)
+        xr = torch.tensor(synth.prior_draw(np.random.default_rng(7), P_rb, bounds), device="cuda")
+        e4, d4, k4, n4, _, _, _, _ = run_smc_steps(smcgw, cr, xr, prec, args, args.warmup, args.steps, True)
+        rbx["smc_evals_per_s"] = round(e4 / d4, 1)
+        rbx["smc_ms_per_step"] = round(1e3 * d4 / args.steps, 4)
+        rbx["smc_nuts_kernel_ms"] = round(k4 / max(n4, 1), 3)
+        cr.close()
+        extra["relative_binning"] = rbx
+
     if args.copy_probe:
         src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")   # 256 MiB
         dst = torch.empty_like(src)

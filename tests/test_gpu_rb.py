@@ -136,7 +136,9 @@ def test_nuts_on_rb_event_parity(smcgw):
 
 def test_smc_evidence_with_relative_binning(smcgw):
     """The local-metric SMC run on the relative-binning event (eps 0.1, fiducial = injection) against the
-    importance-sampling evidence of the full likelihood (tests/golden): mean of two seeds within 0.3."""
+    importance-sampling evidence of the full likelihood (tests/golden): mean of four seeds within 0.3 (the
+    run-to-run spread of this configuration is about 0.17, the relative-binning logL error near the
+    posterior about 1e-2)."""
     from paper_2601_02336_amd import smc
     from test_gpu_metric import _golden_logz
     ev = event(synth.SPEC_SMALL)
@@ -145,7 +147,7 @@ def test_smc_evidence_with_relative_binning(smcgw):
     b = [full[i] for i in idx]
     ref, _ = _golden_logz()
     vals = []
-    for seed in (1, 2):
+    for seed in (1, 2, 3, 4):
         c = smcgw.Context(0)
         _, ne = c.add_event_rb(ev, ev.theta_inj, 0.1)
         c.set_param_map(idx, ev.theta_inj)
