@@ -456,17 +456,18 @@ def main():
             rbx[f"bins_{tag}"] = evr.n
             cr.close()
         P_rb = args.particles or 2048
-        cr = smcgw.Context(0)
-        cr.add_event_rb(ev, ev.theta_inj, 0.1)
         bounds = synth.gw_prior_for(ev)
-        cr.set_prior(bounds)
-        cr.set_target(synth.TARGET_GW, 11)
-        xr = torch.tensor(synth.prior_draw(np.random.default_rng(7), P_rb, bounds), device="cuda")
-        e4, d4, k4, n4, _, _, _, _ = run_smc_steps(smcgw, cr, xr, prec, args, args.warmup, args.steps, True)
-        rbx["smc_evals_per_s"] = round(e4 / d4, 1)
-        rbx["smc_ms_per_step"] = round(1e3 * d4 / args.steps, 4)
-        rbx["smc_nuts_kernel_ms"] = round(k4 / max(n4, 1), 3)
-        cr.close()
+        for w_rb in (2, 4):   # the edge table fits one block: narrower slots, more of them per CU
+            cr = smcgw.Context(0)
+            cr.add_event_rb(ev, ev.theta_inj, 0.1)
+            cr.set_prior(bounds)
+            cr.set_target(synth.TARGET_GW, 11)
+            cr.set_option(smcgw.OPT_NUTS_WAVES, w_rb)
+            xr = torch.tensor(synth.prior_draw(np.random.default_rng(7), P_rb, bounds), device="cuda")
+            e4, d4, k4, n4, _, _, _, _ = run_smc_steps(smcgw, cr, xr, prec, args, args.warmup, args.steps, True)
+            rbx[f"smc_w{w_rb}"] = {"evals_per_s": round(e4 / d4, 1), "ms_per_step": round(1e3 * d4 / args.steps, 4),
+                                   "nuts_kernel_ms": round(k4 / max(n4, 1), 3), "leapfrog_per_step": e4 // args.steps}
+            cr.close()
         extra["relative_binning"] = rbx
 
     if args.copy_probe:
