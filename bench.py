@@ -216,16 +216,26 @@ def run_smc_steps(smcgw, ctx, theta, precision, args, n_warm, n_steps, time_kern
     stats = []
     mm_status = torch.zeros(1, dtype=torch.int32, device="cuda")
 
+    bz = torch.zeros((n_warm + n_steps, 2), dtype=torch.float64, device="cuda")
+    bz_host = torch.zeros((n_warm + n_steps, 2), dtype=torch.float64, pin_memory=True)
+
     def one_step():
+        # the iteration is queued as a whole: beta_t goes from the reweighting to the metric and the NUTS
+        # transition through device memory, and reaches the host through an event while the transition runs
         nonlocal beta, it, hint
-        b, dz, _ = ctx.smc_reweight_resample(theta, logl, grad, beta, args.alpha, args.seed, it, carry=hint)
+        ctx.smc_reweight_resample_async(theta, logl, grad, beta, args.alpha, args.seed, it, bz[it], carry=hint)
+        bz_host[it].copy_(bz[it], non_blocking=True)
+        ready = torch.cuda.Event()
+        ready.record()
+        beta_dev = bz[it, 0:1]
         _, L, _ = ctx.mass_matrix(theta, 0.0, status=mm_status)
         if metric == "local":
-            L, _, _ = ctx.local_metric(theta, b, fallback=L, status=False)
-        out = ctx.nuts_step(theta, logl, grad, L, step=args.step, beta=b, seed=args.seed, iteration=it,
-                            max_depth=args.max_depth, precision=precision, work_hint=hint)
+            L, _, _ = ctx.local_metric(theta, 0.0, fallback=L, status=False, beta_device=beta_dev)
+        out = ctx.nuts_step(theta, logl, grad, L, step=args.step, beta=0.0, seed=args.seed, iteration=it,
+                            max_depth=args.max_depth, precision=precision, work_hint=hint, beta_device=beta_dev)
         hint = None if args.no_hint else out["n_leapfrog"]
-        beta = b
+        ready.synchronize()
+        beta = float(bz_host[it, 0])
         it += 1
         return out
 

@@ -99,6 +99,9 @@ typedef struct {
                                     1: chol is [P][D][D], one factor per particle
                                     (smcgw_local_metric) */
     int32_t reserved;            /* must be 0 */
+    const double *beta_device;   /* non-NULL: beta is read from this device double when the
+                                    kernel starts (e.g. written by
+                                    smcgw_smc_reweight_resample_async), and `beta` is ignored */
 } smcgw_nuts_params;
 
 /* Message for a status code (static storage). */
@@ -222,11 +225,12 @@ int smcgw_mass_matrix(smcgw_ctx *ctx, int P, int D, const double *theta, double 
  * chol_per_particle = 1); fisher [P][D][D] (may be NULL) receives F.  A
  * particle whose M_i or M_i^{-1} is not numerically positive definite gets
  * fallback_chol [D][D] (NULL: the identity) and status [P] = 1 (status may
- * be NULL; 0 otherwise).  All arrays are device arrays; beta in [0, 1].
+ * be NULL; 0 otherwise).  All arrays are device arrays; beta in [0, 1], or
+ * read from the device double beta_device when that is not NULL.
  * Needs the GW target, a prior and a parameter map of dimension D.
  * Asynchronous on the context's stream. */
-int smcgw_local_metric(smcgw_ctx *ctx, int P, int D, const double *theta, double beta, const double *fallback_chol,
-                       double *chol, double *fisher, int32_t *status);
+int smcgw_local_metric(smcgw_ctx *ctx, int P, int D, const double *theta, double beta, const double *beta_device,
+                       const double *fallback_chol, double *chol, double *fisher, int32_t *status);
 
 /* One No-U-Turn transition per particle (Sec. 4: momentum r ~ N(0, M),
  * Hamiltonian H = -log p_t + r^T M^{-1} r / 2, leapfrog Eqs. 11-13,
@@ -264,6 +268,45 @@ int smcgw_nuts_step(smcgw_ctx *ctx, int P, int D, double *theta, double *logl, d
 int smcgw_smc_reweight_resample(smcgw_ctx *ctx, int P, int D, double beta_prev, double alpha, uint64_t seed,
                                 uint64_t iteration, double *theta, double *logl, double *grad, int32_t *carry,
                                 int32_t *ancestors, double *beta_next_host, double *dlogz_host);
+
+/* The same reweighting, temperature search and resampling without a host
+ * synchronisation: out_device [2] (device) receives beta_next and the
+ * evidence increment log(Z_t/Z_{t-1}).  The caller reads them back when it
+ * needs them (e.g. through an event) and can queue the mass matrix and the
+ * NUTS transition first, passing out_device as their beta_device, so the
+ * device does not wait for the host between the steps of an iteration.
+ * beta_next equal to beta_prev < 1 means the temperature could not advance
+ * (the synchronous call's SMCGW_ERR_STALL). */
+int smcgw_smc_reweight_resample_async(smcgw_ctx *ctx, int P, int D, double beta_prev, double alpha, uint64_t seed,
+                                      uint64_t iteration, double *theta, double *logl, double *grad, int32_t *carry,
+                                      int32_t *ancestors, double *out_device);
+
+/* Persistent sampling (Karamanis & Seljak 2024, arXiv:2407.20722; the SMC
+ * variant the paper names as future work, Sec. 7): every earlier population
+ * stays in a pool.  The pool holds T populations of N points, population s
+ * drawn from p_s = L^beta_s pi / Z_s (s = 0: the prior sample, beta_0 = 0,
+ * log Z_0 = 0), and is read as draws of the mixture (1/T) sum_s p_s.  The
+ * next temperature's weights over the pool are
+ *   w_i(beta) = L_i^beta / ((1/T) sum_s L_i^beta_s / Z_s)
+ * (the prior cancels); beta_next solves ESS(beta) = alpha N by the bisection
+ * of smcgw_smc_reweight_resample over [beta_{T-1}, 1] (beta_next = 1 when
+ * ESS(1) >= alpha N), the evidence is the pool mean of the weights,
+ *   log Z(beta_next) = log((1 / (T N)) sum_i w_i(beta_next)),
+ * and N ancestors are drawn from the pool with the Philox uniforms of
+ * smcgw_smc_reweight_resample; theta [N][D], logl [N] and grad [N][D]
+ * (device) receive the drawn points.  theta_pool [T*N][D], logl_pool [T*N]
+ * and grad_pool [T*N][D] (device; grad_pool and grad both NULL or both set)
+ * hold the pool, population s at rows s N .. s N + N - 1; betas_host [T] and
+ * logz_host [T] (host) its temperatures and log evidences.  NaN or -inf
+ * log L: weight zero.  ancestors [N] (device) receives pool indices.
+ * Synchronises: *beta_next_host and *logz_next_host (log Z at beta_next,
+ * not an increment) are host scalars.  Returns SMCGW_ERR_STALL when beta
+ * cannot advance. */
+int smcgw_ps_reweight_resample(smcgw_ctx *ctx, int T, int N, int D, const double *theta_pool,
+                               const double *logl_pool, const double *grad_pool, const double *betas_host,
+                               const double *logz_host, double alpha, uint64_t seed, uint64_t iteration,
+                               double *theta, double *logl, double *grad, int32_t *ancestors, double *beta_next_host,
+                               double *logz_next_host);
 
 /* Sample recycling (Sec. 5, "Samples recycling"): the populations left by
  * the mutations of iterations t = 1..T are pooled and read as draws of the

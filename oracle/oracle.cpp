@@ -1052,6 +1052,76 @@ int orc_rb_prepare(const orc_event* ev, const orc_detector* dets, const double* 
     return 0;
 }
 
+// Persistent sampling (Karamanis & Seljak 2024, arXiv:2407.20722; the SMC
+// variant named as future work in Sec. 7).  Every earlier population stays in
+// a pool: iteration s contributed N points drawn from p_s = L^beta_s pi / Z_s
+// (s = 0 is the prior sample, beta_0 = 0, Z_0 = 1), and the pool of T
+// populations is read as draws of the mixture (1/T) sum_s p_s.  The next
+// temperature's unnormalised weights over the pool are
+//   w_i(beta) = L_i^beta / ((1/T) sum_s L_i^beta_s / Z_s)
+// (the prior cancels).  beta_next solves ESS(beta) = alpha N (N points per
+// population; beta_next = 1 when ESS(1) >= alpha N), by the same bisection
+// as orc_smc_reweight, and the evidence is the pool mean of the weights,
+//   Z(beta_next) = (1 / (T N)) sum_i w_i(beta_next).
+// logl [T][N], betas [T], logz [T] (log Z_s).  Outputs: *beta_next,
+// *logz_next and weights [T*N] normalised to sum one.  Non-finite log L:
+// weight zero.  Returns -6 when beta cannot advance.
+int orc_ps_reweight(int T, int N, const double* logl, const double* betas, const double* logz, double beta_prev,
+                    double alpha, double* beta_next, double* logz_next, double* weights) {
+    if (T < 1 || N < 1) return -1;
+    const int n = T * N;
+    std::vector<double> lmix(n), lw(n);
+    for (int i = 0; i < n; ++i) {
+        const double l = logl[i];
+        if (!(l > -INFINITY)) { lmix[i] = NAN; continue; }
+        std::vector<double> terms(T);
+        for (int t = 0; t < T; ++t) terms[t] = betas[t] * l - logz[t];
+        lmix[i] = lse(terms.data(), T, 1.0) - std::log((double)T);
+    }
+    auto logw = [&](double beta, std::vector<double>& out) {
+        for (int i = 0; i < n; ++i) out[i] = (logl[i] > -INFINITY) ? beta * logl[i] - lmix[i] : -INFINITY;
+    };
+    auto ess = [&](double beta) {
+        logw(beta, lw);
+        const double a = lse(lw.data(), n, 1.0), b = lse(lw.data(), n, 2.0);
+        return std::exp(2.0 * a - b);
+    };
+    const double target = alpha * N;
+    double beta;
+    if (ess(1.0) >= target) {
+        beta = 1.0;
+    } else {
+        double lo = beta_prev, hi = 1.0;
+        for (int it = 0; it < 100 && hi - lo > 1e-14; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            if (ess(mid) >= target) lo = mid; else hi = mid;
+        }
+        beta = lo;
+    }
+    logw(beta, lw);
+    const double l = lse(lw.data(), n, 1.0);
+    *beta_next = beta;
+    *logz_next = l - std::log((double)n);
+    for (int i = 0; i < n; ++i) weights[i] = std::exp(lw[i] - l);
+    return (beta <= beta_prev && beta_prev < 1.0) ? -6 : 0;
+}
+
+// n_draw multinomial draws from n_w weights (orc_resample with the two counts apart).
+int orc_resample_n(int n_w, const double* weights, int n_draw, uint64_t seed, uint64_t iteration, int32_t* ancestors) {
+    std::vector<double> cum(n_w);
+    double s = 0.0;
+    for (int i = 0; i < n_w; ++i) { s += weights[i]; cum[i] = s; }
+    for (int i = 0; i < n_w; ++i) cum[i] /= s;
+    cum[n_w - 1] = 1.0;
+    for (int i = 0; i < n_draw; ++i) {
+        double u[2];
+        uniforms2(seed, 0u, (uint32_t)i, iteration, PURPOSE_RESAMPLE, u);
+        int k = (int)(std::upper_bound(cum.begin(), cum.end(), u[0]) - cum.begin());
+        ancestors[i] = std::min(k, n_w - 1);
+    }
+    return 0;
+}
+
 // A full SMC run: adaptive tempering, multinomial resampling, covariance mass
 // matrix, one NUTS transition per iteration; stops after mutating at beta = 1.
 // x [P][D] holds the prior draws on entry and the final population on exit.

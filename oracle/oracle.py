@@ -301,6 +301,26 @@ def local_metric(target: Target, x, beta: float, want_fisher: bool = True, fallb
     return st, F, L
 
 
+def ps_reweight(logl_pool, betas, logz, beta_prev: float, alpha: float):
+    """Persistent sampling (Karamanis & Seljak 2024): pooled weights of the next temperature.  logl_pool
+    [T][N], betas [T], logz [T].  Returns (rc, beta_next, log Z(beta_next), normalised weights [T*N])."""
+    ll = _f64(logl_pool)
+    T, N = ll.shape
+    w = np.zeros(T * N)
+    b = C.c_double()
+    z = C.c_double()
+    rc = lib().orc_ps_reweight(C.c_int(T), C.c_int(N), _dp(ll), _dp(_f64(betas)), _dp(_f64(logz)),
+                               C.c_double(beta_prev), C.c_double(alpha), C.byref(b), C.byref(z), _dp(w))
+    return rc, b.value, z.value, w
+
+
+def resample_n(weights, n_draw: int, seed: int, iteration: int) -> np.ndarray:
+    w = _f64(weights)
+    a = np.zeros(n_draw, np.int32)
+    lib().orc_resample_n(C.c_int(w.size), _dp(w), C.c_int(n_draw), C.c_uint64(seed), C.c_uint64(iteration), _ip(a))
+    return a
+
+
 def recycle(logl, betas, logz, seed: int):
     """Sample recycling (Sec. 5): logl [T][N] of the populations after each iteration's mutation, betas [T],
     logz [T] (running log evidence).  Returns (logw [T*N], accepted pool indices, Kish ESS)."""

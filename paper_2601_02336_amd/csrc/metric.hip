@@ -97,7 +97,8 @@ __device__ bool block_cholesky(const double* A, double* Lo, int D, int tid) {
 __global__ __launch_bounds__(MET_THREADS) void local_metric_kernel(const DevEvent* __restrict__ evs, int n_events,
                                                                   const int32_t* __restrict__ ev_of_p, ParamMap pm,
                                                                   PrecDesc pd, int P, const double* __restrict__ theta,
-                                                                  double beta, const double* __restrict__ fallback,
+                                                                  double beta_host, const double* __restrict__ beta_dev,
+                                                                  const double* __restrict__ fallback,
                                                                   double* __restrict__ chol, double* __restrict__ fisher,
                                                                   int32_t* __restrict__ status) {
     __shared__ MetricShared S;
@@ -183,6 +184,7 @@ __global__ __launch_bounds__(MET_THREADS) void local_metric_kernel(const DevEven
     }
     __syncthreads();
 
+    const double beta = beta_dev ? *beta_dev : beta_host;
     // J M J over the sampled coordinates (rows and columns in reverse order)
     for (int i = tid; i < MAXDIM * MAXDIM; i += MET_THREADS) {
         const int a = i / MAXDIM, b = i % MAXDIM;
@@ -254,8 +256,10 @@ static PrecDesc prior_precision(const PriorDesc& pr) {
 using namespace smcgw;
 
 extern "C" int smcgw_local_metric(smcgw_ctx* c, int P, int D, const double* theta, double beta,
-                                  const double* fallback_chol, double* chol, double* fisher, int32_t* status) {
-    if (!c || P < 0 || D <= 0 || D > MAXDIM || !(beta >= 0.0 && beta <= 1.0) || (P > 0 && (!theta || !chol)))
+                                  const double* beta_device, const double* fallback_chol, double* chol, double* fisher,
+                                  int32_t* status) {
+    if (!c || P < 0 || D <= 0 || D > MAXDIM || (!beta_device && !(beta >= 0.0 && beta <= 1.0)) ||
+        (P > 0 && (!theta || !chol)))
         return SMCGW_ERR_INVALID;
     if (c->events.empty() || !c->prior_set || c->target.kind != SMCGW_TARGET_GW) return SMCGW_ERR_NOT_INIT;
     if (c->prior.dim != D || c->pmap.dim != D) return SMCGW_ERR_INVALID;
@@ -264,7 +268,7 @@ extern "C" int smcgw_local_metric(smcgw_ctx* c, int P, int D, const double* thet
     const PrecDesc pd = prior_precision(c->prior);
     TimedLaunch tl(c, SMCGW_KERNEL_METRIC);
     hipLaunchKernelGGL(local_metric_kernel, dim3(P), dim3(MET_THREADS), 0, c->stream, c->d_events,
-                       (int)c->events.size(), c->ev_of_p, c->pmap, pd, P, theta, beta, fallback_chol, chol, fisher,
+                       (int)c->events.size(), c->ev_of_p, c->pmap, pd, P, theta, beta, beta_device, fallback_chol, chol, fisher,
                        status);
     return hipGetLastError() == hipSuccess ? SMCGW_OK : SMCGW_ERR_HIP;
 }

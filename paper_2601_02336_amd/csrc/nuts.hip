@@ -50,6 +50,7 @@ struct NutsArgs {
     const int32_t* order;   // start order of the particles (NULL: index order)
     int priority;           // raise wavefront priority with the tree depth
     int chol_pp;            // chol holds one [D][D] factor per particle
+    const double* beta_dev; // beta from device memory (NULL: the value above)
 };
 
 constexpr int MAX_WAVES = 8;
@@ -613,6 +614,7 @@ __global__ __launch_bounds__(WAVES * 64, (WAVES == 1 ? 2 : NUTS_WAVES_PER_SIMD))
     if (!a.chol_pp) load_factor(S, a.chol, D, tid);
     if (tid == 0) {
         A = a;
+        if (a.beta_dev) A.beta = *a.beta_dev;
         for (int k = 0; k < MAXDIM; ++k) {
             S.plo[k] = pri.lo[k]; S.phi[k] = pri.hi[k]; S.pbnd[k] = pri.bnd[k]; S.pkind[k] = pri.kind[k];
             S.pidx[k] = pm.idx[k];
@@ -826,7 +828,8 @@ extern "C" int smcgw_nuts_step(smcgw_ctx* c, int P, int D, double* theta, double
     if (!c || !prm || P < 0 || D <= 0 || D > MAXDIM || (P > 0 && (!theta || !logl || !grad || !chol)))
         return SMCGW_ERR_INVALID;
     if (precision != SMCGW_PLAIN_FP64 && precision != SMCGW_MIXED) return SMCGW_ERR_INVALID;
-    if (prm->max_depth < 0 || prm->max_depth > SMCGW_MAX_DEPTH || !(prm->step > 0.0) || !(prm->beta >= 0.0) ||
+    if (prm->max_depth < 0 || prm->max_depth > SMCGW_MAX_DEPTH || !(prm->step > 0.0) ||
+        (!prm->beta_device && !(prm->beta >= 0.0)) ||
         !(prm->max_delta_h > 0.0) || (prm->chol_per_particle != 0 && prm->chol_per_particle != 1) ||
         prm->reserved != 0)
         return SMCGW_ERR_INVALID;
@@ -877,6 +880,7 @@ extern "C" int smcgw_nuts_step(smcgw_ctx* c, int P, int D, double* theta, double
     a.order = work_hint ? c->d_order : nullptr;
     a.priority = c->nuts_priority;
     a.chol_pp = prm->chol_per_particle;
+    a.beta_dev = prm->beta_device;
     const TargetDesc t = c->target;
     switch (kind) {
     case SMCGW_TARGET_GW:

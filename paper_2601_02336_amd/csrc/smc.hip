@@ -74,22 +74,37 @@ __device__ __forceinline__ double incr_weight(double db, double e) { return db =
 // normalised weights and their inclusive prefix sum (fixed order).
 // out[0] = beta_next, out[1] = log(Z_t / Z_{t-1}), out[2] = cum[P-1].
 // Non-finite logL count as zero weight.
+// Persistent sampling passes lofs [P] (the log mixture density of every
+// pooled point, see pool_logmix_kernel) and n_target (points per
+// population): a point's weight at beta is then L^beta / mixture, written as
+// exp(g_i + (beta - beta_prev) (logL_i - lmax)) with g_i = beta_prev logL_i -
+// lofs_i - max_j(...), the ESS target is alpha n_target and out[1] is log Z
+// at beta_next itself (the pool mean of the weights).  lofs = NULL is
+// standard SMC (g_i = 0, n_target = P).
 __global__ __launch_bounds__(RW_THREADS) void reweight_kernel(const double* __restrict__ logl, int P,
                                                               double beta_prev, double alpha,
+                                                              const double* __restrict__ lofs, int n_target,
                                                               double* __restrict__ cum, double* __restrict__ out) {
     __shared__ double red[2 * RW_CAND * (RW_THREADS / 64)];
     __shared__ double tot[2 * RW_CAND];
     __shared__ double cand[RW_CAND];
     __shared__ double scan[RW_THREADS / 64 + 1];
-    double lm = -INFINITY;
-    for (int i = threadIdx.x; i < P; i += blockDim.x) lm = fmax(lm, ll_at(logl, i));
+    double lm = -INFINITY, gm = -INFINITY;
+    for (int i = threadIdx.x; i < P; i += blockDim.x) {
+        const double l = ll_at(logl, i);
+        lm = fmax(lm, l);
+        if (lofs && l > -INFINITY) gm = fmax(gm, beta_prev * l - lofs[i]);
+    }
     const double lmax = block_max(lm, red);
     if (!(lmax > -INFINITY)) {   // no particle with a finite likelihood: nothing to reweight
         for (int i = threadIdx.x; i < P; i += blockDim.x) cum[i] = 0.0;
         if (threadIdx.x == 0) { out[0] = beta_prev; out[1] = -INFINITY; out[2] = 0.0; }
         return;
     }
-    const double target = alpha * (double)P;
+    const double gmax = lofs ? block_max(gm, red) : 0.0;
+    // base log weight of point i at beta_prev, relative to the largest (0 for standard SMC)
+    auto base = [&](int i, double l) { return lofs ? beta_prev * l - lofs[i] - gmax : 0.0; };
+    const double target = alpha * (double)(lofs ? n_target : P);
     // Each pass resolves RW_LEVELS bisection levels below [lo, hi].  The
     // midpoints those levels can visit are lo + k h, k = 1..15, h = (hi - lo)/16
     // (slot k); they are computed exactly as the sequential bisection computes
@@ -117,15 +132,17 @@ __global__ __launch_bounds__(RW_THREADS) void reweight_kernel(const double* __re
 #pragma unroll
         for (int n = 0; n < 2 * RW_CAND; ++n) s[n] = 0.0;
         for (int i = threadIdx.x; i < P; i += blockDim.x) {
-            const double e = ll_at(logl, i) - lmax;
+            const double l = ll_at(logl, i);
+            const double e = l - lmax;
             if (e == -INFINITY) continue;   // zero weight at every candidate (db > 0)
+            const double g = base(i, l);
             if (pass == 0) {
-                const double w1 = exp((1.0 - beta_prev) * e);
+                const double w1 = exp(g + (1.0 - beta_prev) * e);
                 s[0] += w1;
                 s[1] += w1 * w1;
             }
             const double r = exp(h * e);
-            double w = exp(d0 * e);
+            double w = exp(g + d0 * e);
 #pragma unroll
             for (int k = 1; k < RW_CAND; ++k) {
                 w *= r;
@@ -145,17 +162,23 @@ __global__ __launch_bounds__(RW_THREADS) void reweight_kernel(const double* __re
         }
     }
     const double db = beta - beta_prev;
-    // log-sum-exp of db logL (max of db logL is db lmax for db >= 0)
+    // weight of point i at beta relative to db lmax + gmax (zero for a non-finite logL)
+    auto weight = [&](int i) {
+        const double l = ll_at(logl, i);
+        if (!lofs) return incr_weight(db, l - lmax);
+        return l > -INFINITY ? exp(base(i, l) + db * (l - lmax)) : 0.0;
+    };
+    // log-sum-exp of the log weights (max of db logL is db lmax for db >= 0)
     double s1[1] = {0.0};
-    for (int i = threadIdx.x; i < P; i += blockDim.x) s1[0] += incr_weight(db, ll_at(logl, i) - lmax);
+    for (int i = threadIdx.x; i < P; i += blockDim.x) s1[0] += weight(i);
     block_sums<1>(s1, red, tot);
-    const double lse = db * lmax + log(tot[0]);
+    const double lse = db * lmax + gmax + log(tot[0]);
     // inclusive prefix sum: thread t owns the contiguous chunk [t*ch, (t+1)*ch)
     const int ch = (P + blockDim.x - 1) / blockDim.x;
     const int lo_i = threadIdx.x * ch, hi_i = min(P, lo_i + ch);
     double loc = 0.0;
     const double inv_tot = 1.0 / tot[0];   // normalised weight: exp(db (logL - lmax)) / sum
-    for (int i = lo_i; i < hi_i; ++i) loc += incr_weight(db, ll_at(logl, i) - lmax) * inv_tot;
+    for (int i = lo_i; i < hi_i; ++i) loc += weight(i) * inv_tot;
     // exclusive scan of the chunk totals: lanes (shuffle ladder), then wavefronts
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double inc = loc;
@@ -176,7 +199,7 @@ __global__ __launch_bounds__(RW_THREADS) void reweight_kernel(const double* __re
     if (lane == 0) ex = 0.0;
     double run = scan[wave] + ex;
     for (int i = lo_i; i < hi_i; ++i) {
-        run += incr_weight(db, ll_at(logl, i) - lmax) * inv_tot;
+        run += weight(i) * inv_tot;
         cum[i] = run;
     }
     __syncthreads();
@@ -189,10 +212,10 @@ __global__ __launch_bounds__(RW_THREADS) void reweight_kernel(const double* __re
 
 // Ancestor of particle i: first k with cum_k / cum_{P-1} > u_i (last entry forced to 1).
 __global__ __launch_bounds__(256) void ancestors_kernel(const double* __restrict__ cum, const double* __restrict__ out,
-                                                        int P, uint64_t seed, uint64_t iteration,
+                                                        int P, int n_draw, uint64_t seed, uint64_t iteration,
                                                         int32_t* __restrict__ anc) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= P) return;
+    if (i >= n_draw) return;
     double u, u1;
     rng_uniform2(seed, 0u, (uint32_t)i, iteration, RNG_RESAMPLE, u, u1);
     const double total = out[2];
@@ -376,6 +399,15 @@ __global__ __launch_bounds__(256) void analytic_loglike_kernel(int kind, int P, 
     logl[i] = ll;
 }
 
+// log((1/T) sum_t L^beta_t / Z_t) for one point of log-likelihood l.
+__device__ __forceinline__ double log_mixture(double l, const double* betas, const double* logz, int T) {
+    double m = -INFINITY;
+    for (int t = 0; t < T; ++t) m = fmax(m, betas[t] * l - logz[t]);
+    double s = 0.0;
+    for (int t = 0; t < T; ++t) s += exp(betas[t] * l - logz[t] - m);
+    return m + log(s) - log((double)T);
+}
+
 // Sample recycling (Sec. 5, "Samples recycling").  The populations left by
 // the mutations of iterations t = 1..T form a pool read as draws of the
 // mixture (1/T) sum_t p_t, p_t = L^beta_t pi / Z_t.  Point i's weight for the
@@ -392,13 +424,18 @@ __global__ __launch_bounds__(256) void recycle_weights_kernel(const double* __re
         logw[i] = -INFINITY;
         return;
     }
-    const double* betas = bz;
-    const double* logz = bz + T;
-    double m = -INFINITY;
-    for (int t = 0; t < T; ++t) m = fmax(m, betas[t] * l - logz[t]);
-    double s = 0.0;
-    for (int t = 0; t < T; ++t) s += exp(betas[t] * l - logz[t] - m);
-    logw[i] = l - logz[T - 1] - (m + log(s) - log((double)T));
+    logw[i] = l - bz[2 * T - 1] - log_mixture(l, bz, bz + T, T);
+}
+
+// Log mixture density of the pool at every point (persistent sampling):
+// lofs_i = log((1/T) sum_t L_i^beta_t / Z_t); entries of non-finite logL are
+// not used.
+__global__ __launch_bounds__(256) void pool_logmix_kernel(const double* __restrict__ logl, int n, int T,
+                                                          const double* __restrict__ bz, double* __restrict__ lofs) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double l = logl[i];
+    lofs[i] = l > -INFINITY ? log_mixture(l, bz, bz + T, T) : 0.0;
 }
 
 // Rejection sampling over the pool in one workgroup: point i is kept when
@@ -456,6 +493,11 @@ __global__ __launch_bounds__(SMC_THREADS) void recycle_select_kernel(const doubl
         out[1] = tot[1] > 0.0 ? tot[0] * tot[0] / tot[1] : 0.0;
         out[2] = wmax;
     }
+}
+
+// out[0..1] (beta_next, evidence increment) into the caller's device buffer.
+__global__ void export_pair_kernel(const double* __restrict__ out, double* __restrict__ dst) {
+    if (threadIdx.x < 2) dst[threadIdx.x] = out[threadIdx.x];
 }
 
 // Scratch of the sampler entry points (device), grown on demand.
@@ -546,12 +588,14 @@ extern "C" int smcgw_mass_matrix(smcgw_ctx* c, int P, int D, const double* theta
     return s ? SMCGW_WARN_FALLBACK : SMCGW_OK;
 }
 
-extern "C" int smcgw_smc_reweight_resample(smcgw_ctx* c, int P, int D, double beta_prev, double alpha, uint64_t seed,
-                                           uint64_t iteration, double* theta, double* logl, double* grad,
-                                           int32_t* carry, int32_t* ancestors, double* beta_next_host,
-                                           double* dlogz_host) {
-    if (!c || P < 1 || D <= 0 || D > MAXDIM || !theta || !logl || !ancestors || !beta_next_host || !dlogz_host)
-        return SMCGW_ERR_INVALID;
+namespace smcgw {
+// Reweighting, temperature search, resampling and gather on the context's
+// stream; out (device) holds beta_next, the evidence increment and the
+// weight total when the queued work has run.
+static int reweight_resample(smcgw_ctx* c, int P, int D, double beta_prev, double alpha, uint64_t seed,
+                             uint64_t iteration, double* theta, double* logl, double* grad, int32_t* carry,
+                             int32_t* ancestors, double** out_dev) {
+    if (!c || P < 1 || D <= 0 || D > MAXDIM || !theta || !logl || !ancestors) return SMCGW_ERR_INVALID;
     if (!(alpha > 0.0 && alpha <= 1.0) || !(beta_prev >= 0.0 && beta_prev <= 1.0)) return SMCGW_ERR_INVALID;
     hipSetDevice(c->device);
     const size_t off_cum = 64 * sizeof(double);
@@ -561,21 +605,36 @@ extern "C" int smcgw_smc_reweight_resample(smcgw_ctx* c, int P, int D, double be
     const size_t off_cy = off_g + (size_t)P * D * sizeof(double);
     const size_t bytes = off_cy + (size_t)P * sizeof(int32_t);
     char* s = (char*)sampler_scratch(c, bytes);
-    double* hp = pinned(c);
-    if (!s || !hp) return SMCGW_ERR_OOM;
+    if (!s) return SMCGW_ERR_OOM;
     double* out = (double*)s;
     double* cum = (double*)(s + off_cum);
     double* xo = (double*)(s + off_x);
     double* llo = (double*)(s + off_ll);
     double* go = (double*)(s + off_g);
     int32_t* cyo = (int32_t*)(s + off_cy);
-    hipLaunchKernelGGL(reweight_kernel, dim3(1), dim3(RW_THREADS), 0, c->stream, logl, P, beta_prev, alpha, cum, out);
+    hipLaunchKernelGGL(reweight_kernel, dim3(1), dim3(RW_THREADS), 0, c->stream, logl, P, beta_prev, alpha,
+                       (const double*)nullptr, P, cum, out);
     const dim3 g((P + 255) / 256), b(256);
-    hipLaunchKernelGGL(ancestors_kernel, g, b, 0, c->stream, cum, out, P, seed, iteration, ancestors);
+    hipLaunchKernelGGL(ancestors_kernel, g, b, 0, c->stream, cum, out, P, P, seed, iteration, ancestors);
     hipLaunchKernelGGL(gather_kernel, g, b, 0, c->stream, ancestors, P, D, theta, logl, grad, carry, xo, llo, go,
                        cyo);
     hipLaunchKernelGGL(copy_back_kernel, g, b, 0, c->stream, P, D, xo, llo, go, cyo, theta, logl, grad, carry);
     if (hipGetLastError() != hipSuccess) return SMCGW_ERR_HIP;
+    *out_dev = out;
+    return SMCGW_OK;
+}
+}  // namespace smcgw
+
+extern "C" int smcgw_smc_reweight_resample(smcgw_ctx* c, int P, int D, double beta_prev, double alpha, uint64_t seed,
+                                           uint64_t iteration, double* theta, double* logl, double* grad,
+                                           int32_t* carry, int32_t* ancestors, double* beta_next_host,
+                                           double* dlogz_host) {
+    if (!beta_next_host || !dlogz_host) return SMCGW_ERR_INVALID;
+    double* out = nullptr;
+    int rc = reweight_resample(c, P, D, beta_prev, alpha, seed, iteration, theta, logl, grad, carry, ancestors, &out);
+    if (rc) return rc;
+    double* hp = pinned(c);
+    if (!hp) return SMCGW_ERR_OOM;
     if (hipMemcpyAsync(hp, out, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream) ||
         hipStreamSynchronize(c->stream))
         return SMCGW_ERR_HIP;
@@ -583,6 +642,18 @@ extern "C" int smcgw_smc_reweight_resample(smcgw_ctx* c, int P, int D, double be
     *dlogz_host = hp[1];
     if (!(hp[0] > beta_prev) && beta_prev < 1.0) return SMCGW_ERR_STALL;
     return SMCGW_OK;
+}
+
+extern "C" int smcgw_smc_reweight_resample_async(smcgw_ctx* c, int P, int D, double beta_prev, double alpha,
+                                                 uint64_t seed, uint64_t iteration, double* theta, double* logl,
+                                                 double* grad, int32_t* carry, int32_t* ancestors,
+                                                 double* out_device) {
+    if (!out_device) return SMCGW_ERR_INVALID;
+    double* out = nullptr;
+    int rc = reweight_resample(c, P, D, beta_prev, alpha, seed, iteration, theta, logl, grad, carry, ancestors, &out);
+    if (rc) return rc;
+    hipLaunchKernelGGL(export_pair_kernel, dim3(1), dim3(64), 0, c->stream, out, out_device);
+    return hipGetLastError() == hipSuccess ? SMCGW_OK : SMCGW_ERR_HIP;
 }
 
 extern "C" int smcgw_target_loglike_grad(smcgw_ctx* c, int P, const double* theta, double* logl, double* grad,
@@ -624,5 +695,59 @@ extern "C" int smcgw_recycle(smcgw_ctx* c, int T, int N, const double* logl, con
         return SMCGW_ERR_HIP;
     *n_kept_host = (int64_t)hp[0];
     *ess_host = hp[1];
+    return SMCGW_OK;
+}
+
+extern "C" int smcgw_ps_reweight_resample(smcgw_ctx* c, int T, int N, int D, const double* theta_pool,
+                                          const double* logl_pool, const double* grad_pool, const double* betas_host,
+                                          const double* logz_host, double alpha, uint64_t seed, uint64_t iteration,
+                                          double* theta, double* logl, double* grad, int32_t* ancestors,
+                                          double* beta_next_host, double* logz_next_host) {
+    if (!c || T < 1 || N < 1 || D <= 0 || D > MAXDIM || (int64_t)T * N > INT32_MAX || !theta_pool || !logl_pool ||
+        !betas_host || !logz_host || !theta || !logl || !ancestors || !beta_next_host || !logz_next_host ||
+        ((grad_pool == nullptr) != (grad == nullptr)))
+        return SMCGW_ERR_INVALID;
+    if (!(alpha > 0.0 && alpha <= 1.0)) return SMCGW_ERR_INVALID;
+    for (int t = 0; t < T; ++t)
+        if (!(betas_host[t] >= 0.0 && betas_host[t] <= 1.0) || !std::isfinite(logz_host[t])) return SMCGW_ERR_INVALID;
+    const double beta_prev = betas_host[T - 1];
+    hipSetDevice(c->device);
+    const int n = T * N;
+    const size_t off_bz = 64 * sizeof(double);
+    const size_t off_lofs = off_bz + 2 * (size_t)T * sizeof(double);
+    const size_t off_cum = off_lofs + (size_t)n * sizeof(double);
+    const size_t off_x = off_cum + (size_t)n * sizeof(double);
+    const size_t off_ll = off_x + (size_t)N * D * sizeof(double);
+    const size_t off_g = off_ll + (size_t)N * sizeof(double);
+    const size_t bytes = off_g + (size_t)N * D * sizeof(double);
+    char* s = (char*)sampler_scratch(c, bytes);
+    double* hp = pinned(c);
+    if (!s || !hp) return SMCGW_ERR_OOM;
+    double* out = (double*)s;
+    double* bz = (double*)(s + off_bz);
+    double* lofs = (double*)(s + off_lofs);
+    double* cum = (double*)(s + off_cum);
+    double* xo = (double*)(s + off_x);
+    double* llo = (double*)(s + off_ll);
+    double* go = (double*)(s + off_g);
+    if (hipMemcpyAsync(bz, betas_host, T * sizeof(double), hipMemcpyHostToDevice, c->stream) ||
+        hipMemcpyAsync(bz + T, logz_host, T * sizeof(double), hipMemcpyHostToDevice, c->stream))
+        return SMCGW_ERR_HIP;
+    hipLaunchKernelGGL(pool_logmix_kernel, dim3((n + 255) / 256), dim3(256), 0, c->stream, logl_pool, n, T, bz, lofs);
+    hipLaunchKernelGGL(reweight_kernel, dim3(1), dim3(RW_THREADS), 0, c->stream, logl_pool, n, beta_prev, alpha,
+                       (const double*)lofs, N, cum, out);
+    const dim3 g((N + 255) / 256), b(256);
+    hipLaunchKernelGGL(ancestors_kernel, g, b, 0, c->stream, cum, out, n, N, seed, iteration, ancestors);
+    hipLaunchKernelGGL(gather_kernel, g, b, 0, c->stream, ancestors, N, D, theta_pool, logl_pool, grad_pool,
+                       (const int32_t*)nullptr, xo, llo, go, (int32_t*)nullptr);
+    hipLaunchKernelGGL(copy_back_kernel, g, b, 0, c->stream, N, D, xo, llo, go, (const int32_t*)nullptr, theta, logl,
+                       grad, (int32_t*)nullptr);
+    if (hipGetLastError() != hipSuccess) return SMCGW_ERR_HIP;
+    if (hipMemcpyAsync(hp, out, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream) ||
+        hipStreamSynchronize(c->stream))
+        return SMCGW_ERR_HIP;
+    *beta_next_host = hp[0];
+    *logz_next_host = hp[1];
+    if (!(hp[0] > beta_prev) && beta_prev < 1.0) return SMCGW_ERR_STALL;
     return SMCGW_OK;
 }

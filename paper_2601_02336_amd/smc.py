@@ -34,6 +34,7 @@ class SmcConfig:
     work_hint: bool = True        # start the particles whose ancestors took the longest trees first
     metric: str = "population"    # "population": one covariance metric; "local": one metric per particle
     recycle: bool = False         # pool every iteration's population and draw i.i.d. samples from it
+    variant: str = "standard"     # "standard" SMC, or "persistent" sampling (every population stays in the pool)
 
 
 @dataclasses.dataclass
@@ -57,43 +58,64 @@ class SmcResult:
 
 
 def run_smc(ctx: "smcgw.Context", theta0: torch.Tensor, cfg: SmcConfig) -> SmcResult:
-    """Run the tempered sampler from prior draws theta0 [P, D] (device, float64)."""
+    """Run the tempered sampler from prior draws theta0 [P, D] (device, float64).
+
+    Each iteration is queued without waiting for the host: the reweighting writes beta_t and the evidence
+    increment to device memory, the mass matrix (or the local metric) and the NUTS transition read beta_t
+    from there, and the host reads beta_t back through an event while the transition runs, to decide whether
+    to queue the next iteration.  Diagnostics stay on the device until the run ends."""
     if cfg.metric not in ("population", "local"):
         raise ValueError(f"unknown metric {cfg.metric!r}")
+    if cfg.variant == "persistent":
+        return _run_persistent(ctx, theta0, cfg)
+    if cfg.variant != "standard":
+        raise ValueError(f"unknown variant {cfg.variant!r}")
+    dev = theta0.device
     theta = theta0.clone().contiguous()
     logl, grad = ctx.target_loglike_grad(theta, precision=cfg.precision)
     beta, logz = 0.0, 0.0
-    betas, dlogzs, nlf, depths, divs = [], [], [], [], []
-    fallbacks = 0
-    local_bad = []
+    betas, dlogzs = [], []
+    nlf_d, depth_d, div_d, mm_d, local_d = [], [], [], [], []
     pool_x, pool_ll = [], []
     pops = [] if cfg.record else None
     hint = None   # leapfrog counts of the last transition, resampled with the particles
-    mm_status = torch.zeros(1, dtype=torch.int32, device=theta.device)   # 1: diagonal mass-matrix fallback
+    bz = torch.zeros((cfg.max_iter, 2), dtype=torch.float64, device=dev)     # beta_t, dlogZ_t on the device
+    bz_host = torch.zeros((cfg.max_iter, 2), dtype=torch.float64, pin_memory=True)
     t0 = time.perf_counter()
     it = 0
     while beta < 1.0 and it < cfg.max_iter:
         if cfg.record:
             pops.append(theta.clone())
-        b, dz, _ = ctx.smc_reweight_resample(theta, logl, grad, beta, cfg.alpha, cfg.seed, it, carry=hint)
-        logz += dz
+        ctx.smc_reweight_resample_async(theta, logl, grad, beta, cfg.alpha, cfg.seed, it, bz[it], carry=hint)
+        bz_host[it].copy_(bz[it], non_blocking=True)
+        ready = torch.cuda.Event()
+        ready.record()
+        beta_dev = bz[it, 0:1]
+        mm_status = torch.zeros(1, dtype=torch.int32, device=dev)   # 1: diagonal mass-matrix fallback
         _, L, _ = ctx.mass_matrix(theta, cfg.shrink, status=mm_status)
+        mm_d.append(mm_status)
         if cfg.metric == "local":
             # the population factor stands in for particles whose local metric is not positive definite
-            L, _, st = ctx.local_metric(theta, b, fallback=L)
-            local_bad.append(st.sum())
-        out = ctx.nuts_step(theta, logl, grad, L, step=cfg.step, beta=b, seed=cfg.seed, iteration=it,
-                            max_depth=cfg.max_depth, uturn=cfg.uturn, precision=cfg.precision, work_hint=hint)
+            L, _, st = ctx.local_metric(theta, 0.0, fallback=L, beta_device=beta_dev)
+            local_d.append(st.sum())
+        out = ctx.nuts_step(theta, logl, grad, L, step=cfg.step, beta=0.0, seed=cfg.seed, iteration=it,
+                            max_depth=cfg.max_depth, uturn=cfg.uturn, precision=cfg.precision, work_hint=hint,
+                            beta_device=beta_dev)
         hint = out["n_leapfrog"] if cfg.work_hint else None
         if cfg.recycle:
             pool_x.append(theta.clone())
             pool_ll.append(logl.clone())
+        nlf_d.append(out["n_leapfrog"].sum())
+        depth_d.append(out["depth"].double().mean())
+        div_d.append(out["divergent"].sum())
+        ready.synchronize()   # beta_t is on the host; the transition may still run
+        b, dz = float(bz_host[it, 0]), float(bz_host[it, 1])
+        if not (b > beta) and beta < 1.0:
+            torch.cuda.synchronize()
+            raise smcgw.SmcgwError("smcgw_smc_reweight_resample_async", smcgw.ERR_STALL)
+        logz += dz
         betas.append(b)
         dlogzs.append(dz)
-        nlf.append(int(out["n_leapfrog"].sum().item()))
-        depths.append(float(out["depth"].double().mean().item()))
-        divs.append(int(out["divergent"].sum().item()))
-        fallbacks += int(mm_status.item())
         beta = b
         it += 1
     recycled, ress = None, 0.0
@@ -106,6 +128,65 @@ def run_smc(ctx: "smcgw.Context", theta0: torch.Tensor, cfg: SmcConfig) -> SmcRe
         _, kept, ress = ctx.recycle(torch.stack(pool_ll), betas, running, cfg.seed)
         recycled = torch.cat(pool_x)[kept.long()]
     torch.cuda.synchronize()
-    n_local_bad = int(sum(int(x.item()) for x in local_bad))
+    nlf = [int(x.item()) for x in nlf_d]
+    depths = [float(x.item()) for x in depth_d]
+    divs = [int(x.item()) for x in div_d]
+    fallbacks = sum(int(x.item()) for x in mm_d)
+    n_local_bad = sum(int(x.item()) for x in local_d)
     return SmcResult(logz, betas, dlogzs, it, theta, logl, grad, nlf, depths, divs, time.perf_counter() - t0, pops,
                      fallbacks, n_local_bad, recycled, ress)
+
+
+def _run_persistent(ctx: "smcgw.Context", theta0: torch.Tensor, cfg: SmcConfig) -> SmcResult:
+    """Persistent sampling (Karamanis & Seljak 2024; named in Sec. 7 as future work): the prior sample and every
+    mutated population stay in a pool, each iteration draws the next population from the whole pool with the
+    weights of the next temperature against the pool's mixture, and the evidence at each temperature is the
+    pool's mean weight (smcgw_ps_reweight_resample).  Mutations as in the standard variant."""
+    dev = theta0.device
+    P, D = theta0.shape
+    theta = theta0.clone().contiguous()
+    logl, grad = ctx.target_loglike_grad(theta, precision=cfg.precision)
+    cap = 16
+    pool_x = torch.empty((cap, P, D), dtype=torch.float64, device=dev)
+    pool_ll = torch.empty((cap, P), dtype=torch.float64, device=dev)
+    pool_g = torch.empty((cap, P, D), dtype=torch.float64, device=dev)
+    pool_x[0], pool_ll[0], pool_g[0] = theta, logl, grad
+    pool_beta, pool_logz = [0.0], [0.0]
+    betas, dlogzs, nlf_d, depth_d, div_d, mm_d, local_d = [], [], [], [], [], [], []
+    pops = [] if cfg.record else None
+    beta, it = 0.0, 0
+    t0 = time.perf_counter()
+    while beta < 1.0 and it < cfg.max_iter:
+        T = len(pool_beta)
+        if cfg.record:
+            pops.append(pool_x[:T].reshape(T * P, D).clone())
+        b, lz, _ = ctx.ps_reweight_resample(pool_x[:T].reshape(T * P, D), pool_ll[:T].reshape(T * P),
+                                            pool_g[:T].reshape(T * P, D), pool_beta, pool_logz, cfg.alpha,
+                                            cfg.seed, it, theta, logl, grad)
+        mm_status = torch.zeros(1, dtype=torch.int32, device=dev)
+        _, L, _ = ctx.mass_matrix(theta, cfg.shrink, status=mm_status)
+        mm_d.append(mm_status)
+        if cfg.metric == "local":
+            L, _, st = ctx.local_metric(theta, b, fallback=L)
+            local_d.append(st.sum())
+        out = ctx.nuts_step(theta, logl, grad, L, step=cfg.step, beta=b, seed=cfg.seed, iteration=it,
+                            max_depth=cfg.max_depth, uturn=cfg.uturn, precision=cfg.precision)
+        nlf_d.append(out["n_leapfrog"].sum())
+        depth_d.append(out["depth"].double().mean())
+        div_d.append(out["divergent"].sum())
+        if T == cap:   # grow the pool storage
+            cap *= 2
+            pool_x = torch.cat([pool_x, torch.empty_like(pool_x)])
+            pool_ll = torch.cat([pool_ll, torch.empty_like(pool_ll)])
+            pool_g = torch.cat([pool_g, torch.empty_like(pool_g)])
+        pool_x[T], pool_ll[T], pool_g[T] = theta, logl, grad
+        betas.append(b)
+        dlogzs.append(lz - pool_logz[-1])
+        pool_beta.append(b)
+        pool_logz.append(lz)
+        beta = b
+        it += 1
+    torch.cuda.synchronize()
+    return SmcResult(pool_logz[-1], betas, dlogzs, it, theta, logl, grad, [int(x.item()) for x in nlf_d],
+                     [float(x.item()) for x in depth_d], [int(x.item()) for x in div_d], time.perf_counter() - t0,
+                     pops, sum(int(x.item()) for x in mm_d), sum(int(x.item()) for x in local_d))

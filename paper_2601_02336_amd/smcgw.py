@@ -50,7 +50,7 @@ class Bounds(C.Structure):
 class NutsParams(C.Structure):
     _fields_ = [("step", C.c_double), ("beta", C.c_double), ("max_delta_h", C.c_double),
                 ("max_depth", C.c_int32), ("uturn", C.c_int32), ("seed", C.c_uint64), ("iteration", C.c_uint64),
-                ("chol_per_particle", C.c_int32), ("reserved", C.c_int32)]
+                ("chol_per_particle", C.c_int32), ("reserved", C.c_int32), ("beta_device", C.c_void_p)]
 
 
 _lib = None
@@ -98,7 +98,10 @@ def lib():
         L.smcgw_waveform.argtypes = [vp, i, vp, vp]
         L.smcgw_target_loglike_grad.argtypes = [vp, i, vp, vp, vp, i]
         L.smcgw_mass_matrix.argtypes = [vp, i, i, vp, d, vp, vp, vp]
-        L.smcgw_local_metric.argtypes = [vp, i, i, vp, d, vp, vp, vp, vp]
+        L.smcgw_local_metric.argtypes = [vp, i, i, vp, d, vp, vp, vp, vp, vp]
+        L.smcgw_ps_reweight_resample.argtypes = [vp, i, i, i, vp, vp, vp, vp, vp, d, u64, u64, vp, vp, vp, vp,
+                                                 C.POINTER(d), C.POINTER(d)]
+        L.smcgw_smc_reweight_resample_async.argtypes = [vp, i, i, d, d, u64, u64, vp, vp, vp, vp, vp, vp]
         L.smcgw_add_event_rb.argtypes = [vp, C.POINTER(EventDesc), vp, vp, C.POINTER(Detector), vp, d,
                                          C.POINTER(i), C.POINTER(i)]
         L.smcgw_rb_edges.argtypes = [d, d, i, d, vp, i]
@@ -290,9 +293,13 @@ class Context:
         return inv, L, rc
 
     def local_metric(self, theta: torch.Tensor, beta: float, fallback: Optional[torch.Tensor] = None,
-                     fisher: bool = False, status: bool = True):
+                     fisher: bool = False, status: bool = True, beta_device: Optional[torch.Tensor] = None):
         """Per-particle metric factors chol [P][D][D] (lower Cholesky factor of (beta F + prior precision)^-1).
+        beta_device (a one-element device float64 tensor) supplies beta from device memory instead.
         Returns (chol, fisher or None, status or None); asynchronous."""
+        if beta_device is not None:
+            _dev(beta_device, torch.float64, "beta_device")
+            beta = 0.0
         theta = _dev(theta, torch.float64, "theta")
         P, D = theta.shape
         dev = theta.device
@@ -304,8 +311,8 @@ class Context:
             if tuple(fallback.shape) != (D, D):
                 raise ValueError("fallback must be [D][D]")
         self._stream()
-        _check("smcgw_local_metric", lib().smcgw_local_metric(self._h, P, D, _ptr(theta), beta, _ptr(fallback),
-                                                              _ptr(L), _ptr(F), _ptr(st)))
+        _check("smcgw_local_metric", lib().smcgw_local_metric(self._h, P, D, _ptr(theta), beta, _ptr(beta_device),
+                                                              _ptr(fallback), _ptr(L), _ptr(F), _ptr(st)))
         return L, F, st
 
     def recycle(self, logl_pool: torch.Tensor, betas: Sequence[float], logz: Sequence[float], seed: int):
@@ -330,12 +337,16 @@ class Context:
     def nuts_step(self, theta: torch.Tensor, logl: torch.Tensor, grad: torch.Tensor, chol: torch.Tensor,
                   step: float, beta: float, seed: int, iteration: int, max_depth: int = 10, uturn: bool = True,
                   max_delta_h: float = 1000.0, max_depth_per_particle: Optional[torch.Tensor] = None,
-                  precision: int = MIXED, diagnostics: bool = True, work_hint: Optional[torch.Tensor] = None):
-        """One NUTS transition per particle; chol is one [D][D] factor of M^-1 or [P][D][D], one per particle."""
+                  precision: int = MIXED, diagnostics: bool = True, work_hint: Optional[torch.Tensor] = None,
+                  beta_device: Optional[torch.Tensor] = None):
+        """One NUTS transition per particle; chol is one [D][D] factor of M^-1 or [P][D][D], one per particle.
+        beta_device (a one-element device float64 tensor) supplies beta from device memory instead."""
         theta = _dev(theta, torch.float64, "theta")
         P, D = theta.shape
-        prm = NutsParams(step, beta, max_delta_h, max_depth, 1 if uturn else 0, seed, iteration,
-                         _chol_mode(chol, P, D), 0)
+        if beta_device is not None:
+            _dev(beta_device, torch.float64, "beta_device")
+        prm = NutsParams(step, 0.0 if beta_device is not None else beta, max_delta_h, max_depth, 1 if uturn else 0,
+                         seed, iteration, _chol_mode(chol, P, D), 0, _ptr(beta_device))
         dev = theta.device
         out = {}
         if diagnostics:
@@ -363,7 +374,7 @@ class Context:
         theta = _dev(theta, torch.float64, "theta")
         P, D = theta.shape
         prm = NutsParams(step, beta, max_delta_h, max_depth, 1 if uturn else 0, seed, iteration,
-                         _chol_mode(chol, P, D), 0)
+                         _chol_mode(chol, P, D), 0, None)
         best = C.c_int(0)
         times = (C.c_double * 4)()
         self._stream()
@@ -389,6 +400,53 @@ class Context:
                                                C.byref(dz))
         _check("smcgw_smc_reweight_resample", rc)
         return b.value, dz.value, ancestors
+
+    def ps_reweight_resample(self, theta_pool: torch.Tensor, logl_pool: torch.Tensor,
+                             grad_pool: Optional[torch.Tensor], betas: Sequence[float], logz: Sequence[float],
+                             alpha: float, seed: int, iteration: int, theta: torch.Tensor, logl: torch.Tensor,
+                             grad: Optional[torch.Tensor], ancestors: Optional[torch.Tensor] = None):
+        """Persistent-sampling step over a pool of T populations of N points: theta_pool [T*N][D], logl_pool [T*N]
+        (device), betas/logz of the T populations.  Draws N points into theta/logl/grad; returns
+        (beta_next, log Z(beta_next), ancestors).  Synchronises."""
+        theta_pool = _dev(theta_pool, torch.float64, "theta_pool")
+        _dev(logl_pool, torch.float64, "logl_pool")
+        theta = _dev(theta, torch.float64, "theta")
+        N, D = theta.shape
+        T = len(betas)
+        if len(logz) != T or logl_pool.numel() != T * N or theta_pool.shape != (T * N, D):
+            raise ValueError("pool shapes do not match T populations of the population's size")
+        b = np.ascontiguousarray(betas, dtype=np.float64)
+        z = np.ascontiguousarray(logz, dtype=np.float64)
+        if ancestors is None:
+            ancestors = torch.empty(N, dtype=torch.int32, device=theta.device)
+        bn = C.c_double()
+        lz = C.c_double()
+        self._stream()
+        _check("smcgw_ps_reweight_resample", lib().smcgw_ps_reweight_resample(
+            self._h, T, N, D, _ptr(theta_pool), _ptr(logl_pool), _ptr(grad_pool), b.ctypes.data_as(C.c_void_p),
+            z.ctypes.data_as(C.c_void_p), alpha, seed, iteration, _ptr(theta), _ptr(logl), _ptr(grad),
+            _ptr(ancestors), C.byref(bn), C.byref(lz)))
+        return bn.value, lz.value, ancestors
+
+    def smc_reweight_resample_async(self, theta: torch.Tensor, logl: torch.Tensor, grad: Optional[torch.Tensor],
+                                    beta_prev: float, alpha: float, seed: int, iteration: int, out: torch.Tensor,
+                                    ancestors: Optional[torch.Tensor] = None, carry: Optional[torch.Tensor] = None):
+        """As smc_reweight_resample without synchronising: out (device float64 [2]) receives beta_next and the
+        evidence increment when the queued work has run."""
+        theta = _dev(theta, torch.float64, "theta")
+        _dev(out, torch.float64, "out")
+        if out.numel() < 2:
+            raise ValueError("out needs two entries")
+        P, D = theta.shape
+        if ancestors is None:
+            ancestors = torch.empty(P, dtype=torch.int32, device=theta.device)
+        if carry is not None:
+            _dev(carry, torch.int32, "carry")
+        self._stream()
+        _check("smcgw_smc_reweight_resample_async", lib().smcgw_smc_reweight_resample_async(
+            self._h, P, D, beta_prev, alpha, seed, iteration, _ptr(theta), _ptr(logl), _ptr(grad), _ptr(carry),
+            _ptr(ancestors), _ptr(out)))
+        return ancestors
 
 
 class LogLikelihood(torch.autograd.Function):

@@ -48,5 +48,11 @@ def test_invalid_arguments_rejected_without_gpu():
     assert lib.smcgw_autotune_nuts(None, 1, 1, None, None, None, None, None, 1, 1, None, None) == -1
     assert lib.smcgw_nuts_step(None, 1, 1, None, None, None, None, None, None, None, 1, None, None, None, None) == -1
     assert lib.smcgw_set_option(None, 0, ctypes.c_int64(4)) == -1
-    assert lib.smcgw_local_metric(None, 1, 1, None, ctypes.c_double(1.0), None, None, None, None) == -1
+    assert lib.smcgw_local_metric(None, 1, 1, None, ctypes.c_double(1.0), None, None, None, None, None) == -1
+    assert lib.smcgw_smc_reweight_resample_async(None, 1, 1, ctypes.c_double(0.0), ctypes.c_double(0.5),
+                                                 ctypes.c_uint64(0), ctypes.c_uint64(0), None, None, None, None,
+                                                 None, None) == -1
     assert lib.smcgw_recycle(None, 1, 1, None, None, None, ctypes.c_uint64(0), None, None, None, None) == -1
+    assert lib.smcgw_ps_reweight_resample(None, 1, 1, 1, None, None, None, None, None, ctypes.c_double(0.5),
+                                          ctypes.c_uint64(0), ctypes.c_uint64(0), None, None, None, None, None,
+                                          None) == -1
