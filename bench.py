@@ -107,23 +107,43 @@ def build_event(smcgw, synth, spec=None):
     return synth.make_event(spec or synth.SPEC_8S, wf, zero_ll)
 
 
-def cpu_baseline(ev, synth, x_all, budget_s=12.0):
-    """Time the FP64 oracle on a bounded sample of the same workload."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(ev, synth, x_all, budget_s=12.0, single_budget_s=3.0):
+    """Time the FP64 oracle on a bounded sample of the same workload, on every host thread and on one."""
     from oracle import oracle as O
     t = O.gw_target(ev)
     threads = O.num_threads()
-    n = max(threads, 8)
-    done, elapsed = 0, 0.0
-    while elapsed < budget_s:
-        idx = np.arange(done, done + n) % x_all.shape[0]   # the particles again once all were used
-        t0 = time.perf_counter()
-        O.loglike_grad(t, x_all[idx])
-        elapsed += time.perf_counter() - t0
-        done += n
-        n = min(2 * n, 1024)
+
+    def timed(budget, n0, n_max):
+        n = n0
+        done, elapsed = 0, 0.0
+        while elapsed < budget:
+            idx = np.arange(done, done + n) % x_all.shape[0]   # the particles again once all were used
+            t0 = time.perf_counter()
+            O.loglike_grad(t, x_all[idx])
+            elapsed += time.perf_counter() - t0
+            done += n
+            n = min(2 * n, n_max)
+        return done, elapsed
+
+    done, elapsed = timed(budget_s, max(threads, 8), 1024)
+    O.set_num_threads(1)
+    done1, elapsed1 = timed(single_budget_s, 1, 64)
+    O.set_num_threads(threads)
     return {"value": done / elapsed, "unit": "evals/s", "cores": threads, "kind": "oracle",
             "sample": f"{done} particles of the same 3-detector 8033-bin event, logL + 11-component gradient "
-                      f"(forward-mode dual numbers, FP64), {elapsed:.1f} s on {threads} threads"}
+                      f"(forward-mode dual numbers, FP64), {elapsed:.1f} s on {threads} threads",
+            "single_core_value": done1 / elapsed1, "single_core_sample": f"{done1} particles in {elapsed1:.1f} s",
+            "cpu_model": cpu_model()}
 
 
 def run_batch(smcgw, synth, args):
@@ -465,6 +485,20 @@ def main():
             rbx[f"edges_{tag}"] = ne
             rbx[f"bins_{tag}"] = evr.n
             cr.close()
+            if spec is not None:   # the full grid of the long segment, for comparison
+                cf = smcgw.Context(0)
+                cf.add_event(evr)
+                xf = xr[:1024].contiguous()
+                lf = torch.empty(1024, dtype=torch.float64, device="cuda")
+                gf = torch.empty_like(xf)
+                cf.loglike_grad(xf, lf, gf, precision=prec)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                for _ in range(3):
+                    cf.loglike_grad(xf, lf, gf, precision=prec)
+                torch.cuda.synchronize()
+                extra[f"loglike_grad_{tag}_full_grid_evals_per_s"] = round(1024 * 3 / (time.perf_counter() - t1), 1)
+                cf.close()
         P_rb = args.particles or 2048
         bounds = synth.gw_prior_for(ev)
         for w_rb in (2, 4):   # the edge table fits one block: narrower slots, more of them per CU

@@ -640,6 +640,13 @@ double ess_of(const double* logl, int n, double db) {
 // ====================================================================== C ABI
 extern "C" {
 
+// Threads of the oracle's parallel loops (timing on a chosen number of cores).
+int orc_set_num_threads(int n) {
+    if (n < 1) return -1;
+    omp_set_num_threads(n);
+    return 0;
+}
+
 int orc_philox4x32_10(const uint32_t* ctr, const uint32_t* key, uint32_t* out) {
     philox4x32_10(ctr, key, out);
     return 0;

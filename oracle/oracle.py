@@ -362,5 +362,10 @@ def smc_run(target: Target, x0, alpha: float, step: float, max_depth: int, shrin
     return dict(rc=rc, logz=logz.value, n_iter=n, betas=betas[:n], dlogz=dz[:n], x=x)
 
 
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops."""
+    assert lib().orc_set_num_threads(C.c_int(n)) == 0
+
+
 def num_threads() -> int:
     return int(lib().orc_num_threads())
