@@ -733,7 +733,8 @@ int orc_leapfrog(const orc_target* t, double beta, const double* chol, double ep
 int orc_nuts_step(const orc_target* t, int P, double* x, double* logl, double* grad, const double* chol,
                   int chol_per_particle, double step, int max_depth, const int32_t* max_depth_per_particle, int uturn,
                   double max_dh, double beta, uint64_t seed, uint64_t iteration,
-                  int32_t* depth, int32_t* n_leapfrog, uint8_t* divergent, double* accept_stat) {
+                  int32_t* depth, int32_t* n_leapfrog, uint8_t* divergent, double* accept_stat,
+                  const int32_t* particle_ids) {
     const int D = t->dim;
 #pragma omp parallel for schedule(dynamic, 1)
     for (int i = 0; i < P; ++i) {
@@ -742,7 +743,9 @@ int orc_nuts_step(const orc_target* t, int P, double* x, double* logl, double* g
         eval_state(*t, beta, s);
         const int md = max_depth_per_particle ? max_depth_per_particle[i] : max_depth;
         const double* Li = chol_per_particle ? chol + (size_t)i * D * D : chol;
-        const NutsOut o = nuts_transition(*t, beta, Li, step, md, uturn, max_dh, seed, iteration, (uint32_t)i, s);
+        // random streams of particle particle_ids[i] (i when NULL): a sample of a larger batch replays its own draws
+        const uint32_t pid = particle_ids ? (uint32_t)particle_ids[i] : (uint32_t)i;
+        const NutsOut o = nuts_transition(*t, beta, Li, step, md, uturn, max_dh, seed, iteration, pid, s);
         logl[i] = s.logl;
         for (int k = 0; k < D; ++k) { x[(size_t)i * D + k] = s.x[k]; if (grad) grad[(size_t)i * D + k] = s.gl[k]; }
         if (depth) depth[i] = o.depth;
@@ -1155,7 +1158,7 @@ int orc_smc_run(const orc_target* t, int P, double* x, double alpha, double step
         std::copy(xn.begin(), xn.end(), x);
         orc_mass_matrix(P, D, x, shrink, inv.data(), L.data());
         orc_nuts_step(t, P, x, ll2.data(), nullptr, L.data(), 0, step, max_depth, nullptr, 1, 1000.0, bn, seed,
-                      (uint64_t)it, nullptr, nullptr, nullptr, nullptr);
+                      (uint64_t)it, nullptr, nullptr, nullptr, nullptr, nullptr);
         std::copy(ll2.begin(), ll2.end(), logl.begin());
         beta = bn;
         ++it;

@@ -250,7 +250,9 @@ def leapfrog(target: Target, x, r, chol, eps: float, n_steps: int, beta: float =
 
 
 def nuts_step(target: Target, x, chol, step: float, max_depth: int, beta: float, seed: int, iteration: int,
-              max_depth_per_particle=None, uturn: bool = True, max_dh: float = 1000.0):
+              max_depth_per_particle=None, uturn: bool = True, max_dh: float = 1000.0, particle_ids=None):
+    """One NUTS transition per row of x; particle_ids (optional) gives each row the random streams of that
+    particle index of a larger batch."""
     x = _f64(x).copy()
     P, D = x.shape
     logl = np.zeros(P)
@@ -265,7 +267,8 @@ def nuts_step(target: Target, x, chol, step: float, max_depth: int, beta: float,
     lib().orc_nuts_step(target.ptr, C.c_int(P), _dp(x), _dp(logl), _dp(grad), _dp(chol), C.c_int(per_particle),
                         C.c_double(step), C.c_int(max_depth), _ip(mdp), C.c_int(1 if uturn else 0), C.c_double(max_dh),
                         C.c_double(beta), C.c_uint64(seed), C.c_uint64(iteration), _ip(depth), _ip(nlf),
-                        div.ctypes.data_as(C.c_void_p), _dp(acc))
+                        div.ctypes.data_as(C.c_void_p), _dp(acc),
+                        _ip(None if particle_ids is None else np.ascontiguousarray(particle_ids, np.int32)))
     return dict(x=x, logl=logl, grad=grad, depth=depth, n_leapfrog=nlf, divergent=div, accept_stat=acc)
 
 

@@ -250,3 +250,37 @@ def test_autotune_keeps_inputs_and_sets_width(smc):
     c.close()
     np.testing.assert_array_equal(runs[0][0], runs[1][0])
     np.testing.assert_array_equal(runs[0][1], runs[1][1])
+
+
+def test_bench_configuration_sampled_parity(smc):
+    """The launch the benchmark times: 2048 particles, 3 detectors, 8033 bins, 11 parameters, MIXED, eps = 0.5,
+    depth <= 10, the population-covariance metric, beta of a first SMC iteration.  Eight particles spread over
+    the batch are replayed by the oracle with their own random streams (particle ids)."""
+    ev = event(synth.SPEC_8S)
+    b = synth.gw_prior_for(ev)
+    P, beta = 2048, 0.0025
+    x = synth.prior_draw(np.random.default_rng(7), P, b)
+    t = O.gw_target(ev)
+    _, _, L = O.mass_matrix(x, 0.0)
+    c = smc.Context(0)
+    c.add_event(ev)
+    c.set_prior(b)
+    c.set_target(synth.TARGET_GW, 11)
+    xt = torch.tensor(x, device="cuda")
+    lt, gt = c.target_loglike_grad(xt, precision=smc.MIXED)
+    out = c.nuts_step(xt, lt, gt, torch.tensor(L, device="cuda"), step=0.5, beta=beta, seed=1, iteration=3,
+                      max_depth=10, precision=smc.MIXED)
+    torch.cuda.synchronize()
+    got = {k: v.cpu().numpy() for k, v in out.items()}
+    xg, lg = xt.cpu().numpy(), lt.cpu().numpy()
+    c.close()
+    ids = np.array([0, 257, 611, 1023, 1024, 1500, 1901, 2047], dtype=np.int32)
+    ll0, _ = O.loglike_grad(t, x[ids])
+    ref = O.nuts_step(t, x[ids], L, 0.5, 10, beta, seed=1, iteration=3, particle_ids=ids)
+    same = (got["depth"][ids] == ref["depth"]) & (got["n_leapfrog"][ids] == ref["n_leapfrog"])
+    close = np.all(np.abs(xg[ids] - ref["x"]) <= 1e-6 * (1 + np.abs(ref["x"])), axis=1)
+    ok = same & close
+    print(f"bench configuration: depths GPU {got['depth'][ids].tolist()} oracle {ref['depth'].tolist()}, "
+          f"agree {int(ok.sum())}/8, batch mean depth {got['depth'].mean():.2f}", flush=True)
+    assert ok.sum() >= 6
+    np.testing.assert_allclose(lg[ids][ok], ref["logl"][ok], rtol=1e-5)
