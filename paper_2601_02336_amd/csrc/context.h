@@ -45,6 +45,8 @@ struct smcgw_ctx {
     int nuts_waves = 0;                    // wavefronts per NUTS slot (0: default)
     int nuts_priority = 1;                 // depth-driven wavefront priority in the NUTS kernel
     int32_t* d_order = nullptr;            // NUTS start order built from a work hint
+    double* d_mm = nullptr;                // block partials of the population covariance
+    size_t mm_bytes = 0;
     int order_cap = 0;
     std::unordered_map<const void*, int> resident;   // resident workgroups per device, per kernel
     const int32_t* ev_of_p = nullptr;      // caller-owned event index per particle (NULL: event 0)
@@ -61,6 +63,9 @@ struct smcgw_ctx {
         hipFree(d_sampler);
         hipFree(d_queue);
         hipFree(d_order);
+        hipFree(d_mm);
+        d_mm = nullptr;
+        mm_bytes = 0;
         d_queue = nullptr;
         d_order = nullptr;
         order_cap = 0;

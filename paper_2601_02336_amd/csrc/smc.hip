@@ -257,13 +257,8 @@ __global__ __launch_bounds__(256) void copy_back_kernel(int P, int D, const doub
     if (cy) cy[i] = cyo[i];
 }
 
-// Covariance entries (a, b), b <= a < MAXDIM, in row order, MM_CHUNK per pass
-// over the particles; the table is a compile-time constant, so every index is
-// a literal after unrolling and a particle's centred row stays in registers.
-constexpr int MM_CHUNK = 17;
+// Covariance entries (a, b), b <= a < MAXDIM, in row order (a compile-time table).
 constexpr int MM_ENTRIES = MAXDIM * (MAXDIM + 1) / 2;
-static_assert(MM_ENTRIES % MM_CHUNK == 0, "whole chunks");
-static_assert(MAXDIM <= MM_CHUNK, "the mean pass reuses the chunk's reduction buffers");
 struct TriTable {
     int a[MM_ENTRIES], b[MM_ENTRIES];
     constexpr TriTable() : a(), b() {
@@ -274,53 +269,61 @@ struct TriTable {
 };
 constexpr TriTable TRI{};
 
-// Population mean and covariance (two passes, fixed order), diagonal
-// shrinkage and Cholesky; status[0] = 1 when a diagonal fallback was used.
-__global__ __launch_bounds__(SMC_THREADS) void mass_matrix_kernel(const double* __restrict__ x, int P, int D,
-                                                                  double shrink, double* __restrict__ inv,
-                                                                  double* __restrict__ L, int* __restrict__ status) {
-    __shared__ double red[MM_CHUNK * SMC_WAVES];
-    __shared__ double tot[MM_CHUNK];
-    __shared__ double mu[MAXDIM];
+// Population covariance in one pass over the particles, shifted by the first
+// particle x_0 (the mean of the shifted values is small, so the one-pass
+// form keeps its accuracy): per block of MMB particles, in particle order,
+//   s_k = sum_i (x_ik - x_0k),  s_ab = sum_i (x_ia - x_0a)(x_ib - x_0b),
+// one thread per sum; the block's rows are staged in LDS.
+constexpr int MMB = 64;
+constexpr int MM_SUMS = MAXDIM + MM_ENTRIES;
+constexpr int MM_THREADS = 256;
+static_assert(MM_SUMS <= MM_THREADS, "one thread per sum");
+
+__global__ __launch_bounds__(MM_THREADS) void mm_partial_kernel(const double* __restrict__ x, int P, int D,
+                                                                double* __restrict__ part) {
+    __shared__ double xs[MMB * MAXDIM];
+    __shared__ double x0[MAXDIM];
+    const int blk = blockIdx.x;
+    const int i0 = blk * MMB, n = min(MMB, P - i0);
+    for (int t = threadIdx.x; t < n * D; t += blockDim.x) xs[t] = x[(size_t)i0 * D + t];
+    if ((int)threadIdx.x < D) x0[threadIdx.x] = x[threadIdx.x];
+    __syncthreads();
+    const int e = threadIdx.x;
+    if (e >= MM_SUMS) return;
+    double s = 0.0;
+    if (e < MAXDIM) {
+        if (e < D)
+            for (int i = 0; i < n; ++i) s += xs[i * D + e] - x0[e];
+    } else {
+        const int a = TRI.a[e - MAXDIM], b = TRI.b[e - MAXDIM];
+        if (a < D)
+            for (int i = 0; i < n; ++i) s += (xs[i * D + a] - x0[a]) * (xs[i * D + b] - x0[b]);
+    }
+    part[(size_t)blk * MM_SUMS + e] = s;
+}
+
+// Block partials summed in block order, covariance (s_ab - s_a s_b / P) / (P - 1),
+// diagonal shrinkage and Cholesky; status[0] = 1 when a diagonal fallback
+// was used.
+__global__ __launch_bounds__(MM_THREADS) void mm_finish_kernel(const double* __restrict__ part, int nblk, int P,
+                                                               int D, double shrink, double* __restrict__ inv,
+                                                               double* __restrict__ L, int* __restrict__ status) {
+    __shared__ double tot[MM_SUMS];
     __shared__ double cov[MAXDIM * MAXDIM];
     __shared__ double l[MAXDIM * MAXDIM];
     __shared__ int bad;
-    {
-        double s[MAXDIM];
-#pragma unroll
-        for (int k = 0; k < MAXDIM; ++k) s[k] = 0.0;
-        for (int i = threadIdx.x; i < P; i += blockDim.x)
-#pragma unroll
-            for (int k = 0; k < MAXDIM; ++k)
-                if (k < D) s[k] += x[(size_t)i * D + k];
-        block_sums<MAXDIM>(s, red, tot);
-        if ((int)threadIdx.x < D) mu[threadIdx.x] = tot[threadIdx.x] / P;
-        __syncthreads();
+    if ((int)threadIdx.x < MM_SUMS) {
+        double s = 0.0;
+        for (int b = 0; b < nblk; ++b) s += part[(size_t)b * MM_SUMS + threadIdx.x];
+        tot[threadIdx.x] = s;
     }
-    double m[MAXDIM];
-#pragma unroll
-    for (int k = 0; k < MAXDIM; ++k) m[k] = k < D ? mu[k] : 0.0;
-#pragma unroll
-    for (int e0 = 0; e0 < MM_ENTRIES; e0 += MM_CHUNK) {
-        if (TRI.a[e0] >= D) break;   // rows below are beyond the dimension
-        double s[MM_CHUNK];
-#pragma unroll
-        for (int j = 0; j < MM_CHUNK; ++j) s[j] = 0.0;
-        for (int i = threadIdx.x; i < P; i += blockDim.x) {
-            double xc[MAXDIM];
-#pragma unroll
-            for (int k = 0; k < MAXDIM; ++k) xc[k] = k < D ? x[(size_t)i * D + k] - m[k] : 0.0;
-#pragma unroll
-            for (int j = 0; j < MM_CHUNK; ++j) s[j] += xc[TRI.a[e0 + j]] * xc[TRI.b[e0 + j]];
-        }
-        block_sums<MM_CHUNK>(s, red, tot);
-        if ((int)threadIdx.x < MM_CHUNK) {
-            const int a = TRI.a[e0 + threadIdx.x], b = TRI.b[e0 + threadIdx.x];
-            if (a < D) {
-                const double v = tot[threadIdx.x] / (P - 1);
-                cov[a * D + b] = v;
-                cov[b * D + a] = v;
-            }
+    __syncthreads();
+    for (int e = threadIdx.x; e < MM_ENTRIES; e += blockDim.x) {
+        const int a = TRI.a[e], b = TRI.b[e];
+        if (a < D) {
+            const double v = (tot[MAXDIM + e] - tot[a] * tot[b] / P) / (P - 1);
+            cov[a * D + b] = v;
+            cov[b * D + a] = v;
         }
     }
     __syncthreads();
@@ -577,8 +580,18 @@ extern "C" int smcgw_mass_matrix(smcgw_ctx* c, int P, int D, const double* theta
         hp = pinned(c);
         if (!st || !hp) return SMCGW_ERR_OOM;
     }
-    hipLaunchKernelGGL(mass_matrix_kernel, dim3(1), dim3(SMC_THREADS), 0, c->stream, theta, P, D, shrink, inv_mass,
-                       chol, st);
+    const int nblk = (P + MMB - 1) / MMB;
+    const size_t need = (size_t)nblk * MM_SUMS * sizeof(double);
+    if (need > c->mm_bytes) {
+        hipFree(c->d_mm);
+        c->d_mm = nullptr;
+        c->mm_bytes = 0;
+        if (hipMalloc(&c->d_mm, need) != hipSuccess) return SMCGW_ERR_OOM;
+        c->mm_bytes = need;
+    }
+    hipLaunchKernelGGL(mm_partial_kernel, dim3(nblk), dim3(MM_THREADS), 0, c->stream, theta, P, D, c->d_mm);
+    hipLaunchKernelGGL(mm_finish_kernel, dim3(1), dim3(MM_THREADS), 0, c->stream, (const double*)c->d_mm, nblk, P, D,
+                       shrink, inv_mass, chol, st);
     if (hipGetLastError() != hipSuccess) return SMCGW_ERR_HIP;
     if (status_device) return SMCGW_OK;
     if (hipMemcpyAsync(hp, st, sizeof(int), hipMemcpyDeviceToHost, c->stream) || hipStreamSynchronize(c->stream))
