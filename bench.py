@@ -4,10 +4,12 @@ Workload: one synthetic three-detector event, 8 s at 20-1024 Hz (df = 1/8 Hz,
 8033 bins), 11 source parameters, seeded injection at network SNR 20 in
 Gaussian noise, particles drawn from the prior.
 
-Default (--mode smc): a step is one SMC-NUTS iteration of 2048 particles
-(reweight, adaptive temperature, resampling, population mass matrix and one
-NUTS transition per particle with the likelihood and adjoint gradient at every
-leapfrog step); the value is leapfrog evaluations per second.  --mode loglike:
+Default (--mode smc): a step is one SMC-NUTS iteration (reweight, adaptive
+temperature, resampling, population mass matrix and one NUTS transition per
+particle with the likelihood and adjoint gradient at every leapfrog step) of
+each of three independent runs of 2048 particles (--chains), so that the value
+does not rest on the tree depths of a single run; the value is leapfrog
+evaluations per second.  --mode loglike:
 a step is one batched logL + gradient evaluation of 4096 particles.  Prints
 one JSON line.
 
@@ -68,7 +70,8 @@ def kernel_source_hash():
 def default_smc_workload(args, P):
     """The counters were taken on the default SMC bench run only."""
     return (P == 2048 and args.steps == 8 and args.warmup == 2 and args.alpha == 0.95 and args.step == 0.5
-            and args.max_depth == 10 and args.seed == 1 and not args.no_hint and args.priority == 1)
+            and args.max_depth == 10 and args.seed == 1 and not args.no_hint and args.priority == 1
+            and args.chains == 3)
 
 
 def measured_traffic(kernel):
@@ -227,59 +230,75 @@ def smc_setup(smcgw, synth, ev, P, seed=7):
     return ctx, x_np, torch.tensor(x_np, device="cuda")
 
 
-def run_smc_steps(smcgw, ctx, theta, precision, args, n_warm, n_steps, time_kernels, metric="population"):
-    """SMC iterations from prior draws; returns (evals, seconds, nuts kernel ms, launches, betas, depth
-    histograms, local-metric kernel ms and launches)."""
+class _Chain:
+    """One SMC run: its context, population and per-iteration state."""
+
+    def __init__(self, ctx, theta, seed, precision, n_iter):
+        import torch
+        self.ctx, self.theta, self.seed = ctx, theta, seed
+        self.logl, self.grad = ctx.target_loglike_grad(theta, precision=precision)
+        self.beta, self.it, self.hint = 0.0, 0, None
+        self.mm_status = torch.zeros(1, dtype=torch.int32, device="cuda")
+        self.bz = torch.zeros((n_iter, 2), dtype=torch.float64, device="cuda")
+        self.bz_host = torch.zeros((n_iter, 2), dtype=torch.float64, pin_memory=True)
+
+
+def run_smc_steps(smcgw, chains, precision, args, n_warm, n_steps, time_kernels, metric="population"):
+    """SMC iterations from prior draws, one iteration of every chain (ctx, theta, seed) per step; returns (evals,
+    seconds, nuts kernel ms, launches, betas and depth histograms of the first chain, local-metric kernel ms and
+    launches), kernel times summed over the chains' contexts."""
     import torch
-    logl, grad = ctx.target_loglike_grad(theta, precision=precision)
-    beta, it, hint = 0.0, 0, None
+    runs = [_Chain(ctx, theta, seed, precision, n_warm + n_steps) for ctx, theta, seed in chains]
     stats = []
-    mm_status = torch.zeros(1, dtype=torch.int32, device="cuda")
 
-    bz = torch.zeros((n_warm + n_steps, 2), dtype=torch.float64, device="cuda")
-    bz_host = torch.zeros((n_warm + n_steps, 2), dtype=torch.float64, pin_memory=True)
-
-    def one_step():
+    def iterate(c):
         # the iteration is queued as a whole: beta_t goes from the reweighting to the metric and the NUTS
         # transition through device memory, and reaches the host through an event while the transition runs
-        nonlocal beta, it, hint
-        ctx.smc_reweight_resample_async(theta, logl, grad, beta, args.alpha, args.seed, it, bz[it], carry=hint)
-        bz_host[it].copy_(bz[it], non_blocking=True)
+        it = c.it
+        c.ctx.smc_reweight_resample_async(c.theta, c.logl, c.grad, c.beta, args.alpha, c.seed, it, c.bz[it],
+                                          carry=c.hint)
+        c.bz_host[it].copy_(c.bz[it], non_blocking=True)
         ready = torch.cuda.Event()
         ready.record()
-        beta_dev = bz[it, 0:1]
-        _, L, _ = ctx.mass_matrix(theta, 0.0, status=mm_status)
+        beta_dev = c.bz[it, 0:1]
+        _, L, _ = c.ctx.mass_matrix(c.theta, 0.0, status=c.mm_status)
         if metric == "local":
-            L, _, _ = ctx.local_metric(theta, 0.0, fallback=L, status=False, beta_device=beta_dev)
-        out = ctx.nuts_step(theta, logl, grad, L, step=args.step, beta=0.0, seed=args.seed, iteration=it,
-                            max_depth=args.max_depth, precision=precision, work_hint=hint, beta_device=beta_dev)
-        hint = None if args.no_hint else out["n_leapfrog"]
+            L, _, _ = c.ctx.local_metric(c.theta, 0.0, fallback=L, status=False, beta_device=beta_dev)
+        out = c.ctx.nuts_step(c.theta, c.logl, c.grad, L, step=args.step, beta=0.0, seed=c.seed, iteration=it,
+                              max_depth=args.max_depth, precision=precision, work_hint=c.hint, beta_device=beta_dev)
+        c.hint = None if args.no_hint else out["n_leapfrog"]
         ready.synchronize()
-        beta = float(bz_host[it, 0])
-        it += 1
+        c.beta = float(c.bz_host[it, 0])
+        c.it += 1
         return out
 
     nlf = torch.zeros((), dtype=torch.int64, device="cuda")
     for _ in range(n_warm):
-        out = one_step()
-        nlf += out["n_leapfrog"].sum()   # warm up the same device work as the timed steps
+        for c in runs:
+            nlf += iterate(c)["n_leapfrog"].sum()   # warm up the same device work as the timed steps
     nlf.zero_()
     torch.cuda.synchronize()
-    ctx.timing_read(smcgw.KERNEL_NUTS)
-    ctx.timing_read(smcgw.KERNEL_METRIC)
-    if time_kernels:
-        ctx.timing(smcgw.KERNEL_NUTS, smcgw.KERNEL_METRIC)
+    for c in runs:
+        c.ctx.timing_read(smcgw.KERNEL_NUTS)
+        c.ctx.timing_read(smcgw.KERNEL_METRIC)
+        if time_kernels:
+            c.ctx.timing(smcgw.KERNEL_NUTS, smcgw.KERNEL_METRIC)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(n_steps):
-        out = one_step()
-        nlf += out["n_leapfrog"].sum()
-        stats.append((beta, out["depth"]))
+        for k, c in enumerate(runs):
+            out = iterate(c)
+            nlf += out["n_leapfrog"].sum()
+            if k == 0:
+                stats.append((c.beta, out["depth"]))
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    ctx.timing()
-    k_ms, k_n = ctx.timing_read(smcgw.KERNEL_NUTS)
-    m_ms, m_n = ctx.timing_read(smcgw.KERNEL_METRIC)
+    k_ms = k_n = m_ms = m_n = 0
+    for c in runs:
+        c.ctx.timing()
+        a, b = c.ctx.timing_read(smcgw.KERNEL_NUTS)
+        e, f = c.ctx.timing_read(smcgw.KERNEL_METRIC)
+        k_ms, k_n, m_ms, m_n = k_ms + a, k_n + b, m_ms + e, m_n + f
     depth_hist = [np.bincount(d.cpu().numpy(), minlength=args.max_depth + 1).tolist() for _, d in stats]
     return int(nlf.item()), dt, k_ms, k_n, [b for b, _ in stats], depth_hist, m_ms, m_n
 
@@ -297,6 +316,8 @@ def main():
     ap.add_argument("--step", type=float, default=0.5)
     ap.add_argument("--max-depth", type=int, default=10)
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--chains", type=int, default=3,
+                    help="independent SMC runs per step (mode smc): one iteration of each per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the side measurements")
     ap.add_argument("--no-hint", action="store_true", help="start particles in index order (no work hint)")
@@ -322,11 +343,18 @@ def main():
 
     if args.mode == "smc":
         P = args.particles or 2048
-        ctx, x_np, x = smc_setup(smcgw, synth, ev, P)
-        ctx.set_option(smcgw.OPT_NUTS_PRIORITY, args.priority)
-        ctx.set_option(smcgw.OPT_NUTS_WAVES, args.waves)
-        evals, dt, k_ms, k_n, betas, hist, _, _ = run_smc_steps(smcgw, ctx, x, prec, args, args.warmup, args.steps,
+        chains = []
+        for c in range(args.chains):   # independent runs: prior draws and random streams of their own
+            cctx, cx_np, cx = smc_setup(smcgw, synth, ev, P, seed=7 + c)
+            cctx.set_option(smcgw.OPT_NUTS_PRIORITY, args.priority)
+            cctx.set_option(smcgw.OPT_NUTS_WAVES, args.waves)
+            chains.append((cctx, cx, args.seed + c))
+            if c == 0:
+                ctx, x_np = cctx, cx_np
+        evals, dt, k_ms, k_n, betas, hist, _, _ = run_smc_steps(smcgw, chains, prec, args, args.warmup, args.steps,
                                                                 True)
+        for cctx, _, _ in chains[1:]:
+            cctx.close()
         value = evals / dt
         kernel_s = k_ms / 1e3
         achieved = ops * ev.n * evals / kernel_s / 1e12
@@ -344,13 +372,15 @@ def main():
         workload = (f"SMC-NUTS iteration (reweight + adaptive beta + resample, population mass matrix, one NUTS "
                     f"transition per particle): 3-detector 8 s event, 20-1024 Hz, df=1/8 Hz (8033 bins), 11 params, "
                     f"{P} particles from the prior, alpha={args.alpha}, eps={args.step}, depth<={args.max_depth}, "
-                    f"iterations {args.warmup + 1}-{args.warmup + args.steps} of the run")
+                    f"iterations {args.warmup + 1}-{args.warmup + args.steps}; a step runs one iteration of each of "
+                    f"{args.chains} independent runs (prior draws and random streams of their own), so the value "
+                    f"does not rest on one run's tree depths")
         if not args.no_extra:
             # the plain-FP64 sampler on the same iterations, and the batched-likelihood kernel rates
             ctx2, _, x2 = smc_setup(smcgw, synth, ev, P)
             ctx2.set_option(smcgw.OPT_NUTS_PRIORITY, args.priority)
             ctx2.set_option(smcgw.OPT_NUTS_WAVES, args.waves)
-            e2, d2, _, _, _, _, _, _ = run_smc_steps(smcgw, ctx2, x2,
+            e2, d2, _, _, _, _, _, _ = run_smc_steps(smcgw, [(ctx2, x2, args.seed)],
                                                      smcgw.PLAIN_FP64 if prec == smcgw.MIXED else smcgw.MIXED,
                                                      args, args.warmup, max(2, args.steps // 2), False)
             extra["other_precision_in_sampler_evals_per_s"] = round(e2 / d2, 1)
@@ -360,8 +390,8 @@ def main():
             ctx3, _, x3 = smc_setup(smcgw, synth, ev, P)
             ctx3.set_option(smcgw.OPT_NUTS_PRIORITY, args.priority)
             ctx3.set_option(smcgw.OPT_NUTS_WAVES, args.waves)
-            e3, d3, k3, n3, b3, _, m3, mn3 = run_smc_steps(smcgw, ctx3, x3, prec, args, args.warmup, args.steps,
-                                                           True, metric="local")
+            e3, d3, k3, n3, b3, _, m3, mn3 = run_smc_steps(smcgw, [(ctx3, x3, args.seed)], prec, args, args.warmup,
+                                                           args.steps, True, metric="local")
             # sample recycling over a pool of 30 iterations of this population size (post-processing)
             pool = torch.randn(30, P, dtype=torch.float64, device="cuda") - 50.0
             bts = [min(1.0, 0.001 * 1.3 ** t) for t in range(29)] + [1.0]
@@ -508,7 +538,8 @@ def main():
             cr.set_target(synth.TARGET_GW, 11)
             cr.set_option(smcgw.OPT_NUTS_WAVES, w_rb)
             xr = torch.tensor(synth.prior_draw(np.random.default_rng(7), P_rb, bounds), device="cuda")
-            e4, d4, k4, n4, _, _, _, _ = run_smc_steps(smcgw, cr, xr, prec, args, args.warmup, args.steps, True)
+            e4, d4, k4, n4, _, _, _, _ = run_smc_steps(smcgw, [(cr, xr, args.seed)], prec, args, args.warmup,
+                                                       args.steps, True)
             rbx[f"smc_w{w_rb}"] = {"evals_per_s": round(e4 / d4, 1), "ms_per_step": round(1e3 * d4 / args.steps, 4),
                                    "nuts_kernel_ms": round(k4 / max(n4, 1), 3), "leapfrog_per_step": e4 // args.steps}
             cr.close()
