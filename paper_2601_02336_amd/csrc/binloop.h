@@ -50,10 +50,6 @@ __device__ __forceinline__ BinCoef load_coef(const double* cb) {
     return k;
 }
 
-// Table pointers in the global address space (plain global loads, not flat).
-typedef const __attribute__((address_space(1))) double GDouble;
-typedef const __attribute__((address_space(1))) unsigned long long GU64;
-
 // Per-lane inputs of one bin: f, f^-1/3, ln f and the detectors' whitened data.
 template <int NDET, class U>
 struct BinIn {
@@ -61,54 +57,94 @@ struct BinIn {
     U u[NDET];
 };
 
-__device__ __forceinline__ void load_u(float2& v, GU64* u, size_t i) { v = __builtin_bit_cast(float2, u[i]); }
-__device__ __forceinline__ void load_u(double2& v, GU64* u, size_t i) {
-    v.x = __builtin_bit_cast(double, u[2 * i]);
-    v.y = __builtin_bit_cast(double, u[2 * i + 1]);
+// The bin tables as raw buffer resources.  A chunk's loads then take the
+// chunk's wave-uniform byte offset in a scalar register and a loop-invariant
+// per-lane byte offset, so they cost no vector instructions for addresses.
+// Resource word 3 of a raw (stride-0) buffer on this GPU family: 32-bit data
+// format, no swizzle.
+constexpr int BUF_RSRC_WORD3 = 0x00020000;
+
+struct TableView {
+    __amdgpu_buffer_rsrc_t fwl, u;
+    int npad;
+};
+
+// The pointer and size are made wave-uniform first: a resource must sit in
+// scalar registers, and a descriptor read from LDS is not known to be uniform.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const void* p, size_t bytes) {
+    const unsigned long long a = (unsigned long long)p;
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)a);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(a >> 32));
+    const int n = __builtin_amdgcn_readfirstlane((int)min(bytes, (size_t)0x7fffffff));
+    void* q = (void*)(((unsigned long long)hi << 32) | lo);
+    return __builtin_amdgcn_make_buffer_rsrc(q, (short)0, n, BUF_RSRC_WORD3);
 }
 
-template <int NDET, class U>
-__device__ __forceinline__ void load_bin(BinIn<NDET, U>& x, GDouble* fwl, GU64* u, int npad, int j) {
-    x.f = fwl[(size_t)ROW_F * npad + j];
-    x.w = fwl[(size_t)ROW_W * npad + j];
-    x.l = fwl[(size_t)ROW_LN * npad + j];
+__device__ __forceinline__ double buf_f64(__amdgpu_buffer_rsrc_t r, unsigned lane_bytes, int uniform_bytes) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, lane_bytes, uniform_bytes, 0));
+}
+
+// One chunk of 64 bins starting at bin `base` (wave-uniform).
+template <int NDET>
+__device__ __forceinline__ void load_chunk(BinIn<NDET, float2>& x, const TableView& t, int base, unsigned lane) {
+    const int np8 = t.npad * 8;
+    x.f = buf_f64(t.fwl, lane * 8u, ROW_F * np8 + base * 8);
+    x.w = buf_f64(t.fwl, lane * 8u, ROW_W * np8 + base * 8);
+    x.l = buf_f64(t.fwl, lane * 8u, ROW_LN * np8 + base * 8);
 #pragma unroll
-    for (int d = 0; d < NDET; ++d) load_u(x.u[d], u, (size_t)d * npad + j);
+    for (int d = 0; d < NDET; ++d)
+        x.u[d] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(t.u, lane * 8u, d * np8 + base * 8, 0));
+}
+
+template <int NDET>
+__device__ __forceinline__ void load_chunk(BinIn<NDET, double2>& x, const TableView& t, int base, unsigned lane) {
+    const int np8 = t.npad * 8;
+    x.f = buf_f64(t.fwl, lane * 8u, ROW_F * np8 + base * 8);
+    x.w = buf_f64(t.fwl, lane * 8u, ROW_W * np8 + base * 8);
+    x.l = buf_f64(t.fwl, lane * 8u, ROW_LN * np8 + base * 8);
+#pragma unroll
+    for (int d = 0; d < NDET; ++d)
+        x.u[d] = __builtin_bit_cast(double2,
+                                    __builtin_amdgcn_raw_buffer_load_b128(t.u, lane * 16u, 2 * (d * np8 + base * 8), 0));
 }
 
 // A wavefront visits the blocks blk0, blk0 + blk_step, ... of the padded
 // table; each block is BIN_KB chunks of 64 bins (one bin per lane of a
 // chunk).  The chunks run through two register buffers in turn (U chunks
 // each): while one buffer is computed the other one's table entries are in
-// flight, with no register copies between them.  U = 2 gives each lane two
-// independent bins per step (more instruction-level parallelism, more
-// registers).  Partial sums are accumulated in chunk order, so the result does
-// not depend on U.
+// flight.  Every prefetch is unconditional (the one past the last chunk
+// re-reads the last chunk), so the buffers need no register copies.  The first
+// bin of a block starts the per-lane partial sums and the block ends with
+// their flush.  U = 2 gives each lane two independent bins per step (more
+// instruction-level parallelism, more registers).  Partial sums are
+// accumulated in chunk order, so the result does not depend on U.
 template <int U, class In, class Acc>
-__device__ __forceinline__ void bin_loop(Acc& A, const BinCoef& k, GDouble* fwl, GU64* u, int npad, int blk0,
-                                         int blk_step, int nblk) {
+__device__ __forceinline__ void bin_loop(Acc& A, const BinCoef& k, const TableView& t, int blk0, int blk_step,
+                                         int nblk) {
     static_assert(BIN_KB % (2 * U) == 0, "a block holds a whole number of buffer pairs");
-    const int lane = threadIdx.x & 63;
-    const int nc = blk0 < nblk ? ((nblk - blk0 + blk_step - 1) / blk_step) * BIN_KB : 0;   // this wave's chunks
-    auto bin_of = [&](int c) { return (blk0 + (c / BIN_KB) * blk_step) * TABLE_PAD + 64 * (c % BIN_KB) + lane; };
+    constexpr int PAIRS = BIN_KB / (2 * U);
+    const unsigned lane = threadIdx.x & 63;
+    const int nb = blk0 < nblk ? (nblk - blk0 + blk_step - 1) / blk_step : 0;   // this wave's blocks
+    if (nb == 0) return;
+    const int last = nb * BIN_KB - 1;                                          // this wave's last chunk
+    auto base_of = [&](int c) { return (blk0 + (c / BIN_KB) * blk_step) * TABLE_PAD + 64 * (c % BIN_KB); };
     In a[U], b[U];
-    if (nc > 0) {
 #pragma unroll
-        for (int h = 0; h < U; ++h) load_bin(a[h], fwl, u, npad, bin_of(h));
-    }
-    for (int c = 0; c < nc; c += 2 * U) {
+    for (int h = 0; h < U; ++h) load_chunk(a[h], t, base_of(h), lane);
+    for (int blk = 0; blk < nb; ++blk) {
 #pragma unroll
-        for (int h = 0; h < U; ++h) load_bin(b[h], fwl, u, npad, bin_of(c + U + h));
+        for (int pr = 0; pr < PAIRS; ++pr) {
+            const int c = blk * BIN_KB + 2 * U * pr;
 #pragma unroll
-        for (int h = 0; h < U; ++h) A.bin(k, a[h]);
-        if ((c + U) % BIN_KB == 0) A.flush();
-        if (c + 2 * U < nc) {
+            for (int h = 0; h < U; ++h) load_chunk(b[h], t, base_of(c + U + h), lane);
 #pragma unroll
-            for (int h = 0; h < U; ++h) load_bin(a[h], fwl, u, npad, bin_of(c + 2 * U + h));
+            for (int h = 0; h < U; ++h) A.bin(k, a[h], pr == 0 && h == 0);
+#pragma unroll
+            for (int h = 0; h < U; ++h) load_chunk(a[h], t, base_of(min(c + 2 * U + h, last)), lane);
+#pragma unroll
+            for (int h = 0; h < U; ++h) A.bin(k, b[h], false);
         }
-#pragma unroll
-        for (int h = 0; h < U; ++h) A.bin(k, b[h]);
-        if ((c + 2 * U) % BIN_KB == 0) A.flush();
+        A.flush();
     }
 }
 
@@ -120,7 +156,7 @@ struct MixedAcc {
     double Zr[NDET], Zi[NDET], T[NDET], G[NCOEF];
     float zr[NDET], zi[NDET], tq[NDET];
 
-    __device__ __forceinline__ void bin(const BinCoef& k, const BinIn<NDET, float2>& x) {
+    __device__ __forceinline__ void bin(const BinCoef& k, const BinIn<NDET, float2>& x, bool first) {
         double B[NBASIS];
         basis_rows(x.f, x.w, x.l, B);
         double ph = k.c[0];
@@ -136,11 +172,11 @@ struct MixedAcc {
             sincos_rev_hw(xr, sn, cs);
             const float sr = fmaf(x.u[d].x, cs, x.u[d].y * sn);    // u e^{-2 pi i x}
             const float si = fmaf(x.u[d].y, cs, -x.u[d].x * sn);
-            zr[d] += sr;
-            zi[d] += si;
+            zr[d] = first ? sr : zr[d] + sr;
+            zi[d] = first ? si : zi[d] + si;
             const float q = fmaf(pr[d], si, pim[d] * sr);
             psib = (d == 0) ? q : psib + q;
-            tq[d] = fmaf(q, ff, tq[d]);
+            tq[d] = first ? q * ff : fmaf(q, ff, tq[d]);
         }
         const double pb = (double)psib;
         G[0] += pb;
@@ -148,11 +184,12 @@ struct MixedAcc {
         for (int b = 0; b < NBASIS; ++b) G[1 + b] = fma(pb, B[b], G[1 + b]);
     }
 
+    // Block end: the block's FP32 partials into the FP64 sums (the next block's
+    // first bin restarts them).
     __device__ __forceinline__ void flush() {
 #pragma unroll
         for (int d = 0; d < NDET; ++d) {
             Zr[d] += zr[d]; Zi[d] += zi[d]; T[d] += tq[d];
-            zr[d] = 0.f; zi[d] = 0.f; tq[d] = 0.f;
         }
     }
 };
@@ -160,24 +197,25 @@ struct MixedAcc {
 template <int NDET, int U = 1>
 __device__ __forceinline__ void bins_mixed_wave(const DevEvent* __restrict__ ev, const BinCoef& k, int blk0,
                                                 int blk_step, double mom[MOM_SIZE]) {
-    const int npad = ev->n_pad;
+    const int npad = __builtin_amdgcn_readfirstlane(ev->n_pad);
     MixedAcc<NDET> A;
 #pragma unroll
     for (int d = 0; d < NDET; ++d) {
         A.pr[d] = (float)k.pr[d]; A.pim[d] = (float)k.pi[d];
-        A.Zr[d] = 0.0; A.Zi[d] = 0.0; A.T[d] = 0.0; A.zr[d] = 0.f; A.zi[d] = 0.f; A.tq[d] = 0.f;
+        A.Zr[d] = 0.0; A.Zi[d] = 0.0; A.T[d] = 0.0;
     }
 #pragma unroll
     for (int b = 0; b < NCOEF; ++b) A.G[b] = 0.0;
-    bin_loop<U, BinIn<NDET, float2>>(A, k, (GDouble*)ev->fwl, (GU64*)ev->u32, npad, blk0, blk_step,
-                                     npad / TABLE_PAD);
+    const TableView t{raw_rsrc(ev->fwl, (size_t)NROWS * npad * sizeof(double)),
+                      raw_rsrc(ev->u32, (size_t)NDET * npad * sizeof(float2)), npad};
+    bin_loop<U, BinIn<NDET, float2>>(A, k, t, blk0, blk_step, npad / TABLE_PAD);
 #pragma unroll
     for (int i = 0; i < MOM_SIZE; ++i) mom[i] = 0.0;
 #pragma unroll
     for (int d = 0; d < NDET; ++d) {
-        mom[MOM_ZR + d] = wave_total(A.Zr[d] + A.zr[d]);
-        mom[MOM_ZI + d] = wave_total(A.Zi[d] + A.zi[d]);
-        mom[MOM_T + d] = wave_total(A.T[d] + A.tq[d]);
+        mom[MOM_ZR + d] = wave_total(A.Zr[d]);
+        mom[MOM_ZI + d] = wave_total(A.Zi[d]);
+        mom[MOM_T + d] = wave_total(A.T[d]);
     }
 #pragma unroll
     for (int b = 0; b < NCOEF; ++b) mom[MOM_G + b] = wave_total(A.G[b]);
@@ -188,7 +226,7 @@ template <int NDET>
 struct Fp64Acc {
     double Zr[NDET], Zi[NDET], T[NDET], G[NCOEF];
 
-    __device__ __forceinline__ void bin(const BinCoef& k, const BinIn<NDET, double2>& x) {
+    __device__ __forceinline__ void bin(const BinCoef& k, const BinIn<NDET, double2>& x, bool) {
         double B[NBASIS];
         basis_rows(x.f, x.w, x.l, B);
         double ph = k.c[0];
@@ -220,14 +258,15 @@ struct Fp64Acc {
 template <int NDET, int U = 1>
 __device__ __forceinline__ void bins_fp64_wave(const DevEvent* __restrict__ ev, const BinCoef& k, int blk0,
                                                int blk_step, double mom[MOM_SIZE]) {
-    const int npad = ev->n_pad;
+    const int npad = __builtin_amdgcn_readfirstlane(ev->n_pad);
     Fp64Acc<NDET> A;
 #pragma unroll
     for (int d = 0; d < NDET; ++d) { A.Zr[d] = 0.0; A.Zi[d] = 0.0; A.T[d] = 0.0; }
 #pragma unroll
     for (int b = 0; b < NCOEF; ++b) A.G[b] = 0.0;
-    bin_loop<U, BinIn<NDET, double2>>(A, k, (GDouble*)ev->fwl, (GU64*)ev->u64, npad, blk0, blk_step,
-                                      npad / TABLE_PAD);
+    const TableView t{raw_rsrc(ev->fwl, (size_t)NROWS * npad * sizeof(double)),
+                      raw_rsrc(ev->u64, (size_t)NDET * npad * sizeof(double2)), npad};
+    bin_loop<U, BinIn<NDET, double2>>(A, k, t, blk0, blk_step, npad / TABLE_PAD);
 #pragma unroll
     for (int i = 0; i < MOM_SIZE; ++i) mom[i] = 0.0;
 #pragma unroll
