@@ -12,7 +12,6 @@
 
 namespace smcgw {
 
-constexpr int BIN_KB = TABLE_PAD / 64;   // bins per lane per block (FP32 partials flushed per block)
 
 // Wave-uniform per-particle values the bin loop needs (from the coefficient block).
 struct BinCoef {
@@ -84,65 +83,89 @@ __device__ __forceinline__ double buf_f64(__amdgpu_buffer_rsrc_t r, unsigned lan
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, lane_bytes, uniform_bytes, 0));
 }
 
-// One chunk of 64 bins starting at bin `base` (wave-uniform).
+// A chunk is 128 consecutive bins; lane l takes bins 2l and 2l + 1, so every
+// row of a chunk is read with one 16-byte load per lane.  Wider loads move
+// twice the bytes per memory instruction: the bin loop is bound by the memory
+// instructions in flight (one wavefront alone) or by the request rate of the
+// cache hierarchy (a full device), not by the bytes themselves.
+constexpr int CHUNK_BINS = 128;
+constexpr int BLK_CHUNKS = TABLE_PAD / CHUNK_BINS;   // chunks per block
+
+template <int NDET, class U>
+struct BinPair {
+    BinIn<NDET, U> b[2];
+};
+
+__device__ __forceinline__ double2 buf_f64x2(__amdgpu_buffer_rsrc_t r, unsigned lane_bytes, int uniform_bytes) {
+    return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, lane_bytes, uniform_bytes, 0));
+}
+
+// One chunk starting at bin `base` (wave-uniform).
 template <int NDET>
-__device__ __forceinline__ void load_chunk(BinIn<NDET, float2>& x, const TableView& t, int base, unsigned lane) {
+__device__ __forceinline__ void load_chunk(BinPair<NDET, float2>& x, const TableView& t, int base, unsigned lane) {
     const int np8 = t.npad * 8;
-    x.f = buf_f64(t.fwl, lane * 8u, ROW_F * np8 + base * 8);
-    x.w = buf_f64(t.fwl, lane * 8u, ROW_W * np8 + base * 8);
-    x.l = buf_f64(t.fwl, lane * 8u, ROW_LN * np8 + base * 8);
+    const double2 f = buf_f64x2(t.fwl, lane * 16u, ROW_F * np8 + base * 8);
+    const double2 w = buf_f64x2(t.fwl, lane * 16u, ROW_W * np8 + base * 8);
+    const double2 l = buf_f64x2(t.fwl, lane * 16u, ROW_LN * np8 + base * 8);
+    x.b[0].f = f.x; x.b[1].f = f.y;
+    x.b[0].w = w.x; x.b[1].w = w.y;
+    x.b[0].l = l.x; x.b[1].l = l.y;
 #pragma unroll
-    for (int d = 0; d < NDET; ++d)
-        x.u[d] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(t.u, lane * 8u, d * np8 + base * 8, 0));
+    for (int d = 0; d < NDET; ++d) {
+        const float4 u = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(t.u, lane * 16u,
+                                                                                          d * np8 + base * 8, 0));
+        x.b[0].u[d] = make_float2(u.x, u.y);
+        x.b[1].u[d] = make_float2(u.z, u.w);
+    }
 }
 
 template <int NDET>
-__device__ __forceinline__ void load_chunk(BinIn<NDET, double2>& x, const TableView& t, int base, unsigned lane) {
+__device__ __forceinline__ void load_chunk(BinPair<NDET, double2>& x, const TableView& t, int base, unsigned lane) {
     const int np8 = t.npad * 8;
-    x.f = buf_f64(t.fwl, lane * 8u, ROW_F * np8 + base * 8);
-    x.w = buf_f64(t.fwl, lane * 8u, ROW_W * np8 + base * 8);
-    x.l = buf_f64(t.fwl, lane * 8u, ROW_LN * np8 + base * 8);
+    const double2 f = buf_f64x2(t.fwl, lane * 16u, ROW_F * np8 + base * 8);
+    const double2 w = buf_f64x2(t.fwl, lane * 16u, ROW_W * np8 + base * 8);
+    const double2 l = buf_f64x2(t.fwl, lane * 16u, ROW_LN * np8 + base * 8);
+    x.b[0].f = f.x; x.b[1].f = f.y;
+    x.b[0].w = w.x; x.b[1].w = w.y;
+    x.b[0].l = l.x; x.b[1].l = l.y;
 #pragma unroll
-    for (int d = 0; d < NDET; ++d)
-        x.u[d] = __builtin_bit_cast(double2,
-                                    __builtin_amdgcn_raw_buffer_load_b128(t.u, lane * 16u, 2 * (d * np8 + base * 8), 0));
+    for (int d = 0; d < NDET; ++d) {
+        x.b[0].u[d] = buf_f64x2(t.u, lane * 32u, 2 * (d * np8 + base * 8));
+        x.b[1].u[d] = buf_f64x2(t.u, lane * 32u + 16u, 2 * (d * np8 + base * 8));
+    }
 }
 
 // A wavefront visits the blocks blk0, blk0 + blk_step, ... of the padded
-// table; each block is BIN_KB chunks of 64 bins (one bin per lane of a
-// chunk).  The chunks run through two register buffers in turn (U chunks
-// each): while one buffer is computed the other one's table entries are in
-// flight.  Every prefetch is unconditional (the one past the last chunk
+// table; each block is BLK_CHUNKS chunks.  The chunks run through two register
+// buffers in turn: while one buffer is computed the other one's table entries
+// are in flight.  Every prefetch is unconditional (the one past the last chunk
 // re-reads the last chunk), so the buffers need no register copies.  The first
 // bin of a block starts the per-lane partial sums and the block ends with
-// their flush.  U = 2 gives each lane two independent bins per step (more
-// instruction-level parallelism, more registers).  Partial sums are
-// accumulated in chunk order, so the result does not depend on U.
-template <int U, class In, class Acc>
+// their flush.  A lane adds its bins in chunk order, each chunk's pair in bin
+// order.
+template <class In, class Acc>
 __device__ __forceinline__ void bin_loop(Acc& A, const BinCoef& k, const TableView& t, int blk0, int blk_step,
                                          int nblk) {
-    static_assert(BIN_KB % (2 * U) == 0, "a block holds a whole number of buffer pairs");
-    constexpr int PAIRS = BIN_KB / (2 * U);
+    static_assert(BLK_CHUNKS % 2 == 0, "a block holds a whole number of buffer pairs");
     const unsigned lane = threadIdx.x & 63;
     const int nb = blk0 < nblk ? (nblk - blk0 + blk_step - 1) / blk_step : 0;   // this wave's blocks
     if (nb == 0) return;
-    const int last = nb * BIN_KB - 1;                                          // this wave's last chunk
-    auto base_of = [&](int c) { return (blk0 + (c / BIN_KB) * blk_step) * TABLE_PAD + 64 * (c % BIN_KB); };
-    In a[U], b[U];
-#pragma unroll
-    for (int h = 0; h < U; ++h) load_chunk(a[h], t, base_of(h), lane);
+    const int last = nb * BLK_CHUNKS - 1;                                      // this wave's last chunk
+    auto base_of = [&](int c) {
+        return (blk0 + (c / BLK_CHUNKS) * blk_step) * TABLE_PAD + CHUNK_BINS * (c % BLK_CHUNKS);
+    };
+    In a, b;
+    load_chunk(a, t, base_of(0), lane);
     for (int blk = 0; blk < nb; ++blk) {
 #pragma unroll
-        for (int pr = 0; pr < PAIRS; ++pr) {
-            const int c = blk * BIN_KB + 2 * U * pr;
-#pragma unroll
-            for (int h = 0; h < U; ++h) load_chunk(b[h], t, base_of(c + U + h), lane);
-#pragma unroll
-            for (int h = 0; h < U; ++h) A.bin(k, a[h], pr == 0 && h == 0);
-#pragma unroll
-            for (int h = 0; h < U; ++h) load_chunk(a[h], t, base_of(min(c + 2 * U + h, last)), lane);
-#pragma unroll
-            for (int h = 0; h < U; ++h) A.bin(k, b[h], false);
+        for (int pr = 0; pr < BLK_CHUNKS / 2; ++pr) {
+            const int c = blk * BLK_CHUNKS + 2 * pr;
+            load_chunk(b, t, base_of(c + 1), lane);
+            A.bin(k, a.b[0], pr == 0);
+            A.bin(k, a.b[1], false);
+            load_chunk(a, t, base_of(min(c + 2, last)), lane);
+            A.bin(k, b.b[0], false);
+            A.bin(k, b.b[1], false);
         }
         A.flush();
     }
@@ -194,7 +217,7 @@ struct MixedAcc {
     }
 };
 
-template <int NDET, int U = 1>
+template <int NDET>
 __device__ __forceinline__ void bins_mixed_wave(const DevEvent* __restrict__ ev, const BinCoef& k, int blk0,
                                                 int blk_step, double mom[MOM_SIZE]) {
     const int npad = __builtin_amdgcn_readfirstlane(ev->n_pad);
@@ -208,7 +231,7 @@ __device__ __forceinline__ void bins_mixed_wave(const DevEvent* __restrict__ ev,
     for (int b = 0; b < NCOEF; ++b) A.G[b] = 0.0;
     const TableView t{raw_rsrc(ev->fwl, (size_t)NROWS * npad * sizeof(double)),
                       raw_rsrc(ev->u32, (size_t)NDET * npad * sizeof(float2)), npad};
-    bin_loop<U, BinIn<NDET, float2>>(A, k, t, blk0, blk_step, npad / TABLE_PAD);
+    bin_loop<BinPair<NDET, float2>>(A, k, t, blk0, blk_step, npad / TABLE_PAD);
 #pragma unroll
     for (int i = 0; i < MOM_SIZE; ++i) mom[i] = 0.0;
 #pragma unroll
@@ -255,7 +278,7 @@ struct Fp64Acc {
     __device__ __forceinline__ void flush() {}
 };
 
-template <int NDET, int U = 1>
+template <int NDET>
 __device__ __forceinline__ void bins_fp64_wave(const DevEvent* __restrict__ ev, const BinCoef& k, int blk0,
                                                int blk_step, double mom[MOM_SIZE]) {
     const int npad = __builtin_amdgcn_readfirstlane(ev->n_pad);
@@ -266,7 +289,7 @@ __device__ __forceinline__ void bins_fp64_wave(const DevEvent* __restrict__ ev, 
     for (int b = 0; b < NCOEF; ++b) A.G[b] = 0.0;
     const TableView t{raw_rsrc(ev->fwl, (size_t)NROWS * npad * sizeof(double)),
                       raw_rsrc(ev->u64, (size_t)NDET * npad * sizeof(double2)), npad};
-    bin_loop<U, BinIn<NDET, double2>>(A, k, t, blk0, blk_step, npad / TABLE_PAD);
+    bin_loop<BinPair<NDET, double2>>(A, k, t, blk0, blk_step, npad / TABLE_PAD);
 #pragma unroll
     for (int i = 0; i < MOM_SIZE; ++i) mom[i] = 0.0;
 #pragma unroll

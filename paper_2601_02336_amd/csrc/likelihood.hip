@@ -25,7 +25,6 @@
 namespace smcgw {
 
 constexpr int BINS_WAVES = 4;   // wavefronts (particles) per workgroup
-constexpr int BINS_UNROLL = 1;  // bins per lane per step of the bin loop (2 costs registers, gains nothing)
 
 __global__ __launch_bounds__(256) void prep_kernel(const DevEvent* __restrict__ evs, int n_events,
                                                    const int32_t* __restrict__ ev_of_p, ParamMap pm, int P,
@@ -51,7 +50,7 @@ __global__ __launch_bounds__(256) void bins_mixed_kernel(const DevEvent* __restr
     const int e = __builtin_amdgcn_readfirstlane(event_index(ev_of_p, p, n_events));
     const BinCoef k = load_coef(cb + (size_t)p * CB_SIZE);
     double m[MOM_SIZE];
-    bins_mixed_wave<NDET, BINS_UNROLL>(evs + e, k, 0, 1, m);
+    bins_mixed_wave<NDET>(evs + e, k, 0, 1, m);
     if ((threadIdx.x & 63) == TOTAL_LANE)
         for (int i = 0; i < MOM_SIZE; ++i) mom[(size_t)p * MOM_SIZE + i] = m[i];
 }
@@ -66,7 +65,7 @@ __global__ __launch_bounds__(256) void bins_fp64_kernel(const DevEvent* __restri
     const int e = __builtin_amdgcn_readfirstlane(event_index(ev_of_p, p, n_events));
     const BinCoef k = load_coef(cb + (size_t)p * CB_SIZE);
     double m[MOM_SIZE];
-    bins_fp64_wave<NDET, BINS_UNROLL>(evs + e, k, 0, 1, m);
+    bins_fp64_wave<NDET>(evs + e, k, 0, 1, m);
     if ((threadIdx.x & 63) == TOTAL_LANE)
         for (int i = 0; i < MOM_SIZE; ++i) mom[(size_t)p * MOM_SIZE + i] = m[i];
 }

@@ -54,11 +54,13 @@ struct NutsArgs {
 };
 
 constexpr int MAX_WAVES = 8;
-// Bins per lane per step of the leaf's bin loop, and the wavefronts per SIMD
-// the register budget is sized for (4: 128 VGPRs, 3: 168, 2: 256).
-constexpr int NUTS_UNROLL = 1;
+// Wavefronts per SIMD the register budget is sized for (4: 128 VGPRs, 3: 168,
+// 2: 256).
 constexpr int NUTS_WAVES_PER_SIMD = 3;
 constexpr int MAXD1 = SMCGW_MAX_DEPTH + 1;
+
+// Per-detector terms of a leaf's epilogue (see leaf_finish).
+enum { FD_LL = 0, FD_DLN, FD_GP, FD_T = FD_GP + 4, FD_RA, FD_DEC, FD_SIZE };
 
 struct NutsShared {
     double L[MAXDIM * MAXDIM];
@@ -70,6 +72,7 @@ struct NutsShared {
     double utr[2][MAXD1][MAXDIM];                // U-turn dot-product terms of every level
     double cb[CB_SIZE];
     double mom[MAX_WAVES][MOM_SIZE];
+    double fin_phase[4], fin_det[MAXDET][FD_SIZE], fin_g[NPAR + 1];   // epilogue terms of the leaf
     double th[NPAR];
     double left[5][MAXDIM], right[5][MAXDIM];   // x, r, g (grad log p_t), gl (grad logL), v = M^{-1} r
     double prop[2][MAXDIM], sprop[2][MAXDIM];    // x, gl
@@ -223,8 +226,8 @@ struct NutsState {
     double rec[4][MAXDIM];                               // finished leaf: x, r, g (grad log p_t), gl
     double pgp[MAXDIM];                                  // prior gradient at the leaf in flight
     double plp;                                          // log prior at the leaf in flight
-    double ul[2];                                        // leaf uniforms, by leaf index parity
-    double dtab_u[MAXD1];                                // merge uniform of each doubling
+    double ul[2];                                        // log of the leaf uniforms, by leaf index parity
+    double dtab_u[MAXD1];                                // log of the merge uniform of each doubling
     int dtab_dir[MAXD1];                                 // direction of each doubling
     double h0, logw, sub_logw, uacc, acc_sum, eps, prop_ll, sprop_ll, ll_new, rec_ll, rec_lp;
     int first, stop, j, n, nleaves, depth, nlf, div, dir, md, inflight;
@@ -274,13 +277,14 @@ __device__ __noinline__ void start_transition(NutsShared& S, NutsState& T, const
         T.srho[lane] = 0.0;
     }
     const int md = a.md_per_p ? min(a.md_per_p[p], SMCGW_MAX_DEPTH) : a.max_depth;
-    // every doubling's draws at once, one per lane
+    // every doubling's draws at once, one per lane (the merge uniform as its
+    // log: the merge test u < W_sub / W becomes log u < log W_sub - log W)
     if (lane < md) {
         int dj;
         double uj;
         doubling_draw(a, p, lane, dj, uj);
         T.dtab_dir[lane] = dj;
-        T.dtab_u[lane] = uj;
+        T.dtab_u[lane] = log(uj);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -384,7 +388,8 @@ __device__ __noinline__ void aux_in_flight(const DevEvent* ev, NutsShared& S, Nu
     const int idx = T.inflight;
     double ul0, ul1;
     rng_uniform2(a.seed, (uint32_t)idx, (uint32_t)p, a.iteration, RNG_LEAF, ul0, ul1);
-    if (lane == 0) { T.plp = lpr; T.ul[idx & 1] = ul0; }
+    const double lul0 = log(ul0);   // the sampling test u < w / W is taken as log u < log w - log W
+    if (lane == 0) { T.plp = lpr; T.ul[idx & 1] = lul0; }
 }
 
 // Decisions for the finished leaf (wavefront 0): energy, divergence,
@@ -425,9 +430,9 @@ __device__ __noinline__ void bookkeep(NutsShared& S, NutsState& T, const NutsArg
         srho += r;
         const double lw = -dh;
         const double nlw = log_add_exp(sub_logw, lw);
-        const double ul0 = T.ul[leafc & 1];   // drawn while this leaf was in flight
+        const double lul0 = T.ul[leafc & 1];   // log of the uniform drawn while this leaf was in flight
         ++leafc;
-        if (ul0 < exp(lw - nlw)) {
+        if (lul0 < lw - nlw) {
             if (dl) { S.sprop[0][lane] = x; S.sprop[1][lane] = gl; }
             sprop_ll = ll;
         }
@@ -463,7 +468,7 @@ __device__ __noinline__ void bookkeep(NutsShared& S, NutsState& T, const NutsArg
     } else if (n + 1 == T.nleaves) {
         depth = j + 1;
         __builtin_amdgcn_wave_barrier();
-        if (uacc < exp(sub_logw - logw)) {
+        if (uacc < sub_logw - logw) {   // uacc holds the log of the merge uniform
             if (dl) { S.prop[0][lane] = S.sprop[0][lane]; S.prop[1][lane] = S.sprop[1][lane]; }
             prop_ll = sprop_ll;
         }
@@ -560,24 +565,88 @@ __device__ __noinline__ void leaf_prep_extrinsic(const DevEvent* ev, NutsShared&
     }
 }
 
-// Epilogue of one leaf (wavefront 0): sum the wavefronts' moments, logL and
-// the gradient over the sampled coordinates.
-template <int WAVES>
+// Epilogue of one leaf (wavefront 0): sum the wavefronts' moments, then logL
+// and its gradient (the algebra of finish_particle) spread over lanes, so the
+// chain is a few dependent steps instead of one lane's whole epilogue:
+//   lanes 0..3        the phase part of d logL / d(Mc, q, chi1, chi2): a dot
+//                     product of the basis moments with the prologue's Jacobian;
+//   lanes 4..4+n_det  detector d's terms of logL, of d logL / d ln C_A, of the
+//                     projection derivatives and of the arrival-time terms;
+//   lanes 0..NPAR     one gradient component each, summing the detector terms in
+//                     detector order; lane FIN_LL_LANE the log-likelihood.
+constexpr int FIN_LL_LANE = NPAR;
+
+template <int NDET, int WAVES>
 __device__ __noinline__ void leaf_finish(const DevEvent* ev, NutsShared& S, NutsState& T, int D, int lane) {
     // wavefront totals of the moments, in wavefront order, into S.mom[0]
     if (lane < MOM_SIZE) {
         double s = S.mom[0][lane];
+#pragma unroll
         for (int w = 1; w < WAVES; ++w) s += S.mom[w][lane];
         S.mom[0][lane] = s;
     }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    double g11[NPAR];
-    const double ll = finish_particle(*ev, S.cb, S.mom[0], g11);
-    const int src = lane < D ? S.pidx[lane] : 0;
-    double v = 0.0;
+    const double* c = S.cb;
+    const double* m = S.mom[0];
+    if (lane < 4) {
+        double s = 0.0;
 #pragma unroll
-    for (int q = 0; q < NPAR; ++q) v = (src == q) ? g11[q] : v;
-    if (lane < D) T.gl_new[lane] = v;
+        for (int b = 0; b < NCOEF; ++b) s += c[CB_DC + 4 * b + lane] * m[MOM_G + b];
+        S.fin_phase[lane] = TWO_PI * s;
+    } else if (lane < 4 + NDET) {
+        const int d = lane - 4;
+        const double amp = c[CB_AMP];
+        const double pr = c[CB_PR + d] * amp, pi = c[CB_PI + d] * amp;
+        const double zr = m[MOM_ZR + d], zi = m[MOM_ZI + d], h = ev->hnorm[d];
+        const double re = pr * zr - pi * zi;
+        const double p2 = pr * pr + pi * pi;
+        double* o = S.fin_det[d];
+        o[FD_LL] = re - 0.5 * p2 * h;
+        o[FD_DLN] = re - p2 * h;
+        const double ar = zr - h * pr, ai = -zi - h * pi;   // dlogL / d(Re P', Im P')
+#pragma unroll
+        for (int k = 0; k < 4; ++k) o[FD_GP + k] = amp * (ar * c[CB_DPR + 4 * d + k] + ai * c[CB_DPI + 4 * d + k]);
+        const double t = m[MOM_T + d];
+        o[FD_T] = t;
+        o[FD_RA] = TWO_PI * t * c[CB_DTAU + 2 * d];
+        o[FD_DEC] = TWO_PI * t * c[CB_DTAU + 2 * d + 1];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    // every lane sums the detector terms in detector order (broadcast reads, no
+    // divergence) and keeps the component of its own index: gradient component
+    // q on lane q, logL on FIN_LL_LANE
+    double sum[FD_SIZE];
+#pragma unroll
+    for (int f = 0; f < FD_SIZE; ++f) {
+        double s = 0.0;
+#pragma unroll
+        for (int d = 0; d < NDET; ++d) s += S.fin_det[d][f];
+        sum[f] = s;
+    }
+    const double g_mc = S.fin_phase[0] + sum[FD_DLN] * c[CB_DLNCA_MC];
+    const double g_dl = sum[FD_DLN] * c[CB_DLNCA_DL];
+    const double g_ra = sum[FD_RA] + sum[FD_GP + 2];
+    const double g_dec = sum[FD_DEC] + sum[FD_GP + 3];
+    const double g_tc = TWO_PI * sum[FD_T];
+    const double ll = -0.5 * ev->dd + sum[FD_LL];
+    double v = ll;
+    v = lane == P_MC ? g_mc : v;
+    v = lane == P_Q ? S.fin_phase[1] : v;
+    v = lane == P_CHI1 ? S.fin_phase[2] : v;
+    v = lane == P_CHI2 ? S.fin_phase[3] : v;
+    v = lane == P_DL ? g_dl : v;
+    v = lane == P_IOTA ? sum[FD_GP + 0] : v;
+    v = lane == P_PSI ? sum[FD_GP + 1] : v;
+    v = lane == P_RA ? g_ra : v;
+    v = lane == P_DEC ? g_dec : v;
+    v = lane == P_TC ? g_tc : v;
+    v = lane == P_PHIC ? -m[MOM_G + 0] : v;
+    if (lane <= FIN_LL_LANE) S.fin_g[lane] = v;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (lane < D) T.gl_new[lane] = S.fin_g[S.pidx[lane]];
     if (lane == 0) T.ll_new = ll;
 }
 
@@ -690,14 +759,14 @@ __global__ __launch_bounds__(WAVES * 64, (WAVES == 1 ? 2 : NUTS_WAVES_PER_SIMD))
                     const BinCoef k = load_coef(S.cb);
                     double m[MOM_SIZE];
                     if (PREC == SMCGW_MIXED)
-                        bins_mixed_wave<NDET, NUTS_UNROLL>(ev, k, wave, WAVES, m);
+                        bins_mixed_wave<NDET>(ev, k, wave, WAVES, m);
                     else
-                        bins_fp64_wave<NDET, NUTS_UNROLL>(ev, k, wave, WAVES, m);
+                        bins_fp64_wave<NDET>(ev, k, wave, WAVES, m);
                     if (lane == TOTAL_LANE)
                         for (int i = 0; i < MOM_SIZE; ++i) S.mom[wave][i] = m[i];
                 }
                 __syncthreads();
-                if (wave == 0) leaf_finish<WAVES>(ev, S, T, D, lane);
+                if (wave == 0) leaf_finish<NDET, WAVES>(ev, S, T, D, lane);
             } else if (wave == 0) {
                 double gl;
                 const double ll = analytic_loglike<TK>(S, tgt, D, lane, lane < D ? T.x[lane] : 0.0, gl);
