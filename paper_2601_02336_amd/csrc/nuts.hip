@@ -226,7 +226,7 @@ struct NutsState {
     double rec[4][MAXDIM];                               // finished leaf: x, r, g (grad log p_t), gl
     double pgp[MAXDIM];                                  // prior gradient at the leaf in flight
     double plp;                                          // log prior at the leaf in flight
-    double ul[2];                                        // log of the leaf uniforms, by leaf index parity
+    double ul[2][2];                                     // log u and log(1 - u) of the leaf uniforms, by leaf index parity
     double dtab_u[MAXD1];                                // log of the merge uniform of each doubling
     int dtab_dir[MAXD1];                                 // direction of each doubling
     double h0, logw, sub_logw, uacc, acc_sum, eps, prop_ll, sprop_ll, ll_new, rec_ll, rec_lp;
@@ -322,39 +322,47 @@ template <int TK>
 __device__ __noinline__ int advance(NutsShared& S, NutsState& T, const NutsArgs& a, int lane) {
     const int D = a.D;
     const bool dl = lane < D;
+    const int kk = dl ? lane : 0;
+    // Every tree-state value the step may need is read up front, both tree ends
+    // included, so the LDS round trips overlap instead of following the branches.
+    const int first = T.first, n = T.n, nleaves = T.nleaves, j = T.j, md = T.md, dcur = T.dir;
+    const double ll = T.ll_new, plp = T.plp, eps_prev = T.eps, beta = a.beta;
+    const double gl = T.gl_new[kk], xf = T.x[kk], pg = T.pgp[kk], rh = T.r[kk];
+    const double lx = S.left[0][kk], lr = S.left[1][kk], lg = S.left[2][kk];
+    const double rx = S.right[0][kk], rr = S.right[1][kk], rg = S.right[2][kk];
+    const int dnext = T.dtab_dir[min(j + 1, MAXD1 - 1)];
     double xs, rs, gs;   // start point of the next leapfrog step
     int dir;
-    if (T.first) {
-        if (T.md < 1) return CMD_DONE;
-        xs = dl ? S.left[0][lane] : 0.0;
-        rs = dl ? S.left[1][lane] : 0.0;
-        gs = dl ? S.left[2][lane] : 0.0;
-        dir = T.dir;
+    if (first) {
+        if (md < 1) return CMD_DONE;
+        xs = dl ? lx : 0.0;
+        rs = dl ? lr : 0.0;
+        gs = dl ? lg : 0.0;
+        dir = dcur;
     } else {
-        const double ll = T.ll_new;
-        const double gl = dl ? T.gl_new[lane] : 0.0;
-        const double x = dl ? T.x[lane] : 0.0;
-        const double lp = a.beta * ll + T.plp;
-        const double g = a.beta * gl + (dl ? T.pgp[lane] : 0.0);
-        const double r = dl ? fma(0.5 * T.eps, g, T.r[lane]) : 0.0;
+        const double x = dl ? xf : 0.0;
+        const double lp = beta * ll + plp;
+        const double g = dl ? beta * gl + pg : 0.0;
+        const double r = dl ? fma(0.5 * eps_prev, g, rh) : 0.0;
         if (dl) { T.rec[0][lane] = x; T.rec[1][lane] = r; T.rec[2][lane] = g; T.rec[3][lane] = gl; }
         if (lane == 0) { T.rec_ll = ll; T.rec_lp = lp; }
-        if (T.n + 1 < T.nleaves) {
+        if (n + 1 < nleaves) {
             xs = x; rs = r; gs = g;
-            dir = T.dir;
-        } else if (T.j + 1 < T.md) {
-            dir = T.dtab_dir[T.j + 1];
-            if (dir == T.dir) {
+            dir = dcur;
+        } else if (j + 1 < md) {
+            dir = dnext;
+            if (dir == dcur) {
                 xs = x; rs = r; gs = g;
             } else {
-                const double (*E)[MAXDIM] = dir > 0 ? S.right : S.left;
-                xs = dl ? E[0][lane] : 0.0; rs = dl ? E[1][lane] : 0.0; gs = dl ? E[2][lane] : 0.0;
+                xs = dl ? (dir > 0 ? rx : lx) : 0.0;
+                rs = dl ? (dir > 0 ? rr : lr) : 0.0;
+                gs = dl ? (dir > 0 ? rg : lg) : 0.0;
             }
         } else {
             return CMD_DONE;
         }
     }
-    if (lane == 0) T.inflight = T.first ? 0 : T.nlf + 1;   // leaf index of the next leaf
+    if (lane == 0) T.inflight = first ? 0 : T.nlf + 1;   // leaf index of the next leaf
     const double eps = dir * a.step;
     double r = dl ? fma(0.5 * eps, gs, rs) : 0.0;
     const double v = minv_apply(S, D, lane, r);
@@ -388,8 +396,11 @@ __device__ __noinline__ void aux_in_flight(const DevEvent* ev, NutsShared& S, Nu
     const int idx = T.inflight;
     double ul0, ul1;
     rng_uniform2(a.seed, (uint32_t)idx, (uint32_t)p, a.iteration, RNG_LEAF, ul0, ul1);
-    const double lul0 = log(ul0);   // the sampling test u < w / W is taken as log u < log w - log W
-    if (lane == 0) { T.plp = lpr; T.ul[idx & 1] = lul0; }
+    // The progressive sampling test u < w / (W + w) is taken as log u + log W < log(1 - u) + log w: lanes 0
+    // and 1 take the two logs at once.
+    const double lu = log(lane == 0 ? ul0 : 1.0 - ul0);
+    const double lu0 = __shfl(lu, 0, 64), lu1 = __shfl(lu, 1, 64);
+    if (lane == 0) { T.plp = lpr; T.ul[idx & 1][0] = lu0; T.ul[idx & 1][1] = lu1; }
 }
 
 // Decisions for the finished leaf (wavefront 0): energy, divergence,
@@ -414,9 +425,15 @@ __device__ __noinline__ void bookkeep(NutsShared& S, NutsState& T, const NutsArg
     const double h0 = T.h0;
     const double dh = -lp + 0.5 * dim_sum(S, D, lane, r * v) - h0;
     const bool finite = (dh == dh) && dh != INFINITY && dh != -INFINITY;
-    double acc_sum = T.acc_sum + (finite ? fmin(1.0, exp(-dh)) : 0.0);
-    double srho = dl ? T.srho[lane] : 0.0;
     double sub_logw = T.sub_logw;
+    // Both exponentials of the leaf in one evaluation: lane 0 the log-add term e^{min - max} of the subtree
+    // weight update, lane 1 the acceptance term e^{-dh}.
+    const double lw = -dh;
+    const double lmax = fmax(sub_logw, lw), lmin = fmin(sub_logw, lw);
+    const double ee = exp(lane == 0 ? lmin - lmax : -dh);
+    const double e_add = __shfl(ee, 0, 64), e_acc = __shfl(ee, 1, 64);
+    double acc_sum = T.acc_sum + (finite ? fmin(1.0, e_acc) : 0.0);
+    double srho = dl ? T.srho[lane] : 0.0;
     double sprop_ll = T.sprop_ll;
     uint32_t leafc = T.leafc;
     bool ok = true;
@@ -428,11 +445,11 @@ __device__ __noinline__ void bookkeep(NutsShared& S, NutsState& T, const NutsArg
         for (int l = 1; l <= j; ++l)
             if ((n & ((1 << l) - 1)) == 0 && dl) { S.ck_rho[l][lane] = srho; S.ck_v[l][lane] = v; }
         srho += r;
-        const double lw = -dh;
-        const double nlw = log_add_exp(sub_logw, lw);
-        const double lul0 = T.ul[leafc & 1];   // log of the uniform drawn while this leaf was in flight
+        // uniform drawn while this leaf was in flight: accept with probability w / (W + w)
+        const double lu0 = T.ul[leafc & 1][0], lu1 = T.ul[leafc & 1][1];
         ++leafc;
-        if (lul0 < lw - nlw) {
+        const double nlw = sub_logw == -INFINITY ? lw : lmax + log(1.0 + e_add);
+        if (lu0 + sub_logw < lu1 + lw) {
             if (dl) { S.sprop[0][lane] = x; S.sprop[1][lane] = gl; }
             sprop_ll = ll;
         }
