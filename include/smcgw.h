@@ -57,6 +57,7 @@ enum { SMCGW_PRIOR_FLAT = 0, SMCGW_PRIOR_UNIFORM = 1, SMCGW_PRIOR_LOGUNIFORM = 2
 #define SMCGW_MAX_DIM 16
 #define SMCGW_MAX_DEPTH 12
 #define SMCGW_MAX_EVENTS 64
+#define SMCGW_MAX_BINS (1 << 24)   /* frequency bins of one event (its tables stay below 2 GiB) */
 
 typedef struct smcgw_ctx smcgw_ctx;
 
@@ -122,7 +123,10 @@ int smcgw_set_stream(smcgw_ctx *ctx, void *hip_stream);
  * 4 df conj(d)/S f^{-7/6}, the phase basis of every bin, <d|d> and
  * sum_j 4 df f^{-7/3}/S per detector.  data_reim [n_det][N][2], psd
  * [n_det][N] and dets [n_det] are host arrays; synchronises.  *event_id
- * receives the index used by smcgw_loglike_grad's event_of_particle. */
+ * receives the index used by smcgw_loglike_grad's event_of_particle.
+ * SMCGW_ERR_SHAPE for N outside 1..SMCGW_MAX_BINS, n_det outside
+ * 1..SMCGW_MAX_DET, more than SMCGW_MAX_EVENTS events, or a detector count
+ * that differs from the events already added. */
 int smcgw_add_event(smcgw_ctx *ctx, const smcgw_event_desc *ev, const double *data_reim, const double *psd,
                     const smcgw_detector *dets, int *event_id);
 

@@ -1,17 +1,17 @@
 // Per-wavefront bin loop of the likelihood and its FP64 epilogue, shared by
 // the batched likelihood kernels and the persistent NUTS kernel.
 //
-// A wavefront walks blocks of TABLE_PAD bins (its 64 lanes stride the bins of
-// a block, TABLE_PAD/64 bins per lane) starting at block `blk0` with stride
-// `blk_step`; the per-bin tables are read coalesced and shared by every
-// particle.  Moments (see likelihood.hip) are returned wave-summed in FP64:
-// lane TOTAL_LANE holds the totals of the blocks the wavefront visited.
+// A wavefront walks blocks of TABLE_PAD bins starting at block `blk0` with
+// stride `blk_step`.  A block is read in chunks of 128 bins, lane l taking
+// bins 2l and 2l + 1 of each chunk (TABLE_PAD/64 bins per lane per block); the
+// per-bin tables are read coalesced and shared by every particle.  Moments
+// (see likelihood.hip) are returned wave-summed in FP64: lane TOTAL_LANE holds
+// the totals of the blocks the wavefront visited.
 #pragma once
 
 #include "common.h"
 
 namespace smcgw {
-
 
 // Wave-uniform per-particle values the bin loop needs (from the coefficient block).
 struct BinCoef {

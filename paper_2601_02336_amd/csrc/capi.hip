@@ -276,8 +276,9 @@ static int build_event(smcgw_ctx* c, const smcgw_event_desc* ev, const double* d
 }
 
 static int check_event_desc(smcgw_ctx* c, const smcgw_event_desc* ev) {
-    if (ev->n_bins <= 0 || ev->n_det <= 0 || ev->n_det > MAXDET || !(ev->df > 0.0) || !(ev->f_low > 0.0) ||
-        ev->pn_order < 0 || ev->pn_order > 7)
+    // the bin loop addresses a table row with 32-bit byte offsets
+    if (ev->n_bins <= 0 || ev->n_bins > SMCGW_MAX_BINS || ev->n_det <= 0 || ev->n_det > MAXDET || !(ev->df > 0.0) ||
+        !(ev->f_low > 0.0) || ev->pn_order < 0 || ev->pn_order > 7)
         return SMCGW_ERR_SHAPE;
     if ((int)c->events.size() >= SMCGW_MAX_EVENTS) return SMCGW_ERR_SHAPE;
     if (!c->events.empty() && ev->n_det != c->n_det) return SMCGW_ERR_SHAPE;

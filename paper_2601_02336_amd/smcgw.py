@@ -20,6 +20,7 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "lib", "lib
 
 OK, WARN_FALLBACK = 0, 1
 ERR_INVALID, ERR_SHAPE, ERR_HIP, ERR_OOM, ERR_NOT_INIT, ERR_STALL = -1, -2, -3, -4, -5, -6
+MAX_BINS = 1 << 24   # frequency bins of one event (SMCGW_MAX_BINS)
 PLAIN_FP64, MIXED = 0, 1
 KERNEL_BINS, KERNEL_PREP, KERNEL_FINISH, KERNEL_NUTS, KERNEL_SMC, KERNEL_METRIC = 0, 1, 2, 3, 4, 5
 OPT_NUTS_WAVES = 0

@@ -178,3 +178,20 @@ def test_invalid_calls_raise(smc):
     with pytest.raises(smc.SmcgwError):
         c.loglike_grad(x, precision=7)
     c.close()
+
+
+def test_event_size_limit(smc):
+    """An event beyond SMCGW_MAX_BINS bins is refused before its arrays are read (the bin loop addresses the
+    tables with 32-bit byte offsets)."""
+    import ctypes as C
+    ev = event(synth.SPEC_SMALL)
+    c = smc.Context(0)
+    desc = smc.EventDesc(ev.f_low, ev.df, smc.MAX_BINS + 1, ev.n_det, ev.gmst, ev.t_sun, ev.mpc_m, ev.c_light,
+                         ev.pn_order, 0)
+    dets = (smc.Detector * ev.n_det)(*[smc.Detector(*s.as_tuple()) for s in ev.sites])
+    one = np.zeros(2, dtype=np.float64)
+    eid = C.c_int(-7)
+    rc = smc.lib().smcgw_add_event(c._h, C.byref(desc), one.ctypes.data_as(C.c_void_p),
+                                   one.ctypes.data_as(C.c_void_p), dets, C.byref(eid))
+    assert rc == smc.ERR_SHAPE and eid.value == -7
+    c.close()
