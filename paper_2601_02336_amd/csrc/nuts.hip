@@ -442,8 +442,10 @@ __device__ __noinline__ void bookkeep(NutsShared& S, NutsState& T, const NutsArg
         div = 1;
         ok = false;
     } else {
-        for (int l = 1; l <= j; ++l)
-            if ((n & ((1 << l) - 1)) == 0 && dl) { S.ck_rho[l][lane] = srho; S.ck_v[l][lane] = v; }
+        // this leaf opens the nodes of levels 1 .. ls (n a multiple of 2^l)
+        const int ls = n == 0 ? j : min(j, __builtin_ctz((unsigned)n));
+        if (dl)
+            for (int l = 1; l <= ls; ++l) { S.ck_rho[l][lane] = srho; S.ck_v[l][lane] = v; }
         srho += r;
         // uniform drawn while this leaf was in flight: accept with probability w / (W + w)
         const double lu0 = T.ul[leafc & 1][0], lu1 = T.ul[leafc & 1][1];
@@ -459,18 +461,26 @@ __device__ __noinline__ void bookkeep(NutsShared& S, NutsState& T, const NutsArg
             // needs rho.v_first > 0 and rho.v_last > 0.  All levels at once: the
             // coordinate lanes write their terms, lane l sums level l in
             // coordinate order.
+            // levels 1 .. lc complete here, lc = min(j, trailing zeros of n + 1)
+            const int lc = min(j, __builtin_ctz((unsigned)(n + 1)));
             __builtin_amdgcn_wave_barrier();
             if (dl)
-                for (int l = 1; l <= j; ++l) {
+                for (int l = 1; l <= lc; ++l) {
                     const double nr = srho - S.ck_rho[l][lane];
                     S.utr[0][l][lane] = nr * S.ck_v[l][lane];
                     S.utr[1][l][lane] = nr * v;
                 }
             __builtin_amdgcn_wave_barrier();
             bool fail = false;
-            if (lane >= 1 && lane <= j && ((n + 1) & ((1 << lane) - 1)) == 0) {
+            if (lane >= 1 && lane <= lc) {
+                // all MAXDIM entries read at once, those beyond D masked to zero
                 double sa = 0.0, sb = 0.0;
-                for (int m = 0; m < D; ++m) { sa += S.utr[0][lane][m]; sb += S.utr[1][lane][m]; }
+#pragma unroll
+                for (int m = 0; m < MAXDIM; ++m) {
+                    const bool in = m < D;
+                    sa += in ? S.utr[0][lane][m] : 0.0;
+                    sb += in ? S.utr[1][lane][m] : 0.0;
+                }
                 fail = !(sa > 0.0 && sb > 0.0);
             }
             if (__ballot(fail) != 0) ok = false;
