@@ -4,9 +4,9 @@
 // A wavefront walks blocks of TABLE_PAD bins starting at block `blk0` with
 // stride `blk_step`.  A block is read in chunks of 128 bins, lane l taking
 // bins 2l and 2l + 1 of each chunk (TABLE_PAD/64 bins per lane per block); the
-// per-bin tables are read coalesced and shared by every particle.  Moments
-// (see likelihood.hip) are returned wave-summed in FP64: lane TOTAL_LANE holds
-// the totals of the blocks the wavefront visited.
+// per-bin tables are read coalesced and shared by every particle.  The
+// wavefront's moments (see likelihood.hip), summed in FP64 over the blocks it
+// visited, are written to a moment block by lanes 0..7.
 #pragma once
 
 #include "common.h"
@@ -171,6 +171,84 @@ __device__ __forceinline__ void bin_loop(Acc& A, const BinCoef& k, const TableVi
     }
 }
 
+// Wavefront totals of K per-lane values, written to out[idx[k]] (any address
+// space) by lanes 0..7.  Three halving steps over lane bits 0-2 scatter the
+// values: at each step a lane keeps one half of its list (by its lane bit) and
+// adds the partner lane's copy of that half, the partner being the lane with the
+// opposite bit and the same lower bits (xor 1, xor 2, a rotation by 4 inside
+// the row of 16).  A lane then holds ceil(K/8) partial sums, which full sums
+// over bits 3-5 (a rotation by 8 inside the row, then xor 16 and xor 32)
+// complete.  A list of odd length pads its upper half with a zero.  The order
+// of the additions is fixed, so the totals do not depend on anything but the
+// inputs; the reduction costs about 7 K/2 + 3.5 K/4 + ... instead of 18 K
+// instructions for K separate wavefront sums.
+template <int K>
+__device__ __forceinline__ void wave_totals_to(const double (&v)[K], const int (&idx)[K], double* out) {
+    constexpr int M1 = (K + 1) / 2, M2 = (M1 + 1) / 2, M3 = (M2 + 1) / 2;
+    const int lane = threadIdx.x & 63;
+    const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4;
+    double c1[M1], c2[M2], c3[M3];
+#pragma unroll
+    for (int k = 0; k < M1; ++k) {
+        const double hi = k + M1 < K ? v[k + M1] : 0.0;
+        const double send = b0 ? v[k] : hi;
+        c1[k] = (b0 ? hi : v[k]) + dpp_move<0xb1>(send);   // quad_perm [1,0,3,2]
+    }
+#pragma unroll
+    for (int k = 0; k < M2; ++k) {
+        const double hi = k + M2 < M1 ? c1[k + M2] : 0.0;
+        const double send = b1 ? c1[k] : hi;
+        c2[k] = (b1 ? hi : c1[k]) + dpp_move<0x4e>(send);   // quad_perm [2,3,0,1]
+    }
+#pragma unroll
+    for (int k = 0; k < M3; ++k) {
+        const double hi = k + M3 < M2 ? c2[k + M3] : 0.0;
+        const double send = b2 ? c2[k] : hi;
+        c3[k] = (b2 ? hi : c2[k]) + dpp_move<0x124>(send);   // row_ror:4
+    }
+#pragma unroll
+    for (int k = 0; k < M3; ++k) {
+        double t = c3[k] + dpp_move<0x128>(c3[k]);   // row_ror:8
+        t += __shfl_xor(t, 16, 64);
+        t += __shfl_xor(t, 32, 64);
+        c3[k] = t;
+    }
+    if (lane < 8) {
+#pragma unroll
+        for (int k = 0; k < M3; ++k) {
+            const int p2 = b2 ? k + M3 : k;
+            const int p1 = b1 ? p2 + M2 : p2;
+            const int p0 = b0 ? p1 + M1 : p1;
+            if (p2 < M2 && p1 < M1 && p0 < K) out[idx[p0]] = c3[k];
+        }
+    }
+}
+
+// Moments of NDET detectors from a wavefront's per-lane sums into a moment
+// block (MOM_SIZE entries, those of absent detectors zero).
+template <int NDET>
+__device__ __forceinline__ void store_moments(const double (&Zr)[NDET], const double (&Zi)[NDET],
+                                              const double (&T)[NDET], const double (&G)[NCOEF], double* out) {
+    constexpr int K = 3 * NDET + NCOEF;
+    double v[K];
+    int idx[K];
+#pragma unroll
+    for (int d = 0; d < NDET; ++d) {
+        v[d] = Zr[d]; idx[d] = MOM_ZR + d;
+        v[NDET + d] = Zi[d]; idx[NDET + d] = MOM_ZI + d;
+        v[2 * NDET + d] = T[d]; idx[2 * NDET + d] = MOM_T + d;
+    }
+#pragma unroll
+    for (int b = 0; b < NCOEF; ++b) { v[3 * NDET + b] = G[b]; idx[3 * NDET + b] = MOM_G + b; }
+    wave_totals_to<K>(v, idx, out);
+    const int lane = threadIdx.x & 63;
+    constexpr int ABSENT = MAXDET - NDET;
+    if (lane >= 8 && lane < 8 + 3 * ABSENT) {
+        const int j = lane - 8, d = NDET + j % (ABSENT > 0 ? ABSENT : 1), which = j / (ABSENT > 0 ? ABSENT : 1);
+        out[(which == 0 ? MOM_ZR : which == 1 ? MOM_ZI : MOM_T) + d] = 0.0;
+    }
+}
+
 // MIXED: FP64 phase and argument reduction, FP32 sin/cos, complex products and
 // per-lane partial sums (flushed into FP64 once per block), FP64 basis moments.
 template <int NDET>
@@ -219,7 +297,7 @@ struct MixedAcc {
 
 template <int NDET>
 __device__ __forceinline__ void bins_mixed_wave(const DevEvent* __restrict__ ev, const BinCoef& k, int blk0,
-                                                int blk_step, double mom[MOM_SIZE]) {
+                                                int blk_step, double* mom) {
     const int npad = __builtin_amdgcn_readfirstlane(ev->n_pad);
     MixedAcc<NDET> A;
 #pragma unroll
@@ -232,16 +310,7 @@ __device__ __forceinline__ void bins_mixed_wave(const DevEvent* __restrict__ ev,
     const TableView t{raw_rsrc(ev->fwl, (size_t)NROWS * npad * sizeof(double)),
                       raw_rsrc(ev->u32, (size_t)NDET * npad * sizeof(float2)), npad};
     bin_loop<BinPair<NDET, float2>>(A, k, t, blk0, blk_step, npad / TABLE_PAD);
-#pragma unroll
-    for (int i = 0; i < MOM_SIZE; ++i) mom[i] = 0.0;
-#pragma unroll
-    for (int d = 0; d < NDET; ++d) {
-        mom[MOM_ZR + d] = wave_total(A.Zr[d]);
-        mom[MOM_ZI + d] = wave_total(A.Zi[d]);
-        mom[MOM_T + d] = wave_total(A.T[d]);
-    }
-#pragma unroll
-    for (int b = 0; b < NCOEF; ++b) mom[MOM_G + b] = wave_total(A.G[b]);
+    store_moments<NDET>(A.Zr, A.Zi, A.T, A.G, mom);
 }
 
 // PLAIN_FP64: the same algebra in FP64 throughout.
@@ -280,7 +349,7 @@ struct Fp64Acc {
 
 template <int NDET>
 __device__ __forceinline__ void bins_fp64_wave(const DevEvent* __restrict__ ev, const BinCoef& k, int blk0,
-                                               int blk_step, double mom[MOM_SIZE]) {
+                                               int blk_step, double* mom) {
     const int npad = __builtin_amdgcn_readfirstlane(ev->n_pad);
     Fp64Acc<NDET> A;
 #pragma unroll
@@ -290,25 +359,7 @@ __device__ __forceinline__ void bins_fp64_wave(const DevEvent* __restrict__ ev, 
     const TableView t{raw_rsrc(ev->fwl, (size_t)NROWS * npad * sizeof(double)),
                       raw_rsrc(ev->u64, (size_t)NDET * npad * sizeof(double2)), npad};
     bin_loop<BinPair<NDET, double2>>(A, k, t, blk0, blk_step, npad / TABLE_PAD);
-#pragma unroll
-    for (int i = 0; i < MOM_SIZE; ++i) mom[i] = 0.0;
-#pragma unroll
-    for (int d = 0; d < NDET; ++d) {
-        mom[MOM_ZR + d] = wave_total(A.Zr[d]);
-        mom[MOM_ZI + d] = wave_total(A.Zi[d]);
-        mom[MOM_T + d] = wave_total(A.T[d]);
-    }
-#pragma unroll
-    for (int b = 0; b < NCOEF; ++b) mom[MOM_G + b] = wave_total(A.G[b]);
-}
-
-template <int NDET>
-__device__ __forceinline__ void bins_wave(int precision, const DevEvent* ev, const BinCoef& k, int blk0, int blk_step,
-                                          double mom[MOM_SIZE]) {
-    if (precision == SMCGW_MIXED)
-        bins_mixed_wave<NDET>(ev, k, blk0, blk_step, mom);
-    else
-        bins_fp64_wave<NDET>(ev, k, blk0, blk_step, mom);
+    store_moments<NDET>(A.Zr, A.Zi, A.T, A.G, mom);
 }
 
 // logL and its gradient with respect to the 11 source parameters from the

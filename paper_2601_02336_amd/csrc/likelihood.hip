@@ -49,10 +49,7 @@ __global__ __launch_bounds__(256) void bins_mixed_kernel(const DevEvent* __restr
     if (p >= P) return;
     const int e = __builtin_amdgcn_readfirstlane(event_index(ev_of_p, p, n_events));
     const BinCoef k = load_coef(cb + (size_t)p * CB_SIZE);
-    double m[MOM_SIZE];
-    bins_mixed_wave<NDET>(evs + e, k, 0, 1, m);
-    if ((threadIdx.x & 63) == TOTAL_LANE)
-        for (int i = 0; i < MOM_SIZE; ++i) mom[(size_t)p * MOM_SIZE + i] = m[i];
+    bins_mixed_wave<NDET>(evs + e, k, 0, 1, mom + (size_t)p * MOM_SIZE);
 }
 
 template <int NDET>
@@ -64,10 +61,7 @@ __global__ __launch_bounds__(256) void bins_fp64_kernel(const DevEvent* __restri
     if (p >= P) return;
     const int e = __builtin_amdgcn_readfirstlane(event_index(ev_of_p, p, n_events));
     const BinCoef k = load_coef(cb + (size_t)p * CB_SIZE);
-    double m[MOM_SIZE];
-    bins_fp64_wave<NDET>(evs + e, k, 0, 1, m);
-    if ((threadIdx.x & 63) == TOTAL_LANE)
-        for (int i = 0; i < MOM_SIZE; ++i) mom[(size_t)p * MOM_SIZE + i] = m[i];
+    bins_fp64_wave<NDET>(evs + e, k, 0, 1, mom + (size_t)p * MOM_SIZE);
 }
 
 __global__ __launch_bounds__(256) void finish_kernel(const DevEvent* __restrict__ evs, int n_events,

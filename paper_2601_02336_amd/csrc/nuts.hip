@@ -784,13 +784,10 @@ __global__ __launch_bounds__(WAVES * 64, (WAVES == 1 ? 2 : NUTS_WAVES_PER_SIMD))
             if (TK == SMCGW_TARGET_GW) {
                 {
                     const BinCoef k = load_coef(S.cb);
-                    double m[MOM_SIZE];
                     if (PREC == SMCGW_MIXED)
-                        bins_mixed_wave<NDET>(ev, k, wave, WAVES, m);
+                        bins_mixed_wave<NDET>(ev, k, wave, WAVES, S.mom[wave]);
                     else
-                        bins_fp64_wave<NDET>(ev, k, wave, WAVES, m);
-                    if (lane == TOTAL_LANE)
-                        for (int i = 0; i < MOM_SIZE; ++i) S.mom[wave][i] = m[i];
+                        bins_fp64_wave<NDET>(ev, k, wave, WAVES, S.mom[wave]);
                 }
                 __syncthreads();
                 if (wave == 0) leaf_finish<NDET, WAVES>(ev, S, T, D, lane);
