@@ -29,17 +29,16 @@ constexpr int RW_CAND = 1 << RW_LEVELS;
 constexpr int RW_THREADS = 512;   // 32 FP64 accumulators per thread need the larger register budget
 
 
-// Workgroup sums of K values per thread: wavefront totals (DPP), then added
-// in wavefront order.  tot[k] is valid in all threads
-// after the call; red must hold K * (blockDim.x / 64) doubles.
+// Workgroup sums of K values per thread: wavefront totals (one scattered
+// reduction of all K values), then added in wavefront order.  tot[k] is valid
+// in all threads after the call; red must hold K * (blockDim.x / 64) doubles.
 template <int K>
 __device__ __forceinline__ void block_sums(double (&v)[K], double* red, double* tot) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    int idx[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const double t = wave_total(v[k]);
-        if (lane == TOTAL_LANE) red[k * nw + wave] = t;
-    }
+    for (int k = 0; k < K; ++k) idx[k] = k * nw;
+    wave_totals_to<K>(v, idx, red + wave);
     __syncthreads();
     if ((int)threadIdx.x < K) {
         double s = 0.0;
@@ -87,7 +86,8 @@ __global__ __launch_bounds__(RW_THREADS) void reweight_kernel(const double* __re
                                                               double* __restrict__ cum, double* __restrict__ out) {
     __shared__ double red[2 * RW_CAND * (RW_THREADS / 64)];
     __shared__ double tot[2 * RW_CAND];
-    __shared__ double cand[RW_CAND];
+    __shared__ double cand[2][RW_CAND];   // by pass parity: a wavefront may write the next pass's midpoints
+                                          // while another still walks this pass's
     __shared__ double scan[RW_THREADS / 64 + 1];
     double lm = -INFINITY, gm = -INFINITY;
     for (int i = threadIdx.x; i < P; i += blockDim.x) {
@@ -125,7 +125,8 @@ __global__ __launch_bounds__(RW_THREADS) void reweight_kernel(const double* __re
                 a[2 * n + 1] = mid[n]; b[2 * n + 1] = b[n];
             }
         }
-        if (threadIdx.x < RW_CAND) cand[threadIdx.x] = threadIdx.x == 0 ? 1.0 : mid[threadIdx.x];
+        double* cnd = cand[pass & 1];
+        if (threadIdx.x < RW_CAND) cnd[threadIdx.x] = threadIdx.x == 0 ? 1.0 : mid[threadIdx.x];
         const double h = (hi - lo) * (1.0 / RW_CAND);
         const double d0 = lo - beta_prev;
         double s[2 * RW_CAND];
@@ -156,8 +157,8 @@ __global__ __launch_bounds__(RW_THREADS) void reweight_kernel(const double* __re
         for (int lev = 0; lev < RW_LEVELS; ++lev) {
             if (!(it < 100 && hi - lo > 1e-14)) { beta = lo; break; }
             const int k = (2 * (n - (1 << lev)) + 1) << (RW_LEVELS - 1 - lev);   // grid slot of node n
-            if (tot[2 * k] * tot[2 * k] / tot[2 * k + 1] >= target) { lo = cand[n]; n = 2 * n + 1; }
-            else { hi = cand[n]; n = 2 * n; }
+            if (tot[2 * k] * tot[2 * k] / tot[2 * k + 1] >= target) { lo = cnd[n]; n = 2 * n + 1; }
+            else { hi = cnd[n]; n = 2 * n; }
             ++it;
         }
     }
