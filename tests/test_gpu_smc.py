@@ -138,3 +138,26 @@ def test_mass_matrix_edge_shapes(ctx, P, D):
     assert rc == rc_ref
     np.testing.assert_allclose(inv.cpu().numpy(), inv_ref, rtol=1e-10, atol=1e-12 * np.abs(inv_ref).max())
     np.testing.assert_allclose(L.cpu().numpy(), L_ref, rtol=1e-9, atol=1e-12 * np.abs(L_ref).max())
+
+
+def test_reweight_is_repeatable(ctx):
+    """The one-workgroup bisection and its workgroup sums give bitwise the same beta, increment and ancestors on
+    every call: a guard against races between wavefronts (a wavefront running one bisection pass ahead of
+    another once overwrote the midpoints the other was still reading)."""
+    P, D = 2048, 11
+    rng = np.random.default_rng(5)
+    logl = -0.5 * rng.chisquare(11, P) * 40.0 - 3000.0
+    x = rng.normal(size=(P, D))
+    first = None
+    for rep in range(40):
+        xt, lt = torch.tensor(x, device="cuda"), torch.tensor(logl, device="cuda")
+        b, dz, anc = ctx.smc_reweight_resample(xt, lt, None, 0.002 * (rep % 4), 0.7, seed=9, iteration=rep % 4)
+        got = (b, dz, anc.cpu().numpy())
+        if rep < 4:
+            if first is None:
+                first = []
+            first.append(got)
+        else:
+            ref = first[rep % 4]
+            assert got[0] == ref[0] and got[1] == ref[1]
+            np.testing.assert_array_equal(got[2], ref[2])
