@@ -76,8 +76,10 @@ __device__ __forceinline__ double wave_total(double v) {
 // over bits 3-5 (a rotation by 8 inside the row, then xor 16 and xor 32)
 // complete.  A list of odd length pads its upper half with a zero.  The order
 // of the additions is fixed, so the totals do not depend on anything but the
-// inputs; the reduction costs about 7 K/2 + 3.5 K/4 + ... instead of 18 K
-// instructions for K separate wavefront sums.
+// inputs.  A halving step costs 7 instructions per kept value (selects of the
+// sent and kept halves, two DPP moves, an add), so the reduction takes about
+// 7 (K/2 + K/4 + K/8) + 9 K/8 instructions instead of 18 K for K separate
+// wavefront sums.
 template <int K>
 __device__ __forceinline__ void wave_totals_to(const double (&v)[K], const int (&idx)[K], double* out) {
     constexpr int M1 = (K + 1) / 2, M2 = (M1 + 1) / 2, M3 = (M2 + 1) / 2;
