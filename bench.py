@@ -9,7 +9,9 @@ temperature, resampling, population mass matrix and one NUTS transition per
 particle with the likelihood and adjoint gradient at every leapfrog step) of
 each of three independent runs of 2048 particles (--chains), so that the value
 does not rest on the tree depths of a single run; the value is leapfrog
-evaluations per second.  --mode loglike:
+evaluations per second.  Each run enqueues on a HIP stream of its own, so the
+slots one run's NUTS launch leaves idle in its tail run the other runs'
+particles (--one-stream serialises them).  --mode loglike:
 a step is one batched logL + gradient evaluation of 4096 particles.  Prints
 one JSON line.
 
@@ -233,64 +235,83 @@ def smc_setup(smcgw, synth, ev, P, seed=7):
 class _Chain:
     """One SMC run: its context, population and per-iteration state."""
 
-    def __init__(self, ctx, theta, seed, precision, n_iter):
+    def __init__(self, ctx, theta, seed, precision, n_iter, stream):
         import torch
-        self.ctx, self.theta, self.seed = ctx, theta, seed
+        self.ctx, self.theta, self.seed, self.stream = ctx, theta, seed, stream
         self.logl, self.grad = ctx.target_loglike_grad(theta, precision=precision)
-        self.beta, self.it, self.hint = 0.0, 0, None
+        self.beta, self.it, self.hint, self.ready = 0.0, 0, None, None
         self.mm_status = torch.zeros(1, dtype=torch.int32, device="cuda")
         self.bz = torch.zeros((n_iter, 2), dtype=torch.float64, device="cuda")
         self.bz_host = torch.zeros((n_iter, 2), dtype=torch.float64, pin_memory=True)
+        self.nlf = torch.zeros((), dtype=torch.int64, device="cuda")
 
 
-def run_smc_steps(smcgw, chains, precision, args, n_warm, n_steps, time_kernels, metric="population"):
+def run_smc_steps(smcgw, chains, precision, args, n_warm, n_steps, time_kernels, metric="population",
+                  concurrent=False):
     """SMC iterations from prior draws, one iteration of every chain (ctx, theta, seed) per step; returns (evals,
     seconds, nuts kernel ms, launches, betas and depth histograms of the first chain, local-metric kernel ms and
-    launches), kernel times summed over the chains' contexts."""
+    launches, busy ms), kernel times summed over the chains' contexts, busy ms the time during which at least
+    one timed NUTS transition runs.  With concurrent=True every chain enqueues on a
+    HIP stream of its own (default priority), so one run's NUTS launch fills the slots that another's tail
+    leaves idle; otherwise all chains share the current stream."""
     import torch
-    runs = [_Chain(ctx, theta, seed, precision, n_warm + n_steps) for ctx, theta, seed in chains]
-    stats = []
+    streams = [torch.cuda.Stream() if concurrent else torch.cuda.current_stream() for _ in chains]
+    runs = [_Chain(ctx, theta, seed, precision, n_warm + n_steps, st)
+            for (ctx, theta, seed), st in zip(chains, streams)]
+    torch.cuda.synchronize()
+    depths = []
+    marks = []   # (start, end) events around each timed NUTS transition, for the busy span of overlapping launches
 
-    def iterate(c):
+    def iterate(c, timed=False):
         # the iteration is queued as a whole: beta_t goes from the reweighting to the metric and the NUTS
-        # transition through device memory, and reaches the host through an event while the transition runs
+        # transition through device memory, and reaches the host through an event while the transition runs;
+        # the host waits for it only when the chain's next iteration needs beta_t as its lower bracket
+        if c.ready is not None:
+            c.ready.synchronize()
+            c.beta = float(c.bz_host[c.it - 1, 0])
         it = c.it
-        c.ctx.smc_reweight_resample_async(c.theta, c.logl, c.grad, c.beta, args.alpha, c.seed, it, c.bz[it],
-                                          carry=c.hint)
-        c.bz_host[it].copy_(c.bz[it], non_blocking=True)
-        ready = torch.cuda.Event()
-        ready.record()
-        beta_dev = c.bz[it, 0:1]
-        _, L, _ = c.ctx.mass_matrix(c.theta, 0.0, status=c.mm_status)
-        if metric == "local":
-            L, _, _ = c.ctx.local_metric(c.theta, 0.0, fallback=L, status=False, beta_device=beta_dev)
-        out = c.ctx.nuts_step(c.theta, c.logl, c.grad, L, step=args.step, beta=0.0, seed=c.seed, iteration=it,
-                              max_depth=args.max_depth, precision=precision, work_hint=c.hint, beta_device=beta_dev)
+        with torch.cuda.stream(c.stream):
+            c.ctx.smc_reweight_resample_async(c.theta, c.logl, c.grad, c.beta, args.alpha, c.seed, it, c.bz[it],
+                                              carry=c.hint)
+            c.bz_host[it].copy_(c.bz[it], non_blocking=True)
+            c.ready = torch.cuda.Event()
+            c.ready.record()
+            beta_dev = c.bz[it, 0:1]
+            _, L, _ = c.ctx.mass_matrix(c.theta, 0.0, status=c.mm_status)
+            if metric == "local":
+                L, _, _ = c.ctx.local_metric(c.theta, 0.0, fallback=L, status=False, beta_device=beta_dev)
+            if timed:
+                marks.append((torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)))
+                marks[-1][0].record()
+            out = c.ctx.nuts_step(c.theta, c.logl, c.grad, L, step=args.step, beta=0.0, seed=c.seed, iteration=it,
+                                  max_depth=args.max_depth, precision=precision, work_hint=c.hint,
+                                  beta_device=beta_dev)
+            if timed:
+                marks[-1][1].record()
+            c.nlf += out["n_leapfrog"].sum()
         c.hint = None if args.no_hint else out["n_leapfrog"]
-        ready.synchronize()
-        c.beta = float(c.bz_host[it, 0])
         c.it += 1
         return out
 
-    nlf = torch.zeros((), dtype=torch.int64, device="cuda")
     for _ in range(n_warm):
         for c in runs:
-            nlf += iterate(c)["n_leapfrog"].sum()   # warm up the same device work as the timed steps
-    nlf.zero_()
+            iterate(c)   # warm up the same device work as the timed steps
     torch.cuda.synchronize()
     for c in runs:
+        c.nlf.zero_()
         c.ctx.timing_read(smcgw.KERNEL_NUTS)
         c.ctx.timing_read(smcgw.KERNEL_METRIC)
         if time_kernels:
             c.ctx.timing(smcgw.KERNEL_NUTS, smcgw.KERNEL_METRIC)
     torch.cuda.synchronize()
+    ref = torch.cuda.Event(enable_timing=True)
+    ref.record()
     t0 = time.perf_counter()
     for _ in range(n_steps):
         for k, c in enumerate(runs):
-            out = iterate(c)
-            nlf += out["n_leapfrog"].sum()
+            out = iterate(c, time_kernels)
             if k == 0:
-                stats.append((c.beta, out["depth"]))
+                depths.append(out["depth"])
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     k_ms = k_n = m_ms = m_n = 0
@@ -299,8 +320,21 @@ def run_smc_steps(smcgw, chains, precision, args, n_warm, n_steps, time_kernels,
         a, b = c.ctx.timing_read(smcgw.KERNEL_NUTS)
         e, f = c.ctx.timing_read(smcgw.KERNEL_METRIC)
         k_ms, k_n, m_ms, m_n = k_ms + a, k_n + b, m_ms + e, m_n + f
-    depth_hist = [np.bincount(d.cpu().numpy(), minlength=args.max_depth + 1).tolist() for _, d in stats]
-    return int(nlf.item()), dt, k_ms, k_n, [b for b, _ in stats], depth_hist, m_ms, m_n
+    depth_hist = [np.bincount(d.cpu().numpy(), minlength=args.max_depth + 1).tolist() for d in depths]
+    betas = [float(b) for b in runs[0].bz_host[n_warm:n_warm + n_steps, 0]]
+    busy_ms = union_ms([(ref.elapsed_time(a), ref.elapsed_time(b)) for a, b in marks])
+    return int(sum(int(c.nlf.item()) for c in runs)), dt, k_ms, k_n, betas, depth_hist, m_ms, m_n, busy_ms
+
+
+def union_ms(intervals):
+    """Total length of the union of (start, end) intervals."""
+    total, end = 0.0, -math.inf
+    for a, b in sorted(intervals):
+        if b <= end:
+            continue
+        total += b - max(a, end)
+        end = b
+    return total
 
 
 def main():
@@ -324,6 +358,8 @@ def main():
     ap.add_argument("--priority", type=int, choices=[0, 1], default=1,
                     help="depth-driven wavefront priority in the NUTS kernel")
     ap.add_argument("--waves", type=int, choices=[0, 2, 4, 6, 8], default=0, help="wavefronts per NUTS slot")
+    ap.add_argument("--one-stream", action="store_true",
+                    help="mode smc: enqueue the independent runs on one stream (default: a stream each)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 256 MiB device copy (reference dispatch for memory-traffic counters)")
     args = ap.parse_args()
@@ -351,20 +387,28 @@ def main():
             chains.append((cctx, cx, args.seed + c))
             if c == 0:
                 ctx, x_np = cctx, cx_np
-        evals, dt, k_ms, k_n, betas, hist, _, _ = run_smc_steps(smcgw, chains, prec, args, args.warmup, args.steps,
-                                                                True)
+        evals, dt, k_ms, k_n, betas, hist, _, _, busy_ms = run_smc_steps(smcgw, chains, prec, args, args.warmup,
+                                                                         args.steps, True,
+                                                                         concurrent=not args.one_stream)
+        log(f"nuts busy span {busy_ms:.2f} ms over {args.steps} steps (summed launch durations {k_ms:.2f} ms)")
         for cctx, _, _ in chains[1:]:
             cctx.close()
         value = evals / dt
-        kernel_s = k_ms / 1e3
-        achieved = ops * ev.n * evals / kernel_s / 1e12
+        # The runs' NUTS launches overlap (one run's launch fills the slots another's tail leaves idle), so
+        # each launch's own duration also holds the other launches' work.  The roofline takes the work of all
+        # timed launches over the time during which at least one of them runs; per_launch_frac is the same
+        # work over the summed launch durations.
+        achieved = ops * ev.n * evals / (busy_ms / 1e3) / 1e12
+        per_launch = ops * ev.n * evals / (k_ms / 1e3) / 1e12
         log(f"smc {args.precision}: {evals} evals in {dt:.3f} s -> {value:.4g} evals/s; nuts kernel "
             f"{k_ms / max(k_n, 1):.2f} ms x {k_n}; betas {betas}")
         kname = f"nuts_kernel<3,{'MIXED' if prec == smcgw.MIXED else 'PLAIN_FP64'},GW,{args.waves or 4}>"
         roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TLANEOPS, 3),
                     "unit": "Tlane-op/s", "frac": round(achieved / VALU_PEAK_TLANEOPS, 4),
                     "traffic": measured_traffic(kname) if default_smc_workload(args, P) else None,
-                    "kernel": kname, "kernel_ms": round(k_ms / max(k_n, 1), 3), "ops_per_particle_bin": ops,
+                    "traffic_per": "launch", "kernel": kname, "kernel_ms": round(k_ms / max(k_n, 1), 3),
+                    "launches": k_n, "busy_ms_per_step": round(busy_ms / args.steps, 4),
+                    "per_launch_frac": round(per_launch / VALU_PEAK_TLANEOPS, 4), "ops_per_particle_bin": ops,
                     "evals_in_kernel": evals}
         extra["betas"] = [round(b, 8) for b in betas]
         extra["depth_histograms"] = hist
@@ -374,24 +418,41 @@ def main():
                     f"{P} particles from the prior, alpha={args.alpha}, eps={args.step}, depth<={args.max_depth}, "
                     f"iterations {args.warmup + 1}-{args.warmup + args.steps}; a step runs one iteration of each of "
                     f"{args.chains} independent runs (prior draws and random streams of their own), so the value "
-                    f"does not rest on one run's tree depths")
+                    f"does not rest on one run's tree depths; "
+                    + ("the runs share one stream" if args.one_stream else
+                       "each run enqueues on a HIP stream of its own and their launches overlap"))
+        if not args.no_extra and not args.one_stream:
+            # the same steps with the runs serialised on one stream: what the overlap gains
+            chains1 = []
+            for c in range(args.chains):
+                cctx, _, cx = smc_setup(smcgw, synth, ev, P, seed=7 + c)
+                cctx.set_option(smcgw.OPT_NUTS_PRIORITY, args.priority)
+                cctx.set_option(smcgw.OPT_NUTS_WAVES, args.waves)
+                chains1.append((cctx, cx, args.seed + c))
+            e1, d1, *_ = run_smc_steps(smcgw, chains1, prec, args, args.warmup, args.steps, False)
+            extra["one_stream_evals_per_s"] = round(e1 / d1, 1)
+            for cctx, _, _ in chains1:
+                cctx.close()
         if not args.no_extra:
-            # the plain-FP64 sampler on the same iterations, and the batched-likelihood kernel rates
-            ctx2, _, x2 = smc_setup(smcgw, synth, ev, P)
-            ctx2.set_option(smcgw.OPT_NUTS_PRIORITY, args.priority)
-            ctx2.set_option(smcgw.OPT_NUTS_WAVES, args.waves)
-            e2, d2, _, _, _, _, _, _ = run_smc_steps(smcgw, [(ctx2, x2, args.seed)],
-                                                     smcgw.PLAIN_FP64 if prec == smcgw.MIXED else smcgw.MIXED,
-                                                     args, args.warmup, max(2, args.steps // 2), False)
+            # the other precision in the sampler on the same steps (the same runs, streams and seeds)
+            chains2 = []
+            for c in range(args.chains):
+                cctx, _, cx = smc_setup(smcgw, synth, ev, P, seed=7 + c)
+                cctx.set_option(smcgw.OPT_NUTS_PRIORITY, args.priority)
+                cctx.set_option(smcgw.OPT_NUTS_WAVES, args.waves)
+                chains2.append((cctx, cx, args.seed + c))
+            e2, d2, *_ = run_smc_steps(smcgw, chains2, smcgw.PLAIN_FP64 if prec == smcgw.MIXED else smcgw.MIXED,
+                                       args, args.warmup, args.steps, False, concurrent=not args.one_stream)
             extra["other_precision_in_sampler_evals_per_s"] = round(e2 / d2, 1)
-            ctx2.close()
+            for cctx, _, _ in chains2:
+                cctx.close()
             # the same iterations with the per-particle local metric (beta F + prior precision) in place of
             # the population covariance: sampler rate and the metric kernel's own time
             ctx3, _, x3 = smc_setup(smcgw, synth, ev, P)
             ctx3.set_option(smcgw.OPT_NUTS_PRIORITY, args.priority)
             ctx3.set_option(smcgw.OPT_NUTS_WAVES, args.waves)
-            e3, d3, k3, n3, b3, _, m3, mn3 = run_smc_steps(smcgw, [(ctx3, x3, args.seed)], prec, args, args.warmup,
-                                                           args.steps, True, metric="local")
+            e3, d3, k3, n3, b3, _, m3, mn3, _ = run_smc_steps(smcgw, [(ctx3, x3, args.seed)], prec, args,
+                                                              args.warmup, args.steps, True, metric="local")
             # sample recycling over a pool of 30 iterations of this population size (post-processing)
             pool = torch.randn(30, P, dtype=torch.float64, device="cuda") - 50.0
             bts = [min(1.0, 0.001 * 1.3 ** t) for t in range(29)] + [1.0]
@@ -538,8 +599,8 @@ def main():
             cr.set_target(synth.TARGET_GW, 11)
             cr.set_option(smcgw.OPT_NUTS_WAVES, w_rb)
             xr = torch.tensor(synth.prior_draw(np.random.default_rng(7), P_rb, bounds), device="cuda")
-            e4, d4, k4, n4, _, _, _, _ = run_smc_steps(smcgw, [(cr, xr, args.seed)], prec, args, args.warmup,
-                                                       args.steps, True)
+            e4, d4, k4, n4, *_ = run_smc_steps(smcgw, [(cr, xr, args.seed)], prec, args, args.warmup,
+                                               args.steps, True)
             rbx[f"smc_w{w_rb}"] = {"evals_per_s": round(e4 / d4, 1), "ms_per_step": round(1e3 * d4 / args.steps, 4),
                                    "nuts_kernel_ms": round(k4 / max(n4, 1), 3), "leapfrog_per_step": e4 // args.steps}
             cr.close()

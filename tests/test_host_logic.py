@@ -1,5 +1,6 @@
-"""Host-side behaviour that needs no GPU: the bench's one-GPU contract, the relative-binning edge function's
-argument handling, and argument checks of the sampler entry points (rejected before any device call)."""
+"""Host-side behaviour that needs no GPU: the bench's one-GPU contract and busy-span arithmetic, the
+relative-binning edge function's argument handling, and argument checks of the sampler entry points (rejected
+before any device call)."""
 import ctypes
 import os
 import subprocess
@@ -17,6 +18,16 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode != 0
     assert "one GPU" in r.stderr
     assert r.stdout.strip() == ""
+
+
+def test_bench_busy_span_is_the_union_of_launch_intervals():
+    sys.path.insert(0, ROOT)
+    import bench
+    assert bench.union_ms([]) == 0.0
+    assert bench.union_ms([(0.0, 2.0)]) == 2.0
+    # overlapping, nested, touching and disjoint intervals, in any order
+    assert bench.union_ms([(5.0, 6.0), (0.0, 2.0), (1.0, 3.0), (1.5, 1.8), (3.0, 4.0)]) == 5.0
+    assert bench.union_ms([(0.0, 10.0), (2.0, 3.0), (9.0, 12.0), (20.0, 21.0)]) == 13.0
 
 
 def test_rb_edges_arguments():
