@@ -243,7 +243,7 @@ class _Chain:
         self.mm_status = torch.zeros(1, dtype=torch.int32, device="cuda")
         self.bz = torch.zeros((n_iter, 2), dtype=torch.float64, device="cuda")
         self.bz_host = torch.zeros((n_iter, 2), dtype=torch.float64, pin_memory=True)
-        self.nlf = torch.zeros((), dtype=torch.int64, device="cuda")
+        self.nlf = []   # leapfrog counts of the timed transitions, summed after the timed region
 
 
 def run_smc_steps(smcgw, chains, precision, args, n_warm, n_steps, time_kernels, metric="population",
@@ -262,7 +262,7 @@ def run_smc_steps(smcgw, chains, precision, args, n_warm, n_steps, time_kernels,
     depths = []
     marks = []   # (start, end) events around each timed NUTS transition, for the busy span of overlapping launches
 
-    def iterate(c, timed=False):
+    def iterate(c, timed=False, count=False):
         # the iteration is queued as a whole: beta_t goes from the reweighting to the metric and the NUTS
         # transition through device memory, and reaches the host through an event while the transition runs;
         # the host waits for it only when the chain's next iteration needs beta_t as its lower bracket
@@ -288,8 +288,9 @@ def run_smc_steps(smcgw, chains, precision, args, n_warm, n_steps, time_kernels,
                                   beta_device=beta_dev)
             if timed:
                 marks[-1][1].record()
-            c.nlf += out["n_leapfrog"].sum()
         c.hint = None if args.no_hint else out["n_leapfrog"]
+        if count:
+            c.nlf.append(out["n_leapfrog"])
         c.it += 1
         return out
 
@@ -298,7 +299,6 @@ def run_smc_steps(smcgw, chains, precision, args, n_warm, n_steps, time_kernels,
             iterate(c)   # warm up the same device work as the timed steps
     torch.cuda.synchronize()
     for c in runs:
-        c.nlf.zero_()
         c.ctx.timing_read(smcgw.KERNEL_NUTS)
         c.ctx.timing_read(smcgw.KERNEL_METRIC)
         if time_kernels:
@@ -307,11 +307,16 @@ def run_smc_steps(smcgw, chains, precision, args, n_warm, n_steps, time_kernels,
     ref = torch.cuda.Event(enable_timing=True)
     ref.record()
     t0 = time.perf_counter()
-    for _ in range(n_steps):
+    # A run's next iteration is enqueued as soon as its beta_t has reached the host, whatever the other runs
+    # are doing: waiting on the runs in a fixed order would leave a run's stream idle behind another's wait.
+    left = [n_steps] * len(runs)
+    while any(left):
         for k, c in enumerate(runs):
-            out = iterate(c, time_kernels)
-            if k == 0:
-                depths.append(out["depth"])
+            if left[k] and (c.ready is None or c.ready.query()):
+                out = iterate(c, time_kernels, True)
+                left[k] -= 1
+                if k == 0:
+                    depths.append(out["depth"])
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     k_ms = k_n = m_ms = m_n = 0
@@ -323,7 +328,8 @@ def run_smc_steps(smcgw, chains, precision, args, n_warm, n_steps, time_kernels,
     depth_hist = [np.bincount(d.cpu().numpy(), minlength=args.max_depth + 1).tolist() for d in depths]
     betas = [float(b) for b in runs[0].bz_host[n_warm:n_warm + n_steps, 0]]
     busy_ms = union_ms([(ref.elapsed_time(a), ref.elapsed_time(b)) for a, b in marks])
-    return int(sum(int(c.nlf.item()) for c in runs)), dt, k_ms, k_n, betas, depth_hist, m_ms, m_n, busy_ms
+    evals = sum(int(n.sum().item()) for c in runs for n in c.nlf)
+    return evals, dt, k_ms, k_n, betas, depth_hist, m_ms, m_n, busy_ms
 
 
 def union_ms(intervals):

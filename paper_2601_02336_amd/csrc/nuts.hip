@@ -807,7 +807,9 @@ __global__ __launch_bounds__(WAVES * 64, (WAVES == 1 ? 2 : NUTS_WAVES_PER_SIMD))
 // Start order from a work hint: particles sorted by descending bucket
 // floor(log2(hint)) + 1 (0 for hint <= 0), stable in the particle index.
 // One workgroup; thread t owns the contiguous index chunk [t*ch, (t+1)*ch).
-constexpr int ORDER_THREADS = 1024;
+// Four wavefronts (one per SIMD) fit in the registers of a single NUTS slot,
+// so the kernel starts as soon as one slot of a co-running launch frees.
+constexpr int ORDER_THREADS = 256;
 constexpr int ORDER_BUCKETS = 16;
 
 __device__ __forceinline__ int hint_bucket(int32_t h) { return h <= 0 ? 0 : min(ORDER_BUCKETS - 1, 32 - __clz(h)); }
