@@ -332,6 +332,17 @@ def run_smc_steps(smcgw, chains, precision, args, n_warm, n_steps, time_kernels,
     return evals, dt, k_ms, k_n, betas, depth_hist, m_ms, m_n, busy_ms
 
 
+def runs_rate(smcgw, make_chain, n, precision, args, concurrent, metric="population"):
+    """Evals/s of n independent SMC runs, make_chain(c) -> (ctx, theta, seed), over the bench's steps; each
+    run on a stream of its own when concurrent."""
+    chains = [make_chain(c) for c in range(n)]
+    evals, dt, *_ = run_smc_steps(smcgw, chains, precision, args, args.warmup, args.steps, False, metric=metric,
+                                  concurrent=concurrent)
+    for ctx, _, _ in chains:
+        ctx.close()
+    return evals / dt
+
+
 def union_ms(intervals):
     """Total length of the union of (start, end) intervals."""
     total, end = 0.0, -math.inf
@@ -427,31 +438,22 @@ def main():
                     f"does not rest on one run's tree depths; "
                     + ("the runs share one stream" if args.one_stream else
                        "each run enqueues on a HIP stream of its own and their launches overlap"))
+
+        def full_grid_run(c):   # run c of the headline: its own prior draws and random streams
+            cctx, _, cx = smc_setup(smcgw, synth, ev, P, seed=7 + c)
+            cctx.set_option(smcgw.OPT_NUTS_PRIORITY, args.priority)
+            cctx.set_option(smcgw.OPT_NUTS_WAVES, args.waves)
+            return cctx, cx, args.seed + c
+
         if not args.no_extra and not args.one_stream:
             # the same steps with the runs serialised on one stream: what the overlap gains
-            chains1 = []
-            for c in range(args.chains):
-                cctx, _, cx = smc_setup(smcgw, synth, ev, P, seed=7 + c)
-                cctx.set_option(smcgw.OPT_NUTS_PRIORITY, args.priority)
-                cctx.set_option(smcgw.OPT_NUTS_WAVES, args.waves)
-                chains1.append((cctx, cx, args.seed + c))
-            e1, d1, *_ = run_smc_steps(smcgw, chains1, prec, args, args.warmup, args.steps, False)
-            extra["one_stream_evals_per_s"] = round(e1 / d1, 1)
-            for cctx, _, _ in chains1:
-                cctx.close()
+            extra["one_stream_evals_per_s"] = round(runs_rate(smcgw, full_grid_run, args.chains, prec, args,
+                                                              False), 1)
         if not args.no_extra:
             # the other precision in the sampler on the same steps (the same runs, streams and seeds)
-            chains2 = []
-            for c in range(args.chains):
-                cctx, _, cx = smc_setup(smcgw, synth, ev, P, seed=7 + c)
-                cctx.set_option(smcgw.OPT_NUTS_PRIORITY, args.priority)
-                cctx.set_option(smcgw.OPT_NUTS_WAVES, args.waves)
-                chains2.append((cctx, cx, args.seed + c))
-            e2, d2, *_ = run_smc_steps(smcgw, chains2, smcgw.PLAIN_FP64 if prec == smcgw.MIXED else smcgw.MIXED,
-                                       args, args.warmup, args.steps, False, concurrent=not args.one_stream)
-            extra["other_precision_in_sampler_evals_per_s"] = round(e2 / d2, 1)
-            for cctx, _, _ in chains2:
-                cctx.close()
+            extra["other_precision_in_sampler_evals_per_s"] = round(runs_rate(
+                smcgw, full_grid_run, args.chains, smcgw.PLAIN_FP64 if prec == smcgw.MIXED else smcgw.MIXED, args,
+                not args.one_stream), 1)
             # the same iterations with the per-particle local metric (beta F + prior precision) in place of
             # the population covariance: sampler rate and the metric kernel's own time
             ctx3, _, x3 = smc_setup(smcgw, synth, ev, P)
@@ -472,7 +474,10 @@ def main():
                 "evals_per_s": round(e3 / d3, 1), "ms_per_step": round(1e3 * d3 / args.steps, 4),
                 "leapfrog_per_step": round(e3 / args.steps, 1), "nuts_kernel_ms": round(k3 / max(n3, 1), 3),
                 "metric_kernel_ms": round(m3 / max(mn3, 1), 4), "metric_launches": mn3,
-                "betas": [round(b, 8) for b in b3]}
+                "betas": [round(b, 8) for b in b3],
+                # the headline's three runs with the local metric, overlapping as in the headline
+                "runs_overlapping_evals_per_s": round(runs_rate(smcgw, full_grid_run, args.chains, prec, args,
+                                                                not args.one_stream, metric="local"), 1)}
             ctx3.close()
     elif args.mode == "batch":
         r = run_batch(smcgw, synth, args)
@@ -610,6 +615,18 @@ def main():
             rbx[f"smc_w{w_rb}"] = {"evals_per_s": round(e4 / d4, 1), "ms_per_step": round(1e3 * d4 / args.steps, 4),
                                    "nuts_kernel_ms": round(k4 / max(n4, 1), 3), "leapfrog_per_step": e4 // args.steps}
             cr.close()
+
+        def rb_run(c):   # an independent run on the relative-binning event, four wavefronts per slot
+            cr = smcgw.Context(0)
+            cr.add_event_rb(ev, ev.theta_inj, 0.1)
+            cr.set_prior(bounds)
+            cr.set_target(synth.TARGET_GW, 11)
+            cr.set_option(smcgw.OPT_NUTS_WAVES, 4)
+            xr = torch.tensor(synth.prior_draw(np.random.default_rng(7 + c), P_rb, bounds), device="cuda")
+            return cr, xr, args.seed + c
+
+        rbx["smc_w4_runs_overlapping_evals_per_s"] = round(runs_rate(smcgw, rb_run, args.chains, prec, args,
+                                                                     not args.one_stream), 1)
         extra["relative_binning"] = rbx
 
     if args.copy_probe:
