@@ -11,8 +11,9 @@ Paper context (arXiv:2601.02336): the likelihood is the stationary-Gaussian
 frequency-domain form (Sec. 2, Eq. 2), the experiments use a three-detector
 network, a uniform prior in every source parameter except a log-uniform
 luminosity distance (Sec. 6, "Simulated BBH signals").  The exact PSD, sites
-and priors are not printed there; the readings used here are the ones listed
-in DESIGN.md ("Readings of the paper").
+and priors are not printed there; this module fixes them: S(f) = S0 (f/100 Hz)^2
+with S0 = 1e-46 (doubled for the third detector), three L-shaped sites at
+fixed latitude, longitude and arm azimuth, and the prior boxes below.
 """
 from __future__ import annotations
 
