@@ -178,6 +178,9 @@ def run_batch(smcgw, synth, args):
     _, L, _ = ctx.mass_matrix(torch.tensor(synth.prior_draw(rng, 4096, bounds), device="cuda"), 0.0)
     L = (L * 0.05).contiguous()
     bins = torch.tensor([e.n for e in evs], dtype=torch.int64, device="cuda")[eop.long()]
+    # start order: each particle's known work (leaves of its forced tree times its event's length in units of
+    # the shortest event), longest first, so that the deep trees on long events do not start last
+    hint = None if args.no_hint else ((2 ** md.long() - 1) * bins // min(e.n for e in evs)).to(torch.int32)
 
     tuned = None
     if args.waves == 0:
@@ -188,7 +191,8 @@ def run_batch(smcgw, synth, args):
 
     def step(i, uturn):
         return ctx.nuts_step(x, logl, grad, L, step=0.2, beta=0.005, seed=3, iteration=i, max_depth=10,
-                             max_depth_per_particle=None if uturn else md, uturn=uturn, precision=prec)
+                             max_depth_per_particle=None if uturn else md, uturn=uturn, precision=prec,
+                             work_hint=None if uturn else hint)
 
     div = 0
     for i in range(args.warmup):
