@@ -38,10 +38,10 @@ METRIC = "logL+grad evals/s (3 det, 8k bins, 11 params); log-Z err vs FP64 oracl
 VALU_PEAK_TLANEOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 # Algorithmic VALU lane-operations per (particle, bin) of the MIXED bin loop with 3 detectors
-# (transcendentals counted as 4): phase 8 FP64 FMA; per detector 1 FMA (delay) + 2 (round, subtract)
-# + 1 convert + 4 (sin) + 4 (cos) + 4 (complex product) + 2 (Z) + 2 (q) + 1 (T) + 1 (psibar) = 22;
+# (transcendentals counted as 4): phase 8 FP64 FMA; per detector 1 FMA (delay) + 1 (fractional part)
+# + 1 convert + 4 (sin) + 4 (cos) + 4 (complex product) + 2 (Z) + 2 (q) + 1 (T) + 1 (psibar) = 21;
 # moments 1 convert + 8 FP64 FMA + 1 add; frequency convert 1.
-OPS_PER_PARTICLE_BIN = {"mixed": 8 + 3 * 22 + 10 + 1,
+OPS_PER_PARTICLE_BIN = {"mixed": 8 + 3 * 21 + 10 + 1,
                         # PLAIN_FP64: same algebra, FP64 sincospi counted as the 40 VALU operations of a
                         # range-reduced polynomial pair, no converts.
                         "plain": 8 + 3 * (1 + 2 + 40 + 4 + 2 + 2 + 1 + 1) + 9}

@@ -28,7 +28,7 @@ __device__ __forceinline__ double uniform_d(double v) {
 }
 
 
-// sin(2 pi x), cos(2 pi x) for |x| <= 1/2 on the hardware transcendental unit
+// sin(2 pi x), cos(2 pi x) for 0 <= x < 1 on the hardware transcendental unit
 // (v_sin_f32 / v_cos_f32 take their argument in revolutions).
 __device__ __forceinline__ void sincos_rev_hw(float x, float& s, float& c) {
     s = __builtin_amdgcn_sinf(x);
@@ -214,8 +214,10 @@ struct MixedAcc {
         float psib;
 #pragma unroll
         for (int d = 0; d < NDET; ++d) {
+            // fractional part of the phase in one FP64 instruction (exact); as a float
+            // it is within 2^-25 revolutions of the exact value
             const double phd = fma(x.f, k.tau[d], ph);
-            const float xr = (float)(phd - rint(phd));
+            const float xr = (float)__builtin_amdgcn_fract(phd);
             float sn, cs;
             sincos_rev_hw(xr, sn, cs);
             const float sr = fmaf(x.u[d].x, cs, x.u[d].y * sn);    // u e^{-2 pi i x}
