@@ -25,10 +25,12 @@ def _ctx(smc, ev, idx=None):
     return c
 
 
-def _compare(smc, ev, idx, P, seed, precisions=("plain", "mixed")):
+def _compare(smc, ev, idx, P, seed, precisions=("plain", "mixed"), x=None):
     full = synth.gw_prior_for(ev)
     b = [full[i] for i in idx]
-    x = synth.prior_draw(np.random.default_rng(seed), P, b)
+    if x is None:
+        x = synth.prior_draw(np.random.default_rng(seed), P, b)
+    P = len(x)
     tgt = O.gw_target(ev, param_index=idx)
     ll_ref, g_ref = O.loglike_grad(tgt, x)
     c = _ctx(smc, ev, idx)
@@ -54,6 +56,21 @@ def test_parity_one_detector_four_params(smc):
 def test_parity_three_detectors_eleven_params(smc):
     """3 detectors, 8033 bins (ragged tail of the 512-bin padding), 11 params."""
     _compare(smc, event(synth.SPEC_8S), list(range(11)), 45, 2)
+
+
+def test_parity_at_prior_corners(smc):
+    """The per-detector phase reduction (fractional part of the phase in cycles) at the extremes of the
+    phase: chirp mass, spins, coalescence time and phase at the ends of their prior ranges (64 corners,
+    the other parameters drawn from the prior), 3 detectors, 8033 bins."""
+    ev = event(synth.SPEC_8S)
+    full = synth.gw_prior_for(ev)
+    x = synth.prior_draw(np.random.default_rng(5), 64, full)
+    corners = [0, 1, 2, 3, 9, 10]   # Mc, q, chi1, chi2, t_c, phi_c
+    for i in range(64):
+        for k, j in enumerate(corners):
+            lo, hi = full[j].lo, full[j].hi
+            x[i, j] = hi - 1e-9 * (hi - lo) if (i >> k) & 1 else lo
+    _compare(smc, ev, list(range(11)), 64, 0, x=x)
 
 
 def test_parity_full_size_sampled(smc):
