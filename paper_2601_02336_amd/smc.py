@@ -7,7 +7,8 @@ multinomially, refresh the mass matrix (Sec. 5: the population covariance,
 or per particle the local metric beta F + prior precision) and mutate every particle with one NUTS transition at beta_t
 (Sec. 4).  The run stops after the mutation at beta = 1.  All arithmetic runs
 in libsmcgw; this loop only sequences the calls and reads beta and the
-evidence increment back once per iteration.
+evidence increment back once per iteration.  Independent runs can share the
+device through run_smc_concurrent, each on a HIP stream of its own.
 """
 from __future__ import annotations
 
@@ -64,12 +65,60 @@ def run_smc(ctx: "smcgw.Context", theta0: torch.Tensor, cfg: SmcConfig) -> SmcRe
     increment to device memory, the mass matrix (or the local metric) and the NUTS transition read beta_t
     from there, and the host reads beta_t back through an event while the transition runs, to decide whether
     to queue the next iteration.  Diagnostics stay on the device until the run ends."""
-    if cfg.metric not in ("population", "local"):
-        raise ValueError(f"unknown metric {cfg.metric!r}")
+    _check_config(cfg)
     if cfg.variant == "persistent":
         return _run_persistent(ctx, theta0, cfg)
-    if cfg.variant != "standard":
+    steps = _standard_iterations(ctx, theta0, cfg)
+    while True:
+        try:
+            next(steps)
+        except StopIteration as done:
+            return done.value
+
+
+def run_smc_concurrent(runs) -> List[SmcResult]:
+    """Independent standard runs [(ctx, theta0, cfg), ...] (one context each) overlapped on one device.
+
+    Every run enqueues on a HIP stream of its own (default priority).  A NUTS launch leaves slots idle while
+    its longest trees finish; the other runs' launches take them.  The host queues a run's next iteration as
+    soon as that run's beta_t has arrived.  Each result is bitwise the one run_smc gives for the same run."""
+    gens, streams = [], []
+    caller = torch.cuda.current_stream()
+    for ctx, theta0, cfg in runs:
+        _check_config(cfg)
+        if cfg.variant != "standard":
+            raise ValueError("run_smc_concurrent takes standard runs only")
+        s = torch.cuda.Stream(device=theta0.device)
+        s.wait_stream(caller)   # theta0 and the contexts' set-up were queued on the caller's stream
+        streams.append(s)
+        gens.append(_standard_iterations(ctx, theta0, cfg))
+    results: List[Optional[SmcResult]] = [None] * len(gens)
+    waiting: List[Optional[torch.cuda.Event]] = [None] * len(gens)
+    active = [True] * len(gens)
+    while any(active):
+        for k, g in enumerate(gens):
+            if not active[k] or (waiting[k] is not None and not waiting[k].query()):
+                continue
+            with torch.cuda.stream(streams[k]):
+                try:
+                    waiting[k] = next(g)
+                except StopIteration as done:
+                    results[k] = done.value
+                    active[k] = False
+    torch.cuda.synchronize()
+    return results
+
+
+def _check_config(cfg: SmcConfig) -> None:
+    if cfg.metric not in ("population", "local"):
+        raise ValueError(f"unknown metric {cfg.metric!r}")
+    if cfg.variant not in ("standard", "persistent"):
         raise ValueError(f"unknown variant {cfg.variant!r}")
+
+
+def _standard_iterations(ctx: "smcgw.Context", theta0: torch.Tensor, cfg: SmcConfig):
+    """The standard run as a generator: it queues one iteration, yields the event that brings beta_t to the
+    host, and continues when resumed; its return value is the SmcResult."""
     dev = theta0.device
     theta = theta0.clone().contiguous()
     logl, grad = ctx.target_loglike_grad(theta, precision=cfg.precision)
@@ -108,6 +157,7 @@ def run_smc(ctx: "smcgw.Context", theta0: torch.Tensor, cfg: SmcConfig) -> SmcRe
         nlf_d.append(out["n_leapfrog"].sum())
         depth_d.append(out["depth"].double().mean())
         div_d.append(out["divergent"].sum())
+        yield ready
         ready.synchronize()   # beta_t is on the host; the transition may still run
         b, dz = float(bz_host[it, 0]), float(bz_host[it, 1])
         if not (b > beta) and beta < 1.0:
@@ -127,7 +177,7 @@ def run_smc(ctx: "smcgw.Context", theta0: torch.Tensor, cfg: SmcConfig) -> SmcRe
             running.append(acc)
         _, kept, ress = ctx.recycle(torch.stack(pool_ll), betas, running, cfg.seed)
         recycled = torch.cat(pool_x)[kept.long()]
-    torch.cuda.synchronize()
+    torch.cuda.current_stream(dev).synchronize()   # this run's stream only: concurrent runs keep going
     nlf = [int(x.item()) for x in nlf_d]
     depths = [float(x.item()) for x in depth_d]
     divs = [int(x.item()) for x in div_d]
