@@ -474,6 +474,28 @@ def main():
             for _ in range(5):
                 _, kept_r, _ = ctx3.recycle(pool, bts, lzs, 1)
             extra["recycle_ms_30x%d" % P] = round(1e3 * (time.perf_counter() - t_r) / 5, 4)
+            # every slot busy: 768 particles (three 4-wavefront slots on each of the 256 CUs), forced depth-7
+            # trees with the U-turn check off, so no slot idles until the launch ends
+            P_full, d_full = 768, 7
+            x_full = torch.tensor(synth.prior_draw(np.random.default_rng(1), P_full, synth.gw_prior_for(ev)),
+                                  device="cuda")
+            l_full, g_full = ctx3.target_loglike_grad(x_full, precision=prec)
+            md_full = torch.full((P_full,), d_full, dtype=torch.int32, device="cuda")
+            L_full = torch.eye(11, dtype=torch.float64, device="cuda") * 0.01
+            ms_full = []
+            for i in range(3):
+                xx, ll, gg = x_full.clone(), l_full.clone(), g_full.clone()
+                torch.cuda.synchronize()
+                ctx3.timing_read(smcgw.KERNEL_NUTS)
+                ctx3.timing(smcgw.KERNEL_NUTS)
+                ctx3.nuts_step(xx, ll, gg, L_full, step=0.1, beta=0.01, seed=1, iteration=i, max_depth=d_full,
+                               uturn=False, max_depth_per_particle=md_full, precision=prec)
+                ctx3.timing()
+                ms_full.append(ctx3.timing_read(smcgw.KERNEL_NUTS)[0])
+            rate_full = P_full * (2 ** d_full - 1) / (min(ms_full) / 1e3)
+            extra["full_load_nuts"] = {"evals_per_s": round(rate_full, 1), "kernel_ms": round(min(ms_full), 4),
+                                       "frac": round(ops * ev.n * rate_full / 1e12 / VALU_PEAK_TLANEOPS, 4),
+                                       "particles": P_full, "forced_depth": d_full}
             extra["local_metric_sampler"] = {
                 "evals_per_s": round(e3 / d3, 1), "ms_per_step": round(1e3 * d3 / args.steps, 4),
                 "leapfrog_per_step": round(e3 / args.steps, 1), "nuts_kernel_ms": round(k3 / max(n3, 1), 3),
