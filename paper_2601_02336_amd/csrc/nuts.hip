@@ -66,6 +66,8 @@ struct NutsShared {
     double L[MAXDIM * MAXDIM];
     double LT[MAXDIM * MAXDIM];                  // transpose of L
     double Minv[MAXDIM * MAXDIM];
+    double Linv[MAXDIM * MAXDIM];                // L^{-1}
+    double M[MAXDIM * MAXDIM];                   // the mass matrix itself, (L L^T)^{-1} (reflective walls)
     double vec[MAXDIM], red[2][MAXDIM];          // cross-lane exchange of wavefront 0
     double pred[MAXDIM];                         // cross-lane exchange of the auxiliary wavefront
     ExtAngles ang;                               // extrinsic transcendentals of the leaf in flight
@@ -170,18 +172,45 @@ __device__ __forceinline__ double log_prior_lane(const NutsShared& S, int k, dou
     }
 }
 
-// Reflect (flipping this momentum component) or wrap into the box.
-__device__ __forceinline__ void boundary_lane(const NutsShared& S, int k, double& x, double& r) {
+// Fold this lane's coordinate back into the box: reflect about the wall it
+// crossed (repeated until inside) or wrap a periodic one.  Returns true when
+// the coordinate was reflected an odd number of times, i.e. its velocity
+// component must be reversed (see reverse_velocities).
+__device__ __forceinline__ bool boundary_lane(const NutsShared& S, int k, double& x) {
     const double lo = S.plo[k], hi = S.phi[k];
+    bool odd = false;
     if (S.pbnd[k] == SMCGW_BND_REFLECT) {
         for (int it = 0; it < 64 && (x < lo || x > hi); ++it) {
             x = (x > hi) ? 2.0 * hi - x : 2.0 * lo - x;
-            r = -r;
+            odd = !odd;
         }
     } else if (S.pbnd[k] == SMCGW_BND_PERIODIC) {
         const double w = hi - lo;
         for (int it = 0; it < 64 && (x < lo || x >= hi); ++it) x = (x >= hi) ? x - w : x + w;
     }
+    return odd;
+}
+
+// (M v) for this lane's coordinate, M the mass matrix.
+__device__ __forceinline__ double m_apply(NutsShared& S, int D, int lane, double v) {
+    if (lane < MAXDIM) S.vec[lane] = (lane < D) ? v : 0.0;
+    __builtin_amdgcn_wave_barrier();
+    const int row = lane < D ? lane : 0;
+    double acc = 0.0;
+#pragma unroll
+    for (int m = 0; m < MAXDIM; ++m) acc = fma(S.M[row * MAXDIM + m], S.vec[m], acc);
+    __builtin_amdgcn_wave_barrier();
+    return lane < D ? acc : 0.0;
+}
+
+// Reflective walls (Sec. 5, Eqs. 15-16) for a general metric: a coordinate
+// folded back reverses its velocity dx_k/dt = v_k = (M^{-1} r)_k and keeps the
+// other velocity components, r -> r - 2 v_k M e_k (summed over the folded
+// coordinates).  With a diagonal M this is r_k -> -r_k; with a dense M it is
+// what keeps the step reversible and volume preserving.  Called by the whole
+// wavefront only when some lane folded.
+__device__ __forceinline__ double reverse_velocities(NutsShared& S, int D, int lane, bool odd, double v, double r) {
+    return r + m_apply(S, D, lane, odd ? -2.0 * v : 0.0);
 }
 
 // Analytic likelihoods (one coordinate per lane of wavefront 0).
@@ -367,7 +396,8 @@ __device__ __noinline__ int advance(NutsShared& S, NutsState& T, const NutsArgs&
     double r = dl ? fma(0.5 * eps, gs, rs) : 0.0;
     const double v = minv_apply(S, D, lane, r);
     double x = dl ? fma(eps, v, xs) : 0.0;
-    if (dl) boundary_lane(S, lane, x, r);
+    const bool odd = dl ? boundary_lane(S, lane, x) : false;
+    if (__ballot(odd) != 0) r = reverse_velocities(S, D, lane, odd, v, r);
     __builtin_amdgcn_wave_barrier();
     if (dl) { T.x[lane] = x; T.r[lane] = r; }
     if (lane == 0) T.eps = eps;
@@ -686,13 +716,36 @@ __device__ __forceinline__ void load_factor(NutsShared& S, const double* chol, i
     }
 }
 
-__device__ __forceinline__ void derive_metric(NutsShared& S, int D, int tid) {
+// M^{-1} = L L^T, L^T, and the mass matrix M = L^{-T} L^{-1} (for the
+// reflective walls) from the factor in LDS.  Every thread of the workgroup
+// calls it (it holds a barrier).
+__device__ __noinline__ void derive_metric(NutsShared& S, int D, int tid) {
     for (int i = tid; i < MAXDIM * MAXDIM; i += blockDim.x) {
         const int r = i / MAXDIM, c = i % MAXDIM;
         double s = 0.0;
         for (int m = 0; m < D; ++m) s = fma(S.L[r * MAXDIM + m], S.L[c * MAXDIM + m], s);
         S.Minv[i] = s;
         S.LT[i] = S.L[c * MAXDIM + r];
+    }
+    // column c of L^{-1} by forward substitution, one thread per column
+    if (tid < MAXDIM) {
+        const int c = tid;
+        for (int r = 0; r < MAXDIM; ++r) {
+            double y = 0.0;
+            if (c < D && r < D && r >= c) {
+                double s = (r == c) ? 1.0 : 0.0;
+                for (int k = c; k < r; ++k) s = fma(-S.L[r * MAXDIM + k], S.Linv[k * MAXDIM + c], s);
+                y = s / S.L[r * MAXDIM + r];
+            }
+            S.Linv[r * MAXDIM + c] = y;
+        }
+    }
+    __syncthreads();
+    for (int i = tid; i < MAXDIM * MAXDIM; i += blockDim.x) {
+        const int r = i / MAXDIM, c = i % MAXDIM;
+        double s = 0.0;
+        for (int k = 0; k < D; ++k) s = fma(S.Linv[k * MAXDIM + r], S.Linv[k * MAXDIM + c], s);
+        S.M[i] = s;
     }
 }
 

@@ -87,14 +87,18 @@ def test_bimodal_eleven_dims_parity(smc):
     assert ok.mean() >= 0.99
 
 
-def test_boundaries_parity(smc):
-    """Reflective and periodic coordinates with long trajectories that cross them."""
+@pytest.mark.parametrize("dense", [False, True])
+def test_boundaries_parity(smc, dense):
+    """Reflective and periodic coordinates with long trajectories that cross them (Sec. 5, Eqs. 15-18).
+    With a dense metric a fold reverses the crossing coordinate's velocity (M^{-1} r)_k, which changes
+    every momentum component."""
     D = 3
     b = [Bound(-1.0, 1.0, synth.BND_REFLECT, synth.PRIOR_UNIFORM),
          Bound(0.0, 2 * math.pi, synth.BND_PERIODIC, synth.PRIOR_UNIFORM),
          Bound(-1e300, 1e300, synth.BND_NONE, synth.PRIOR_FLAT)]
     x0 = np.random.default_rng(2).uniform([-1, 0, -2], [1, 2 * math.pi, 2], size=(256, D))
-    got, ref, ok = _analytic_case(smc, synth.TARGET_GAUSS, D, b, None, np.diag([1.5, 2.0, 1.0]), step=0.9, x0=x0)
+    L = np.array([[1.5, 0.0, 0.0], [0.8, 1.8, 0.0], [-0.6, 0.4, 1.0]]) if dense else np.diag([1.5, 2.0, 1.0])
+    got, ref, ok = _analytic_case(smc, synth.TARGET_GAUSS, D, b, None, L, step=0.9, x0=x0)
     assert ok.mean() >= 0.99
     assert np.all(got["x"][:, 0] >= -1) and np.all(got["x"][:, 0] <= 1)
     assert np.all(got["x"][:, 1] >= 0) and np.all(got["x"][:, 1] < 2 * math.pi)

@@ -70,15 +70,23 @@ def test_leapfrog_energy_error_second_order():
     assert errs[1] / errs[2] == pytest.approx(4.0, rel=0.3)
 
 
-def test_leapfrog_reversible_through_boundaries():
-    """L steps, flip r, L steps returns to the start, across reflections and wraps."""
+@pytest.mark.parametrize("dense", [False, True])
+def test_leapfrog_reversible_through_boundaries(dense):
+    """L steps, flip r, L steps returns to the start, across reflections and wraps (Eqs. 11-13, 15-18).
+
+    With a dense metric a fold must reverse the crossing coordinate's velocity (M^{-1} r)_k; flipping only
+    the momentum component r_k misses the start point by O(1) here."""
     D = 3
     b = [Bound(-1.0, 1.0, synth.BND_REFLECT, synth.PRIOR_FLAT),
          Bound(-1.0, 1.0, synth.BND_PERIODIC, synth.PRIOR_FLAT),
-         Bound(-1e300, 1e300, synth.BND_NONE, synth.PRIOR_FLAT)]
+         Bound(-1.0, 1.0, synth.BND_REFLECT, synth.PRIOR_FLAT)]
     t = std_normal_target(D, b)
     rng = np.random.default_rng(4)
-    L = np.diag([1.0, 0.8, 1.2])
+    if dense:
+        A = np.array([[1.0, 0.0, 0.0], [0.7, 0.8, 0.0], [-0.6, 0.5, 0.9]])
+        L = A
+    else:
+        L = np.diag([1.0, 0.8, 1.2])
     crossings = 0
     for _ in range(20):
         x0 = rng.uniform(-0.9, 0.9, D)
@@ -87,8 +95,35 @@ def test_leapfrog_reversible_through_boundaries():
         crossings += int(np.any(np.abs(x0 + 0.3 * 12 * (L @ L.T) @ r0) > 1))
         x2, r2, _ = O.leapfrog(t, x1, -r1, L, 0.3, 12)
         np.testing.assert_allclose(x2, x0, atol=1e-12)
-        np.testing.assert_allclose(-r2, r0, atol=1e-12)
+        np.testing.assert_allclose(-r2, r0, atol=1e-11)
     assert crossings > 5
+
+
+def test_reflection_reverses_velocity_component():
+    """A fold reverses dx_k/dt = (M^{-1} r)_k of the crossing coordinate and keeps every other velocity
+    component; the map is an involution and, with M^{-1} diagonal, it is r_k -> -r_k (Eqs. 15-16)."""
+    b = [Bound(0.0, 1.0, synth.BND_REFLECT, synth.PRIOR_UNIFORM),
+         Bound(-2.0, 2.0, synth.BND_REFLECT, synth.PRIOR_UNIFORM),
+         Bound(0.0, 2 * math.pi, synth.BND_PERIODIC, synth.PRIOR_UNIFORM)]
+    t = O.Target(synth.TARGET_GAUSS, 3, b)
+    L = np.array([[0.9, 0.0, 0.0], [0.4, 1.1, 0.0], [-0.3, 0.6, 0.7]])
+    Minv = L @ L.T
+    x = np.array([[1.25, 0.3, 1.0], [0.4, -2.5, 8.0], [-0.1, 2.2, 1.0], [3.4, 0.0, 0.5]])
+    r = np.array([[0.5, -1.0, 0.2], [1.5, 0.3, -0.7], [-0.4, 0.9, 1.1], [0.6, 0.6, 0.6]])
+    y, s = O.apply_boundaries(t, x, r, L)
+    v0, v1 = r @ Minv, s @ Minv   # velocities before and after (Minv symmetric)
+    folds = np.array([[1, 0], [0, 1], [1, 1], [3, 0]])   # reflections of coordinates 0 and 1 (3.4 folds thrice)
+    for i in range(4):
+        sign = np.array([(-1.0) ** folds[i, 0], (-1.0) ** folds[i, 1], 1.0])
+        np.testing.assert_allclose(v1[i], sign * v0[i], rtol=1e-13, atol=1e-14)
+    # folding back from the reflected point with the reversed velocity is the identity
+    z, q = O.apply_boundaries(t, np.array([[1.0 + (1.0 - y[0, 0]), 0.3, 1.0]]), s[:1], L)
+    np.testing.assert_allclose(z[0, 0], y[0, 0], rtol=1e-15)
+    np.testing.assert_allclose(q[0], r[0], rtol=1e-13)
+    # a diagonal metric flips the momentum component itself
+    _, sd = O.apply_boundaries(t, x, r, np.diag([0.9, 1.1, 0.7]))
+    np.testing.assert_allclose(sd[:, :2], r[:, :2] * (-1.0) ** folds, rtol=1e-14)
+    np.testing.assert_allclose(sd[:, 2], r[:, 2])
 
 
 def test_boundary_maps():
