@@ -26,9 +26,11 @@
 //     PRD 80, 084043 (2009), Eq. (3.18) and Table I;
 //   aligned-spin spin-orbit / spin-spin terms as collected in Khan et al.,
 //     PRD 93, 044007 (2016), Appendix B (from Bohe, Marsat, Blanchet 2013 and
-//     Mikoczi, Vasuth, Gergely 2005).  The 3PN spin-spin terms are omitted.
-// Parity unpinned: the 2.5PN-3.5PN coefficients (phi_5 .. phi_7) are checked
-// only by hand against the cited equations; lower orders are pinned by tests.
+//     Mikoczi, Vasuth, Gergely 2005).  The 3PN and 3.5PN spin-spin terms are
+//     omitted.  Every coefficient kept is pinned by an independent derivation:
+//     energy balance with the published binding energy and flux (non-spinning
+//     and spin-orbit, any mass ratio) and the Kerr test-mass limit (the 2PN
+//     self-spin term).
 //
 // Antenna patterns and arrival-time delays are the textbook long-wavelength
 // forms (e.g. Anderson, Brady, Creighton, Flanagan, PRD 63, 042003 (2001),
