@@ -103,7 +103,75 @@ typedef struct {
     const double *beta_device;   /* non-NULL: beta is read from this device double when the
                                     kernel starts (e.g. written by
                                     smcgw_smc_reweight_resample_async), and `beta` is ignored */
+    const double *state_device;  /* non-NULL: the particles are independent SMC runs of run_size
+                                    consecutive particles each, run r with the device state
+                                    state_device + r SMCGW_STATE_SIZE (see smcgw_smc_iteration):
+                                    its temperature, iteration index (the Philox counter) and done
+                                    flag replace beta / beta_device / iteration, run r draws with
+                                    key seed + r and its particles' counters count from 0 within
+                                    the run, a done run's particles are left untouched, and a shared
+                                    factor (chol_per_particle = 0) is one [D][D] factor per run */
+    int32_t run_size;            /* particles per run when state_device is set (P a multiple of it) */
+    int32_t reserved2;           /* must be 0 */
 } smcgw_nuts_params;
+
+/* ------------------------------------------------------------ SMC state
+ * Device-resident state of one SMC run (SMCGW_STATE_SIZE doubles), read and
+ * updated on the device by smcgw_smc_iteration, so the host never touches
+ * the temperature or the evidence:
+ *   [SMCGW_ST_BETA]   beta_t, the temperature reached (0 before the first iteration)
+ *   [SMCGW_ST_LOGZ]   log Z_t = sum of the increments so far (Sec. 3.1, Eq. 8), FP64
+ *   [SMCGW_ST_DLOGZ]  the last increment log(Z_t / Z_{t-1}) (Sec. 3.1, Eq. 7)
+ *   [SMCGW_ST_ITER]   index t of the last iteration (keys its resampling and transition streams)
+ *   [SMCGW_ST_NEXT]   index of the next iteration (0 at the start)
+ *   [SMCGW_ST_DONE]   1 once the run has ended: its last iteration mutated at beta = 1, or the
+ *                     ladder stalled; every later iteration leaves the run untouched
+ *   [SMCGW_ST_STALL]  1 when beta could not advance (the run ended without reaching 1)
+ * A fresh run's state is all zeros.  Per-iteration record (SMCGW_HIST_SIZE
+ * doubles per row, row t written by iteration t when t < history_cap):
+ *   beta_t, log Z_t, log(Z_t / Z_{t-1}), leapfrog steps of the transition,
+ *   summed tree depth, divergent transitions, 1 if the population covariance
+ *   fell back to its diagonal, particles whose local metric fell back. */
+#define SMCGW_STATE_SIZE 8
+enum { SMCGW_ST_BETA = 0, SMCGW_ST_LOGZ = 1, SMCGW_ST_DLOGZ = 2, SMCGW_ST_ITER = 3, SMCGW_ST_NEXT = 4,
+       SMCGW_ST_DONE = 5, SMCGW_ST_STALL = 6 };
+#define SMCGW_HIST_SIZE 8
+enum { SMCGW_H_BETA = 0, SMCGW_H_LOGZ = 1, SMCGW_H_DLOGZ = 2, SMCGW_H_LEAPFROG = 3, SMCGW_H_DEPTH = 4,
+       SMCGW_H_DIVERGENT = 5, SMCGW_H_MM_FALLBACK = 6, SMCGW_H_METRIC_FALLBACKS = 7 };
+#define SMCGW_MAX_RUNS 64
+
+/* One SMC iteration of n_runs independent runs (Sec. 3 and Sec. 4): run r
+ * owns particles [r P, (r+1) P) of the population arrays below (all device
+ * arrays, sized for n_runs * P particles), its state state[r] and its record
+ * history[r][history_cap]. */
+typedef struct {
+    int32_t n_runs, P, D;           /* runs, particles per run, sampled coordinates */
+    int32_t precision;              /* SMCGW_PLAIN_FP64 or SMCGW_MIXED (likelihood inside NUTS) */
+    double *theta, *logl, *grad;    /* [n_runs P][D], [n_runs P], [n_runs P][D]: population, updated in place */
+    int32_t *ancestors;             /* [n_runs P]: indices within each run after resampling */
+    int32_t *n_leapfrog;            /* [n_runs P]: leapfrog steps of each particle's last transition; resampled
+                                       with the particles and used as the start-order hint of the next
+                                       transition (zeros before the first iteration) */
+    int32_t *depth;                 /* [n_runs P] doublings of the last transition */
+    uint8_t *divergent;             /* [n_runs P] */
+    double *accept_stat;            /* [n_runs P] (may be NULL) */
+    double *inv_mass, *chol;        /* [n_runs][D][D]: population covariance and its factor, per run */
+    int32_t *mm_status;             /* [n_runs]: 1 when the covariance fell back to its diagonal */
+    double *chol_pp;                /* [n_runs P][D][D] per-particle local metric factors, or NULL: the
+                                       population metric */
+    int32_t *metric_status;         /* [n_runs P] (local metric only) */
+    double *state;                  /* [n_runs][SMCGW_STATE_SIZE] */
+    double *history;                /* [n_runs][history_cap][SMCGW_HIST_SIZE] (may be NULL) */
+    int32_t history_cap;
+    int32_t max_depth;              /* NUTS depth limit */
+    double alpha;                   /* ESS target fraction (Sec. 3, Eq. 6) */
+    double shrink;                  /* diagonal shrinkage of the covariance */
+    double step;                    /* leapfrog step */
+    double max_delta_h;             /* divergence threshold on H - H0 */
+    uint64_t seed;                  /* run r uses Philox key seed + r */
+    int32_t uturn;                  /* 1: NUTS stops at a U-turn */
+    int32_t reserved;               /* must be 0 */
+} smcgw_smc_iter_desc;
 
 /* Message for a status code (static storage). */
 const char *smcgw_status_string(int status);
@@ -284,6 +352,39 @@ int smcgw_smc_reweight_resample(smcgw_ctx *ctx, int P, int D, double beta_prev, 
 int smcgw_smc_reweight_resample_async(smcgw_ctx *ctx, int P, int D, double beta_prev, double alpha, uint64_t seed,
                                       uint64_t iteration, double *theta, double *logl, double *grad, int32_t *carry,
                                       int32_t *ancestors, double *out_device);
+
+/* One whole SMC iteration of every run in desc, queued on the context's
+ * stream without a host synchronisation (Sec. 3, Eqs. 3-8; Sec. 4; Sec. 5):
+ *   1. per run: reweighting from beta_{t-1} = state[BETA] to beta_t by the
+ *      bisection of smcgw_smc_reweight_resample, the evidence increment and
+ *      the running log Z accumulated in FP64 in the state, multinomial
+ *      resampling with the uniforms of iteration t = state[NEXT] (key
+ *      seed + r) and the gather of theta, logl, grad and n_leapfrog;
+ *   2. per run: the population covariance, its shrinkage and factor;
+ *   3. with chol_pp: every particle's local metric at its run's beta_t, the
+ *      run's population factor standing in where it is not positive definite;
+ *   4. one persistent NUTS launch over all n_runs P particles at their runs'
+ *      temperatures (iteration t, key seed + r), the longest predicted trees
+ *      first;
+ *   5. per run: the record row t (history).
+ * A run whose state says done is left untouched, so the call may be queued
+ * past the end of every run; the host reads state[DONE] when it needs to
+ * know (e.g. through an event).  Allocates its scratch on the first call for
+ * a shape (so a graph of it, smcgw_smc_graph_create, captures no
+ * allocation).  Runs are independent: run r's results are bitwise those of
+ * a one-run call with seed + r on its particles. */
+int smcgw_smc_iteration(smcgw_ctx *ctx, const smcgw_smc_iter_desc *desc);
+
+/* A HIP graph of smcgw_smc_iteration(ctx, desc), captured once on a private
+ * stream (every pointer in desc is baked in) and replayed on the context's
+ * stream.  Replays read the temperature, iteration index and done flag from
+ * the device state, so one graph serves every iteration of the runs; replays
+ * after every run is done change nothing.  *graph receives the handle. */
+typedef struct smcgw_graph smcgw_graph;
+int smcgw_smc_graph_create(smcgw_ctx *ctx, const smcgw_smc_iter_desc *desc, smcgw_graph **graph);
+/* Replays the graph `count` times on the context's current stream (asynchronous). */
+int smcgw_graph_launch(smcgw_graph *graph, int count);
+int smcgw_graph_destroy(smcgw_graph *graph);
 
 /* Persistent sampling (Karamanis & Seljak 2024, arXiv:2407.20722; the SMC
  * variant the paper names as future work, Sec. 7): every earlier population

@@ -88,6 +88,21 @@ struct TimedLaunch {
     ~TimedLaunch();
 };
 int ctx_reserve(smcgw_ctx* c, int P);
+// SMC pieces queued by smcgw_smc_iteration (smc.hip, metric.hip, nuts.hip).
+void* sampler_scratch(smcgw_ctx* c, size_t bytes);
+size_t reweight_scratch_bytes(int n_runs, int P, int D);
+int queue_reweight_resample(smcgw_ctx* c, int n_runs, int P, int D, double beta_prev, double alpha, uint64_t seed,
+                            uint64_t iteration, double* theta, double* logl, double* grad, int32_t* carry,
+                            int32_t* ancestors, double* st, double* hist, int hist_cap, double** out_dev);
+int mm_reserve(smcgw_ctx* c, int n_runs, int P);
+int queue_mass_matrix_runs(smcgw_ctx* c, int n_runs, int P, int D, const double* theta, double shrink, double* inv,
+                           double* chol, int32_t* status, const double* st);
+int queue_local_metric(smcgw_ctx* c, int P, int D, const double* theta, const double* st, int run_size,
+                       const double* fallback_runs, double* chol, int32_t* status);
+int queue_record(smcgw_ctx* c, int n_runs, int P, const int32_t* nlf, const int32_t* depth, const uint8_t* div,
+                 const int32_t* mm_status, const int32_t* metric_status, const double* st, double* hist,
+                 int hist_cap);
+int nuts_reserve(smcgw_ctx* c, int P, bool hint);
 int ctx_loglike(smcgw_ctx* c, int P, const int32_t* ev_of_p, const double* theta, double* logl, double* grad,
                 int precision);
 }  // namespace smcgw

@@ -100,13 +100,18 @@ __global__ __launch_bounds__(MET_THREADS) void local_metric_kernel(const DevEven
                                                                   double beta_host, const double* __restrict__ beta_dev,
                                                                   const double* __restrict__ fallback,
                                                                   double* __restrict__ chol, double* __restrict__ fisher,
-                                                                  int32_t* __restrict__ status) {
+                                                                  int32_t* __restrict__ status,
+                                                                  const double* __restrict__ st, int run_size) {
     __shared__ MetricShared S;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int p = blockIdx.x;
     const int D = pm.dim;
+    // independent runs: particle p belongs to run p / run_size, whose state gives beta; a finished run is skipped
+    const int run = st ? p / run_size : 0;
+    if (st && st[(size_t)run * SMCGW_STATE_SIZE + SMCGW_ST_DONE] != 0.0) return;
+    if (st && fallback) fallback += (size_t)run * D * D;
     const DevEvent& ev = evs[event_index(ev_of_p, p, n_events)];
     const int n_det = ev.n_det;
 
@@ -184,7 +189,7 @@ __global__ __launch_bounds__(MET_THREADS) void local_metric_kernel(const DevEven
     }
     __syncthreads();
 
-    const double beta = beta_dev ? *beta_dev : beta_host;
+    const double beta = st ? st[(size_t)run * SMCGW_STATE_SIZE + SMCGW_ST_BETA] : beta_dev ? *beta_dev : beta_host;
     // J M J over the sampled coordinates (rows and columns in reverse order)
     for (int i = tid; i < MAXDIM * MAXDIM; i += MET_THREADS) {
         const int a = i / MAXDIM, b = i % MAXDIM;
@@ -253,6 +258,22 @@ static PrecDesc prior_precision(const PriorDesc& pr) {
 
 }  // namespace smcgw
 
+namespace smcgw {
+// Local metric of n_runs * run_size particles at their runs' temperatures
+// (state st), the run's own population factor as the fallback.
+int queue_local_metric(smcgw_ctx* c, int P, int D, const double* theta, const double* st, int run_size,
+                       const double* fallback_runs, double* chol, int32_t* status) {
+    if (c->events.empty() || !c->prior_set || c->target.kind != SMCGW_TARGET_GW) return SMCGW_ERR_NOT_INIT;
+    if (c->prior.dim != D || c->pmap.dim != D) return SMCGW_ERR_INVALID;
+    const PrecDesc pd = prior_precision(c->prior);
+    TimedLaunch tl(c, SMCGW_KERNEL_METRIC);
+    hipLaunchKernelGGL(local_metric_kernel, dim3(P), dim3(MET_THREADS), 0, c->stream, c->d_events,
+                       (int)c->events.size(), c->ev_of_p, c->pmap, pd, P, theta, 0.0, (const double*)nullptr,
+                       fallback_runs, chol, (double*)nullptr, status, st, run_size);
+    return hipGetLastError() == hipSuccess ? SMCGW_OK : SMCGW_ERR_HIP;
+}
+}  // namespace smcgw
+
 using namespace smcgw;
 
 extern "C" int smcgw_local_metric(smcgw_ctx* c, int P, int D, const double* theta, double beta,
@@ -269,6 +290,6 @@ extern "C" int smcgw_local_metric(smcgw_ctx* c, int P, int D, const double* thet
     TimedLaunch tl(c, SMCGW_KERNEL_METRIC);
     hipLaunchKernelGGL(local_metric_kernel, dim3(P), dim3(MET_THREADS), 0, c->stream, c->d_events,
                        (int)c->events.size(), c->ev_of_p, c->pmap, pd, P, theta, beta, beta_device, fallback_chol, chol, fisher,
-                       status);
+                       status, (const double*)nullptr, P);
     return hipGetLastError() == hipSuccess ? SMCGW_OK : SMCGW_ERR_HIP;
 }

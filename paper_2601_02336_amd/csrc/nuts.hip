@@ -51,6 +51,8 @@ struct NutsArgs {
     int priority;           // raise wavefront priority with the tree depth
     int chol_pp;            // chol holds one [D][D] factor per particle
     const double* beta_dev; // beta from device memory (NULL: the value above)
+    const double* state;    // independent runs' states (NULL: one run with the values above)
+    int run_size;           // particles per run when state is set
 };
 
 constexpr int MAX_WAVES = 8;
@@ -261,12 +263,16 @@ struct NutsState {
     double h0, logw, sub_logw, uacc, acc_sum, eps, prop_ll, sprop_ll, ll_new, rec_ll, rec_lp;
     int first, stop, j, n, nleaves, depth, nlf, div, dir, md, inflight;
     uint32_t leafc;
+    // the particle's run: temperature, Philox key and iteration, particle index within the run
+    double beta;
+    uint64_t seed, iter;
+    uint32_t pid;
 };
 
 // Direction and merge uniform of doubling j (Philox stream DOUBLING).
-__device__ __forceinline__ void doubling_draw(const NutsArgs& a, int p, int j, int& dir, double& uacc) {
+__device__ __forceinline__ void doubling_draw(const NutsState& T, int j, int& dir, double& uacc) {
     double ud0, ud1;
-    rng_uniform2(a.seed, (uint32_t)j, (uint32_t)p, a.iteration, RNG_DOUBLING, ud0, ud1);
+    rng_uniform2(T.seed, (uint32_t)j, T.pid, T.iter, RNG_DOUBLING, ud0, ud1);
     dir = (ud0 < 0.5) ? -1 : 1;
     uacc = ud1;
 }
@@ -282,11 +288,12 @@ __device__ __noinline__ void start_transition(NutsShared& S, NutsState& T, const
     double gp;
     const double lpr = dim_sum(S, D, lane, dl ? log_prior_lane(S, kk, x, gp) : 0.0);
     if (!dl) gp = 0.0;
-    const double lp = a.beta * ll + lpr;
-    const double g = a.beta * gl + gp;
+    const double beta = T.beta;
+    const double lp = beta * ll + lpr;
+    const double g = beta * gl + gp;
     // r = L^{-T} z with z ~ N(0, I) from Box-Muller on Philox uniform pairs.
     double u0, u1;
-    rng_uniform2(a.seed, (uint32_t)(lane >> 1), (uint32_t)p, a.iteration, RNG_MOMENTUM, u0, u1);
+    rng_uniform2(T.seed, (uint32_t)(lane >> 1), T.pid, T.iter, RNG_MOMENTUM, u0, u1);
     const double rad = sqrt(-2.0 * log(1.0 - u0));
     const double z = (lane & 1) ? rad * sin(2.0 * PI * u1) : rad * cos(2.0 * PI * u1);
     double accz = dl ? z : 0.0, r = 0.0;
@@ -311,7 +318,7 @@ __device__ __noinline__ void start_transition(NutsShared& S, NutsState& T, const
     if (lane < md) {
         int dj;
         double uj;
-        doubling_draw(a, p, lane, dj, uj);
+        doubling_draw(T, lane, dj, uj);
         T.dtab_dir[lane] = dj;
         T.dtab_u[lane] = log(uj);
     }
@@ -355,7 +362,7 @@ __device__ __noinline__ int advance(NutsShared& S, NutsState& T, const NutsArgs&
     // Every tree-state value the step may need is read up front, both tree ends
     // included, so the LDS round trips overlap instead of following the branches.
     const int first = T.first, n = T.n, nleaves = T.nleaves, j = T.j, md = T.md, dcur = T.dir;
-    const double ll = T.ll_new, plp = T.plp, eps_prev = T.eps, beta = a.beta;
+    const double ll = T.ll_new, plp = T.plp, eps_prev = T.eps, beta = T.beta;
     const double gl = T.gl_new[kk], xf = T.x[kk], pg = T.pgp[kk], rh = T.r[kk];
     const double lx = S.left[0][kk], lr = S.left[1][kk], lg = S.left[2][kk];
     const double rx = S.right[0][kk], rr = S.right[1][kk], rg = S.right[2][kk];
@@ -425,7 +432,7 @@ __device__ __noinline__ void aux_in_flight(const DevEvent* ev, NutsShared& S, Nu
     if (dl) T.pgp[lane] = gp;
     const int idx = T.inflight;
     double ul0, ul1;
-    rng_uniform2(a.seed, (uint32_t)idx, (uint32_t)p, a.iteration, RNG_LEAF, ul0, ul1);
+    rng_uniform2(T.seed, (uint32_t)idx, T.pid, T.iter, RNG_LEAF, ul0, ul1);
     // The progressive sampling test u < w / (W + w) is taken as log u + log W < log(1 - u) + log w: lanes 0
     // and 1 take the two logs at once.
     const double lu = log(lane == 0 ? ul0 : 1.0 - ul0);
@@ -760,7 +767,9 @@ __global__ __launch_bounds__(WAVES * 64, (WAVES == 1 ? 2 : NUTS_WAVES_PER_SIMD))
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int D = a.D;
 
-    if (!a.chol_pp) load_factor(S, a.chol, D, tid);
+    // one factor for the whole launch; per-run factors are loaded when a particle's run changes
+    const bool run_factor = !a.chol_pp && a.state;
+    if (!a.chol_pp && !a.state) load_factor(S, a.chol, D, tid);
     if (tid == 0) {
         A = a;
         if (a.beta_dev) A.beta = *a.beta_dev;
@@ -776,12 +785,13 @@ __global__ __launch_bounds__(WAVES * 64, (WAVES == 1 ? 2 : NUTS_WAVES_PER_SIMD))
         for (int k = 0; k < NPAR; ++k) S.pfixed[k] = pm.fixed[k];
     }
     __syncthreads();
-    if (!a.chol_pp) {
+    if (!a.chol_pp && !a.state) {
         derive_metric(S, D, tid);
         __syncthreads();
     }
 
-    int ev_cached = -1;   // event whose descriptor S.ev holds
+    int ev_cached = -1;    // event whose descriptor S.ev holds
+    int run_cached = -1;   // run whose factor S.L holds (per-run factors)
     for (;;) {
         if (tid == 0) {
             const int q = __hip_atomic_fetch_add(a.queue, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -790,6 +800,33 @@ __global__ __launch_bounds__(WAVES * 64, (WAVES == 1 ? 2 : NUTS_WAVES_PER_SIMD))
         __syncthreads();
         const int p = __builtin_amdgcn_readfirstlane(S.p);
         if (p >= a.P) break;
+        // the particle's run (uniform over the workgroup)
+        const int run = a.state ? p / a.run_size : 0;
+        if (a.state && a.state[(size_t)run * SMCGW_STATE_SIZE + SMCGW_ST_DONE] != 0.0) {
+            __syncthreads();   // every thread has read S.p before thread 0 pulls the next particle
+            continue;          // a finished run's particles are left untouched
+        }
+        if (tid == 0) {
+            if (a.state) {
+                const double* st = a.state + (size_t)run * SMCGW_STATE_SIZE;
+                T.beta = st[SMCGW_ST_BETA];
+                T.iter = (uint64_t)st[SMCGW_ST_ITER];
+                T.seed = a.seed + (uint64_t)run;
+                T.pid = (uint32_t)(p - run * a.run_size);
+            } else {
+                T.beta = A.beta;
+                T.iter = a.iteration;
+                T.seed = a.seed;
+                T.pid = (uint32_t)p;
+            }
+        }
+        if (run_factor && run != run_cached) {   // the previous transition's readers are past a barrier
+            load_factor(S, a.chol + (size_t)run * D * D, D, tid);
+            __syncthreads();
+            derive_metric(S, D, tid);
+            run_cached = run;
+        }
+        __syncthreads();
         // The particle's event descriptor is copied into LDS (all threads, ordered
         // before its first use by the barrier that follows advance), so the
         // leaf's serial phases read it without a round trip to the L2.
@@ -969,6 +1006,19 @@ int launch_gw(smcgw_ctx* c, int precision, const NutsArgs& a, const PriorDesc& p
 
 }  // namespace
 
+// The work-queue counter and the start-order buffer for P particles.
+int smcgw::nuts_reserve(smcgw_ctx* c, int P, bool hint) {
+    if (!c->d_queue && hipMalloc(&c->d_queue, 256) != hipSuccess) return SMCGW_ERR_OOM;
+    if (hint && P > c->order_cap) {
+        hipFree(c->d_order);
+        c->d_order = nullptr;
+        c->order_cap = 0;
+        if (hipMalloc(&c->d_order, (size_t)P * sizeof(int32_t)) != hipSuccess) return SMCGW_ERR_OOM;
+        c->order_cap = P;
+    }
+    return SMCGW_OK;
+}
+
 extern "C" int smcgw_nuts_step(smcgw_ctx* c, int P, int D, double* theta, double* logl, double* grad,
                                const double* chol, const smcgw_nuts_params* prm,
                                const int32_t* max_depth_per_particle, const int32_t* work_hint, int precision,
@@ -979,7 +1029,9 @@ extern "C" int smcgw_nuts_step(smcgw_ctx* c, int P, int D, double* theta, double
     if (prm->max_depth < 0 || prm->max_depth > SMCGW_MAX_DEPTH || !(prm->step > 0.0) ||
         (!prm->beta_device && !(prm->beta >= 0.0)) ||
         !(prm->max_delta_h > 0.0) || (prm->chol_per_particle != 0 && prm->chol_per_particle != 1) ||
-        prm->reserved != 0)
+        prm->reserved != 0 || prm->reserved2 != 0)
+        return SMCGW_ERR_INVALID;
+    if (prm->state_device && (prm->run_size < 1 || P % prm->run_size != 0 || P / prm->run_size > SMCGW_MAX_RUNS))
         return SMCGW_ERR_INVALID;
     if (!c->prior_set || c->prior.dim != D) return SMCGW_ERR_NOT_INIT;
     const int kind = c->target.kind;
@@ -990,15 +1042,8 @@ extern "C" int smcgw_nuts_step(smcgw_ctx* c, int P, int D, double* theta, double
     }
     if (P == 0) return SMCGW_OK;
     hipSetDevice(c->device);
-    if (!c->d_queue && hipMalloc(&c->d_queue, 256) != hipSuccess) return SMCGW_ERR_OOM;
+    if (nuts_reserve(c, P, work_hint != nullptr) != SMCGW_OK) return SMCGW_ERR_OOM;
     if (work_hint) {
-        if (P > c->order_cap) {
-            hipFree(c->d_order);
-            c->d_order = nullptr;
-            c->order_cap = 0;
-            if (hipMalloc(&c->d_order, (size_t)P * sizeof(int32_t)) != hipSuccess) return SMCGW_ERR_OOM;
-            c->order_cap = P;
-        }
         hipLaunchKernelGGL(order_kernel, dim3(1), dim3(ORDER_THREADS), 0, c->stream, work_hint, P, c->d_order);
         if (hipGetLastError() != hipSuccess) return SMCGW_ERR_HIP;
     }
@@ -1029,6 +1074,8 @@ extern "C" int smcgw_nuts_step(smcgw_ctx* c, int P, int D, double* theta, double
     a.priority = c->nuts_priority;
     a.chol_pp = prm->chol_per_particle;
     a.beta_dev = prm->beta_device;
+    a.state = prm->state_device;
+    a.run_size = prm->state_device ? prm->run_size : P;
     const TargetDesc t = c->target;
     switch (kind) {
     case SMCGW_TARGET_GW:

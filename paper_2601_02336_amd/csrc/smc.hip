@@ -27,6 +27,11 @@ constexpr int SMC_WAVES = SMC_THREADS / 64;
 constexpr int RW_LEVELS = 4;
 constexpr int RW_CAND = 1 << RW_LEVELS;
 constexpr int RW_THREADS = 512;   // 32 FP64 accumulators per thread need the larger register budget
+// Per-run result block of the reweighting: beta_next, the evidence increment,
+// the weight total, and whether the run's resampling is skipped.
+constexpr int OUT_SIZE = 4;
+constexpr int OUT_SKIP = 3;
+constexpr double SKIP_NONE = 0.0, SKIP_DONE = 1.0, SKIP_STALL = 2.0;
 
 
 // Workgroup sums of K values per thread: wavefront totals (one scattered
@@ -80,15 +85,34 @@ __device__ __forceinline__ double incr_weight(double db, double e) { return db =
 // lofs_i - max_j(...), the ESS target is alpha n_target and out[1] is log Z
 // at beta_next itself (the pool mean of the weights).  lofs = NULL is
 // standard SMC (g_i = 0, n_target = P).
+//
+// Independent runs: run r = blockIdx.y takes logl + r P, cum + r P and
+// out + r OUT_SIZE.  With a run state st (st + r SMCGW_STATE_SIZE), beta_prev
+// is the state's temperature; a run that is done, or whose last iteration
+// already mutated at beta = 1, gets out[OUT_SKIP] = SKIP_DONE and nothing
+// else, and a ladder that cannot advance gets SKIP_STALL.
 __global__ __launch_bounds__(RW_THREADS) void reweight_kernel(const double* __restrict__ logl, int P,
                                                               double beta_prev, double alpha,
                                                               const double* __restrict__ lofs, int n_target,
-                                                              double* __restrict__ cum, double* __restrict__ out) {
+                                                              double* __restrict__ cum, double* __restrict__ out,
+                                                              const double* __restrict__ st) {
     __shared__ double red[2 * RW_CAND * (RW_THREADS / 64)];
     __shared__ double tot[2 * RW_CAND];
     __shared__ double cand[2][RW_CAND];   // by pass parity: a wavefront may write the next pass's midpoints
                                           // while another still walks this pass's
     __shared__ double scan[RW_THREADS / 64 + 1];
+    const int rix = blockIdx.y;   // run index
+    logl += (size_t)rix * P;
+    cum += (size_t)rix * P;
+    out += (size_t)rix * OUT_SIZE;
+    if (st) {
+        st += (size_t)rix * SMCGW_STATE_SIZE;
+        if (st[SMCGW_ST_DONE] != 0.0 || (st[SMCGW_ST_BETA] >= 1.0 && st[SMCGW_ST_NEXT] > 0.0)) {
+            if (threadIdx.x == 0) out[OUT_SKIP] = SKIP_DONE;
+            return;
+        }
+        beta_prev = st[SMCGW_ST_BETA];
+    }
     double lm = -INFINITY, gm = -INFINITY;
     for (int i = threadIdx.x; i < P; i += blockDim.x) {
         const double l = ll_at(logl, i);
@@ -98,7 +122,10 @@ __global__ __launch_bounds__(RW_THREADS) void reweight_kernel(const double* __re
     const double lmax = block_max(lm, red);
     if (!(lmax > -INFINITY)) {   // no particle with a finite likelihood: nothing to reweight
         for (int i = threadIdx.x; i < P; i += blockDim.x) cum[i] = 0.0;
-        if (threadIdx.x == 0) { out[0] = beta_prev; out[1] = -INFINITY; out[2] = 0.0; }
+        if (threadIdx.x == 0) {
+            out[0] = beta_prev; out[1] = -INFINITY; out[2] = 0.0;
+            out[OUT_SKIP] = st ? SKIP_STALL : SKIP_NONE;
+        }
         return;
     }
     const double gmax = lofs ? block_max(gm, red) : 0.0;
@@ -208,17 +235,25 @@ __global__ __launch_bounds__(RW_THREADS) void reweight_kernel(const double* __re
         out[0] = beta;
         out[1] = lse - log((double)P);
         out[2] = cum[P - 1];
+        out[OUT_SKIP] = (st && !(beta > beta_prev) && beta_prev < 1.0) ? SKIP_STALL : SKIP_NONE;
     }
 }
 
 // Ancestor of particle i: first k with cum_k / cum_{P-1} > u_i (last entry forced to 1).
+// Run r = blockIdx.y draws n_draw ancestors among its P weights with key
+// seed + r and, with a run state, the iteration index state[NEXT].
 __global__ __launch_bounds__(256) void ancestors_kernel(const double* __restrict__ cum, const double* __restrict__ out,
                                                         int P, int n_draw, uint64_t seed, uint64_t iteration,
-                                                        int32_t* __restrict__ anc) {
+                                                        int32_t* __restrict__ anc, const double* __restrict__ st) {
+    const int run = blockIdx.y;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_draw) return;
+    out += (size_t)run * OUT_SIZE;
+    if (i >= n_draw || out[OUT_SKIP] != SKIP_NONE) return;
+    cum += (size_t)run * P;
+    anc += (size_t)run * n_draw;
+    if (st) iteration = (uint64_t)st[(size_t)run * SMCGW_STATE_SIZE + SMCGW_ST_NEXT];
     double u, u1;
-    rng_uniform2(seed, 0u, (uint32_t)i, iteration, RNG_RESAMPLE, u, u1);
+    rng_uniform2(seed + (uint64_t)run, 0u, (uint32_t)i, iteration, RNG_RESAMPLE, u, u1);
     const double total = out[2];
     int lo = 0, hi = P - 1;   // search the first index with normalised cum > u
     while (lo < hi) {
@@ -229,33 +264,69 @@ __global__ __launch_bounds__(256) void ancestors_kernel(const double* __restrict
     anc[i] = lo;
 }
 
-__global__ __launch_bounds__(256) void gather_kernel(const int32_t* __restrict__ anc, int P, int D,
+// Gather of run r = blockIdx.y: P particles drawn from its n_src candidates
+// (n_src = P for standard SMC, the pool for persistent sampling).
+__global__ __launch_bounds__(256) void gather_kernel(const int32_t* __restrict__ anc, int P, int D, int n_src,
                                                      const double* __restrict__ x, const double* __restrict__ ll,
                                                      const double* __restrict__ g, const int32_t* __restrict__ cy,
                                                      double* __restrict__ xo, double* __restrict__ llo,
-                                                     double* __restrict__ go, int32_t* __restrict__ cyo) {
+                                                     double* __restrict__ go, int32_t* __restrict__ cyo,
+                                                     const double* __restrict__ out) {
+    const int run = blockIdx.y;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= P) return;
-    const int a = anc[i];
-    for (int k = 0; k < D; ++k) xo[(size_t)i * D + k] = x[(size_t)a * D + k];
-    llo[i] = ll[a];
+    if (i >= P || out[(size_t)run * OUT_SIZE + OUT_SKIP] != SKIP_NONE) return;
+    const size_t src = (size_t)run * n_src + anc[(size_t)run * P + i], dst = (size_t)run * P + i;
+    for (int k = 0; k < D; ++k) xo[dst * D + k] = x[src * D + k];
+    llo[dst] = ll[src];
     if (g)
-        for (int k = 0; k < D; ++k) go[(size_t)i * D + k] = g[(size_t)a * D + k];
-    if (cy) cyo[i] = cy[a];
+        for (int k = 0; k < D; ++k) go[dst * D + k] = g[src * D + k];
+    if (cy) cyo[dst] = cy[src];
 }
 
 __global__ __launch_bounds__(256) void copy_back_kernel(int P, int D, const double* __restrict__ xo,
                                                         const double* __restrict__ llo, const double* __restrict__ go,
                                                         const int32_t* __restrict__ cyo, double* __restrict__ x,
                                                         double* __restrict__ ll, double* __restrict__ g,
-                                                        int32_t* __restrict__ cy) {
+                                                        int32_t* __restrict__ cy, const double* __restrict__ out) {
+    const int run = blockIdx.y;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= P) return;
-    for (int k = 0; k < D; ++k) x[(size_t)i * D + k] = xo[(size_t)i * D + k];
-    ll[i] = llo[i];
+    if (i >= P || out[(size_t)run * OUT_SIZE + OUT_SKIP] != SKIP_NONE) return;
+    const size_t j = (size_t)run * P + i;
+    for (int k = 0; k < D; ++k) x[j * D + k] = xo[j * D + k];
+    ll[j] = llo[j];
     if (g)
-        for (int k = 0; k < D; ++k) g[(size_t)i * D + k] = go[(size_t)i * D + k];
-    if (cy) cy[i] = cyo[i];
+        for (int k = 0; k < D; ++k) g[j * D + k] = go[j * D + k];
+    if (cy) cy[j] = cyo[j];
+}
+
+// Run states after the reweighting (one thread per run): the temperature,
+// the increment and the running log evidence log Z_t = log Z_{t-1} +
+// log(Z_t / Z_{t-1}) in FP64 (Sec. 3.1, Eq. 8), the iteration index, and the
+// first three entries of the record row t.  A skipped run is marked done
+// (stalled when the temperature could not advance).
+__global__ void state_update_kernel(const double* __restrict__ out, int n_runs, double* __restrict__ st,
+                                    double* __restrict__ hist, int hist_cap) {
+    const int r = threadIdx.x;
+    if (r >= n_runs) return;
+    const double* o = out + (size_t)r * OUT_SIZE;
+    double* s = st + (size_t)r * SMCGW_STATE_SIZE;
+    if (o[OUT_SKIP] != SKIP_NONE) {
+        if (o[OUT_SKIP] == SKIP_STALL) s[SMCGW_ST_STALL] = 1.0;
+        s[SMCGW_ST_DONE] = 1.0;
+        return;
+    }
+    const double t = s[SMCGW_ST_NEXT];
+    s[SMCGW_ST_BETA] = o[0];
+    s[SMCGW_ST_DLOGZ] = o[1];
+    s[SMCGW_ST_LOGZ] += o[1];
+    s[SMCGW_ST_ITER] = t;
+    s[SMCGW_ST_NEXT] = t + 1.0;
+    if (hist && t < (double)hist_cap) {
+        double* h = hist + ((size_t)r * hist_cap + (size_t)t) * SMCGW_HIST_SIZE;
+        h[SMCGW_H_BETA] = o[0];
+        h[SMCGW_H_LOGZ] = s[SMCGW_ST_LOGZ];
+        h[SMCGW_H_DLOGZ] = o[1];
+    }
 }
 
 // Covariance entries (a, b), b <= a < MAXDIM, in row order (a compile-time table).
@@ -280,10 +351,22 @@ constexpr int MM_SUMS = MAXDIM + MM_ENTRIES;
 constexpr int MM_THREADS = 256;
 static_assert(MM_SUMS <= MM_THREADS, "one thread per sum");
 
+// A run whose state says done (st, nullable) is skipped.
+__device__ __forceinline__ bool run_is_done(const double* st, int run) {
+    return st && st[(size_t)run * SMCGW_STATE_SIZE + SMCGW_ST_DONE] != 0.0;
+}
+
+// Run r = blockIdx.y covers particles [r P, (r+1) P); its block partials go
+// to part + r gridDim.x MM_SUMS.
 __global__ __launch_bounds__(MM_THREADS) void mm_partial_kernel(const double* __restrict__ x, int P, int D,
-                                                                double* __restrict__ part) {
+                                                                double* __restrict__ part,
+                                                                const double* __restrict__ st) {
     __shared__ double xs[MMB * MAXDIM];
     __shared__ double x0[MAXDIM];
+    const int run = blockIdx.y;
+    if (run_is_done(st, run)) return;
+    x += (size_t)run * P * D;
+    part += (size_t)run * gridDim.x * MM_SUMS;
     const int blk = blockIdx.x;
     const int i0 = blk * MMB, n = min(MMB, P - i0);
     for (int t = threadIdx.x; t < n * D; t += blockDim.x) xs[t] = x[(size_t)i0 * D + t];
@@ -306,13 +389,21 @@ __global__ __launch_bounds__(MM_THREADS) void mm_partial_kernel(const double* __
 // Block partials summed in block order, covariance (s_ab - s_a s_b / P) / (P - 1),
 // diagonal shrinkage and Cholesky; status[0] = 1 when a diagonal fallback
 // was used.
+// One workgroup per run (blockIdx.x): inv, L + run D D, status + run.
 __global__ __launch_bounds__(MM_THREADS) void mm_finish_kernel(const double* __restrict__ part, int nblk, int P,
                                                                int D, double shrink, double* __restrict__ inv,
-                                                               double* __restrict__ L, int* __restrict__ status) {
+                                                               double* __restrict__ L, int* __restrict__ status,
+                                                               const double* __restrict__ st) {
     __shared__ double tot[MM_SUMS];
     __shared__ double cov[MAXDIM * MAXDIM];
     __shared__ double l[MAXDIM * MAXDIM];
     __shared__ int bad;
+    const int run = blockIdx.x;
+    if (run_is_done(st, run)) return;
+    part += (size_t)run * nblk * MM_SUMS;
+    inv += (size_t)run * D * D;
+    L += (size_t)run * D * D;
+    status += run;
     if ((int)threadIdx.x < MM_SUMS) {
         double s = 0.0;
         for (int b = 0; b < nblk; ++b) s += part[(size_t)b * MM_SUMS + threadIdx.x];
@@ -401,6 +492,42 @@ __global__ __launch_bounds__(256) void analytic_loglike_kernel(int kind, int P, 
             for (int k = 0; k < D; ++k) gi[k] = (w1 * (prm[k] - xi[k]) + w2 * (prm[D + k] - xi[k])) / (sg * sg) / (w1 + w2);
     }
     logl[i] = ll;
+}
+
+// Record row t = state[ITER] of run r = blockIdx.x after its transition:
+// leapfrog steps, summed depth, divergent transitions (fixed-order sums over
+// the run's particles), the covariance fallback flag and the local metric's
+// fallbacks.  A run that was done before this iteration is skipped.
+constexpr int REC_THREADS = 256;
+__global__ __launch_bounds__(REC_THREADS) void record_kernel(int P, const int32_t* __restrict__ nlf,
+                                                             const int32_t* __restrict__ depth,
+                                                             const uint8_t* __restrict__ div,
+                                                             const int32_t* __restrict__ mm_status,
+                                                             const int32_t* __restrict__ metric_status,
+                                                             const double* __restrict__ st, double* __restrict__ hist,
+                                                             int hist_cap) {
+    __shared__ double red[4 * (REC_THREADS / 64)];
+    __shared__ double tot[4];
+    const int run = blockIdx.x;
+    const double* s = st + (size_t)run * SMCGW_STATE_SIZE;
+    if (s[SMCGW_ST_DONE] != 0.0 || !(s[SMCGW_ST_ITER] < (double)hist_cap)) return;
+    const size_t base = (size_t)run * P;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < P; i += blockDim.x) {
+        v[0] += (double)nlf[base + i];
+        v[1] += (double)depth[base + i];
+        v[2] += (double)div[base + i];
+        if (metric_status) v[3] += (double)metric_status[base + i];
+    }
+    block_sums<4>(v, red, tot);
+    if (threadIdx.x == 0) {
+        double* h = hist + ((size_t)run * hist_cap + (size_t)s[SMCGW_ST_ITER]) * SMCGW_HIST_SIZE;
+        h[SMCGW_H_LEAPFROG] = tot[0];
+        h[SMCGW_H_DEPTH] = tot[1];
+        h[SMCGW_H_DIVERGENT] = tot[2];
+        h[SMCGW_H_METRIC_FALLBACKS] = tot[3];
+        h[SMCGW_H_MM_FALLBACK] = mm_status ? (double)mm_status[run] : 0.0;
+    }
 }
 
 // log((1/T) sum_t L^beta_t / Z_t) for one point of log-likelihood l.
@@ -582,17 +709,11 @@ extern "C" int smcgw_mass_matrix(smcgw_ctx* c, int P, int D, const double* theta
         if (!st || !hp) return SMCGW_ERR_OOM;
     }
     const int nblk = (P + MMB - 1) / MMB;
-    const size_t need = (size_t)nblk * MM_SUMS * sizeof(double);
-    if (need > c->mm_bytes) {
-        hipFree(c->d_mm);
-        c->d_mm = nullptr;
-        c->mm_bytes = 0;
-        if (hipMalloc(&c->d_mm, need) != hipSuccess) return SMCGW_ERR_OOM;
-        c->mm_bytes = need;
-    }
-    hipLaunchKernelGGL(mm_partial_kernel, dim3(nblk), dim3(MM_THREADS), 0, c->stream, theta, P, D, c->d_mm);
+    if (mm_reserve(c, 1, P) != SMCGW_OK) return SMCGW_ERR_OOM;
+    hipLaunchKernelGGL(mm_partial_kernel, dim3(nblk), dim3(MM_THREADS), 0, c->stream, theta, P, D, c->d_mm,
+                       (const double*)nullptr);
     hipLaunchKernelGGL(mm_finish_kernel, dim3(1), dim3(MM_THREADS), 0, c->stream, (const double*)c->d_mm, nblk, P, D,
-                       shrink, inv_mass, chol, st);
+                       shrink, inv_mass, chol, st, (const double*)nullptr);
     if (hipGetLastError() != hipSuccess) return SMCGW_ERR_HIP;
     if (status_device) return SMCGW_OK;
     if (hipMemcpyAsync(hp, st, sizeof(int), hipMemcpyDeviceToHost, c->stream) || hipStreamSynchronize(c->stream))
@@ -603,21 +724,26 @@ extern "C" int smcgw_mass_matrix(smcgw_ctx* c, int P, int D, const double* theta
 }
 
 namespace smcgw {
-// Reweighting, temperature search, resampling and gather on the context's
-// stream; out (device) holds beta_next, the evidence increment and the
-// weight total when the queued work has run.
-static int reweight_resample(smcgw_ctx* c, int P, int D, double beta_prev, double alpha, uint64_t seed,
-                             uint64_t iteration, double* theta, double* logl, double* grad, int32_t* carry,
-                             int32_t* ancestors, double** out_dev) {
-    if (!c || P < 1 || D <= 0 || D > MAXDIM || !theta || !logl || !ancestors) return SMCGW_ERR_INVALID;
+// Reweighting, temperature search, resampling and gather of n_runs runs of P
+// particles on the context's stream (run r: particles [r P, (r+1) P)); out
+// (device, [n_runs][OUT_SIZE]) holds beta_next, the evidence increment, the
+// weight total and the skip flag of each run when the queued work has run.
+// With run states st, beta_prev and the iteration index come from them and
+// state_update_kernel advances them (and fills the record rows in hist).
+int queue_reweight_resample(smcgw_ctx* c, int n_runs, int P, int D, double beta_prev, double alpha, uint64_t seed,
+                            uint64_t iteration, double* theta, double* logl, double* grad, int32_t* carry,
+                            int32_t* ancestors, double* st, double* hist, int hist_cap, double** out_dev) {
+    if (!c || n_runs < 1 || P < 1 || D <= 0 || D > MAXDIM || !theta || !logl || !ancestors) return SMCGW_ERR_INVALID;
     if (!(alpha > 0.0 && alpha <= 1.0) || !(beta_prev >= 0.0 && beta_prev <= 1.0)) return SMCGW_ERR_INVALID;
+    if ((size_t)n_runs * P > (size_t)INT32_MAX) return SMCGW_ERR_SHAPE;
     hipSetDevice(c->device);
-    const size_t off_cum = 64 * sizeof(double);
-    const size_t off_x = off_cum + (size_t)P * sizeof(double);
-    const size_t off_ll = off_x + (size_t)P * D * sizeof(double);
-    const size_t off_g = off_ll + (size_t)P * sizeof(double);
-    const size_t off_cy = off_g + (size_t)P * D * sizeof(double);
-    const size_t bytes = off_cy + (size_t)P * sizeof(int32_t);
+    const size_t n = (size_t)n_runs * P;
+    const size_t off_cum = 64 * sizeof(double) * ((n_runs * OUT_SIZE + 63) / 64);
+    const size_t off_x = off_cum + n * sizeof(double);
+    const size_t off_ll = off_x + n * D * sizeof(double);
+    const size_t off_g = off_ll + n * sizeof(double);
+    const size_t off_cy = off_g + n * D * sizeof(double);
+    const size_t bytes = off_cy + n * sizeof(int32_t);
     char* s = (char*)sampler_scratch(c, bytes);
     if (!s) return SMCGW_ERR_OOM;
     double* out = (double*)s;
@@ -626,16 +752,69 @@ static int reweight_resample(smcgw_ctx* c, int P, int D, double beta_prev, doubl
     double* llo = (double*)(s + off_ll);
     double* go = (double*)(s + off_g);
     int32_t* cyo = (int32_t*)(s + off_cy);
-    hipLaunchKernelGGL(reweight_kernel, dim3(1), dim3(RW_THREADS), 0, c->stream, logl, P, beta_prev, alpha,
-                       (const double*)nullptr, P, cum, out);
-    const dim3 g((P + 255) / 256), b(256);
-    hipLaunchKernelGGL(ancestors_kernel, g, b, 0, c->stream, cum, out, P, P, seed, iteration, ancestors);
-    hipLaunchKernelGGL(gather_kernel, g, b, 0, c->stream, ancestors, P, D, theta, logl, grad, carry, xo, llo, go,
-                       cyo);
-    hipLaunchKernelGGL(copy_back_kernel, g, b, 0, c->stream, P, D, xo, llo, go, cyo, theta, logl, grad, carry);
+    hipLaunchKernelGGL(reweight_kernel, dim3(1, n_runs), dim3(RW_THREADS), 0, c->stream, logl, P, beta_prev, alpha,
+                       (const double*)nullptr, P, cum, out, (const double*)st);
+    const dim3 g((P + 255) / 256, n_runs), b(256);
+    hipLaunchKernelGGL(ancestors_kernel, g, b, 0, c->stream, cum, out, P, P, seed, iteration, ancestors,
+                       (const double*)st);
+    hipLaunchKernelGGL(gather_kernel, g, b, 0, c->stream, ancestors, P, D, P, theta, logl, grad, carry, xo, llo, go,
+                       cyo, (const double*)out);
+    hipLaunchKernelGGL(copy_back_kernel, g, b, 0, c->stream, P, D, xo, llo, go, cyo, theta, logl, grad, carry,
+                       (const double*)out);
+    if (st)
+        hipLaunchKernelGGL(state_update_kernel, dim3(1), dim3(SMCGW_MAX_RUNS), 0, c->stream, (const double*)out,
+                           n_runs, st, hist, hist_cap);
     if (hipGetLastError() != hipSuccess) return SMCGW_ERR_HIP;
     *out_dev = out;
     return SMCGW_OK;
+}
+
+size_t reweight_scratch_bytes(int n_runs, int P, int D) {
+    const size_t n = (size_t)n_runs * P;
+    return 64 * sizeof(double) * ((n_runs * OUT_SIZE + 63) / 64) + n * (2 * D + 2) * sizeof(double) +
+           n * sizeof(int32_t);
+}
+
+// Block partials of the population covariance for n_runs runs of P particles.
+int mm_reserve(smcgw_ctx* c, int n_runs, int P) {
+    const int nblk = (P + MMB - 1) / MMB;
+    const size_t need = (size_t)n_runs * nblk * MM_SUMS * sizeof(double);
+    if (need <= c->mm_bytes) return SMCGW_OK;
+    hipFree(c->d_mm);
+    c->d_mm = nullptr;
+    c->mm_bytes = 0;
+    if (hipMalloc(&c->d_mm, need) != hipSuccess) return SMCGW_ERR_OOM;
+    c->mm_bytes = need;
+    return SMCGW_OK;
+}
+
+// Covariance, shrinkage and factor of every run (run r: particles [r P, (r+1) P),
+// inv, chol + r D D, status + r); runs whose state says done are skipped.
+int queue_mass_matrix_runs(smcgw_ctx* c, int n_runs, int P, int D, const double* theta, double shrink, double* inv,
+                           double* chol, int32_t* status, const double* st) {
+    const int nblk = (P + MMB - 1) / MMB;
+    if ((size_t)n_runs * nblk * MM_SUMS * sizeof(double) > c->mm_bytes) return SMCGW_ERR_INVALID;
+    hipLaunchKernelGGL(mm_partial_kernel, dim3(nblk, n_runs), dim3(MM_THREADS), 0, c->stream, theta, P, D, c->d_mm,
+                       st);
+    hipLaunchKernelGGL(mm_finish_kernel, dim3(n_runs), dim3(MM_THREADS), 0, c->stream, (const double*)c->d_mm, nblk, P,
+                       D, shrink, inv, chol, status, st);
+    return hipGetLastError() == hipSuccess ? SMCGW_OK : SMCGW_ERR_HIP;
+}
+
+// Record rows of every run after its transition.
+int queue_record(smcgw_ctx* c, int n_runs, int P, const int32_t* nlf, const int32_t* depth, const uint8_t* div,
+                 const int32_t* mm_status, const int32_t* metric_status, const double* st, double* hist,
+                 int hist_cap) {
+    hipLaunchKernelGGL(record_kernel, dim3(n_runs), dim3(REC_THREADS), 0, c->stream, P, nlf, depth, div, mm_status,
+                       metric_status, st, hist, hist_cap);
+    return hipGetLastError() == hipSuccess ? SMCGW_OK : SMCGW_ERR_HIP;
+}
+
+static int reweight_resample(smcgw_ctx* c, int P, int D, double beta_prev, double alpha, uint64_t seed,
+                             uint64_t iteration, double* theta, double* logl, double* grad, int32_t* carry,
+                             int32_t* ancestors, double** out_dev) {
+    return queue_reweight_resample(c, 1, P, D, beta_prev, alpha, seed, iteration, theta, logl, grad, carry, ancestors,
+                                   nullptr, nullptr, 0, out_dev);
 }
 }  // namespace smcgw
 
@@ -749,13 +928,14 @@ extern "C" int smcgw_ps_reweight_resample(smcgw_ctx* c, int T, int N, int D, con
         return SMCGW_ERR_HIP;
     hipLaunchKernelGGL(pool_logmix_kernel, dim3((n + 255) / 256), dim3(256), 0, c->stream, logl_pool, n, T, bz, lofs);
     hipLaunchKernelGGL(reweight_kernel, dim3(1), dim3(RW_THREADS), 0, c->stream, logl_pool, n, beta_prev, alpha,
-                       (const double*)lofs, N, cum, out);
+                       (const double*)lofs, N, cum, out, (const double*)nullptr);
     const dim3 g((N + 255) / 256), b(256);
-    hipLaunchKernelGGL(ancestors_kernel, g, b, 0, c->stream, cum, out, n, N, seed, iteration, ancestors);
-    hipLaunchKernelGGL(gather_kernel, g, b, 0, c->stream, ancestors, N, D, theta_pool, logl_pool, grad_pool,
-                       (const int32_t*)nullptr, xo, llo, go, (int32_t*)nullptr);
+    hipLaunchKernelGGL(ancestors_kernel, g, b, 0, c->stream, cum, out, n, N, seed, iteration, ancestors,
+                       (const double*)nullptr);
+    hipLaunchKernelGGL(gather_kernel, g, b, 0, c->stream, ancestors, N, D, n, theta_pool, logl_pool, grad_pool,
+                       (const int32_t*)nullptr, xo, llo, go, (int32_t*)nullptr, (const double*)out);
     hipLaunchKernelGGL(copy_back_kernel, g, b, 0, c->stream, N, D, xo, llo, go, (const int32_t*)nullptr, theta, logl,
-                       grad, (int32_t*)nullptr);
+                       grad, (int32_t*)nullptr, (const double*)out);
     if (hipGetLastError() != hipSuccess) return SMCGW_ERR_HIP;
     if (hipMemcpyAsync(hp, out, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream) ||
         hipStreamSynchronize(c->stream))

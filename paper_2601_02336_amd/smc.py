@@ -2,13 +2,18 @@
 
 One iteration (arXiv:2601.02336, Sec. 3): reweight the population by
 L^(beta_t - beta_{t-1}) with beta_t chosen so that ESS = alpha P (Eqs. 4-6),
-accumulate the evidence increment (Sec. 3.1, Eqs. 7-8), resample
-multinomially, refresh the mass matrix (Sec. 5: the population covariance,
-or per particle the local metric beta F + prior precision) and mutate every particle with one NUTS transition at beta_t
-(Sec. 4).  The run stops after the mutation at beta = 1.  All arithmetic runs
-in libsmcgw; this loop only sequences the calls and reads beta and the
-evidence increment back once per iteration.  Independent runs can share the
-device through run_smc_concurrent, each on a HIP stream of its own.
+accumulate the evidence (Sec. 3.1, Eqs. 7-8), resample multinomially, refresh
+the mass matrix (Sec. 5: the population covariance, or per particle the local
+metric beta F + prior precision) and mutate every particle with one NUTS
+transition at beta_t (Sec. 4).  The run stops after the mutation at beta = 1.
+
+The whole iteration is one library call (smcgw_smc_iteration): the
+temperature, the running log evidence, the iteration index and the done flag
+live in device memory, so this module only queues iterations and reads the
+done flag back; every number it reports (beta ladder, log Z, increments,
+diagnostics) is the library's own record.  Independent runs share the device
+either batched in one call (run_smc_batched: their transitions share one
+persistent NUTS launch) or on streams of their own (run_smc_concurrent).
 """
 from __future__ import annotations
 
@@ -16,6 +21,7 @@ import dataclasses
 import time
 from typing import List, Optional
 
+import numpy as np
 import torch
 
 from . import smcgw
@@ -32,17 +38,17 @@ class SmcConfig:
     precision: int = smcgw.MIXED
     uturn: bool = True
     record: bool = False          # keep each iteration's population (for replay checks)
-    work_hint: bool = True        # start the particles whose ancestors took the longest trees first
     metric: str = "population"    # "population": one covariance metric; "local": one metric per particle
     recycle: bool = False         # pool every iteration's population and draw i.i.d. samples from it
     variant: str = "standard"     # "standard" SMC, or "persistent" sampling (every population stays in the pool)
+    graph: bool = False           # replay a captured HIP graph of the iteration instead of queuing it call by call
 
 
 @dataclasses.dataclass
 class SmcResult:
     logz: float
     betas: List[float]
-    dlogz: List[float]
+    dlogz: Optional[List[float]]   # evidence increments (standard SMC; persistent sampling reports logz_path only)
     n_iter: int
     theta: torch.Tensor
     logl: torch.Tensor
@@ -56,19 +62,30 @@ class SmcResult:
     local_metric_fallbacks: int = 0                     # particles whose local metric was not positive definite
     recycled: Optional[torch.Tensor] = None             # i.i.d. posterior draws from the recycled pool
     recycled_ess: float = 0.0                           # Kish ESS of the pool's recycling weights
+    logz_path: Optional[List[float]] = None             # log Z after each iteration (library values)
 
 
 def run_smc(ctx: "smcgw.Context", theta0: torch.Tensor, cfg: SmcConfig) -> SmcResult:
-    """Run the tempered sampler from prior draws theta0 [P, D] (device, float64).
-
-    Each iteration is queued without waiting for the host: the reweighting writes beta_t and the evidence
-    increment to device memory, the mass matrix (or the local metric) and the NUTS transition read beta_t
-    from there, and the host reads beta_t back through an event while the transition runs, to decide whether
-    to queue the next iteration.  Diagnostics stay on the device until the run ends."""
+    """Run the tempered sampler from prior draws theta0 [P, D] (device, float64)."""
     _check_config(cfg)
     if cfg.variant == "persistent":
         return _run_persistent(ctx, theta0, cfg)
-    steps = _standard_iterations(ctx, theta0, cfg)
+    steps = _standard_iterations(ctx, theta0, cfg, 1)
+    while True:
+        try:
+            next(steps)
+        except StopIteration as done:
+            return done.value[0]
+
+
+def run_smc_batched(ctx: "smcgw.Context", theta0: torch.Tensor, n_runs: int, cfg: SmcConfig) -> List[SmcResult]:
+    """n_runs independent standard runs (theta0 [n_runs P, D], run r in rows [r P, (r+1) P)) advanced together:
+    one smcgw_smc_iteration call per iteration, whose NUTS transitions of all runs share one persistent launch.
+    Run r draws with key cfg.seed + r and its result is bitwise that of run_smc with that seed."""
+    _check_config(cfg)
+    if cfg.variant != "standard":
+        raise ValueError("run_smc_batched takes standard runs only")
+    steps = _standard_iterations(ctx, theta0, cfg, n_runs)
     while True:
         try:
             next(steps)
@@ -79,9 +96,9 @@ def run_smc(ctx: "smcgw.Context", theta0: torch.Tensor, cfg: SmcConfig) -> SmcRe
 def run_smc_concurrent(runs) -> List[SmcResult]:
     """Independent standard runs [(ctx, theta0, cfg), ...] (one context each) overlapped on one device.
 
-    Every run enqueues on a HIP stream of its own (default priority).  A NUTS launch leaves slots idle while
-    its longest trees finish; the other runs' launches take them.  The host queues a run's next iteration as
-    soon as that run's beta_t has arrived.  Each result is bitwise the one run_smc gives for the same run."""
+    Every run enqueues on a HIP stream of its own (default priority).  The host queues a run's next iteration
+    as soon as its previous state has reached the host.  Each result is bitwise the one run_smc gives for the
+    same run."""
     gens, streams = [], []
     caller = torch.cuda.current_stream()
     for ctx, theta0, cfg in runs:
@@ -91,7 +108,7 @@ def run_smc_concurrent(runs) -> List[SmcResult]:
         s = torch.cuda.Stream(device=theta0.device)
         s.wait_stream(caller)   # theta0 and the contexts' set-up were queued on the caller's stream
         streams.append(s)
-        gens.append(_standard_iterations(ctx, theta0, cfg))
+        gens.append(_standard_iterations(ctx, theta0, cfg, 1))
     results: List[Optional[SmcResult]] = [None] * len(gens)
     waiting: List[Optional[torch.cuda.Event]] = [None] * len(gens)
     active = [True] * len(gens)
@@ -103,7 +120,7 @@ def run_smc_concurrent(runs) -> List[SmcResult]:
                 try:
                     waiting[k] = next(g)
                 except StopIteration as done:
-                    results[k] = done.value
+                    results[k] = done.value[0]
                     active[k] = False
     torch.cuda.synchronize()
     return results
@@ -116,75 +133,76 @@ def _check_config(cfg: SmcConfig) -> None:
         raise ValueError(f"unknown variant {cfg.variant!r}")
 
 
-def _standard_iterations(ctx: "smcgw.Context", theta0: torch.Tensor, cfg: SmcConfig):
-    """The standard run as a generator: it queues one iteration, yields the event that brings beta_t to the
-    host, and continues when resumed; its return value is the SmcResult."""
-    dev = theta0.device
-    theta = theta0.clone().contiguous()
-    logl, grad = ctx.target_loglike_grad(theta, precision=cfg.precision)
-    beta, logz = 0.0, 0.0
-    betas, dlogzs = [], []
-    nlf_d, depth_d, div_d, mm_d, local_d = [], [], [], [], []
-    pool_x, pool_ll = [], []
-    pops = [] if cfg.record else None
-    hint = None   # leapfrog counts of the last transition, resampled with the particles
-    bz = torch.zeros((cfg.max_iter, 2), dtype=torch.float64, device=dev)     # beta_t, dlogZ_t on the device
-    bz_host = torch.zeros((cfg.max_iter, 2), dtype=torch.float64, pin_memory=True)
+def _standard_iterations(ctx: "smcgw.Context", theta0: torch.Tensor, cfg: SmcConfig, n_runs: int):
+    """Standard runs as a generator: it queues iterations, yields the event that brings the run states to the
+    host and continues when resumed; its return value is the list of SmcResults.  The next iteration is queued
+    before the host waits for the previous state, so the device never waits for the host; an iteration queued
+    after a run has finished leaves it untouched."""
+    runs = smcgw.SmcRuns(ctx, theta0.contiguous(), n_runs, alpha=cfg.alpha, step=cfg.step,
+                         max_depth=cfg.max_depth, shrink=cfg.shrink, seed=cfg.seed, precision=cfg.precision,
+                         metric=cfg.metric, uturn=cfg.uturn, history_cap=cfg.max_iter)
+    graph = runs.graph() if cfg.graph else None
+    pops, pool_x, pool_ll = [], [], []
+    state_host = torch.zeros((n_runs, smcgw.STATE_SIZE), dtype=torch.float64, pin_memory=True)
     t0 = time.perf_counter()
-    it = 0
-    while beta < 1.0 and it < cfg.max_iter:
+
+    def queue_one():
         if cfg.record:
-            pops.append(theta.clone())
-        ctx.smc_reweight_resample_async(theta, logl, grad, beta, cfg.alpha, cfg.seed, it, bz[it], carry=hint)
-        bz_host[it].copy_(bz[it], non_blocking=True)
+            pops.append(runs.theta.clone())
+        if graph is not None:
+            graph.launch(1)
+        else:
+            runs.step()
+        if cfg.recycle:
+            pool_x.append(runs.theta.clone())
+            pool_ll.append(runs.logl.clone())
+
+    queue_one()
+    queued = 1
+    while True:
+        state_host.copy_(runs.state_dev, non_blocking=True)
         ready = torch.cuda.Event()
         ready.record()
-        beta_dev = bz[it, 0:1]
-        mm_status = torch.zeros(1, dtype=torch.int32, device=dev)   # 1: diagonal mass-matrix fallback
-        _, L, _ = ctx.mass_matrix(theta, cfg.shrink, status=mm_status)
-        mm_d.append(mm_status)
-        if cfg.metric == "local":
-            # the population factor stands in for particles whose local metric is not positive definite
-            L, _, st = ctx.local_metric(theta, 0.0, fallback=L, beta_device=beta_dev)
-            local_d.append(st.sum())
-        out = ctx.nuts_step(theta, logl, grad, L, step=cfg.step, beta=0.0, seed=cfg.seed, iteration=it,
-                            max_depth=cfg.max_depth, uturn=cfg.uturn, precision=cfg.precision, work_hint=hint,
-                            beta_device=beta_dev)
-        hint = out["n_leapfrog"] if cfg.work_hint else None
-        if cfg.recycle:
-            pool_x.append(theta.clone())
-            pool_ll.append(logl.clone())
-        nlf_d.append(out["n_leapfrog"].sum())
-        depth_d.append(out["depth"].double().mean())
-        div_d.append(out["divergent"].sum())
+        if queued < cfg.max_iter:
+            queue_one()
+            queued += 1
         yield ready
-        ready.synchronize()   # beta_t is on the host; the transition may still run
-        b, dz = float(bz_host[it, 0]), float(bz_host[it, 1])
-        if not (b > beta) and beta < 1.0:
-            torch.cuda.synchronize()
-            raise smcgw.SmcgwError("smcgw_smc_reweight_resample_async", smcgw.ERR_STALL)
-        logz += dz
-        betas.append(b)
-        dlogzs.append(dz)
-        beta = b
-        it += 1
-    recycled, ress = None, 0.0
-    if cfg.recycle and pool_ll:
-        # Sec. 5, "Samples recycling": every mutated population is a draw of its p_t
-        running, acc = [], 0.0
-        for dz in dlogzs:
-            acc += dz
-            running.append(acc)
-        _, kept, ress = ctx.recycle(torch.stack(pool_ll), betas, running, cfg.seed)
-        recycled = torch.cat(pool_x)[kept.long()]
-    torch.cuda.current_stream(dev).synchronize()   # this run's stream only: concurrent runs keep going
-    nlf = [int(x.item()) for x in nlf_d]
-    depths = [float(x.item()) for x in depth_d]
-    divs = [int(x.item()) for x in div_d]
-    fallbacks = sum(int(x.item()) for x in mm_d)
-    n_local_bad = sum(int(x.item()) for x in local_d)
-    return SmcResult(logz, betas, dlogzs, it, theta, logl, grad, nlf, depths, divs, time.perf_counter() - t0, pops,
-                     fallbacks, n_local_bad, recycled, ress)
+        ready.synchronize()
+        st = state_host.numpy()
+        if np.any(st[:, smcgw.ST_STALL] != 0):
+            torch.cuda.current_stream().synchronize()
+            raise smcgw.SmcgwError("smcgw_smc_iteration", smcgw.ERR_STALL)
+        if np.all(smcgw.runs_finished(st) | (st[:, smcgw.ST_NEXT] >= cfg.max_iter)):
+            break
+    torch.cuda.current_stream().synchronize()   # this run's stream only: concurrent runs keep going
+    if graph is not None:
+        graph.close()
+    seconds = time.perf_counter() - t0
+    state = runs.state()
+    hist = runs.history()
+    results = []
+    for r in range(n_runs):
+        n = int(state[r, smcgw.ST_NEXT])
+        h = hist[r, :n]
+        sl = runs.run_slice(r)
+        recycled, ress = None, 0.0
+        if cfg.recycle and n > 0:
+            # Sec. 5, "Samples recycling": every mutated population is a draw of its p_t, normalised by the
+            # running evidence the library recorded for iteration t
+            ll = torch.stack([x[sl] for x in pool_ll[:n]])
+            _, kept, ress = ctx.recycle(ll, h[:, smcgw.H_BETA].tolist(), h[:, smcgw.H_LOGZ].tolist(),
+                                        cfg.seed + r)
+            recycled = torch.cat([x[sl] for x in pool_x[:n]])[kept.long()]
+        results.append(SmcResult(
+            logz=float(state[r, smcgw.ST_LOGZ]), betas=h[:, smcgw.H_BETA].tolist(),
+            dlogz=h[:, smcgw.H_DLOGZ].tolist(), n_iter=n, theta=runs.theta[sl], logl=runs.logl[sl],
+            grad=runs.grad[sl], n_leapfrog=[int(v) for v in h[:, smcgw.H_LEAPFROG]],
+            mean_depth=(h[:, smcgw.H_DEPTH] / runs.P).tolist(), divergent=[int(v) for v in h[:, smcgw.H_DIVERGENT]],
+            seconds=seconds, populations=[x[sl] for x in pops[:n]] if cfg.record else None,
+            mass_matrix_fallbacks=int(h[:, smcgw.H_MM_FALLBACK].sum()),
+            local_metric_fallbacks=int(h[:, smcgw.H_METRIC_FALLBACKS].sum()),
+            recycled=recycled, recycled_ess=ress, logz_path=h[:, smcgw.H_LOGZ].tolist()))
+    return results
 
 
 def _run_persistent(ctx: "smcgw.Context", theta0: torch.Tensor, cfg: SmcConfig) -> SmcResult:
@@ -202,7 +220,7 @@ def _run_persistent(ctx: "smcgw.Context", theta0: torch.Tensor, cfg: SmcConfig) 
     pool_g = torch.empty((cap, P, D), dtype=torch.float64, device=dev)
     pool_x[0], pool_ll[0], pool_g[0] = theta, logl, grad
     pool_beta, pool_logz = [0.0], [0.0]
-    betas, dlogzs, nlf_d, depth_d, div_d, mm_d, local_d = [], [], [], [], [], [], []
+    betas, nlf_d, depth_d, div_d, mm_d, local_d = [], [], [], [], [], []
     pops = [] if cfg.record else None
     beta, it = 0.0, 0
     t0 = time.perf_counter()
@@ -231,12 +249,12 @@ def _run_persistent(ctx: "smcgw.Context", theta0: torch.Tensor, cfg: SmcConfig) 
             pool_g = torch.cat([pool_g, torch.empty_like(pool_g)])
         pool_x[T], pool_ll[T], pool_g[T] = theta, logl, grad
         betas.append(b)
-        dlogzs.append(lz - pool_logz[-1])
         pool_beta.append(b)
         pool_logz.append(lz)
         beta = b
         it += 1
     torch.cuda.synchronize()
-    return SmcResult(pool_logz[-1], betas, dlogzs, it, theta, logl, grad, [int(x.item()) for x in nlf_d],
+    return SmcResult(pool_logz[-1], betas, None, it, theta, logl, grad, [int(x.item()) for x in nlf_d],
                      [float(x.item()) for x in depth_d], [int(x.item()) for x in div_d], time.perf_counter() - t0,
-                     pops, sum(int(x.item()) for x in mm_d), sum(int(x.item()) for x in local_d))
+                     pops, sum(int(x.item()) for x in mm_d), sum(int(x.item()) for x in local_d),
+                     logz_path=pool_logz[1:])

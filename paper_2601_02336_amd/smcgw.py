@@ -51,7 +51,28 @@ class Bounds(C.Structure):
 class NutsParams(C.Structure):
     _fields_ = [("step", C.c_double), ("beta", C.c_double), ("max_delta_h", C.c_double),
                 ("max_depth", C.c_int32), ("uturn", C.c_int32), ("seed", C.c_uint64), ("iteration", C.c_uint64),
-                ("chol_per_particle", C.c_int32), ("reserved", C.c_int32), ("beta_device", C.c_void_p)]
+                ("chol_per_particle", C.c_int32), ("reserved", C.c_int32), ("beta_device", C.c_void_p),
+                ("state_device", C.c_void_p), ("run_size", C.c_int32), ("reserved2", C.c_int32)]
+
+
+# Device run state and per-iteration record (smcgw_smc_iteration): entries of one run's state and of one
+# record row.
+STATE_SIZE = 8
+ST_BETA, ST_LOGZ, ST_DLOGZ, ST_ITER, ST_NEXT, ST_DONE, ST_STALL = range(7)
+HIST_SIZE = 8
+H_BETA, H_LOGZ, H_DLOGZ, H_LEAPFROG, H_DEPTH, H_DIVERGENT, H_MM_FALLBACK, H_METRIC_FALLBACKS = range(8)
+MAX_RUNS = 64
+
+
+class SmcIterDesc(C.Structure):
+    _fields_ = [("n_runs", C.c_int32), ("P", C.c_int32), ("D", C.c_int32), ("precision", C.c_int32),
+                ("theta", C.c_void_p), ("logl", C.c_void_p), ("grad", C.c_void_p), ("ancestors", C.c_void_p),
+                ("n_leapfrog", C.c_void_p), ("depth", C.c_void_p), ("divergent", C.c_void_p),
+                ("accept_stat", C.c_void_p), ("inv_mass", C.c_void_p), ("chol", C.c_void_p),
+                ("mm_status", C.c_void_p), ("chol_pp", C.c_void_p), ("metric_status", C.c_void_p),
+                ("state", C.c_void_p), ("history", C.c_void_p), ("history_cap", C.c_int32),
+                ("max_depth", C.c_int32), ("alpha", C.c_double), ("shrink", C.c_double), ("step", C.c_double),
+                ("max_delta_h", C.c_double), ("seed", C.c_uint64), ("uturn", C.c_int32), ("reserved", C.c_int32)]
 
 
 _lib = None
@@ -115,6 +136,10 @@ def lib():
         L.smcgw_timing_read.argtypes = [vp, i, C.POINTER(d), C.POINTER(C.c_int64)]
         L.smcgw_smc_reweight_resample.argtypes = [vp, i, i, d, d, u64, u64, vp, vp, vp, vp, vp,
                                                   C.POINTER(d), C.POINTER(d)]
+        L.smcgw_smc_iteration.argtypes = [vp, C.POINTER(SmcIterDesc)]
+        L.smcgw_smc_graph_create.argtypes = [vp, C.POINTER(SmcIterDesc), C.POINTER(vp)]
+        L.smcgw_graph_launch.argtypes = [vp, i]
+        L.smcgw_graph_destroy.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -347,7 +372,7 @@ class Context:
         if beta_device is not None:
             _dev(beta_device, torch.float64, "beta_device")
         prm = NutsParams(step, 0.0 if beta_device is not None else beta, max_delta_h, max_depth, 1 if uturn else 0,
-                         seed, iteration, _chol_mode(chol, P, D), 0, _ptr(beta_device))
+                         seed, iteration, _chol_mode(chol, P, D), 0, _ptr(beta_device), None, 0, 0)
         dev = theta.device
         out = {}
         if diagnostics:
@@ -375,7 +400,7 @@ class Context:
         theta = _dev(theta, torch.float64, "theta")
         P, D = theta.shape
         prm = NutsParams(step, beta, max_delta_h, max_depth, 1 if uturn else 0, seed, iteration,
-                         _chol_mode(chol, P, D), 0, None)
+                         _chol_mode(chol, P, D), 0, None, None, 0, 0)
         best = C.c_int(0)
         times = (C.c_double * 4)()
         self._stream()
@@ -448,6 +473,99 @@ class Context:
             self._h, P, D, beta_prev, alpha, seed, iteration, _ptr(theta), _ptr(logl), _ptr(grad), _ptr(carry),
             _ptr(ancestors), _ptr(out)))
         return ancestors
+
+
+class Graph:
+    """A captured SMC iteration (smcgw_smc_graph_create), replayed on the context's current stream."""
+
+    def __init__(self, ctx: "Context", desc: SmcIterDesc):
+        self._ctx = ctx
+        self._h = C.c_void_p()
+        ctx._stream()
+        _check("smcgw_smc_graph_create", lib().smcgw_smc_graph_create(ctx._h, C.byref(desc), C.byref(self._h)))
+
+    def launch(self, count: int = 1):
+        self._ctx._stream()
+        _check("smcgw_graph_launch", lib().smcgw_graph_launch(self._h, count))
+
+    def close(self):
+        if self._h:
+            lib().smcgw_graph_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class SmcRuns:
+    """Device buffers of n_runs independent SMC runs of P particles each (run r: rows [r P, (r+1) P)) and the
+    whole-iteration call over them (smcgw_smc_iteration).  Run r draws with Philox key seed + r.  The runs'
+    states (temperature, running log evidence, iteration index, done flag) and per-iteration records stay on
+    the device; state() and history() copy them out."""
+
+    def __init__(self, ctx: "Context", theta0: torch.Tensor, n_runs: int, *, alpha: float, step: float,
+                 max_depth: int, shrink: float, seed: int, precision: int, metric: str = "population",
+                 uturn: bool = True, max_delta_h: float = 1000.0, history_cap: int = 512):
+        theta0 = _dev(theta0, torch.float64, "theta0")
+        n, D = theta0.shape
+        if n_runs < 1 or n_runs > MAX_RUNS or n % n_runs != 0:
+            raise ValueError("theta0 must hold n_runs equal runs")
+        if metric not in ("population", "local"):
+            raise ValueError(f"unknown metric {metric!r}")
+        dev = theta0.device
+        P = n // n_runs
+        self.ctx, self.n_runs, self.P, self.D = ctx, n_runs, P, D
+        self.theta = theta0.clone()
+        self.logl, self.grad = ctx.target_loglike_grad(self.theta, precision=precision)
+        i32 = dict(dtype=torch.int32, device=dev)
+        f64 = dict(dtype=torch.float64, device=dev)
+        self.ancestors = torch.zeros(n, **i32)
+        self.n_leapfrog = torch.zeros(n, **i32)
+        self.depth = torch.zeros(n, **i32)
+        self.divergent = torch.zeros(n, dtype=torch.uint8, device=dev)
+        self.accept_stat = torch.zeros(n, **f64)
+        self.inv_mass = torch.zeros((n_runs, D, D), **f64)
+        self.chol = torch.zeros((n_runs, D, D), **f64)
+        self.mm_status = torch.zeros(n_runs, **i32)
+        self.chol_pp = torch.zeros((n, D, D), **f64) if metric == "local" else None
+        self.metric_status = torch.zeros(n, **i32) if metric == "local" else None
+        self.state_dev = torch.zeros((n_runs, STATE_SIZE), **f64)
+        self.history_cap = history_cap
+        self.history_dev = torch.zeros((n_runs, history_cap, HIST_SIZE), **f64)
+        self.desc = SmcIterDesc(n_runs, P, D, precision, _ptr(self.theta), _ptr(self.logl), _ptr(self.grad),
+                                _ptr(self.ancestors), _ptr(self.n_leapfrog), _ptr(self.depth), _ptr(self.divergent),
+                                _ptr(self.accept_stat), _ptr(self.inv_mass), _ptr(self.chol), _ptr(self.mm_status),
+                                _ptr(self.chol_pp), _ptr(self.metric_status), _ptr(self.state_dev),
+                                _ptr(self.history_dev), history_cap, max_depth, alpha, shrink, step, max_delta_h,
+                                seed, 1 if uturn else 0, 0)
+
+    def step(self):
+        """Queue one iteration of every run (asynchronous)."""
+        self.ctx._stream()
+        _check("smcgw_smc_iteration", lib().smcgw_smc_iteration(self.ctx._h, C.byref(self.desc)))
+
+    def graph(self) -> Graph:
+        """A HIP graph of one iteration over these buffers."""
+        return Graph(self.ctx, self.desc)
+
+    def state(self) -> np.ndarray:
+        """[n_runs][STATE_SIZE] copy of the run states (synchronises)."""
+        return self.state_dev.cpu().numpy()
+
+    def history(self) -> np.ndarray:
+        """[n_runs][history_cap][HIST_SIZE] copy of the records (synchronises)."""
+        return self.history_dev.cpu().numpy()
+
+    def run_slice(self, r: int) -> slice:
+        return slice(r * self.P, (r + 1) * self.P)
+
+
+def runs_finished(state: np.ndarray) -> np.ndarray:
+    """Per run: True once its last iteration mutated at beta = 1, or the run has stopped."""
+    return (state[:, ST_DONE] != 0) | ((state[:, ST_BETA] >= 1.0) & (state[:, ST_NEXT] > 0))
 
 
 class LogLikelihood(torch.autograd.Function):

@@ -74,7 +74,7 @@ def test_ps_run_replays_the_oracle(smcgw):
         x0 = np.random.default_rng(seed).normal(mu0, s0, size=(2000, D))
         r = smc.run_smc(c, torch.tensor(x0, device="cuda"),
                         smc.SmcConfig(alpha=0.5, step=0.5, max_depth=6, seed=seed, precision=smcgw.PLAIN_FP64,
-                                      variant="persistent", work_hint=False))
+                                      variant="persistent"))
         c.close()
         print(f"seed {seed}: GPU log Z {r.logz:.6f} ({r.n_iter} it), oracle {lz_ref:.6f} ({it_ref} it), "
               f"exact {exact:.6f}", flush=True)
