@@ -459,59 +459,56 @@ double kinetic(int D, const double* L, const double* r) {
     return 0.5 * s;
 }
 
-// y = M v with M = (L L^T)^{-1}: solve L w = v, then L^T y = w.
-void mass_apply(int D, const double* L, const double* v, double* y) {
-    double w[64];
-    for (int i = 0; i < D; ++i) {
-        double s = v[i];
-        for (int k = 0; k < i; ++k) s -= L[i * D + k] * w[k];
-        w[i] = s / L[i * D + i];
-    }
-    for (int i = D - 1; i >= 0; --i) {
-        double s = w[i];
-        for (int k = i + 1; k < D; ++k) s -= L[k * D + i] * y[k];
-        y[i] = s / L[i * D + i];
-    }
-}
-
 // ---------------------------------------------------------------- boundaries
-// Map a position back into the prior box after a drift x += eps M^{-1} r
-// (Sec. 5, Eqs. 15-18).  A periodic coordinate wraps by the box width and the
-// momentum is untouched.  A reflective coordinate is folded back about the
-// wall it crossed (repeated until inside), and every fold reverses that
-// coordinate's velocity dx_k/dt = (M^{-1} r)_k while the other velocity
-// components are kept:
-//   r -> r - 2 (M^{-1} r)_k M e_k   (one term per coordinate folded an odd number of times).
-// With a diagonal M this is the paper's r_k -> -r_k; with a dense M it is the
-// reversal that keeps the drift-and-fold step reversible (integrating back
-// from the folded point with -r retraces it) and volume preserving (the
-// momentum map is a reflection, determinant -1, the fold another).
-void apply_boundaries(const orc_target& t, const double* L, double* x, double* r) {
+// The drift x += eps M^{-1} r of the leapfrog (Sec. 4, Eq. 12) inside the prior
+// box (Sec. 5, Eqs. 15-18).  Reflective walls: the drift runs at velocity
+// v = M^{-1} r until the first coordinate k reaches its wall, the momentum is
+// reflected there,
+//   r -> r - 2 (v_k / (M^{-1})_kk) e_k,
+// which reverses v_k and keeps the kinetic energy r^T M^{-1} r / 2, and the
+// drift goes on with the new velocity for the rest of the step (a specular
+// reflection in the metric; repeated for every wall met).  With a diagonal
+// M this is the paper's fold of the coordinate and flip of its momentum
+// component; for any M the step stays reversible (drifting back from the
+// end point with -r retraces the path) and volume preserving.  Periodic
+// coordinates wrap by the box width at the end, the momentum untouched.
+void drift(const orc_target& t, const double* L, double eps, double* x, double* r) {
     const int D = t.dim;
-    double dv[32];
-    bool any = false;
-    for (int k = 0; k < D; ++k) {
-        dv[k] = 0.0;
-        const orc_bound& b = t.bounds[k];
-        if (b.bnd == 1) {
-            int folds = 0;
-            for (int it = 0; it < 64 && (x[k] < b.lo || x[k] > b.hi); ++it) {
-                x[k] = (x[k] > b.hi) ? 2.0 * b.hi - x[k] : 2.0 * b.lo - x[k];
-                ++folds;
-            }
-            if (folds & 1) { dv[k] = 1.0; any = true; }
-        } else if (b.bnd == 2) {
-            const double w = b.hi - b.lo;
-            for (int it = 0; it < 64 && (x[k] < b.lo || x[k] >= b.hi); ++it)
-                x[k] = (x[k] >= b.hi) ? x[k] - w : x[k] + w;
-        }
-    }
-    if (!any) return;
-    double v[32], y[32];
+    double v[32], minv_kk[32];
     inv_mass_apply(D, L, r, v);
-    for (int k = 0; k < D; ++k) dv[k] = dv[k] != 0.0 ? -2.0 * v[k] : 0.0;   // velocity change
-    mass_apply(D, L, dv, y);                                                  // momentum change M dv
-    for (int k = 0; k < D; ++k) r[k] += y[k];
+    for (int k = 0; k < D; ++k) {
+        double s = 0.0;
+        for (int m = 0; m <= k; ++m) s += L[k * D + m] * L[k * D + m];
+        minv_kk[k] = s;   // (L L^T)_kk
+    }
+    double rem = 1.0;   // fraction of the step left
+    for (int it = 0; it < 64; ++it) {
+        int first = -1;
+        double frac = rem, wall = 0.0;
+        for (int k = 0; k < D; ++k) {
+            const orc_bound& b = t.bounds[k];
+            const double u = eps * v[k];
+            if (b.bnd != 1 || u == 0.0) continue;
+            const double w = u > 0.0 ? b.hi : b.lo;
+            const double f = std::max((w - x[k]) / u, 0.0);
+            if (f < frac) { frac = f; first = k; wall = w; }
+        }
+        if (first < 0) {
+            for (int k = 0; k < D; ++k) x[k] += (rem * eps) * v[k];
+            break;
+        }
+        for (int k = 0; k < D; ++k) x[k] += (frac * eps) * v[k];
+        x[first] = wall;
+        rem -= frac;
+        r[first] -= 2.0 * v[first] / minv_kk[first];
+        inv_mass_apply(D, L, r, v);
+    }
+    for (int k = 0; k < D; ++k) {
+        const orc_bound& b = t.bounds[k];
+        if (b.bnd != 2) continue;
+        const double w = b.hi - b.lo;
+        for (int it = 0; it < 64 && (x[k] < b.lo || x[k] >= b.hi); ++it) x[k] = (x[k] >= b.hi) ? x[k] - w : x[k] + w;
+    }
 }
 
 // ---------------------------------------------------------------- one state
@@ -532,11 +529,8 @@ void eval_state(const orc_target& t, double beta, State& s) {
 // One leapfrog step of size eps (negative eps integrates backwards in time).
 void leapfrog(const orc_target& t, double beta, const double* L, double eps, State& s) {
     const int D = t.dim;
-    double v[32];
     for (int k = 0; k < D; ++k) s.r[k] += 0.5 * eps * s.g[k];     // r - eps/2 dU/dx, U = -log p_t
-    inv_mass_apply(D, L, s.r, v);
-    for (int k = 0; k < D; ++k) s.x[k] += eps * v[k];
-    apply_boundaries(t, L, s.x, s.r);
+    drift(t, L, eps, s.x, s.r);
     eval_state(t, beta, s);
     for (int k = 0; k < D; ++k) s.r[k] += 0.5 * eps * s.g[k];
 }
@@ -744,10 +738,11 @@ int orc_logprior(const orc_target* t, int P, const double* x, double* lp, double
     return 0;
 }
 
-// Apply the boundary maps in place to P points (positions x, momenta r) with
-// the metric M^{-1} = chol chol^T (chol [D][D], shared by the points).
-int orc_apply_boundaries(const orc_target* t, int P, const double* chol, double* x, double* r) {
-    for (int i = 0; i < P; ++i) apply_boundaries(*t, chol, x + (size_t)i * t->dim, r + (size_t)i * t->dim);
+// The drift of one leapfrog step, x += eps M^{-1} r inside the box, in place
+// for P points (positions x, momenta r) with M^{-1} = chol chol^T (chol
+// [D][D], shared by the points).
+int orc_drift(const orc_target* t, int P, const double* chol, double eps, double* x, double* r) {
+    for (int i = 0; i < P; ++i) drift(*t, chol, eps, x + (size_t)i * t->dim, r + (size_t)i * t->dim);
     return 0;
 }
 

@@ -233,13 +233,13 @@ def logprior(target: Target, x: np.ndarray, want_grad: bool = True):
     return (lp, g) if want_grad else lp
 
 
-def apply_boundaries(target: Target, x: np.ndarray, r: np.ndarray, chol=None):
-    """Boundary maps of Sec. 5 applied to points x [P][D] with momenta r, metric M^{-1} = chol chol^T
-    (identity when chol is None)."""
+def drift(target: Target, x: np.ndarray, r: np.ndarray, eps: float, chol=None):
+    """The leapfrog drift x += eps M^{-1} r inside the prior box (reflective walls, periodic wraps) for points
+    x [P][D] with momenta r, metric M^{-1} = chol chol^T (identity when chol is None)."""
     x = _f64(x).copy()
     r = _f64(r).copy()
     L = np.eye(x.shape[1]) if chol is None else _f64(chol)
-    lib().orc_apply_boundaries(target.ptr, C.c_int(x.shape[0]), _dp(L), _dp(x), _dp(r))
+    lib().orc_drift(target.ptr, C.c_int(x.shape[0]), _dp(L), C.c_double(eps), _dp(x), _dp(r))
     return x, r
 
 

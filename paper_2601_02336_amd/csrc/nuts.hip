@@ -68,8 +68,6 @@ struct NutsShared {
     double L[MAXDIM * MAXDIM];
     double LT[MAXDIM * MAXDIM];                  // transpose of L
     double Minv[MAXDIM * MAXDIM];
-    double Linv[MAXDIM * MAXDIM];                // L^{-1}
-    double M[MAXDIM * MAXDIM];                   // the mass matrix itself, (L L^T)^{-1} (reflective walls)
     double vec[MAXDIM], red[2][MAXDIM];          // cross-lane exchange of wavefront 0
     double pred[MAXDIM];                         // cross-lane exchange of the auxiliary wavefront
     ExtAngles ang;                               // extrinsic transcendentals of the leaf in flight
@@ -174,45 +172,57 @@ __device__ __forceinline__ double log_prior_lane(const NutsShared& S, int k, dou
     }
 }
 
-// Fold this lane's coordinate back into the box: reflect about the wall it
-// crossed (repeated until inside) or wrap a periodic one.  Returns true when
-// the coordinate was reflected an odd number of times, i.e. its velocity
-// component must be reversed (see reverse_velocities).
-__device__ __forceinline__ bool boundary_lane(const NutsShared& S, int k, double& x) {
-    const double lo = S.plo[k], hi = S.phi[k];
-    bool odd = false;
-    if (S.pbnd[k] == SMCGW_BND_REFLECT) {
-        for (int it = 0; it < 64 && (x < lo || x > hi); ++it) {
-            x = (x > hi) ? 2.0 * hi - x : 2.0 * lo - x;
-            odd = !odd;
+// The drift x += eps M^{-1} r of one leapfrog step inside the prior box
+// (Sec. 4, Eq. 12; Sec. 5, Eqs. 15-18), one coordinate per lane of wavefront
+// 0, v = M^{-1} r on entry.  The drift runs at velocity v until the first
+// reflective coordinate k reaches its wall (the earliest over the lanes,
+// lowest k on ties); there the momentum is reflected in the metric,
+//   r_k -> r_k - 2 v_k / (M^{-1})_kk,   v -> v - 2 v_k / (M^{-1})_kk M^{-1} e_k,
+// which reverses v_k and keeps the kinetic energy, and the drift goes on for
+// the rest of the step.  With a diagonal metric this is the fold of the
+// coordinate and the flip of its momentum component; for any metric the step
+// stays reversible and volume preserving.  Periodic coordinates wrap at the
+// end.  A step that meets no wall costs one ballot.
+__device__ __forceinline__ void drift_lane(NutsShared& S, int D, int lane, double eps, double& x, double& r,
+                                           double v) {
+    const bool dl = lane < D;
+    const int kk = dl ? lane : 0;
+    const bool refl = dl && S.pbnd[kk] == SMCGW_BND_REFLECT;
+    const double lo = S.plo[kk], hi = S.phi[kk];
+    double rem = 1.0;   // fraction of the step left
+    for (int it = 0; it < 64; ++it) {
+        const double u = eps * v;
+        double fr = 2.0, wall = 0.0;   // fraction of the step at which this coordinate meets its wall
+        if (refl && u != 0.0) {
+            wall = u > 0.0 ? hi : lo;
+            fr = fmax((wall - x) / u, 0.0);
         }
-    } else if (S.pbnd[k] == SMCGW_BND_PERIODIC) {
+        const bool hit = fr < rem;
+        if (__ballot(hit) == 0) {
+            if (dl) x = fma(rem * eps, v, x);
+            break;
+        }
+        if (lane < MAXDIM) S.red[0][lane] = hit ? fr : 2.0;
+        __builtin_amdgcn_wave_barrier();
+        double fmin = 2.0;
+        int kmin = 0;
+#pragma unroll
+        for (int m = 0; m < MAXDIM; ++m) {
+            const double f = S.red[0][m];
+            if (f < fmin) { fmin = f; kmin = m; }
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (dl) x = lane == kmin ? wall : fma(fmin * eps, v, x);
+        rem -= fmin;
+        const double vk = __shfl(v, kmin, 64);
+        const double c = 2.0 * vk / S.Minv[kmin * MAXDIM + kmin];
+        if (lane == kmin) r -= c;
+        if (dl) v = fma(-c, S.Minv[kk * MAXDIM + kmin], v);
+    }
+    if (dl && S.pbnd[kk] == SMCGW_BND_PERIODIC) {
         const double w = hi - lo;
         for (int it = 0; it < 64 && (x < lo || x >= hi); ++it) x = (x >= hi) ? x - w : x + w;
     }
-    return odd;
-}
-
-// (M v) for this lane's coordinate, M the mass matrix.
-__device__ __forceinline__ double m_apply(NutsShared& S, int D, int lane, double v) {
-    if (lane < MAXDIM) S.vec[lane] = (lane < D) ? v : 0.0;
-    __builtin_amdgcn_wave_barrier();
-    const int row = lane < D ? lane : 0;
-    double acc = 0.0;
-#pragma unroll
-    for (int m = 0; m < MAXDIM; ++m) acc = fma(S.M[row * MAXDIM + m], S.vec[m], acc);
-    __builtin_amdgcn_wave_barrier();
-    return lane < D ? acc : 0.0;
-}
-
-// Reflective walls (Sec. 5, Eqs. 15-16) for a general metric: a coordinate
-// folded back reverses its velocity dx_k/dt = v_k = (M^{-1} r)_k and keeps the
-// other velocity components, r -> r - 2 v_k M e_k (summed over the folded
-// coordinates).  With a diagonal M this is r_k -> -r_k; with a dense M it is
-// what keeps the step reversible and volume preserving.  Called by the whole
-// wavefront only when some lane folded.
-__device__ __forceinline__ double reverse_velocities(NutsShared& S, int D, int lane, bool odd, double v, double r) {
-    return r + m_apply(S, D, lane, odd ? -2.0 * v : 0.0);
 }
 
 // Analytic likelihoods (one coordinate per lane of wavefront 0).
@@ -402,9 +412,8 @@ __device__ __noinline__ int advance(NutsShared& S, NutsState& T, const NutsArgs&
     const double eps = dir * a.step;
     double r = dl ? fma(0.5 * eps, gs, rs) : 0.0;
     const double v = minv_apply(S, D, lane, r);
-    double x = dl ? fma(eps, v, xs) : 0.0;
-    const bool odd = dl ? boundary_lane(S, lane, x) : false;
-    if (__ballot(odd) != 0) r = reverse_velocities(S, D, lane, odd, v, r);
+    double x = dl ? xs : 0.0;
+    drift_lane(S, D, lane, eps, x, r, v);
     __builtin_amdgcn_wave_barrier();
     if (dl) { T.x[lane] = x; T.r[lane] = r; }
     if (lane == 0) T.eps = eps;
@@ -715,7 +724,8 @@ __device__ __noinline__ void leaf_finish(const DevEvent* ev, NutsShared& S, Nuts
 }
 
 // The Cholesky factor L of M^{-1} ([D][D], row-major) into LDS, zero-padded
-// to MAXDIM; derive_metric then forms M^{-1} = L L^T and L^T from it.
+// to MAXDIM; derive_metric then forms M^{-1} = L L^T and L^T from it (every
+// thread a share of the entries; the caller's barrier orders them).
 __device__ __forceinline__ void load_factor(NutsShared& S, const double* chol, int D, int tid) {
     for (int i = tid; i < MAXDIM * MAXDIM; i += blockDim.x) {
         const int r = i / MAXDIM, c = i % MAXDIM;
@@ -723,9 +733,6 @@ __device__ __forceinline__ void load_factor(NutsShared& S, const double* chol, i
     }
 }
 
-// M^{-1} = L L^T, L^T, and the mass matrix M = L^{-T} L^{-1} (for the
-// reflective walls) from the factor in LDS.  Every thread of the workgroup
-// calls it (it holds a barrier).
 __device__ __noinline__ void derive_metric(NutsShared& S, int D, int tid) {
     for (int i = tid; i < MAXDIM * MAXDIM; i += blockDim.x) {
         const int r = i / MAXDIM, c = i % MAXDIM;
@@ -733,26 +740,6 @@ __device__ __noinline__ void derive_metric(NutsShared& S, int D, int tid) {
         for (int m = 0; m < D; ++m) s = fma(S.L[r * MAXDIM + m], S.L[c * MAXDIM + m], s);
         S.Minv[i] = s;
         S.LT[i] = S.L[c * MAXDIM + r];
-    }
-    // column c of L^{-1} by forward substitution, one thread per column
-    if (tid < MAXDIM) {
-        const int c = tid;
-        for (int r = 0; r < MAXDIM; ++r) {
-            double y = 0.0;
-            if (c < D && r < D && r >= c) {
-                double s = (r == c) ? 1.0 : 0.0;
-                for (int k = c; k < r; ++k) s = fma(-S.L[r * MAXDIM + k], S.Linv[k * MAXDIM + c], s);
-                y = s / S.L[r * MAXDIM + r];
-            }
-            S.Linv[r * MAXDIM + c] = y;
-        }
-    }
-    __syncthreads();
-    for (int i = tid; i < MAXDIM * MAXDIM; i += blockDim.x) {
-        const int r = i / MAXDIM, c = i % MAXDIM;
-        double s = 0.0;
-        for (int k = 0; k < D; ++k) s = fma(S.Linv[k * MAXDIM + r], S.Linv[k * MAXDIM + c], s);
-        S.M[i] = s;
     }
 }
 
@@ -826,7 +813,7 @@ __global__ __launch_bounds__(WAVES * 64, (WAVES == 1 ? 2 : NUTS_WAVES_PER_SIMD))
             derive_metric(S, D, tid);
             run_cached = run;
         }
-        __syncthreads();
+        __syncthreads();   // T's run values and the factor are visible to every wavefront
         // The particle's event descriptor is copied into LDS (all threads, ordered
         // before its first use by the barrier that follows advance), so the
         // leaf's serial phases read it without a round trip to the L2.

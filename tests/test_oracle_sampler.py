@@ -74,8 +74,8 @@ def test_leapfrog_energy_error_second_order():
 def test_leapfrog_reversible_through_boundaries(dense):
     """L steps, flip r, L steps returns to the start, across reflections and wraps (Eqs. 11-13, 15-18).
 
-    With a dense metric a fold must reverse the crossing coordinate's velocity (M^{-1} r)_k; flipping only
-    the momentum component r_k misses the start point by O(1) here."""
+    With a dense metric the wall must reflect the momentum in the metric and the drift continue with the
+    new velocity; folding the coordinate and flipping only r_k misses the start point by O(1) here."""
     D = 3
     b = [Bound(-1.0, 1.0, synth.BND_REFLECT, synth.PRIOR_FLAT),
          Bound(-1.0, 1.0, synth.BND_PERIODIC, synth.PRIOR_FLAT),
@@ -99,47 +99,81 @@ def test_leapfrog_reversible_through_boundaries(dense):
     assert crossings > 5
 
 
-def test_reflection_reverses_velocity_component():
-    """A fold reverses dx_k/dt = (M^{-1} r)_k of the crossing coordinate and keeps every other velocity
-    component; the map is an involution and, with M^{-1} diagonal, it is r_k -> -r_k (Eqs. 15-16)."""
-    b = [Bound(0.0, 1.0, synth.BND_REFLECT, synth.PRIOR_UNIFORM),
-         Bound(-2.0, 2.0, synth.BND_REFLECT, synth.PRIOR_UNIFORM),
-         Bound(0.0, 2 * math.pi, synth.BND_PERIODIC, synth.PRIOR_UNIFORM)]
-    t = O.Target(synth.TARGET_GAUSS, 3, b)
-    L = np.array([[0.9, 0.0, 0.0], [0.4, 1.1, 0.0], [-0.3, 0.6, 0.7]])
-    Minv = L @ L.T
-    x = np.array([[1.25, 0.3, 1.0], [0.4, -2.5, 8.0], [-0.1, 2.2, 1.0], [3.4, 0.0, 0.5]])
-    r = np.array([[0.5, -1.0, 0.2], [1.5, 0.3, -0.7], [-0.4, 0.9, 1.1], [0.6, 0.6, 0.6]])
-    y, s = O.apply_boundaries(t, x, r, L)
-    v0, v1 = r @ Minv, s @ Minv   # velocities before and after (Minv symmetric)
-    folds = np.array([[1, 0], [0, 1], [1, 1], [3, 0]])   # reflections of coordinates 0 and 1 (3.4 folds thrice)
-    for i in range(4):
-        sign = np.array([(-1.0) ** folds[i, 0], (-1.0) ** folds[i, 1], 1.0])
-        np.testing.assert_allclose(v1[i], sign * v0[i], rtol=1e-13, atol=1e-14)
-    # folding back from the reflected point with the reversed velocity is the identity
-    z, q = O.apply_boundaries(t, np.array([[1.0 + (1.0 - y[0, 0]), 0.3, 1.0]]), s[:1], L)
-    np.testing.assert_allclose(z[0, 0], y[0, 0], rtol=1e-15)
-    np.testing.assert_allclose(q[0], r[0], rtol=1e-13)
-    # a diagonal metric flips the momentum component itself
-    _, sd = O.apply_boundaries(t, x, r, np.diag([0.9, 1.1, 0.7]))
-    np.testing.assert_allclose(sd[:, :2], r[:, :2] * (-1.0) ** folds, rtol=1e-14)
-    np.testing.assert_allclose(sd[:, 2], r[:, 2])
-
-
-def test_boundary_maps():
+def test_drift_with_diagonal_metric_folds_and_flips():
+    """With a diagonal metric the drift through a reflective wall is the paper's rule (Sec. 5, Eqs. 15-16):
+    fold the coordinate back about the wall, once per crossing, and flip its momentum component each time;
+    a periodic coordinate wraps with its momentum untouched (Eqs. 17-18)."""
     b = [Bound(0.0, 1.0, synth.BND_REFLECT, synth.PRIOR_UNIFORM),
          Bound(0.0, 2 * math.pi, synth.BND_PERIODIC, synth.PRIOR_UNIFORM)]
     t = O.Target(synth.TARGET_GAUSS, 2, b)
-    x = np.array([[1.3, 7.0], [-0.2, -0.5], [2.6, 13.0], [0.5, 3.0]])
-    r = np.array([[1.0, 1.0], [-2.0, 3.0], [4.0, -1.0], [1.0, 1.0]])
-    y, s = O.apply_boundaries(t, x, r)
-    np.testing.assert_allclose(y[:, 0], [0.7, 0.2, 0.6, 0.5], atol=1e-15)
-    np.testing.assert_allclose(s[:, 0], [-1.0, 2.0, 4.0, 1.0])      # one flip per reflection
-    np.testing.assert_allclose(y[:, 1], np.mod(x[:, 1], 2 * math.pi), atol=1e-14)
-    np.testing.assert_allclose(s[:, 1], r[:, 1])                    # periodic: momentum untouched
-    # reflection about a bound is an involution
-    z, q = O.apply_boundaries(t, np.array([[2.0 - y[0, 0], 1.0]]), -s[:1])
-    assert z[0, 0] == pytest.approx(y[0, 0])
+    L = np.diag([0.7, 1.3])
+    x0 = np.array([[0.9, 6.0], [0.1, 0.5], [0.6, 3.0], [0.5, 3.0]])
+    r = np.array([[1.0, 1.0], [-2.0, -3.0], [4.5, -1.0], [0.2, 0.1]])
+    eps = 0.8
+    y, s = O.drift(t, x0, r, eps, L)
+    free = x0 + eps * r * np.diag(L @ L.T)
+    expect, flips = free[:, 0].copy(), np.zeros(4)
+    for i in range(4):
+        while expect[i] < 0 or expect[i] > 1:
+            expect[i] = 2 - expect[i] if expect[i] > 1 else -expect[i]
+            flips[i] += 1
+    np.testing.assert_allclose(y[:, 0], expect, atol=1e-14)
+    np.testing.assert_allclose(s[:, 0], r[:, 0] * (-1.0) ** flips, rtol=1e-14)
+    assert flips.tolist() == [1, 1, 2, 0]
+    np.testing.assert_allclose(y[:, 1], np.mod(free[:, 1], 2 * math.pi), atol=1e-13)
+    np.testing.assert_allclose(s[:, 1], r[:, 1])
+
+
+def _dense_box():
+    b = [Bound(0.0, 1.0, synth.BND_REFLECT, synth.PRIOR_UNIFORM),
+         Bound(-2.0, 2.0, synth.BND_REFLECT, synth.PRIOR_UNIFORM),
+         Bound(0.0, 2 * math.pi, synth.BND_PERIODIC, synth.PRIOR_UNIFORM)]
+    L = np.array([[0.9, 0.0, 0.0], [0.8, 0.6, 0.0], [-0.3, 0.6, 0.7]])
+    return O.Target(synth.TARGET_GAUSS, 3, b), L
+
+
+def test_drift_with_dense_metric_conserves_energy_and_reverses():
+    """Specular reflection in the metric: the kinetic energy r^T M^{-1} r / 2 is the same after any number of
+    wall reflections, and drifting back from the end point with -r returns to the start."""
+    t, L = _dense_box()
+    rng = np.random.default_rng(17)
+    x0 = rng.uniform([0.05, -1.9, 0.0], [0.95, 1.9, 6.2], size=(64, 3))
+    r0 = rng.normal(size=(64, 3)) * 3.0
+    x1, r1 = O.drift(t, x0, r0, 0.9, L)
+    Minv = L @ L.T
+    k0 = 0.5 * np.einsum("pi,ij,pj->p", r0, Minv, r0)
+    k1 = 0.5 * np.einsum("pi,ij,pj->p", r1, Minv, r1)
+    crossed = np.any(np.abs(r1 - r0) > 1e-12, axis=1)
+    assert crossed.sum() > 20
+    np.testing.assert_allclose(k1, k0, rtol=1e-12)
+    assert np.all((x1[:, 0] >= 0) & (x1[:, 0] <= 1) & (x1[:, 1] >= -2) & (x1[:, 1] <= 2))
+    x2, r2 = O.drift(t, x1, -r1, 0.9, L)
+    np.testing.assert_allclose(x2, x0, atol=1e-12)
+    np.testing.assert_allclose(-r2, r0, atol=1e-11)
+
+
+def test_drift_preserves_phase_space_volume():
+    """|det| of the Jacobian of (x, r) -> drift(x, r) is 1 at points whose path meets one or two walls
+    (central differences), as the NUTS acceptance rule needs."""
+    t, L = _dense_box()
+    pts = [(np.array([0.8, 0.5, 1.0]), np.array([2.0, 0.5, 0.3])),
+           (np.array([0.3, 1.6, 2.0]), np.array([-1.5, 2.5, -0.4])),
+           (np.array([0.9, -1.7, 5.0]), np.array([3.0, -3.0, 1.0]))]
+    for x, r in pts:
+        x1, r1 = O.drift(t, x[None], r[None], 0.7, L)
+        free = x + 0.7 * (L @ L.T) @ r
+        assert free[0] > 1 or free[0] < 0 or free[1] > 2 or free[1] < -2   # the path meets a wall
+        z = np.concatenate([x, r])
+        J = np.zeros((6, 6))
+        h = 1e-7
+        for k in range(6):
+            zp, zm = z.copy(), z.copy()
+            zp[k] += h
+            zm[k] -= h
+            a = np.concatenate(O.drift(t, zp[None, :3], zp[None, 3:], 0.7, L), axis=1)[0]
+            c = np.concatenate(O.drift(t, zm[None, :3], zm[None, 3:], 0.7, L), axis=1)[0]
+            J[:, k] = (a - c) / (2 * h)
+        assert abs(abs(np.linalg.det(J)) - 1.0) < 1e-6
 
 
 # --------------------------------------------------------------- NUTS
