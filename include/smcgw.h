@@ -170,8 +170,11 @@ typedef struct {
     double max_delta_h;             /* divergence threshold on H - H0 */
     uint64_t seed;                  /* run r uses Philox key seed + r */
     int32_t uturn;                  /* 1: NUTS stops at a U-turn */
-    int32_t reserved;               /* must be 0 */
+    int32_t nuts_form;              /* SMCGW_NUTS_PERSISTENT, or SMCGW_NUTS_SWEEPS: the plain comparison form
+                                       (smcgw_nuts_step_sweeps; precision SMCGW_PLAIN_FP64, the call then
+                                       synchronises and cannot be captured in a graph) */
 } smcgw_smc_iter_desc;
+enum { SMCGW_NUTS_PERSISTENT = 0, SMCGW_NUTS_SWEEPS = 1 };
 
 /* Message for a status code (static storage). */
 const char *smcgw_status_string(int status);
@@ -261,6 +264,19 @@ int smcgw_set_target(smcgw_ctx *ctx, int kind, int dim, const double *params, in
 int smcgw_loglike_grad(smcgw_ctx *ctx, int P, const int32_t *event_of_particle, const double *theta, double *logl,
                        double *grad, int precision);
 
+/* The plain comparison form of smcgw_loglike_grad: logL of Sec. 2, Eq. 2 with
+ * every per-bin quantity in FP64 (FP64 sin / cos, the per-bin |h|^2 written
+ * out) and the gradient by forward-mode tangents, the derivatives with
+ * respect to the 11 source parameters carried through every per-bin operation
+ * as an automatic forward-mode differentiation computes them (the paper
+ * differentiates automatically, Sec. 5 "JAX implementation").  Same
+ * arguments, layouts and results as smcgw_loglike_grad (grad NULL: the value
+ * only, the tangents are still carried).  Events added with
+ * smcgw_add_event only (SMCGW_ERR_INVALID when a relative-binning event is
+ * present). */
+int smcgw_loglike_grad_tangent(smcgw_ctx *ctx, int P, const int32_t *event_of_particle, const double *theta,
+                               double *logl, double *grad);
+
 /* logL and its gradient of the context's current target (smcgw_set_target):
  * the event likelihood (as smcgw_loglike_grad with event_of_particle taken
  * from smcgw_set_event_map) or an analytic test likelihood.  theta [P][dim],
@@ -323,6 +339,25 @@ int smcgw_nuts_step(smcgw_ctx *ctx, int P, int D, double *theta, double *logl, d
                     const smcgw_nuts_params *params, const int32_t *max_depth_per_particle,
                     const int32_t *work_hint, int precision, int32_t *depth, int32_t *n_leapfrog,
                     uint8_t *divergent, double *accept_stat);
+
+/* The plain comparison form of smcgw_nuts_step: the same transition (tree,
+ * random streams, decisions, outputs) advanced in lockstep sweeps, one
+ * leapfrog step of every unfinished particle per sweep, with the likelihood
+ * and gradient of smcgw_loglike_grad_tangent (FP64, forward-mode tangents).
+ * A sweep is one launch of the tree step (one wavefront per particle) and
+ * one batched likelihood launch over the particles still building their tree;
+ * the tree states wait in device memory between sweeps.  Sweeps run in
+ * groups of sweeps_per_group (1..64) captured once in a HIP graph (kept by the
+ * context while the arguments stay the same) and replayed; after each group
+ * the host reads the number of unfinished particles, so the call
+ * synchronises, and it returns when that number is zero.  *n_sweeps_host
+ * (may be NULL) receives the sweeps run.  Arguments as smcgw_nuts_step
+ * (state_device / run_size included, no work hint); the GW target on events
+ * added with smcgw_add_event only. */
+int smcgw_nuts_step_sweeps(smcgw_ctx *ctx, int P, int D, double *theta, double *logl, double *grad,
+                           const double *chol, const smcgw_nuts_params *params,
+                           const int32_t *max_depth_per_particle, int32_t *depth, int32_t *n_leapfrog,
+                           uint8_t *divergent, double *accept_stat, int sweeps_per_group, int *n_sweeps_host);
 
 /* Reweighting, adaptive temperature and multinomial resampling of one SMC
  * iteration (Sec. 3, Eqs. 4-6): beta_next solves ESS(beta) = alpha P by

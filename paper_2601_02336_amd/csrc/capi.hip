@@ -123,6 +123,8 @@ extern "C" int smcgw_destroy(smcgw_ctx* c) {
     hipFree(c->d_small);
     hipFree(c->d_cb);
     hipFree(c->d_mom);
+    hipFree(c->d_tan);
+    c->sweep_free();
     c->sampler_free();
     for (auto& v : c->ev_pending)
         for (auto& pr : v) { hipEventDestroy(pr.first); hipEventDestroy(pr.second); }
@@ -198,10 +200,13 @@ static void site_geometry(const smcgw_detector& s, double pos[3], double resp[3]
 }
 
 namespace smcgw {
+// Buffers of one event's tables.
+constexpr int EVENT_BUFS = 5;
+
 // Builds the full-grid tables of one event on the device (synchronises).  On
-// success de describes them and bufs holds fwl, u32, u64 and wmom.
+// success de describes them and bufs holds fwl, u32, u64, wmom and wa2.
 static int build_event(smcgw_ctx* c, const smcgw_event_desc* ev, const double* data_reim, const double* psd,
-                       const smcgw_detector* dets, DevEvent& de, void* bufs[4]) {
+                       const smcgw_detector* dets, DevEvent& de, void* bufs[EVENT_BUFS]) {
     const int n = ev->n_bins, nd = ev->n_det;
     const int npad = ((n + TABLE_PAD - 1) / TABLE_PAD) * TABLE_PAD;
     // Power-of-two scale of the whitened data, so the FP32 table sits near unit magnitude.
@@ -216,11 +221,12 @@ static int build_event(smcgw_ctx* c, const smcgw_event_desc* ev, const double* d
     const double us = umax > 0.0 ? std::ldexp(1.0, (int)std::lround(std::log2(umax))) : 1.0;
 
     hipSetDevice(c->device);
-    double *d_data = nullptr, *d_psd = nullptr, *fwl = nullptr, *sums = nullptr, *wmom = nullptr;
+    double *d_data = nullptr, *d_psd = nullptr, *fwl = nullptr, *sums = nullptr, *wmom = nullptr, *wa2 = nullptr;
     float2* u32 = nullptr;
     double2* u64 = nullptr;
     auto fail = [&](int code) {
         hipFree(d_data); hipFree(d_psd); hipFree(fwl); hipFree(u32); hipFree(u64); hipFree(sums); hipFree(wmom);
+        hipFree(wa2);
         return code;
     };
     if (hipMalloc(&d_data, sizeof(double) * 2 * nd * (size_t)n) != hipSuccess ||
@@ -229,12 +235,13 @@ static int build_event(smcgw_ctx* c, const smcgw_event_desc* ev, const double* d
         hipMalloc(&u32, sizeof(float2) * nd * (size_t)npad) != hipSuccess ||
         hipMalloc(&u64, sizeof(double2) * nd * (size_t)npad) != hipSuccess ||
         hipMalloc(&sums, sizeof(double) * 2 * MAXDET) != hipSuccess ||
-        hipMalloc(&wmom, sizeof(double) * nd * NGEO * NGEO) != hipSuccess)
+        hipMalloc(&wmom, sizeof(double) * nd * NGEO * NGEO) != hipSuccess ||
+        hipMalloc(&wa2, sizeof(double) * nd * (size_t)npad) != hipSuccess)
         return fail(SMCGW_ERR_OOM);
     if (hipMemcpyAsync(d_data, data_reim, sizeof(double) * 2 * nd * (size_t)n, hipMemcpyHostToDevice, c->stream) ||
         hipMemcpyAsync(d_psd, psd, sizeof(double) * nd * (size_t)n, hipMemcpyHostToDevice, c->stream))
         return fail(SMCGW_ERR_HIP);
-    if (launch_build_tables(d_data, d_psd, nd, n, npad, ev->f_low, ev->df, us, fwl, u32, u64, sums, c->stream) ||
+    if (launch_build_tables(d_data, d_psd, nd, n, npad, ev->f_low, ev->df, us, fwl, u32, u64, wa2, sums, c->stream) ||
         launch_metric_moments(d_psd, nd, n, ev->f_low, ev->df, us, wmom, c->stream))
         return fail(SMCGW_ERR_HIP);
     double hs[2 * MAXDET];
@@ -256,6 +263,7 @@ static int build_event(smcgw_ctx* c, const smcgw_event_desc* ev, const double* d
     de.u32 = u32;
     de.u64 = u64;
     de.wmom = wmom;
+    de.wa2 = wa2;
     de.dd = 0.0;
     for (int d = 0; d < nd; ++d) {
         de.hnorm[d] = hs[2 * d] / (us * us);
@@ -272,6 +280,7 @@ static int build_event(smcgw_ctx* c, const smcgw_event_desc* ev, const double* d
     bufs[1] = u32;
     bufs[2] = u64;
     bufs[3] = wmom;
+    bufs[4] = wa2;
     return SMCGW_OK;
 }
 
@@ -285,15 +294,16 @@ static int check_event_desc(smcgw_ctx* c, const smcgw_event_desc* ev) {
     return SMCGW_OK;
 }
 
-static int register_event(smcgw_ctx* c, const DevEvent& de, void* const bufs[4], int* event_id) {
+static int register_event(smcgw_ctx* c, const DevEvent& de, void* const bufs[EVENT_BUFS], int* event_id) {
     const int id = (int)c->events.size();
     if (hipMemcpyAsync(c->d_events + id, &de, sizeof(de), hipMemcpyHostToDevice, c->stream) ||
         hipStreamSynchronize(c->stream)) {
-        for (int k = 0; k < 4; ++k) hipFree(bufs[k]);
+        for (int k = 0; k < EVENT_BUFS; ++k) hipFree(bufs[k]);
         return SMCGW_ERR_HIP;
     }
     c->events.push_back(de);
-    for (int k = 0; k < 4; ++k) c->event_bufs.push_back(bufs[k]);
+    for (int k = 0; k < EVENT_BUFS; ++k)
+        if (bufs[k]) c->event_bufs.push_back(bufs[k]);
     c->n_det = de.n_det;
     if (event_id) *event_id = id;
     return SMCGW_OK;
@@ -306,7 +316,7 @@ extern "C" int smcgw_add_event(smcgw_ctx* c, const smcgw_event_desc* ev, const d
     int rc = check_event_desc(c, ev);
     if (rc) return rc;
     DevEvent de;
-    void* bufs[4];
+    void* bufs[EVENT_BUFS];
     rc = build_event(c, ev, data_reim, psd, dets, de, bufs);
     if (rc) return rc;
     return register_event(c, de, bufs, event_id);
@@ -354,7 +364,7 @@ extern "C" int smcgw_add_event_rb(smcgw_ctx* c, const smcgw_event_desc* ev, cons
     const int ne = smcgw_rb_edges(ev->f_low, ev->df, ev->n_bins, eps, ej.data(), (int)ej.size());
     if (ne < 2) return ne < 0 ? ne : SMCGW_ERR_SHAPE;
     DevEvent full;
-    void* fb[4];
+    void* fb[EVENT_BUFS];
     rc = build_event(c, ev, data_reim, psd, dets, full, fb);
     if (rc) return rc;
     const int n = ev->n_bins, nd = ev->n_det, id = (int)c->events.size();
@@ -365,7 +375,7 @@ extern "C" int smcgw_add_event_rb(smcgw_ctx* c, const smcgw_event_desc* ev, cons
     int32_t *d_edges = nullptr, *d_id = nullptr;
     auto release = [&]() {
         hipFree(v); hipFree(a0); hipFree(a1); hipFree(d_edges); hipFree(cb0); hipFree(th0); hipFree(d_id);
-        hipFree(fb[0]); hipFree(fb[1]); hipFree(fb[2]);
+        hipFree(fb[0]); hipFree(fb[1]); hipFree(fb[2]); hipFree(fb[4]);
     };
     auto fail = [&](int code) {
         release();
@@ -404,7 +414,8 @@ extern "C" int smcgw_add_event_rb(smcgw_ctx* c, const smcgw_event_desc* ev, cons
     de.fwl = fwl;
     de.u32 = u32;
     de.u64 = u64;
-    void* bufs[4] = {fwl, u32, u64, fb[3]};
+    de.wa2 = nullptr;   // the plain form's per-bin <h|h> needs the full grid
+    void* bufs[EVENT_BUFS] = {fwl, u32, u64, fb[3], nullptr};
     rc = register_event(c, de, bufs, event_id);
     if (rc == SMCGW_OK && n_edges) *n_edges = ne;
     return rc;

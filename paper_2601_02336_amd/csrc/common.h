@@ -147,6 +147,8 @@ struct DevEvent {
     double pos[MAXDET][3];   // detector positions [m]
     double resp[MAXDET][3][3];
     const double* wmom;      // [n_det][NGEO][NGEO]: sum_j 4 df f^-7/3 / S / u_scale^2 g_a g_b (local metric)
+    const double* wa2;       // [n_det][n_pad]: 4 df f^-7/3 / S / u_scale^2 per bin (plain form; NULL for a
+                             // relative-binning event)
 };
 
 // Functions of f whose combination is the phase of detector d in cycles:
@@ -205,7 +207,7 @@ hipError_t launch_rb_tables(const double* fwl_full, const double2* u64_full, int
                             int npad, double* fwl, float2* u32, double2* u64, hipStream_t s);
 hipError_t launch_build_tables(const double* d_data, const double* d_psd, int n_det, int n_bins, int n_pad,
                                double f_low, double df, double u_scale, double* fwl, float2* u32, double2* u64,
-                               double* sums, hipStream_t s);
+                               double* wa2, double* sums, hipStream_t s);
 hipError_t launch_prep(const DevEvent* d_events, int n_events, const int32_t* ev_of_p, const ParamMap& pm, int P,
                        const double* theta, double* cb, hipStream_t s);
 hipError_t launch_bins(const DevEvent* d_events, int n_events, const int32_t* ev_of_p, int P, int n_det, int precision,

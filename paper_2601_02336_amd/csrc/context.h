@@ -35,6 +35,8 @@ struct smcgw_ctx {
     double* d_cb = nullptr;
     double* d_mom = nullptr;
     int cap = 0;
+    double* d_tan = nullptr;               // tangent moment blocks of the plain form, [tan_cap][12]
+    int tan_cap = 0;
     // sampler state
     bool prior_set = false;
     smcgw::PriorDesc prior{};
@@ -53,10 +55,28 @@ struct smcgw_ctx {
     void* d_sampler = nullptr;
     size_t sampler_bytes = 0;
     double* h_pinned = nullptr;            // small pinned host buffer for scalar read-backs
+    // lockstep-sweep transition (the plain comparison form): tree states, next positions, their
+    // likelihoods, active flags and count; the captured group of sweeps and the arguments it was captured for
+    void* d_sweep = nullptr;
+    size_t sweep_bytes = 0;
+    hipGraph_t sweep_graph = nullptr;
+    hipGraphExec_t sweep_exec = nullptr;
+    std::vector<unsigned char> sweep_key;
     // kernel timing (events recorded around launches when enabled)
     unsigned timing_mask = 0;              // bit c: time kernel class c
     std::vector<hipEvent_t> ev_pool;       // free events
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending[SMCGW_KERNEL_CLASSES];
+
+    void sweep_free() {
+        if (sweep_exec) hipGraphExecDestroy(sweep_exec);
+        if (sweep_graph) hipGraphDestroy(sweep_graph);
+        sweep_exec = nullptr;
+        sweep_graph = nullptr;
+        sweep_key.clear();
+        hipFree(d_sweep);
+        d_sweep = nullptr;
+        sweep_bytes = 0;
+    }
 
     void sampler_free() {
         hipFree(d_target_params);
@@ -90,6 +110,7 @@ struct TimedLaunch {
 int ctx_reserve(smcgw_ctx* c, int P);
 // SMC pieces queued by smcgw_smc_iteration (smc.hip, metric.hip, nuts.hip).
 void* sampler_scratch(smcgw_ctx* c, size_t bytes);
+double* pinned(smcgw_ctx* c);
 size_t reweight_scratch_bytes(int n_runs, int P, int D);
 int queue_reweight_resample(smcgw_ctx* c, int n_runs, int P, int D, double beta_prev, double alpha, uint64_t seed,
                             uint64_t iteration, double* theta, double* logl, double* grad, int32_t* carry,
@@ -103,6 +124,11 @@ int queue_record(smcgw_ctx* c, int n_runs, int P, const int32_t* nlf, const int3
                  const int32_t* mm_status, const int32_t* metric_status, const double* st, double* hist,
                  int hist_cap);
 int nuts_reserve(smcgw_ctx* c, int P, bool hint);
+// The plain form of the likelihood (plain.hip).
+int tangent_reserve(smcgw_ctx* c, int P);
+int queue_loglike_tangent(smcgw_ctx* c, int P, const int32_t* ev_of_p, const double* theta, const uint8_t* active,
+                          double* logl, double* grad);
+bool tangent_supported(const smcgw_ctx* c);
 int ctx_loglike(smcgw_ctx* c, int P, const int32_t* ev_of_p, const double* theta, double* logl, double* grad,
                 int precision);
 }  // namespace smcgw

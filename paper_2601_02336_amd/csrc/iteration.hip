@@ -29,8 +29,10 @@ int check_desc(smcgw_ctx* c, const smcgw_smc_iter_desc* d) {
     if ((size_t)d->n_runs * d->P > (size_t)INT32_MAX / 2) return SMCGW_ERR_SHAPE;
     if (!d->theta || !d->logl || !d->grad || !d->ancestors || !d->n_leapfrog || !d->depth || !d->divergent ||
         !d->inv_mass || !d->chol || !d->mm_status || !d->state || (d->chol_pp && !d->metric_status) ||
-        (d->history && d->history_cap < 1) || d->reserved != 0)
+        (d->history && d->history_cap < 1))
         return SMCGW_ERR_INVALID;
+    if (d->nuts_form != SMCGW_NUTS_PERSISTENT && d->nuts_form != SMCGW_NUTS_SWEEPS) return SMCGW_ERR_INVALID;
+    if (d->nuts_form == SMCGW_NUTS_SWEEPS && d->precision != SMCGW_PLAIN_FP64) return SMCGW_ERR_INVALID;
     if (d->precision != SMCGW_PLAIN_FP64 && d->precision != SMCGW_MIXED) return SMCGW_ERR_INVALID;
     if (!(d->alpha > 0.0 && d->alpha <= 1.0) || !(d->shrink >= 0.0) || !(d->step > 0.0) || !(d->max_delta_h > 0.0) ||
         d->max_depth < 0 || d->max_depth > SMCGW_MAX_DEPTH)
@@ -77,9 +79,15 @@ int queue(smcgw_ctx* c, const smcgw_smc_iter_desc* d) {
     prm.chol_per_particle = d->chol_pp ? 1 : 0;
     prm.state_device = d->state;
     prm.run_size = P;
-    // the leapfrog counts gathered with the particles are the start-order hint, then the new counts
-    rc = smcgw_nuts_step(c, n, D, d->theta, d->logl, d->grad, d->chol_pp ? d->chol_pp : d->chol, &prm, nullptr,
-                         d->n_leapfrog, d->precision, d->depth, d->n_leapfrog, d->divergent, d->accept_stat);
+    if (d->nuts_form == SMCGW_NUTS_SWEEPS) {
+        rc = smcgw_nuts_step_sweeps(c, n, D, d->theta, d->logl, d->grad, d->chol_pp ? d->chol_pp : d->chol, &prm,
+                                    nullptr, d->depth, d->n_leapfrog, d->divergent, d->accept_stat, 8, nullptr);
+    } else {
+        // the leapfrog counts gathered with the particles are the start-order hint, then the new counts
+        rc = smcgw_nuts_step(c, n, D, d->theta, d->logl, d->grad, d->chol_pp ? d->chol_pp : d->chol, &prm,
+                             nullptr, d->n_leapfrog, d->precision, d->depth, d->n_leapfrog, d->divergent,
+                             d->accept_stat);
+    }
     if (rc) return rc;
     if (d->history)
         rc = queue_record(c, R, P, d->n_leapfrog, d->depth, d->divergent, d->mm_status,
@@ -102,6 +110,7 @@ extern "C" int smcgw_smc_graph_create(smcgw_ctx* c, const smcgw_smc_iter_desc* d
     *out = nullptr;
     int rc = check_desc(c, desc);
     if (rc) return rc;
+    if (desc->nuts_form != SMCGW_NUTS_PERSISTENT) return SMCGW_ERR_INVALID;   // the sweeps wait for the host
     rc = reserve(c, desc);
     if (rc) return rc;
     hipStream_t cap = nullptr;

@@ -20,6 +20,8 @@
 // Random numbers come from Philox4x32-10 with counter (index, particle,
 // iteration, purpose), so every decision can be replayed.
 #include <algorithm>
+#include <cstring>
+#include <vector>
 
 #include "binloop.h"
 #include "coeffs.h"
@@ -945,6 +947,165 @@ __global__ __launch_bounds__(ORDER_THREADS) void order_kernel(const int32_t* __r
 
 __global__ void zero_int_kernel(int* q) { *q = 0; }
 
+// ------------------------------------------------------------------ lockstep sweeps
+// The plain comparison form of the transition: the same tree, random streams
+// and decisions as nuts_kernel, but advanced one leapfrog step per particle per
+// sweep.  A sweep is one launch of nuts_sweep_kernel (one wavefront per
+// particle: the tree step that books the leaf just evaluated and moves to the
+// next one) and one batched likelihood launch over the particles still
+// building their tree; the tree state waits in global memory between sweeps.
+
+// A particle's tree between sweeps.
+struct SweepState {
+    NutsState T;
+    double left[5][MAXDIM], right[5][MAXDIM];
+    double prop[2][MAXDIM], sprop[2][MAXDIM];
+    double ck_rho[MAXD1][MAXDIM], ck_v[MAXD1][MAXDIM];
+    double end_ll[2], end_lp[2];
+    int phase;
+    int pad;
+};
+static_assert(sizeof(NutsState) % 8 == 0 && sizeof(SweepState) % 8 == 0, "copied in 8-byte words");
+enum { SW_START = 0, SW_RUN = 1, SW_DONE = 2 };
+
+__device__ __forceinline__ void copy_words(void* dst, const void* src, size_t bytes, int lane) {
+    unsigned long long* d = (unsigned long long*)dst;
+    const unsigned long long* s = (const unsigned long long*)src;
+    for (size_t i = lane; i < bytes / 8; i += 64) d[i] = s[i];
+}
+
+// Tree state between LDS and the particle's record.
+__device__ __forceinline__ void sweep_save(SweepState& G, const NutsShared& S, const NutsState& T, int lane) {
+    copy_words(&G.T, &T, sizeof(NutsState), lane);
+    copy_words(G.left, S.left, sizeof(S.left), lane);
+    copy_words(G.right, S.right, sizeof(S.right), lane);
+    copy_words(G.prop, S.prop, sizeof(S.prop), lane);
+    copy_words(G.sprop, S.sprop, sizeof(S.sprop), lane);
+    copy_words(G.ck_rho, S.ck_rho, sizeof(S.ck_rho), lane);
+    copy_words(G.ck_v, S.ck_v, sizeof(S.ck_v), lane);
+    copy_words(G.end_ll, S.end_ll, sizeof(S.end_ll), lane);
+    copy_words(G.end_lp, S.end_lp, sizeof(S.end_lp), lane);
+}
+
+__device__ __forceinline__ void sweep_load(const SweepState& G, NutsShared& S, NutsState& T, int lane) {
+    copy_words(&T, &G.T, sizeof(NutsState), lane);
+    copy_words(S.left, G.left, sizeof(S.left), lane);
+    copy_words(S.right, G.right, sizeof(S.right), lane);
+    copy_words(S.prop, G.prop, sizeof(S.prop), lane);
+    copy_words(S.sprop, G.sprop, sizeof(S.sprop), lane);
+    copy_words(S.ck_rho, G.ck_rho, sizeof(S.ck_rho), lane);
+    copy_words(S.ck_v, G.ck_v, sizeof(S.ck_v), lane);
+    copy_words(S.end_ll, G.end_ll, sizeof(S.end_ll), lane);
+    copy_words(S.end_lp, G.end_lp, sizeof(S.end_lp), lane);
+}
+
+// Every particle starts its transition; the next-position rows hold the
+// current points until the first sweep replaces them.
+__global__ __launch_bounds__(256) void sweep_init_kernel(SweepState* __restrict__ st, uint8_t* __restrict__ active,
+                                                         const double* __restrict__ theta, double* __restrict__ x_next,
+                                                         int P, int D) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    st[p].phase = SW_START;
+    active[p] = 1;
+    for (int k = 0; k < D; ++k) x_next[(size_t)p * D + k] = theta[(size_t)p * D + k];
+}
+
+// One tree step of particle p = blockIdx.x: the transition's start on the
+// first sweep, else the booking of the leaf whose likelihood ll_in / gl_in
+// the batched likelihood has just computed; then either the next leaf's
+// position (x_next, active = 1) or the transition's outputs (active = 0).
+__global__ __launch_bounds__(64) void nuts_sweep_kernel(NutsArgs a, PriorDesc pri, ParamMap pm,
+                                                        SweepState* __restrict__ st,
+                                                        const double* __restrict__ ll_in,
+                                                        const double* __restrict__ gl_in,
+                                                        double* __restrict__ x_next, uint8_t* __restrict__ active) {
+    __shared__ NutsShared S;
+    __shared__ NutsState T;
+    __shared__ NutsArgs A;
+    const int p = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int D = a.D;
+    SweepState& G = st[p];
+    const int phase = __builtin_amdgcn_readfirstlane(G.phase);
+    if (phase == SW_DONE) return;
+    const int run = a.state ? p / a.run_size : 0;
+    if (a.state && a.state[(size_t)run * SMCGW_STATE_SIZE + SMCGW_ST_DONE] != 0.0) {
+        if (lane == 0) { G.phase = SW_DONE; active[p] = 0; }   // a finished run's particles are left untouched
+        return;
+    }
+    const double* chol = a.chol_pp ? a.chol + (size_t)p * D * D : a.state ? a.chol + (size_t)run * D * D : a.chol;
+    load_factor(S, chol, D, lane);
+    if (lane == 0) {
+        A = a;
+        if (a.beta_dev) A.beta = *a.beta_dev;
+        for (int k = 0; k < MAXDIM; ++k) {
+            S.plo[k] = pri.lo[k]; S.phi[k] = pri.hi[k]; S.pbnd[k] = pri.bnd[k]; S.pkind[k] = pri.kind[k];
+            S.pidx[k] = pm.idx[k];
+            const double lo = pri.lo[k], hi = pri.hi[k];
+            S.pnorm[k] = k >= D ? 0.0
+                       : pri.kind[k] == SMCGW_PRIOR_UNIFORM ? -log(hi - lo)
+                       : pri.kind[k] == SMCGW_PRIOR_LOGUNIFORM ? -log(log(hi / lo))
+                       : pri.kind[k] == SMCGW_PRIOR_GAUSSIAN ? -0.5 * log(2.0 * PI * hi * hi) : 0.0;
+        }
+        for (int k = 0; k < NPAR; ++k) S.pfixed[k] = pm.fixed[k];
+    }
+    __syncthreads();
+    derive_metric(S, D, lane);
+    if (phase == SW_START) {
+        if (lane == 0) {
+            if (a.state) {
+                const double* rs = a.state + (size_t)run * SMCGW_STATE_SIZE;
+                T.beta = rs[SMCGW_ST_BETA];
+                T.iter = (uint64_t)rs[SMCGW_ST_ITER];
+                T.seed = a.seed + (uint64_t)run;
+                T.pid = (uint32_t)(p - run * a.run_size);
+            } else {
+                T.beta = A.beta;
+                T.iter = a.iteration;
+                T.seed = a.seed;
+                T.pid = (uint32_t)p;
+            }
+        }
+        __syncthreads();
+        start_transition(S, T, A, p, lane);
+    } else {
+        sweep_load(G, S, T, lane);
+        __syncthreads();
+        if (lane < D) T.gl_new[lane] = gl_in[(size_t)p * D + lane];
+        if (lane == 0) T.ll_new = ll_in[p];
+    }
+    __syncthreads();
+    const int cmd = advance<SMCGW_TARGET_GW>(S, T, A, lane);
+    bookkeep(S, T, A, p, lane);
+    __syncthreads();
+    if (cmd == CMD_DONE || __builtin_amdgcn_readfirstlane(T.stop)) {
+        write_outputs(S, T, A, p, lane);
+        if (lane == 0) { G.phase = SW_DONE; active[p] = 0; }
+        return;
+    }
+    aux_in_flight<SMCGW_TARGET_GW>(a.events + event_index(a.ev_of_p, p, a.n_events), S, T, A, p, lane);
+    __syncthreads();
+    if (lane < D) x_next[(size_t)p * D + lane] = T.x[lane];
+    sweep_save(G, S, T, lane);
+    if (lane == 0) { G.phase = SW_RUN; active[p] = 1; }
+}
+
+// Particles still building their tree (one workgroup).
+__global__ __launch_bounds__(256) void sweep_count_kernel(const uint8_t* __restrict__ active, int P,
+                                                          int* __restrict__ count) {
+    __shared__ int part[256];
+    int n = 0;
+    for (int i = threadIdx.x; i < P; i += blockDim.x) n += active[i];
+    part[threadIdx.x] = n;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int s = 0;
+        for (int t = 0; t < 256; ++t) s += part[t];
+        *count = s;
+    }
+}
+
 }  // namespace smcgw
 
 using namespace smcgw;
@@ -1145,3 +1306,165 @@ extern "C" int smcgw_autotune_nuts(smcgw_ctx* c, int P, int D, const double* the
     return rc;
 }
 
+namespace {
+
+// Scratch of the sweep form: tree states [P], next positions [P][D], their
+// logL [P] and gradients [P][D], active flags [P] and the active count.
+struct SweepScratch {
+    SweepState* st;
+    double *x_next, *ll, *gl;
+    uint8_t* active;
+    int* count;
+};
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+int sweep_reserve(smcgw_ctx* c, int P, int D, SweepScratch& s) {
+    const size_t b_st = align256((size_t)P * sizeof(SweepState));
+    const size_t b_x = align256((size_t)P * D * sizeof(double));
+    const size_t b_ll = align256((size_t)P * sizeof(double));
+    const size_t b_act = align256((size_t)P);
+    const size_t need = b_st + 2 * b_x + b_ll + b_act + 256;
+    if (need > c->sweep_bytes) {
+        c->sweep_free();
+        if (hipMalloc(&c->d_sweep, need) != hipSuccess) return SMCGW_ERR_OOM;
+        c->sweep_bytes = need;
+    }
+    char* base = (char*)c->d_sweep;
+    s.st = (SweepState*)base;
+    s.x_next = (double*)(base + b_st);
+    s.ll = (double*)(base + b_st + b_x);
+    s.gl = (double*)(base + b_st + b_x + b_ll);
+    s.active = (uint8_t*)(base + b_st + 2 * b_x + b_ll);
+    s.count = (int*)(base + b_st + 2 * b_x + b_ll + b_act);
+    return SMCGW_OK;
+}
+
+// One group of sweeps and the active count, on the context's stream.
+int queue_sweep_group(smcgw_ctx* c, const NutsArgs& a, const SweepScratch& s, int sweeps) {
+    for (int k = 0; k < sweeps; ++k) {
+        {
+            TimedLaunch tl(c, SMCGW_KERNEL_NUTS);
+            hipLaunchKernelGGL(nuts_sweep_kernel, dim3(a.P), dim3(64), 0, c->stream, a, c->prior, c->pmap, s.st,
+                               (const double*)s.ll, (const double*)s.gl, s.x_next, s.active);
+        }
+        if (hipGetLastError() != hipSuccess) return SMCGW_ERR_HIP;
+        const int rc = queue_loglike_tangent(c, a.P, c->ev_of_p, s.x_next, s.active, s.ll, s.gl);
+        if (rc) return rc;
+    }
+    hipLaunchKernelGGL(sweep_count_kernel, dim3(1), dim3(256), 0, c->stream, (const uint8_t*)s.active, a.P, s.count);
+    return hipGetLastError() == hipSuccess ? SMCGW_OK : SMCGW_ERR_HIP;
+}
+
+}  // namespace
+
+extern "C" int smcgw_nuts_step_sweeps(smcgw_ctx* c, int P, int D, double* theta, double* logl, double* grad,
+                                      const double* chol, const smcgw_nuts_params* prm,
+                                      const int32_t* max_depth_per_particle, int32_t* depth, int32_t* n_leapfrog,
+                                      uint8_t* divergent, double* accept_stat, int sweeps_per_group,
+                                      int* n_sweeps_host) {
+    if (!c || !prm || P < 0 || D <= 0 || D > MAXDIM || (P > 0 && (!theta || !logl || !grad || !chol)) ||
+        sweeps_per_group < 1 || sweeps_per_group > 64)
+        return SMCGW_ERR_INVALID;
+    if (prm->max_depth < 0 || prm->max_depth > SMCGW_MAX_DEPTH || !(prm->step > 0.0) ||
+        (!prm->beta_device && !prm->state_device && !(prm->beta >= 0.0)) || !(prm->max_delta_h > 0.0) ||
+        (prm->chol_per_particle != 0 && prm->chol_per_particle != 1) || prm->reserved != 0 || prm->reserved2 != 0)
+        return SMCGW_ERR_INVALID;
+    if (prm->state_device && (prm->run_size < 1 || P % prm->run_size != 0 || P / prm->run_size > SMCGW_MAX_RUNS))
+        return SMCGW_ERR_INVALID;
+    if (!c->prior_set || c->prior.dim != D || c->target.kind != SMCGW_TARGET_GW || c->events.empty() ||
+        c->pmap.dim != D)
+        return SMCGW_ERR_NOT_INIT;
+    if (!tangent_supported(c)) return SMCGW_ERR_INVALID;
+    if (n_sweeps_host) *n_sweeps_host = 0;
+    if (P == 0) return SMCGW_OK;
+    hipSetDevice(c->device);
+    SweepScratch s;
+    int rc = tangent_reserve(c, P);
+    if (rc == SMCGW_OK) rc = sweep_reserve(c, P, D, s);
+    int* hp = (int*)pinned(c);
+    if (rc) return rc;
+    if (!hp) return SMCGW_ERR_OOM;
+    NutsArgs a{};
+    a.P = P;
+    a.D = D;
+    a.theta = theta;
+    a.logl = logl;
+    a.grad = grad;
+    a.chol = chol;
+    a.step = prm->step;
+    a.beta = prm->beta;
+    a.max_dh = prm->max_delta_h;
+    a.max_depth = prm->max_depth;
+    a.uturn = prm->uturn ? 1 : 0;
+    a.seed = prm->seed;
+    a.iteration = prm->iteration;
+    a.md_per_p = max_depth_per_particle;
+    a.depth_out = depth;
+    a.nlf_out = n_leapfrog;
+    a.div_out = divergent;
+    a.acc_out = accept_stat;
+    a.events = c->d_events;
+    a.n_events = (int)c->events.size();
+    a.ev_of_p = c->ev_of_p;
+    a.chol_pp = prm->chol_per_particle;
+    a.beta_dev = prm->beta_device;
+    a.state = prm->state_device;
+    a.run_size = prm->state_device ? prm->run_size : P;
+    hipLaunchKernelGGL(sweep_init_kernel, dim3((P + 255) / 256), dim3(256), 0, c->stream, s.st, s.active,
+                       (const double*)theta, s.x_next, P, D);
+    if (hipGetLastError() != hipSuccess) return SMCGW_ERR_HIP;
+    // the group graph is captured once for these arguments and replayed
+    std::vector<unsigned char> key(sizeof(NutsArgs) + sizeof(PriorDesc) + sizeof(ParamMap) + 3 * sizeof(int));
+    unsigned char* kp = key.data();
+    std::memcpy(kp, &a, sizeof(a));
+    std::memcpy(kp + sizeof(a), &c->prior, sizeof(PriorDesc));
+    std::memcpy(kp + sizeof(a) + sizeof(PriorDesc), &c->pmap, sizeof(ParamMap));
+    const int extra[3] = {sweeps_per_group, c->n_det, (int)(c->timing_mask != 0)};
+    std::memcpy(kp + sizeof(a) + sizeof(PriorDesc) + sizeof(ParamMap), extra, sizeof(extra));
+    if (key != c->sweep_key || !c->sweep_exec) {
+        if (c->sweep_exec) hipGraphExecDestroy(c->sweep_exec);
+        if (c->sweep_graph) hipGraphDestroy(c->sweep_graph);
+        c->sweep_exec = nullptr;
+        c->sweep_graph = nullptr;
+        c->sweep_key.clear();
+        hipStream_t cap = nullptr;
+        if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return SMCGW_ERR_HIP;
+        const hipStream_t saved = c->stream;
+        const unsigned saved_mask = c->timing_mask;
+        c->stream = cap;
+        c->timing_mask = 0;   // no timing events inside the graph
+        bool ok = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        hipGraph_t g = nullptr;
+        if (ok) {
+            rc = queue_sweep_group(c, a, s, sweeps_per_group);
+            ok = hipStreamEndCapture(cap, &g) == hipSuccess && rc == SMCGW_OK;
+        }
+        c->stream = saved;
+        c->timing_mask = saved_mask;
+        (void)hipStreamDestroy(cap);
+        if (ok) ok = hipGraphInstantiate(&c->sweep_exec, g, nullptr, nullptr, 0) == hipSuccess;
+        if (!ok) {
+            if (g) (void)hipGraphDestroy(g);
+            c->sweep_exec = nullptr;
+            return rc ? rc : SMCGW_ERR_HIP;
+        }
+        c->sweep_graph = g;
+        c->sweep_key = key;
+    }
+    // every transition ends within 2^max_depth sweeps (one leaf per sweep, the start included)
+    const int md = max_depth_per_particle ? SMCGW_MAX_DEPTH : prm->max_depth;
+    const long limit = (1L << md) + 1;
+    long sweeps = 0;
+    for (;;) {
+        if (hipGraphLaunch(c->sweep_exec, c->stream) != hipSuccess) return SMCGW_ERR_HIP;
+        sweeps += sweeps_per_group;
+        if (hipMemcpyAsync(hp, s.count, sizeof(int), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess)
+            return SMCGW_ERR_HIP;
+        if (*hp == 0) break;
+        if (sweeps > limit + sweeps_per_group) return SMCGW_ERR_HIP;
+    }
+    if (n_sweeps_host) *n_sweeps_host = (int)sweeps;
+    return SMCGW_OK;
+}

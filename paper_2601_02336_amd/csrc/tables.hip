@@ -4,7 +4,8 @@
 // f_j = f_low + j df, every particle reuses the same per-bin quantities:
 //   u_dj = 4 df conj(d_dj) f_j^-7/6 / S_dj            (whitened data x amplitude shape)
 //   f_j, f_j^-1/3, ln f_j                           (phase basis generators)
-//   H_d  = sum_j 4 df f_j^-7/3 / S_dj,  <d|d>_d = sum_j 4 df |d_dj|^2 / S_dj.
+//   H_d  = sum_j 4 df f_j^-7/3 / S_dj,  <d|d>_d = sum_j 4 df |d_dj|^2 / S_dj,
+//   w_dj a_j^2 = 4 df f_j^-7/3 / S_dj per bin (the plain form's per-bin <h|h>).
 // The tables are zero-padded to a multiple of TABLE_PAD bins; padded bins have
 // u = 0 and finite basis values, so they add nothing to any sum.
 #include "common.h"
@@ -14,7 +15,8 @@ namespace smcgw {
 __global__ __launch_bounds__(256) void build_tables_kernel(const double* __restrict__ data, const double* __restrict__ psd,
                                                            int n_det, int n, int npad, double f_low, double df,
                                                            double inv_us, double* __restrict__ fwl,
-                                                           float2* __restrict__ u32, double2* __restrict__ u64) {
+                                                           float2* __restrict__ u32, double2* __restrict__ u64,
+                                                           double* __restrict__ wa2) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= npad) return;
     const double f = f_low + df * (double)j;
@@ -23,14 +25,16 @@ __global__ __launch_bounds__(256) void build_tables_kernel(const double* __restr
     fwl[(size_t)ROW_LN * npad + j] = log(f);
     const double a = pow(f, -7.0 / 6.0);
     for (int d = 0; d < n_det; ++d) {
-        double ur = 0.0, ui = 0.0;
+        double ur = 0.0, ui = 0.0, h = 0.0;
         if (j < n) {
             const double w = 4.0 * df / psd[(size_t)d * n + j];
             const double* dd = data + 2 * ((size_t)d * n + j);
             ur = w * a * dd[0] * inv_us;
             ui = -w * a * dd[1] * inv_us;
+            h = w * a * a * inv_us * inv_us;
         }
         u64[(size_t)d * npad + j] = make_double2(ur, ui);
+        wa2[(size_t)d * npad + j] = h;
         u32[(size_t)d * npad + j] = make_float2((float)ur, (float)ui);
     }
 }
@@ -257,9 +261,9 @@ hipError_t launch_rb_tables(const double* fwl_full, const double2* u64_full, int
 
 hipError_t launch_build_tables(const double* d_data, const double* d_psd, int n_det, int n_bins, int n_pad,
                                double f_low, double df, double u_scale, double* fwl, float2* u32, double2* u64,
-                               double* sums, hipStream_t s) {
+                               double* wa2, double* sums, hipStream_t s) {
     hipLaunchKernelGGL(build_tables_kernel, dim3((n_pad + 255) / 256), dim3(256), 0, s, d_data, d_psd, n_det, n_bins,
-                       n_pad, f_low, df, 1.0 / u_scale, fwl, u32, u64);
+                       n_pad, f_low, df, 1.0 / u_scale, fwl, u32, u64, wa2);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(table_sums_kernel, dim3(n_det), dim3(256), 0, s, d_data, d_psd, n_bins, f_low, df, sums);

@@ -72,7 +72,8 @@ class SmcIterDesc(C.Structure):
                 ("mm_status", C.c_void_p), ("chol_pp", C.c_void_p), ("metric_status", C.c_void_p),
                 ("state", C.c_void_p), ("history", C.c_void_p), ("history_cap", C.c_int32),
                 ("max_depth", C.c_int32), ("alpha", C.c_double), ("shrink", C.c_double), ("step", C.c_double),
-                ("max_delta_h", C.c_double), ("seed", C.c_uint64), ("uturn", C.c_int32), ("reserved", C.c_int32)]
+                ("max_delta_h", C.c_double), ("seed", C.c_uint64), ("uturn", C.c_int32), ("nuts_form", C.c_int32)]
+NUTS_PERSISTENT, NUTS_SWEEPS = 0, 1
 
 
 _lib = None
@@ -87,13 +88,16 @@ def rb_edges(f_low: float, df: float, n_bins: int, eps: float) -> np.ndarray:
     return out[:m].copy()
 
 
-def _chol_mode(chol: torch.Tensor, P: int, D: int) -> int:
-    """0 for one shared [D][D] factor, 1 for per-particle [P][D][D] factors."""
+def _chol_mode(chol: torch.Tensor, P: int, D: int, n_runs: int = 0) -> int:
+    """0 for one shared [D][D] factor (or, with n_runs independent runs, one [D][D] factor per run),
+    1 for per-particle [P][D][D] factors."""
     _dev(chol, torch.float64, "chol")
     if tuple(chol.shape) == (D, D):
         return 0
     if tuple(chol.shape) == (P, D, D):
         return 1
+    if n_runs > 0 and tuple(chol.shape) == (n_runs, D, D):
+        return 0
     raise ValueError(f"chol must be [{D}][{D}] or [{P}][{D}][{D}], got {tuple(chol.shape)}")
 
 
@@ -136,6 +140,9 @@ def lib():
         L.smcgw_timing_read.argtypes = [vp, i, C.POINTER(d), C.POINTER(C.c_int64)]
         L.smcgw_smc_reweight_resample.argtypes = [vp, i, i, d, d, u64, u64, vp, vp, vp, vp, vp,
                                                   C.POINTER(d), C.POINTER(d)]
+        L.smcgw_loglike_grad_tangent.argtypes = [vp, i, vp, vp, vp, vp]
+        L.smcgw_nuts_step_sweeps.argtypes = [vp, i, i, vp, vp, vp, vp, C.POINTER(NutsParams), vp, vp, vp, vp, vp, i,
+                                             C.POINTER(i)]
         L.smcgw_smc_iteration.argtypes = [vp, C.POINTER(SmcIterDesc)]
         L.smcgw_smc_graph_create.argtypes = [vp, C.POINTER(SmcIterDesc), C.POINTER(vp)]
         L.smcgw_graph_launch.argtypes = [vp, i]
@@ -281,6 +288,59 @@ class Context:
             self._h, P, _ptr(event_of_particle), _ptr(theta), _ptr(logl), _ptr(grad) if want_grad else None,
             precision))
         return (logl, grad) if want_grad else logl
+
+    def loglike_grad_tangent(self, theta: torch.Tensor, logl: Optional[torch.Tensor] = None,
+                             grad: Optional[torch.Tensor] = None, want_grad: bool = True,
+                             event_of_particle: Optional[torch.Tensor] = None):
+        """The plain comparison form (smcgw_loglike_grad_tangent): FP64 per-bin terms, gradient by forward-mode
+        tangents."""
+        theta = _dev(theta, torch.float64, "theta")
+        P = theta.shape[0]
+        if logl is None:
+            logl = torch.empty(P, dtype=torch.float64, device=theta.device)
+        if want_grad and grad is None:
+            grad = torch.empty_like(theta)
+        if event_of_particle is not None:
+            _dev(event_of_particle, torch.int32, "event_of_particle")
+        self._stream()
+        _check("smcgw_loglike_grad_tangent", lib().smcgw_loglike_grad_tangent(
+            self._h, P, _ptr(event_of_particle), _ptr(theta), _ptr(logl), _ptr(grad) if want_grad else None))
+        return (logl, grad) if want_grad else logl
+
+    def nuts_step_sweeps(self, theta: torch.Tensor, logl: torch.Tensor, grad: torch.Tensor, chol: torch.Tensor,
+                         step: float, beta: float, seed: int, iteration: int, max_depth: int = 10,
+                         uturn: bool = True, max_delta_h: float = 1000.0,
+                         max_depth_per_particle: Optional[torch.Tensor] = None, sweeps_per_group: int = 8,
+                         beta_device: Optional[torch.Tensor] = None, state: Optional[torch.Tensor] = None,
+                         run_size: int = 0):
+        """The plain comparison form of nuts_step (smcgw_nuts_step_sweeps): lockstep sweeps with the
+        forward-mode plain likelihood, groups of sweeps replayed from a HIP graph.  Synchronises; returns the
+        diagnostics dict with n_sweeps added."""
+        theta = _dev(theta, torch.float64, "theta")
+        P, D = theta.shape
+        if beta_device is not None:
+            _dev(beta_device, torch.float64, "beta_device")
+        if state is not None:
+            _dev(state, torch.float64, "state")
+        n_runs = P // run_size if (state is not None and run_size > 0) else 0
+        prm = NutsParams(step, 0.0 if (beta_device is not None or state is not None) else beta, max_delta_h,
+                         max_depth, 1 if uturn else 0, seed, iteration, _chol_mode(chol, P, D, n_runs), 0,
+                         _ptr(beta_device), _ptr(state), run_size if state is not None else 0, 0)
+        dev = theta.device
+        out = dict(depth=torch.empty(P, dtype=torch.int32, device=dev),
+                   n_leapfrog=torch.empty(P, dtype=torch.int32, device=dev),
+                   divergent=torch.empty(P, dtype=torch.uint8, device=dev),
+                   accept_stat=torch.empty(P, dtype=torch.float64, device=dev))
+        if max_depth_per_particle is not None:
+            _dev(max_depth_per_particle, torch.int32, "max_depth_per_particle")
+        n = C.c_int(0)
+        self._stream()
+        _check("smcgw_nuts_step_sweeps", lib().smcgw_nuts_step_sweeps(
+            self._h, P, D, _ptr(theta), _ptr(logl), _ptr(grad), _ptr(chol), C.byref(prm),
+            _ptr(max_depth_per_particle), _ptr(out["depth"]), _ptr(out["n_leapfrog"]), _ptr(out["divergent"]),
+            _ptr(out["accept_stat"]), sweeps_per_group, C.byref(n)))
+        out["n_sweeps"] = n.value
+        return out
 
     def target_loglike_grad(self, theta: torch.Tensor, logl: Optional[torch.Tensor] = None,
                             grad: Optional[torch.Tensor] = None, precision: int = MIXED):
@@ -508,7 +568,8 @@ class SmcRuns:
 
     def __init__(self, ctx: "Context", theta0: torch.Tensor, n_runs: int, *, alpha: float, step: float,
                  max_depth: int, shrink: float, seed: int, precision: int, metric: str = "population",
-                 uturn: bool = True, max_delta_h: float = 1000.0, history_cap: int = 512):
+                 uturn: bool = True, max_delta_h: float = 1000.0, history_cap: int = 512,
+                 nuts_form: int = NUTS_PERSISTENT):
         theta0 = _dev(theta0, torch.float64, "theta0")
         n, D = theta0.shape
         if n_runs < 1 or n_runs > MAX_RUNS or n % n_runs != 0:
@@ -519,7 +580,10 @@ class SmcRuns:
         P = n // n_runs
         self.ctx, self.n_runs, self.P, self.D = ctx, n_runs, P, D
         self.theta = theta0.clone()
-        self.logl, self.grad = ctx.target_loglike_grad(self.theta, precision=precision)
+        if nuts_form == NUTS_SWEEPS:   # the plain comparison form evaluates with its own likelihood
+            self.logl, self.grad = ctx.loglike_grad_tangent(self.theta)
+        else:
+            self.logl, self.grad = ctx.target_loglike_grad(self.theta, precision=precision)
         i32 = dict(dtype=torch.int32, device=dev)
         f64 = dict(dtype=torch.float64, device=dev)
         self.ancestors = torch.zeros(n, **i32)
@@ -540,7 +604,7 @@ class SmcRuns:
                                 _ptr(self.accept_stat), _ptr(self.inv_mass), _ptr(self.chol), _ptr(self.mm_status),
                                 _ptr(self.chol_pp), _ptr(self.metric_status), _ptr(self.state_dev),
                                 _ptr(self.history_dev), history_cap, max_depth, alpha, shrink, step, max_delta_h,
-                                seed, 1 if uturn else 0, 0)
+                                seed, 1 if uturn else 0, nuts_form)
 
     def step(self):
         """Queue one iteration of every run (asynchronous)."""
