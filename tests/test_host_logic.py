@@ -1,4 +1,4 @@
-"""Host-side behaviour that needs no GPU: the bench's one-GPU contract and busy-span arithmetic, the
+"""Host-side behaviour that needs no GPU: the bench's one-GPU contract, its iteration table and traffic gate, the
 relative-binning edge function's argument handling, and argument checks of the sampler entry points (rejected
 before any device call)."""
 import ctypes
@@ -20,14 +20,34 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.stdout.strip() == ""
 
 
-def test_bench_busy_span_is_the_union_of_launch_intervals():
+def test_bench_iteration_table_and_traffic_gate(tmp_path, monkeypatch):
+    """The per-iteration rows are the runs' records divided by the run size (the largest divergent fraction over
+    the runs), and counter traffic is reported only for the kernel sources, kernel and command it was taken on."""
     sys.path.insert(0, ROOT)
     import bench
-    assert bench.union_ms([]) == 0.0
-    assert bench.union_ms([(0.0, 2.0)]) == 2.0
-    # overlapping, nested, touching and disjoint intervals, in any order
-    assert bench.union_ms([(5.0, 6.0), (0.0, 2.0), (1.0, 3.0), (1.5, 1.8), (3.0, 4.0)]) == 5.0
-    assert bench.union_ms([(0.0, 10.0), (2.0, 3.0), (9.0, 12.0), (20.0, 21.0)]) == 13.0
+    from paper_2601_02336_amd import smcgw
+    h = np.zeros((2, 3, smcgw.HIST_SIZE))
+    h[:, :, smcgw.H_BETA] = [[0.1, 0.2, 0.3], [0.15, 0.25, 0.35]]
+    h[:, :, smcgw.H_DIVERGENT] = [[1, 0, 5], [2, 0, 1]]
+    h[:, :, smcgw.H_DEPTH] = [[40, 60, 80], [40, 60, 100]]
+    h[:, :, smcgw.H_LEAPFROG] = [[100, 200, 300], [1, 2, 3]]
+    rows = bench.iteration_table(smcgw, h, 20)
+    assert [r["divergent_frac"] for r in rows] == [0.1, 0.0, 0.25]
+    assert [r["mean_depth"] for r in rows] == [2.0, 3.0, 4.5]
+    assert [r["leapfrog"] for r in rows] == [101, 202, 303]
+    assert rows[2]["beta"] == [0.3, 0.35]
+    f = tmp_path / "traffic.txt"
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    assert bench.measured_traffic("k", "") is None                       # no file
+    body = ("# made by a counter run\nkernel=k\nbench_args=--steps 3\nsource_sha256={}\n"
+            "traffic_bytes_per_launch=30\nfetch_bytes_per_launch=20\nwrite_bytes_per_launch=10\n")
+    f.write_text(body.format(bench.kernel_source_hash()))
+    assert bench.measured_traffic("k", "--steps 3") == {"bytes_per_launch": 30, "fetch_bytes_per_launch": 20,
+                                                        "write_bytes_per_launch": 10}
+    assert bench.measured_traffic("other", "--steps 3") is None          # another kernel
+    assert bench.measured_traffic("k", "") is None                       # another command
+    f.write_text(body.format("0" * 64))
+    assert bench.measured_traffic("k", "--steps 3") is None              # other sources
 
 
 def test_rb_edges_arguments():
