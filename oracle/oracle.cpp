@@ -878,15 +878,48 @@ int orc_mass_matrix(int P, int D, const double* x, double shrink, double* inv_ma
 // F_kl = sum_d 4 df sum_j Re(conj(dh_dj/dtheta_k) dh_dj/dtheta_l) / S_dj,
 // from 11-tangent dual numbers of the strain, and the prior precision the
 // inverse variance of each coordinate's prior (uniform (hi-lo)^2/12,
-// log-uniform its variance, Gaussian sigma^2; 0 for a flat prior).  Outputs
-// per particle: fisher [D][D] (may be NULL) and chol [D][D], the lower
-// Cholesky factor of M^{-1}.  GW targets only.  A particle whose M or M^{-1}
+// log-uniform its variance, Gaussian sigma^2; 0 for a flat prior).  For the
+// analytic test likelihoods F is the exact Hessian of -log L instead (see
+// analytic_hessian).  Outputs per particle: fisher [D][D] (may be NULL) and
+// chol [D][D], the lower Cholesky factor of M^{-1}.  A particle whose M or M^{-1}
 // is not numerically positive definite takes fallback [D][D] (the identity
 // when NULL) and status[i] = 1 (status may be NULL).  Returns the number of
 // such particles.
+// Exact Hessian of -log L of the analytic test likelihoods at x, H [D][D]:
+// the standard normal gives the identity, the Gaussian likelihood N(y; x,
+// sigma_l^2) gives diag(1 / sigma_l^2), and the unweighted sum of two
+// isotropic Gaussians N(m1, s^2) + N(m2, s^2) gives
+//   I / s^2 - r1 r2 (m1 - m2)(m1 - m2)^T / s^4
+// with r_i = N_i / (N_1 + N_2) the components' shares at x (the Hessian of
+// log sum_i N_i is the shares' mean of the components' Hessians plus the
+// shares' covariance of their gradients (m_i - x) / s^2).
+static void analytic_hessian(const orc_target& t, const double* x, double* H) {
+    const int D = t.dim;
+    for (int i = 0; i < D * D; ++i) H[i] = 0.0;
+    if (t.kind == 1) {
+        for (int k = 0; k < D; ++k) H[k * D + k] = 1.0;
+    } else if (t.kind == 2) {
+        const double* sg = t.params + D;
+        for (int k = 0; k < D; ++k) H[k * D + k] = 1.0 / (sg[k] * sg[k]);
+    } else {
+        const double* m1 = t.params; const double* m2 = t.params + D; const double sg = t.params[2 * D];
+        double s1 = 0.0, s2 = 0.0;
+        for (int k = 0; k < D; ++k) {
+            s1 += (x[k] - m1[k]) * (x[k] - m1[k]);
+            s2 += (x[k] - m2[k]) * (x[k] - m2[k]);
+        }
+        // r1 = 1 / (1 + exp(l2 - l1)), with l_i = -s_i / (2 s^2) (common factors cancel)
+        const double r1 = 1.0 / (1.0 + std::exp(-0.5 * (s2 - s1) / (sg * sg))), r2 = 1.0 - r1;
+        const double s4 = sg * sg * sg * sg;
+        for (int a = 0; a < D; ++a)
+            for (int b = 0; b < D; ++b)
+                H[a * D + b] = (a == b ? 1.0 / (sg * sg) : 0.0) - r1 * r2 * (m1[a] - m2[a]) * (m1[b] - m2[b]) / s4;
+    }
+}
+
 int orc_local_metric(const orc_target* t, int P, const double* x, double beta, const double* fallback, double* fisher,
                      double* chol, int32_t* status) {
-    if (t->kind != 0) return -1;
+    if (t->kind < 0 || t->kind > 3) return -1;
     const int D = t->dim;
     std::vector<double> prec(D, 0.0);
     for (int k = 0; k < D; ++k) {
@@ -904,27 +937,36 @@ int orc_local_metric(const orc_target* t, int P, const double* x, double beta, c
     int bad = 0;
 #pragma omp parallel for schedule(dynamic, 1) reduction(+ : bad)
     for (int i = 0; i < P; ++i) {
-        double th[NP];
-        expand_gw(*t, x + (size_t)i * D, th);
-        D11 td[NP];
-        for (int k = 0; k < NP; ++k) { td[k] = D11(th[k]); td[k].d[k] = 1.0; }
-        const orc_event& ev = *t->ev;
-        double F11[NP][NP] = {};
-        for (int d = 0; d < ev.n_det; ++d)
-            for (int j = 0; j < ev.n_bins; ++j) {
-                const double f = ev.f_low + ev.df * j;
-                const Cx<D11> h = detector_strain(ev, t->dets[d], td, f);
-                const double w = 4.0 * ev.df / t->psd[(size_t)d * ev.n_bins + j];
-                for (int a = 0; a < NP; ++a)
-                    for (int b = 0; b < NP; ++b)
-                        F11[a][b] += w * (h.re.d[a] * h.re.d[b] + h.im.d[a] * h.im.d[b]);
-            }
+        std::vector<double> F((size_t)D * D);
+        if (t->kind == 0) {
+            double th[NP];
+            expand_gw(*t, x + (size_t)i * D, th);
+            D11 td[NP];
+            for (int k = 0; k < NP; ++k) { td[k] = D11(th[k]); td[k].d[k] = 1.0; }
+            const orc_event& ev = *t->ev;
+            double F11[NP][NP] = {};
+            for (int d = 0; d < ev.n_det; ++d)
+                for (int j = 0; j < ev.n_bins; ++j) {
+                    const double f = ev.f_low + ev.df * j;
+                    const Cx<D11> h = detector_strain(ev, t->dets[d], td, f);
+                    const double w = 4.0 * ev.df / t->psd[(size_t)d * ev.n_bins + j];
+                    for (int a = 0; a < NP; ++a)
+                        for (int b = 0; b < NP; ++b)
+                            F11[a][b] += w * (h.re.d[a] * h.re.d[b] + h.im.d[a] * h.im.d[b]);
+                }
+            for (int a = 0; a < D; ++a)
+                for (int b = 0; b < D; ++b) {
+                    const int ia = t->param_index ? t->param_index[a] : a, ib = t->param_index ? t->param_index[b] : b;
+                    F[a * D + b] = F11[ia][ib];
+                }
+        } else {
+            analytic_hessian(*t, x + (size_t)i * D, F.data());
+        }
         std::vector<double> M((size_t)D * D), R((size_t)D * D, 0.0), Minv((size_t)D * D), Lo((size_t)D * D, 0.0);
         for (int a = 0; a < D; ++a)
             for (int b = 0; b < D; ++b) {
-                const int ia = t->param_index ? t->param_index[a] : a, ib = t->param_index ? t->param_index[b] : b;
-                if (fisher) fisher[(size_t)i * D * D + a * D + b] = F11[ia][ib];
-                M[a * D + b] = beta * F11[ia][ib] + (a == b ? prec[a] : 0.0);
+                if (fisher) fisher[(size_t)i * D * D + a * D + b] = F[a * D + b];
+                M[a * D + b] = beta * F[a * D + b] + (a == b ? prec[a] : 0.0);
             }
         // M = R R^T, then M^{-1} column by column (R y = e_j, R^T z = y), then M^{-1} = L L^T.
         bool ok = true;

@@ -294,8 +294,9 @@ def resample(weights, seed: int, iteration: int) -> np.ndarray:
 
 def local_metric(target: Target, x, beta: float, want_fisher: bool = True, fallback=None):
     """Per-particle metric of the tempered posterior (Sec. 5, local geometry): (status [P], fisher [P][D][D],
-    chol [P][D][D]) with chol the lower Cholesky factor of (beta F + diag(prior precision))^{-1}; particles
-    whose matrix is not positive definite get `fallback` (identity when None) and status 1."""
+    chol [P][D][D]) with chol the lower Cholesky factor of (beta F + diag(prior precision))^{-1}; F is the
+    Fisher matrix of the event likelihood, or the exact Hessian of -log L of an analytic test likelihood.
+    Particles whose matrix is not positive definite get `fallback` (identity when None) and status 1."""
     x = _f64(x)
     P, D = x.shape
     F = np.zeros((P, D, D)) if want_fisher else None

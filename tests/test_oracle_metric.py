@@ -154,3 +154,67 @@ def test_flat_prior_at_beta_zero_takes_the_fallback():
     # any beta > 0 with a non-degenerate Fisher block is positive definite again
     st, _, _ = O.local_metric(t, x, 1.0, want_fisher=False)
     assert not st.any()
+
+
+def _bimodal_target(D=11, sg=0.1):
+    b = [synth.Bound(-5.0, 5.0, synth.BND_REFLECT, synth.PRIOR_UNIFORM)] * D
+    return O.Target(synth.TARGET_BIMODAL, D, b, params=np.concatenate([np.ones(D), -np.ones(D), [sg]]))
+
+
+def test_analytic_hessian_matches_second_differences():
+    """The bimodal mixture's exact Hessian (the metric's F for analytic targets) against central second
+    differences of the oracle's log L: near either mode, on the saddle between them (where the shares' term
+    makes it indefinite) and in between."""
+    D = 11
+    t = _bimodal_target(D)
+    rng = np.random.default_rng(5)
+    d1 = np.ones(D) / math.sqrt(D)
+    pts = [np.ones(D) + 0.05 * rng.normal(size=D), -np.ones(D) + 0.05 * rng.normal(size=D),
+           0.0003 * rng.normal(size=D), d1 * 0.004 + 0.01 * rng.normal(size=D)]
+    x = np.array(pts)
+    _, F, _ = O.local_metric(t, x, 1.0)
+    h = 1e-5   # the shares change on a scale s^2 / (2 |m1 - m2|) ~ 1e-3 across the saddle
+
+    def ll(y):
+        return O.loglike_grad(t, np.atleast_2d(y), want_grad=False)
+
+    for i, xi in enumerate(x):
+        H = np.zeros((D, D))
+        for k in range(D):
+            for l in range(D):
+                ek, el = np.eye(D)[k] * h, np.eye(D)[l] * h
+                v = ll(np.array([xi + ek + el, xi + ek - el, xi - ek + el, xi - ek - el]))
+                H[k, l] = -(v[0] - v[1] - v[2] + v[3]) / (4 * h * h)
+        scale = np.max(np.abs(F[i]))
+        assert np.max(np.abs(H - F[i])) <= 1e-5 * scale, (i, np.max(np.abs(H - F[i])) / scale)
+    # the shares' term: at the saddle r1 = r2 = 1/2 and F = I/s^2 - (1/4) d d^T / s^4 with d = 2 (1, ..., 1)
+    _, F0, _ = O.local_metric(t, np.zeros((1, D)), 1.0)
+    assert F0[0][0, 1] == pytest.approx(-0.25 * 4 / 1e-4, rel=1e-14)
+    assert F0[0][0, 0] == pytest.approx(100.0 - 0.25 * 4 / 1e-4, rel=1e-14)
+
+
+def test_analytic_metric_closed_forms():
+    """Gaussian likelihood N(y; x, sl^2) under a Gaussian prior N(mu0, s0^2): M = diag(beta / sl^2 + 1 / s0^2),
+    so the factor is diag(M^-1/2).  The bimodal mixture near a mode at beta: M = beta I / s^2 + 12 / 10^2
+    (uniform prior on [-5, 5]) up to the other component's share; on the saddle the metric is not positive
+    definite and the particle takes the fallback."""
+    D = 4
+    sl, s0 = np.array([0.2, 0.5, 1.0, 2.0]), np.array([1.0, 3.0, 0.5, 2.0])
+    b = [synth.Bound(0.0, s0[k], synth.BND_NONE, synth.PRIOR_GAUSSIAN) for k in range(D)]
+    t = O.Target(synth.TARGET_GAUSS_X_GAUSS, D, b, params=np.concatenate([np.zeros(D), sl]))
+    x = np.random.default_rng(1).normal(size=(3, D))
+    for beta in (0.0, 0.3, 1.0):
+        st, F, L = O.local_metric(t, x, beta)
+        assert not st.any()
+        want = np.diag(1.0 / np.sqrt(beta / sl ** 2 + 1.0 / s0 ** 2))
+        for i in range(3):
+            np.testing.assert_allclose(F[i], np.diag(1.0 / sl ** 2), rtol=1e-15)
+            np.testing.assert_allclose(L[i], want, rtol=1e-14, atol=1e-300)
+    D = 11
+    t = _bimodal_target(D)
+    x = np.array([np.ones(D) * 1.01, np.zeros(D)])
+    fb = np.eye(D) * 0.7
+    st, F, L = O.local_metric(t, x, 0.25, fallback=fb)
+    assert st.tolist() == [0, 1]
+    np.testing.assert_allclose(L[0], np.eye(D) / math.sqrt(0.25 / 0.01 + 0.12), rtol=1e-9)
+    assert np.array_equal(L[1], fb)
