@@ -1015,7 +1015,10 @@ __global__ __launch_bounds__(256) void sweep_init_kernel(SweepState* __restrict_
 // first sweep, else the booking of the leaf whose likelihood ll_in / gl_in
 // the batched likelihood has just computed; then either the next leaf's
 // position (x_next, active = 1) or the transition's outputs (active = 0).
-__global__ __launch_bounds__(64) void nuts_sweep_kernel(NutsArgs a, PriorDesc pri, ParamMap pm,
+// The tree steps are out-of-line functions shared with nuts_kernel, and a
+// function's register budget is the loosest of its callers': the occupancy
+// bound here matches nuts_kernel's so the shared steps keep its budget.
+__global__ __launch_bounds__(64, NUTS_WAVES_PER_SIMD) void nuts_sweep_kernel(NutsArgs a, PriorDesc pri, ParamMap pm,
                                                         SweepState* __restrict__ st,
                                                         const double* __restrict__ ll_in,
                                                         const double* __restrict__ gl_in,
