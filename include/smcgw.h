@@ -306,7 +306,8 @@ int smcgw_mass_matrix(smcgw_ctx *ctx, int P, int D, const double *theta, double 
  * the mutation).  Read as the Gauss-Newton Hessian
  *   M_i = beta F(theta_i) + diag(prior precision),
  * F the Fisher matrix <dh/dtheta_k | dh/dtheta_l> of the event likelihood
- * (Sec. 2, Eq. 2) over the sampled coordinates, the prior precision
+ * (Sec. 2, Eq. 2) over the sampled coordinates (for an analytic test
+ * likelihood, the exact Hessian of -log L), the prior precision
  * 12/(hi-lo)^2 (uniform), the inverse variance (log-uniform), 1/sigma^2
  * (Gaussian) or 0 (flat).  chol [P][D][D] receives the lower Cholesky
  * factor of M_i^{-1} (the layout smcgw_nuts_step takes with
@@ -315,8 +316,9 @@ int smcgw_mass_matrix(smcgw_ctx *ctx, int P, int D, const double *theta, double 
  * fallback_chol [D][D] (NULL: the identity) and status [P] = 1 (status may
  * be NULL; 0 otherwise).  All arrays are device arrays; beta in [0, 1], or
  * read from the device double beta_device when that is not NULL.
- * Needs the GW target, a prior and a parameter map of dimension D.
- * Asynchronous on the context's stream. */
+ * Needs a prior of dimension D and the GW target with a parameter map of
+ * dimension D, or an analytic target of dimension D.  Asynchronous on the
+ * context's stream. */
 int smcgw_local_metric(smcgw_ctx *ctx, int P, int D, const double *theta, double beta, const double *beta_device,
                        const double *fallback_chol, double *chol, double *fisher, int32_t *status);
 

@@ -40,8 +40,8 @@ int check_desc(smcgw_ctx* c, const smcgw_smc_iter_desc* d) {
     if (!c->prior_set || c->prior.dim != d->D) return SMCGW_ERR_NOT_INIT;
     if (c->target.kind == SMCGW_TARGET_GW) {
         if (c->events.empty() || c->pmap.dim != d->D) return SMCGW_ERR_NOT_INIT;
-    } else if (c->target.dim != d->D || d->chol_pp) {
-        return SMCGW_ERR_NOT_INIT;   // the local metric needs the event likelihood
+    } else if (c->target.dim != d->D) {
+        return SMCGW_ERR_NOT_INIT;
     }
     return SMCGW_OK;
 }

@@ -86,14 +86,64 @@ __device__ bool block_cholesky(const double* A, double* Lo, int D, int tid) {
     return true;
 }
 
+// M = beta F + diag(prior precision) over the sampled coordinates (F with
+// row stride fs, coordinate a of the sample being row idx[a]), then the lower
+// Cholesky factor of M^{-1} into chol[p], or the fallback where M or the
+// factor is not numerically positive definite.  The factor comes from the
+// order-reversed matrix: with J the reversal permutation and J M J = R R^T,
+// M^{-1} = (J R^-T J)(J R^-T J)^T and J R^-T J is lower triangular with a
+// positive diagonal, so it is that factor; it needs one Cholesky and one
+// triangular inverse.
+__device__ void finish_metric(MetricShared& S, const double* F, int fs, const int* idx, int D, double beta,
+                              const PrecDesc& pd,
+                              const double* __restrict__ fallback, double* __restrict__ chol,
+                              double* __restrict__ fisher, int32_t* __restrict__ status, int p, int tid) {
+    // J M J (rows and columns in reverse order)
+    for (int i = tid; i < MAXDIM * MAXDIM; i += MET_THREADS) {
+        const int a = i / MAXDIM, b = i % MAXDIM;
+        double v = 0.0;
+        if (a < D && b < D) {
+            const int ra = D - 1 - a, rb = D - 1 - b;
+            const double f = F[idx[ra] * fs + idx[rb]];
+            v = beta * f + (a == b ? pd.prec[ra] : 0.0);
+            if (fisher) fisher[(size_t)p * D * D + ra * D + rb] = f;
+        }
+        S.M[i] = v;
+    }
+    __syncthreads();
+    bool ok = block_cholesky(S.M, S.R, D, tid);
+    if (ok) {
+        // X = R^{-1}, thread c solving column c by forward substitution
+        if (tid < D) {
+            const int c = tid;
+            for (int r = 0; r < D; ++r) {
+                double v = (r == c) ? 1.0 : 0.0;
+                for (int k = c; k < r; ++k) v -= S.R[r * MAXDIM + k] * S.Y[k * MAXDIM + c];
+                S.Y[r * MAXDIM + c] = r < c ? 0.0 : v / S.R[r * MAXDIM + r];
+            }
+        }
+        __syncthreads();
+    }
+    // factor L[i][j] = X[D-1-j][D-1-i]; a non-finite entry takes the fallback too
+    bool bad_entry = false;
+    if (ok)
+        for (int i = tid; i < D * D; i += MET_THREADS) {
+            const double v = S.Y[(D - 1 - i % D) * MAXDIM + (D - 1 - i / D)];
+            bad_entry |= !isfinite(v);
+        }
+    ok = ok && !__syncthreads_or(bad_entry);
+    for (int i = tid; i < D * D; i += MET_THREADS) {
+        const int a = i / D, b = i % D;
+        chol[(size_t)p * D * D + i] = ok ? S.Y[(D - 1 - b) * MAXDIM + (D - 1 - a)]
+                                    : fallback ? fallback[i] : (a == b ? 1.0 : 0.0);
+    }
+    if (status && tid == 0) status[p] = ok ? 0 : 1;
+}
+
 // One workgroup of two wavefronts per particle.  The coefficient block is
 // built as in the NUTS leaf: the intrinsic part with one tangent per lane on
 // wavefront 0, the extrinsic part (shared sin / cos in parallel lanes, then
-// one detector and tangent per lane) on wavefront 1.  The lower Cholesky
-// factor of M^{-1} comes from the order-reversed matrix: with J the
-// reversal permutation and J M J = R R^T, M^{-1} = (J R^-T J)(J R^-T J)^T and
-// J R^-T J is lower triangular with a positive diagonal, so it is that
-// factor; it needs one Cholesky and one triangular inverse.
+// one detector and tangent per lane) on wavefront 1.
 __global__ __launch_bounds__(MET_THREADS) void local_metric_kernel(const DevEvent* __restrict__ evs, int n_events,
                                                                   const int32_t* __restrict__ ev_of_p, ParamMap pm,
                                                                   PrecDesc pd, int P, const double* __restrict__ theta,
@@ -190,46 +240,60 @@ __global__ __launch_bounds__(MET_THREADS) void local_metric_kernel(const DevEven
     __syncthreads();
 
     const double beta = st ? st[(size_t)run * SMCGW_STATE_SIZE + SMCGW_ST_BETA] : beta_dev ? *beta_dev : beta_host;
-    // J M J over the sampled coordinates (rows and columns in reverse order)
-    for (int i = tid; i < MAXDIM * MAXDIM; i += MET_THREADS) {
-        const int a = i / MAXDIM, b = i % MAXDIM;
-        double v = 0.0;
-        if (a < D && b < D) {
-            const int ra = D - 1 - a, rb = D - 1 - b;
-            const double f = S.F[pm.idx[ra] * NPAR + pm.idx[rb]];
-            v = beta * f + (a == b ? pd.prec[ra] : 0.0);
-            if (fisher) fisher[(size_t)p * D * D + ra * D + rb] = f;
+    finish_metric(S, S.F, NPAR, pm.idx, D, beta, pd, fallback, chol, fisher, status, p, tid);
+}
+
+// The analytic test likelihoods take the exact Hessian of -log L as F: the
+// identity (standard normal), diag(1 / sigma_l^2) (Gaussian likelihood), and
+// for the unweighted sum of two isotropic Gaussians N(m1, s^2) + N(m2, s^2)
+//   F = I / s^2 - r1 r2 (m1 - m2)(m1 - m2)^T / s^4,
+// r_i the components' shares at the particle (the shares' mean of the
+// components' Hessians less the shares' covariance of their gradients).
+// Near a mode F is positive definite; across the saddle between the modes it
+// is not, and the particle takes the fallback.  One workgroup per particle.
+__global__ __launch_bounds__(MET_THREADS) void analytic_metric_kernel(TargetDesc tg, PrecDesc pd, int P,
+                                                                     const double* __restrict__ theta,
+                                                                     double beta_host, const double* __restrict__ beta_dev,
+                                                                     const double* __restrict__ fallback,
+                                                                     double* __restrict__ chol, double* __restrict__ fisher,
+                                                                     int32_t* __restrict__ status,
+                                                                     const double* __restrict__ st, int run_size) {
+    __shared__ MetricShared S;
+    __shared__ double F[MAXDIM * MAXDIM];
+    __shared__ int idx[MAXDIM];
+    const int tid = threadIdx.x;
+    const int p = blockIdx.x;
+    const int D = tg.dim;
+    const int run = st ? p / run_size : 0;
+    if (st && st[(size_t)run * SMCGW_STATE_SIZE + SMCGW_ST_DONE] != 0.0) return;
+    if (st && fallback) fallback += (size_t)run * D * D;
+    if (tid < MAXDIM) idx[tid] = tid;
+    for (int e = tid; e < D * D; e += MET_THREADS) {
+        const int k = e / D, l = e % D;
+        double f = 0.0;
+        if (tg.kind == SMCGW_TARGET_GAUSS) {
+            f = k == l ? 1.0 : 0.0;
+        } else if (tg.kind == SMCGW_TARGET_GAUSS_X_GAUSS) {
+            const double sl = tg.params[D + k];
+            f = k == l ? 1.0 / (sl * sl) : 0.0;
+        } else {
+            const double* x = theta + (size_t)p * D;
+            const double* m1 = tg.params;
+            const double* m2 = tg.params + D;
+            const double sg = tg.params[2 * D], s2g = sg * sg;
+            double s1 = 0.0, s2 = 0.0;
+            for (int j = 0; j < D; ++j) {
+                s1 += (x[j] - m1[j]) * (x[j] - m1[j]);
+                s2 += (x[j] - m2[j]) * (x[j] - m2[j]);
+            }
+            const double r1 = 1.0 / (1.0 + exp(-0.5 * (s2 - s1) / s2g)), r2 = 1.0 - r1;
+            f = (k == l ? 1.0 / s2g : 0.0) - r1 * r2 * (m1[k] - m2[k]) * (m1[l] - m2[l]) / (s2g * s2g);
         }
-        S.M[i] = v;
+        F[k * MAXDIM + l] = f;
     }
     __syncthreads();
-    bool ok = block_cholesky(S.M, S.R, D, tid);
-    if (ok) {
-        // X = R^{-1}, thread c solving column c by forward substitution
-        if (tid < D) {
-            const int c = tid;
-            for (int r = 0; r < D; ++r) {
-                double v = (r == c) ? 1.0 : 0.0;
-                for (int k = c; k < r; ++k) v -= S.R[r * MAXDIM + k] * S.Y[k * MAXDIM + c];
-                S.Y[r * MAXDIM + c] = r < c ? 0.0 : v / S.R[r * MAXDIM + r];
-            }
-        }
-        __syncthreads();
-    }
-    // factor L[i][j] = X[D-1-j][D-1-i]; a non-finite entry takes the fallback too
-    bool bad_entry = false;
-    if (ok)
-        for (int i = tid; i < D * D; i += MET_THREADS) {
-            const double v = S.Y[(D - 1 - i % D) * MAXDIM + (D - 1 - i / D)];
-            bad_entry |= !isfinite(v);
-        }
-    ok = ok && !__syncthreads_or(bad_entry);
-    for (int i = tid; i < D * D; i += MET_THREADS) {
-        const int a = i / D, b = i % D;
-        chol[(size_t)p * D * D + i] = ok ? S.Y[(D - 1 - b) * MAXDIM + (D - 1 - a)]
-                                    : fallback ? fallback[i] : (a == b ? 1.0 : 0.0);
-    }
-    if (status && tid == 0) status[p] = ok ? 0 : 1;
+    const double beta = st ? st[(size_t)run * SMCGW_STATE_SIZE + SMCGW_ST_BETA] : beta_dev ? *beta_dev : beta_host;
+    finish_metric(S, F, MAXDIM, idx, D, beta, pd, fallback, chol, fisher, status, p, tid);
 }
 
 // Prior precision of each sampled coordinate: 12 / (hi - lo)^2 (uniform),
@@ -261,16 +325,36 @@ static PrecDesc prior_precision(const PriorDesc& pr) {
 namespace smcgw {
 // Local metric of n_runs * run_size particles at their runs' temperatures
 // (state st), the run's own population factor as the fallback.
-int queue_local_metric(smcgw_ctx* c, int P, int D, const double* theta, const double* st, int run_size,
-                       const double* fallback_runs, double* chol, int32_t* status) {
-    if (c->events.empty() || !c->prior_set || c->target.kind != SMCGW_TARGET_GW) return SMCGW_ERR_NOT_INIT;
-    if (c->prior.dim != D || c->pmap.dim != D) return SMCGW_ERR_INVALID;
+static int metric_target_ok(smcgw_ctx* c, int D) {
+    if (!c->prior_set) return SMCGW_ERR_NOT_INIT;
+    if (c->target.kind == SMCGW_TARGET_GW) {
+        if (c->events.empty()) return SMCGW_ERR_NOT_INIT;
+        return c->prior.dim == D && c->pmap.dim == D ? SMCGW_OK : SMCGW_ERR_INVALID;
+    }
+    if (c->target.dim <= 0) return SMCGW_ERR_NOT_INIT;
+    return c->prior.dim == D && c->target.dim == D ? SMCGW_OK : SMCGW_ERR_INVALID;
+}
+
+static int launch_metric(smcgw_ctx* c, int P, const double* theta, double beta, const double* beta_dev,
+                         const double* fallback, double* chol, double* fisher, int32_t* status, const double* st,
+                         int run_size) {
     const PrecDesc pd = prior_precision(c->prior);
     TimedLaunch tl(c, SMCGW_KERNEL_METRIC);
-    hipLaunchKernelGGL(local_metric_kernel, dim3(P), dim3(MET_THREADS), 0, c->stream, c->d_events,
-                       (int)c->events.size(), c->ev_of_p, c->pmap, pd, P, theta, 0.0, (const double*)nullptr,
-                       fallback_runs, chol, (double*)nullptr, status, st, run_size);
+    if (c->target.kind == SMCGW_TARGET_GW)
+        hipLaunchKernelGGL(local_metric_kernel, dim3(P), dim3(MET_THREADS), 0, c->stream, c->d_events,
+                           (int)c->events.size(), c->ev_of_p, c->pmap, pd, P, theta, beta, beta_dev, fallback, chol,
+                           fisher, status, st, run_size);
+    else
+        hipLaunchKernelGGL(analytic_metric_kernel, dim3(P), dim3(MET_THREADS), 0, c->stream, c->target, pd, P, theta,
+                           beta, beta_dev, fallback, chol, fisher, status, st, run_size);
     return hipGetLastError() == hipSuccess ? SMCGW_OK : SMCGW_ERR_HIP;
+}
+
+int queue_local_metric(smcgw_ctx* c, int P, int D, const double* theta, const double* st, int run_size,
+                       const double* fallback_runs, double* chol, int32_t* status) {
+    const int rc = metric_target_ok(c, D);
+    if (rc) return rc;
+    return launch_metric(c, P, theta, 0.0, nullptr, fallback_runs, chol, nullptr, status, st, run_size);
 }
 }  // namespace smcgw
 
@@ -282,14 +366,9 @@ extern "C" int smcgw_local_metric(smcgw_ctx* c, int P, int D, const double* thet
     if (!c || P < 0 || D <= 0 || D > MAXDIM || (!beta_device && !(beta >= 0.0 && beta <= 1.0)) ||
         (P > 0 && (!theta || !chol)))
         return SMCGW_ERR_INVALID;
-    if (c->events.empty() || !c->prior_set || c->target.kind != SMCGW_TARGET_GW) return SMCGW_ERR_NOT_INIT;
-    if (c->prior.dim != D || c->pmap.dim != D) return SMCGW_ERR_INVALID;
+    const int rc = metric_target_ok(c, D);
+    if (rc) return rc;
     if (P == 0) return SMCGW_OK;
     hipSetDevice(c->device);
-    const PrecDesc pd = prior_precision(c->prior);
-    TimedLaunch tl(c, SMCGW_KERNEL_METRIC);
-    hipLaunchKernelGGL(local_metric_kernel, dim3(P), dim3(MET_THREADS), 0, c->stream, c->d_events,
-                       (int)c->events.size(), c->ev_of_p, c->pmap, pd, P, theta, beta, beta_device, fallback_chol, chol, fisher,
-                       status, (const double*)nullptr, P);
-    return hipGetLastError() == hipSuccess ? SMCGW_OK : SMCGW_ERR_HIP;
+    return launch_metric(c, P, theta, beta, beta_device, fallback_chol, chol, fisher, status, nullptr, P);
 }

@@ -226,3 +226,46 @@ def test_smc_with_local_metric(smcgw):
     mean = float(np.mean([r.logz for r in got["local"]]))
     print(f"local metric: mean log Z {mean:.4f}, reference {ref_logz:.4f}", flush=True)
     assert abs(mean - ref_logz) <= 0.3
+
+
+@pytest.mark.parametrize("kind", ["bimodal", "gauss_x_gauss"])
+def test_local_metric_parity_analytic_targets(smcgw, kind):
+    """Analytic test likelihoods take the exact Hessian of -log L as F.  The bimodal mixture of the toy problem
+    (11 dimensions, modes at +-1, s = 0.1, uniform prior on [-5, 5]) at particles near the modes, across the
+    saddle (not positive definite: the fallback) and in between; the Gaussian likelihood at 16 dimensions
+    (the largest sampled dimension).  Hessian, factor and status against the oracle."""
+    if kind == "bimodal":
+        D = 11
+        b = [Bound(-5.0, 5.0, synth.BND_REFLECT, synth.PRIOR_UNIFORM)] * D
+        prm = np.concatenate([np.ones(D), -np.ones(D), [0.1]])
+        tk = synth.TARGET_BIMODAL
+        rng = np.random.default_rng(3)
+        sgn = np.where(np.arange(300) % 3 == 0, 1.0, -1.0)[:, None]
+        x = np.concatenate([sgn * 1.0 + 0.1 * rng.normal(size=(300, D)), 0.002 * rng.normal(size=(60, D)),
+                            rng.uniform(-5, 5, size=(40, D))])
+    else:
+        D = 16
+        b = [Bound(0.0, 2.0, synth.BND_NONE, synth.PRIOR_GAUSSIAN)] * D
+        rng = np.random.default_rng(4)
+        prm = np.concatenate([rng.normal(size=D), rng.uniform(0.1, 2.0, size=D)])
+        tk = synth.TARGET_GAUSS_X_GAUSS
+        x = rng.normal(size=(200, D))
+    t = O.Target(tk, D, b, params=prm)
+    fb = np.eye(D) * 0.3
+    c = smcgw.Context(0)
+    c.set_prior(b)
+    c.set_target(tk, D, prm)
+    for beta in (1.0, 0.01):
+        st_r, F_r, L_r = O.local_metric(t, x, beta, fallback=fb)
+        L, F, st = c.local_metric(torch.tensor(x, device="cuda"), beta, fallback=torch.tensor(fb, device="cuda"),
+                                  fisher=True)
+        L, F, st = L.cpu().numpy(), F.cpu().numpy(), st.cpu().numpy()
+        scale = np.max(np.abs(F_r), axis=(1, 2))[:, None, None]
+        e_f = float(np.max(np.abs(F - F_r) / scale))
+        e_l = float(np.max(np.abs(L - L_r) / np.max(np.abs(L_r), axis=(1, 2))[:, None, None]))
+        print(f"{kind} beta={beta}: fallbacks {int(st.sum())}/{len(x)}, F err {e_f:.1e}, L err {e_l:.1e}", flush=True)
+        np.testing.assert_array_equal(st, st_r)
+        assert e_f <= 1e-12 and e_l <= 1e-12
+        if kind == "bimodal":
+            assert 0 < st.sum() < len(x)   # the saddle takes the fallback, the modes do not
+    c.close()
