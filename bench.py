@@ -46,7 +46,7 @@ OPS_PER_PARTICLE_BIN = {"mixed": 8 + 3 * 21 + 10 + 1,
 
 # The headline sampler: the paper's per-particle local metric (Sec. 5, Eq. 14) with the step that keeps
 # every timed transition's divergent fraction below 5 %.
-HEADLINE = dict(metric="local", step=0.1, alpha=0.95, max_depth=10, runs=3, particles=2048)
+HEADLINE = dict(metric="local", step=0.08, alpha=0.95, max_depth=10, runs=3, particles=2048)
 KERNEL_NAME = "nuts_kernel<3,MIXED,GW,4>"
 
 
@@ -296,6 +296,7 @@ def smc_extras(args, smcgw, synth, ev, prec, value, R, P):
     import torch
     ex = {}
     cap = args.warmup + args.steps + 8
+    log("graph against eager iterations")
     # the same iterations replayed from a captured HIP graph of the whole iteration
     ctx, runs, _ = make_runs(smcgw, synth, ev, R, P, prec, args.metric, args.step, args.alpha, args.max_depth,
                              args.seed, cap)
@@ -312,6 +313,7 @@ def smc_extras(args, smcgw, synth, ev, prec, value, R, P):
     n_plain = min(args.steps, 6)
     for name, form, p_ in (("plain_fp64_sweeps_tangent", smcgw.NUTS_SWEEPS, smcgw.PLAIN_FP64),
                            ("plain_fp64_persistent_adjoint", smcgw.NUTS_PERSISTENT, smcgw.PLAIN_FP64)):
+        log(name)
         ctx, runs, _ = make_runs(smcgw, synth, ev, R, P, p_, args.metric, args.step, args.alpha, args.max_depth,
                                  args.seed, cap, nuts_form=form)
         d_, e_, *_ = time_iterations(smcgw, ctx, runs, args.warmup, n_plain, False)
@@ -319,6 +321,7 @@ def smc_extras(args, smcgw, synth, ev, prec, value, R, P):
         ex[name] = {"evals_per_s": round(e_ / d_, 1), "ms_per_step": round(1e3 * d_ / n_plain, 3),
                     "timed_iterations": f"{args.warmup + 1}-{args.warmup + n_plain}"}
     ex["mixed_over_plain_form"] = round(value / ex["plain_fp64_sweeps_tangent"]["evals_per_s"], 2)
+    log("population metric; full load")
     # the population covariance as the metric (the config's other reading), same step
     ctx, runs, _ = make_runs(smcgw, synth, ev, R, P, prec, "population", args.step, args.alpha, args.max_depth,
                              args.seed, cap)
@@ -362,6 +365,73 @@ def smc_extras(args, smcgw, synth, ev, prec, value, R, P):
     return ex
 
 
+def side_extras(args, smcgw, synth, ev, prec):
+    """Relative binning (8 s and 128 s events folded onto their edges, eps 0.1, fiducial point the injection),
+    the full 128 s likelihood, the SMC iterations on the 8 s relative-binning event and sample recycling of a
+    30 x 2048 pool."""
+    import torch
+    ex = {}
+    ev128 = build_event(smcgw, synth, synth.SPEC_128S)
+    for tag, e in (("8s", ev), ("128s", ev128)):
+        for form in ("full", "rb"):
+            c = smcgw.Context(0)
+            ne = e.n
+            if form == "full":
+                c.add_event(e)
+            else:
+                _, ne = c.add_event_rb(e, e.theta_inj, 0.1)
+            x = torch.tensor(synth.prior_draw(np.random.default_rng(8), 4096, synth.gw_prior_for(e)), device="cuda")
+            ll = torch.empty(4096, dtype=torch.float64, device="cuda")
+            g = torch.empty_like(x)
+            rate = timed_rate(lambda: c.loglike_grad(x, ll, g, precision=prec), 4096, 0.5)
+            c.close()
+            ex[f"loglike_grad_{tag}_{form}"] = {"evals_per_s": round(rate, 1), "bins": ne}
+    c = smcgw.Context(0)
+    c.add_event_rb(ev, ev.theta_inj, 0.1)
+    bounds = synth.gw_prior_for(ev)
+    c.set_prior(bounds)
+    c.set_target(synth.TARGET_GW, 11)
+    R, P = args.runs, args.particles or HEADLINE["particles"]
+    x = np.concatenate([synth.prior_draw(np.random.default_rng(7 + r), P, bounds) for r in range(R)])
+    runs = smcgw.SmcRuns(c, torch.tensor(x, device="cuda"), R, alpha=args.alpha, step=args.step,
+                         max_depth=args.max_depth, shrink=0.0, seed=args.seed, precision=prec, metric=args.metric,
+                         history_cap=args.warmup + args.steps + 8)
+    d_, e_, k_ms, k_n, _, _, h = time_iterations(smcgw, c, runs, args.warmup, args.steps, True)
+    c.close()
+    ex["smc_rb_8s"] = {"evals_per_s": round(e_ / d_, 1), "ms_per_step": round(1e3 * d_ / args.steps, 4),
+                       "max_divergent_frac": max(r["divergent_frac"] for r in iteration_table(smcgw, h, P))}
+    c = smcgw.Context(0)
+    c.add_event(ev)
+    pool = torch.tensor(np.random.default_rng(3).normal(-20.0, 3.0, size=(30, 2048)), device="cuda")
+    bts = np.linspace(0.02, 1.0, 30).tolist()
+    lzs = np.linspace(-1.0, -10.0, 30).tolist()
+    c.recycle(pool, bts, lzs, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        c.recycle(pool, bts, lzs, 1)
+    ex["recycle_ms_30x2048"] = round(1e3 * (time.perf_counter() - t0) / 5, 4)
+    c.close()
+    return ex
+
+
+def timed_rate(f, per_call, min_s):
+    """Calls per second of f times per_call, after two warm-up calls, timed for at least min_s."""
+    import torch
+    for _ in range(2):
+        f()
+    torch.cuda.synchronize()
+    n, t0 = 0, time.perf_counter()
+    while True:
+        for _ in range(10):
+            f()
+        n += 10
+        torch.cuda.synchronize()
+        if time.perf_counter() - t0 >= min_s:
+            break
+    return per_call * n / (time.perf_counter() - t0)
+
+
 # ------------------------------------------------------------------ batched likelihood
 def loglike_rates(smcgw, synth, ev, P=4096, min_s=1.0):
     """Batched logL (+ gradient) rates at P particles, each form timed for at least min_s."""
@@ -375,20 +445,7 @@ def loglike_rates(smcgw, synth, ev, P=4096, min_s=1.0):
              "mixed_forward_only": lambda: c.loglike_grad(x, ll, g, want_grad=False, precision=smcgw.MIXED),
              "plain_fp64_adjoint_grad": lambda: c.loglike_grad(x, ll, g, precision=smcgw.PLAIN_FP64),
              "plain_fp64_tangent_grad": lambda: c.loglike_grad_tangent(x, ll, g)}
-    out = {}
-    for name, f in forms.items():
-        for _ in range(2):
-            f()
-        torch.cuda.synchronize()
-        n, t0 = 0, time.perf_counter()
-        while True:
-            for _ in range(10):
-                f()
-            n += 10
-            torch.cuda.synchronize()
-            if time.perf_counter() - t0 >= min_s:
-                break
-        out[name] = round(P * n / (time.perf_counter() - t0), 1)
+    out = {name: round(timed_rate(f, P, min_s), 1) for name, f in forms.items()}
     c.close()
     return out
 
@@ -544,6 +601,9 @@ def main():
     if not args.no_extra:
         log("batched likelihood rates")
         extra["loglike_4096_evals_per_s"] = loglike_rates(smcgw, synth, ev)
+    if not args.no_extra and args.mode == "smc":
+        log("relative binning, long segment, recycling")
+        extra.update(side_extras(args, smcgw, synth, ev, prec))
     log_z = None
     if not args.no_extra and args.mode == "smc":
         log("log Z error of a full run against the FP64 oracle")

@@ -23,8 +23,10 @@ _SRC = os.path.join(_HERE, "oracle.cpp")
 def build(force: bool = True) -> str:
     """Compile the oracle with g++ (OpenMP, -O2, FP64, no fast-math)."""
     if force or not os.path.exists(_LIB_PATH):
-        cmd = ["g++", "-O2", "-fopenmp", "-std=c++17", "-Wall", "-shared", "-fPIC", _SRC, "-o", _LIB_PATH]
+        tmp = _LIB_PATH + ".tmp"   # replaced atomically: a process that has the library loaded keeps its copy
+        cmd = ["g++", "-O2", "-fopenmp", "-std=c++17", "-Wall", "-shared", "-fPIC", _SRC, "-o", tmp]
         subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
 

@@ -104,9 +104,11 @@ __global__ __launch_bounds__(MOM_THREADS) void metric_moments_kernel(const doubl
             for (int y = 0; y <= x; ++y) acc[e++] += w * g[x] * g[y];
     }
     int e = 0;
+#pragma unroll
     for (int x = 0; x < NGEO; ++x)
+#pragma unroll
         for (int y = 0; y <= x; ++y) {
-            part[threadIdx.x] = acc[e++];
+            part[threadIdx.x] = acc[e++];   // unrolled: acc stays in registers
             __syncthreads();
             if (threadIdx.x == 0) {
                 double s = 0.0;

@@ -38,3 +38,25 @@ def grad_err(g, g_ref, w):
 
 
 CONFIG0_INDEX = [0, 1, 9, 10]   # chirp mass, q, t_c, phi_c
+
+
+def log_ess(ll, db):
+    w = db * (ll - ll.max())
+    return 2 * np.log(np.sum(np.exp(w))) - np.log(np.sum(np.exp(2 * w)))
+
+
+def ladder_bound(betas_ref, lls_ref, lls_gpu):
+    """First-order bound on how far likelihood errors move the beta ladder (Sec. 3, Eq. 6): beta_t solves
+    log ESS(beta_t - beta_{t-1}) = log(alpha N); an error e_i in logL_i shifts log ESS by at most
+    4 (beta_t - beta_{t-1}) max|e|, so the root moves by that over |d log ESS / d beta|, and a shift of
+    beta_{t-1} carries over to beta_t one for one."""
+    bounds, acc, prev = [], 0.0, 0.0
+    for b, ll, lg in zip(betas_ref, lls_ref, lls_gpu):
+        db = b - prev
+        e = float(np.max(np.abs(lg - ll)))
+        h = 1e-6 * max(db, 1e-12)
+        slope = abs(log_ess(ll, db + h) - log_ess(ll, db - h)) / (2 * h)
+        acc += 4 * db * e / max(slope, 1e-300) if b < 1.0 else 0.0
+        bounds.append(acc)
+        prev = b
+    return np.array(bounds)

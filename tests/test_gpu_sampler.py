@@ -10,7 +10,7 @@ from paper_2601_02336_amd import synth
 from paper_2601_02336_amd.synth import Bound
 from oracle import oracle as O
 
-from helpers import CONFIG0_INDEX, event
+from helpers import CONFIG0_INDEX, event, ladder_bound
 
 pytestmark = pytest.mark.gpu
 
@@ -74,28 +74,6 @@ def _replay_logz(ev, idx, populations, alpha):
     return lz, betas, lls
 
 
-def _log_ess(ll, db):
-    w = db * (ll - ll.max())
-    return 2 * np.log(np.sum(np.exp(w))) - np.log(np.sum(np.exp(2 * w)))
-
-
-def _ladder_bound(betas_ref, lls_ref, lls_gpu):
-    """First-order bound on how far likelihood errors move the beta ladder (Sec. 3, Eq. 6): beta_t solves
-    log ESS(beta_t - beta_{t-1}) = log(alpha N); an error e_i in logL_i shifts log ESS by at most
-    4 (beta_t - beta_{t-1}) max|e|, so the root moves by that over |d log ESS / d beta|, and a shift of
-    beta_{t-1} carries over to beta_t one for one."""
-    bounds, acc, prev = [], 0.0, 0.0
-    for b, ll, lg in zip(betas_ref, lls_ref, lls_gpu):
-        db = b - prev
-        e = float(np.max(np.abs(lg - ll)))
-        h = 1e-6 * max(db, 1e-12)
-        slope = abs(_log_ess(ll, db + h) - _log_ess(ll, db - h)) / (2 * h)
-        acc += 4 * db * e / max(slope, 1e-300) if b < 1.0 else 0.0
-        bounds.append(acc)
-        prev = b
-    return np.array(bounds)
-
-
 def test_smc_gw_mixed_precision_evidence(mods):
     """1-detector TaylorF2 event, (Mc, q, t_c, phi_c), 256 particles, alpha = 0.5, depth <= 6.
     The MIXED run's log Z is recomputed with the oracle's FP64 logL on the run's own populations:
@@ -118,7 +96,7 @@ def test_smc_gw_mixed_precision_evidence(mods):
         lz_ref, betas_ref, lls_ref = _replay_logz(ev, idx, r.populations, 0.5)
         lls_gpu = [c.loglike_grad(pop, want_grad=False, precision=prec).cpu().numpy() for pop in r.populations]
         c.close()
-        bound = _ladder_bound(betas_ref, lls_ref, lls_gpu)
+        bound = ladder_bound(betas_ref, lls_ref, lls_gpu)
         print(f"{name}: log Z {r.logz:.6f}, FP64 replay {lz_ref:.6f}, |d| {abs(r.logz - lz_ref):.2e}, "
               f"{r.n_iter} iterations, {sum(r.n_leapfrog)} leapfrog steps, {r.seconds:.2f} s; beta ladder "
               f"|d| {np.round(np.abs(np.array(r.betas) - betas_ref), 10).tolist()} first-order bound "
