@@ -284,6 +284,20 @@ int smcgw_loglike_grad_tangent(smcgw_ctx *ctx, int P, const int32_t *event_of_pa
 int smcgw_target_loglike_grad(smcgw_ctx *ctx, int P, const double *theta, double *logl, double *grad,
                               int precision);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the batched
+ * likelihood and gradient of smcgw_loglike_grad, same arguments and results,
+ * with its per-particle scratch (1 KiB per particle of coefficient and moment
+ * blocks) in a fixed device array of SMCGW_NOALLOC_MAX_P particles (16 MiB)
+ * that each GPU holds from the first context on it until the process ends.
+ * It calls no allocation, creates no event and does not synchronise.
+ * SMCGW_ERR_SHAPE for P > SMCGW_NOALLOC_MAX_P.  Every call on one GPU shares
+ * that GPU's array: calls that overlap on one GPU (other streams, other
+ * contexts, other host threads) race and must be serialised by the caller. */
+#define SMCGW_NOALLOC_MAX_P 16384
+int smcgw_loglike_grad_noalloc(smcgw_ctx *ctx, int P, const int32_t *event_of_particle, const double *theta,
+                               double *logl, double *grad, int precision);
+
 /* Projected detector strain h_d(f_j; theta) of event event_id for one point
  * of the 11 source parameters (theta11, host), written to the device array
  * h_reim [n_det][N][2].  Used to build injections. */

@@ -110,6 +110,12 @@ extern "C" int smcgw_create(smcgw_ctx** out, int device, void* hip_stream) {
         delete c;
         return SMCGW_ERR_OOM;
     }
+    if (noalloc_init(device) != SMCGW_OK) {   // this device's fixed scratch address, once per device
+        hipFree(c->d_events);
+        hipFree(c->d_small);
+        delete c;
+        return SMCGW_ERR_HIP;
+    }
     *out = c;
     return SMCGW_OK;
 }

@@ -216,5 +216,6 @@ hipError_t launch_finish(const DevEvent* d_events, int n_events, const int32_t* 
                          const double* cb, const double* mom, double* logl, double* grad, hipStream_t s);
 hipError_t launch_waveform(const DevEvent* d_events, int event_id, const double* cb, double* h_reim, int n_bins,
                            int n_det, hipStream_t s);
+int noalloc_init(int device);   // the fixed scratch of smcgw_loglike_grad_noalloc on this device
 
 }  // namespace smcgw

@@ -21,6 +21,7 @@
 #include "binloop.h"
 #include "coeffs.h"
 #include "common.h"
+#include "context.h"
 
 namespace smcgw {
 
@@ -102,6 +103,28 @@ __global__ __launch_bounds__(256) void waveform_kernel(const DevEvent* __restric
     }
 }
 
+// ------------------------------------------------------------- fixed scratch
+// Coefficient and moment blocks of smcgw_loglike_grad_noalloc, for at most
+// SMCGW_NOALLOC_MAX_P particles (16 MiB).  Every GPU the library runs on
+// holds its own copy until the process ends.  Host code must not pass the
+// array's name to a kernel (it is a host-side stand-in there): the device
+// address of each GPU's copy is looked up once per device at context set-up
+// and kept in noalloc_base.
+static __device__ __align__(256) double scratch[(size_t)SMCGW_NOALLOC_MAX_P * (CB_SIZE + MOM_SIZE)];
+
+constexpr int NOALLOC_DEVICES = 64;
+static double* noalloc_base[NOALLOC_DEVICES] = {};
+
+// Resolves this device's scratch address (the device must be current).
+int noalloc_init(int device) {
+    if (device < 0 || device >= NOALLOC_DEVICES) return SMCGW_ERR_INVALID;
+    if (noalloc_base[device]) return SMCGW_OK;
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return SMCGW_ERR_HIP;
+    noalloc_base[device] = (double*)ptr;
+    return SMCGW_OK;
+}
+
 // ------------------------------------------------------------- launchers
 hipError_t launch_prep(const DevEvent* d_events, int n_events, const int32_t* ev_of_p, const ParamMap& pm, int P,
                        const double* theta, double* cb, hipStream_t s) {
@@ -151,3 +174,26 @@ hipError_t launch_waveform(const DevEvent* d_events, int event_id, const double*
 }
 
 }  // namespace smcgw
+
+using namespace smcgw;
+
+// The batched likelihood of smcgw_loglike_grad with its per-particle blocks in
+// the fixed scratch array: no allocation, no event, no host synchronisation.
+extern "C" int smcgw_loglike_grad_noalloc(smcgw_ctx* c, int P, const int32_t* event_of_particle, const double* theta,
+                                          double* logl, double* grad, int precision) {
+    if (!c || P < 0 || (P > 0 && (!theta || !logl))) return SMCGW_ERR_INVALID;
+    if (precision != SMCGW_PLAIN_FP64 && precision != SMCGW_MIXED) return SMCGW_ERR_INVALID;
+    if (P > SMCGW_NOALLOC_MAX_P) return SMCGW_ERR_SHAPE;
+    if (c->events.empty()) return SMCGW_ERR_NOT_INIT;
+    if (P == 0) return SMCGW_OK;
+    if (c->device < 0 || c->device >= NOALLOC_DEVICES || !noalloc_base[c->device]) return SMCGW_ERR_NOT_INIT;
+    hipSetDevice(c->device);
+    double* cb = noalloc_base[c->device];
+    double* mom = cb + (size_t)SMCGW_NOALLOC_MAX_P * CB_SIZE;
+    const int ne = (int)c->events.size();
+    if (launch_prep(c->d_events, ne, event_of_particle, c->pmap, P, theta, cb, c->stream) != hipSuccess ||
+        launch_bins(c->d_events, ne, event_of_particle, P, c->n_det, precision, cb, mom, c->stream) != hipSuccess ||
+        launch_finish(c->d_events, ne, event_of_particle, c->pmap, P, cb, mom, logl, grad, c->stream) != hipSuccess)
+        return SMCGW_ERR_HIP;
+    return SMCGW_OK;
+}

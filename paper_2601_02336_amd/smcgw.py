@@ -21,6 +21,7 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "lib", "lib
 OK, WARN_FALLBACK = 0, 1
 ERR_INVALID, ERR_SHAPE, ERR_HIP, ERR_OOM, ERR_NOT_INIT, ERR_STALL = -1, -2, -3, -4, -5, -6
 MAX_BINS = 1 << 24   # frequency bins of one event (SMCGW_MAX_BINS)
+NOALLOC_MAX_P = 16384   # particles of smcgw_loglike_grad_noalloc (SMCGW_NOALLOC_MAX_P)
 PLAIN_FP64, MIXED = 0, 1
 KERNEL_BINS, KERNEL_PREP, KERNEL_FINISH, KERNEL_NUTS, KERNEL_SMC, KERNEL_METRIC = 0, 1, 2, 3, 4, 5
 OPT_NUTS_WAVES = 0
@@ -140,6 +141,7 @@ def lib():
         L.smcgw_timing_read.argtypes = [vp, i, C.POINTER(d), C.POINTER(C.c_int64)]
         L.smcgw_smc_reweight_resample.argtypes = [vp, i, i, d, d, u64, u64, vp, vp, vp, vp, vp,
                                                   C.POINTER(d), C.POINTER(d)]
+        L.smcgw_loglike_grad_noalloc.argtypes = [vp, i, vp, vp, vp, vp, i]
         L.smcgw_loglike_grad_tangent.argtypes = [vp, i, vp, vp, vp, vp]
         L.smcgw_nuts_step_sweeps.argtypes = [vp, i, i, vp, vp, vp, vp, C.POINTER(NutsParams), vp, vp, vp, vp, vp, i,
                                              C.POINTER(i)]
@@ -288,6 +290,20 @@ class Context:
             self._h, P, _ptr(event_of_particle), _ptr(theta), _ptr(logl), _ptr(grad) if want_grad else None,
             precision))
         return (logl, grad) if want_grad else logl
+
+    def loglike_grad_noalloc(self, theta: torch.Tensor, logl: torch.Tensor, grad: Optional[torch.Tensor],
+                             event_of_particle: Optional[torch.Tensor] = None, precision: int = MIXED):
+        """smcgw_loglike_grad_noalloc into caller-provided logl [P] and grad [P][D] (grad may be None):
+        the library allocates nothing (at most NOALLOC_MAX_P particles)."""
+        theta = _dev(theta, torch.float64, "theta")
+        _dev(logl, torch.float64, "logl")
+        if grad is not None:
+            _dev(grad, torch.float64, "grad")
+        if event_of_particle is not None:
+            _dev(event_of_particle, torch.int32, "event_of_particle")
+        self._stream()
+        return lib().smcgw_loglike_grad_noalloc(self._h, theta.shape[0], _ptr(event_of_particle), _ptr(theta),
+                                                _ptr(logl), _ptr(grad), precision)
 
     def loglike_grad_tangent(self, theta: torch.Tensor, logl: Optional[torch.Tensor] = None,
                              grad: Optional[torch.Tensor] = None, want_grad: bool = True,
