@@ -1,5 +1,7 @@
 """Batching: eight events of 4-32 s (4017-64897 bins, 3 detectors, 11 params) and uneven NUTS trees in
 one persistent launch, each particle reading its own event's tables through the event map."""
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -26,6 +28,12 @@ def batch():
     rng = np.random.default_rng(12)
     _, _, L = O.mass_matrix(synth.prior_draw(rng, 4000, bounds), 0.0)
     return evs, bounds, L * 0.05
+
+
+def _agree(a, b, xtol=1e-6):
+    """Rows whose tree (depth, leapfrog count) and selected point (xtol relative) agree."""
+    same = (a["depth"] == b["depth"]) & (a["n_leapfrog"] == b["n_leapfrog"])
+    return same & np.all(np.abs(a["x"] - b["x"]) <= xtol * (1 + np.abs(b["x"])), axis=1)
 
 
 def _ctx(smc, evs, bounds, eop):
@@ -129,3 +137,44 @@ def test_multi_event_uneven_depths_full_size(smc, batch):
         ref_ll, _ = O.loglike_grad(O.gw_target(evs[k], bounds=bounds), th[p:p + 1])
         assert abs(lt[p].item() - ref_ll[0]) <= 1e-6 * abs(ref_ll[0])
     c.close()
+
+
+def _ragged_reference():
+    """The oracle's transitions of sampled particles (tests/golden/make_ragged_uturn_reference.py)."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "ragged_uturn_transition.txt")
+    r = np.array([[float(v) for v in line.split()] for line in open(path) if not line.startswith("#")])
+    return dict(ids=r[:, 0].astype(np.int64), event=r[:, 1].astype(np.int32), depth=r[:, 2].astype(np.int32),
+                n_leapfrog=r[:, 3].astype(np.int32), sensitive=r[:, 5].astype(bool), logl=r[:, 6], x=r[:, 7:])
+
+
+def test_multi_event_natural_uturn_sampled_parity(smc, batch):
+    """The 16384-particle, 8-event launch with the U-turn check on, from prior draws, against the oracle's
+    transitions of 24 sampled particles of the 4 s and 8 s events (4017 and 8033 bins), each replayed on its
+    own random streams against its own event and stored by tests/golden/make_ragged_uturn_reference.py
+    (oracle only).  Every sampled particle takes the oracle's tree and point (1e-6 relative) unless the
+    oracle's own transition changes when its start moves by a relative 1e-7."""
+    evs, bounds, L = batch
+    ref = _ragged_reference()
+    P = 16384
+    eop = (np.arange(P) % 8).astype(np.int32)
+    x = synth.prior_draw(np.random.default_rng(15), P, bounds)
+    assert np.array_equal(eop[ref["ids"]], ref["event"])
+    c = _ctx(smc, evs, bounds, torch.tensor(eop, device="cuda"))
+    xt = torch.tensor(x, device="cuda")
+    lt, gt = c.target_loglike_grad(xt, precision=smc.MIXED)
+    out = c.nuts_step(xt, lt, gt, torch.tensor(L, device="cuda"), step=0.2, beta=0.005, seed=6, iteration=2,
+                      max_depth=10, precision=smc.MIXED)
+    torch.cuda.synchronize()
+    ids = ref["ids"]
+    got = {k: out[k].cpu().numpy()[ids] for k in ("depth", "n_leapfrog")}
+    got["x"] = xt.cpu().numpy()[ids]
+    got["logl"] = lt.cpu().numpy()[ids]
+    c.close()
+    ok = _agree(got, ref)
+    print(f"natural U-turn, {len(ids)} sampled particles of the short events: agree {int(ok.sum())}, "
+          f"oracle-sensitive {int(ref['sensitive'].sum())}; disagreeing {ids[~ok].tolist()} (sensitive "
+          f"{ref['sensitive'][~ok].tolist()}); oracle depths {np.bincount(ref['depth'], minlength=11).tolist()}",
+          flush=True)
+    assert np.all(ref["sensitive"][~ok])
+    assert (~ok).sum() <= ref["sensitive"].sum()
+    np.testing.assert_allclose(got["logl"][ok], ref["logl"][ok], rtol=1e-5)

@@ -1,5 +1,6 @@
 """Parity of the persistent HIP NUTS kernel with the oracle's NUTS (shared Philox streams)."""
 import math
+import os
 
 import numpy as np
 import pytest
@@ -9,7 +10,7 @@ from paper_2601_02336_amd import synth
 from paper_2601_02336_amd.synth import Bound
 from oracle import oracle as O
 
-from helpers import CONFIG0_INDEX, event
+from helpers import CONFIG0_INDEX, event, ladder_bound, widths
 
 pytestmark = pytest.mark.gpu
 
@@ -165,19 +166,47 @@ def _gw_case(smc, ev, idx, P, beta, max_depth, precision, seed=7, step=0.25, shr
         c.set_option(smc.OPT_NUTS_WAVES, waves)
     got = _run_gpu(c, x, ll, g, L, step, beta, seed, 1, max_depth, precision)
     c.close()
-    return got, ref
+    return got, ref, dict(t=t, x=x, L=L, step=step, md=max_depth, beta=beta, seed=seed, w=widths(b))
+
+
+def _logl_consistent(got, ref, ok, rel):
+    """On the agreeing particles, the stored logL differs from the oracle's by no more than the likelihood's
+    own relative error rel plus the first-order change sum_k |g_k dx_k| from the difference of the points."""
+    dx = np.abs(got["x"][ok] - ref["x"][ok])
+    bound = rel * np.abs(ref["logl"][ok]) + 2.0 * np.sum(np.abs(ref["grad"][ok]) * dx, axis=1) + 1e-12
+    err = np.abs(got["logl"][ok] - ref["logl"][ok])
+    assert np.all(err <= bound), float(np.max(err / bound))
+
+
+def _explained(got, ref, case, xtol, floor):
+    """Agreement with the oracle (tree and point to xtol), and for every particle that disagrees whether the
+    oracle's own transition changes when its start moves by the largest difference seen on the agreeing
+    particles (at least floor) of each coordinate's prior width."""
+    ok = _agree(got, ref, xtol)
+    w = case["w"]
+    diff = np.max(np.abs(got["x"] - ref["x"]) / w, axis=1)
+    scale = max(floor, float(diff[ok].max())) if ok.any() else floor
+    bad = np.flatnonzero(~ok)
+    ids = np.arange(len(ok), dtype=np.int32)
+    sens = _sensitive(case["t"], case["x"][bad], case["L"], case["step"], case["md"], case["beta"], case["seed"], 1,
+                      ids[bad], {k: v[bad] for k, v in ref.items()}, scale * w) if bad.size else np.zeros(0, bool)
+    return ok, bad, sens, scale
 
 
 def test_gw_one_detector_parity(smc):
+    """1-detector, 4 parameters, 96 particles: PLAIN takes the oracle's tree and point (1e-9) for every
+    particle; MIXED (1e-6) for every particle except ones whose oracle transition itself changes when the start
+    moves by the largest difference MIXED leaves on the agreeing ones."""
     ev = event(synth.SPEC_SMALL)
-    for name, prec, need in (("plain", smc.PLAIN_FP64, 0.97), ("mixed", smc.MIXED, 0.9)):
-        got, ref = _gw_case(smc, ev, CONFIG0_INDEX, 48, 0.3, 6, prec)
-        ok = _agree(got, ref, 1e-6)
-        print(f"gw 1-det {name}: agree {ok.mean():.3f}, depths {np.bincount(ref['depth'])}", flush=True)
-        assert ok.mean() >= need
-        # selected points agree to 1e-6 relative in MIXED, which moves logL by up to ~1e-5 relative;
-        # the likelihood's own precision is pinned by the likelihood parity tests
-        np.testing.assert_allclose(got["logl"][ok], ref["logl"][ok], rtol=1e-5 if name == "mixed" else 1e-10)
+    for name, prec, xtol, floor in (("plain", smc.PLAIN_FP64, 1e-9, 1e-12), ("mixed", smc.MIXED, 1e-6, 1e-9)):
+        got, ref, case = _gw_case(smc, ev, CONFIG0_INDEX, 96, 0.3, 6, prec)
+        ok, bad, sens, scale = _explained(got, ref, case, xtol, floor)
+        print(f"gw 1-det {name}: agree {int(ok.sum())}/{len(ok)}, disagreeing {bad.tolist()} oracle-sensitive at "
+              f"{scale:.1e} of the width {sens.tolist()}, depths {np.bincount(ref['depth'])}", flush=True)
+        assert ok.mean() >= 0.95 and sens.all()
+        if name == "plain":
+            assert ok.all()
+        _logl_consistent(got, ref, ok, 1e-6 if name == "mixed" else 1e-11)
 
 
 @pytest.mark.parametrize("waves", [2, 6, 8])
@@ -185,20 +214,75 @@ def test_gw_parity_at_every_slot_width(smc, waves):
     """Slot widths other than the default 4: the 2048-bin table has 4 blocks, so at widths 6 and 8 some
     wavefronts hold no block and the bin loop's split across wavefronts changes."""
     ev = event(synth.SPEC_SMALL)
-    for name, prec, need in (("plain", smc.PLAIN_FP64, 0.97), ("mixed", smc.MIXED, 0.9)):
-        got, ref = _gw_case(smc, ev, CONFIG0_INDEX, 48, 0.3, 6, prec, waves=waves)
-        ok = _agree(got, ref, 1e-6)
-        print(f"gw 1-det {name}, {waves} wavefronts per slot: agree {ok.mean():.3f}", flush=True)
-        assert ok.mean() >= need
-        np.testing.assert_allclose(got["logl"][ok], ref["logl"][ok], rtol=1e-5 if name == "mixed" else 1e-10)
+    for name, prec, xtol, floor in (("plain", smc.PLAIN_FP64, 1e-9, 1e-12), ("mixed", smc.MIXED, 1e-6, 1e-9)):
+        got, ref, case = _gw_case(smc, ev, CONFIG0_INDEX, 96, 0.3, 6, prec, waves=waves)
+        ok, bad, sens, scale = _explained(got, ref, case, xtol, floor)
+        print(f"gw 1-det {name}, {waves} wavefronts per slot: agree {int(ok.sum())}/{len(ok)}, disagreeing "
+              f"{bad.tolist()} oracle-sensitive {sens.tolist()}", flush=True)
+        assert ok.mean() >= 0.95 and sens.all()
+        if name == "plain":
+            assert ok.all()
+        _logl_consistent(got, ref, ok, 1e-6 if name == "mixed" else 1e-11)
 
 
-def test_gw_three_detector_parity(smc):
+def _sensitive(t, x, chol, step, max_depth, beta, seed, it, ids, ref, scale, tries=3):
+    """Rows whose oracle transition itself changes (another tree, or a selected point beyond 1e-6 relative)
+    when the start point moves by scale per coordinate in seeded random directions."""
+    rng = np.random.default_rng(12345)
+    out = np.zeros(len(ids), dtype=bool)
+    for _ in range(tries):
+        xp = x + scale * rng.choice([-1.0, 1.0], size=x.shape)
+        alt = O.nuts_step(t, xp, chol, step, max_depth, beta, seed=seed, iteration=it, particle_ids=ids)
+        out |= ~_agree(alt, ref, 1e-6)
+    return out
+
+
+@pytest.mark.parametrize("form", ["persistent", "sweeps"])
+def test_gw_three_detector_plain_parity(smc, form):
+    """PLAIN transitions on the 3-detector, 8033-bin, 11-parameter target (64 particles, eps 0.25, depth <= 5,
+    beta 0.05), in the persistent kernel and in lockstep sweeps with the forward-mode gradient.  Every
+    particle takes the oracle's tree and point (1e-9 relative), except ones whose oracle transition itself
+    changes when the start point moves by the largest difference seen on the agreeing particles (at least
+    1e-12 of each coordinate's prior width)."""
     ev = event(synth.SPEC_8S)
-    got, ref = _gw_case(smc, ev, list(range(11)), 12, 0.05, 4, smc.PLAIN_FP64)
-    ok = _agree(got, ref, 1e-6)
-    print(f"gw 3-det plain: agree {ok.mean():.3f}, depths {np.bincount(ref['depth'])}", flush=True)
-    assert ok.mean() >= 11 / 12
+    idx = list(range(11))
+    b = synth.gw_prior_for(ev)
+    P, beta, md, step, seed = 64, 0.05, 5, 0.25, 7
+    rng = np.random.default_rng(seed)
+    x = synth.prior_draw(rng, P, b)
+    t = O.gw_target(ev, param_index=idx)
+    ll, g = O.loglike_grad(t, x)
+    _, _, L = O.mass_matrix(synth.prior_draw(rng, 4000, b), 0.0)
+    L = L * 0.05
+    ids = np.arange(P, dtype=np.int32)
+    ref = O.nuts_step(t, x, L, step, md, beta, seed=seed, iteration=1, particle_ids=ids)
+    c = smc.Context(0)
+    c.add_event(ev)
+    c.set_prior(b)
+    c.set_target(synth.TARGET_GW, 11)
+    if form == "persistent":
+        got = _run_gpu(c, x, ll, g, L, step, beta, seed, 1, md, smc.PLAIN_FP64)
+    else:
+        xt, lt, gt = (torch.tensor(v, device="cuda") for v in (x, ll, g))
+        out = c.nuts_step_sweeps(xt, lt, gt, torch.tensor(L, device="cuda"), step=step, beta=beta, seed=seed,
+                                 iteration=1, max_depth=md)
+        torch.cuda.synchronize()
+        got = {k: v.cpu().numpy() for k, v in out.items() if k != "n_sweeps"}
+        got.update(x=xt.cpu().numpy(), logl=lt.cpu().numpy(), grad=gt.cpu().numpy())
+    c.close()
+    w = widths(b)
+    ok = _agree(got, ref, 1e-9)
+    diff = np.max(np.abs(got["x"] - ref["x"]) / w, axis=1)
+    scale = max(1e-12, float(diff[ok].max())) if ok.any() else 1e-12
+    bad = np.flatnonzero(~ok)
+    sens = _sensitive(t, x[bad], L, step, md, beta, seed, 1, ids[bad], {k: v[bad] for k, v in ref.items()},
+                      scale * w) if bad.size else np.zeros(0, bool)
+    print(f"gw 3-det plain {form}: agree {int(ok.sum())}/{P}, largest agreeing difference {scale:.1e} of the "
+          f"width, disagreeing {bad.tolist()} sensitive {sens.tolist()}, depths {np.bincount(ref['depth'])}",
+          flush=True)
+    assert ok.mean() >= 0.95
+    assert sens.all()
+    _logl_consistent(got, ref, ok, 1e-11)
 
 
 def test_schedule_does_not_change_results(smc):
@@ -271,38 +355,77 @@ def test_autotune_keeps_inputs_and_sets_width(smc):
     np.testing.assert_array_equal(runs[0][1], runs[1][1])
 
 
-def test_bench_configuration_sampled_parity(smc):
-    """The launch the benchmark times: 2048 particles, 3 detectors, 8033 bins, 11 parameters, MIXED, eps = 0.5,
-    depth <= 10, the population-covariance metric, beta of a first SMC iteration.  Sixteen particles spread
-    over the batch are replayed by the oracle with their own random streams (particle ids).  At eps = 0.5 the
-    trajectories are chaotic (a 1e-13 change of the start point changes trees), so MIXED rounding sends some
-    particles onto other trees: at least 10 of the 16 must agree."""
+def _bench_launch_reference():
+    """The oracle's replay of the benchmark's first iteration (tests/golden/make_bench_launch_reference.py)."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "bench_launch_first_iteration.txt")
+    ref = {"rows": []}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("#"):
+                continue
+            key, rest = line.split(" ", 1)
+            if key in ("beta", "dlogz"):
+                ref[key] = float(rest)
+            elif key == "ancestors":
+                ref["ancestors"] = np.array(rest.split(), dtype=np.int32)
+            else:
+                ref["rows"].append([float(v) for v in line.split()])
+    r = np.array(ref["rows"])
+    ref.update(ids=r[:, 0].astype(np.int32), depth=r[:, 1].astype(np.int32), n_leapfrog=r[:, 2].astype(np.int32),
+               divergent=r[:, 3].astype(np.uint8), sensitive=r[:, 4].astype(bool), logl=r[:, 5], x=r[:, 6:])
+    return ref
+
+
+@pytest.mark.parametrize("precision", ["mixed", "plain"])
+def test_bench_launch_sampled_parity(smc, precision):
+    """The launch the benchmark times, at full size: the first SMC iteration of three runs of 2048 particles
+    (3 detectors, 8033 bins, 11 parameters, MIXED, alpha 0.95, eps 0.08, depth <= 10, the per-particle local
+    metric) in one iteration call, against the oracle's FP64 replay of run 0 from the same prior draws (its own
+    likelihoods, temperature, resampling, covariance and local metric, then 64 sampled transitions on their
+    own random streams; stored by tests/golden/make_bench_launch_reference.py, which calls only the oracle).
+    The temperature agrees to the first-order bound of MIXED's likelihood error and the ancestors agree.  The
+    oracle's own transitions change under a relative 1e-7 move of the start point for the particles it marks
+    sensitive; every sampled particle where the GPU takes another tree or point (1e-6 relative) must be one
+    of them, and there may be no more such particles than sensitive ones.  The same holds for the launch at
+    PLAIN_FP64: at eps 0.08 most trees run 500-1023 leapfrog steps, over which even FP64 rounding differences
+    grow into other trees for some of the sensitive particles."""
+    ref = _bench_launch_reference()
     ev = event(synth.SPEC_8S)
     b = synth.gw_prior_for(ev)
-    P, beta = 2048, 0.0025
-    x = synth.prior_draw(np.random.default_rng(7), P, b)
-    t = O.gw_target(ev)
-    _, _, L = O.mass_matrix(x, 0.0)
+    R, P, alpha, step, md, seed = 3, 2048, 0.95, 0.08, 10, 1
+    x0 = np.concatenate([synth.prior_draw(np.random.default_rng(7 + r), P, b) for r in range(R)])
     c = smc.Context(0)
     c.add_event(ev)
     c.set_prior(b)
     c.set_target(synth.TARGET_GW, 11)
-    xt = torch.tensor(x, device="cuda")
-    lt, gt = c.target_loglike_grad(xt, precision=smc.MIXED)
-    out = c.nuts_step(xt, lt, gt, torch.tensor(L, device="cuda"), step=0.5, beta=beta, seed=1, iteration=3,
-                      max_depth=10, precision=smc.MIXED)
+    prec = smc.MIXED if precision == "mixed" else smc.PLAIN_FP64
+    runs = smc.SmcRuns(c, torch.tensor(x0, device="cuda"), R, alpha=alpha, step=step, max_depth=md, shrink=0.0,
+                       seed=seed, precision=prec, metric="local", history_cap=4)
+    ll_gpu0 = runs.logl[:P].cpu().numpy()
+    runs.step()
     torch.cuda.synchronize()
-    got = {k: v.cpu().numpy() for k, v in out.items()}
-    xg, lg = xt.cpu().numpy(), lt.cpu().numpy()
+    anc = runs.ancestors[:P].cpu().numpy()
+    got = {k: getattr(runs, k)[:P].cpu().numpy() for k in ("depth", "n_leapfrog")}
+    got["x"] = runs.theta[:P].cpu().numpy()
+    got["logl"] = runs.logl[:P].cpu().numpy()
+    beta_gpu = float(runs.history()[0, 0, smc.H_BETA])
     c.close()
-    ids = np.array([0, 129, 257, 400, 611, 777, 1023, 1024, 1190, 1350, 1500, 1666, 1777, 1901, 2000, 2047],
-                   dtype=np.int32)
-    ll0, _ = O.loglike_grad(t, x[ids])
-    ref = O.nuts_step(t, x[ids], L, 0.5, 10, beta, seed=1, iteration=3, particle_ids=ids)
-    same = (got["depth"][ids] == ref["depth"]) & (got["n_leapfrog"][ids] == ref["n_leapfrog"])
-    close = np.all(np.abs(xg[ids] - ref["x"]) <= 1e-6 * (1 + np.abs(ref["x"])), axis=1)
-    ok = same & close
-    print(f"bench configuration: depths GPU {got['depth'][ids].tolist()} oracle {ref['depth'].tolist()}, "
-          f"agree {int(ok.sum())}/{len(ids)}, batch mean depth {got['depth'].mean():.2f}", flush=True)
-    assert ok.sum() >= 10
-    np.testing.assert_allclose(lg[ids][ok], ref["logl"][ok], rtol=1e-5)
+    t = O.gw_target(ev)
+    ll = O.loglike_grad(t, x0[:P], want_grad=False)   # the first-order bound needs the FP64 likelihoods
+    bound = 2 * ladder_bound([ref["beta"]], [ll], [ll_gpu0])[0] + 1e-12
+    same_anc = anc == ref["ancestors"]
+    ids = ref["ids"]
+    g_ = {k: v[ids] for k, v in got.items()}
+    ok = _agree(g_, ref, 1e-6)
+    bad = ~ok
+    print(f"bench launch, {precision}: beta GPU {beta_gpu:.10g} oracle {ref['beta']:.10g} (first-order bound {bound:.1e}); "
+          f"ancestors equal {same_anc.mean():.4f}; sampled {len(ids)}: agree {int(ok.sum())}, oracle-sensitive "
+          f"{int(ref['sensitive'].sum())}; disagreeing {ids[bad].tolist()} (sensitive "
+          f"{ref['sensitive'][bad].tolist()}, GPU depth/leapfrog {g_['depth'][bad].tolist()}/"
+          f"{g_['n_leapfrog'][bad].tolist()}, oracle {ref['depth'][bad].tolist()}/{ref['n_leapfrog'][bad].tolist()}); "
+          f"oracle depths {np.bincount(ref['depth']).tolist()}", flush=True)
+    assert abs(beta_gpu - ref["beta"]) <= bound
+    assert same_anc.mean() >= 0.99 and np.all(same_anc[ids])
+    assert np.all(ref["sensitive"][bad])
+    assert bad.sum() <= ref["sensitive"].sum()
+    np.testing.assert_allclose(g_["logl"][ok], ref["logl"][ok], rtol=1e-5 if precision == "mixed" else 1e-9)
