@@ -8,6 +8,8 @@
 * The running log Z kept in the device state is the sum of the recorded increments (Sec. 3.1, Eq. 8)
   and matches the oracle's FP64 reweighting of the recorded ladder.
 """
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -147,3 +149,59 @@ def test_iteration_matches_oracle_ladder(mods):
     assert r.n_iter == ref["n_iter"]
     np.testing.assert_allclose(r.betas, ref["betas"], rtol=1e-9, atol=1e-14)
     assert abs(r.logz - ref["logz"]) < 1e-6
+
+
+@pytest.mark.parametrize("n_runs,P,D", [(64, 2, 3), (3, 300, 16), (1, 5000, 1)])
+def test_iteration_edge_shapes_match_oracle_runs(mods, n_runs, P, D):
+    """The most runs one call takes (64) with the fewest particles a run may have (2), the largest sampled
+    dimension (16) and a single coordinate: every run, batched in one call per iteration, follows the oracle's
+    own whole FP64 run with key seed + r (Gaussian prior x Gaussian likelihood; beta ladder to 1e-9, log Z to
+    1e-6)."""
+    smc, smcgw = mods
+    rng = np.random.default_rng(n_runs * 1000 + D)
+    mu0, s0 = np.zeros(D), np.full(D, 2.0)
+    prm = np.concatenate([rng.normal(size=D), rng.uniform(0.3, 1.5, size=D)])
+    bounds = [synth.Bound(mu0[k], s0[k], synth.BND_NONE, synth.PRIOR_GAUSSIAN) for k in range(D)]
+    t = O.Target(synth.TARGET_GAUSS_X_GAUSS, D, bounds, params=prm)
+    x0 = rng.normal(size=(n_runs * P, D)) * s0 + mu0
+    c = smcgw.Context(0)
+    c.set_prior(bounds)
+    c.set_target(synth.TARGET_GAUSS_X_GAUSS, D, prm)
+    res = smc.run_smc_batched(c, torch.tensor(x0, device="cuda"), n_runs,
+                              smc.SmcConfig(alpha=0.5, step=0.5, max_depth=6, seed=30, precision=smcgw.PLAIN_FP64))
+    c.close()
+    worst = 0.0
+    for r in range(n_runs):
+        ref = O.smc_run(t, x0[r * P:(r + 1) * P], alpha=0.5, step=0.5, max_depth=6, shrink=0.0, seed=30 + r)
+        assert res[r].n_iter == ref["n_iter"], r
+        np.testing.assert_allclose(res[r].betas, ref["betas"], rtol=1e-9, atol=1e-14)
+        worst = max(worst, abs(res[r].logz - ref["logz"]))
+    print(f"{n_runs} runs x {P} particles, D = {D}: iterations {[x.n_iter for x in res[:4]]}..., "
+          f"max |d log Z| {worst:.1e}", flush=True)
+    assert worst < 1e-6
+
+
+def test_iteration_rejects_bad_descriptors(mods):
+    """Shapes beyond the limits and the plain form at MIXED precision are refused before anything is queued."""
+    smc, smcgw = mods
+    D = 2
+    bounds = [synth.Bound(0.0, 1.0, synth.BND_NONE, synth.PRIOR_GAUSSIAN)] * D
+    c = smcgw.Context(0)
+    c.set_prior(bounds)
+    c.set_target(synth.TARGET_GAUSS, D)
+    runs = smcgw.SmcRuns(c, torch.zeros((8, D), dtype=torch.float64, device="cuda"), 2, alpha=0.5, step=0.5,
+                         max_depth=4, shrink=0.0, seed=1, precision=smcgw.PLAIN_FP64, history_cap=4)
+    L = smcgw.lib()
+    snap = runs.state_dev.clone()
+    for field, value, code in (("n_runs", smcgw.MAX_RUNS + 1, smcgw.ERR_SHAPE), ("P", 1, smcgw.ERR_SHAPE),
+                               ("D", 17, smcgw.ERR_SHAPE), ("alpha", 0.0, smcgw.ERR_INVALID),
+                               ("max_depth", 99, smcgw.ERR_INVALID), ("nuts_form", smcgw.NUTS_SWEEPS, smcgw.ERR_INVALID),
+                               ("precision", 7, smcgw.ERR_INVALID)):
+        desc = smcgw.SmcIterDesc.from_buffer_copy(runs.desc)
+        if field == "nuts_form":
+            desc.precision = smcgw.MIXED
+        setattr(desc, field, value)
+        assert L.smcgw_smc_iteration(c._h, ctypes.byref(desc)) == code, field
+    torch.cuda.synchronize()
+    assert torch.equal(runs.state_dev, snap)
+    c.close()

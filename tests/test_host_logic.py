@@ -78,3 +78,20 @@ def test_sampler_entry_points_reject_bad_arguments():
                                         None, None, None, None) == smcgw.ERR_INVALID
     assert L.smcgw_recycle(None, 0, 4, None, None, None, u(0), None, None, None, None) == smcgw.ERR_INVALID
     assert L.smcgw_add_event_rb(None, None, None, None, None, None, d(0.1), None, None) == smcgw.ERR_INVALID
+
+
+def test_iteration_entry_points_reject_bad_arguments():
+    """The whole-iteration call, its graph and the plain comparison form refuse NULL contexts, descriptors and
+    handles before any device call."""
+    from paper_2601_02336_amd import smcgw
+    L = smcgw.lib()
+    desc = smcgw.SmcIterDesc()
+    assert L.smcgw_smc_iteration(None, None) == smcgw.ERR_INVALID
+    assert L.smcgw_smc_iteration(None, ctypes.byref(desc)) == smcgw.ERR_INVALID
+    out = ctypes.c_void_p()
+    assert L.smcgw_smc_graph_create(None, ctypes.byref(desc), ctypes.byref(out)) == smcgw.ERR_INVALID
+    assert L.smcgw_smc_graph_create(None, ctypes.byref(desc), None) == smcgw.ERR_INVALID
+    assert L.smcgw_graph_launch(None, 1) == smcgw.ERR_INVALID
+    assert L.smcgw_graph_destroy(None) == smcgw.ERR_INVALID
+    assert L.smcgw_loglike_grad_tangent(None, 4, None, None, None, None) == smcgw.ERR_INVALID
+    assert L.smcgw_loglike_grad_noalloc(None, 4, None, None, None, None, smcgw.MIXED) == smcgw.ERR_INVALID
