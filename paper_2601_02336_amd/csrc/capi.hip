@@ -42,20 +42,20 @@ TimedLaunch::TimedLaunch(smcgw_ctx* ctx, int kernel_class) : c(ctx), cls(kernel_
     if (!on()) return;
     a = pool_event(c);
     b = pool_event(c);
-    if (a) hipEventRecord(a, c->stream);
+    if (a) (void)hipEventRecord(a, c->stream);
 }
 
 TimedLaunch::~TimedLaunch() {
     if (!on() || !a || !b) return;
-    hipEventRecord(b, c->stream);
+    (void)hipEventRecord(b, c->stream);
     c->ev_pending[cls].push_back({a, b});
 }
 
 int ctx_reserve(smcgw_ctx* c, int P) {
     if (P <= c->cap) return SMCGW_OK;
     const int cap = std::max(P, std::max(2 * c->cap, 256));
-    hipFree(c->d_cb);
-    hipFree(c->d_mom);
+    (void)hipFree(c->d_cb);
+    (void)hipFree(c->d_mom);
     c->d_cb = nullptr;
     c->d_mom = nullptr;
     c->cap = 0;
@@ -106,13 +106,13 @@ extern "C" int smcgw_create(smcgw_ctx** out, int device, void* hip_stream) {
     for (int k = 0; k < NPAR; ++k) { c->pmap.idx[k] = k; c->pmap.fixed[k] = 0.0; }
     if (hipMalloc(&c->d_events, SMCGW_MAX_EVENTS * sizeof(DevEvent)) != hipSuccess ||
         hipMalloc(&c->d_small, 4096) != hipSuccess) {
-        hipFree(c->d_events);
+        (void)hipFree(c->d_events);
         delete c;
         return SMCGW_ERR_OOM;
     }
     if (noalloc_init(device) != SMCGW_OK) {   // this device's fixed scratch address, once per device
-        hipFree(c->d_events);
-        hipFree(c->d_small);
+        (void)hipFree(c->d_events);
+        (void)hipFree(c->d_small);
         delete c;
         return SMCGW_ERR_HIP;
     }
@@ -122,19 +122,19 @@ extern "C" int smcgw_create(smcgw_ctx** out, int device, void* hip_stream) {
 
 extern "C" int smcgw_destroy(smcgw_ctx* c) {
     if (!c) return SMCGW_ERR_INVALID;
-    hipSetDevice(c->device);
-    hipStreamSynchronize(c->stream);
-    for (void* p : c->event_bufs) hipFree(p);
-    hipFree(c->d_events);
-    hipFree(c->d_small);
-    hipFree(c->d_cb);
-    hipFree(c->d_mom);
-    hipFree(c->d_tan);
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    for (void* p : c->event_bufs) (void)hipFree(p);
+    (void)hipFree(c->d_events);
+    (void)hipFree(c->d_small);
+    (void)hipFree(c->d_cb);
+    (void)hipFree(c->d_mom);
+    (void)hipFree(c->d_tan);
     c->sweep_free();
     c->sampler_free();
     for (auto& v : c->ev_pending)
-        for (auto& pr : v) { hipEventDestroy(pr.first); hipEventDestroy(pr.second); }
-    for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
+        for (auto& pr : v) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     delete c;
     return SMCGW_OK;
 }
@@ -164,7 +164,7 @@ extern "C" int smcgw_timing_enable(smcgw_ctx* c, int class_mask) {
 extern "C" int smcgw_timing_read(smcgw_ctx* c, int kernel_class, double* total_ms, int64_t* launches) {
     if (!c || kernel_class < 0 || kernel_class >= SMCGW_KERNEL_CLASSES || !total_ms || !launches)
         return SMCGW_ERR_INVALID;
-    hipSetDevice(c->device);
+    if (hipSetDevice(c->device) != hipSuccess) return SMCGW_ERR_HIP;
     if (hipStreamSynchronize(c->stream) != hipSuccess) return SMCGW_ERR_HIP;
     double tot = 0.0;
     int64_t n = 0;
@@ -226,13 +226,13 @@ static int build_event(smcgw_ctx* c, const smcgw_event_desc* ev, const double* d
         }
     const double us = umax > 0.0 ? std::ldexp(1.0, (int)std::lround(std::log2(umax))) : 1.0;
 
-    hipSetDevice(c->device);
+    if (hipSetDevice(c->device) != hipSuccess) return SMCGW_ERR_HIP;
     double *d_data = nullptr, *d_psd = nullptr, *fwl = nullptr, *sums = nullptr, *wmom = nullptr, *wa2 = nullptr;
     float2* u32 = nullptr;
     double2* u64 = nullptr;
     auto fail = [&](int code) {
-        hipFree(d_data); hipFree(d_psd); hipFree(fwl); hipFree(u32); hipFree(u64); hipFree(sums); hipFree(wmom);
-        hipFree(wa2);
+        (void)hipFree(d_data); (void)hipFree(d_psd); (void)hipFree(fwl); (void)hipFree(u32); (void)hipFree(u64); (void)hipFree(sums); (void)hipFree(wmom);
+        (void)hipFree(wa2);
         return code;
     };
     if (hipMalloc(&d_data, sizeof(double) * 2 * nd * (size_t)n) != hipSuccess ||
@@ -254,9 +254,9 @@ static int build_event(smcgw_ctx* c, const smcgw_event_desc* ev, const double* d
     if (hipMemcpyAsync(hs, sums, sizeof(double) * 2 * nd, hipMemcpyDeviceToHost, c->stream) ||
         hipStreamSynchronize(c->stream))
         return fail(SMCGW_ERR_HIP);
-    hipFree(d_data);
-    hipFree(d_psd);
-    hipFree(sums);
+    (void)hipFree(d_data);
+    (void)hipFree(d_psd);
+    (void)hipFree(sums);
 
     std::memset(&de, 0, sizeof(de));
     de.n_bins = n;
@@ -304,7 +304,7 @@ static int register_event(smcgw_ctx* c, const DevEvent& de, void* const bufs[EVE
     const int id = (int)c->events.size();
     if (hipMemcpyAsync(c->d_events + id, &de, sizeof(de), hipMemcpyHostToDevice, c->stream) ||
         hipStreamSynchronize(c->stream)) {
-        for (int k = 0; k < EVENT_BUFS; ++k) hipFree(bufs[k]);
+        for (int k = 0; k < EVENT_BUFS; ++k) (void)hipFree(bufs[k]);
         return SMCGW_ERR_HIP;
     }
     c->events.push_back(de);
@@ -380,12 +380,12 @@ extern "C" int smcgw_add_event_rb(smcgw_ctx* c, const smcgw_event_desc* ev, cons
     double2 *u64 = nullptr, *v = nullptr, *a0 = nullptr, *a1 = nullptr;
     int32_t *d_edges = nullptr, *d_id = nullptr;
     auto release = [&]() {
-        hipFree(v); hipFree(a0); hipFree(a1); hipFree(d_edges); hipFree(cb0); hipFree(th0); hipFree(d_id);
-        hipFree(fb[0]); hipFree(fb[1]); hipFree(fb[2]); hipFree(fb[4]);
+        (void)hipFree(v); (void)hipFree(a0); (void)hipFree(a1); (void)hipFree(d_edges); (void)hipFree(cb0); (void)hipFree(th0); (void)hipFree(d_id);
+        (void)hipFree(fb[0]); (void)hipFree(fb[1]); (void)hipFree(fb[2]); (void)hipFree(fb[4]);
     };
     auto fail = [&](int code) {
         release();
-        hipFree(fb[3]); hipFree(fwl); hipFree(u32); hipFree(u64);
+        (void)hipFree(fb[3]); (void)hipFree(fwl); (void)hipFree(u32); (void)hipFree(u64);
         return code;
     };
     if (hipMalloc(&fwl, sizeof(double) * NROWS * (size_t)npad) != hipSuccess ||
@@ -452,14 +452,14 @@ extern "C" int smcgw_loglike_grad(smcgw_ctx* c, int P, const int32_t* event_of_p
     if (!c || P < 0 || (P > 0 && (!theta || !logl))) return SMCGW_ERR_INVALID;
     if (precision != SMCGW_PLAIN_FP64 && precision != SMCGW_MIXED) return SMCGW_ERR_INVALID;
     if (P == 0) return SMCGW_OK;
-    hipSetDevice(c->device);
+    if (hipSetDevice(c->device) != hipSuccess) return SMCGW_ERR_HIP;
     return ctx_loglike(c, P, event_of_particle, theta, logl, grad, precision);
 }
 
 extern "C" int smcgw_waveform(smcgw_ctx* c, int event_id, const double* theta11, double* h_reim) {
     if (!c || !theta11 || !h_reim) return SMCGW_ERR_INVALID;
     if (event_id < 0 || event_id >= (int)c->events.size()) return SMCGW_ERR_INVALID;
-    hipSetDevice(c->device);
+    if (hipSetDevice(c->device) != hipSuccess) return SMCGW_ERR_HIP;
     int rc = ctx_reserve(c, 1);
     if (rc) return rc;
     // d_small: [0, 88) theta11, [128, 132) event index

@@ -68,28 +68,28 @@ struct smcgw_ctx {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending[SMCGW_KERNEL_CLASSES];
 
     void sweep_free() {
-        if (sweep_exec) hipGraphExecDestroy(sweep_exec);
-        if (sweep_graph) hipGraphDestroy(sweep_graph);
+        if (sweep_exec) (void)hipGraphExecDestroy(sweep_exec);
+        if (sweep_graph) (void)hipGraphDestroy(sweep_graph);
         sweep_exec = nullptr;
         sweep_graph = nullptr;
         sweep_key.clear();
-        hipFree(d_sweep);
+        (void)hipFree(d_sweep);
         d_sweep = nullptr;
         sweep_bytes = 0;
     }
 
     void sampler_free() {
-        hipFree(d_target_params);
-        hipFree(d_sampler);
-        hipFree(d_queue);
-        hipFree(d_order);
-        hipFree(d_mm);
+        (void)hipFree(d_target_params);
+        (void)hipFree(d_sampler);
+        (void)hipFree(d_queue);
+        (void)hipFree(d_order);
+        (void)hipFree(d_mm);
         d_mm = nullptr;
         mm_bytes = 0;
         d_queue = nullptr;
         d_order = nullptr;
         order_cap = 0;
-        if (h_pinned) hipHostFree(h_pinned);
+        if (h_pinned) (void)hipHostFree(h_pinned);
         d_target_params = nullptr;
         d_sampler = nullptr;
         h_pinned = nullptr;

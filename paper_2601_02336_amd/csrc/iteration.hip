@@ -49,7 +49,7 @@ int check_desc(smcgw_ctx* c, const smcgw_smc_iter_desc* d) {
 // Every device buffer the iteration's kernels use, sized before anything is
 // queued (so that a capture records no allocation).
 int reserve(smcgw_ctx* c, const smcgw_smc_iter_desc* d) {
-    hipSetDevice(c->device);
+    if (hipSetDevice(c->device) != hipSuccess) return SMCGW_ERR_HIP;
     if (!sampler_scratch(c, reweight_scratch_bytes(d->n_runs, d->P, d->D))) return SMCGW_ERR_OOM;
     if (mm_reserve(c, d->n_runs, d->P) != SMCGW_OK) return SMCGW_ERR_OOM;
     if (nuts_reserve(c, d->n_runs * d->P, true) != SMCGW_OK) return SMCGW_ERR_OOM;
@@ -144,7 +144,7 @@ extern "C" int smcgw_smc_graph_create(smcgw_ctx* c, const smcgw_smc_iter_desc* d
 
 extern "C" int smcgw_graph_launch(smcgw_graph* g, int count) {
     if (!g || count < 0) return SMCGW_ERR_INVALID;
-    hipSetDevice(g->c->device);
+    if (hipSetDevice(g->c->device) != hipSuccess) return SMCGW_ERR_HIP;
     for (int k = 0; k < count; ++k)
         if (hipGraphLaunch(g->exec, g->c->stream) != hipSuccess) return SMCGW_ERR_HIP;
     return SMCGW_OK;
@@ -152,7 +152,7 @@ extern "C" int smcgw_graph_launch(smcgw_graph* g, int count) {
 
 extern "C" int smcgw_graph_destroy(smcgw_graph* g) {
     if (!g) return SMCGW_ERR_INVALID;
-    hipSetDevice(g->c->device);
+    (void)hipSetDevice(g->c->device);
     (void)hipStreamSynchronize(g->c->stream);
     (void)hipGraphExecDestroy(g->exec);
     (void)hipGraphDestroy(g->graph);

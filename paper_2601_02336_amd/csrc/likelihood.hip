@@ -187,7 +187,7 @@ extern "C" int smcgw_loglike_grad_noalloc(smcgw_ctx* c, int P, const int32_t* ev
     if (c->events.empty()) return SMCGW_ERR_NOT_INIT;
     if (P == 0) return SMCGW_OK;
     if (c->device < 0 || c->device >= NOALLOC_DEVICES || !noalloc_base[c->device]) return SMCGW_ERR_NOT_INIT;
-    hipSetDevice(c->device);
+    if (hipSetDevice(c->device) != hipSuccess) return SMCGW_ERR_HIP;
     double* cb = noalloc_base[c->device];
     double* mom = cb + (size_t)SMCGW_NOALLOC_MAX_P * CB_SIZE;
     const int ne = (int)c->events.size();

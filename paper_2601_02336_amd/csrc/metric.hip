@@ -369,6 +369,6 @@ extern "C" int smcgw_local_metric(smcgw_ctx* c, int P, int D, const double* thet
     const int rc = metric_target_ok(c, D);
     if (rc) return rc;
     if (P == 0) return SMCGW_OK;
-    hipSetDevice(c->device);
+    if (hipSetDevice(c->device) != hipSuccess) return SMCGW_ERR_HIP;
     return launch_metric(c, P, theta, beta, beta_device, fallback_chol, chol, fisher, status, nullptr, P);
 }

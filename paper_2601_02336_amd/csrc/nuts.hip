@@ -1161,7 +1161,7 @@ int launch_gw(smcgw_ctx* c, int precision, const NutsArgs& a, const PriorDesc& p
 int smcgw::nuts_reserve(smcgw_ctx* c, int P, bool hint) {
     if (!c->d_queue && hipMalloc(&c->d_queue, 256) != hipSuccess) return SMCGW_ERR_OOM;
     if (hint && P > c->order_cap) {
-        hipFree(c->d_order);
+        (void)hipFree(c->d_order);
         c->d_order = nullptr;
         c->order_cap = 0;
         if (hipMalloc(&c->d_order, (size_t)P * sizeof(int32_t)) != hipSuccess) return SMCGW_ERR_OOM;
@@ -1192,7 +1192,7 @@ extern "C" int smcgw_nuts_step(smcgw_ctx* c, int P, int D, double* theta, double
         return SMCGW_ERR_NOT_INIT;
     }
     if (P == 0) return SMCGW_OK;
-    hipSetDevice(c->device);
+    if (hipSetDevice(c->device) != hipSuccess) return SMCGW_ERR_HIP;
     if (nuts_reserve(c, P, work_hint != nullptr) != SMCGW_OK) return SMCGW_ERR_OOM;
     if (work_hint) {
         hipLaunchKernelGGL(order_kernel, dim3(1), dim3(ORDER_THREADS), 0, c->stream, work_hint, P, c->d_order);
@@ -1256,7 +1256,7 @@ extern "C" int smcgw_autotune_nuts(smcgw_ctx* c, int P, int D, const double* the
                                    int trials, int* best_waves, double* times_ms) {
     if (!c || !prm || P < 1 || D <= 0 || D > MAXDIM || !theta || !logl || !grad || !chol || trials < 1 || trials > 16)
         return SMCGW_ERR_INVALID;
-    hipSetDevice(c->device);
+    if (hipSetDevice(c->device) != hipSuccess) return SMCGW_ERR_HIP;
     const size_t nx = (size_t)P * D * sizeof(double), nl = (size_t)P * sizeof(double);
     double *x = nullptr, *l = nullptr, *g = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1381,7 +1381,7 @@ extern "C" int smcgw_nuts_step_sweeps(smcgw_ctx* c, int P, int D, double* theta,
     if (!tangent_supported(c)) return SMCGW_ERR_INVALID;
     if (n_sweeps_host) *n_sweeps_host = 0;
     if (P == 0) return SMCGW_OK;
-    hipSetDevice(c->device);
+    if (hipSetDevice(c->device) != hipSuccess) return SMCGW_ERR_HIP;
     SweepScratch s;
     int rc = tangent_reserve(c, P);
     if (rc == SMCGW_OK) rc = sweep_reserve(c, P, D, s);
@@ -1426,8 +1426,8 @@ extern "C" int smcgw_nuts_step_sweeps(smcgw_ctx* c, int P, int D, double* theta,
     const int extra[3] = {sweeps_per_group, c->n_det, (int)(c->timing_mask != 0)};
     std::memcpy(kp + sizeof(a) + sizeof(PriorDesc) + sizeof(ParamMap), extra, sizeof(extra));
     if (key != c->sweep_key || !c->sweep_exec) {
-        if (c->sweep_exec) hipGraphExecDestroy(c->sweep_exec);
-        if (c->sweep_graph) hipGraphDestroy(c->sweep_graph);
+        if (c->sweep_exec) (void)hipGraphExecDestroy(c->sweep_exec);
+        if (c->sweep_graph) (void)hipGraphDestroy(c->sweep_graph);
         c->sweep_exec = nullptr;
         c->sweep_graph = nullptr;
         c->sweep_key.clear();

@@ -162,7 +162,7 @@ int tangent_reserve(smcgw_ctx* c, int P) {
     int rc = ctx_reserve(c, P);
     if (rc) return rc;
     if (P <= c->tan_cap) return SMCGW_OK;
-    hipFree(c->d_tan);
+    (void)hipFree(c->d_tan);
     c->d_tan = nullptr;
     c->tan_cap = 0;
     const int cap = std::max(P, c->cap);
@@ -212,7 +212,7 @@ extern "C" int smcgw_loglike_grad_tangent(smcgw_ctx* c, int P, const int32_t* ev
     if (c->events.empty()) return SMCGW_ERR_NOT_INIT;
     if (!tangent_supported(c)) return SMCGW_ERR_INVALID;
     if (P == 0) return SMCGW_OK;
-    hipSetDevice(c->device);
+    if (hipSetDevice(c->device) != hipSuccess) return SMCGW_ERR_HIP;
     int rc = tangent_reserve(c, P);
     if (rc) return rc;
     return queue_loglike_tangent(c, P, event_of_particle, theta, nullptr, logl, grad);

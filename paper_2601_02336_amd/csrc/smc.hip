@@ -634,7 +634,7 @@ __global__ void export_pair_kernel(const double* __restrict__ out, double* __res
 // Scratch of the sampler entry points (device), grown on demand.
 void* sampler_scratch(smcgw_ctx* c, size_t bytes) {
     if (bytes <= c->sampler_bytes) return c->d_sampler;
-    hipFree(c->d_sampler);
+    (void)hipFree(c->d_sampler);
     c->d_sampler = nullptr;
     c->sampler_bytes = 0;
     const size_t cap = std::max(bytes, (size_t)1 << 20);
@@ -683,7 +683,7 @@ extern "C" int smcgw_set_target(smcgw_ctx* c, int kind, int dim, const double* p
     default: return SMCGW_ERR_INVALID;
     }
     if (n_params < need || (need > 0 && !params)) return SMCGW_ERR_INVALID;
-    hipSetDevice(c->device);
+    if (hipSetDevice(c->device) != hipSuccess) return SMCGW_ERR_HIP;
     if (!c->d_target_params && hipMalloc(&c->d_target_params, 64 * sizeof(double)) != hipSuccess)
         return SMCGW_ERR_OOM;
     if (need > 0 &&
@@ -700,7 +700,7 @@ extern "C" int smcgw_mass_matrix(smcgw_ctx* c, int P, int D, const double* theta
                                  double* chol, int32_t* status_device) {
     if (!c || !theta || !inv_mass || !chol || P < 2 || D <= 0 || D > MAXDIM || !(shrink >= 0.0))
         return SMCGW_ERR_INVALID;
-    hipSetDevice(c->device);
+    if (hipSetDevice(c->device) != hipSuccess) return SMCGW_ERR_HIP;
     int* st = status_device;
     double* hp = nullptr;
     if (!st) {
@@ -736,7 +736,7 @@ int queue_reweight_resample(smcgw_ctx* c, int n_runs, int P, int D, double beta_
     if (!c || n_runs < 1 || P < 1 || D <= 0 || D > MAXDIM || !theta || !logl || !ancestors) return SMCGW_ERR_INVALID;
     if (!(alpha > 0.0 && alpha <= 1.0) || !(beta_prev >= 0.0 && beta_prev <= 1.0)) return SMCGW_ERR_INVALID;
     if ((size_t)n_runs * P > (size_t)INT32_MAX) return SMCGW_ERR_SHAPE;
-    hipSetDevice(c->device);
+    if (hipSetDevice(c->device) != hipSuccess) return SMCGW_ERR_HIP;
     const size_t n = (size_t)n_runs * P;
     const size_t off_cum = 64 * sizeof(double) * ((n_runs * OUT_SIZE + 63) / 64);
     const size_t off_x = off_cum + n * sizeof(double);
@@ -780,7 +780,7 @@ int mm_reserve(smcgw_ctx* c, int n_runs, int P) {
     const int nblk = (P + MMB - 1) / MMB;
     const size_t need = (size_t)n_runs * nblk * MM_SUMS * sizeof(double);
     if (need <= c->mm_bytes) return SMCGW_OK;
-    hipFree(c->d_mm);
+    (void)hipFree(c->d_mm);
     c->d_mm = nullptr;
     c->mm_bytes = 0;
     if (hipMalloc(&c->d_mm, need) != hipSuccess) return SMCGW_ERR_OOM;
@@ -854,7 +854,7 @@ extern "C" int smcgw_target_loglike_grad(smcgw_ctx* c, int P, const double* thet
     if (!c || P < 0 || (P > 0 && (!theta || !logl))) return SMCGW_ERR_INVALID;
     if (precision != SMCGW_PLAIN_FP64 && precision != SMCGW_MIXED) return SMCGW_ERR_INVALID;
     if (P == 0) return SMCGW_OK;
-    hipSetDevice(c->device);
+    if (hipSetDevice(c->device) != hipSuccess) return SMCGW_ERR_HIP;
     if (c->target.kind == SMCGW_TARGET_GW) return ctx_loglike(c, P, c->ev_of_p, theta, logl, grad, precision);
     if (c->target.dim <= 0) return SMCGW_ERR_NOT_INIT;
     hipLaunchKernelGGL(analytic_loglike_kernel, dim3((P + 255) / 256), dim3(256), 0, c->stream, c->target.kind, P,
@@ -870,7 +870,7 @@ extern "C" int smcgw_recycle(smcgw_ctx* c, int T, int N, const double* logl, con
         return SMCGW_ERR_INVALID;
     for (int t = 0; t < T; ++t)
         if (!(betas_host[t] >= 0.0 && betas_host[t] <= 1.0) || !std::isfinite(logz_host[t])) return SMCGW_ERR_INVALID;
-    hipSetDevice(c->device);
+    if (hipSetDevice(c->device) != hipSuccess) return SMCGW_ERR_HIP;
     const int n = T * N;
     char* s = (char*)sampler_scratch(c, 64 * sizeof(double) + 2 * (size_t)T * sizeof(double));
     double* hp = pinned(c);
@@ -904,7 +904,7 @@ extern "C" int smcgw_ps_reweight_resample(smcgw_ctx* c, int T, int N, int D, con
     for (int t = 0; t < T; ++t)
         if (!(betas_host[t] >= 0.0 && betas_host[t] <= 1.0) || !std::isfinite(logz_host[t])) return SMCGW_ERR_INVALID;
     const double beta_prev = betas_host[T - 1];
-    hipSetDevice(c->device);
+    if (hipSetDevice(c->device) != hipSuccess) return SMCGW_ERR_HIP;
     const int n = T * N;
     const size_t off_bz = 64 * sizeof(double);
     const size_t off_lofs = off_bz + 2 * (size_t)T * sizeof(double);
