@@ -581,8 +581,8 @@ def main():
                     help="also run one 256 MiB device copy (reference dispatch for memory-traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for {args.gpus}); splitting particles across GPUs is "
-              "described in the design notes and not part of this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); splitting the particles across GPUs is "
+              "not implemented", file=sys.stderr)
         sys.exit(2)
 
     from paper_2601_02336_amd import smcgw, synth

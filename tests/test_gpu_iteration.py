@@ -2,7 +2,7 @@
 
 * Independent runs batched in one call (their NUTS transitions in one persistent launch) give, run by
   run, bitwise the results of one-run calls with seed + r.
-* A captured graph of the iteration, replayed with the driver's own eager work (state read-backs,
+* A captured graph of the iteration, replayed with the host loop's own eager work (state read-backs,
   population copies) between the replays, reproduces the eager iterations row by row.
 * Iterations queued after a run has finished leave it untouched, so the host may queue ahead.
 * The running log Z kept in the device state is the sum of the recorded increments (Sec. 3.1, Eq. 8)
