@@ -65,9 +65,10 @@ def test_batched_runs_equal_standalone_runs(mods, metric):
     c.close()
 
 
-def test_graph_replays_equal_eager_iterations(mods):
+@pytest.mark.parametrize("metric", ["population", "local"])
+def test_graph_replays_equal_eager_iterations(mods, metric):
     """Every replay of the graph is checked: the per-iteration records (beta, log Z, increment, leapfrog
-    steps, depth, divergences) equal those of the eager run row by row."""
+    steps, depth, divergences) equal those of the eager run row by row, with either metric."""
     smc, smcgw = mods
     ev = event(synth.SPEC_SMALL)
     c, b = _gw_context(smcgw, ev, CONFIG0_INDEX)
@@ -76,7 +77,7 @@ def test_graph_replays_equal_eager_iterations(mods):
     out = {}
     for graph in (False, True):
         cfg = smc.SmcConfig(alpha=0.5, step=0.5, max_depth=6, seed=7, precision=smcgw.MIXED, graph=graph,
-                            record=True)
+                            record=True, metric=metric)
         out[graph] = smc.run_smc_batched(c, x0, R, cfg)
     for r in range(R):
         e, g = out[False][r], out[True][r]
