@@ -338,8 +338,10 @@ int smcgw_local_metric(smcgw_ctx *ctx, int P, int D, const double *theta, double
 
 /* One No-U-Turn transition per particle (Sec. 4: momentum r ~ N(0, M),
  * Hamiltonian H = -log p_t + r^T M^{-1} r / 2, leapfrog Eqs. 11-13,
- * reflective / periodic boundaries of Sec. 5; multinomial trajectory
- * sampling with the generalised U-turn criterion).  theta [P][D], logl [P]
+ * reflective / periodic boundaries of Sec. 5, a reflecting wall taken as the
+ * specular reflection of the drift in the metric, which flips the crossing
+ * coordinate's velocity and conserves the kinetic energy; multinomial
+ * trajectory sampling with the generalised U-turn criterion).  theta [P][D], logl [P]
  * and grad [P][D] (device) hold the current point, its likelihood and the
  * likelihood gradient on entry and the selected point on exit.  chol [D][D]
  * (device) is the Cholesky factor of M^{-1}, or chol [P][D][D] one factor
