@@ -32,14 +32,15 @@ sys.path.insert(0, ROOT)
 METRIC = "logL+grad evals/s (3 det, 8k bins, 11 params); log-Z err vs FP64 oracle"
 
 # Peak VALU issue rate of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-operations/s
-# (a wave64 instruction occupies a SIMD for 4 cycles; transcendentals issue at quarter rate).
+# (a wave64 FMA, FP32 or FP64, occupies a SIMD for 4 cycles; a wave64 v_sin_f32 / v_cos_f32 occupies it for
+# 8 cycles, twice an FMA, and does not overlap other VALU instructions).
 VALU_PEAK_TLANEOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 # Algorithmic VALU lane-operations per (particle, bin) of the MIXED bin loop with 3 detectors
-# (transcendentals counted as 4): phase 8 FP64 FMA; per detector 1 FMA (delay) + 1 (fractional part)
-# + 1 convert + 4 (sin) + 4 (cos) + 4 (complex product) + 2 (Z) + 2 (q) + 1 (T) + 1 (psibar) = 21;
+# (a transcendental counted as 2): phase 8 FP64 FMA; per detector 1 FMA (delay) + 1 (fractional part)
+# + 1 convert + 2 (sin) + 2 (cos) + 4 (complex product) + 2 (Z) + 2 (q) + 1 (T) + 1 (psibar) = 17;
 # moments 1 convert + 8 FP64 FMA + 1 add; frequency convert 1.
-OPS_PER_PARTICLE_BIN = {"mixed": 8 + 3 * 21 + 10 + 1,
+OPS_PER_PARTICLE_BIN = {"mixed": 8 + 3 * 17 + 10 + 1,
                         # PLAIN_FP64: same algebra, FP64 sincospi counted as the 40 VALU operations of a
                         # range-reduced polynomial pair, no converts.
                         "plain": 8 + 3 * (1 + 2 + 40 + 4 + 2 + 2 + 1 + 1) + 9}
