@@ -332,37 +332,54 @@ def smc_extras(args, smcgw, synth, ev, prec, value, R, P):
                                "max_divergent_frac": max(r["divergent_frac"] for r in iteration_table(smcgw, h, P)),
                                "kernel_frac": round(OPS_PER_PARTICLE_BIN[args.precision] * ev.n * e_ /
                                                     (k_ms / 1e3) / 1e12 / VALU_PEAK_TLANEOPS, 4)}
-    # every slot busy: 768 particles (three 4-wavefront slots on each of the 256 CUs), forced depth-7 trees with
-    # the U-turn check off; the rate counts the leapfrog steps the launch reports
+    # every slot busy: forced depth-7 trees with the U-turn check off, the rate counting the leapfrog steps the
+    # launch reports.  768 particles give one particle to each slot (three 4-wavefront slots on each of the 256
+    # CUs), so the launch lasts as long as the slowest slot; 6144 give each slot a queue of eight, so the slots
+    # stay busy until the last round.
     c3 = smcgw.Context(0)
     c3.add_event(ev)
     bounds = synth.gw_prior_for(ev)
     c3.set_prior(bounds)
     c3.set_target(synth.TARGET_GW, 11)
-    P_full, d_full = 768, 7
-    x_full = torch.tensor(synth.prior_draw(np.random.default_rng(1), P_full, bounds), device="cuda")
-    l_full, g_full = c3.target_loglike_grad(x_full, precision=prec)
-    md_full = torch.full((P_full,), d_full, dtype=torch.int32, device="cuda")
+    d_full = 7
     L_full = torch.eye(11, dtype=torch.float64, device="cuda") * 0.01
-    best = None
-    for i in range(3):
-        xx, ll, gg = x_full.clone(), l_full.clone(), g_full.clone()
-        torch.cuda.synchronize()
-        c3.timing_read(smcgw.KERNEL_NUTS)
-        c3.timing(smcgw.KERNEL_NUTS)
-        o = c3.nuts_step(xx, ll, gg, L_full, step=0.1, beta=0.01, seed=1, iteration=i, max_depth=d_full, uturn=False,
-                         max_depth_per_particle=md_full, precision=prec)
-        c3.timing()
-        ms = c3.timing_read(smcgw.KERNEL_NUTS)[0]
-        n = int(o["n_leapfrog"].sum().item())
-        if best is None or n / ms > best[0] / best[1]:
-            best = (n, ms)
+    for key, P_full in (("one_particle_per_slot", 768), ("full_load_nuts", 6144)):
+        x_full = torch.tensor(synth.prior_draw(np.random.default_rng(1), P_full, bounds), device="cuda")
+        l_full, g_full = c3.target_loglike_grad(x_full, precision=prec)
+        md_full = torch.full((P_full,), d_full, dtype=torch.int32, device="cuda")
+        best = None
+        for i in range(3):
+            xx, ll, gg = x_full.clone(), l_full.clone(), g_full.clone()
+            torch.cuda.synchronize()
+            c3.timing_read(smcgw.KERNEL_NUTS)
+            c3.timing(smcgw.KERNEL_NUTS)
+            o = c3.nuts_step(xx, ll, gg, L_full, step=0.1, beta=0.01, seed=1, iteration=i, max_depth=d_full,
+                             uturn=False, max_depth_per_particle=md_full, precision=prec)
+            c3.timing()
+            ms = c3.timing_read(smcgw.KERNEL_NUTS)[0]
+            n = int(o["n_leapfrog"].sum().item())
+            if best is None or n / ms > best[0] / best[1]:
+                best = (n, ms)
+        rate_full = best[0] / (best[1] / 1e3)
+        ex[key] = {"particles": P_full, "evals_per_s": round(rate_full, 1), "kernel_ms": round(best[1], 4),
+                   "leapfrog_counted": best[0], "leapfrog_expected": P_full * (2 ** d_full - 1),
+                   "frac": round(OPS_PER_PARTICLE_BIN[args.precision] * ev.n * rate_full / 1e12 /
+                                 VALU_PEAK_TLANEOPS, 4)}
     c3.close()
-    rate_full = best[0] / (best[1] / 1e3)
-    ex["full_load_nuts"] = {"evals_per_s": round(rate_full, 1), "kernel_ms": round(best[1], 4),
-                            "leapfrog_counted": best[0], "leapfrog_expected": P_full * (2 ** d_full - 1),
-                            "frac": round(OPS_PER_PARTICLE_BIN[args.precision] * ev.n * rate_full / 1e12 /
-                                          VALU_PEAK_TLANEOPS, 4)}
+    # the same iterations with 1 and 8 runs per launch: a launch ends with the longest trees its particles
+    # drew, so the idle tail shrinks against the launch as the runs per launch grow
+    log("runs per launch")
+    scan = []
+    for r_ in (1, 8):
+        ctx, runs, _ = make_runs(smcgw, synth, ev, r_, P, prec, args.metric, args.step, args.alpha,
+                                 args.max_depth, args.seed, cap)
+        d_, e_, k_ms, k_n, _, _, h = time_iterations(smcgw, ctx, runs, args.warmup, args.steps, True)
+        ctx.close()
+        scan.append({"runs": r_, "evals_per_s": round(e_ / d_, 1), "ms_per_step": round(1e3 * d_ / args.steps, 4),
+                     "per_launch_frac": round(OPS_PER_PARTICLE_BIN[args.precision] * ev.n * e_ / (k_ms / 1e3) /
+                                              1e12 / VALU_PEAK_TLANEOPS, 4),
+                     "max_divergent_frac": max(r["divergent_frac"] for r in iteration_table(smcgw, h, P))})
+    ex["runs_per_launch"] = scan
     return ex
 
 

@@ -762,6 +762,8 @@ __global__ __launch_bounds__(WAVES * 64, (WAVES == 1 ? 2 : NUTS_WAVES_PER_SIMD))
     if (tid == 0) {
         A = a;
         if (a.beta_dev) A.beta = *a.beta_dev;
+        // once per launch on one lane: kept rolled, so the logs are not copied out per coordinate
+#pragma unroll 1
         for (int k = 0; k < MAXDIM; ++k) {
             S.plo[k] = pri.lo[k]; S.phi[k] = pri.hi[k]; S.pbnd[k] = pri.bnd[k]; S.pkind[k] = pri.kind[k];
             S.pidx[k] = pm.idx[k];
@@ -1042,6 +1044,7 @@ __global__ __launch_bounds__(64, NUTS_WAVES_PER_SIMD) void nuts_sweep_kernel(Nut
     if (lane == 0) {
         A = a;
         if (a.beta_dev) A.beta = *a.beta_dev;
+#pragma unroll 1
         for (int k = 0; k < MAXDIM; ++k) {
             S.plo[k] = pri.lo[k]; S.phi[k] = pri.hi[k]; S.pbnd[k] = pri.bnd[k]; S.pkind[k] = pri.kind[k];
             S.pidx[k] = pm.idx[k];
