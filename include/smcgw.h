@@ -488,7 +488,9 @@ int smcgw_recycle(smcgw_ctx *ctx, int T, int N, const double *logl, const double
 /* ------------------------------------------------------------ options
  * Launch-shape options of a context (chosen by the autotuner or by hand).
  *   SMCGW_OPT_NUTS_WAVES: wavefronts that share one particle's bin loop in the
- *     persistent NUTS kernel (2, 4, 6 or 8; 0 = the library default of 4).
+ *     persistent NUTS kernel (2, 4, 6 or 8; 0 = the library default: 2 when
+ *     no event of the context has more than 1024 padded bins, as with
+ *     relative-binning events, else 4).
  *   SMCGW_OPT_NUTS_PRIORITY: 1 (default) raises the issue priority of a
  *     slot's wavefronts as its tree deepens, so the longest trajectories of
  *     a transition run ahead of the short ones that share their compute

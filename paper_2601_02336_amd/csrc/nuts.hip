@@ -1147,10 +1147,21 @@ int launch_gw_w(smcgw_ctx* c, int precision, const NutsArgs& a, const PriorDesc&
     return launch_persistent(c, nuts_kernel<NDET, SMCGW_PLAIN_FP64, SMCGW_TARGET_GW, W>, W * 64, a, pri, pm, t);
 }
 
+// Slot width when none is set: the bin loop splits an event into blocks of
+// TABLE_PAD bins, one wavefront per block, so when no event of the context has
+// more than two blocks (relative-binning events) wider slots add wavefronts
+// that hold only prologue roles; two-wavefront slots give every compute unit
+// twice the particles in flight instead.  Otherwise four.
+int default_nuts_waves(const smcgw_ctx* c) {
+    int blocks = 0;
+    for (const DevEvent& e : c->events) blocks = std::max(blocks, e.n_pad / TABLE_PAD);
+    return blocks <= 2 ? 2 : 4;
+}
+
 template <int NDET>
 int launch_gw(smcgw_ctx* c, int precision, const NutsArgs& a, const PriorDesc& pri, const ParamMap& pm,
               const TargetDesc& t) {
-    switch (c->nuts_waves) {
+    switch (c->nuts_waves ? c->nuts_waves : default_nuts_waves(c)) {
     case 2: return launch_gw_w<NDET, 2>(c, precision, a, pri, pm, t);
     case 6: return launch_gw_w<NDET, 6>(c, precision, a, pri, pm, t);
     case 8: return launch_gw_w<NDET, 8>(c, precision, a, pri, pm, t);

@@ -161,3 +161,37 @@ def test_smc_evidence_with_relative_binning(smcgw):
         assert r.betas[-1] == 1.0
         vals.append(r.logz)
     assert abs(np.mean(vals) - ref) <= 0.3
+
+
+def test_rb_default_slot_width_gives_the_same_transitions(smcgw):
+    """A relative-binning event fits in one block of bins, so the library's default slot width is two
+    wavefronts there; the bin sums have the same terms in the same order as with four, so every output of a
+    NUTS step equals the one with four wavefronts set by hand."""
+    ev = event(synth.SPEC_SMALL)
+    idx = CONFIG0_INDEX
+    full = synth.gw_prior_for(ev)
+    b = [full[i] for i in idx]
+    rng = np.random.default_rng(11)
+    x = synth.prior_draw(rng, 256, b)
+    L = torch.tensor(np.diag(0.05 * widths(b)), device="cuda")
+    outs = []
+    for w in (0, 4):
+        c = smcgw.Context(0)
+        c.add_event_rb(ev, ev.theta_inj, 0.1)
+        c.set_param_map(idx, ev.theta_inj)
+        c.set_prior(b)
+        c.set_target(synth.TARGET_GW, len(idx))
+        c.set_option(smcgw.OPT_NUTS_WAVES, w)
+        xt = torch.tensor(x, device="cuda")
+        lt, gt = c.target_loglike_grad(xt, precision=smcgw.MIXED)
+        out = c.nuts_step(xt, lt, gt, L, step=0.25, beta=0.3, seed=5, iteration=2, max_depth=6,
+                          precision=smcgw.MIXED)
+        torch.cuda.synchronize()
+        outs.append({"x": xt.cpu(), "logl": lt.cpu(), "grad": gt.cpu(), **{k: v.cpu() for k, v in out.items()}})
+        c.close()
+    print("depths", np.bincount(outs[0]["depth"].numpy()), flush=True)
+    for k in outs[0]:
+        a, b2 = outs[0][k], outs[1][k]
+        if a.is_floating_point():   # the same NaNs (if any) at the same places count as equal
+            a, b2 = torch.nan_to_num(a, nan=7.0), torch.nan_to_num(b2, nan=7.0)
+        assert torch.equal(a, b2), k
