@@ -343,7 +343,7 @@ def smc_extras(args, smcgw, synth, ev, prec, value, R, P):
     c3.set_target(synth.TARGET_GW, 11)
     d_full = 7
     L_full = torch.eye(11, dtype=torch.float64, device="cuda") * 0.01
-    for key, P_full in (("one_particle_per_slot", 768), ("full_load_nuts", 6144)):
+    for key, P_full in (("lone_slots", 96), ("one_particle_per_slot", 768), ("full_load_nuts", 6144)):
         x_full = torch.tensor(synth.prior_draw(np.random.default_rng(1), P_full, bounds), device="cuda")
         l_full, g_full = c3.target_loglike_grad(x_full, precision=prec)
         md_full = torch.full((P_full,), d_full, dtype=torch.int32, device="cuda")
@@ -380,7 +380,98 @@ def smc_extras(args, smcgw, synth, ev, prec, value, R, P):
                                               1e12 / VALU_PEAK_TLANEOPS, 4),
                      "max_divergent_frac": max(r["divergent_frac"] for r in iteration_table(smcgw, h, P))})
     ex["runs_per_launch"] = scan
+    log("tail model")
+    ex["tail_model"] = tail_model(args, smcgw, synth, ev, prec, R, P, cap, ex["lone_slots"], ex["full_load_nuts"])
     return ex
+
+
+def queue_span(work, order, slots, lone_us, full_us):
+    """Span (us) and slot occupancy of one persistent NUTS launch in a queue model: `slots` slots take the
+    particles in `order`, particle p needs work[p] leaves, and while b slots are busy each advances at one leaf
+    per lone_us + (full_us - lone_us) * (b - 1) / (slots - 1) microseconds."""
+    work = np.asarray(work, dtype=np.float64)
+    rem = np.zeros(slots)
+    busy = np.zeros(slots, dtype=bool)
+    q = 0
+    for k in range(slots):
+        while q < len(order) and work[order[q]] <= 0:
+            q += 1
+        if q < len(order):
+            rem[k], busy[k] = work[order[q]], True
+            q += 1
+    t = slot_time = 0.0
+    while busy.any():
+        b = int(busy.sum())
+        leaf = lone_us + (full_us - lone_us) * ((b - 1) / (slots - 1) if slots > 1 else 1.0)
+        dt = rem[busy].min() * leaf
+        t += dt
+        slot_time += b * dt
+        rem[busy] -= dt / leaf
+        for k in np.nonzero(busy & (rem <= 1e-9))[0]:
+            while q < len(order) and work[order[q]] <= 0:
+                q += 1
+            if q < len(order):
+                rem[k] = work[order[q]]
+                q += 1
+            else:
+                busy[k] = False
+    return t, (slot_time / (slots * t) if t > 0 else 1.0)
+
+
+def start_order(hint):
+    """The NUTS launch's start order for a work hint: descending floor(log2(hint)) + 1 (0 for hint <= 0, at most
+    15), stable in the particle index."""
+    h = np.asarray(hint, dtype=np.int64)
+    bucket = np.where(h <= 0, 0, np.minimum(15, np.floor(np.log2(np.maximum(h, 1))).astype(np.int64) + 1))
+    return np.lexsort((np.arange(len(h)), -bucket))
+
+
+def tail_model(args, smcgw, synth, ev, prec, R, P, cap, lone, full):
+    """The headline's iterations replayed with each NUTS launch timed on its own and the per-particle leapfrog
+    counts read back; a queue model (queue_span), calibrated on the lone-slot and full-load launches, predicts
+    each launch's span from those counts in the launch's own start order (the ancestors' last counts, as the
+    iteration uses them) and in the order of the counts themselves (longest first).  The calibration launches
+    have the U-turn check off, so the headline's leaves are somewhat longer than the model's (the ratio
+    measured / model is reported per launch); the slot occupancy does not depend on that common scale."""
+    import torch
+    slots = 3 * torch.cuda.get_device_properties(0).multi_processor_count
+    lone_us = 1e3 * lone["kernel_ms"] / (2 ** 7 - 1)
+    full_us = slots / full["evals_per_s"] * 1e6
+    ctx, runs, _ = make_runs(smcgw, synth, ev, R, P, prec, args.metric, args.step, args.alpha, args.max_depth,
+                             args.seed, cap)
+    ctx.timing(smcgw.KERNEL_NUTS)
+    prev = None
+    measured, model_hint, model_lpt, occ_hint, occ_lpt, corr = [], [], [], [], [], []
+    for it in range(args.warmup + args.steps):
+        ctx.timing_read(smcgw.KERNEL_NUTS)
+        runs.step()
+        torch.cuda.synchronize()
+        ms, n = ctx.timing_read(smcgw.KERNEL_NUTS)
+        nlf = runs.n_leapfrog.cpu().numpy().astype(np.int64)
+        anc = runs.ancestors.cpu().numpy().astype(np.int64) + np.repeat(np.arange(R) * P, P)
+        if it >= args.warmup and prev is not None and n == 1:
+            hint = prev[anc]
+            sh, oh = queue_span(nlf, start_order(hint), slots, lone_us, full_us)
+            sl, ol = queue_span(nlf, np.argsort(-nlf, kind="stable"), slots, lone_us, full_us)
+            measured.append(ms)
+            model_hint.append(sh / 1e3)
+            model_lpt.append(sl / 1e3)
+            occ_hint.append(oh)
+            occ_lpt.append(ol)
+            corr.append(float(np.corrcoef(np.log1p(nlf), np.log1p(hint))[0, 1]))
+        prev = nlf
+    ctx.timing()
+    ctx.close()
+    ratio = np.array(measured) / np.array(model_hint)
+    return {"slots": slots, "lone_leaf_us": round(lone_us, 3), "full_leaf_us": round(full_us, 3),
+            "launches": len(measured), "measured_launch_ms": round(float(np.mean(measured)), 4),
+            "model_launch_ms": round(float(np.mean(model_hint)), 4),
+            "measured_over_model": [round(float(ratio.min()), 3), round(float(ratio.mean()), 3),
+                                    round(float(ratio.max()), 3)],
+            "model_slot_occupancy": round(float(np.mean(occ_hint)), 4),
+            "model_launch_ms_longest_first": round(float(np.mean(model_lpt)), 4),
+            "model_slot_occupancy_longest_first": round(float(np.mean(occ_lpt)), 4),
+            "corr_log_count_ancestor_count": [round(float(np.min(corr)), 3), round(float(np.max(corr)), 3)]}
 
 
 def side_extras(args, smcgw, synth, ev, prec):

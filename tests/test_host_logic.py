@@ -20,6 +20,29 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.stdout.strip() == ""
 
 
+def test_bench_queue_model_and_start_order():
+    """The queue model behind the bench's tail figures: slots take particles in order and share their compute
+    unit (the leaf time grows from lone_us with one busy slot to full_us with every slot busy); a bad order leaves
+    slots idle in the tail, longest first does not; the start order is the launch's log2 buckets of the hint,
+    descending and stable."""
+    sys.path.insert(0, ROOT)
+    import bench
+    span, occ = bench.queue_span([3, 2], [0, 1], 1, 1.0, 1.0)
+    assert span == pytest.approx(5.0) and occ == pytest.approx(1.0)
+    span, occ = bench.queue_span([4, 4, 4, 4], [0, 1, 2, 3], 2, 1.0, 1.0)
+    assert span == pytest.approx(8.0) and occ == pytest.approx(1.0)
+    span, occ = bench.queue_span([1, 1, 1, 3], [0, 1, 2, 3], 2, 1.0, 1.0)
+    assert span == pytest.approx(4.0) and occ == pytest.approx(0.75)
+    span, occ = bench.queue_span([1, 1, 1, 3], [3, 0, 1, 2], 2, 1.0, 1.0)
+    assert span == pytest.approx(3.0) and occ == pytest.approx(1.0)
+    # contention: two busy slots take the full-load leaf time, a lone one the lone time
+    assert bench.queue_span([1, 1], [0, 1], 2, 1.0, 2.0)[0] == pytest.approx(2.0)
+    assert bench.queue_span([1], [0], 2, 1.0, 2.0)[0] == pytest.approx(1.0)
+    # particles without leaves take no slot time
+    assert bench.queue_span([0, 2, 0], [0, 1, 2], 1, 1.0, 1.0)[0] == pytest.approx(2.0)
+    assert bench.start_order([0, 5, 100, 5, 1]).tolist() == [2, 1, 3, 4, 0]
+
+
 def test_bench_iteration_table_and_traffic_gate(tmp_path, monkeypatch):
     """The per-iteration rows are the runs' records divided by the run size (the largest divergent fraction over
     the runs), and counter traffic is reported only for the kernel sources, kernel and command it was taken on."""
