@@ -426,13 +426,21 @@ def start_order(hint):
     return np.lexsort((np.arange(len(h)), -bucket))
 
 
+def striped_order(n, queues=8, stripe=16):
+    """The start order of a launch without a hint, the XCDs' queues taken side by side: particle p is the
+    k-th of queue (p // stripe) % queues with k = (p // (stripe * queues)) * stripe + p % stripe."""
+    p = np.arange(n)
+    return np.lexsort(((p // stripe) % queues, (p // (stripe * queues)) * stripe + p % stripe))
+
+
 def tail_model(args, smcgw, synth, ev, prec, R, P, cap, lone, full):
     """The headline's iterations replayed with each NUTS launch timed on its own and the per-particle leapfrog
-    counts read back; a queue model (queue_span), calibrated on the lone-slot and full-load launches, predicts
-    each launch's span from those counts in the launch's own start order (the ancestors' last counts, as the
-    iteration uses them) and in the order of the counts themselves (longest first).  The calibration launches
-    have the U-turn check off, so the headline's leaves are somewhat longer than the model's (the ratio
-    measured / model is reported per launch); the slot occupancy does not depend on that common scale."""
+    counts and ancestors read back; a queue model (queue_span), calibrated on the lone-slot and full-load
+    launches, predicts each launch's span from those counts in the launch's own start order (the XCDs' stripes
+    of neighbouring particles, striped_order), in the order a hint of the ancestors' last counts would give
+    (start_order) and in the order of the counts themselves (longest first).  The calibration launches have the
+    U-turn check off, so the headline's leaves are somewhat longer than the model's (the ratio measured / model
+    is reported per launch); the slot occupancy does not depend on that common scale."""
     import torch
     slots = 3 * torch.cuda.get_device_properties(0).multi_processor_count
     lone_us = 1e3 * lone["kernel_ms"] / (2 ** 7 - 1)
@@ -441,7 +449,7 @@ def tail_model(args, smcgw, synth, ev, prec, R, P, cap, lone, full):
                              args.seed, cap)
     ctx.timing(smcgw.KERNEL_NUTS)
     prev = None
-    measured, model_hint, model_lpt, occ_hint, occ_lpt, corr = [], [], [], [], [], []
+    measured, model_own, model_hint, model_lpt, occ_own, occ_hint, occ_lpt, corr = [], [], [], [], [], [], [], []
     for it in range(args.warmup + args.steps):
         ctx.timing_read(smcgw.KERNEL_NUTS)
         runs.step()
@@ -451,24 +459,28 @@ def tail_model(args, smcgw, synth, ev, prec, R, P, cap, lone, full):
         anc = runs.ancestors.cpu().numpy().astype(np.int64) + np.repeat(np.arange(R) * P, P)
         if it >= args.warmup and prev is not None and n == 1:
             hint = prev[anc]
+            so, oo = queue_span(nlf, striped_order(len(nlf)), slots, lone_us, full_us)
             sh, oh = queue_span(nlf, start_order(hint), slots, lone_us, full_us)
             sl, ol = queue_span(nlf, np.argsort(-nlf, kind="stable"), slots, lone_us, full_us)
             measured.append(ms)
+            model_own.append(so / 1e3)
             model_hint.append(sh / 1e3)
             model_lpt.append(sl / 1e3)
+            occ_own.append(oo)
             occ_hint.append(oh)
             occ_lpt.append(ol)
             corr.append(float(np.corrcoef(np.log1p(nlf), np.log1p(hint))[0, 1]))
         prev = nlf
     ctx.timing()
     ctx.close()
-    ratio = np.array(measured) / np.array(model_hint)
+    ratio = np.array(measured) / np.array(model_own)
     return {"slots": slots, "lone_leaf_us": round(lone_us, 3), "full_leaf_us": round(full_us, 3),
             "launches": len(measured), "measured_launch_ms": round(float(np.mean(measured)), 4),
-            "model_launch_ms": round(float(np.mean(model_hint)), 4),
+            "model_launch_ms": round(float(np.mean(model_own)), 4),
             "measured_over_model": [round(float(ratio.min()), 3), round(float(ratio.mean()), 3),
                                     round(float(ratio.max()), 3)],
-            "model_slot_occupancy": round(float(np.mean(occ_hint)), 4),
+            "model_slot_occupancy": round(float(np.mean(occ_own)), 4),
+            "model_slot_occupancy_ancestor_hint": round(float(np.mean(occ_hint)), 4),
             "model_launch_ms_longest_first": round(float(np.mean(model_lpt)), 4),
             "model_slot_occupancy_longest_first": round(float(np.mean(occ_lpt)), 4),
             "corr_log_count_ancestor_count": [round(float(np.min(corr)), 3), round(float(np.max(corr)), 3)]}

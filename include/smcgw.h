@@ -149,9 +149,7 @@ typedef struct {
     int32_t precision;              /* SMCGW_PLAIN_FP64 or SMCGW_MIXED (likelihood inside NUTS) */
     double *theta, *logl, *grad;    /* [n_runs P][D], [n_runs P], [n_runs P][D]: population, updated in place */
     int32_t *ancestors;             /* [n_runs P]: indices within each run after resampling */
-    int32_t *n_leapfrog;            /* [n_runs P]: leapfrog steps of each particle's last transition; resampled
-                                       with the particles and used as the start-order hint of the next
-                                       transition (zeros before the first iteration) */
+    int32_t *n_leapfrog;            /* [n_runs P]: leapfrog steps of each particle's last transition */
     int32_t *depth;                 /* [n_runs P] doublings of the last transition */
     uint8_t *divergent;             /* [n_runs P] */
     double *accept_stat;            /* [n_runs P] (may be NULL) */
@@ -347,11 +345,14 @@ int smcgw_local_metric(smcgw_ctx *ctx, int P, int D, const double *theta, double
  * (device) is the Cholesky factor of M^{-1}, or chol [P][D][D] one factor
  * per particle when params->chol_per_particle = 1.  max_depth_per_particle [P]
  * (device, NULL = params->max_depth) caps each tree.  work_hint [P]
- * (device, NULL = particle order) is a predicted leapfrog count per particle,
- * e.g. the n_leapfrog of its ancestor's previous transition: particles start
- * in descending order of floor(log2(hint)) so that the longest trees do not
- * start last.  It changes only the schedule; every output is the same for
- * any hint.  Per-particle diagnostics (device, each may be NULL): doublings
+ * (device) is a predicted leapfrog count per particle, for callers that know
+ * it (e.g. forced depths): particles start in descending order of
+ * floor(log2(hint)) so that the longest trees do not start last.  Without it
+ * (NULL) the particles are dealt to the GPU's XCDs in stripes of 16
+ * neighbouring indices, each XCD's slots taking their own stripes first and
+ * the others' after, so that neighbouring particles, whose inputs and
+ * outputs share cache lines, pass through one L2.  The hint changes only
+ * the schedule; every output is the same with or without it.  Per-particle diagnostics (device, each may be NULL): doublings
  * done, leapfrog steps, divergence flag, mean acceptance statistic. */
 int smcgw_nuts_step(smcgw_ctx *ctx, int P, int D, double *theta, double *logl, double *grad, const double *chol,
                     const smcgw_nuts_params *params, const int32_t *max_depth_per_particle,
@@ -412,13 +413,13 @@ int smcgw_smc_reweight_resample_async(smcgw_ctx *ctx, int P, int D, double beta_
  *      bisection of smcgw_smc_reweight_resample, the evidence increment and
  *      the running log Z accumulated in FP64 in the state, multinomial
  *      resampling with the uniforms of iteration t = state[NEXT] (key
- *      seed + r) and the gather of theta, logl, grad and n_leapfrog;
+ *      seed + r) and the gather of theta, logl and grad;
  *   2. per run: the population covariance, its shrinkage and factor;
  *   3. with chol_pp: every particle's local metric at its run's beta_t, the
  *      run's population factor standing in where it is not positive definite;
  *   4. one persistent NUTS launch over all n_runs P particles at their runs'
- *      temperatures (iteration t, key seed + r), the longest predicted trees
- *      first;
+ *      temperatures (iteration t, key seed + r), without a work hint (a
+ *      particle's tree length hardly depends on its ancestor's);
  *   5. per run: the record row t (history).
  * A run whose state says done is left untouched, so the call may be queued
  * past the end of every run; the host reads state[DONE] when it needs to

@@ -4,8 +4,7 @@
 //
 // Everything the iteration needs from one step to the next lives on the
 // device: each run's temperature, running log evidence, iteration index and
-// done flag (the run state), the start-order hint (the last transition's
-// leapfrog counts, resampled with the particles).  The host only queues the
+// done flag (the run state).  The host only queues the
 // work, so the same launch sequence serves every iteration and can be
 // captured once.
 #include <algorithm>
@@ -52,7 +51,7 @@ int reserve(smcgw_ctx* c, const smcgw_smc_iter_desc* d) {
     if (hipSetDevice(c->device) != hipSuccess) return SMCGW_ERR_HIP;
     if (!sampler_scratch(c, reweight_scratch_bytes(d->n_runs, d->P, d->D))) return SMCGW_ERR_OOM;
     if (mm_reserve(c, d->n_runs, d->P) != SMCGW_OK) return SMCGW_ERR_OOM;
-    if (nuts_reserve(c, d->n_runs * d->P, true) != SMCGW_OK) return SMCGW_ERR_OOM;
+    if (nuts_reserve(c, d->n_runs * d->P, false) != SMCGW_OK) return SMCGW_ERR_OOM;
     return SMCGW_OK;
 }
 
@@ -60,7 +59,7 @@ int queue(smcgw_ctx* c, const smcgw_smc_iter_desc* d) {
     const int R = d->n_runs, P = d->P, D = d->D, n = R * P;
     double* out = nullptr;
     int rc = queue_reweight_resample(c, R, P, D, 0.0, d->alpha, d->seed, 0, d->theta, d->logl, d->grad,
-                                     d->n_leapfrog, d->ancestors, d->state, d->history, d->history_cap, &out);
+                                     nullptr, d->ancestors, d->state, d->history, d->history_cap, &out);
     if (rc) return rc;
     rc = queue_mass_matrix_runs(c, R, P, D, d->theta, d->shrink, d->inv_mass, d->chol, d->mm_status, d->state);
     if (rc) return rc;
@@ -83,9 +82,10 @@ int queue(smcgw_ctx* c, const smcgw_smc_iter_desc* d) {
         rc = smcgw_nuts_step_sweeps(c, n, D, d->theta, d->logl, d->grad, d->chol_pp ? d->chol_pp : d->chol, &prm,
                                     nullptr, d->depth, d->n_leapfrog, d->divergent, d->accept_stat, 8, nullptr);
     } else {
-        // the leapfrog counts gathered with the particles are the start-order hint, then the new counts
+        // no start-order hint: a particle's leapfrog count hardly depends on its ancestor's, so the launch
+        // deals the particles to the XCDs in stripes of neighbours instead
         rc = smcgw_nuts_step(c, n, D, d->theta, d->logl, d->grad, d->chol_pp ? d->chol_pp : d->chol, &prm,
-                             nullptr, d->n_leapfrog, d->precision, d->depth, d->n_leapfrog, d->divergent,
+                             nullptr, nullptr, d->precision, d->depth, d->n_leapfrog, d->divergent,
                              d->accept_stat);
     }
     if (rc) return rc;

@@ -745,6 +745,21 @@ __device__ __noinline__ void derive_metric(NutsShared& S, int D, int tid) {
     }
 }
 
+// Particle queues of a launch without a work hint.  The particles are dealt
+// in stripes of STRIPE neighbouring indices, stripe g to queue g mod N_QUEUES,
+// one queue per XCD: a slot takes the next particle of its own XCD's queue
+// and, once that is drained, of the others in turn.  Neighbouring particles,
+// whose inputs and outputs share cache lines, then pass through one XCD's L2
+// instead of leaving partly written lines in several.  A queue is drained for
+// good once a fetch runs past P (its particle indices only grow), so every
+// slot leaves after at most N_QUEUES empty fetches.
+constexpr int N_QUEUES = 8;
+constexpr int STRIPE = 16;
+
+__device__ __forceinline__ int striped_particle(int queue, int k) {
+    return ((k / STRIPE) * N_QUEUES + queue) * STRIPE + k % STRIPE;
+}
+
 template <int NDET, int PREC, int TK, int WAVES>
 __global__ __launch_bounds__(WAVES * 64, (WAVES == 1 ? 2 : NUTS_WAVES_PER_SIMD)) void nuts_kernel(NutsArgs a, PriorDesc pri, ParamMap pm,
                                                                              TargetDesc tgt) {
@@ -783,10 +798,29 @@ __global__ __launch_bounds__(WAVES * 64, (WAVES == 1 ? 2 : NUTS_WAVES_PER_SIMD))
 
     int ev_cached = -1;    // event whose descriptor S.ev holds
     int run_cached = -1;   // run whose factor S.L holds (per-run factors)
+    // this slot's XCD (hardware register XCC_ID) and the queues it has seen drained
+    const int home = (int)(__builtin_amdgcn_s_getreg((31 << 11) | 20) & (N_QUEUES - 1));
+    unsigned drained = 0;
     for (;;) {
         if (tid == 0) {
-            const int q = __hip_atomic_fetch_add(a.queue, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            S.p = (q < a.P && a.order) ? a.order[q] : q;
+            if (a.order) {
+                const int q = __hip_atomic_fetch_add(a.queue, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                S.p = q < a.P ? a.order[q] : a.P;
+            } else {
+                int next = a.P;
+                for (int t = 0; t < N_QUEUES; ++t) {
+                    const int x = (home + t) & (N_QUEUES - 1);
+                    if (drained & (1u << x)) continue;
+                    const int k = __hip_atomic_fetch_add(a.queue + x, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const int cand = striped_particle(x, k);
+                    if (cand < a.P) {
+                        next = cand;
+                        break;
+                    }
+                    drained |= 1u << x;
+                }
+                S.p = next;
+            }
         }
         __syncthreads();
         const int p = __builtin_amdgcn_readfirstlane(S.p);
@@ -947,7 +981,9 @@ __global__ __launch_bounds__(ORDER_THREADS) void order_kernel(const int32_t* __r
     }
 }
 
-__global__ void zero_int_kernel(int* q) { *q = 0; }
+__global__ void zero_queues_kernel(int* q) {
+    if (threadIdx.x < N_QUEUES) q[threadIdx.x] = 0;
+}
 
 // ------------------------------------------------------------------ lockstep sweeps
 // The plain comparison form of the transition: the same tree, random streams
@@ -1131,7 +1167,7 @@ int launch_persistent(smcgw_ctx* c, K kernel, int block, const NutsArgs& a, cons
         it = c->resident.emplace((const void*)kernel, dev_cus * per_cu).first;
     }
     const int grid = std::max(1, std::min(a.P, it->second));
-    hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, c->stream, a.queue);
+    hipLaunchKernelGGL(zero_queues_kernel, dim3(1), dim3(N_QUEUES), 0, c->stream, a.queue);
     {
         TimedLaunch tl(c, SMCGW_KERNEL_NUTS);
         hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), 0, c->stream, a, pri, pm, t);

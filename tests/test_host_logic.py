@@ -41,6 +41,11 @@ def test_bench_queue_model_and_start_order():
     # particles without leaves take no slot time
     assert bench.queue_span([0, 2, 0], [0, 1, 2], 1, 1.0, 1.0)[0] == pytest.approx(2.0)
     assert bench.start_order([0, 5, 100, 5, 1]).tolist() == [2, 1, 3, 4, 0]
+    # without a hint: stripes of 16 neighbours dealt to 8 queues, the queues taken side by side
+    order = bench.striped_order(300)
+    assert sorted(order.tolist()) == list(range(300))
+    assert order[:3].tolist() == [0, 16, 32] and order[8:10].tolist() == [1, 17]
+    assert order[127] == 127 and order[128] == 128 and order[256:259].tolist() == [256, 272, 288]
 
 
 def test_bench_iteration_table_and_traffic_gate(tmp_path, monkeypatch):
