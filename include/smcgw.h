@@ -285,8 +285,8 @@ int smcgw_target_loglike_grad(smcgw_ctx *ctx, int P, const double *theta, double
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the batched
  * likelihood and gradient of smcgw_loglike_grad, same arguments and results,
- * with its per-particle scratch (1 KiB per particle of coefficient and moment
- * blocks) in a fixed device array of SMCGW_NOALLOC_MAX_P particles (16 MiB)
+ * with its per-particle scratch (the 832 B coefficient block of each
+ * particle) in a fixed device array of SMCGW_NOALLOC_MAX_P particles (13 MiB)
  * that each GPU holds from the first context on it until the process ends.
  * It calls no allocation, creates no event and does not synchronise.
  * SMCGW_ERR_SHAPE for P > SMCGW_NOALLOC_MAX_P.  Every call on one GPU shares
@@ -518,7 +518,9 @@ int smcgw_autotune_nuts(smcgw_ctx *ctx, int P, int D, const double *theta, const
  * stream around every launch of the kernel classes whose bit is set in
  * class_mask (bit c = class c; 0 turns timing off).
  * smcgw_timing_read synchronises, returns the summed duration [ms] and the
- * launch count of one class since the last read, and resets that class. */
+ * launch count of one class since the last read, and resets that class.
+ * The batched likelihood's epilogue runs inside its bin-loop kernel (class
+ * BINS); class FINISH is kept for compatibility and records no launch. */
 enum { SMCGW_KERNEL_BINS = 0, SMCGW_KERNEL_PREP = 1, SMCGW_KERNEL_FINISH = 2, SMCGW_KERNEL_NUTS = 3,
        SMCGW_KERNEL_SMC = 4, SMCGW_KERNEL_METRIC = 5, SMCGW_KERNEL_CLASSES = 6 };
 int smcgw_timing_enable(smcgw_ctx *ctx, int class_mask);

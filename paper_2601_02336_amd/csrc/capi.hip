@@ -55,12 +55,9 @@ int ctx_reserve(smcgw_ctx* c, int P) {
     if (P <= c->cap) return SMCGW_OK;
     const int cap = std::max(P, std::max(2 * c->cap, 256));
     (void)hipFree(c->d_cb);
-    (void)hipFree(c->d_mom);
     c->d_cb = nullptr;
-    c->d_mom = nullptr;
     c->cap = 0;
     if (hipMalloc(&c->d_cb, (size_t)cap * CB_SIZE * sizeof(double)) != hipSuccess) return SMCGW_ERR_OOM;
-    if (hipMalloc(&c->d_mom, (size_t)cap * MOM_SIZE * sizeof(double)) != hipSuccess) return SMCGW_ERR_OOM;
     c->cap = cap;
     return SMCGW_OK;
 }
@@ -78,14 +75,8 @@ int ctx_loglike(smcgw_ctx* c, int P, const int32_t* ev_of_p, const double* theta
     }
     {
         TimedLaunch t(c, SMCGW_KERNEL_BINS);
-        if (launch_bins(c->d_events, (int)c->events.size(), ev_of_p, P, c->n_det, precision, c->d_cb, c->d_mom,
-                        c->stream) != hipSuccess)
-            return SMCGW_ERR_HIP;
-    }
-    {
-        TimedLaunch t(c, SMCGW_KERNEL_FINISH);
-        if (launch_finish(c->d_events, (int)c->events.size(), ev_of_p, c->pmap, P, c->d_cb, c->d_mom, logl, grad,
-                          c->stream) != hipSuccess)
+        if (launch_bins(c->d_events, (int)c->events.size(), ev_of_p, c->pmap, P, c->n_det, precision, c->d_cb, logl,
+                        grad, c->stream) != hipSuccess)
             return SMCGW_ERR_HIP;
     }
     return SMCGW_OK;
@@ -128,7 +119,6 @@ extern "C" int smcgw_destroy(smcgw_ctx* c) {
     (void)hipFree(c->d_events);
     (void)hipFree(c->d_small);
     (void)hipFree(c->d_cb);
-    (void)hipFree(c->d_mom);
     (void)hipFree(c->d_tan);
     c->sweep_free();
     c->sampler_free();

@@ -210,10 +210,9 @@ hipError_t launch_build_tables(const double* d_data, const double* d_psd, int n_
                                double* wa2, double* sums, hipStream_t s);
 hipError_t launch_prep(const DevEvent* d_events, int n_events, const int32_t* ev_of_p, const ParamMap& pm, int P,
                        const double* theta, double* cb, hipStream_t s);
-hipError_t launch_bins(const DevEvent* d_events, int n_events, const int32_t* ev_of_p, int P, int n_det, int precision,
-                       const double* cb, double* mom, hipStream_t s);
-hipError_t launch_finish(const DevEvent* d_events, int n_events, const int32_t* ev_of_p, const ParamMap& pm, int P,
-                         const double* cb, const double* mom, double* logl, double* grad, hipStream_t s);
+// The bin loop and the epilogue of every particle: logl [P] and grad [P][pm.dim] (grad may be NULL).
+hipError_t launch_bins(const DevEvent* d_events, int n_events, const int32_t* ev_of_p, const ParamMap& pm, int P,
+                       int n_det, int precision, const double* cb, double* logl, double* grad, hipStream_t s);
 hipError_t launch_waveform(const DevEvent* d_events, int event_id, const double* cb, double* h_reim, int n_bins,
                            int n_det, hipStream_t s);
 int noalloc_init(int device);   // the fixed scratch of smcgw_loglike_grad_noalloc on this device

@@ -33,7 +33,6 @@ struct smcgw_ctx {
     smcgw::ParamMap pmap;
     // likelihood scratch, sized for `cap` particles
     double* d_cb = nullptr;
-    double* d_mom = nullptr;
     int cap = 0;
     double* d_tan = nullptr;               // tangent moment blocks of the plain form, [tan_cap][12]
     int tan_cap = 0;

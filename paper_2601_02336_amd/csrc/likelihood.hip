@@ -13,11 +13,12 @@
 // prologue's Jacobians.
 //
 // Kernels:
-//   prep   (one lane per particle): coefficient block, FP64.
-//   bins   (one wavefront per particle): lanes stride the frequency bins, the
-//          shared per-bin tables are read coalesced and each lane keeps its own
-//          partial sums; a wavefront shuffle tree reduces them in FP64.
-//   finish (one lane per particle): logL and the gradient, FP64.
+//   prep (eight lanes per particle): coefficient block, FP64 dual numbers with
+//        one tangent per lane.
+//   bins (one wavefront per particle): lanes stride the frequency bins, the
+//        shared per-bin tables are read coalesced and each lane keeps its own
+//        partial sums; a wavefront shuffle tree reduces them in FP64 into LDS,
+//        and lane 0 forms logL and the gradient from them (FP64).
 #include "binloop.h"
 #include "coeffs.h"
 #include "common.h"
@@ -27,56 +28,95 @@ namespace smcgw {
 
 constexpr int BINS_WAVES = 4;   // wavefronts (particles) per workgroup
 
+// Eight lanes per particle, as the persistent NUTS kernel splits a leaf's
+// prologue: lanes 0-3 carry one intrinsic tangent each (Mc, q, chi1, chi2)
+// while lanes 4-7 take the sines and cosines of the four extrinsic angles;
+// then lane 4k + d (k = 0, 1) builds detector d with its ra (k = 0) or dec
+// (k = 1) tangent, and lane 0 the amplitude.  One particle's chain is a
+// quarter of the one-lane prologue's.
+constexpr int PREP_LANES = 8;
+constexpr int PREP_PER_BLOCK = 256 / PREP_LANES;
+static_assert(2 * MAXDET == PREP_LANES && ANG_COUNT == PREP_LANES - 4, "prologue lane split");
+
 __global__ __launch_bounds__(256) void prep_kernel(const DevEvent* __restrict__ evs, int n_events,
                                                    const int32_t* __restrict__ ev_of_p, ParamMap pm, int P,
                                                    const double* __restrict__ theta, double* __restrict__ cb) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= P) return;
+    __shared__ double ang_sh[PREP_PER_BLOCK][ANG_COUNT][2];
+    const int g = threadIdx.x / PREP_LANES, j = threadIdx.x % PREP_LANES;
+    const int p = blockIdx.x * PREP_PER_BLOCK + g;
+    const bool live = p < P;
     double th[NPAR];
-    expand_params(pm, theta + (size_t)p * pm.dim, th);
-    const DevEvent& ev = evs[event_index(ev_of_p, p, n_events)];
-    double* c = cb + (size_t)p * CB_SIZE;
-    prep_intrinsic(ev, th, c);
-    prep_extrinsic(ev, th, c);
+    const DevEvent& ev = evs[event_index(ev_of_p, live ? p : 0, n_events)];
+    double* c = cb + (size_t)(live ? p : 0) * CB_SIZE;
+    if (live) {
+        expand_params(pm, theta + (size_t)p * pm.dim, th);
+        if (j < 4) {
+            prep_intrinsic_n<1>(ev, th, c, j, j == 0);
+        } else {
+            double sn, cs;
+            sincos(extrinsic_angle(ev, th, j - 4), &sn, &cs);
+            ang_sh[g][j - 4][0] = sn;
+            ang_sh[g][j - 4][1] = cs;
+        }
+    }
+    __syncthreads();
+    if (live) {
+        ExtAngles ang;
+#pragma unroll
+        for (int k = 0; k < ANG_COUNT; ++k) { ang.sc[k][0] = ang_sh[g][k][0]; ang.sc[k][1] = ang_sh[g][k][1]; }
+        const int k = j / MAXDET, d = j % MAXDET;
+        prep_extrinsic_det_n<1>(ev, th, ang, c, d, k, k == 0);
+        if (j == 0) prep_extrinsic_common(ev, th, c);
+    }
 }
 
-// One wavefront per particle over all bins of its event.
+// One wavefront per particle over all bins of its event, then the epilogue:
+// the wavefront's coefficient block and moments sit in LDS and lane 0 forms
+// logL and the gradient over the sampled coordinates.
+template <int NDET, int PREC>
+__device__ __forceinline__ void bins_and_finish(const DevEvent* __restrict__ evs, int n_events,
+                                                const int32_t* __restrict__ ev_of_p, const ParamMap& pm, int P,
+                                                const double* __restrict__ cb, double* __restrict__ logl,
+                                                double* __restrict__ grad) {
+    __shared__ double cb_sh[BINS_WAVES][CB_SIZE];
+    __shared__ double mom_sh[BINS_WAVES][MOM_SIZE];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int p = blockIdx.x * BINS_WAVES + wave;
+    if (p >= P) return;   // the whole wavefront: there is no workgroup barrier below
+    const int e = __builtin_amdgcn_readfirstlane(event_index(ev_of_p, p, n_events));
+    for (int i = lane; i < CB_SIZE; i += 64) cb_sh[wave][i] = cb[(size_t)p * CB_SIZE + i];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const BinCoef k = load_coef(cb_sh[wave]);
+    if (PREC == SMCGW_MIXED)
+        bins_mixed_wave<NDET>(evs + e, k, 0, 1, mom_sh[wave]);
+    else
+        bins_fp64_wave<NDET>(evs + e, k, 0, 1, mom_sh[wave]);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (lane == 0) {
+        double g[NPAR];
+        logl[p] = finish_particle(evs[e], cb_sh[wave], mom_sh[wave], g);
+        if (grad)
+            for (int q = 0; q < pm.dim; ++q) grad[(size_t)p * pm.dim + q] = g[pm.idx[q]];
+    }
+}
+
 template <int NDET>
 __global__ __launch_bounds__(256) void bins_mixed_kernel(const DevEvent* __restrict__ evs, int n_events,
-                                                         const int32_t* __restrict__ ev_of_p, int P,
-                                                         const double* __restrict__ cb, double* __restrict__ mom) {
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int p = blockIdx.x * BINS_WAVES + wave;
-    if (p >= P) return;
-    const int e = __builtin_amdgcn_readfirstlane(event_index(ev_of_p, p, n_events));
-    const BinCoef k = load_coef(cb + (size_t)p * CB_SIZE);
-    bins_mixed_wave<NDET>(evs + e, k, 0, 1, mom + (size_t)p * MOM_SIZE);
+                                                         const int32_t* __restrict__ ev_of_p, ParamMap pm, int P,
+                                                         const double* __restrict__ cb, double* __restrict__ logl,
+                                                         double* __restrict__ grad) {
+    bins_and_finish<NDET, SMCGW_MIXED>(evs, n_events, ev_of_p, pm, P, cb, logl, grad);
 }
 
 template <int NDET>
 __global__ __launch_bounds__(256) void bins_fp64_kernel(const DevEvent* __restrict__ evs, int n_events,
-                                                        const int32_t* __restrict__ ev_of_p, int P,
-                                                        const double* __restrict__ cb, double* __restrict__ mom) {
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int p = blockIdx.x * BINS_WAVES + wave;
-    if (p >= P) return;
-    const int e = __builtin_amdgcn_readfirstlane(event_index(ev_of_p, p, n_events));
-    const BinCoef k = load_coef(cb + (size_t)p * CB_SIZE);
-    bins_fp64_wave<NDET>(evs + e, k, 0, 1, mom + (size_t)p * MOM_SIZE);
-}
-
-__global__ __launch_bounds__(256) void finish_kernel(const DevEvent* __restrict__ evs, int n_events,
-                                                     const int32_t* __restrict__ ev_of_p, ParamMap pm, int P, const double* __restrict__ cb,
-                                                     const double* __restrict__ mom, double* __restrict__ logl,
-                                                     double* __restrict__ grad) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= P) return;
-    const DevEvent& ev = evs[event_index(ev_of_p, p, n_events)];
-    double g[NPAR];
-    const double ll = finish_particle(ev, cb + (size_t)p * CB_SIZE, mom + (size_t)p * MOM_SIZE, g);
-    logl[p] = ll;
-    if (grad)
-        for (int k = 0; k < pm.dim; ++k) grad[(size_t)p * pm.dim + k] = g[pm.idx[k]];
+                                                        const int32_t* __restrict__ ev_of_p, ParamMap pm, int P,
+                                                        const double* __restrict__ cb, double* __restrict__ logl,
+                                                        double* __restrict__ grad) {
+    bins_and_finish<NDET, SMCGW_PLAIN_FP64>(evs, n_events, ev_of_p, pm, P, cb, logl, grad);
 }
 
 // Projected strain of one parameter point (FP64), h_reim [n_det][N][2].
@@ -104,13 +144,13 @@ __global__ __launch_bounds__(256) void waveform_kernel(const DevEvent* __restric
 }
 
 // ------------------------------------------------------------- fixed scratch
-// Coefficient and moment blocks of smcgw_loglike_grad_noalloc, for at most
-// SMCGW_NOALLOC_MAX_P particles (16 MiB).  Every GPU the library runs on
+// Coefficient blocks of smcgw_loglike_grad_noalloc, for at most
+// SMCGW_NOALLOC_MAX_P particles (13 MiB).  Every GPU the library runs on
 // holds its own copy until the process ends.  Host code must not pass the
 // array's name to a kernel (it is a host-side stand-in there): the device
 // address of each GPU's copy is looked up once per device at context set-up
 // and kept in noalloc_base.
-static __device__ __align__(256) double scratch[(size_t)SMCGW_NOALLOC_MAX_P * (CB_SIZE + MOM_SIZE)];
+static __device__ __align__(256) double scratch[(size_t)SMCGW_NOALLOC_MAX_P * CB_SIZE];
 
 constexpr int NOALLOC_DEVICES = 64;
 static double* noalloc_base[NOALLOC_DEVICES] = {};
@@ -129,41 +169,32 @@ int noalloc_init(int device) {
 hipError_t launch_prep(const DevEvent* d_events, int n_events, const int32_t* ev_of_p, const ParamMap& pm, int P,
                        const double* theta, double* cb, hipStream_t s) {
     if (P <= 0) return hipSuccess;
-    hipLaunchKernelGGL(prep_kernel, dim3((P + 255) / 256), dim3(256), 0, s, d_events, n_events, ev_of_p, pm, P, theta,
-                       cb);
+    hipLaunchKernelGGL(prep_kernel, dim3((P + PREP_PER_BLOCK - 1) / PREP_PER_BLOCK), dim3(256), 0, s, d_events,
+                       n_events, ev_of_p, pm, P, theta, cb);
     return hipGetLastError();
 }
 
-hipError_t launch_bins(const DevEvent* d_events, int n_events, const int32_t* ev_of_p, int P, int n_det, int precision,
-                       const double* cb, double* mom, hipStream_t s) {
-    if (P <= 0) return hipSuccess;
+template <int NDET>
+hipError_t launch_bins_ndet(const DevEvent* d_events, int n_events, const int32_t* ev_of_p, const ParamMap& pm,
+                            int P, int precision, const double* cb, double* logl, double* grad, hipStream_t s) {
     const dim3 grid((P + BINS_WAVES - 1) / BINS_WAVES), block(64 * BINS_WAVES);
-    if (precision == SMCGW_MIXED) {
-        switch (n_det) {
-        case 1: hipLaunchKernelGGL(bins_mixed_kernel<1>, grid, block, 0, s, d_events, n_events, ev_of_p, P, cb, mom); break;
-        case 2: hipLaunchKernelGGL(bins_mixed_kernel<2>, grid, block, 0, s, d_events, n_events, ev_of_p, P, cb, mom); break;
-        case 3: hipLaunchKernelGGL(bins_mixed_kernel<3>, grid, block, 0, s, d_events, n_events, ev_of_p, P, cb, mom); break;
-        case 4: hipLaunchKernelGGL(bins_mixed_kernel<4>, grid, block, 0, s, d_events, n_events, ev_of_p, P, cb, mom); break;
-        default: return hipErrorInvalidValue;
-        }
-    } else {
-        switch (n_det) {
-        case 1: hipLaunchKernelGGL(bins_fp64_kernel<1>, grid, block, 0, s, d_events, n_events, ev_of_p, P, cb, mom); break;
-        case 2: hipLaunchKernelGGL(bins_fp64_kernel<2>, grid, block, 0, s, d_events, n_events, ev_of_p, P, cb, mom); break;
-        case 3: hipLaunchKernelGGL(bins_fp64_kernel<3>, grid, block, 0, s, d_events, n_events, ev_of_p, P, cb, mom); break;
-        case 4: hipLaunchKernelGGL(bins_fp64_kernel<4>, grid, block, 0, s, d_events, n_events, ev_of_p, P, cb, mom); break;
-        default: return hipErrorInvalidValue;
-        }
-    }
+    if (precision == SMCGW_MIXED)
+        hipLaunchKernelGGL(bins_mixed_kernel<NDET>, grid, block, 0, s, d_events, n_events, ev_of_p, pm, P, cb, logl, grad);
+    else
+        hipLaunchKernelGGL(bins_fp64_kernel<NDET>, grid, block, 0, s, d_events, n_events, ev_of_p, pm, P, cb, logl, grad);
     return hipGetLastError();
 }
 
-hipError_t launch_finish(const DevEvent* d_events, int n_events, const int32_t* ev_of_p, const ParamMap& pm, int P,
-                         const double* cb, const double* mom, double* logl, double* grad, hipStream_t s) {
+hipError_t launch_bins(const DevEvent* d_events, int n_events, const int32_t* ev_of_p, const ParamMap& pm, int P,
+                       int n_det, int precision, const double* cb, double* logl, double* grad, hipStream_t s) {
     if (P <= 0) return hipSuccess;
-    hipLaunchKernelGGL(finish_kernel, dim3((P + 255) / 256), dim3(256), 0, s, d_events, n_events, ev_of_p, pm, P, cb,
-                       mom, logl, grad);
-    return hipGetLastError();
+    switch (n_det) {
+    case 1: return launch_bins_ndet<1>(d_events, n_events, ev_of_p, pm, P, precision, cb, logl, grad, s);
+    case 2: return launch_bins_ndet<2>(d_events, n_events, ev_of_p, pm, P, precision, cb, logl, grad, s);
+    case 3: return launch_bins_ndet<3>(d_events, n_events, ev_of_p, pm, P, precision, cb, logl, grad, s);
+    case 4: return launch_bins_ndet<4>(d_events, n_events, ev_of_p, pm, P, precision, cb, logl, grad, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_waveform(const DevEvent* d_events, int event_id, const double* cb, double* h_reim, int n_bins,
@@ -177,8 +208,9 @@ hipError_t launch_waveform(const DevEvent* d_events, int event_id, const double*
 
 using namespace smcgw;
 
-// The batched likelihood of smcgw_loglike_grad with its per-particle blocks in
-// the fixed scratch array: no allocation, no event, no host synchronisation.
+// The batched likelihood of smcgw_loglike_grad with its per-particle coefficient
+// blocks in the fixed scratch array: no allocation, no event, no host
+// synchronisation.
 extern "C" int smcgw_loglike_grad_noalloc(smcgw_ctx* c, int P, const int32_t* event_of_particle, const double* theta,
                                           double* logl, double* grad, int precision) {
     if (!c || P < 0 || (P > 0 && (!theta || !logl))) return SMCGW_ERR_INVALID;
@@ -189,11 +221,10 @@ extern "C" int smcgw_loglike_grad_noalloc(smcgw_ctx* c, int P, const int32_t* ev
     if (c->device < 0 || c->device >= NOALLOC_DEVICES || !noalloc_base[c->device]) return SMCGW_ERR_NOT_INIT;
     if (hipSetDevice(c->device) != hipSuccess) return SMCGW_ERR_HIP;
     double* cb = noalloc_base[c->device];
-    double* mom = cb + (size_t)SMCGW_NOALLOC_MAX_P * CB_SIZE;
     const int ne = (int)c->events.size();
     if (launch_prep(c->d_events, ne, event_of_particle, c->pmap, P, theta, cb, c->stream) != hipSuccess ||
-        launch_bins(c->d_events, ne, event_of_particle, P, c->n_det, precision, cb, mom, c->stream) != hipSuccess ||
-        launch_finish(c->d_events, ne, event_of_particle, c->pmap, P, cb, mom, logl, grad, c->stream) != hipSuccess)
+        launch_bins(c->d_events, ne, event_of_particle, c->pmap, P, c->n_det, precision, cb, logl, grad,
+                    c->stream) != hipSuccess)
         return SMCGW_ERR_HIP;
     return SMCGW_OK;
 }
