@@ -583,7 +583,7 @@ def loglike_mode(args, smcgw, synth, ev, prec, extra):
     for _ in range(args.warmup):
         ctx.loglike_grad(x, logl, grad, precision=prec)
     torch.cuda.synchronize()
-    # the rate: calls queued back to back, in groups of `steps`, for at least a second
+    # the rate: calls queued back to back, in groups of `steps`, for at least --min-seconds
     n_calls, t0 = 0, time.perf_counter()
     while True:
         for _ in range(args.steps):
@@ -591,7 +591,7 @@ def loglike_mode(args, smcgw, synth, ev, prec, extra):
         n_calls += args.steps
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        if dt >= 1.0:
+        if dt >= args.min_seconds:
             break
     # the bin kernel's own duration: `steps` more calls with HIP events around its launches
     ctx.timing_read(smcgw.KERNEL_BINS)
@@ -705,6 +705,8 @@ def main():
     ap.add_argument("--max-depth", type=int, default=HEADLINE["max_depth"])
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--waves", type=int, choices=[0, 2, 4, 6, 8], default=0, help="wavefronts per NUTS slot")
+    ap.add_argument("--min-seconds", type=float, default=1.0,
+                    help="loglike mode: time the rate over at least this long (0: exactly --steps calls)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the side measurements")
     ap.add_argument("--copy-probe", action="store_true",
