@@ -153,12 +153,15 @@ def cpu_baseline(ev, synth, x_all, budget_s=12.0, single_budget_s=3.0):
 
 # ------------------------------------------------------------------ the SMC hot path
 def make_runs(smcgw, synth, ev, n_runs, P, precision, metric, step, alpha, max_depth, seed, cap, nuts_form=0,
-              draw_seed=7):
-    """A context on the event and n_runs independent runs of P prior draws (run r: draws of seed draw_seed + r,
-    Philox key seed + r)."""
+              draw_seed=7, rb_eps=None):
+    """A context on the event (folded onto relative-binning edges at rb_eps around the injection when given)
+    and n_runs independent runs of P prior draws (run r: draws of seed draw_seed + r, Philox key seed + r)."""
     import torch
     ctx = smcgw.Context(0)
-    ctx.add_event(ev)
+    if rb_eps is None:
+        ctx.add_event(ev)
+    else:
+        ctx.add_event_rb(ev, ev.theta_inj, rb_eps)
     bounds = synth.gw_prior_for(ev)
     ctx.set_prior(bounds)
     ctx.set_target(synth.TARGET_GW, 11)
@@ -203,6 +206,76 @@ def time_iterations(smcgw, ctx, runs, n_warm, n_steps, kernel_events, graph=Fals
         g.close()
     h = runs.history()[:, n_warm:n_warm + n_steps]
     return dt, int(h[..., smcgw.H_LEAPFROG].sum()), k_ms, k_n, m_ms, m_n, h
+
+
+def make_stream_runs(smcgw, synth, ev, R, P, precision, metric, step, alpha, max_depth, seed, cap, waves,
+                     rb_eps=None):
+    """The R runs of one make_runs call (run r: draws of seed 7 + r, Philox key seed + r), each as a context of
+    its own with a HIP stream of its own, so that one run's iterations never wait for another's."""
+    import torch
+    lanes = []
+    for r in range(R):
+        ctx, runs, x = make_runs(smcgw, synth, ev, 1, P, precision, metric, step, alpha, max_depth, seed + r, cap,
+                                 draw_seed=7 + r, rb_eps=rb_eps)
+        ctx.set_option(smcgw.OPT_NUTS_WAVES, waves)
+        lanes.append((ctx, runs, x, torch.cuda.Stream()))
+    cur = torch.cuda.current_stream()
+    for lane in lanes:
+        lane[3].wait_stream(cur)   # the runs' set-up was queued on the current stream
+    return lanes
+
+
+def union_ms(start, end):
+    """Length of the union of the intervals [start_k, end_k]."""
+    total, lo, hi = 0.0, None, None
+    for s, e in sorted(zip(start, end)):
+        if hi is None or s > hi:
+            total += 0.0 if hi is None else hi - lo
+            lo, hi = s, e
+        else:
+            hi = max(hi, e)
+    return total + (0.0 if hi is None else hi - lo)
+
+
+def time_iterations_streams(smcgw, lanes, n_warm, n_steps):
+    """time_iterations for runs on streams of their own: every stream gets its iterations queued round-robin
+    (the host never waits), the NUTS launches are timed with HIP events against one shared reference event.
+    Returns wall seconds, the timed leapfrog evaluations, the NUTS launches' summed ms, count and busy ms (the
+    union of their intervals, during which at least one launch runs), the local-metric kernel's summed ms and
+    count, and the records [runs][n_steps][row]."""
+    import torch
+
+    def one():
+        for ctx, runs, _, s in lanes:
+            with torch.cuda.stream(s):
+                runs.step()
+
+    for _ in range(n_warm):
+        one()
+    torch.cuda.synchronize()
+    for ctx, *_ in lanes:
+        ctx.timing_read(smcgw.KERNEL_NUTS)
+        ctx.timing_read(smcgw.KERNEL_METRIC)
+        ctx.timing(smcgw.KERNEL_NUTS, smcgw.KERNEL_METRIC)
+    ref = torch.cuda.Event(enable_timing=True)
+    ref.record()
+    ref.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(n_steps):
+        one()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    starts, ends, m_ms, m_n = [], [], 0.0, 0
+    for ctx, *_ in lanes:
+        ctx.timing()
+        s_, e_ = ctx.timing_intervals(smcgw.KERNEL_NUTS, ref)
+        starts.extend(s_)
+        ends.extend(e_)
+        a, b = ctx.timing_read(smcgw.KERNEL_METRIC)
+        m_ms, m_n = m_ms + a, m_n + b
+    h = np.concatenate([runs.history()[:, n_warm:n_warm + n_steps] for _, runs, _, _ in lanes], axis=0)
+    k_ms = float(np.sum(np.asarray(ends) - np.asarray(starts)))
+    return (dt, int(h[..., smcgw.H_LEAPFROG].sum()), k_ms, len(starts), union_ms(starts, ends), m_ms, m_n, h)
 
 
 def iteration_table(smcgw, h, P):
@@ -254,49 +327,77 @@ def smc_mode(args, smcgw, synth, ev, prec, extra):
     import torch
     R, P = args.runs, args.particles or HEADLINE["particles"]
     cap = args.warmup + args.steps + 8
-    ctx, runs, x_np = make_runs(smcgw, synth, ev, R, P, prec, args.metric, args.step, args.alpha, args.max_depth,
-                                args.seed, cap)
-    ctx.set_option(smcgw.OPT_NUTS_WAVES, args.waves)
-    dt, evals, k_ms, k_n, m_ms, m_n, h = time_iterations(smcgw, ctx, runs, args.warmup, args.steps, True)
-    ctx.close()
+    ops = OPS_PER_PARTICLE_BIN[args.precision]
+    if args.layout == "streams":
+        lanes = make_stream_runs(smcgw, synth, ev, R, P, prec, args.metric, args.step, args.alpha, args.max_depth,
+                                 args.seed, cap, args.waves)
+        x_np = np.concatenate([lane[2] for lane in lanes])
+        dt, evals, k_ms, k_n, busy_ms, m_ms, m_n, h = time_iterations_streams(smcgw, lanes, args.warmup, args.steps)
+        for lane in lanes:
+            lane[0].close()
+    else:
+        ctx, runs, x_np = make_runs(smcgw, synth, ev, R, P, prec, args.metric, args.step, args.alpha,
+                                    args.max_depth, args.seed, cap)
+        ctx.set_option(smcgw.OPT_NUTS_WAVES, args.waves)
+        dt, evals, k_ms, k_n, m_ms, m_n, h = time_iterations(smcgw, ctx, runs, args.warmup, args.steps, True)
+        ctx.close()
+        busy_ms = k_ms
     table = iteration_table(smcgw, h, P)
     value = evals / dt
-    ops = OPS_PER_PARTICLE_BIN[args.precision]
-    # one NUTS launch per step carries every run's transitions: the kernel's own rate is the work of the timed
-    # launches over their summed durations (the mean launch duration times the launch count)
-    achieved = ops * ev.n * evals / (k_ms / 1e3) / 1e12
+    # the kernel's own rate: the algorithmic work of the timed launches over the time in which at least one of
+    # them runs (one stream: their summed durations; several: the union of their intervals, since launches on
+    # different streams overlap).  kernel_ms is the mean duration of one launch, as a kernel trace reports it.
+    achieved = ops * ev.n * evals / (busy_ms / 1e3) / 1e12
     kname = f"nuts_kernel<3,{'MIXED' if prec == smcgw.MIXED else 'PLAIN_FP64'},GW,{args.waves or 4}>"
     traffic = measured_traffic(kname, " ".join(sys.argv[1:]))
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TLANEOPS, 3),
                 "unit": "Tlane-op/s", "frac": round(achieved / VALU_PEAK_TLANEOPS, 4),
                 "traffic": traffic["bytes_per_launch"] if traffic else None, "traffic_per": "launch",
                 "kernel": kname, "kernel_ms": round(k_ms / max(k_n, 1), 4), "launches": k_n,
+                "busy_ms": round(busy_ms, 3), "streams": R if args.layout == "streams" else 1,
                 "ops_per_particle_bin": ops, "evals_in_kernel": evals,
                 "algorithmic_lane_ops_per_launch": round(ops * ev.n * evals / max(k_n, 1))}
     if traffic:
         roofline["traffic_detail"] = traffic
-    log(f"smc {args.precision}: {evals} evals in {dt:.3f} s -> {value:.4g} evals/s; nuts kernel "
-        f"{k_ms / max(k_n, 1):.3f} ms x {k_n} (frac {achieved / VALU_PEAK_TLANEOPS:.3f}); local metric "
-        f"{m_ms / max(m_n, 1):.3f} ms x {m_n}; max divergent {max(r['divergent_frac'] for r in table)}")
+    log(f"smc {args.precision} ({args.layout}): {evals} evals in {dt:.3f} s -> {value:.4g} evals/s; nuts kernel "
+        f"{k_ms / max(k_n, 1):.3f} ms x {k_n}, busy {busy_ms:.1f} ms (frac {achieved / VALU_PEAK_TLANEOPS:.3f}); "
+        f"local metric {m_ms / max(m_n, 1):.3f} ms x {m_n}; max divergent {max(r['divergent_frac'] for r in table)}")
     extra["iterations"] = table
     extra["max_divergent_frac"] = max(r["divergent_frac"] for r in table)
     extra["local_metric_kernel_ms"] = round(m_ms / max(m_n, 1), 4)
-    extra["nuts_kernel_share_of_step"] = round(k_ms / (1e3 * dt), 4)
+    extra["nuts_busy_share_of_wall"] = round(busy_ms / (1e3 * dt), 4)
+    if args.layout == "streams":
+        queued = (f"each run a context of its own on a HIP stream of its own, one iteration call per run and "
+                  f"step, queued round-robin with no host waits, so one run's next iteration can start while "
+                  f"another's NUTS launch is still in its tail")
+    else:
+        queued = "queued as one call whose transitions share one persistent NUTS launch"
     workload = (f"SMC-NUTS iteration (reweight + adaptive beta + evidence + resample, population covariance, "
                 f"per-particle local metric, one NUTS transition per particle): 3-detector 8 s event, 20-1024 Hz, "
                 f"df=1/8 Hz (8033 bins), 11 params, alpha={args.alpha}, eps={args.step}, depth<={args.max_depth}, "
                 f"metric={args.metric}; a step is one iteration of each of {R} independent runs of {P} prior-draw "
-                f"particles, queued as one call whose transitions share one persistent NUTS launch; timed "
-                f"iterations {args.warmup + 1}-{args.warmup + args.steps}")
+                f"particles, {queued}; timed iterations {args.warmup + 1}-{args.warmup + args.steps}")
     if not args.no_extra:
-        extra.update(smc_extras(args, smcgw, synth, ev, prec, value, R, P))
+        extra.update(smc_extras(args, smcgw, synth, ev, prec, value, R, P, evals))
     return value, 1e3 * dt / args.steps, roofline, workload, x_np[:256], R * P
 
 
-def smc_extras(args, smcgw, synth, ev, prec, value, R, P):
+def smc_extras(args, smcgw, synth, ev, prec, value, R, P, evals):
     import torch
     ex = {}
     cap = args.warmup + args.steps + 8
+    log("all runs in one call")
+    # the same runs queued as one iteration call per step, every run's transitions in one shared NUTS launch
+    ctx, runs, _ = make_runs(smcgw, synth, ev, R, P, prec, args.metric, args.step, args.alpha, args.max_depth,
+                             args.seed, cap)
+    ctx.set_option(smcgw.OPT_NUTS_WAVES, args.waves)
+    d1, e1, k1, n1, *_ = time_iterations(smcgw, ctx, runs, args.warmup, args.steps, True)
+    ctx.close()
+    ex["one_call_form"] = {"evals_per_s": round(e1 / d1, 1), "ms_per_step": round(1e3 * d1 / args.steps, 4),
+                           "kernel_ms": round(k1 / max(n1, 1), 4),
+                           "per_launch_frac": round(OPS_PER_PARTICLE_BIN[args.precision] * ev.n * e1 / (k1 / 1e3) /
+                                                    1e12 / VALU_PEAK_TLANEOPS, 4),
+                           "same_evals_as_headline": e1 == evals}
     log("graph against eager iterations")
     # the same iterations replayed from a captured HIP graph of the whole iteration
     ctx, runs, _ = make_runs(smcgw, synth, ev, R, P, prec, args.metric, args.step, args.alpha, args.max_depth,
@@ -521,6 +622,14 @@ def side_extras(args, smcgw, synth, ev, prec):
     c.close()
     ex["smc_rb_8s"] = {"evals_per_s": round(e_ / d_, 1), "ms_per_step": round(1e3 * d_ / args.steps, 4),
                        "max_divergent_frac": max(r["divergent_frac"] for r in iteration_table(smcgw, h, P))}
+    # the same runs, each on a stream of its own (the headline's layout)
+    lanes = make_stream_runs(smcgw, synth, ev, R, P, prec, args.metric, args.step, args.alpha, args.max_depth,
+                             args.seed, args.warmup + args.steps + 8, 0, rb_eps=0.1)
+    d2, e2, _, _, busy2, _, _, _ = time_iterations_streams(smcgw, lanes, args.warmup, args.steps)
+    for lane in lanes:
+        lane[0].close()
+    ex["smc_rb_8s_streams"] = {"evals_per_s": round(e2 / d2, 1), "ms_per_step": round(1e3 * d2 / args.steps, 4),
+                               "nuts_busy_share_of_wall": round(busy2 / (1e3 * d2), 4), "same_evals": e2 == e_}
     c = smcgw.Context(0)
     c.add_event(ev)
     pool = torch.tensor(np.random.default_rng(3).normal(-20.0, 3.0, size=(30, 2048)), device="cuda")
@@ -705,6 +814,8 @@ def main():
     ap.add_argument("--max-depth", type=int, default=HEADLINE["max_depth"])
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--waves", type=int, choices=[0, 2, 4, 6, 8], default=0, help="wavefronts per NUTS slot")
+    ap.add_argument("--layout", choices=["streams", "one-call"], default="streams",
+                    help="smc mode: runs on streams of their own, or all runs in one iteration call")
     ap.add_argument("--min-seconds", type=float, default=1.0,
                     help="loglike mode: time the rate over at least this long (0: exactly --steps calls)")
     ap.add_argument("--no-cpu-baseline", action="store_true")

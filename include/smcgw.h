@@ -496,8 +496,14 @@ int smcgw_recycle(smcgw_ctx *ctx, int T, int N, const double *logl, const double
  *     slot's wavefronts as its tree deepens, so the longest trajectories of
  *     a transition run ahead of the short ones that share their compute
  *     unit; 0 keeps every wavefront at the same priority.  Scheduling only:
- *     the outputs do not depend on it. */
-enum { SMCGW_OPT_NUTS_WAVES = 0, SMCGW_OPT_NUTS_PRIORITY = 1 };
+ *     the outputs do not depend on it.
+ *   SMCGW_OPT_NUTS_SLOTS_PER_CU: at most this many NUTS workgroups (slots)
+ *     per compute unit in one launch (0, the default: as many as fit; values
+ *     above what fits are clamped).  A caller that runs independent batches
+ *     on several streams can give each launch a share of every compute unit,
+ *     so that one launch's tail overlaps another's work.  Scheduling only:
+ *     the outputs do not depend on it.  Accepts 0..64. */
+enum { SMCGW_OPT_NUTS_WAVES = 0, SMCGW_OPT_NUTS_PRIORITY = 1, SMCGW_OPT_NUTS_SLOTS_PER_CU = 2 };
 int smcgw_set_option(smcgw_ctx *ctx, int option, int64_t value);
 
 /* Autotuner of the NUTS slot width: runs `trials` transitions of the given
@@ -525,6 +531,17 @@ enum { SMCGW_KERNEL_BINS = 0, SMCGW_KERNEL_PREP = 1, SMCGW_KERNEL_FINISH = 2, SM
        SMCGW_KERNEL_SMC = 4, SMCGW_KERNEL_METRIC = 5, SMCGW_KERNEL_CLASSES = 6 };
 int smcgw_timing_enable(smcgw_ctx *ctx, int class_mask);
 int smcgw_timing_read(smcgw_ctx *ctx, int kernel_class, double *total_ms, int64_t *launches);
+/* The same records one launch at a time, against a reference: ref_event is a
+ * hipEvent_t (created with timing enabled, on this context's device) that the
+ * caller has recorded before the launches; start_ms[k] / end_ms[k] (host,
+ * cap entries each) receive launch k's start and end in ms after it.
+ * Contexts that run on several streams of one device can share the reference
+ * to find when their launches overlap.  Synchronises the context's stream and
+ * the reference, consumes the class's records as smcgw_timing_read does and
+ * sets *launches to their number; if that exceeds cap only the first cap are
+ * written and SMCGW_ERR_SHAPE is returned. */
+int smcgw_timing_intervals(smcgw_ctx *ctx, int kernel_class, void *ref_event, double *start_ms, double *end_ms,
+                           int64_t cap, int64_t *launches);
 
 #ifdef __cplusplus
 }

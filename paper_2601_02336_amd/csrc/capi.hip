@@ -140,6 +140,10 @@ extern "C" int smcgw_set_option(smcgw_ctx* c, int option, int64_t value) {
         if (value != 0 && value != 1) return SMCGW_ERR_INVALID;
         c->nuts_priority = (int)value;
         return SMCGW_OK;
+    case SMCGW_OPT_NUTS_SLOTS_PER_CU:
+        if (value < 0 || value > 64) return SMCGW_ERR_INVALID;
+        c->nuts_slots_per_cu = (int)value;
+        return SMCGW_OK;
     default:
         return SMCGW_ERR_INVALID;
     }
@@ -171,6 +175,37 @@ extern "C" int smcgw_timing_read(smcgw_ctx* c, int kernel_class, double* total_m
     *total_ms = tot;
     *launches = n;
     return SMCGW_OK;
+}
+
+extern "C" int smcgw_timing_intervals(smcgw_ctx* c, int kernel_class, void* ref_event, double* start_ms,
+                                      double* end_ms, int64_t cap, int64_t* launches) {
+    if (!c || kernel_class < 0 || kernel_class >= SMCGW_KERNEL_CLASSES || !ref_event || !launches || cap < 0 ||
+        (cap > 0 && (!start_ms || !end_ms)))
+        return SMCGW_ERR_INVALID;
+    if (hipSetDevice(c->device) != hipSuccess) return SMCGW_ERR_HIP;
+    const hipEvent_t ref = (hipEvent_t)ref_event;
+    if (hipStreamSynchronize(c->stream) != hipSuccess || hipEventSynchronize(ref) != hipSuccess)
+        return SMCGW_ERR_HIP;
+    int64_t n = 0;
+    bool ok = true;
+    for (auto& pr : c->ev_pending[kernel_class]) {
+        float s = 0.f, e = 0.f;
+        if (hipEventElapsedTime(&s, ref, pr.first) == hipSuccess && hipEventElapsedTime(&e, ref, pr.second) == hipSuccess) {
+            if (n < cap) {
+                start_ms[n] = s;
+                end_ms[n] = e;
+            }
+            ++n;
+        } else {
+            ok = false;
+        }
+        c->ev_pool.push_back(pr.first);
+        c->ev_pool.push_back(pr.second);
+    }
+    c->ev_pending[kernel_class].clear();
+    *launches = n;
+    if (!ok) return SMCGW_ERR_HIP;
+    return n > cap ? SMCGW_ERR_SHAPE : SMCGW_OK;
 }
 
 extern "C" int smcgw_set_stream(smcgw_ctx* c, void* hip_stream) {

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <unordered_map>
+#include <utility>
 #include <vector>
 
 #include "common.h"
@@ -45,11 +46,12 @@ struct smcgw_ctx {
     void* d_queue = nullptr;               // work-queue counter of the persistent kernels
     int nuts_waves = 0;                    // wavefronts per NUTS slot (0: default)
     int nuts_priority = 1;                 // depth-driven wavefront priority in the NUTS kernel
+    int nuts_slots_per_cu = 0;             // cap on resident NUTS workgroups per CU (0: none)
     int32_t* d_order = nullptr;            // NUTS start order built from a work hint
     double* d_mm = nullptr;                // block partials of the population covariance
     size_t mm_bytes = 0;
     int order_cap = 0;
-    std::unordered_map<const void*, int> resident;   // resident workgroups per device, per kernel
+    std::unordered_map<const void*, std::pair<int, int>> resident;   // (CUs, workgroups per CU), per kernel
     const int32_t* ev_of_p = nullptr;      // caller-owned event index per particle (NULL: event 0)
     void* d_sampler = nullptr;
     size_t sampler_bytes = 0;

@@ -1164,9 +1164,11 @@ int launch_persistent(smcgw_ctx* c, K kernel, int block, const NutsArgs& a, cons
             return SMCGW_ERR_HIP;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess || per_cu < 1)
             per_cu = 1;
-        it = c->resident.emplace((const void*)kernel, dev_cus * per_cu).first;
+        it = c->resident.emplace((const void*)kernel, std::make_pair(dev_cus, per_cu)).first;
     }
-    const int grid = std::max(1, std::min(a.P, it->second));
+    int per_cu = it->second.second;
+    if (c->nuts_slots_per_cu > 0) per_cu = std::min(per_cu, c->nuts_slots_per_cu);
+    const int grid = std::max(1, std::min(a.P, it->second.first * per_cu));
     hipLaunchKernelGGL(zero_queues_kernel, dim3(1), dim3(N_QUEUES), 0, c->stream, a.queue);
     {
         TimedLaunch tl(c, SMCGW_KERNEL_NUTS);

@@ -26,6 +26,7 @@ PLAIN_FP64, MIXED = 0, 1
 KERNEL_BINS, KERNEL_PREP, KERNEL_FINISH, KERNEL_NUTS, KERNEL_SMC, KERNEL_METRIC = 0, 1, 2, 3, 4, 5
 OPT_NUTS_WAVES = 0
 OPT_NUTS_PRIORITY = 1
+OPT_NUTS_SLOTS_PER_CU = 2
 
 
 class SmcgwError(RuntimeError):
@@ -139,6 +140,7 @@ def lib():
                                           C.POINTER(d)]
         L.smcgw_set_option.argtypes = [vp, i, C.c_int64]
         L.smcgw_timing_read.argtypes = [vp, i, C.POINTER(d), C.POINTER(C.c_int64)]
+        L.smcgw_timing_intervals.argtypes = [vp, i, vp, vp, vp, C.c_int64, C.POINTER(C.c_int64)]
         L.smcgw_smc_reweight_resample.argtypes = [vp, i, i, d, d, u64, u64, vp, vp, vp, vp, vp,
                                                   C.POINTER(d), C.POINTER(d)]
         L.smcgw_loglike_grad_noalloc.argtypes = [vp, i, vp, vp, vp, vp, i]
@@ -218,6 +220,17 @@ class Context:
         n = C.c_int64()
         _check("smcgw_timing_read", lib().smcgw_timing_read(self._h, kernel_class, C.byref(ms), C.byref(n)))
         return ms.value, n.value
+
+    def timing_intervals(self, kernel_class: int, ref: "torch.cuda.Event", cap: int = 65536):
+        """(start_ms, end_ms) arrays of one kernel class's launches since the last read, in ms after the
+        recorded timing event ref (which may be shared by contexts on other streams of the device)."""
+        start = np.zeros(cap)
+        end = np.zeros(cap)
+        n = C.c_int64()
+        _check("smcgw_timing_intervals", lib().smcgw_timing_intervals(
+            self._h, kernel_class, C.c_void_p(ref.cuda_event), start.ctypes.data, end.ctypes.data, cap,
+            C.byref(n)))
+        return start[:n.value], end[:n.value]
 
     # ------------------------------------------------------------ set-up
     def add_event(self, ev: "synth.Event") -> int:

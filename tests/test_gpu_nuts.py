@@ -286,8 +286,9 @@ def test_gw_three_detector_plain_parity(smc, form):
 
 
 def test_schedule_does_not_change_results(smc):
-    """Start order (work hint) and depth-driven wavefront priority only reorder work: every output is
-    bitwise the same.  1500 particles with ragged hints also exercise the order kernel's chunking."""
+    """Start order (work hint), depth-driven wavefront priority and the cap on slots per CU only reorder
+    work: every output is bitwise the same.  1500 particles with ragged hints also exercise the order kernel's
+    chunking; one slot per CU gives each of the 256 workgroups about six particles."""
     ev = event(synth.SPEC_8S)
     idx = list(range(11))
     full = synth.gw_prior_for(ev)
@@ -306,8 +307,9 @@ def test_schedule_does_not_change_results(smc):
     Lt = torch.tensor(L * 0.05, device="cuda")
     hint = torch.tensor(rng.integers(-3, 3000, size=P), dtype=torch.int32, device="cuda")
     runs = []
-    for prio, h in ((0, None), (1, None), (1, hint), (0, hint)):
+    for prio, h, spc in ((0, None, 0), (1, None, 0), (1, hint, 0), (0, hint, 0), (1, None, 1), (1, hint, 2)):
         c.set_option(smc.OPT_NUTS_PRIORITY, prio)
+        c.set_option(smc.OPT_NUTS_SLOTS_PER_CU, spc)
         xs, ls, gs = xt.clone(), ll.clone(), g.clone()
         o = c.nuts_step(xs, ls, gs, Lt, step=0.25, beta=0.05, seed=5, iteration=2, max_depth=6,
                         precision=smc.MIXED, work_hint=h)

@@ -49,3 +49,69 @@ def test_run_smc_concurrent_equals_run_smc():
         np.testing.assert_array_equal(a.theta.cpu().numpy(), t.theta.cpu().numpy())
         np.testing.assert_array_equal(a.logl.cpu().numpy(), t.logl.cpu().numpy())
     assert alone[0].logz != alone[1].logz
+
+
+def test_runs_on_streams_equal_one_call_and_time_their_launches():
+    """The headline's layout: R runs queued as R contexts on R streams, round-robin with no host waits, give
+    bitwise the populations and records of the same runs in one iteration call (run r of the call has Philox
+    key seed + r).  The NUTS launches' intervals against a shared reference event are ordered on each stream,
+    overlap across streams, and a too-small buffer is an error (3-detector 8 s event, 3 x 256 particles, local
+    metric, depth <= 6, 4 iterations)."""
+    from paper_2601_02336_amd import smcgw
+    ev = event(synth.SPEC_8S)
+    b = synth.gw_prior_for(ev)
+    R, P, T = 3, 256, 4
+
+    def make(n_runs, seed, draws):
+        c = smcgw.Context(0)
+        c.add_event(ev)
+        c.set_prior(b)
+        c.set_target(synth.TARGET_GW, 11)
+        x = np.concatenate([synth.prior_draw(np.random.default_rng(d), P, b) for d in draws])
+        runs = smcgw.SmcRuns(c, torch.tensor(x, device="cuda"), n_runs, alpha=0.9, step=0.1, max_depth=6,
+                             shrink=0.0, seed=seed, precision=smcgw.MIXED, metric="local", history_cap=8)
+        return c, runs
+
+    c1, one = make(R, 5, [30 + r for r in range(R)])
+    for _ in range(T):
+        one.step()
+    torch.cuda.synchronize()
+    lanes = [make(1, 5 + r, [30 + r]) + (torch.cuda.Stream(),) for r in range(R)]
+    cur = torch.cuda.current_stream()
+    for c, _, s in lanes:
+        s.wait_stream(cur)
+        c.timing(smcgw.KERNEL_NUTS)
+    ref = torch.cuda.Event(enable_timing=True)
+    ref.record()
+    ref.synchronize()
+    for _ in range(T):
+        for _, runs, s in lanes:
+            with torch.cuda.stream(s):
+                runs.step()
+    torch.cuda.synchronize()
+    h1 = one.history()
+    for r, (c, runs, _) in enumerate(lanes):
+        sl = one.run_slice(r)
+        np.testing.assert_array_equal(runs.theta.cpu().numpy(), one.theta[sl].cpu().numpy())
+        np.testing.assert_array_equal(runs.logl.cpu().numpy(), one.logl[sl].cpu().numpy())
+        np.testing.assert_array_equal(runs.history()[0, :T], h1[r, :T])
+    c_, _, _ = lanes[0]
+    c_.timing()
+    with pytest.raises(RuntimeError):
+        c_.timing_intervals(smcgw.KERNEL_NUTS, ref, cap=T - 1)   # consumes the records, reports the shortfall
+    starts, ends = [], []
+    for c, _, _ in lanes[1:]:
+        c.timing()
+        s_, e_ = c.timing_intervals(smcgw.KERNEL_NUTS, ref)
+        assert len(s_) == T and (s_ >= 0).all() and (e_ > s_).all() and (s_[1:] >= e_[:-1]).all()
+        starts.append(s_)
+        ends.append(e_)
+    overlap = min(ends[0][-1], ends[1][-1]) > max(starts[0][0], starts[1][0])
+    print(f"stream 1 launches {np.round(starts[0], 2)}..{np.round(ends[0], 2)} ms; stream 2 "
+          f"{np.round(starts[1], 2)}..{np.round(ends[1], 2)} ms", flush=True)
+    assert overlap
+    s_, _ = lanes[1][0].timing_intervals(smcgw.KERNEL_NUTS, ref)
+    assert len(s_) == 0
+    for c, _, _ in lanes:
+        c.close()
+    c1.close()

@@ -48,6 +48,21 @@ def test_bench_queue_model_and_start_order():
     assert order[127] == 127 and order[128] == 128 and order[256:259].tolist() == [256, 272, 288]
 
 
+def test_bench_busy_time_is_the_union_of_launch_intervals():
+    """Launches on several streams overlap: the kernel's busy time is the length of the union of their
+    intervals (nested, touching, disjoint and unsorted intervals; one stream's back-to-back launches give their
+    summed durations)."""
+    sys.path.insert(0, ROOT)
+    import bench
+    assert bench.union_ms([], []) == 0.0
+    assert bench.union_ms([5.0, 0.0, 1.0], [6.0, 2.0, 3.0]) == pytest.approx(4.0)
+    assert bench.union_ms([0.0, 0.5], [3.0, 1.0]) == pytest.approx(3.0)
+    assert bench.union_ms([0.0, 2.0], [2.0, 4.0]) == pytest.approx(4.0)
+    s = [0.0, 10.0, 25.0]
+    e = [9.0, 20.0, 26.0]
+    assert bench.union_ms(s, e) == pytest.approx(sum(b - a for a, b in zip(s, e)))
+
+
 def test_bench_iteration_table_and_traffic_gate(tmp_path, monkeypatch):
     """The per-iteration rows are the runs' records divided by the run size (the largest divergent fraction over
     the runs), and counter traffic is reported only for the kernel sources, kernel and command it was taken on."""
