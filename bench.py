@@ -355,6 +355,7 @@ def smc_mode(args, smcgw, synth, ev, prec, extra):
                 "traffic": traffic["bytes_per_launch"] if traffic else None, "traffic_per": "launch",
                 "kernel": kname, "kernel_ms": round(k_ms / max(k_n, 1), 4), "launches": k_n,
                 "busy_ms": round(busy_ms, 3), "streams": R if args.layout == "streams" else 1,
+                "mean_launches_in_flight": round(k_ms / max(busy_ms, 1e-9), 3),
                 "ops_per_particle_bin": ops, "evals_in_kernel": evals,
                 "algorithmic_lane_ops_per_launch": round(ops * ev.n * evals / max(k_n, 1))}
     if traffic:
