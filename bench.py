@@ -55,7 +55,8 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_nuts_smc_3det_8033bins_3x2048p.txt")
+TRAFFIC_FILES = [os.path.join(ROOT, "profiles", f"traffic_nuts_smc_3det_8033bins_3x2048p{s}.txt")
+                 for s in ("", "_streams")]
 
 
 def kernel_source_hash():
@@ -74,19 +75,20 @@ def kernel_source_hash():
 
 
 def measured_traffic(kernel, command):
-    """HBM bytes per launch from the committed counter summary, or None when it was taken on other kernel
-    sources, for another kernel or with another command."""
-    try:
-        with open(TRAFFIC_FILE) as f:
-            kv = dict(line.strip().split("=", 1) for line in f if "=" in line and not line.startswith("#"))
-    except OSError:
-        return None
-    if kv.get("kernel") != kernel or kv.get("source_sha256") != kernel_source_hash() or \
-            kv.get("bench_args") != command:
-        return None
-    return {"bytes_per_launch": int(kv["traffic_bytes_per_launch"]),
-            "fetch_bytes_per_launch": int(kv["fetch_bytes_per_launch"]),
-            "write_bytes_per_launch": int(kv["write_bytes_per_launch"])}
+    """HBM bytes per launch from the committed counter summaries: the one taken on these kernel sources, for this
+    kernel and with this command, or None."""
+    for path in TRAFFIC_FILES:
+        try:
+            with open(path) as f:
+                kv = dict(line.strip().split("=", 1) for line in f if "=" in line and not line.startswith("#"))
+        except OSError:
+            continue
+        if kv.get("kernel") == kernel and kv.get("source_sha256") == kernel_source_hash() and \
+                kv.get("bench_args") == command:
+            return {"bytes_per_launch": int(kv["traffic_bytes_per_launch"]),
+                    "fetch_bytes_per_launch": int(kv["fetch_bytes_per_launch"]),
+                    "write_bytes_per_launch": int(kv["write_bytes_per_launch"])}
+    return None
 
 
 def build_event(smcgw, synth, spec=None):
@@ -344,10 +346,11 @@ def smc_mode(args, smcgw, synth, ev, prec, extra):
         busy_ms = k_ms
     table = iteration_table(smcgw, h, P)
     value = evals / dt
-    # the kernel's own rate: the algorithmic work of the timed launches over the time in which at least one of
-    # them runs (one stream: their summed durations; several: the union of their intervals, since launches on
-    # different streams overlap).  kernel_ms is the mean duration of one launch, as a kernel trace reports it.
-    achieved = ops * ev.n * evals / (busy_ms / 1e3) / 1e12
+    # the kernel's own rate: the algorithmic work of a launch over its duration, i.e. the timed launches' work
+    # over their summed durations (kernel_ms is the mean duration, as a kernel trace reports it).  Launches on
+    # several streams overlap and stretch each other's durations; for them the work over the union of their
+    # intervals (busy_ms, the time in which at least one runs) is reported beside it as busy_span_frac.
+    achieved = ops * ev.n * evals / (k_ms / 1e3) / 1e12
     kname = f"nuts_kernel<3,{'MIXED' if prec == smcgw.MIXED else 'PLAIN_FP64'},GW,{args.waves or 4}>"
     traffic = measured_traffic(kname, " ".join(sys.argv[1:]))
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TLANEOPS, 3),
@@ -356,12 +359,14 @@ def smc_mode(args, smcgw, synth, ev, prec, extra):
                 "kernel": kname, "kernel_ms": round(k_ms / max(k_n, 1), 4), "launches": k_n,
                 "busy_ms": round(busy_ms, 3), "streams": R if args.layout == "streams" else 1,
                 "mean_launches_in_flight": round(k_ms / max(busy_ms, 1e-9), 3),
+                "busy_span_frac": round(ops * ev.n * evals / (busy_ms / 1e3) / 1e12 / VALU_PEAK_TLANEOPS, 4),
                 "ops_per_particle_bin": ops, "evals_in_kernel": evals,
                 "algorithmic_lane_ops_per_launch": round(ops * ev.n * evals / max(k_n, 1))}
     if traffic:
         roofline["traffic_detail"] = traffic
     log(f"smc {args.precision} ({args.layout}): {evals} evals in {dt:.3f} s -> {value:.4g} evals/s; nuts kernel "
-        f"{k_ms / max(k_n, 1):.3f} ms x {k_n}, busy {busy_ms:.1f} ms (frac {achieved / VALU_PEAK_TLANEOPS:.3f}); "
+        f"{k_ms / max(k_n, 1):.3f} ms x {k_n} (frac {achieved / VALU_PEAK_TLANEOPS:.3f}), busy {busy_ms:.1f} ms "
+        f"(frac {roofline['busy_span_frac']:.3f}); "
         f"local metric {m_ms / max(m_n, 1):.3f} ms x {m_n}; max divergent {max(r['divergent_frac'] for r in table)}")
     extra["iterations"] = table
     extra["max_divergent_frac"] = max(r["divergent_frac"] for r in table)
@@ -373,6 +378,7 @@ def smc_mode(args, smcgw, synth, ev, prec, extra):
                   f"another's NUTS launch is still in its tail")
     else:
         queued = "queued as one call whose transitions share one persistent NUTS launch"
+
     workload = (f"SMC-NUTS iteration (reweight + adaptive beta + evidence + resample, population covariance, "
                 f"per-particle local metric, one NUTS transition per particle): 3-detector 8 s event, 20-1024 Hz, "
                 f"df=1/8 Hz (8033 bins), 11 params, alpha={args.alpha}, eps={args.step}, depth<={args.max_depth}, "
@@ -387,18 +393,36 @@ def smc_extras(args, smcgw, synth, ev, prec, value, R, P, evals):
     import torch
     ex = {}
     cap = args.warmup + args.steps + 8
-    log("all runs in one call")
-    # the same runs queued as one iteration call per step, every run's transitions in one shared NUTS launch
-    ctx, runs, _ = make_runs(smcgw, synth, ev, R, P, prec, args.metric, args.step, args.alpha, args.max_depth,
-                             args.seed, cap)
-    ctx.set_option(smcgw.OPT_NUTS_WAVES, args.waves)
-    d1, e1, k1, n1, *_ = time_iterations(smcgw, ctx, runs, args.warmup, args.steps, True)
-    ctx.close()
-    ex["one_call_form"] = {"evals_per_s": round(e1 / d1, 1), "ms_per_step": round(1e3 * d1 / args.steps, 4),
-                           "kernel_ms": round(k1 / max(n1, 1), 4),
-                           "per_launch_frac": round(OPS_PER_PARTICLE_BIN[args.precision] * ev.n * e1 / (k1 / 1e3) /
-                                                    1e12 / VALU_PEAK_TLANEOPS, 4),
-                           "same_evals_as_headline": e1 == evals}
+    ops_eval = OPS_PER_PARTICLE_BIN[args.precision] * ev.n
+    if args.layout == "one-call":
+        log("each run on a stream of its own")
+        # the same runs, each a context on a stream of its own: one run's NUTS launch takes the slots another
+        # run's launch frees in its tail, so the launches overlap (2-3 in flight).  Reported both over the
+        # launches' busy span (the union of their intervals) and per launch (one launch's work over its own
+        # duration, which the overlap stretches).
+        lanes = make_stream_runs(smcgw, synth, ev, R, P, prec, args.metric, args.step, args.alpha, args.max_depth,
+                                 args.seed, cap, args.waves)
+        d1, e1, k1, n1, b1, *_ = time_iterations_streams(smcgw, lanes, args.warmup, args.steps)
+        for lane in lanes:
+            lane[0].close()
+        ex["streams_form"] = {"evals_per_s": round(e1 / d1, 1), "ms_per_step": round(1e3 * d1 / args.steps, 4),
+                              "launches": n1, "kernel_ms": round(k1 / max(n1, 1), 4), "busy_ms": round(b1, 3),
+                              "busy_span_frac": round(ops_eval * e1 / (b1 / 1e3) / 1e12 / VALU_PEAK_TLANEOPS, 4),
+                              "per_launch_frac": round(ops_eval * e1 / (k1 / 1e3) / 1e12 / VALU_PEAK_TLANEOPS, 4),
+                              "mean_launches_in_flight": round(k1 / max(b1, 1e-9), 3),
+                              "same_evals_as_headline": e1 == evals}
+    else:
+        log("all runs in one call")
+        # the same runs queued as one iteration call per step, every run's transitions in one shared NUTS launch
+        ctx, runs, _ = make_runs(smcgw, synth, ev, R, P, prec, args.metric, args.step, args.alpha, args.max_depth,
+                                 args.seed, cap)
+        ctx.set_option(smcgw.OPT_NUTS_WAVES, args.waves)
+        d1, e1, k1, n1, *_ = time_iterations(smcgw, ctx, runs, args.warmup, args.steps, True)
+        ctx.close()
+        ex["one_call_form"] = {"evals_per_s": round(e1 / d1, 1), "ms_per_step": round(1e3 * d1 / args.steps, 4),
+                               "kernel_ms": round(k1 / max(n1, 1), 4),
+                               "per_launch_frac": round(ops_eval * e1 / (k1 / 1e3) / 1e12 / VALU_PEAK_TLANEOPS, 4),
+                               "same_evals_as_headline": e1 == evals}
     log("graph against eager iterations")
     # the same iterations replayed from a captured HIP graph of the whole iteration
     ctx, runs, _ = make_runs(smcgw, synth, ev, R, P, prec, args.metric, args.step, args.alpha, args.max_depth,
@@ -815,8 +839,9 @@ def main():
     ap.add_argument("--max-depth", type=int, default=HEADLINE["max_depth"])
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--waves", type=int, choices=[0, 2, 4, 6, 8], default=0, help="wavefronts per NUTS slot")
-    ap.add_argument("--layout", choices=["streams", "one-call"], default="streams",
-                    help="smc mode: runs on streams of their own, or all runs in one iteration call")
+    ap.add_argument("--layout", choices=["one-call", "streams"], default="one-call",
+                    help="smc mode: all runs in one iteration call (one NUTS launch per step), or each run on "
+                         "a stream of its own")
     ap.add_argument("--min-seconds", type=float, default=1.0,
                     help="loglike mode: time the rate over at least this long (0: exactly --steps calls)")
     ap.add_argument("--no-cpu-baseline", action="store_true")

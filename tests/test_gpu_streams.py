@@ -52,7 +52,7 @@ def test_run_smc_concurrent_equals_run_smc():
 
 
 def test_runs_on_streams_equal_one_call_and_time_their_launches():
-    """The headline's layout: R runs queued as R contexts on R streams, round-robin with no host waits, give
+    """The streams layout: R runs queued as R contexts on R streams, round-robin with no host waits, give
     bitwise the populations and records of the same runs in one iteration call (run r of the call has Philox
     key seed + r).  The NUTS launches' intervals against a shared reference event are ordered on each stream,
     overlap across streams, and a too-small buffer is an error (3-detector 8 s event, 3 x 256 particles, local

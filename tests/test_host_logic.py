@@ -65,7 +65,8 @@ def test_bench_busy_time_is_the_union_of_launch_intervals():
 
 def test_bench_iteration_table_and_traffic_gate(tmp_path, monkeypatch):
     """The per-iteration rows are the runs' records divided by the run size (the largest divergent fraction over
-    the runs), and counter traffic is reported only for the kernel sources, kernel and command it was taken on."""
+    the runs), and counter traffic is reported only for the kernel sources, kernel and command it was taken on
+    (the first of the committed summaries that matches all three)."""
     sys.path.insert(0, ROOT)
     import bench
     from paper_2601_02336_amd import smcgw
@@ -80,8 +81,12 @@ def test_bench_iteration_table_and_traffic_gate(tmp_path, monkeypatch):
     assert [r["leapfrog"] for r in rows] == [101, 202, 303]
     assert rows[2]["beta"] == [0.3, 0.35]
     f = tmp_path / "traffic.txt"
-    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    g = tmp_path / "traffic_other_layout.txt"
+    monkeypatch.setattr(bench, "TRAFFIC_FILES", [str(tmp_path / "absent.txt"), str(g), str(f)])
     assert bench.measured_traffic("k", "") is None                       # no file
+    g.write_text("kernel=k\nbench_args=--steps 3 --layout streams\nsource_sha256={}\ntraffic_bytes_per_launch=9\n"
+                 "fetch_bytes_per_launch=6\nwrite_bytes_per_launch=3\n".format(bench.kernel_source_hash()))
+    assert bench.measured_traffic("k", "--steps 3 --layout streams")["bytes_per_launch"] == 9
     body = ("# made by a counter run\nkernel=k\nbench_args=--steps 3\nsource_sha256={}\n"
             "traffic_bytes_per_launch=30\nfetch_bytes_per_launch=20\nwrite_bytes_per_launch=10\n")
     f.write_text(body.format(bench.kernel_source_hash()))
