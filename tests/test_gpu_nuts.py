@@ -316,6 +316,9 @@ def test_schedule_does_not_change_results(smc):
         torch.cuda.synchronize()
         runs.append([xs.cpu().numpy(), ls.cpu().numpy(), gs.cpu().numpy()] +
                     [o[k].cpu().numpy() for k in ("depth", "n_leapfrog", "divergent", "accept_stat")])
+    for bad in (-1, 65):
+        with pytest.raises(RuntimeError):
+            c.set_option(smc.OPT_NUTS_SLOTS_PER_CU, bad)
     c.close()
     print(f"depths {np.bincount(runs[0][3])}", flush=True)
     assert runs[0][4].min() >= 1
